@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the streaming-GCP gradient step on one MI355X.
+
+Workload (the configuration the metric is quoted on): dense Poisson-count
+slices of 200x200x200 FP32, rank 16, window 10, Poisson loss with log link.
+One step = one gcp_loss_grad (objective and all gradients) over the current
+slice and its full window of 10 stored slices, inputs resident in HBM.
+
+Prints ONE JSON line:  grad steps/s (fused), ms per step, the unfused
+("plain") path's rate on the same GPU, the roofline entry for the dominant
+kernel (algorithmic bytes / kernel time from HIP events on the library's
+stream), and the FP64 CPU oracle's rate on this host (with its error against
+the GPU result).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--fused-only", action="store_true",
+                    help="time the fused step only (for profiler runs)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        return 2
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream
+
+    dims, R, H, loss = (200, 200, 200), 16, 10, "poisson_log"
+    print(f"bench: generating workload {dims} R={R} H={H} {loss}", file=sys.stderr, flush=True)
+    prob = gi.c2_problem(dims=dims, rank=R, window=H)
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X_t = T(prob.X_t)
+    A = [T(a) for a in prob.A]
+    s_t = T(prob.s_t)
+    Xh = [T(x) for x in prob.X_hist]
+    Sh = T(prob.s_hist)
+    plain = not (args.no_plain or args.fused_only)
+    st = Stream(dims, R, H, loss, A, Xh, Sh, list(prob.t_hist), plain=plain)
+    del Xh
+    torch.cuda.synchronize()
+    out = (torch.empty(1, device=dev), [torch.empty(n, R, device=dev) for n in dims],
+           torch.empty(R, device=dev))
+
+    def run(n, plain_path=False):
+        for _ in range(n):
+            st.loss_grad(X_t, A, s_t, plain=plain_path, out=out)
+
+    # ---- fused path -------------------------------------------------------
+    print("bench: warmup", file=sys.stderr, flush=True)
+    run(args.warmup)
+    torch.cuda.synchronize()
+    st.kernel_timing(True, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, kern_n = st.kernel_time()
+    st.kernel_timing(False)
+    assert st.sync() == 0, "device reported a numeric failure"
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"bench: fused {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+    gpu_res = (float(out[0].item()), [g.double().cpu().numpy() for g in out[1]],
+               out[2].double().cpu().numpy())
+
+    ns = H + 1
+    omega = int(np.prod(dims))
+    alg_bytes = ns * omega * 4 + 4 * R * sum(dims) * 2 + 4 * R * (ns + 1)
+    alg_flops = omega * (4 * R * ns + 8 * R)
+    kavg_s = kern_ms / max(kern_n, 1) / 1e3
+    achieved = alg_bytes / kavg_s / 1e9
+
+    # ---- plain path -------------------------------------------------------
+    plain_ms = None
+    if plain:
+        run(2, True)
+        torch.cuda.synchronize()
+        n_plain = max(3, args.steps // 10)
+        t0 = time.perf_counter()
+        run(n_plain, True)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3 / n_plain
+        assert st.sync() == 0
+        print(f"bench: plain {plain_ms:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # ---- CPU oracle ---------------------------------------------------------
+    cpu = None
+    err = None
+    if not (args.no_cpu_baseline or args.fused_only):
+        from oracle import gcp as og
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        p64 = prob.promoted()
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        F = og.objective(p64)
+        G, gs = og.gradient(p64)
+        csec = time.perf_counter() - c0
+        scale = og.loss_terms_abs(p64)
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        err = {"loss": abs(gpu_res[0] - F) / max(abs(F), scale),
+               **{f"G{k + 1}": rel(gpu_res[1][k], G[k]) for k in range(3)},
+               "g_s": rel(gpu_res[2], gs)}
+        cpu = {"value": 1.0 / csec, "unit": "grad steps/s", "cores": int(cores),
+               "kind": "oracle",
+               "sample": "one full objective+gradient evaluation of the same 200^3 x 11-slice "
+                         "workload (FP64 NumPy oracle, BLAS threads as listed)"}
+
+    res = {
+        "metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
+        "value": 1e3 / ms_per_step,
+        "unit": "grad steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C2 dense Poisson-count slices 200x200x200, rank 16, window 10, "
+                               "Poisson-log loss, one gcp_loss_grad over X_t and 10 stored slices",
+                   "dims": list(dims), "rank": R, "window": H, "loss": loss,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fused dense objective+gradient kernel",
+                     "kernel_ms": kavg_s * 1e3, "alg_bytes_per_launch": alg_bytes,
+                     "alg_gflops_per_launch": alg_flops / 1e9,
+                     "fp32_tflops": alg_flops / kavg_s / 1e12,
+                     "fp32_frac": alg_flops / kavg_s / 1e12 / FP32_PEAK_TFLOPS},
+        "plain_ms_per_step": plain_ms,
+        "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
+        "err_vs_oracle": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,207 @@
+/*
+ * gcpstream: streaming generalized CP (GCP) objective and gradient on one
+ * MI355X (gfx950).  C ABI.
+ *
+ * The method is OnlineGCP (Phipps, Johnson, Kolda, "Streaming Generalized
+ * Canonical Polyadic Tensor Decompositions").  At time step t the library
+ * evaluates, over the current d-way slice X_t and a window H_t of stored past
+ * slices X_h (Section 4.1, eq. gcp_stream_problem_1),
+ *
+ *   F = sum_i f(x_it, m_i(s_t)) + sum_{h in H_t} w_h sum_i f(x_ih, m_i(s_h))
+ *       + lambda/2 sum_k ||A^(k)||_F^2 + mu/2 ||s_t||^2,
+ *   m_i(s) = sum_j s_j prod_k A^(k)[i_k, j]        (eq. CP_model)
+ *   w_h = w theta^(t-h)                             (Section 4.1)
+ *
+ * and its gradients (eqs. gcp_grad_A, gcp_grad_lambda, Section 4.2)
+ *
+ *   G^(k) = Y_t(k) Z_k diag(s_t) + sum_h w_h Y_h(k) Z_k diag(s_h) + lambda A^(k)
+ *   g_s   = Z^T vec(Y_t) + mu s_t,        y_i = df/dm (x_i, m_i).
+ *
+ * Losses: Gaussian f = (x-m)^2; Poisson with log link f = e^m - x m;
+ * Bernoulli with logit link f = log(1+e^m) - x m (Section 2.2 with the
+ * m-independent terms dropped).
+ *
+ * Conventions shared by every call
+ *  - Only d = 3 slices are supported (GCP_E_UNSUPPORTED otherwise).
+ *  - A dense slice is I_1 x I_2 x I_3, row-major (last index contiguous),
+ *    base aligned to 16 bytes.  A factor matrix A^(k) is I_k x R row-major.
+ *  - Every array argument is a DEVICE pointer unless marked "host".
+ *  - The library never allocates or frees device memory: the caller passes
+ *    one workspace of gcp_workspace_size() bytes (256-byte aligned) that the
+ *    stream owns until gcp_stream_destroy.  The handle lives on the host heap.
+ *  - Every call is asynchronous on the HIP stream given at init and performs
+ *    no host synchronisation, except where documented (gcp_stream_sync and
+ *    the sample dump).  A handle is not thread-safe.
+ *  - Argument, shape, alignment and state errors are detected before any
+ *    launch and leave the stream unchanged.  Device-detected numeric failures
+ *    (non-finite loss or gradient, a failed Cholesky pivot) set a status word
+ *    in the workspace that gcp_stream_sync returns (GCP_E_NUMERIC).
+ *  - Outputs are overwritten, never accumulated into.
+ */
+#ifndef GCPSTREAM_H
+#define GCPSTREAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCP_ABI_VERSION 1
+#define GCP_MAX_D 3
+#define GCP_MAX_RANK 64
+#define GCP_MAX_WINDOW 64
+
+typedef struct gcp_stream gcp_stream;
+
+typedef enum {
+  GCP_OK = 0,
+  GCP_E_ARG = 1,          /* bad scalar argument or null pointer          */
+  GCP_E_SHAPE = 2,        /* dimension / size mismatch                     */
+  GCP_E_ALIGN = 3,        /* misaligned dense base or workspace            */
+  GCP_E_STATE = 4,        /* call not valid in the stream's current state  */
+  GCP_E_WORKSPACE = 5,    /* workspace too small                           */
+  GCP_E_DEVICE = 6,       /* a HIP runtime call failed                     */
+  GCP_E_NUMERIC = 7,      /* device found a non-finite value / bad pivot   */
+  GCP_E_UNSUPPORTED = 8   /* valid request outside what is implemented     */
+} gcp_status;
+
+typedef enum {
+  GCP_LOSS_GAUSSIAN = 0,
+  GCP_LOSS_POISSON_LOG = 1,
+  GCP_LOSS_BERNOULLI_LOGIT = 2
+} gcp_loss;
+
+typedef enum { GCP_F32 = 0, GCP_F64 = 1 } gcp_dtype;
+typedef enum { GCP_SLICE_DENSE = 0, GCP_SLICE_COO = 1 } gcp_slice_kind;
+
+/* Bits of the `want` argument of gcp_loss_grad. */
+enum {
+  GCP_WANT_LOSS = 1,      /* write *loss                                  */
+  GCP_WANT_GRAD = 2,      /* write G^(1..d) and g_s                       */
+  GCP_IMPL_PLAIN = 256    /* run the unfused multi-kernel path instead    */
+};
+
+/* Flags of gcp_params.flags. */
+enum {
+  GCP_FLAG_PLAIN_SCRATCH = 1  /* reserve the unfused path's scratch (2 slices) */
+};
+
+/* Table 1 (Section 4.2) of the paper, plus layout and sampling controls. */
+typedef struct {
+  uint32_t abi_version;   /* GCP_ABI_VERSION                               */
+  int32_t d;              /* slice order; must be 3                        */
+  int64_t dims[GCP_MAX_D];/* I_1, I_2, I_3                                 */
+  int32_t rank;           /* R, 1..GCP_MAX_RANK                            */
+  int32_t window;         /* H, 0..GCP_MAX_WINDOW                          */
+  int32_t loss;           /* gcp_loss                                      */
+  int32_t dtype;          /* gcp_dtype: GCP_F64 is for verification only  */
+  int32_t slice_kind;     /* gcp_slice_kind of every slice of the stream  */
+  int32_t flags;          /* GCP_FLAG_*                                    */
+  double w, theta;        /* history weights w_h = w theta^(t-h)          */
+  double lambda, mu;      /* factor / temporal-weight regularisation       */
+  double lower;           /* lower bound l (-INFINITY: none)               */
+  double alpha_f;         /* ADAM rate of the factor solver (Alg. 2)       */
+  double beta1, beta2, adam_eps;
+  int32_t tau_f;          /* factor iterations per gcp_update_factors      */
+  int32_t reserved0;
+  int64_t max_nnz;        /* COO: largest nnz of any slice                 */
+  int64_t p, q;           /* COO: nonzero / zero samples per gradient      */
+  uint64_t seed;          /* reservoir draws and the sampler               */
+} gcp_params;
+
+/* One slice.  DENSE: vals holds prod(dims) values, coords is NULL.
+ * COO: nnz entries; coords is nnz x 3 int32 row-major, sorted by row-major
+ * linear index with no duplicates; vals are the (non-zero) values. */
+typedef struct {
+  int32_t kind;           /* gcp_slice_kind */
+  int32_t reserved;
+  const void* vals;       /* float or double, per gcp_params.dtype */
+  const int32_t* coords;
+  int64_t nnz;
+} gcp_slice;
+
+/* Fills *params with the paper's defaults (Table 2 caption, Section 6):
+ * w = theta = 1, lambda = mu = 0, beta1 = 0.9, beta2 = 0.999, eps = 1e-8,
+ * lower = -inf, alpha_f = 1e-3, tau_f = 1, FP32, dense. */
+void gcp_params_default(gcp_params* params);
+
+/* Bytes of device workspace a stream with these parameters needs. */
+gcp_status gcp_workspace_size(const gcp_params* params, size_t* bytes);
+
+/* Creates a stream.  A0[k] (k < d) are the initial factor matrices; they and
+ * the n_hist initial window slices X_hist[h] (host array of slice structs
+ * whose data pointers are device pointers) with their weights s_hist
+ * (device, n_hist x R) and host time stamps t_hist are COPIED into the
+ * workspace, so the caller may free them after the stream has executed the
+ * copies.  The stream's time index starts at max(t_hist)+1 (1 if empty).
+ * n_hist must not exceed params->window. */
+gcp_status gcp_stream_init(const gcp_params* params, const void* const* A0,
+                           int32_t n_hist, const gcp_slice* X_hist,
+                           const void* s_hist, const int64_t* t_hist,
+                           void* workspace, size_t ws_bytes,
+                           hipStream_t hip_stream, gcp_stream** out);
+
+/* Objective and gradient at (A, s_t) over X_t and the stream's window, with
+ * the stream's current t for w_h (Section 4.2, eq. spatial_gcp_grad for the
+ * stored-slice history).  A[k] may alias the stream's own factors
+ * (gcp_factor_ptr).  want: GCP_WANT_LOSS and/or GCP_WANT_GRAD; add
+ * GCP_IMPL_PLAIN for the unfused path (needs GCP_FLAG_PLAIN_SCRATCH).
+ * loss: device scalar; G[k]: I_k x R; g_s: R.  Null outputs are allowed for
+ * the parts not wanted.  On COO streams the data terms are the stratified
+ * sampled estimates of Section 4.3 (see gcp_dump_samples). */
+gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t,
+                         const void* const* A, const void* s_t, uint32_t want,
+                         void* loss, void* const* G, void* g_s);
+
+/* Temporal weights for X_t with the stream's factors held fixed (Alg. 1,
+ * temporal step; eq. gcp_stream_temporal_problem).  Gaussian loss only: the
+ * least-squares solve of Section 5, (Gamma + mu/2 I) s = Z^T vec(X_t) with
+ * Gamma = hadamard_k A^(k)^T A^(k), formed and solved in FP64 on the device,
+ * then s <- max(s, l).  Writes s_t (R values of the stream dtype). */
+gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t);
+
+/* Factor update for X_t with weights s_t (Alg. 1 factor step; Alg. 4 inner
+ * iterations): tau_f times [full gradient over X_t and the window, then the
+ * ADAM Step of Alg. 2 with the stream's global iteration index], then
+ * A_old <- A, then the reservoir window update with X_t and s_t, then
+ * t <- t+1.  X_t may be reused by the caller once the HIP stream has passed
+ * this call. */
+gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t,
+                              const void* s_t);
+
+/* Copies the stream's current factors into A_out[k] (device). */
+gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out);
+
+/* Device pointer to the stream's current factor k (valid until destroy). */
+gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr);
+
+/* Host-side stream state: current t, window size, Adam iteration index, and
+ * the time stamp held by each window slot (host array of params->window). */
+gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window,
+                           int64_t* adam_iter, int64_t* slot_times);
+
+/* Waits for the HIP stream and returns the deferred device status
+ * (GCP_E_NUMERIC if a kernel flagged one), clearing it. */
+gcp_status gcp_stream_sync(gcp_stream* s);
+
+gcp_status gcp_stream_destroy(gcp_stream* s);
+
+/* Measurement tooling.  With enable != 0, each following gcp_loss_grad
+ * records a pair of HIP events on the stream's HIP stream immediately before
+ * and after its main gradient kernel (up to `capacity` pairs; the events are
+ * created here, outside any timed region).  gcp_kernel_time waits for the
+ * recorded events, returns the summed kernel milliseconds and the number of
+ * launches timed, and starts a new count.  enable = 0 destroys the events. */
+gcp_status gcp_kernel_timing(gcp_stream* s, int32_t enable, int32_t capacity);
+gcp_status gcp_kernel_time(gcp_stream* s, double* total_ms, int64_t* count);
+
+const char* gcp_status_string(gcp_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCPSTREAM_H */

@@ -1,0 +1,418 @@
+// C-ABI shell of gcpstream: argument validation, workspace layout, the
+// stream's host-side state (time index, window slots, ADAM iteration) and the
+// launch sequences of each call.  Declarations and contracts are in
+// include/gcpstream.h.
+#include "../../include/gcpstream.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace gcp;
+
+struct WsLayout {
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, total;
+  size_t fac_elems;       // sum_k I_k R
+  size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
+  size_t plain_bytes, part_bytes;
+};
+
+struct gcp_stream {
+  gcp_params p;
+  size_t es;
+  size_t omega;
+  int dims[3];
+  hipStream_t st;
+  char* ws;
+  WsLayout L;
+  int64_t t;
+  int nwin;
+  int64_t slot_t[GCP_MAX_WINDOW];
+  int64_t adam_i;
+  int* status;
+  std::vector<hipEvent_t> ev;   // begin/end pairs for gcp_kernel_timing
+  int ev_used;
+};
+
+namespace {
+
+gcp_status check_params(const gcp_params* p) {
+  if (!p) return GCP_E_ARG;
+  if (p->abi_version != GCP_ABI_VERSION) return GCP_E_ARG;
+  if (p->d != 3) return GCP_E_UNSUPPORTED;
+  for (int k = 0; k < 3; ++k)
+    if (p->dims[k] < 1 || p->dims[k] > (1 << 30)) return GCP_E_SHAPE;
+  if ((double)p->dims[0] * p->dims[1] * p->dims[2] > 9.0e15) return GCP_E_SHAPE;
+  if ((double)p->dims[0] * p->dims[1] >= 2147483647.0) return GCP_E_SHAPE;
+  if (p->rank < 1 || p->rank > GCP_MAX_RANK) return GCP_E_ARG;
+  if (p->window < 0 || p->window > GCP_MAX_WINDOW) return GCP_E_ARG;
+  if (p->loss < 0 || p->loss > 2) return GCP_E_ARG;
+  if (p->dtype != GCP_F32 && p->dtype != GCP_F64) return GCP_E_ARG;
+  if (p->slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  if (!(p->theta > 0.0 && p->theta <= 1.0)) return GCP_E_ARG;
+  if (!isfinite(p->w) || !isfinite(p->lambda) || !isfinite(p->mu) || p->lambda < 0 || p->mu < 0)
+    return GCP_E_ARG;
+  if (isnan(p->lower) || p->lower == INFINITY) return GCP_E_ARG;
+  if (p->tau_f < 0) return GCP_E_ARG;
+  if (!(p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps >= 0))
+    return GCP_E_ARG;
+  if ((p->flags & GCP_FLAG_PLAIN_SCRATCH) && p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
+  return GCP_OK;
+}
+
+WsLayout layout_for(const gcp_params* p) {
+  WsLayout L;
+  const size_t es = p->dtype == GCP_F64 ? 8 : 4;
+  const int I1 = (int)p->dims[0], I2 = (int)p->dims[1], I3 = (int)p->dims[2], R = p->rank;
+  const size_t omega = (size_t)I1 * I2 * I3;
+  L.fac_off[0] = 0;
+  L.fac_off[1] = (size_t)I1 * R;
+  L.fac_off[2] = L.fac_off[1] + (size_t)I2 * R;
+  L.fac_elems = L.fac_off[2] + (size_t)I3 * R;
+  const size_t fb = align_up(L.fac_elems * es, 256);
+  size_t off = 0;
+  L.status = off; off += 256;
+  L.A = off; off += fb;
+  L.Aold = off; off += fb;
+  L.u = off; off += fb;
+  L.v = off; off += fb;
+  L.G = off; off += fb;
+  L.gs = off; off = align_up(off + (size_t)R * es, 256);
+  L.loss = off; off += 256;
+  L.shist = off; off = align_up(off + (size_t)p->window * R * es, 256);
+  L.ring = off; off = align_up(off + (size_t)p->window * omega * es, 256);
+  L.part_bytes = dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
+  L.part = off; off = align_up(off + L.part_bytes, 256);
+  L.ls = off; off = align_up(off + ls_scratch_bytes(I1, I2, I3, R), 256);
+  L.plain_bytes = (p->flags & GCP_FLAG_PLAIN_SCRATCH) ? dense_plain_scratch_bytes(I1, I2, I3, R, p->dtype) : 0;
+  L.plain = off; off = align_up(off + L.plain_bytes, 256);
+  L.total = off;
+  return L;
+}
+
+bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+gcp_status check_dense_slice(const gcp_stream* s, const gcp_slice* X) {
+  if (!X || X->kind != GCP_SLICE_DENSE || !X->vals) return GCP_E_ARG;
+  if (!aligned16(X->vals)) return GCP_E_ALIGN;
+  return GCP_OK;
+}
+
+char* fac_ptr(gcp_stream* s, size_t block, int k) { return s->ws + block + s->L.fac_off[k] * s->es; }
+
+void fill_window(gcp_stream* s, DenseCall& c) {
+  int n = 1;
+  for (int slot = 0; slot < s->nwin; ++slot, ++n) {
+    c.X[n] = s->ws + s->L.ring + (size_t)slot * s->omega * s->es;
+    c.S[n] = s->ws + s->L.shist + (size_t)slot * s->p.rank * s->es;
+    c.c[n] = s->p.w * pow(s->p.theta, (double)(s->t - s->slot_t[slot]));
+  }
+  c.ns = n;
+}
+
+DenseCall base_call(gcp_stream* s) {
+  DenseCall c;
+  memset(&c, 0, sizeof(c));
+  c.I1 = s->dims[0];
+  c.I2 = s->dims[1];
+  c.I3 = s->dims[2];
+  c.R = s->p.rank;
+  c.loss = s->p.loss;
+  c.dtype = s->p.dtype;
+  c.lam = s->p.lambda;
+  c.mu = s->p.mu;
+  c.part = s->ws + s->L.part;
+  c.part_bytes = s->L.part_bytes;
+  c.status = s->status;
+  c.stream = s->st;
+  c.c[0] = 1.0;
+  return c;
+}
+
+gcp_status hip_status(hipError_t e) { return e == hipSuccess ? GCP_OK : GCP_E_DEVICE; }
+
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+void gcp_params_default(gcp_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->abi_version = GCP_ABI_VERSION;
+  p->d = 3;
+  p->rank = 1;
+  p->loss = GCP_LOSS_GAUSSIAN;
+  p->dtype = GCP_F32;
+  p->slice_kind = GCP_SLICE_DENSE;
+  p->w = 1.0;
+  p->theta = 1.0;
+  p->lambda = 0.0;
+  p->mu = 0.0;
+  p->lower = -INFINITY;
+  p->alpha_f = 1e-3;
+  p->beta1 = 0.9;
+  p->beta2 = 0.999;
+  p->adam_eps = 1e-8;
+  p->tau_f = 1;
+}
+
+gcp_status gcp_workspace_size(const gcp_params* p, size_t* bytes) {
+  if (!bytes) return GCP_E_ARG;
+  gcp_status st = check_params(p);
+  if (st != GCP_OK) return st;
+  *bytes = layout_for(p).total;
+  return GCP_OK;
+}
+
+gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n_hist, const gcp_slice* X_hist,
+                           const void* s_hist, const int64_t* t_hist, void* workspace, size_t ws_bytes,
+                           hipStream_t hip_stream, gcp_stream** out) {
+  if (!out) return GCP_E_ARG;
+  *out = nullptr;
+  gcp_status st = check_params(p);
+  if (st != GCP_OK) return st;
+  if (!A0 || !A0[0] || !A0[1] || !A0[2] || !workspace) return GCP_E_ARG;
+  if (n_hist < 0 || n_hist > p->window) return GCP_E_ARG;
+  if (n_hist > 0 && (!X_hist || !s_hist || !t_hist)) return GCP_E_ARG;
+  if (((uintptr_t)workspace & 255u) != 0) return GCP_E_ALIGN;
+  WsLayout L = layout_for(p);
+  if (ws_bytes < L.total) return GCP_E_WORKSPACE;
+  for (int h = 0; h < n_hist; ++h) {
+    if (X_hist[h].kind != GCP_SLICE_DENSE || !X_hist[h].vals) return GCP_E_ARG;
+    if (!aligned16(X_hist[h].vals)) return GCP_E_ALIGN;
+    if (h > 0 && t_hist[h] <= t_hist[h - 1]) return GCP_E_ARG;
+    if (t_hist[h] < 1) return GCP_E_ARG;
+  }
+  gcp_stream* s = new (std::nothrow) gcp_stream();
+  if (!s) return GCP_E_ARG;
+  s->p = *p;
+  s->es = p->dtype == GCP_F64 ? 8 : 4;
+  for (int k = 0; k < 3; ++k) s->dims[k] = (int)p->dims[k];
+  s->omega = (size_t)s->dims[0] * s->dims[1] * s->dims[2];
+  s->st = hip_stream;
+  s->ws = static_cast<char*>(workspace);
+  s->L = L;
+  s->status = reinterpret_cast<int*>(s->ws + L.status);
+  s->nwin = n_hist;
+  s->t = n_hist > 0 ? t_hist[n_hist - 1] + 1 : 1;
+  for (int h = 0; h < n_hist; ++h) s->slot_t[h] = t_hist[h];
+  hipError_t e = hipMemsetAsync(s->ws + L.status, 0, 256, s->st);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    size_t nb = (size_t)s->dims[k] * p->rank * s->es;
+    e = hipMemcpyAsync(fac_ptr(s, L.A, k), A0[k], nb, hipMemcpyDeviceToDevice, s->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(fac_ptr(s, L.Aold, k), A0[k], nb, hipMemcpyDeviceToDevice, s->st);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
+  for (int h = 0; h < n_hist && e == hipSuccess; ++h) {
+    e = hipMemcpyAsync(s->ws + L.ring + (size_t)h * s->omega * s->es, X_hist[h].vals, s->omega * s->es,
+                       hipMemcpyDeviceToDevice, s->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->ws + L.shist + (size_t)h * p->rank * s->es,
+                         static_cast<const char*>(s_hist) + (size_t)h * p->rank * s->es, p->rank * s->es,
+                         hipMemcpyDeviceToDevice, s->st);
+  }
+  if (e != hipSuccess) {
+    delete s;
+    return GCP_E_DEVICE;
+  }
+  *out = s;
+  return GCP_OK;
+}
+
+gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, uint32_t want,
+                         void* loss, void* const* G, void* g_s) {
+  if (!s || !A || !A[0] || !A[1] || !A[2] || !s_t) return GCP_E_ARG;
+  if (want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD | GCP_IMPL_PLAIN)) return GCP_E_ARG;
+  if (!(want & (GCP_WANT_LOSS | GCP_WANT_GRAD))) return GCP_E_ARG;
+  if ((want & GCP_WANT_LOSS) && !loss) return GCP_E_ARG;
+  if ((want & GCP_WANT_GRAD) && (!G || !G[0] || !G[1] || !G[2] || !g_s)) return GCP_E_ARG;
+  gcp_status st = check_dense_slice(s, X_t);
+  if (st != GCP_OK) return st;
+  const bool plain = want & GCP_IMPL_PLAIN;
+  if (plain && s->L.plain_bytes == 0) return GCP_E_STATE;
+  DenseCall c = base_call(s);
+  c.want = want & (GCP_WANT_LOSS | GCP_WANT_GRAD);
+  c.X[0] = X_t->vals;
+  c.S[0] = s_t;
+  fill_window(s, c);
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = A[k];
+    c.G[k] = (want & GCP_WANT_GRAD) ? G[k] : nullptr;
+  }
+  c.gs = (want & GCP_WANT_GRAD) ? g_s : nullptr;
+  c.loss_out = (want & GCP_WANT_LOSS) ? loss : nullptr;
+  if ((want & GCP_WANT_GRAD) == 0) {
+    // the fused kernel always forms gradients; route them to scratch
+    for (int k = 0; k < 3; ++k) c.G[k] = fac_ptr(s, s->L.G, k);
+    c.gs = s->ws + s->L.gs;
+  }
+  if (!plain && s->ev_used + 2 <= (int)s->ev.size()) {
+    c.ev_begin = s->ev[s->ev_used];
+    c.ev_end = s->ev[s->ev_used + 1];
+    s->ev_used += 2;
+  }
+  hipError_t e = plain ? dense_plain_run(c, s->ws + s->L.plain, s->L.plain_bytes) : dense_fused_run(c);
+  return hip_status(e);
+}
+
+gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
+  if (!s || !s_t) return GCP_E_ARG;
+  if (s->p.loss != GCP_LOSS_GAUSSIAN) return GCP_E_UNSUPPORTED;
+  gcp_status st = check_dense_slice(s, X_t);
+  if (st != GCP_OK) return st;
+  const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  return hip_status(ls_solve_run(s->dims[0], s->dims[1], s->dims[2], s->p.rank, s->p.dtype, X_t->vals, A, s->p.mu,
+                                 s->p.lower, s_t, s->ws + s->L.ls, s->status, s->st));
+}
+
+gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+  if (!s || !s_t) return GCP_E_ARG;
+  gcp_status st = check_dense_slice(s, X_t);
+  if (st != GCP_OK) return st;
+  const gcp_params& p = s->p;
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
+    DenseCall c = base_call(s);
+    c.want = kWantGrad;
+    c.X[0] = X_t->vals;
+    c.S[0] = s_t;
+    fill_window(s, c);
+    for (int k = 0; k < 3; ++k) {
+      c.A[k] = fac_ptr(s, s->L.A, k);
+      c.G[k] = fac_ptr(s, s->L.G, k);
+    }
+    c.gs = s->ws + s->L.gs;
+    e = dense_fused_run(c);
+    if (e != hipSuccess) break;
+    const double n = (double)(s->adam_i + 1);
+    const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
+    e = adam_run(p.dtype, (int64_t)s->L.fac_elems, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u,
+                 s->ws + s->L.v, alpha_t, p.beta1, p.beta2, p.adam_eps, p.lower, s->st);
+    s->adam_i += 1;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ws + s->L.Aold, s->ws + s->L.A, s->L.fac_elems * s->es, hipMemcpyDeviceToDevice, s->st);
+  // reservoir window update (Algorithm 1), then t <- t+1
+  int slot = -1;
+  if (p.window > 0) {
+    if (s->nwin < p.window) {
+      slot = s->nwin++;
+    } else {
+      uint64_t j = splitmix64(p.seed ^ (uint64_t)s->t) % (uint64_t)s->t + 1;
+      if (j <= (uint64_t)p.window) slot = (int)(j - 1);
+    }
+  }
+  if (slot >= 0 && e == hipSuccess) {
+    e = hipMemcpyAsync(s->ws + s->L.ring + (size_t)slot * s->omega * s->es, X_t->vals, s->omega * s->es,
+                       hipMemcpyDeviceToDevice, s->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->ws + s->L.shist + (size_t)slot * p.rank * s->es, s_t, p.rank * s->es,
+                         hipMemcpyDeviceToDevice, s->st);
+    s->slot_t[slot] = s->t;
+  }
+  s->t += 1;
+  return hip_status(e);
+}
+
+gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out) {
+  if (!s || !A_out || !A_out[0] || !A_out[1] || !A_out[2]) return GCP_E_ARG;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 3 && e == hipSuccess; ++k)
+    e = hipMemcpyAsync(A_out[k], fac_ptr(s, s->L.A, k), (size_t)s->dims[k] * s->p.rank * s->es,
+                       hipMemcpyDeviceToDevice, s->st);
+  return hip_status(e);
+}
+
+gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr) {
+  if (!s || !ptr || k < 0 || k > 2) return GCP_E_ARG;
+  *ptr = fac_ptr(s, s->L.A, k);
+  return GCP_OK;
+}
+
+gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window, int64_t* adam_iter, int64_t* slot_times) {
+  if (!s) return GCP_E_ARG;
+  if (t) *t = s->t;
+  if (n_window) *n_window = s->nwin;
+  if (adam_iter) *adam_iter = s->adam_i;
+  if (slot_times)
+    for (int h = 0; h < s->p.window; ++h) slot_times[h] = h < s->nwin ? s->slot_t[h] : 0;
+  return GCP_OK;
+}
+
+gcp_status gcp_stream_sync(gcp_stream* s) {
+  if (!s) return GCP_E_ARG;
+  if (hipStreamSynchronize(s->st) != hipSuccess) return GCP_E_DEVICE;
+  int word = 0;
+  if (hipMemcpy(&word, s->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return GCP_E_DEVICE;
+  if (word != 0) {
+    if (hipMemset(s->status, 0, sizeof(int)) != hipSuccess) return GCP_E_DEVICE;
+    return GCP_E_NUMERIC;
+  }
+  return GCP_OK;
+}
+
+gcp_status gcp_kernel_timing(gcp_stream* s, int32_t enable, int32_t capacity) {
+  if (!s || capacity < 0) return GCP_E_ARG;
+  if (hipStreamSynchronize(s->st) != hipSuccess) return GCP_E_DEVICE;
+  for (hipEvent_t e : s->ev) hipEventDestroy(e);
+  s->ev.clear();
+  s->ev_used = 0;
+  if (!enable) return GCP_OK;
+  s->ev.resize((size_t)capacity * 2);
+  for (auto& e : s->ev)
+    if (hipEventCreate(&e) != hipSuccess) return GCP_E_DEVICE;
+  return GCP_OK;
+}
+
+gcp_status gcp_kernel_time(gcp_stream* s, double* total_ms, int64_t* count) {
+  if (!s || !total_ms || !count) return GCP_E_ARG;
+  double tot = 0.0;
+  for (int i = 0; i + 1 < s->ev_used; i += 2) {
+    if (hipEventSynchronize(s->ev[i + 1]) != hipSuccess) return GCP_E_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]) != hipSuccess) return GCP_E_DEVICE;
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = s->ev_used / 2;
+  s->ev_used = 0;
+  return GCP_OK;
+}
+
+gcp_status gcp_stream_destroy(gcp_stream* s) {
+  if (!s) return GCP_E_ARG;
+  hipStreamSynchronize(s->st);
+  for (hipEvent_t e : s->ev) hipEventDestroy(e);
+  delete s;
+  return GCP_OK;
+}
+
+const char* gcp_status_string(gcp_status st) {
+  switch (st) {
+    case GCP_OK: return "ok";
+    case GCP_E_ARG: return "invalid argument";
+    case GCP_E_SHAPE: return "shape mismatch";
+    case GCP_E_ALIGN: return "misaligned pointer";
+    case GCP_E_STATE: return "invalid stream state";
+    case GCP_E_WORKSPACE: return "workspace too small";
+    case GCP_E_DEVICE: return "HIP runtime error";
+    case GCP_E_NUMERIC: return "non-finite value or failed pivot on the device";
+    case GCP_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal interfaces between the C-ABI shell (abi.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gcp {
+
+constexpr int kMaxNs = 65;        // current slice + window of at most 64
+constexpr int kMaxRank = 64;
+
+enum Loss { kGaussian = 0, kPoissonLog = 1, kBernoulliLogit = 2 };
+enum Want { kWantLoss = 1, kWantGrad = 2 };
+
+// Deferred device status bits (workspace word).
+enum StatusBits { kStatusNonFinite = 1, kStatusPivot = 2, kStatusSampler = 4 };
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Elementwise loss and derivative (Section 2.2 with log / logit links).
+template <typename T, int LOSS>
+struct LossFn;
+
+template <typename T>
+struct LossFn<T, kGaussian> {
+  __device__ __forceinline__ static void eval(T x, T m, T& f, T& y) {
+    T d = m - x;
+    f = d * d;
+    y = d + d;
+  }
+};
+
+template <typename T>
+struct LossFn<T, kPoissonLog> {
+  __device__ __forceinline__ static void eval(T x, T m, T& f, T& y) {
+    T e = exp(m);
+    f = e - x * m;
+    y = e - x;
+  }
+};
+
+template <typename T>
+struct LossFn<T, kBernoulliLogit> {
+  __device__ __forceinline__ static void eval(T x, T m, T& f, T& y) {
+    // log(1+e^m) = max(m,0) + log1p(e^-|m|); sigmoid from the same e^-|m|
+    T e = exp(-fabs(m));
+    T inv = T(1) / (T(1) + e);
+    T sig = m >= T(0) ? inv : e * inv;
+    f = fmax(m, T(0)) + log1p(e) - x * m;
+    y = sig - x;
+  }
+};
+
+// Kahan-compensated accumulation.
+template <typename T>
+struct Kahan {
+  T s = 0, c = 0;
+  __device__ __forceinline__ void add(T v) {
+    T yv = v - c;
+    T t = s + yv;
+    c = (t - s) - yv;
+    s = t;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Dense fused objective / gradient over the current slice and the window.
+struct DenseCall {
+  int I1, I2, I3, R;
+  int ns;                       // 1 + number of window slices
+  int loss;
+  int want;
+  int dtype;                    // 0 = f32, 1 = f64
+  const void* X[kMaxNs];        // slice h (0 = current)
+  const void* S[kMaxNs];        // weight row of slice h (R values)
+  double c[kMaxNs];             // c_0 = 1, c_h = w theta^(t-h)
+  const void* A[3];
+  void* G[3];
+  void* gs;
+  void* loss_out;
+  double lam, mu;
+  void* part;                   // partial-sum scratch (workspace)
+  size_t part_bytes;
+  int* status;
+  hipStream_t stream;
+  hipEvent_t ev_begin;          // optional: recorded around the main kernel
+  hipEvent_t ev_end;
+};
+
+size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype);
+hipError_t dense_fused_run(const DenseCall& c);
+
+// Unfused baseline: model, elementwise, per-mode MTTKRP kernels.
+size_t dense_plain_scratch_bytes(int I1, int I2, int I3, int R, int dtype);
+hipError_t dense_plain_run(const DenseCall& c, void* scratch, size_t scratch_bytes);
+
+// Least-squares temporal solve (FP64 normal equations).
+size_t ls_scratch_bytes(int I1, int I2, int I3, int R);
+hipError_t ls_solve_run(int I1, int I2, int I3, int R, int dtype, const void* X,
+                        const void* const* A, double mu, double lower, void* s_out,
+                        void* scratch, int* status, hipStream_t st);
+
+// ADAM step over a flat array (Algorithm 2, Step).
+hipError_t adam_run(int dtype, int64_t n, void* a, const void* g, void* u, void* v,
+                    double alpha_t, double beta1, double beta2, double eps,
+                    double lower, hipStream_t st);
+
+}  // namespace gcp

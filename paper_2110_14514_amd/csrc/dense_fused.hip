@@ -1,0 +1,416 @@
+// Fused single-pass objective and gradient over a dense slice and its window.
+//
+// For every entry i of the slice and every slice h of {t} u H_t this computes
+// the model m_ih = sum_j s_hj prod_k A^(k)[i_k,j] (eq. CP_model with the
+// historical model of eq. gcp_stream_problem_1: stored weight, current
+// factors), the loss f and derivative y (Section 2.2), and contracts
+//   yhat_ij = sum_h c_h y_ih s_hj
+// with the Khatri-Rao rows to give all three factor gradients at once
+// (eq. gcp_grad_A per slice, summed with the history weights c_h), plus the
+// temporal-weight gradient from the current slice only (eq. gcp_grad_lambda).
+// Y, M and the Khatri-Rao matrices are never materialised.
+//
+// Work decomposition: a workgroup (4 waves) owns a tile of TB1 x TB2 index
+// pairs (i1,i2) and all of I3.  Lanes run along i3 (coalesced loads of each
+// slice row), waves split the tile's pairs.  Per pair, mode-3 contributions
+// stay lane-local; the mode-1/2 vector V = sum_i3 yhat * A3[i3] is reduced
+// across the wave with a reduce-scatter and added into per-wave LDS rows.
+// Partial results of each tile go to a partial buffer that a second kernel
+// sums in a fixed order, so results are bitwise reproducible (no atomics).
+#include "common.hpp"
+
+namespace gcp {
+namespace {
+
+constexpr int kNW = 4;
+constexpr int kWG = 64 * kNW;
+constexpr int kTBMax = 16;
+
+template <typename T>
+struct FusedArgs {
+  const T* X[kMaxNs];
+  const T* S[kMaxNs];
+  T c[kMaxNs];
+  const T* A1;
+  const T* A2;
+  const T* A3;
+  T* G1p;
+  T* G2p;
+  T* G3p;
+  T* gsp;
+  T* lossp;
+  int I1, I2, I3, R, ns, want, tb1, tb2, nb2;
+};
+
+struct Tiling {
+  int tb1, tb2, nb1, nb2, ntiles;
+};
+
+Tiling tiling_for(int I1, int I2) {
+  long pairs = (long)I1 * I2;
+  int tb = pairs >= 200000 ? 16 : (pairs >= 4096 ? 8 : 4);
+  Tiling t;
+  t.tb1 = t.tb2 = tb;
+  t.nb1 = (I1 + tb - 1) / tb;
+  t.nb2 = (I2 + tb - 1) / tb;
+  t.ntiles = t.nb1 * t.nb2;
+  return t;
+}
+
+struct PartLayout {
+  size_t g1, g2, g3, gs, loss, total;
+};
+
+PartLayout part_layout(int I1, int I2, int I3, int R, size_t es) {
+  Tiling t = tiling_for(I1, I2);
+  PartLayout p;
+  size_t off = 0;
+  p.g1 = off; off = align_up(off + (size_t)t.nb2 * I1 * R * es, 256);
+  p.g2 = off; off = align_up(off + (size_t)t.nb1 * I2 * R * es, 256);
+  p.g3 = off; off = align_up(off + (size_t)t.ntiles * I3 * R * es, 256);
+  p.gs = off; off = align_up(off + (size_t)t.ntiles * R * es, 256);
+  p.loss = off; off = align_up(off + (size_t)t.ntiles * es, 256);
+  p.total = off;
+  return p;
+}
+
+// Reduce-scatter of RT per-lane values over the 64 lanes of a wave.  On
+// return the lane holds the wave sum of element jl = lane >> (6 - log2 RT);
+// lanes with (lane & (64/RT - 1)) == 0 hold the primary copy.
+template <typename T, int RT>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[RT], int lane) {
+  int mask = 32;
+#pragma unroll
+  for (int half = RT / 2; half >= 1; half /= 2) {
+    const bool hi = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      T send = hi ? v[i] : v[i + half];
+      T keep = hi ? v[i + half] : v[i];
+      v[i] = keep + __shfl_xor(send, mask);
+    }
+    mask >>= 1;
+  }
+  T r = v[0];
+  for (; mask >= 1; mask >>= 1) r += __shfl_xor(r, mask);
+  return r;
+}
+
+template <int RT>
+__device__ __forceinline__ int log2c() {
+  return RT == 1 ? 0 : RT == 2 ? 1 : RT == 4 ? 2 : RT == 8 ? 3 : RT == 16 ? 4 : RT == 32 ? 5 : 6;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+template <typename T, int LOSS, int RT>
+__global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
+  __shared__ T a1s[kTBMax][RT];
+  __shared__ T a2s[kTBMax][RT];
+  __shared__ T g1w[kNW][kTBMax][RT];
+  __shared__ T g2w[kNW][kTBMax][RT];
+  __shared__ T g3x[64][RT + 1];
+  __shared__ T gsx[kNW][RT];
+  __shared__ T lsx[kNW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tile = blockIdx.x;
+  const int b1 = tile / a.nb2;
+  const int b2 = tile % a.nb2;
+  const int i10 = b1 * a.tb1;
+  const int i20 = b2 * a.tb2;
+  const int n1 = min(a.tb1, a.I1 - i10);
+  const int n2 = min(a.tb2, a.I2 - i20);
+  const int R = a.R;
+  const int I2 = a.I2, I3 = a.I3;
+  const bool want_loss = a.want & kWantLoss;
+
+  for (int idx = tid; idx < kTBMax * RT; idx += kWG) {
+    int r = idx / RT, j = idx % RT;
+    a1s[r][j] = (r < n1 && j < R) ? a.A1[(size_t)(i10 + r) * R + j] : T(0);
+    a2s[r][j] = (r < n2 && j < R) ? a.A2[(size_t)(i20 + r) * R + j] : T(0);
+  }
+  for (int idx = tid; idx < kNW * kTBMax * RT; idx += kWG) {
+    (&g1w[0][0][0])[idx] = T(0);
+    (&g2w[0][0][0])[idx] = T(0);
+  }
+  __syncthreads();
+
+  T gs[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) gs[j] = T(0);
+  Kahan<T> lacc;
+  const int npairs = n1 * n2;
+  const int jl = lane >> (6 - log2c<RT>());
+  const bool primary = (lane & ((64 / RT) - 1)) == 0;
+
+  for (int c0 = 0; c0 < I3; c0 += 64) {
+    const int i3 = c0 + lane;
+    const bool valid = i3 < I3;
+    T a3r[RT], g3[RT];
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+      a3r[j] = (valid && j < R) ? a.A3[(size_t)i3 * R + j] : T(0);
+      g3[j] = T(0);
+    }
+    for (int q = wave; q < npairs; q += kNW) {
+      const int i1l = q / n2, i2l = q % n2;
+      T W[RT], P[RT], yh[RT];
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        W[j] = a1s[i1l][j] * a2s[i2l][j];
+        P[j] = W[j] * a3r[j];
+        yh[j] = T(0);
+      }
+      const size_t off = ((size_t)(i10 + i1l) * I2 + (i20 + i2l)) * I3 + (valid ? i3 : 0);
+      for (int h = 0; h < a.ns; ++h) {
+        const T* Sh = a.S[h];
+        T x = valid ? a.X[h][off] : T(0);
+        T m = T(0);
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+          if (j < R) m += P[j] * Sh[j];
+        T f, y;
+        LossFn<T, LOSS>::eval(x, m, f, y);
+        const T ch = a.c[h];
+        if (want_loss && valid) lacc.add(ch * f);
+        y = valid ? y * ch : T(0);
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+          if (j < R) yh[j] += y * Sh[j];
+        if (h == 0) {
+#pragma unroll
+          for (int j = 0; j < RT; ++j) gs[j] += y * P[j];
+        }
+      }
+      T V[RT];
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        g3[j] += yh[j] * W[j];
+        V[j] = yh[j] * a3r[j];
+      }
+      T v = wave_reduce_scatter<T, RT>(V, lane);
+      if (primary) {
+        g1w[wave][i1l][jl] += v * a2s[i2l][jl];
+        g2w[wave][i2l][jl] += v * a1s[i1l][jl];
+      }
+    }
+    // combine the waves' mode-3 partials for this chunk in a fixed order
+    for (int w = 0; w < kNW; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int j = 0; j < RT; ++j) g3x[lane][j] = (w == 0 ? T(0) : g3x[lane][j]) + g3[j];
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < 64 * RT; idx += kWG) {
+      int l = idx / RT, j = idx % RT;
+      if (c0 + l < I3 && j < R) a.G3p[((size_t)tile * I3 + c0 + l) * R + j] = g3x[l][j];
+    }
+    __syncthreads();
+  }
+
+  // temporal-weight gradient and loss partials
+  {
+    T v = wave_reduce_scatter<T, RT>(gs, lane);
+    if (primary) gsx[wave][jl] = v;
+    T ls = wave_sum(lacc.s);
+    if (lane == 0) lsx[wave] = ls;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kTBMax * RT; idx += kWG) {
+    int l = idx / RT, j = idx % RT;
+    if (j < R) {
+      if (l < n1) {
+        T s = g1w[0][l][j];
+        for (int w = 1; w < kNW; ++w) s += g1w[w][l][j];
+        a.G1p[((size_t)b2 * a.I1 + i10 + l) * R + j] = s;
+      }
+      if (l < n2) {
+        T s = g2w[0][l][j];
+        for (int w = 1; w < kNW; ++w) s += g2w[w][l][j];
+        a.G2p[((size_t)b1 * I2 + i20 + l) * R + j] = s;
+      }
+    }
+  }
+  if (tid < R) {
+    T s = gsx[0][tid];
+    for (int w = 1; w < kNW; ++w) s += gsx[w][tid];
+    a.gsp[(size_t)tile * R + tid] = s;
+  }
+  if (tid == 0) {
+    T s = lsx[0];
+    for (int w = 1; w < kNW; ++w) s += lsx[w];
+    a.lossp[tile] = s;
+  }
+}
+
+template <typename T>
+struct ReduceArgs {
+  const T* G1p;
+  const T* G2p;
+  const T* G3p;
+  const T* gsp;
+  const T* lossp;
+  const T* A1;
+  const T* A2;
+  const T* A3;
+  const T* st;
+  T* G1;
+  T* G2;
+  T* G3;
+  T* gs;
+  T* loss;
+  T lam, mu;
+  int I1, I2, I3, R, nb1, nb2, ntiles, want, gblocks;
+  int* status;
+};
+
+template <typename T>
+__device__ __forceinline__ void flag_nonfinite(T v, int* status) {
+  if (!isfinite(v)) atomicOr(status, (int)kStatusNonFinite);
+}
+
+// Sums the per-tile partials in tile order (Kahan), adds the regularisation
+// gradients, and (last workgroup) forms the objective.
+template <typename T>
+__global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
+  const int R = r.R;
+  if ((int)blockIdx.x < r.gblocks) {
+    const int n1 = r.I1 * R, n2 = r.I2 * R, n3 = r.I3 * R;
+    const int total = n1 + n2 + n3 + R;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += r.gblocks * blockDim.x) {
+      Kahan<T> k;
+      T out;
+      if (idx < n1) {
+        for (int b = 0; b < r.nb2; ++b) k.add(r.G1p[(size_t)b * n1 + idx]);
+        out = k.s + r.lam * r.A1[idx];
+        r.G1[idx] = out;
+      } else if (idx < n1 + n2) {
+        int e = idx - n1;
+        for (int b = 0; b < r.nb1; ++b) k.add(r.G2p[(size_t)b * n2 + e]);
+        out = k.s + r.lam * r.A2[e];
+        r.G2[e] = out;
+      } else if (idx < n1 + n2 + n3) {
+        int e = idx - n1 - n2;
+        for (int b = 0; b < r.ntiles; ++b) k.add(r.G3p[(size_t)b * n3 + e]);
+        out = k.s + r.lam * r.A3[e];
+        r.G3[e] = out;
+      } else {
+        int j = idx - n1 - n2 - n3;
+        for (int b = 0; b < r.ntiles; ++b) k.add(r.gsp[(size_t)b * R + j]);
+        out = k.s + r.mu * r.st[j];
+        r.gs[j] = out;
+      }
+      flag_nonfinite(out, r.status);
+    }
+    return;
+  }
+  // objective: data partials + lambda/2 sum ||A||^2 + mu/2 ||s||^2
+  __shared__ T red[256];
+  Kahan<T> k;
+  for (int b = threadIdx.x; b < r.ntiles; b += 256) k.add(r.lossp[b]);
+  Kahan<T> kr;
+  const T* mats[3] = {r.A1, r.A2, r.A3};
+  const int rows[3] = {r.I1, r.I2, r.I3};
+  for (int m = 0; m < 3; ++m)
+    for (int e = threadIdx.x; e < rows[m] * R; e += 256) kr.add(mats[m][e] * mats[m][e]);
+  Kahan<T> ks;
+  for (int j = threadIdx.x; j < R; j += 256) ks.add(r.st[j] * r.st[j]);
+  red[threadIdx.x] = k.s + T(0.5) * r.lam * kr.s + T(0.5) * r.mu * ks.s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    r.loss[0] = red[0];
+    flag_nonfinite(red[0], r.status);
+  }
+}
+
+template <typename T, int LOSS, int RT>
+hipError_t launch_fused(const DenseCall& c, const Tiling& tl, const PartLayout& pl) {
+  FusedArgs<T> a;
+  for (int h = 0; h < c.ns; ++h) {
+    a.X[h] = static_cast<const T*>(c.X[h]);
+    a.S[h] = static_cast<const T*>(c.S[h]);
+    a.c[h] = static_cast<T>(c.c[h]);
+  }
+  char* base = static_cast<char*>(c.part);
+  a.A1 = static_cast<const T*>(c.A[0]);
+  a.A2 = static_cast<const T*>(c.A[1]);
+  a.A3 = static_cast<const T*>(c.A[2]);
+  a.G1p = reinterpret_cast<T*>(base + pl.g1);
+  a.G2p = reinterpret_cast<T*>(base + pl.g2);
+  a.G3p = reinterpret_cast<T*>(base + pl.g3);
+  a.gsp = reinterpret_cast<T*>(base + pl.gs);
+  a.lossp = reinterpret_cast<T*>(base + pl.loss);
+  a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
+  a.tb1 = tl.tb1; a.tb2 = tl.tb2; a.nb2 = tl.nb2;
+  if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);
+  hipLaunchKernelGGL((fused_dense_v1<T, LOSS, RT>), dim3(tl.ntiles), dim3(kWG), 0, c.stream, a);
+  hipError_t e = hipGetLastError();
+  if (c.ev_end) hipEventRecord(c.ev_end, c.stream);
+  if (e != hipSuccess) return e;
+
+  ReduceArgs<T> r;
+  r.G1p = a.G1p; r.G2p = a.G2p; r.G3p = a.G3p; r.gsp = a.gsp; r.lossp = a.lossp;
+  r.A1 = a.A1; r.A2 = a.A2; r.A3 = a.A3;
+  r.st = static_cast<const T*>(c.S[0]);
+  r.G1 = static_cast<T*>(c.G[0]);
+  r.G2 = static_cast<T*>(c.G[1]);
+  r.G3 = static_cast<T*>(c.G[2]);
+  r.gs = static_cast<T*>(c.gs);
+  r.loss = static_cast<T*>(c.loss_out);
+  r.lam = (T)c.lam; r.mu = (T)c.mu;
+  r.I1 = c.I1; r.I2 = c.I2; r.I3 = c.I3; r.R = c.R;
+  r.nb1 = tl.nb1; r.nb2 = tl.nb2; r.ntiles = tl.ntiles; r.want = c.want;
+  r.status = c.status;
+  const int total = (c.I1 + c.I2 + c.I3 + 1) * c.R;
+  r.gblocks = (c.want & kWantGrad) ? std::min(1024, (total + 255) / 256) : 0;
+  const int blocks = r.gblocks + ((c.want & kWantLoss) ? 1 : 0);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((fused_reduce<T>), dim3(blocks), dim3(256), 0, c.stream, r);
+  return hipGetLastError();
+}
+
+template <typename T, int LOSS>
+hipError_t dispatch_rank(const DenseCall& c, const Tiling& tl, const PartLayout& pl) {
+  if (c.R <= 4) return launch_fused<T, LOSS, 4>(c, tl, pl);
+  if (c.R <= 8) return launch_fused<T, LOSS, 8>(c, tl, pl);
+  if (c.R <= 16) return launch_fused<T, LOSS, 16>(c, tl, pl);
+  if (c.R <= 32) return launch_fused<T, LOSS, 32>(c, tl, pl);
+  return launch_fused<T, LOSS, 64>(c, tl, pl);
+}
+
+template <typename T>
+hipError_t dispatch_loss(const DenseCall& c, const Tiling& tl, const PartLayout& pl) {
+  switch (c.loss) {
+    case kGaussian: return dispatch_rank<T, kGaussian>(c, tl, pl);
+    case kPoissonLog: return dispatch_rank<T, kPoissonLog>(c, tl, pl);
+    default: return dispatch_rank<T, kBernoulliLogit>(c, tl, pl);
+  }
+}
+
+}  // namespace
+
+size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype) {
+  return part_layout(I1, I2, I3, R, dtype ? sizeof(double) : sizeof(float)).total;
+}
+
+hipError_t dense_fused_run(const DenseCall& c) {
+  Tiling tl = tiling_for(c.I1, c.I2);
+  PartLayout pl = part_layout(c.I1, c.I2, c.I3, c.R, c.dtype ? sizeof(double) : sizeof(float));
+  if (pl.total > c.part_bytes) return hipErrorInvalidValue;
+  return c.dtype ? dispatch_loss<double>(c, tl, pl) : dispatch_loss<float>(c, tl, pl);
+}
+
+}  // namespace gcp

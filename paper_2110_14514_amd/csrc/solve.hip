@@ -1,0 +1,176 @@
+// Least-squares temporal-weight solve for the Gaussian loss (Section 5: one
+// least-squares solve replaces the SGD temporal solver of Algorithm 3).
+//
+// The temporal subproblem (eq. gcp_stream_temporal_problem) with
+// f = (x-m)^2 and m = Z s is stationary where
+//     (Gamma + mu/2 I) s = b,   Gamma = hadamard_k A^(k)^T A^(k),
+//                               b = Z^T vec(X_t).
+// Pass 1 streams X_t once and forms per-workgroup partials of b in FP32.
+// Pass 2 (one workgroup) sums the partials in FP64, forms Gamma in FP64, and
+// solves by an FP64 Cholesky factorisation in LDS; then s <- max(s, l).
+#include "common.hpp"
+
+namespace gcp {
+namespace {
+
+constexpr int kPairChunk = 64;
+
+struct LsLayout {
+  int nchunks, ygs;
+  size_t bytes;
+};
+
+LsLayout ls_layout(int I1, int I2, int I3, int R) {
+  LsLayout L;
+  L.nchunks = (int)(((size_t)I1 * I2 + kPairChunk - 1) / kPairChunk);
+  L.ygs = (I3 + 255) / 256;
+  L.bytes = align_up((size_t)L.nchunks * L.ygs * R * sizeof(double), 256);
+  return L;
+}
+
+// b partials: workgroup (chunk of pairs, block of 256 i3): thread i3 sums
+// x * A1[i1] * A2[i2] * A3[i3] over the chunk's pairs.
+template <typename T, int RT>
+__global__ void __launch_bounds__(256) k_ls_b(const T* __restrict__ X, const T* __restrict__ A1,
+                                              const T* __restrict__ A2, const T* __restrict__ A3,
+                                              double* __restrict__ bp, int I1, int I2, int I3, int R) {
+  __shared__ T sm[4][RT];
+  const int chunk = blockIdx.x;
+  const int i3 = blockIdx.y * 256 + threadIdx.x;
+  const size_t p0 = (size_t)chunk * kPairChunk;
+  const size_t npairs = (size_t)I1 * I2;
+  T acc[RT];
+  for (int j = 0; j < RT; ++j) acc[j] = T(0);
+  if (i3 < I3) {
+    T a3[RT];
+    for (int j = 0; j < RT; ++j) a3[j] = j < R ? A3[(size_t)i3 * R + j] : T(0);
+    for (size_t p = p0; p < p0 + kPairChunk && p < npairs; ++p) {
+      int i1 = (int)(p / I2), i2 = (int)(p - (size_t)i1 * I2);
+      T x = X[p * I3 + i3];
+      for (int j = 0; j < RT; ++j)
+        if (j < R) acc[j] += x * A1[(size_t)i1 * R + j] * A2[(size_t)i2 * R + j] * a3[j];
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < RT; ++j) {
+    T v = acc[j];
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) sm[wave][j] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < R) {
+    int j = threadIdx.x;
+    double v = (((double)sm[0][j] + (double)sm[1][j]) + (double)sm[2][j]) + (double)sm[3][j];
+    bp[((size_t)chunk * gridDim.y + blockIdx.y) * R + j] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_ls_solve(const double* __restrict__ bp, int nparts,
+                                                  const T* __restrict__ A1, const T* __restrict__ A2,
+                                                  const T* __restrict__ A3, int I1, int I2, int I3, int R,
+                                                  double half_mu, double lower, T* __restrict__ s_out,
+                                                  int* status) {
+  __shared__ double L[kMaxRank][kMaxRank + 1];
+  __shared__ double b[kMaxRank];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  // b = sum of partials (fixed order)
+  for (int j = tid; j < R; j += 256) {
+    double s = 0.0;
+    for (int c = 0; c < nparts; ++c) s += bp[(size_t)c * R + j];
+    b[j] = s;
+  }
+  // Gamma[r][c] = prod_k sum_i A_k[i][r] A_k[i][c]  (FP64)
+  for (int idx = tid; idx < R * R; idx += 256) {
+    int r = idx / R, c = idx % R;
+    if (c > r) continue;
+    const T* mats[3] = {A1, A2, A3};
+    const int rows[3] = {I1, I2, I3};
+    double g = 1.0;
+    for (int k = 0; k < 3; ++k) {
+      double d = 0.0;
+      for (int i = 0; i < rows[k]; ++i) d += (double)mats[k][(size_t)i * R + r] * (double)mats[k][(size_t)i * R + c];
+      g *= d;
+    }
+    if (r == c) g += half_mu;
+    L[r][c] = g;
+  }
+  __syncthreads();
+  // right-looking Cholesky, lower triangle in place
+  for (int k = 0; k < R; ++k) {
+    if (tid == 0) {
+      double d = L[k][k];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        d = 1.0;
+      }
+      L[k][k] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < R; i += 256) L[i][k] /= L[k][k];
+    __syncthreads();
+    for (int idx = tid; idx < R * R; idx += 256) {
+      int i = idx / R, j = idx % R;
+      if (j > k && i >= j) L[i][j] -= L[i][k] * L[j][k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    // L y = b ; L^T s = y
+    for (int i = 0; i < R; ++i) {
+      double v = b[i];
+      for (int j = 0; j < i; ++j) v -= L[i][j] * b[j];
+      b[i] = v / L[i][i];
+    }
+    for (int i = R - 1; i >= 0; --i) {
+      double v = b[i];
+      for (int j = i + 1; j < R; ++j) v -= L[j][i] * b[j];
+      b[i] = v / L[i][i];
+    }
+    if (bad) atomicOr(status, (int)kStatusPivot);
+  }
+  __syncthreads();
+  for (int j = tid; j < R; j += 256) {
+    double v = bad ? (double)NAN : fmax(b[j], lower);
+    s_out[j] = (T)v;
+  }
+}
+
+template <typename T, int RT>
+hipError_t run_ls(int I1, int I2, int I3, int R, const void* X, const void* const* A, double mu, double lower,
+                  void* s_out, void* scratch, int* status, hipStream_t st) {
+  LsLayout L = ls_layout(I1, I2, I3, R);
+  double* bp = static_cast<double*>(scratch);
+  hipLaunchKernelGGL((k_ls_b<T, RT>), dim3(L.nchunks, L.ygs), dim3(256), 0, st, static_cast<const T*>(X),
+                     static_cast<const T*>(A[0]), static_cast<const T*>(A[1]), static_cast<const T*>(A[2]), bp,
+                     I1, I2, I3, R);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ls_solve<T>), dim3(1), dim3(256), 0, st, bp, L.nchunks * L.ygs,
+                     static_cast<const T*>(A[0]), static_cast<const T*>(A[1]), static_cast<const T*>(A[2]), I1,
+                     I2, I3, R, 0.5 * mu, lower, static_cast<T*>(s_out), status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_ls_t(int I1, int I2, int I3, int R, const void* X, const void* const* A, double mu, double lower,
+                    void* s_out, void* scratch, int* status, hipStream_t st) {
+  if (R <= 8) return run_ls<T, 8>(I1, I2, I3, R, X, A, mu, lower, s_out, scratch, status, st);
+  if (R <= 16) return run_ls<T, 16>(I1, I2, I3, R, X, A, mu, lower, s_out, scratch, status, st);
+  if (R <= 32) return run_ls<T, 32>(I1, I2, I3, R, X, A, mu, lower, s_out, scratch, status, st);
+  return run_ls<T, 64>(I1, I2, I3, R, X, A, mu, lower, s_out, scratch, status, st);
+}
+
+}  // namespace
+
+size_t ls_scratch_bytes(int I1, int I2, int I3, int R) { return ls_layout(I1, I2, I3, R).bytes; }
+
+hipError_t ls_solve_run(int I1, int I2, int I3, int R, int dtype, const void* X, const void* const* A, double mu,
+                        double lower, void* s_out, void* scratch, int* status, hipStream_t st) {
+  return dtype ? run_ls_t<double>(I1, I2, I3, R, X, A, mu, lower, s_out, scratch, status, st)
+               : run_ls_t<float>(I1, I2, I3, R, X, A, mu, lower, s_out, scratch, status, st);
+}
+
+}  // namespace gcp

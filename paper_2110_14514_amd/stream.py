@@ -1,0 +1,189 @@
+"""Python handle over the C ABI.  PyTorch supplies device memory (the
+workspace, outputs) and the HIP stream; every computation runs in the
+library's kernels.  Function names mirror the C calls."""
+from __future__ import annotations
+
+import ctypes
+import math
+from ctypes import byref, c_int32, c_int64, c_size_t, c_void_p
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _native as N
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+def _ptr_array(ts: Sequence[torch.Tensor]):
+    arr = (c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _dense_slice(x: torch.Tensor) -> N.GcpSlice:
+    if not x.is_contiguous():
+        raise ValueError("dense slices must be contiguous (row-major)")
+    return N.GcpSlice(N.SLICE_DENSE, 0, x.data_ptr(), None, 0)
+
+
+def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
+                lam=0.0, mu=0.0, lower=-math.inf, alpha_f=1e-3, beta1=0.9,
+                beta2=0.999, adam_eps=1e-8, tau_f=1, seed=0,
+                dtype=torch.float32, plain=False) -> N.GcpParams:
+    lib = N.load()
+    p = N.GcpParams()
+    lib.gcp_params_default(byref(p))
+    p.d = len(dims)
+    for k, n in enumerate(list(dims)[:3]):
+        p.dims[k] = int(n)
+    p.rank = int(rank)
+    p.window = int(window)
+    p.loss = N.LOSS_IDS[loss]
+    p.dtype = N.F64 if dtype == torch.float64 else N.F32
+    p.flags = N.FLAG_PLAIN_SCRATCH if plain else 0
+    p.w, p.theta, p.lam, p.mu, p.lower = float(w), float(theta), float(lam), float(mu), float(lower)
+    p.alpha_f, p.beta1, p.beta2, p.adam_eps = float(alpha_f), float(beta1), float(beta2), float(adam_eps)
+    p.tau_f = int(tau_f)
+    p.seed = int(seed) & ((1 << 64) - 1)
+    return p
+
+
+def gcp_workspace_size(params: N.GcpParams) -> int:
+    lib = N.load()
+    n = c_size_t(0)
+    N.check(lib.gcp_workspace_size(byref(params), byref(n)), "gcp_workspace_size")
+    return int(n.value)
+
+
+class Stream:
+    """One streaming-GCP state on one device (Algorithm 1's loop state)."""
+
+    def __init__(self, dims, rank: int, window: int, loss: str, A0: Sequence[torch.Tensor],
+                 X_hist: Sequence[torch.Tensor] = (), s_hist: Optional[torch.Tensor] = None,
+                 t_hist: Optional[Sequence[int]] = None, **kw):
+        self.lib = N.load()
+        self.dtype = A0[0].dtype
+        self.device = A0[0].device
+        if self.device.type != "cuda":
+            raise ValueError("gcpstream runs on the GPU only: pass device tensors")
+        self.params = make_params(dims, rank, window, loss, dtype=self.dtype, **kw)
+        self.dims = tuple(int(n) for n in dims)
+        self.rank = int(rank)
+        self.window = int(window)
+        self.loss = loss
+        nbytes = gcp_workspace_size(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.hip_stream = torch.cuda.current_stream(self.device)
+        n_hist = len(X_hist)
+        slices = (N.GcpSlice * max(1, n_hist))()
+        for h, x in enumerate(X_hist):
+            slices[h] = _dense_slice(x)
+        th = (c_int64 * max(1, n_hist))(*(list(t_hist) if t_hist is not None else []))
+        A0c = [a.contiguous() for a in A0]
+        sh = s_hist.contiguous() if s_hist is not None and n_hist > 0 else None
+        handle = c_void_p(0)
+        N.check(self.lib.gcp_stream_init(byref(self.params), _ptr_array(A0c), n_hist, slices,
+                                         _ptr(sh), th, _ptr(self.workspace), nbytes,
+                                         c_void_p(self.hip_stream.cuda_stream), byref(handle)),
+                "gcp_stream_init")
+        self._keep = (A0c, sh, list(X_hist))  # alive until the copies have run
+        self.handle = handle
+
+    # -- calls ----------------------------------------------------------
+    def loss_grad(self, X_t: torch.Tensor, A: Sequence[torch.Tensor], s_t: torch.Tensor,
+                  want_loss: bool = True, want_grad: bool = True, plain: bool = False,
+                  out=None):
+        want = (N.WANT_LOSS if want_loss else 0) | (N.WANT_GRAD if want_grad else 0)
+        if plain:
+            want |= N.IMPL_PLAIN
+        dev, dt = self.device, self.dtype
+        if out is None:
+            loss = torch.empty(1, dtype=dt, device=dev)
+            G = [torch.empty(n, self.rank, dtype=dt, device=dev) for n in self.dims]
+            g_s = torch.empty(self.rank, dtype=dt, device=dev)
+        else:
+            loss, G, g_s = out
+        sl = _dense_slice(X_t)
+        Ac = [a.contiguous() for a in A]
+        N.check(self.lib.gcp_loss_grad(self.handle, byref(sl), _ptr_array(Ac), _ptr(s_t.contiguous()),
+                                       want, _ptr(loss), _ptr_array(G), _ptr(g_s)),
+                "gcp_loss_grad")
+        return loss, G, g_s
+
+    def solve_st(self, X_t: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        s = out if out is not None else torch.empty(self.rank, dtype=self.dtype, device=self.device)
+        sl = _dense_slice(X_t)
+        N.check(self.lib.gcp_solve_st(self.handle, byref(sl), _ptr(s)), "gcp_solve_st")
+        return s
+
+    def update_factors(self, X_t: torch.Tensor, s_t: torch.Tensor) -> None:
+        sl = _dense_slice(X_t)
+        N.check(self.lib.gcp_update_factors(self.handle, byref(sl), _ptr(s_t.contiguous())),
+                "gcp_update_factors")
+
+    def step(self, X_t: torch.Tensor) -> torch.Tensor:
+        """One OnlineGCP time step (Algorithm 1 body): s_t, then the factors."""
+        s_t = self.solve_st(X_t)
+        self.update_factors(X_t, s_t)
+        return s_t
+
+    def factors(self) -> List[torch.Tensor]:
+        out = [torch.empty(n, self.rank, dtype=self.dtype, device=self.device) for n in self.dims]
+        N.check(self.lib.gcp_get_factors(self.handle, _ptr_array(out)), "gcp_get_factors")
+        return out
+
+    def info(self):
+        t = c_int64(0)
+        nw = c_int32(0)
+        it = c_int64(0)
+        slots = (c_int64 * max(1, self.window))()
+        N.check(self.lib.gcp_stream_info(self.handle, byref(t), byref(nw), byref(it), slots),
+                "gcp_stream_info")
+        return {"t": t.value, "n_window": nw.value, "adam_iter": it.value,
+                "slot_times": [slots[i] for i in range(nw.value)]}
+
+    def kernel_timing(self, enable: bool, capacity: int = 0) -> None:
+        N.check(self.lib.gcp_kernel_timing(self.handle, int(enable), int(capacity)),
+                "gcp_kernel_timing")
+
+    def kernel_time(self):
+        ms = ctypes.c_double(0.0)
+        n = c_int64(0)
+        N.check(self.lib.gcp_kernel_time(self.handle, byref(ms), byref(n)), "gcp_kernel_time")
+        return ms.value, n.value
+
+    def sync(self) -> int:
+        return int(self.lib.gcp_stream_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            torch.cuda.synchronize(self.device)
+            self.lib.gcp_stream_destroy(self.handle)
+            self.handle = c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# names of the C calls, for callers that want them one-to-one
+def gcp_stream_init(*a, **kw) -> Stream:
+    return Stream(*a, **kw)
+
+
+def gcp_loss_grad(stream: Stream, X_t, A, s_t, **kw):
+    return stream.loss_grad(X_t, A, s_t, **kw)
+
+
+def gcp_solve_st(stream: Stream, X_t, out=None):
+    return stream.solve_st(X_t, out)
+
+
+def gcp_update_factors(stream: Stream, X_t, s_t):
+    return stream.update_factors(X_t, s_t)

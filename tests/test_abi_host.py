@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI: the library loads, exports every call that
+include/gcpstream.h declares, and rejects bad arguments before any launch.
+CPU only (no compute call reaches the device)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_calls():
+    text = open(os.path.join(ROOT, "include", "gcpstream.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:gcp_status|void|const char\*)\s+(gcp_\w+)\s*\(",
+                                 text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2110_14514_amd import _native as N
+    return N.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2110_14514_amd import _native as N
+    names = _declared_calls()
+    assert "gcp_loss_grad" in names and "gcp_stream_init" in names
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in N.SIGNATURES, f"binding lacks {n}"
+
+
+def test_params_struct_layout_matches_header(lib):
+    from paper_2110_14514_amd import _native as N
+    p = N.GcpParams()
+    lib.gcp_params_default(ctypes.byref(p))
+    assert p.abi_version == N.ABI_VERSION and p.d == 3
+    assert p.beta1 == 0.9 and p.beta2 == 0.999 and p.adam_eps == 1e-8
+    assert p.w == 1.0 and p.theta == 1.0 and p.lam == 0.0 and p.mu == 0.0
+    assert math.isinf(p.lower) and p.lower < 0 and p.tau_f == 1
+    assert ctypes.sizeof(N.GcpParams) == 168
+    assert ctypes.sizeof(N.GcpSlice) == 32
+
+
+def _params(lib, **kw):
+    from paper_2110_14514_amd import _native as N
+    p = N.GcpParams()
+    lib.gcp_params_default(ctypes.byref(p))
+    p.dims[0], p.dims[1], p.dims[2] = 20, 30, 40
+    p.rank, p.window = 4, 3
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ws(lib, p):
+    n = ctypes.c_size_t(0)
+    return lib.gcp_workspace_size(ctypes.byref(p), ctypes.byref(n)), n.value
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("abi_version", 99, "E_ARG"), ("d", 4, "E_UNSUPPORTED"), ("rank", 0, "E_ARG"),
+    ("rank", 65, "E_ARG"), ("window", 65, "E_ARG"), ("window", -1, "E_ARG"),
+    ("loss", 3, "E_ARG"), ("dtype", 5, "E_ARG"), ("theta", 0.0, "E_ARG"),
+    ("theta", 1.5, "E_ARG"), ("mu", -1.0, "E_ARG"), ("slice_kind", 7, "E_UNSUPPORTED"),
+])
+def test_invalid_params_rejected(lib, field, value, code):
+    from paper_2110_14514_amd import _native as N
+    st, _ = _ws(lib, _params(lib, **{field: value}))
+    assert st == getattr(N, code)
+
+
+def test_workspace_monotone_in_window_and_dims(lib):
+    sizes = [_ws(lib, _params(lib, window=h))[1] for h in (0, 1, 3, 10)]
+    assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+    # the stored window dominates: H slices of omega floats at least
+    assert sizes[-1] - sizes[0] >= 10 * 20 * 30 * 40 * 4
+    st, small = _ws(lib, _params(lib))
+    p = _params(lib)
+    p.dims[2] = 80
+    assert _ws(lib, p)[1] > small
+
+
+def test_init_rejects_before_launch(lib):
+    from paper_2110_14514_amd import _native as N
+    p = _params(lib)
+    out = ctypes.c_void_p(0)
+    arr = (ctypes.c_void_p * 3)(16, 16, 16)
+    # null workspace
+    assert lib.gcp_stream_init(ctypes.byref(p), arr, 0, None, None, None, None, 0, None,
+                               ctypes.byref(out)) == N.E_ARG
+    # misaligned workspace
+    assert lib.gcp_stream_init(ctypes.byref(p), arr, 0, None, None, None, ctypes.c_void_p(4096 + 8),
+                               1 << 30, None, ctypes.byref(out)) == N.E_ALIGN
+    # too small
+    assert lib.gcp_stream_init(ctypes.byref(p), arr, 0, None, None, None, ctypes.c_void_p(4096),
+                               16, None, ctypes.byref(out)) == N.E_WORKSPACE
+    # more history than the window holds
+    assert lib.gcp_stream_init(ctypes.byref(p), arr, 4, None, None, None, ctypes.c_void_p(4096),
+                               1 << 30, None, ctypes.byref(out)) == N.E_ARG
+    assert out.value is None
+
+
+def test_null_handle_calls(lib):
+    from paper_2110_14514_amd import _native as N
+    assert lib.gcp_loss_grad(None, None, None, None, 3, None, None, None) == N.E_ARG
+    assert lib.gcp_solve_st(None, None, None) == N.E_ARG
+    assert lib.gcp_update_factors(None, None, None) == N.E_ARG
+    assert lib.gcp_stream_sync(None) == N.E_ARG
+    assert lib.gcp_stream_destroy(None) == N.E_ARG
+    assert lib.gcp_status_string(N.E_NUMERIC).startswith(b"non-finite")

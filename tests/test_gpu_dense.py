@@ -1,0 +1,199 @@
+"""GPU parity of the dense path (fused and unfused) against the FP64 oracle,
+through the C ABI.  Normwise relative tolerance 1e-5 on FP32 results."""
+import math
+import zlib
+
+import numpy as np
+import pytest
+
+import gcp_inputs as gi
+from oracle import gcp as og
+from oracle.solve import ls_temporal
+from oracle.stream import StreamOracle
+
+from helpers import TOL, compare, gpu_loss_grad, make_stream, rel_err, to_device
+
+pytestmark = pytest.mark.gpu
+
+# (dims, rank, window): several tiles, ragged pair tiles, ragged i3 chunks
+# (I3 not a multiple of 64), ranks that are not a power of two, R = 64.
+SHAPES = [
+    ((5, 6, 7), 4, 0),
+    ((7, 9, 70), 5, 2),
+    ((17, 33, 129), 16, 3),
+    ((9, 4, 64), 32, 1),
+    ((20, 30, 40), 8, 10),
+    ((3, 3, 3), 64, 1),
+    ((40, 41, 13), 12, 4),
+]
+
+
+def _print_case(*a):
+    print("case:", *a, flush=True)
+
+
+@pytest.mark.parametrize("loss", og.LOSSES)
+@pytest.mark.parametrize("dims,R,H", SHAPES)
+def test_fused_matches_oracle(dims, R, H, loss):
+    _print_case("fused", dims, R, H, loss)
+    prob = gi.random_dense(dims, R, H, loss, seed=zlib.crc32(repr((dims, R, H, loss)).encode()) % 1000,
+                           w=1.3, theta=0.8, lam=0.05, mu=0.2)
+    got, code, _ = gpu_loss_grad(prob)
+    assert code == 0
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= TOL, errs
+
+
+@pytest.mark.parametrize("loss", og.LOSSES)
+@pytest.mark.parametrize("dims,R,H", SHAPES[:5])
+def test_plain_matches_oracle(dims, R, H, loss):
+    _print_case("plain", dims, R, H, loss)
+    prob = gi.random_dense(dims, R, H, loss, seed=17, w=0.7, theta=0.9, lam=0.1, mu=0.05)
+    got, code, _ = gpu_loss_grad(prob, plain=True)
+    assert code == 0
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= TOL, errs
+
+
+@pytest.mark.parametrize("loss", og.LOSSES)
+def test_fp64_instantiation_is_exact(loss):
+    _print_case("fp64", loss)
+    prob = gi.random_dense((6, 7, 67), 6, 2, loss, seed=3, w=1.1, theta=0.7, lam=0.2,
+                           mu=0.3, dtype=np.float64)
+    got, code, _ = gpu_loss_grad(prob)
+    assert code == 0
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= 1e-12, errs
+
+
+def test_c1_config():
+    _print_case("C1")
+    prob = gi.c1_problem()
+    got, code, _ = gpu_loss_grad(prob)
+    assert code == 0
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_c2_full_size():
+    """C2 at its full size (200^3, R=16, H=10, Poisson-log) in the launch
+    configuration the bench times; every output compared."""
+    _print_case("C2 full")
+    prob = gi.c2_problem()
+    got, code, _ = gpu_loss_grad(prob)
+    assert code == 0
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_bitwise_repeatable():
+    import torch
+    _print_case("repeat")
+    prob = gi.random_dense((17, 33, 129), 16, 3, "poisson_log", seed=5)
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    outs = []
+    for _ in range(3):
+        loss, G, g_s = st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+        torch.cuda.synchronize()
+        outs.append([loss.cpu().numpy()] + [g.cpu().numpy() for g in G] + [g_s.cpu().numpy()])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_want_loss_only_and_grad_only():
+    import torch
+    _print_case("want bits")
+    prob = gi.random_dense((8, 9, 10), 4, 2, "bernoulli_logit", seed=6)
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    l1, G1, g1 = st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+    G = [torch.full_like(g, 7.0) for g in G1]
+    gs = torch.full_like(g1, 7.0)
+    loss = torch.full_like(l1, 7.0)
+    st.loss_grad(dev["X_t"], dev["A"], dev["s_t"], want_grad=False, out=(loss, G, gs))
+    torch.cuda.synchronize()
+    assert loss.item() == l1.item()
+    assert all(torch.all(g == 7.0) for g in G) and torch.all(gs == 7.0)
+    st.loss_grad(dev["X_t"], dev["A"], dev["s_t"], want_loss=False, out=(loss, G, gs))
+    torch.cuda.synchronize()
+    assert loss.item() == 7.0 and torch.equal(G[0], G1[0]) and torch.equal(gs, g1)
+
+
+def test_nonfinite_is_reported():
+    import torch
+    _print_case("nonfinite")
+    prob = gi.random_dense((8, 9, 10), 4, 0, "poisson_log", seed=7)
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    dev["X_t"][1, 2, 3] = float("nan")
+    st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+    assert st.sync() == 7          # GCP_E_NUMERIC, then cleared
+    dev["X_t"][1, 2, 3] = 0.0
+    st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+    assert st.sync() == 0
+
+
+def test_ls_solve_matches_oracle():
+    import torch
+    _print_case("ls solve")
+    for dims, R, mu in [((20, 30, 40), 4, 0.0), ((33, 17, 129), 16, 0.5), ((9, 10, 11), 32, 1.0)]:
+        prob = gi.random_dense(dims, R, 0, "gaussian", seed=R)
+        prob.mu = mu
+        dev = to_device(prob)
+        st = make_stream(prob, dev)
+        s = st.solve_st(dev["X_t"])
+        torch.cuda.synchronize()
+        assert st.sync() == 0
+        ref = ls_temporal(prob.promoted().X_t, prob.promoted().A, mu)
+        assert rel_err(s.cpu().numpy(), ref) <= TOL
+
+
+def test_singular_gram_is_reported():
+    import torch
+    _print_case("singular")
+    prob = gi.random_dense((6, 7, 8), 3, 0, "gaussian", seed=2)
+    prob.A[0][:, 2] = 0.0          # Gamma singular with mu = 0
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    s = st.solve_st(dev["X_t"])
+    torch.cuda.synchronize()
+    assert st.sync() == 7
+    assert torch.isnan(s).all()
+
+
+def test_stream_steps_match_oracle():
+    """C1 stream: five OnlineGCP steps (LS weights, tau_f=3 Adam iterations
+    with window, reservoir push) against the oracle stream."""
+    import torch
+    _print_case("stream C1")
+    data = gi.c1_stream()
+    H = 3
+    g = gi.rng(99)
+    A0 = [a + 0.1 * g.standard_normal(a.shape) for a in data.A_true]
+    Xf = data.X.astype(np.float32)
+    A0f = [a.astype(np.float32) for a in A0]
+    S0 = data.S_true[:H].astype(np.float32)
+    kw = dict(loss="gaussian", window=H, w=1.0, theta=0.95, lam=0.01, mu=0.02,
+              alpha_f=1e-2, tau_f=3, seed=11)
+    orc = StreamOracle([a.astype(np.float64) for a in A0f], [x.astype(np.float64) for x in Xf[:H]],
+                       S0.astype(np.float64), np.arange(1, H + 1), **kw)
+    from paper_2110_14514_amd import Stream
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    st = Stream(Xf.shape[1:], 4, H, "gaussian", [tt(a) for a in A0f], [tt(x) for x in Xf[:H]],
+                tt(S0), list(range(1, H + 1)), w=1.0, theta=0.95, lam=0.01, mu=0.02,
+                alpha_f=1e-2, tau_f=3, seed=11)
+    for t in range(H, H + 8):
+        X = tt(Xf[t])
+        s_gpu = st.step(X)
+        s_or = orc.step(Xf[t].astype(np.float64))
+        torch.cuda.synchronize()
+        assert st.sync() == 0
+        assert rel_err(s_gpu.cpu().numpy(), s_or) <= 1e-4
+        info = st.info()
+        assert info["t"] == orc.t and info["slot_times"] == orc.slots
+    A_gpu = [a.cpu().numpy() for a in st.factors()]
+    for k in range(3):
+        assert rel_err(A_gpu[k], orc.A[k]) <= 1e-4
+        assert rel_err(A_gpu[k] - A0f[k], orc.A[k] - A0f[k]) <= 1e-2
