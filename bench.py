@@ -23,6 +23,10 @@ import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
@@ -36,7 +40,22 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="instead of the workload, run a plain device-to-device copy of this "
+                         "many MiB a few times (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+    return 0
 
 
 def main():
@@ -45,6 +64,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
               "supported (the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
         return 2
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

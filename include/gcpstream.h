@@ -86,7 +86,11 @@ enum {
 
 /* Flags of gcp_params.flags. */
 enum {
-  GCP_FLAG_PLAIN_SCRATCH = 1  /* reserve the unfused path's scratch (2 slices) */
+  GCP_FLAG_PLAIN_SCRATCH = 1, /* reserve the unfused path's scratch (2 slices) */
+  GCP_FLAG_KERNEL_VALU = 2,   /* fused path: always the vector-ALU kernel      */
+  GCP_FLAG_KERNEL_MFMA = 4    /* fused path: the matrix-core kernel wherever it
+                                 applies (FP32, R <= 32, window <= 63);
+                                 default: chosen by rank                     */
 };
 
 /* Table 1 (Section 4.2) of the paper, plus layout and sampling controls. */
@@ -150,11 +154,29 @@ gcp_status gcp_stream_init(const gcp_params* params, const void* const* A0,
  * (gcp_factor_ptr).  want: GCP_WANT_LOSS and/or GCP_WANT_GRAD; add
  * GCP_IMPL_PLAIN for the unfused path (needs GCP_FLAG_PLAIN_SCRATCH).
  * loss: device scalar; G[k]: I_k x R; g_s: R.  Null outputs are allowed for
- * the parts not wanted.  On COO streams the data terms are the stratified
- * sampled estimates of Section 4.3 (see gcp_dump_samples). */
+ * the parts not wanted.
+ * COO streams (FP32): the data terms of every slice are the stratified
+ * sampled estimates of Section 4.3 / Algorithm 6 with p nonzero and q zero
+ * draws per slice and weights eta/p, zeta/q; the regularisation terms are
+ * exact.  Draws use Philox4x32-10 with key = seed and counter = (draw number,
+ * slice time stamp, call number, stratum + 2*attempt); the call number
+ * starts at 0 and advances by one per sampled evaluation (including each
+ * iteration of gcp_update_factors).  Zero draws are redrawn (at most 64
+ * times, else GCP_E_NUMERIC) while they hit a stored entry.  Results are
+ * accumulated with floating-point atomics (order-dependent rounding). */
 gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t,
                          const void* const* A, const void* s_t, uint32_t want,
                          void* loss, void* const* G, void* g_s);
+
+/* As gcp_loss_grad, with every gradient output multiplied on the device by
+ * the scalar *grad_scale (device pointer, stream dtype; NULL means 1).  This
+ * is the adjoint used by the differentiation wrapper: dL/dA^(k) =
+ * grad_scale * G^(k), dL/ds_t = grad_scale * g_s, with the model recomputed
+ * rather than stored.  The objective output is not scaled. */
+gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t,
+                                const void* const* A, const void* s_t,
+                                uint32_t want, const void* grad_scale,
+                                void* loss, void* const* G, void* g_s);
 
 /* Temporal weights for X_t with the stream's factors held fixed (Alg. 1,
  * temporal step; eq. gcp_stream_temporal_problem).  Gaussian loss only: the
@@ -178,10 +200,14 @@ gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out);
 /* Device pointer to the stream's current factor k (valid until destroy). */
 gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr);
 
-/* Host-side stream state: current t, window size, Adam iteration index, and
- * the time stamp held by each window slot (host array of params->window). */
+/* Host-side stream state: current t, window size, Adam iteration index, the
+ * time stamp held by each window slot (host array of params->window), and
+ * the sampler's call number (COO streams: the number of sampled gradient
+ * evaluations so far; the next one draws with this number).  Any output may
+ * be NULL. */
 gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window,
-                           int64_t* adam_iter, int64_t* slot_times);
+                           int64_t* adam_iter, int64_t* slot_times,
+                           int64_t* sample_call);
 
 /* Waits for the HIP stream and returns the deferred device status
  * (GCP_E_NUMERIC if a kernel flagged one), clearing it. */

@@ -1,0 +1,131 @@
+"""FP64 oracle for the stratified sampled gradient (Section 4.3, Algorithm 6).
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check and CPU baseline).
+
+For a sparse slice with eta stored nonzeros out of omega = I1 I2 I3 entries
+(zeta = omega - eta zeros), p nonzeros and q zeros are drawn uniformly with
+replacement; zero candidates are drawn as uniform index tuples and rejected
+when they hit a stored nonzero.  Each drawn entry contributes
+    ytilde = (eta/p) df/dm(x, m)      for a nonzero draw,
+    ytilde = (zeta/q) df/dm(0, m)     for a zero draw,
+to the gradient tensor, and the factor and weight gradients are the MTTKRPs
+of eqs. gcp_grad_A / gcp_grad_lambda with ytilde in place of y.  The window
+slices are sampled the same way and weighted by w_h; the regularisation
+gradients are exact.  The objective is estimated with the same draws and the
+same weights applied to f.
+
+The random draws are specified so that two independent implementations
+produce the same samples: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+random numbers: as easy as 1, 2, 3", SC 2011) with key (seed low 32 bits,
+seed high 32 bits) and counter
+    (sample number, slice time stamp, call number, stratum + 2 * attempt)
+with stratum 0 for nonzeros and 1 for zeros.  A nonzero draw uses word 0:
+index = floor(word0 * eta / 2^32).  A zero draw uses words 0..2:
+i_k = floor(word_k * I_k / 2^32); attempt 0, 1, ... until the tuple is not a
+stored nonzero (at most 64 attempts).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .gcp import loss_dfdm, loss_f
+
+M0, M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+W0, W1 = 0x9E3779B9, 0xBB67AE85
+MASK32 = np.uint64(0xFFFFFFFF)
+MAX_ATTEMPTS = 64
+
+
+def philox4x32_10(ctr, key):
+    """ctr: (4, n) uint32-valued array, key: (k0, k1).  Returns (4, n)."""
+    c = [np.asarray(ctr[i], dtype=np.uint64) & MASK32 for i in range(4)]
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    for rnd in range(10):
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & MASK32
+        c = [hi1 ^ c[1] ^ np.uint64(k0), lo1, hi0 ^ c[3] ^ np.uint64(k1), lo0]
+        k0 = (k0 + W0) & 0xFFFFFFFF
+        k1 = (k1 + W1) & 0xFFFFFFFF
+    return np.stack(c).astype(np.uint64)
+
+
+def _scale(word, n):
+    return ((np.asarray(word, np.uint64) * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+
+
+def draw_nonzeros(seed: int, stamp: int, call: int, p: int, eta: int):
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    c = np.arange(p, dtype=np.uint64)
+    ctr = [c, np.full(p, stamp & 0xFFFFFFFF, np.uint64), np.full(p, call & 0xFFFFFFFF, np.uint64),
+           np.zeros(p, np.uint64)]
+    return _scale(philox4x32_10(ctr, key)[0], eta)
+
+
+def draw_zeros(seed: int, stamp: int, call: int, q: int, dims, nonzero_lin: np.ndarray):
+    """Accepted zero coordinates (q x 3) and the attempt that produced each."""
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    c = np.arange(q, dtype=np.uint64)
+    out = np.zeros((q, 3), np.int64)
+    attempt_of = np.full(q, -1, np.int64)
+    todo = np.arange(q)
+    for a in range(MAX_ATTEMPTS):
+        if todo.size == 0:
+            break
+        ctr = [c[todo], np.full(todo.size, stamp & 0xFFFFFFFF, np.uint64),
+               np.full(todo.size, call & 0xFFFFFFFF, np.uint64),
+               np.full(todo.size, 1 + 2 * a, np.uint64)]
+        w = philox4x32_10(ctr, key)
+        idx = np.stack([_scale(w[k], dims[k]) for k in range(3)], axis=1)
+        lin = (idx[:, 0] * dims[1] + idx[:, 1]) * dims[2] + idx[:, 2]
+        hit = np.isin(lin, nonzero_lin)
+        ok = ~hit
+        out[todo[ok]] = idx[ok]
+        attempt_of[todo[ok]] = a
+        todo = todo[hit]
+    if todo.size:
+        raise RuntimeError("zero sampling did not terminate")
+    return out, attempt_of
+
+
+def sampled_terms(loss, coo, s, A, seed, stamp, call, p, q):
+    """Per-draw coordinates, x values and weights for one slice."""
+    dims = coo.dims
+    omega = int(np.prod(dims))
+    eta = coo.coords.shape[0]
+    zeta = omega - eta
+    lin = (coo.coords[:, 0].astype(np.int64) * dims[1] + coo.coords[:, 1]) * dims[2] + coo.coords[:, 2]
+    nz = draw_nonzeros(seed, stamp, call, p, eta) if p > 0 else np.zeros(0, np.int64)
+    zc, _ = draw_zeros(seed, stamp, call, q, dims, lin) if q > 0 else (np.zeros((0, 3), np.int64), None)
+    coords = np.concatenate([coo.coords[nz].astype(np.int64), zc], axis=0)
+    x = np.concatenate([coo.vals[nz].astype(np.float64), np.zeros(q)])
+    wgt = np.concatenate([np.full(p, eta / p if p else 0.0), np.full(q, zeta / q if q else 0.0)])
+    return coords, x, wgt
+
+
+def sampled_loss_grad(prob, call: int = 0):
+    """(F~, G~^(1..3), g~_s) for a sparse problem (gcp_inputs.SparseProblem)."""
+    A = [np.asarray(a, np.float64) for a in prob.A]
+    R = A[0].shape[1]
+    slices = [(prob.X_t, np.asarray(prob.s_t, np.float64), 1.0, prob.t)]
+    for h, sl in enumerate(prob.X_hist):
+        c = prob.w * prob.theta ** (prob.t - int(prob.t_hist[h]))
+        slices.append((sl, np.asarray(prob.s_hist[h], np.float64), c, int(prob.t_hist[h])))
+    G = [prob.lam * a.copy() for a in A]
+    g_s = prob.mu * np.asarray(prob.s_t, np.float64).copy()
+    F = 0.5 * prob.lam * sum(float(np.sum(a * a)) for a in A) + \
+        0.5 * prob.mu * float(np.sum(np.asarray(prob.s_t, np.float64) ** 2))
+    for n, (coo, s, c, stamp) in enumerate(slices):
+        coords, x, wgt = sampled_terms(prob.loss, coo, s, A, prob.seed, stamp, call, prob.p, prob.q)
+        rows = [A[k][coords[:, k]] for k in range(3)]
+        m = np.sum(s[None, :] * rows[0] * rows[1] * rows[2], axis=1)
+        F += c * float(np.sum(wgt * loss_f(prob.loss, x, m)))
+        yt = c * wgt * loss_dfdm(prob.loss, x, m)
+        for k in range(3):
+            others = [rows[l] for l in range(3) if l != k]
+            contrib = yt[:, None] * s[None, :] * others[0] * others[1]
+            np.add.at(G[k], coords[:, k], contrib)
+        if n == 0:
+            g_s += np.sum(yt[:, None] * rows[0] * rows[1] * rows[2], axis=0)
+    return F, G, g_s

@@ -28,6 +28,8 @@ F32, F64 = 0, 1
 SLICE_DENSE, SLICE_COO = 0, 1
 WANT_LOSS, WANT_GRAD, IMPL_PLAIN = 1, 2, 256
 FLAG_PLAIN_SCRATCH = 1
+FLAG_KERNEL_VALU = 2
+FLAG_KERNEL_MFMA = 4
 
 
 class GcpParams(Structure):
@@ -57,12 +59,14 @@ SIGNATURES = {
                                   c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "gcp_loss_grad": (c_int32, [c_void_p, POINTER(GcpSlice), POINTER(c_void_p), c_void_p,
                                 c_uint32, c_void_p, POINTER(c_void_p), c_void_p]),
+    "gcp_loss_grad_scaled": (c_int32, [c_void_p, POINTER(GcpSlice), POINTER(c_void_p), c_void_p,
+                                       c_uint32, c_void_p, c_void_p, POINTER(c_void_p), c_void_p]),
     "gcp_solve_st": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p]),
     "gcp_update_factors": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p]),
     "gcp_get_factors": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "gcp_factor_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
     "gcp_stream_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32),
-                                  POINTER(c_int64), POINTER(c_int64)]),
+                                  POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "gcp_stream_sync": (c_int32, [c_void_p]),
     "gcp_stream_destroy": (c_int32, [c_void_p]),
     "gcp_kernel_timing": (c_int32, [c_void_p, c_int32, c_int32]),

@@ -17,6 +17,7 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, total;
+  size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
   size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
   size_t plain_bytes, part_bytes;
@@ -34,6 +35,8 @@ struct gcp_stream {
   int nwin;
   int64_t slot_t[GCP_MAX_WINDOW];
   int64_t adam_i;
+  int64_t slot_nnz[GCP_MAX_WINDOW];
+  int64_t sample_call;
   int* status;
   std::vector<hipEvent_t> ev;   // begin/end pairs for gcp_kernel_timing
   int ev_used;
@@ -53,7 +56,14 @@ gcp_status check_params(const gcp_params* p) {
   if (p->window < 0 || p->window > GCP_MAX_WINDOW) return GCP_E_ARG;
   if (p->loss < 0 || p->loss > 2) return GCP_E_ARG;
   if (p->dtype != GCP_F32 && p->dtype != GCP_F64) return GCP_E_ARG;
-  if (p->slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  if (p->slice_kind != GCP_SLICE_DENSE && p->slice_kind != GCP_SLICE_COO) return GCP_E_UNSUPPORTED;
+  if (p->slice_kind == GCP_SLICE_COO) {
+    if (p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
+    if (p->p < 0 || p->q < 0 || p->p + p->q < 1) return GCP_E_ARG;
+    if (p->max_nnz < 1 || p->max_nnz >= ((int64_t)1 << 32)) return GCP_E_ARG;
+    if (p->flags & GCP_FLAG_PLAIN_SCRATCH) return GCP_E_UNSUPPORTED;
+    if (p->dims[0] * p->dims[1] * p->dims[2] >= ((int64_t)1 << 62)) return GCP_E_SHAPE;
+  }
   if (!(p->theta > 0.0 && p->theta <= 1.0)) return GCP_E_ARG;
   if (!isfinite(p->w) || !isfinite(p->lambda) || !isfinite(p->mu) || p->lambda < 0 || p->mu < 0)
     return GCP_E_ARG;
@@ -62,6 +72,8 @@ gcp_status check_params(const gcp_params* p) {
   if (!(p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps >= 0))
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_PLAIN_SCRATCH) && p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
+  if ((p->flags & GCP_FLAG_KERNEL_VALU) && (p->flags & GCP_FLAG_KERNEL_MFMA)) return GCP_E_ARG;
+  if (p->flags & ~(GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_KERNEL_VALU | GCP_FLAG_KERNEL_MFMA)) return GCP_E_ARG;
   return GCP_OK;
 }
 
@@ -85,10 +97,13 @@ WsLayout layout_for(const gcp_params* p) {
   L.gs = off; off = align_up(off + (size_t)R * es, 256);
   L.loss = off; off += 256;
   L.shist = off; off = align_up(off + (size_t)p->window * R * es, 256);
-  L.ring = off; off = align_up(off + (size_t)p->window * omega * es, 256);
-  L.part_bytes = dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
+  const bool coo = p->slice_kind == GCP_SLICE_COO;
+  L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
+  L.ring = off;
+  off = align_up(off + (coo ? (size_t)p->window * L.coo_slot : (size_t)p->window * omega * es), 256);
+  L.part_bytes = coo ? 0 : dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
   L.part = off; off = align_up(off + L.part_bytes, 256);
-  L.ls = off; off = align_up(off + ls_scratch_bytes(I1, I2, I3, R), 256);
+  L.ls = off; off = align_up(off + (coo ? 0 : ls_scratch_bytes(I1, I2, I3, R)), 256);
   L.plain_bytes = (p->flags & GCP_FLAG_PLAIN_SCRATCH) ? dense_plain_scratch_bytes(I1, I2, I3, R, p->dtype) : 0;
   L.plain = off; off = align_up(off + L.plain_bytes, 256);
   L.total = off;
@@ -99,8 +114,65 @@ bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
 gcp_status check_dense_slice(const gcp_stream* s, const gcp_slice* X) {
   if (!X || X->kind != GCP_SLICE_DENSE || !X->vals) return GCP_E_ARG;
+  if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_ARG;
   if (!aligned16(X->vals)) return GCP_E_ALIGN;
   return GCP_OK;
+}
+
+gcp_status check_coo_slice(const gcp_stream* s, const gcp_slice* X) {
+  if (!X || X->kind != GCP_SLICE_COO || s->p.slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
+  if (X->nnz < 0 || X->nnz >= ((int64_t)1 << 32)) return GCP_E_SHAPE;
+  if (X->nnz > 0 && (!X->vals || !X->coords)) return GCP_E_ARG;
+  if (s->p.p > 0 && X->nnz == 0) return GCP_E_ARG;               // no nonzero to draw
+  if (s->p.q > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;  // no zero to draw
+  if (((uintptr_t)X->coords & 3u) || ((uintptr_t)X->vals & 3u)) return GCP_E_ALIGN;
+  return GCP_OK;
+}
+
+char* coo_slot_coords(gcp_stream* s, int slot) { return s->ws + s->L.ring + (size_t)slot * s->L.coo_slot; }
+char* coo_slot_vals(gcp_stream* s, int slot) {
+  return coo_slot_coords(s, slot) + (size_t)s->p.max_nnz * 12;
+}
+
+hipError_t store_coo_slot(gcp_stream* s, int slot, const gcp_slice* X) {
+  hipError_t e = hipSuccess;
+  if (X->nnz > 0) {
+    e = hipMemcpyAsync(coo_slot_coords(s, slot), X->coords, (size_t)X->nnz * 12, hipMemcpyDeviceToDevice, s->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(coo_slot_vals(s, slot), X->vals, (size_t)X->nnz * 4, hipMemcpyDeviceToDevice, s->st);
+  }
+  s->slot_nnz[slot] = X->nnz;
+  return e;
+}
+
+SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, int want,
+                         void* loss, void* const* G, void* g_s) {
+  SampledCall c;
+  memset(&c, 0, sizeof(c));
+  c.I1 = s->dims[0]; c.I2 = s->dims[1]; c.I3 = s->dims[2]; c.R = s->p.rank;
+  c.loss = s->p.loss; c.want = want;
+  c.coords[0] = X_t->coords; c.vals[0] = X_t->vals; c.nnz[0] = X_t->nnz; c.stamp[0] = s->t;
+  c.S[0] = s_t; c.c[0] = 1.0;
+  int n = 1;
+  for (int slot = 0; slot < s->nwin; ++slot, ++n) {
+    c.coords[n] = reinterpret_cast<const int32_t*>(coo_slot_coords(s, slot));
+    c.vals[n] = coo_slot_vals(s, slot);
+    c.nnz[n] = s->slot_nnz[slot];
+    c.stamp[n] = s->slot_t[slot];
+    c.S[n] = s->ws + s->L.shist + (size_t)slot * s->p.rank * s->es;
+    c.c[n] = s->p.w * pow(s->p.theta, (double)(s->t - s->slot_t[slot]));
+  }
+  c.ns = n;
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = A[k];
+    c.G[k] = G[k];
+  }
+  c.gs = g_s; c.loss_out = loss;
+  c.lam = s->p.lambda; c.mu = s->p.mu;
+  c.p = s->p.p; c.q = s->p.q; c.seed = s->p.seed;
+  c.call = s->sample_call++;
+  c.status = s->status; c.stream = s->st;
+  return c;
 }
 
 char* fac_ptr(gcp_stream* s, size_t block, int k) { return s->ws + block + s->L.fac_off[k] * s->es; }
@@ -131,6 +203,7 @@ DenseCall base_call(gcp_stream* s) {
   c.status = s->status;
   c.stream = s->st;
   c.c[0] = 1.0;
+  c.kernel = (s->p.flags & GCP_FLAG_KERNEL_VALU) ? 1 : ((s->p.flags & GCP_FLAG_KERNEL_MFMA) ? 2 : 0);
   return c;
 }
 
@@ -190,8 +263,15 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   WsLayout L = layout_for(p);
   if (ws_bytes < L.total) return GCP_E_WORKSPACE;
   for (int h = 0; h < n_hist; ++h) {
-    if (X_hist[h].kind != GCP_SLICE_DENSE || !X_hist[h].vals) return GCP_E_ARG;
-    if (!aligned16(X_hist[h].vals)) return GCP_E_ALIGN;
+    if (p->slice_kind == GCP_SLICE_DENSE) {
+      if (X_hist[h].kind != GCP_SLICE_DENSE || !X_hist[h].vals) return GCP_E_ARG;
+      if (!aligned16(X_hist[h].vals)) return GCP_E_ALIGN;
+    } else {
+      if (X_hist[h].kind != GCP_SLICE_COO || X_hist[h].nnz < 0 || X_hist[h].nnz > p->max_nnz) return GCP_E_SHAPE;
+      if (X_hist[h].nnz > 0 && (!X_hist[h].vals || !X_hist[h].coords)) return GCP_E_ARG;
+      if (p->p > 0 && X_hist[h].nnz == 0) return GCP_E_ARG;
+      if (p->q > 0 && X_hist[h].nnz >= p->dims[0] * p->dims[1] * p->dims[2]) return GCP_E_ARG;
+    }
     if (h > 0 && t_hist[h] <= t_hist[h - 1]) return GCP_E_ARG;
     if (t_hist[h] < 1) return GCP_E_ARG;
   }
@@ -217,8 +297,11 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
   for (int h = 0; h < n_hist && e == hipSuccess; ++h) {
-    e = hipMemcpyAsync(s->ws + L.ring + (size_t)h * s->omega * s->es, X_hist[h].vals, s->omega * s->es,
-                       hipMemcpyDeviceToDevice, s->st);
+    if (p->slice_kind == GCP_SLICE_COO)
+      e = store_coo_slot(s, h, &X_hist[h]);
+    else
+      e = hipMemcpyAsync(s->ws + L.ring + (size_t)h * s->omega * s->es, X_hist[h].vals, s->omega * s->es,
+                         hipMemcpyDeviceToDevice, s->st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->ws + L.shist + (size_t)h * p->rank * s->es,
                          static_cast<const char*>(s_hist) + (size_t)h * p->rank * s->es, p->rank * s->es,
@@ -234,15 +317,37 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
 
 gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, uint32_t want,
                          void* loss, void* const* G, void* g_s) {
+  return gcp_loss_grad_scaled(s, X_t, A, s_t, want, nullptr, loss, G, g_s);
+}
+
+gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t,
+                                uint32_t want, const void* grad_scale, void* loss, void* const* G, void* g_s) {
   if (!s || !A || !A[0] || !A[1] || !A[2] || !s_t) return GCP_E_ARG;
   if (want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD | GCP_IMPL_PLAIN)) return GCP_E_ARG;
   if (!(want & (GCP_WANT_LOSS | GCP_WANT_GRAD))) return GCP_E_ARG;
   if ((want & GCP_WANT_LOSS) && !loss) return GCP_E_ARG;
   if ((want & GCP_WANT_GRAD) && (!G || !G[0] || !G[1] || !G[2] || !g_s)) return GCP_E_ARG;
+  if (s->p.slice_kind == GCP_SLICE_COO) {
+    gcp_status st = check_coo_slice(s, X_t);
+    if (st != GCP_OK) return st;
+    if ((want & GCP_IMPL_PLAIN) || grad_scale) return GCP_E_UNSUPPORTED;
+    void* Gs[3];
+    for (int k = 0; k < 3; ++k) Gs[k] = (want & GCP_WANT_GRAD) ? G[k] : fac_ptr(s, s->L.G, k);
+    SampledCall c = sampled_call(s, X_t, A, s_t, want & (GCP_WANT_LOSS | GCP_WANT_GRAD),
+                                 (want & GCP_WANT_LOSS) ? loss : s->ws + s->L.loss, Gs,
+                                 (want & GCP_WANT_GRAD) ? g_s : s->ws + s->L.gs);
+    if (s->ev_used + 2 <= (int)s->ev.size()) {
+      c.ev_begin = s->ev[s->ev_used];
+      c.ev_end = s->ev[s->ev_used + 1];
+      s->ev_used += 2;
+    }
+    return hip_status(sampled_run(c));
+  }
   gcp_status st = check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
   const bool plain = want & GCP_IMPL_PLAIN;
   if (plain && s->L.plain_bytes == 0) return GCP_E_STATE;
+  if (plain && grad_scale) return GCP_E_UNSUPPORTED;
   DenseCall c = base_call(s);
   c.want = want & (GCP_WANT_LOSS | GCP_WANT_GRAD);
   c.X[0] = X_t->vals;
@@ -254,6 +359,7 @@ gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const*
   }
   c.gs = (want & GCP_WANT_GRAD) ? g_s : nullptr;
   c.loss_out = (want & GCP_WANT_LOSS) ? loss : nullptr;
+  c.grad_scale = grad_scale;
   if ((want & GCP_WANT_GRAD) == 0) {
     // the fused kernel always forms gradients; route them to scratch
     for (int k = 0; k < 3; ++k) c.G[k] = fac_ptr(s, s->L.G, k);
@@ -271,6 +377,7 @@ gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const*
 gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
   if (!s || !s_t) return GCP_E_ARG;
   if (s->p.loss != GCP_LOSS_GAUSSIAN) return GCP_E_UNSUPPORTED;
+  if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
   gcp_status st = check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
@@ -280,11 +387,26 @@ gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
 
 gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   if (!s || !s_t) return GCP_E_ARG;
-  gcp_status st = check_dense_slice(s, X_t);
+  const bool coo = s->p.slice_kind == GCP_SLICE_COO;
+  gcp_status st = coo ? check_coo_slice(s, X_t) : check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
+  if (coo && X_t->nnz > s->p.max_nnz && s->p.window > 0) return GCP_E_SHAPE;
   const gcp_params& p = s->p;
   hipError_t e = hipSuccess;
   for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
+    if (coo) {
+      const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+      void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
+      SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs);
+      e = sampled_run(c);
+      if (e != hipSuccess) break;
+      const double n = (double)(s->adam_i + 1);
+      const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
+      e = adam_run(p.dtype, (int64_t)s->L.fac_elems, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u,
+                   s->ws + s->L.v, alpha_t, p.beta1, p.beta2, p.adam_eps, p.lower, s->st);
+      s->adam_i += 1;
+      continue;
+    }
     DenseCall c = base_call(s);
     c.want = kWantGrad;
     c.X[0] = X_t->vals;
@@ -316,8 +438,11 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     }
   }
   if (slot >= 0 && e == hipSuccess) {
-    e = hipMemcpyAsync(s->ws + s->L.ring + (size_t)slot * s->omega * s->es, X_t->vals, s->omega * s->es,
-                       hipMemcpyDeviceToDevice, s->st);
+    if (coo)
+      e = store_coo_slot(s, slot, X_t);
+    else
+      e = hipMemcpyAsync(s->ws + s->L.ring + (size_t)slot * s->omega * s->es, X_t->vals, s->omega * s->es,
+                         hipMemcpyDeviceToDevice, s->st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->ws + s->L.shist + (size_t)slot * p.rank * s->es, s_t, p.rank * s->es,
                          hipMemcpyDeviceToDevice, s->st);
@@ -342,8 +467,10 @@ gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr) {
   return GCP_OK;
 }
 
-gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window, int64_t* adam_iter, int64_t* slot_times) {
+gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window, int64_t* adam_iter, int64_t* slot_times,
+                           int64_t* sample_call) {
   if (!s) return GCP_E_ARG;
+  if (sample_call) *sample_call = s->sample_call;
   if (t) *t = s->t;
   if (n_window) *n_window = s->nwin;
   if (adam_iter) *adam_iter = s->adam_i;

@@ -87,10 +87,44 @@ struct DenseCall {
   hipStream_t stream;
   hipEvent_t ev_begin;          // optional: recorded around the main kernel
   hipEvent_t ev_end;
+  int kernel;                   // 0 automatic, 1 VALU kernel, 2 matrix-core kernel
+  const void* grad_scale;       // optional device scalar multiplying the gradients
 };
+
+// Matrix-core (MFMA) variant of the fused kernel: work plan and launcher.
+struct MfmaPlan {
+  int tb1, tb2, nb1, nb2, nblocks, nwg;
+};
+bool mfma_supported(int R, int ns, int dtype);
+MfmaPlan mfma_plan(int I1, int I2, int I3);
+hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
+                             float* gsp, float* lossp);
 
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t dense_fused_run(const DenseCall& c);
+
+// Stratified sampled objective/gradient over COO slices (FP32).
+struct SampledCall {
+  int I1, I2, I3, R, ns, loss, want;
+  const int32_t* coords[kMaxNs];  // nnz x 3, sorted by row-major linear index
+  const void* vals[kMaxNs];
+  int64_t nnz[kMaxNs];
+  int64_t stamp[kMaxNs];          // time stamp of slice h (sampler counter word)
+  const void* S[kMaxNs];
+  double c[kMaxNs];
+  const void* A[3];
+  void* G[3];
+  void* gs;
+  void* loss_out;
+  double lam, mu;
+  int64_t p, q;
+  uint64_t seed;
+  int64_t call;                   // sampler call number
+  int* status;
+  hipStream_t stream;
+  hipEvent_t ev_begin, ev_end;
+};
+hipError_t sampled_run(const SampledCall& c);
 
 // Unfused baseline: model, elementwise, per-mode MTTKRP kernels.
 size_t dense_plain_scratch_bytes(int I1, int I2, int I3, int R, int dtype);

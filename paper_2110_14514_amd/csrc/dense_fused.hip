@@ -59,19 +59,30 @@ Tiling tiling_for(int I1, int I2) {
 
 struct PartLayout {
   size_t g1, g2, g3, gs, loss, total;
+  int s1, s2, s3;               // slots of G1 rows, G2 rows, and G3/g_s/loss
 };
+
+PartLayout part_layout_slots(int I1, int I2, int I3, int R, size_t es, int s1, int s2, int s3) {
+  PartLayout p;
+  p.s1 = s1; p.s2 = s2; p.s3 = s3;
+  size_t off = 0;
+  p.g1 = off; off = align_up(off + (size_t)s1 * I1 * R * es, 256);
+  p.g2 = off; off = align_up(off + (size_t)s2 * I2 * R * es, 256);
+  p.g3 = off; off = align_up(off + (size_t)s3 * I3 * R * es, 256);
+  p.gs = off; off = align_up(off + (size_t)s3 * R * es, 256);
+  p.loss = off; off = align_up(off + (size_t)s3 * es, 256);
+  p.total = off;
+  return p;
+}
 
 PartLayout part_layout(int I1, int I2, int I3, int R, size_t es) {
   Tiling t = tiling_for(I1, I2);
-  PartLayout p;
-  size_t off = 0;
-  p.g1 = off; off = align_up(off + (size_t)t.nb2 * I1 * R * es, 256);
-  p.g2 = off; off = align_up(off + (size_t)t.nb1 * I2 * R * es, 256);
-  p.g3 = off; off = align_up(off + (size_t)t.ntiles * I3 * R * es, 256);
-  p.gs = off; off = align_up(off + (size_t)t.ntiles * R * es, 256);
-  p.loss = off; off = align_up(off + (size_t)t.ntiles * es, 256);
-  p.total = off;
-  return p;
+  return part_layout_slots(I1, I2, I3, R, es, t.nb2, t.nb1, t.ntiles);
+}
+
+PartLayout part_layout_mfma(int I1, int I2, int I3, int R) {
+  MfmaPlan m = mfma_plan(I1, I2, I3);
+  return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2, m.nb1, m.nwg);
 }
 
 // Reduce-scatter of RT per-lane values over the 64 lanes of a wave.  On
@@ -268,48 +279,57 @@ struct ReduceArgs {
   T* gs;
   T* loss;
   T lam, mu;
+  const T* gscale;
   int I1, I2, I3, R, nb1, nb2, ntiles, want, gblocks;
   int* status;
 };
 
+// Sums the partial slots of every output in a fixed order and adds the
+// regularisation gradients; the last workgroup forms the objective.  One
+// wave per output element: lane l sums slots l, l+64, ... (Kahan), then the
+// 64 lane sums are combined by a fixed butterfly, so the result does not
+// depend on scheduling.
 template <typename T>
-__device__ __forceinline__ void flag_nonfinite(T v, int* status) {
-  if (!isfinite(v)) atomicOr(status, (int)kStatusNonFinite);
+__device__ __forceinline__ T wave_sum_fixed(T v) {
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+  return v;
 }
 
-// Sums the per-tile partials in tile order (Kahan), adds the regularisation
-// gradients, and (last workgroup) forms the objective.
 template <typename T>
 __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
   const int R = r.R;
+  const int lane = threadIdx.x & 63;
   if ((int)blockIdx.x < r.gblocks) {
     const int n1 = r.I1 * R, n2 = r.I2 * R, n3 = r.I3 * R;
     const int total = n1 + n2 + n3 + R;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += r.gblocks * blockDim.x) {
-      Kahan<T> k;
-      T out;
+    const T sc = r.gscale ? r.gscale[0] : T(1);
+    const int wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (int idx = wave0; idx < total; idx += r.gblocks * 4) {
+      const T* src;
+      size_t stride;
+      int slots;
+      T reg;
+      T* dst;
       if (idx < n1) {
-        for (int b = 0; b < r.nb2; ++b) k.add(r.G1p[(size_t)b * n1 + idx]);
-        out = k.s + r.lam * r.A1[idx];
-        r.G1[idx] = out;
+        src = r.G1p + idx; stride = n1; slots = r.nb2; reg = r.lam * r.A1[idx]; dst = r.G1 + idx;
       } else if (idx < n1 + n2) {
-        int e = idx - n1;
-        for (int b = 0; b < r.nb1; ++b) k.add(r.G2p[(size_t)b * n2 + e]);
-        out = k.s + r.lam * r.A2[e];
-        r.G2[e] = out;
+        const int e = idx - n1;
+        src = r.G2p + e; stride = n2; slots = r.nb1; reg = r.lam * r.A2[e]; dst = r.G2 + e;
       } else if (idx < n1 + n2 + n3) {
-        int e = idx - n1 - n2;
-        for (int b = 0; b < r.ntiles; ++b) k.add(r.G3p[(size_t)b * n3 + e]);
-        out = k.s + r.lam * r.A3[e];
-        r.G3[e] = out;
+        const int e = idx - n1 - n2;
+        src = r.G3p + e; stride = n3; slots = r.ntiles; reg = r.lam * r.A3[e]; dst = r.G3 + e;
       } else {
-        int j = idx - n1 - n2 - n3;
-        for (int b = 0; b < r.ntiles; ++b) k.add(r.gsp[(size_t)b * R + j]);
-        out = k.s + r.mu * r.st[j];
-        r.gs[j] = out;
+        const int j = idx - n1 - n2 - n3;
+        src = r.gsp + j; stride = R; slots = r.ntiles; reg = r.mu * r.st[j]; dst = r.gs + j;
       }
-      flag_nonfinite(out, r.status);
+      Kahan<T> k;
+      for (int b = lane; b < slots; b += 64) k.add(src[(size_t)b * stride]);
+      const T sum = wave_sum_fixed(k.s);
+      if (lane == 0) {
+        const T out = sc * (sum + reg);
+        *dst = out;
+        if (!isfinite(out)) atomicOr(r.status, (int)kStatusNonFinite);
+      }
     }
     return;
   }
@@ -332,8 +352,39 @@ __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
   }
   if (threadIdx.x == 0) {
     r.loss[0] = red[0];
-    flag_nonfinite(red[0], r.status);
+    if (!isfinite(red[0])) atomicOr(r.status, (int)kStatusNonFinite);
   }
+}
+
+template <typename T>
+hipError_t launch_reduce(const DenseCall& c, const PartLayout& pl) {
+  char* base = static_cast<char*>(c.part);
+  ReduceArgs<T> r;
+  r.G1p = reinterpret_cast<const T*>(base + pl.g1);
+  r.G2p = reinterpret_cast<const T*>(base + pl.g2);
+  r.G3p = reinterpret_cast<const T*>(base + pl.g3);
+  r.gsp = reinterpret_cast<const T*>(base + pl.gs);
+  r.lossp = reinterpret_cast<const T*>(base + pl.loss);
+  r.A1 = static_cast<const T*>(c.A[0]);
+  r.A2 = static_cast<const T*>(c.A[1]);
+  r.A3 = static_cast<const T*>(c.A[2]);
+  r.st = static_cast<const T*>(c.S[0]);
+  r.G1 = static_cast<T*>(c.G[0]);
+  r.G2 = static_cast<T*>(c.G[1]);
+  r.G3 = static_cast<T*>(c.G[2]);
+  r.gs = static_cast<T*>(c.gs);
+  r.loss = static_cast<T*>(c.loss_out);
+  r.lam = (T)c.lam; r.mu = (T)c.mu;
+  r.gscale = static_cast<const T*>(c.grad_scale);
+  r.I1 = c.I1; r.I2 = c.I2; r.I3 = c.I3; r.R = c.R;
+  r.nb1 = pl.s2; r.nb2 = pl.s1; r.ntiles = pl.s3; r.want = c.want;
+  r.status = c.status;
+  const int total = (c.I1 + c.I2 + c.I3 + 1) * c.R;
+  r.gblocks = (c.want & kWantGrad) ? std::min(2048, (total + 3) / 4) : 0;
+  const int blocks = r.gblocks + ((c.want & kWantLoss) ? 1 : 0);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((fused_reduce<T>), dim3(blocks), dim3(256), 0, c.stream, r);
+  return hipGetLastError();
 }
 
 template <typename T, int LOSS, int RT>
@@ -361,25 +412,7 @@ hipError_t launch_fused(const DenseCall& c, const Tiling& tl, const PartLayout& 
   if (c.ev_end) hipEventRecord(c.ev_end, c.stream);
   if (e != hipSuccess) return e;
 
-  ReduceArgs<T> r;
-  r.G1p = a.G1p; r.G2p = a.G2p; r.G3p = a.G3p; r.gsp = a.gsp; r.lossp = a.lossp;
-  r.A1 = a.A1; r.A2 = a.A2; r.A3 = a.A3;
-  r.st = static_cast<const T*>(c.S[0]);
-  r.G1 = static_cast<T*>(c.G[0]);
-  r.G2 = static_cast<T*>(c.G[1]);
-  r.G3 = static_cast<T*>(c.G[2]);
-  r.gs = static_cast<T*>(c.gs);
-  r.loss = static_cast<T*>(c.loss_out);
-  r.lam = (T)c.lam; r.mu = (T)c.mu;
-  r.I1 = c.I1; r.I2 = c.I2; r.I3 = c.I3; r.R = c.R;
-  r.nb1 = tl.nb1; r.nb2 = tl.nb2; r.ntiles = tl.ntiles; r.want = c.want;
-  r.status = c.status;
-  const int total = (c.I1 + c.I2 + c.I3 + 1) * c.R;
-  r.gblocks = (c.want & kWantGrad) ? std::min(1024, (total + 255) / 256) : 0;
-  const int blocks = r.gblocks + ((c.want & kWantLoss) ? 1 : 0);
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((fused_reduce<T>), dim3(blocks), dim3(256), 0, c.stream, r);
-  return hipGetLastError();
+  return launch_reduce<T>(c, pl);
 }
 
 template <typename T, int LOSS>
@@ -403,10 +436,27 @@ hipError_t dispatch_loss(const DenseCall& c, const Tiling& tl, const PartLayout&
 }  // namespace
 
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype) {
-  return part_layout(I1, I2, I3, R, dtype ? sizeof(double) : sizeof(float)).total;
+  size_t v = part_layout(I1, I2, I3, R, dtype ? sizeof(double) : sizeof(float)).total;
+  if (dtype == 0) v = std::max(v, part_layout_mfma(I1, I2, I3, R).total);
+  return v;
 }
 
 hipError_t dense_fused_run(const DenseCall& c) {
+  const bool mfma_ok = mfma_supported(c.R, c.ns, c.dtype);
+  bool use_mfma = c.kernel == 2 ? mfma_ok : (c.kernel == 1 ? false : (mfma_ok && c.R > 8));
+  if (use_mfma) {
+    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3);
+    PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R);
+    if (pl.total > c.part_bytes) return hipErrorInvalidValue;
+    char* base = static_cast<char*>(c.part);
+    if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);
+    hipError_t e = dense_mfma_launch(c, mp, reinterpret_cast<float*>(base + pl.g1),
+                                     reinterpret_cast<float*>(base + pl.g2), reinterpret_cast<float*>(base + pl.g3),
+                                     reinterpret_cast<float*>(base + pl.gs), reinterpret_cast<float*>(base + pl.loss));
+    if (c.ev_end) hipEventRecord(c.ev_end, c.stream);
+    if (e != hipSuccess) return e;
+    return launch_reduce<float>(c, pl);
+  }
   Tiling tl = tiling_for(c.I1, c.I2);
   PartLayout pl = part_layout(c.I1, c.I2, c.I3, c.R, c.dtype ? sizeof(double) : sizeof(float));
   if (pl.total > c.part_bytes) return hipErrorInvalidValue;

@@ -30,13 +30,28 @@ def _dense_slice(x: torch.Tensor) -> N.GcpSlice:
     return N.GcpSlice(N.SLICE_DENSE, 0, x.data_ptr(), None, 0)
 
 
+def _slice(x) -> N.GcpSlice:
+    """A dense tensor, or a (coords int32 [nnz,3], vals [nnz]) pair sorted by
+    row-major linear index."""
+    if isinstance(x, torch.Tensor):
+        return _dense_slice(x)
+    coords, vals = x
+    if coords.dtype != torch.int32 or not coords.is_contiguous() or not vals.is_contiguous():
+        raise ValueError("COO slices need contiguous int32 coords [nnz,3] and values [nnz]")
+    return N.GcpSlice(N.SLICE_COO, 0, vals.data_ptr(), coords.data_ptr(), int(vals.numel()))
+
+
 def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 lam=0.0, mu=0.0, lower=-math.inf, alpha_f=1e-3, beta1=0.9,
                 beta2=0.999, adam_eps=1e-8, tau_f=1, seed=0,
-                dtype=torch.float32, plain=False) -> N.GcpParams:
+                dtype=torch.float32, plain=False, kernel: str = "auto",
+                slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0) -> N.GcpParams:
     lib = N.load()
+    n_p, n_q = p, q
     p = N.GcpParams()
     lib.gcp_params_default(byref(p))
+    p.slice_kind = N.SLICE_COO if slice_kind == "coo" else N.SLICE_DENSE
+    p.max_nnz, p.p, p.q = int(max_nnz), int(n_p), int(n_q)
     p.d = len(dims)
     for k, n in enumerate(list(dims)[:3]):
         p.dims[k] = int(n)
@@ -44,7 +59,8 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.window = int(window)
     p.loss = N.LOSS_IDS[loss]
     p.dtype = N.F64 if dtype == torch.float64 else N.F32
-    p.flags = N.FLAG_PLAIN_SCRATCH if plain else 0
+    p.flags = (N.FLAG_PLAIN_SCRATCH if plain else 0) | {
+        "auto": 0, "valu": N.FLAG_KERNEL_VALU, "mfma": N.FLAG_KERNEL_MFMA}[kernel]
     p.w, p.theta, p.lam, p.mu, p.lower = float(w), float(theta), float(lam), float(mu), float(lower)
     p.alpha_f, p.beta1, p.beta2, p.adam_eps = float(alpha_f), float(beta1), float(beta2), float(adam_eps)
     p.tau_f = int(tau_f)
@@ -71,6 +87,7 @@ class Stream:
         if self.device.type != "cuda":
             raise ValueError("gcpstream runs on the GPU only: pass device tensors")
         self.params = make_params(dims, rank, window, loss, dtype=self.dtype, **kw)
+        self.coo = self.params.slice_kind == N.SLICE_COO
         self.dims = tuple(int(n) for n in dims)
         self.rank = int(rank)
         self.window = int(window)
@@ -81,7 +98,7 @@ class Stream:
         n_hist = len(X_hist)
         slices = (N.GcpSlice * max(1, n_hist))()
         for h, x in enumerate(X_hist):
-            slices[h] = _dense_slice(x)
+            slices[h] = _slice(x)
         th = (c_int64 * max(1, n_hist))(*(list(t_hist) if t_hist is not None else []))
         A0c = [a.contiguous() for a in A0]
         sh = s_hist.contiguous() if s_hist is not None and n_hist > 0 else None
@@ -91,12 +108,13 @@ class Stream:
                                          c_void_p(self.hip_stream.cuda_stream), byref(handle)),
                 "gcp_stream_init")
         self._keep = (A0c, sh, list(X_hist))  # alive until the copies have run
+        # (the copies run on the caller's stream; tensors stay referenced)
         self.handle = handle
 
     # -- calls ----------------------------------------------------------
     def loss_grad(self, X_t: torch.Tensor, A: Sequence[torch.Tensor], s_t: torch.Tensor,
                   want_loss: bool = True, want_grad: bool = True, plain: bool = False,
-                  out=None):
+                  out=None, grad_scale: Optional[torch.Tensor] = None):
         want = (N.WANT_LOSS if want_loss else 0) | (N.WANT_GRAD if want_grad else 0)
         if plain:
             want |= N.IMPL_PLAIN
@@ -107,10 +125,11 @@ class Stream:
             g_s = torch.empty(self.rank, dtype=dt, device=dev)
         else:
             loss, G, g_s = out
-        sl = _dense_slice(X_t)
+        sl = _slice(X_t)
         Ac = [a.contiguous() for a in A]
-        N.check(self.lib.gcp_loss_grad(self.handle, byref(sl), _ptr_array(Ac), _ptr(s_t.contiguous()),
-                                       want, _ptr(loss), _ptr_array(G), _ptr(g_s)),
+        N.check(self.lib.gcp_loss_grad_scaled(self.handle, byref(sl), _ptr_array(Ac),
+                                              _ptr(s_t.contiguous()), want, _ptr(grad_scale),
+                                              _ptr(loss), _ptr_array(G), _ptr(g_s)),
                 "gcp_loss_grad")
         return loss, G, g_s
 
@@ -120,8 +139,8 @@ class Stream:
         N.check(self.lib.gcp_solve_st(self.handle, byref(sl), _ptr(s)), "gcp_solve_st")
         return s
 
-    def update_factors(self, X_t: torch.Tensor, s_t: torch.Tensor) -> None:
-        sl = _dense_slice(X_t)
+    def update_factors(self, X_t, s_t: torch.Tensor) -> None:
+        sl = _slice(X_t)
         N.check(self.lib.gcp_update_factors(self.handle, byref(sl), _ptr(s_t.contiguous())),
                 "gcp_update_factors")
 
@@ -141,10 +160,12 @@ class Stream:
         nw = c_int32(0)
         it = c_int64(0)
         slots = (c_int64 * max(1, self.window))()
-        N.check(self.lib.gcp_stream_info(self.handle, byref(t), byref(nw), byref(it), slots),
+        call = c_int64(0)
+        N.check(self.lib.gcp_stream_info(self.handle, byref(t), byref(nw), byref(it), slots,
+                                         byref(call)),
                 "gcp_stream_info")
         return {"t": t.value, "n_window": nw.value, "adam_iter": it.value,
-                "slot_times": [slots[i] for i in range(nw.value)]}
+                "slot_times": [slots[i] for i in range(nw.value)], "sample_call": call.value}
 
     def kernel_timing(self, enable: bool, capacity: int = 0) -> None:
         N.check(self.lib.gcp_kernel_timing(self.handle, int(enable), int(capacity)),

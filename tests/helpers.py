@@ -41,10 +41,10 @@ def make_stream(prob, dev, plain=False, **kw):
                   lam=prob.lam, mu=prob.mu, plain=plain, **kw)
 
 
-def gpu_loss_grad(prob, plain=False, stream=None):
+def gpu_loss_grad(prob, plain=False, stream=None, kernel="auto"):
     import torch
     dev = to_device(prob)
-    st = stream or make_stream(prob, dev, plain=plain)
+    st = stream or make_stream(prob, dev, plain=plain, kernel=kernel)
     loss, G, g_s = st.loss_grad(dev["X_t"], dev["A"], dev["s_t"], plain=plain)
     torch.cuda.synchronize()
     code = st.sync()

@@ -25,6 +25,9 @@ SHAPES = [
     ((20, 30, 40), 8, 10),
     ((3, 3, 3), 64, 1),
     ((40, 41, 13), 12, 4),
+    ((6, 5, 200), 16, 20),      # two h-tiles, 3 full 64-wide groups + 8-wide tail
+    ((4, 7, 66), 32, 40),       # three h-tiles, I3 not a multiple of 4
+    ((3, 4, 128), 20, 60),      # four h-tiles
 ]
 
 
@@ -32,13 +35,14 @@ def _print_case(*a):
     print("case:", *a, flush=True)
 
 
+@pytest.mark.parametrize("kernel", ["valu", "mfma"])
 @pytest.mark.parametrize("loss", og.LOSSES)
 @pytest.mark.parametrize("dims,R,H", SHAPES)
-def test_fused_matches_oracle(dims, R, H, loss):
-    _print_case("fused", dims, R, H, loss)
+def test_fused_matches_oracle(dims, R, H, loss, kernel):
+    _print_case("fused", kernel, dims, R, H, loss)
     prob = gi.random_dense(dims, R, H, loss, seed=zlib.crc32(repr((dims, R, H, loss)).encode()) % 1000,
                            w=1.3, theta=0.8, lam=0.05, mu=0.2)
-    got, code, _ = gpu_loss_grad(prob)
+    got, code, _ = gpu_loss_grad(prob, kernel=kernel)
     assert code == 0
     errs = compare(prob, got, og)
     assert max(errs.values()) <= TOL, errs
@@ -75,12 +79,14 @@ def test_c1_config():
     assert max(errs.values()) <= TOL, errs
 
 
-def test_c2_full_size():
+@pytest.mark.parametrize("kernel", ["auto", "valu"])
+def test_c2_full_size(kernel):
     """C2 at its full size (200^3, R=16, H=10, Poisson-log) in the launch
-    configuration the bench times; every output compared."""
-    _print_case("C2 full")
+    configuration the bench times (automatic kernel choice); every output
+    compared."""
+    _print_case("C2 full", kernel)
     prob = gi.c2_problem()
-    got, code, _ = gpu_loss_grad(prob)
+    got, code, _ = gpu_loss_grad(prob, kernel=kernel)
     assert code == 0
     errs = compare(prob, got, og)
     assert max(errs.values()) <= TOL, errs
@@ -116,6 +122,7 @@ def test_want_loss_only_and_grad_only():
     torch.cuda.synchronize()
     assert loss.item() == l1.item()
     assert all(torch.all(g == 7.0) for g in G) and torch.all(gs == 7.0)
+    loss.fill_(7.0)
     st.loss_grad(dev["X_t"], dev["A"], dev["s_t"], want_loss=False, out=(loss, G, gs))
     torch.cuda.synchronize()
     assert loss.item() == 7.0 and torch.equal(G[0], G1[0]) and torch.equal(gs, g1)
