@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default) is the configuration the metric is quoted on; the others "
+                         "print their own line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run a plain device-to-device copy of this "
                          "many MiB a few times (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
@@ -58,6 +61,137 @@ def copy_probe(mib: int):
     return 0
 
 
+def _time(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def _line(workload, value_unit, ms, steps, warmup, alg_bytes, alg_flops, kern_s, extra):
+    ach = alg_bytes / kern_s / 1e9
+    out = {"metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
+           "value": 1e3 / ms, "unit": value_unit, "n_gpus": 1, "ms_per_step": ms, "steps": steps,
+           "warmup": warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": workload},
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel_ms": kern_s * 1e3,
+                        "alg_bytes_per_launch": alg_bytes,
+                        "fp32_tflops": alg_flops / kern_s / 1e12,
+                        "fp32_frac": alg_flops / kern_s / 1e12 / FP32_PEAK_TFLOPS}}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_c3(args):
+    """C3: 1000x1000x64 binary slices, rank 32, window 20, Bernoulli-logit."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream
+    dims, R, H = (1000, 1000, 64), 32, 20
+    print("bench: generating C3 on the device", file=sys.stderr, flush=True)
+    X_t, A, s_t, Xh, Sh = gi.device_dense_window(dims, R, H, "bernoulli_logit", seed=2)
+    st = Stream(dims, R, H, "bernoulli_logit", A, Xh, Sh, list(range(1, H + 1)))
+    del Xh
+    torch.cuda.synchronize()
+    out = (torch.empty(1, device="cuda"), [torch.empty(n, R, device="cuda") for n in dims],
+           torch.empty(R, device="cuda"))
+    fn = lambda: st.loss_grad(X_t, A, s_t, out=out)
+    st.kernel_timing(True, args.steps)
+    sec = _time(fn, args.steps, 0, torch.cuda.synchronize)
+    ms, n = st.kernel_time()
+    st.kernel_timing(False)
+    assert st.sync() == 0
+    omega = int(np.prod(dims))
+    _line("C3 dense binary slices 1000x1000x64, rank 32, window 20, Bernoulli-logit",
+          "grad steps/s", sec * 1e3, args.steps, 0, (H + 1) * omega * 4,
+          omega * (4 * R * (H + 1) + 8 * R), ms / max(n, 1) / 1e3, {})
+    return 0
+
+
+def bench_c4(args):
+    """C4: 64 streams, dims U{50..300}^3, rank {8,16,32}, window 4..16,
+    Gaussian/Poisson-log; one batched factor update (persistent launch)."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Batch, Stream
+    specs = gi.c4_specs()
+    streams, Xb, Sb = [], [], []
+    tot_bytes = 0
+    tot_flops = 0
+    print("bench: generating C4 on the device", file=sys.stderr, flush=True)
+    for sp in specs:
+        X_t, A, s_t, Xh, Sh = gi.device_dense_window(sp.dims, sp.rank, sp.window, sp.loss, sp.seed)
+        streams.append(Stream(sp.dims, sp.rank, sp.window, sp.loss, A, Xh, Sh,
+                              list(range(1, sp.window + 1)), alpha_f=1e-4, tau_f=1))
+        Xb.append(X_t)
+        Sb.append(s_t)
+        om = int(np.prod(sp.dims))
+        tot_bytes += (sp.window + 1) * om * 4
+        tot_flops += om * (4 * sp.rank * (sp.window + 1) + 8 * sp.rank)
+        del Xh
+    torch.cuda.synchronize()
+    b = Batch(streams, Xb, Sb)
+    fn = lambda: b.loss_grad()
+    sec = _time(fn, args.steps, args.warmup, torch.cuda.synchronize)
+    g = torch.cuda.CUDAGraph()
+    cs = streams[0].hip_stream
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=cs):
+        b.loss_grad()
+    gsec = _time(g.replay, args.steps, args.warmup, torch.cuda.synchronize)
+    assert b.sync_streams() == 0
+    _line("C4 64 independent streams, dims U{50..300}^3, rank {8,16,32}, window 4..16, "
+          "Gaussian/Poisson-log; one batched gcp_batch_loss_grad (all 64 stream gradients)",
+          "batched grad steps/s (64 streams each)", gsec * 1e3, args.steps, args.warmup,
+          tot_bytes, tot_flops, gsec,
+          {"eager_ms_per_step": sec * 1e3, "graph_ms_per_step": gsec * 1e3,
+           "stream_steps_per_s": 64 / gsec})
+    return 0
+
+
+def bench_c5(args):
+    """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
+    rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream
+    print("bench: generating C5", file=sys.stderr, flush=True)
+    prob = gi.sparse_problem()
+    T = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    coo = lambda sl: (T(sl.coords, torch.int32), T(sl.vals))
+    R, H = prob.rank, len(prob.X_hist)
+    st = Stream(prob.dims, R, H, prob.loss, [T(a) for a in prob.A], [coo(x) for x in prob.X_hist],
+                T(prob.s_hist), list(prob.t_hist), seed=prob.seed, slice_kind="coo",
+                max_nnz=prob.X_t.coords.shape[0], p=prob.p, q=prob.q)
+    Xt = coo(prob.X_t)
+    A = [T(a) for a in prob.A]
+    s_t = T(prob.s_t)
+    out = (torch.empty(1, device="cuda"), [torch.empty(n, R, device="cuda") for n in prob.dims],
+           torch.empty(R, device="cuda"))
+    fn = lambda: st.loss_grad(Xt, A, s_t, out=out)
+    for _ in range(args.warmup):
+        fn()
+    st.kernel_timing(True, args.steps)
+    sec = _time(fn, args.steps, 0, torch.cuda.synchronize)
+    ms, n = st.kernel_time()
+    st.kernel_timing(False)
+    assert st.sync() == 0
+    draws = (H + 1) * (prob.p + prob.q)
+    # algorithmic bytes: a nonzero draw reads its coordinates and value (16 B);
+    # a zero draw is a generated tuple plus one membership probe (8 B)
+    alg = (H + 1) * (prob.p * 16 + prob.q * 8)
+    _line("C5 sampled COO slices 2000x2000x500, 2M nonzeros, rank 32, window 8, p=q=2M, "
+          "Poisson-log", "grad steps/s", sec * 1e3, args.steps, args.warmup, alg,
+          draws * 16 * R, ms / max(n, 1) / 1e3, {"draws_per_step": draws,
+                                                  "draws_per_s": draws / (ms / max(n, 1) / 1e3)})
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -66,6 +200,8 @@ def main():
         return 2
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.workload != "c2":
+        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

@@ -327,3 +327,37 @@ def sparse_problem(dims=(2000, 2000, 500), rank: int = 32, window: int = 8,
                          S[:-1], np.arange(1, t, dtype=np.int64), t,
                          nnz if p is None else p, nnz if q is None else q,
                          seed, 0, loss=loss)
+
+
+# ------------------------------------------------- on-device synthesis --
+def device_dense_window(dims, rank: int, window: int, loss: str, seed: int, device="cuda"):
+    """Random full-size inputs on the device for timing (torch generator):
+    slices drawn from the loss's distribution around a random planted
+    parameter of the given rank, evaluation point factors U(-0.5, 0.5)
+    (Poisson) or N(0, 0.3^2) (others), weights U(0.5, 1.5)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    ns = window + 1
+
+    def planted(scale):
+        A = [torch.rand(n, rank, generator=g, device=device) * 2 - 1 for n in dims]
+        s = torch.rand(rank, generator=g, device=device) + 0.5
+        M = torch.einsum("ir,jr,kr->ijk", (A[0] * s * scale).contiguous(), A[1].contiguous(),
+                         A[2].contiguous())
+        return M
+
+    Xs = []
+    for _ in range(ns):
+        M = planted(0.3)
+        if loss == "gaussian":
+            X = M + torch.randn(M.shape, generator=g, device=device)
+        elif loss == "poisson_log":
+            X = torch.poisson(torch.exp(M.clamp(max=3.0)), generator=g)
+        else:
+            X = (torch.rand(M.shape, generator=g, device=device) < torch.sigmoid(M - 3.0)).float()
+        Xs.append(X.contiguous())
+        del M
+    A = [(torch.rand(n, rank, generator=g, device=device) - 0.5).contiguous() for n in dims]
+    S = torch.rand(ns, rank, generator=g, device=device) + 0.5
+    return Xs[-1], A, S[-1].contiguous(), Xs[:-1], S[:-1].contiguous()

@@ -215,6 +215,53 @@ gcp_status gcp_stream_sync(gcp_stream* s);
 
 gcp_status gcp_stream_destroy(gcp_stream* s);
 
+/* ------------------------------------------------------------------------
+ * Batching: many independent dense FP32 streams (rank <= 32, window <= 31)
+ * advanced together.  Each stream keeps its own workspace; the batch adds a
+ * workspace of gcp_batch_workspace_size() bytes with the stream descriptors,
+ * work list, partial sums and the streams' device-side step state.
+ * Per stream the caller registers fixed device buffers: X_t (dense slice)
+ * and s_t (R weights) as inputs, and optional outputs for
+ * gcp_batch_loss_grad (loss scalar, G[3], g_s; NULL: not written).  The
+ * caller refreshes the input buffers' contents before each call.
+ * All per-call state (time index, window fill and slot time stamps, ADAM
+ * iteration) is kept on the device, so any sequence of batch calls issued on
+ * the batch's HIP stream may be captured once as a HIP graph and replayed.
+ * While a stream is in a batch its host-side state (gcp_stream_info) is stale
+ * until gcp_batch_sync_streams.  Outputs match the per-stream calls.
+ * ------------------------------------------------------------------------ */
+typedef struct gcp_batch gcp_batch;
+
+typedef struct {
+  const void* X_t;      /* device, I1*I2*I3 values, 16-byte aligned */
+  const void* s_t;      /* device, R values                          */
+  void* loss;           /* device scalar or NULL                     */
+  void* G[3];           /* device I_k x R, or NULL                    */
+  void* g_s;            /* device R, or NULL                          */
+} gcp_batch_io;
+
+gcp_status gcp_batch_workspace_size(gcp_stream* const* streams, int32_t n, size_t* bytes);
+
+/* Builds the batch (synchronous: uploads descriptors and state). */
+gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, int32_t n, void* workspace,
+                            size_t ws_bytes, hipStream_t hip_stream, gcp_batch** out);
+
+/* Objective and gradients of every stream at its current factors over its
+ * registered X_t and window: one persistent launch plus one reduce launch.
+ * Writes the registered outputs (want: GCP_WANT_LOSS | GCP_WANT_GRAD). */
+gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want);
+
+/* gcp_update_factors for every stream with its registered X_t and s_t
+ * (tau_f of the first stream; all streams must share it): tau_f x [batched
+ * gradient, batched ADAM step], then A_old <- A and the reservoir window
+ * update with the draw made on the device, then t <- t+1. */
+gcp_status gcp_batch_update_factors(gcp_batch* b);
+
+/* Copies the device-side step state back into the stream handles (waits). */
+gcp_status gcp_batch_sync_streams(gcp_batch* b);
+
+gcp_status gcp_batch_destroy(gcp_batch* b);
+
 /* Measurement tooling.  With enable != 0, each following gcp_loss_grad
  * records a pair of HIP events on the stream's HIP stream immediately before
  * and after its main gradient kernel (up to `capacity` pairs; the events are

@@ -50,6 +50,11 @@ class GcpSlice(Structure):
                 ("coords", c_void_p), ("nnz", c_int64)]
 
 
+class GcpBatchIO(Structure):
+    _fields_ = [("X_t", c_void_p), ("s_t", c_void_p), ("loss", c_void_p),
+                ("G", c_void_p * 3), ("g_s", c_void_p)]
+
+
 # name -> (restype, argtypes), in header order
 SIGNATURES = {
     "gcp_params_default": (None, [POINTER(GcpParams)]),
@@ -69,6 +74,13 @@ SIGNATURES = {
                                   POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "gcp_stream_sync": (c_int32, [c_void_p]),
     "gcp_stream_destroy": (c_int32, [c_void_p]),
+    "gcp_batch_workspace_size": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
+    "gcp_batch_create": (c_int32, [POINTER(c_void_p), POINTER(GcpBatchIO), c_int32, c_void_p,
+                                   c_size_t, c_void_p, POINTER(c_void_p)]),
+    "gcp_batch_loss_grad": (c_int32, [c_void_p, c_uint32]),
+    "gcp_batch_update_factors": (c_int32, [c_void_p]),
+    "gcp_batch_sync_streams": (c_int32, [c_void_p]),
+    "gcp_batch_destroy": (c_int32, [c_void_p]),
     "gcp_kernel_timing": (c_int32, [c_void_p, c_int32, c_int32]),
     "gcp_kernel_time": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "gcp_status_string": (c_char_p, [c_int32]),

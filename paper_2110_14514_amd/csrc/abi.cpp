@@ -8,7 +8,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -178,6 +180,9 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
 char* fac_ptr(gcp_stream* s, size_t block, int k) { return s->ws + block + s->L.fac_off[k] * s->es; }
 
 void fill_window(gcp_stream* s, DenseCall& c) {
+  c.ring = s->ws + s->L.ring;
+  c.shist = s->ws + s->L.shist;
+  c.omega = s->omega;
   int n = 1;
   for (int slot = 0; slot < s->nwin; ++slot, ++n) {
     c.X[n] = s->ws + s->L.ring + (size_t)slot * s->omega * s->es;
@@ -540,6 +545,267 @@ const char* gcp_status_string(gcp_status st) {
     case GCP_E_UNSUPPORTED: return "unsupported configuration";
   }
   return "unknown status";
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------- batching
+struct gcp_batch {
+  std::vector<gcp_stream*> streams;
+  hipStream_t st;
+  char* ws;
+  BatchRun run_out;     // reduce writes the registered outputs
+  BatchRun run_step;    // reduce writes each stream's gradient scratch
+  int* status;
+  int tau_f;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t desc_out, desc_step, state, items, counter, outstart, facstart, cpystart, parts, total;
+  int nitems;
+  std::vector<size_t> part_off;
+  std::vector<MfmaPlan> plans;
+};
+
+size_t mfma_part_bytes(const MfmaPlan& m, int I1, int I2, int I3, int R) {
+  size_t b = 0;
+  b = align_up(b + (size_t)m.nb2 * I1 * R * 4, 256);
+  b = align_up(b + (size_t)m.nb1 * I2 * R * 4, 256);
+  b = align_up(b + (size_t)m.nwg * I3 * R * 4, 256);
+  b = align_up(b + (size_t)m.nwg * R * 4, 256);
+  b = align_up(b + (size_t)m.nwg * 4, 256);
+  return b;
+}
+
+gcp_status batch_check(gcp_stream* const* streams, int32_t n) {
+  if (!streams || n < 1) return GCP_E_ARG;
+  for (int i = 0; i < n; ++i) {
+    const gcp_stream* s = streams[i];
+    if (!s) return GCP_E_ARG;
+    if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32) return GCP_E_UNSUPPORTED;
+    if (s->p.rank > 32 || s->p.window > 31) return GCP_E_UNSUPPORTED;
+    if (s->p.tau_f != streams[0]->p.tau_f) return GCP_E_ARG;
+    if (s->st != streams[0]->st) return GCP_E_ARG;
+  }
+  return GCP_OK;
+}
+
+BatchLayout batch_layout(gcp_stream* const* streams, int32_t n) {
+  BatchLayout L;
+  size_t off = 0;
+  L.nitems = 0;
+  for (int i = 0; i < n; ++i) {
+    const gcp_stream* s = streams[i];
+    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2]));
+    L.nitems += L.plans.back().nwg;
+  }
+  L.desc_out = off; off = align_up(off + n * sizeof(BatchDesc), 256);
+  L.desc_step = off; off = align_up(off + n * sizeof(BatchDesc), 256);
+  L.state = off; off = align_up(off + n * sizeof(BatchState), 256);
+  L.items = off; off = align_up(off + (size_t)L.nitems * sizeof(int2), 256);
+  L.counter = off; off += 256;
+  L.outstart = off; off = align_up(off + n * sizeof(int64_t), 256);
+  L.facstart = off; off = align_up(off + n * sizeof(int64_t), 256);
+  L.cpystart = off; off = align_up(off + n * sizeof(int64_t), 256);
+  L.parts = off;
+  for (int i = 0; i < n; ++i) {
+    const gcp_stream* s = streams[i];
+    L.part_off.push_back(off);
+    off = align_up(off + mfma_part_bytes(L.plans[i], s->dims[0], s->dims[1], s->dims[2], s->p.rank), 256);
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+gcp_status gcp_batch_workspace_size(gcp_stream* const* streams, int32_t n, size_t* bytes) {
+  if (!bytes) return GCP_E_ARG;
+  gcp_status st = batch_check(streams, n);
+  if (st != GCP_OK) return st;
+  *bytes = batch_layout(streams, n).total;
+  return GCP_OK;
+}
+
+gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, int32_t n, void* workspace,
+                            size_t ws_bytes, hipStream_t hip_stream, gcp_batch** out) {
+  if (!out || !io || !workspace) return GCP_E_ARG;
+  *out = nullptr;
+  gcp_status st = batch_check(streams, n);
+  if (st != GCP_OK) return st;
+  if (((uintptr_t)workspace & 255u) != 0) return GCP_E_ALIGN;
+  BatchLayout L = batch_layout(streams, n);
+  if (ws_bytes < L.total) return GCP_E_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    if (!io[i].X_t || !io[i].s_t) return GCP_E_ARG;
+    if (!aligned16(io[i].X_t)) return GCP_E_ALIGN;
+  }
+  char* ws = static_cast<char*>(workspace);
+  std::vector<BatchDesc> dout(n), dstep(n);
+  std::vector<BatchState> state(n);
+  std::vector<int64_t> outstart(n), facstart(n), cpystart(n);
+  std::vector<std::pair<double, int>> order;
+  int64_t nout = 0, nfac = 0, ncpy = 0;
+  for (int i = 0; i < n; ++i) {
+    gcp_stream* s = streams[i];
+    const MfmaPlan& m = L.plans[i];
+    const int I1 = s->dims[0], I2 = s->dims[1], I3 = s->dims[2], R = s->p.rank;
+    BatchDesc d;
+    memset(&d, 0, sizeof(d));
+    d.Xt = static_cast<const float*>(io[i].X_t);
+    d.st = static_cast<const float*>(io[i].s_t);
+    d.ring = reinterpret_cast<float*>(s->ws + s->L.ring);
+    d.shist = reinterpret_cast<float*>(s->ws + s->L.shist);
+    d.A = reinterpret_cast<float*>(s->ws + s->L.A);
+    d.Aold = reinterpret_cast<float*>(s->ws + s->L.Aold);
+    d.u = reinterpret_cast<float*>(s->ws + s->L.u);
+    d.v = reinterpret_cast<float*>(s->ws + s->L.v);
+    d.Gs = reinterpret_cast<float*>(s->ws + s->L.G);
+    char* pb = ws + L.part_off[i];
+    size_t o = 0;
+    d.G1p = reinterpret_cast<float*>(pb + o); o = align_up(o + (size_t)m.nb2 * I1 * R * 4, 256);
+    d.G2p = reinterpret_cast<float*>(pb + o); o = align_up(o + (size_t)m.nb1 * I2 * R * 4, 256);
+    d.G3p = reinterpret_cast<float*>(pb + o); o = align_up(o + (size_t)m.nwg * I3 * R * 4, 256);
+    d.gsp = reinterpret_cast<float*>(pb + o); o = align_up(o + (size_t)m.nwg * R * 4, 256);
+    d.lossp = reinterpret_cast<float*>(pb + o);
+    d.omega = (int64_t)s->omega;
+    d.fac_elems = (int64_t)s->L.fac_elems;
+    d.fac_off1 = (int64_t)s->L.fac_off[1];
+    d.fac_off2 = (int64_t)s->L.fac_off[2];
+    d.I1 = I1; d.I2 = I2; d.I3 = I3; d.R = R; d.H = s->p.window; d.loss = s->p.loss;
+    d.variant = batch_variant(s->p.loss, R, s->p.window);
+    d.tb1 = m.tb1; d.tb2 = m.tb2; d.nb1 = m.nb1; d.nb2 = m.nb2; d.nblocks = m.nblocks; d.nwg = m.nwg;
+    d.w = s->p.w; d.theta = s->p.theta; d.lam = (float)s->p.lambda; d.mu = (float)s->p.mu;
+    d.lower = s->p.lower == -INFINITY ? -INFINITY : (float)s->p.lower;
+    d.alpha = s->p.alpha_f; d.beta1 = (float)s->p.beta1; d.beta2 = (float)s->p.beta2;
+    d.beta1d = s->p.beta1; d.beta2d = s->p.beta2;
+    d.eps = (float)s->p.adam_eps;
+    d.seed = s->p.seed;
+    // step descriptor: gradients into the stream's scratch
+    dstep[i] = d;
+    for (int k = 0; k < 3; ++k) dstep[i].outG[k] = reinterpret_cast<float*>(fac_ptr(s, s->L.G, k));
+    dstep[i].outgs = reinterpret_cast<float*>(s->ws + s->L.gs);
+    dstep[i].outloss = reinterpret_cast<float*>(s->ws + s->L.loss);
+    // output descriptor: registered outputs, scratch where none was given
+    dout[i] = dstep[i];
+    for (int k = 0; k < 3; ++k)
+      if (io[i].G[k]) dout[i].outG[k] = static_cast<float*>(io[i].G[k]);
+    if (io[i].g_s) dout[i].outgs = static_cast<float*>(io[i].g_s);
+    if (io[i].loss) dout[i].outloss = static_cast<float*>(io[i].loss);
+    BatchState& b = state[i];
+    memset(&b, 0, sizeof(b));
+    b.t = s->t;
+    b.adam_i = s->adam_i;
+    b.nwin = s->nwin;
+    b.pending_slot = -1;
+    for (int h = 0; h < s->nwin; ++h) b.slot_t[h] = s->slot_t[h];
+    outstart[i] = nout;
+    nout += (int64_t)(I1 + I2 + I3 + 1) * R + 1;
+    facstart[i] = nfac;
+    nfac += (int64_t)s->L.fac_elems;
+    cpystart[i] = ncpy;
+    ncpy += (int64_t)s->L.fac_elems + (int64_t)s->omega + R;
+    const double cost = (double)s->omega * (s->p.window + 1) * (R > 16 ? 2.0 : 1.0) / m.nwg;
+    order.push_back({cost, i});
+  }
+  // work list: most expensive items first, so the tail is made of short items
+  std::sort(order.begin(), order.end(), [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+    return x.first > y.first;
+  });
+  std::vector<int2> items;
+  for (auto& pr : order)
+    for (int w = 0; w < L.plans[pr.second].nwg; ++w) items.push_back(make_int2(pr.second, w));
+  hipError_t e = hipMemcpy(ws + L.desc_out, dout.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.desc_step, dstep.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.state, state.data(), n * sizeof(BatchState), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.outstart, outstart.data(), n * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.facstart, facstart.data(), n * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.cpystart, cpystart.data(), n * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(ws + L.counter, 0, 256);
+  if (e != hipSuccess) return GCP_E_DEVICE;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  gcp_batch* b = new (std::nothrow) gcp_batch();
+  if (!b) return GCP_E_ARG;
+  b->streams.assign(streams, streams + n);
+  b->st = hip_stream;
+  b->ws = ws;
+  b->status = reinterpret_cast<int*>(ws + L.counter) + 16;
+  b->tau_f = streams[0]->p.tau_f;
+  BatchRun r;
+  r.desc = reinterpret_cast<const BatchDesc*>(ws + L.desc_out);
+  r.state = reinterpret_cast<BatchState*>(ws + L.state);
+  r.items = reinterpret_cast<const int2*>(ws + L.items);
+  r.nitems = (int)items.size();
+  r.counter = reinterpret_cast<int*>(ws + L.counter);
+  r.nstreams = n;
+  r.outstart = reinterpret_cast<const int64_t*>(ws + L.outstart);
+  r.nout = nout;
+  r.facstart = reinterpret_cast<const int64_t*>(ws + L.facstart);
+  r.nfac = nfac;
+  r.cpystart = reinterpret_cast<const int64_t*>(ws + L.cpystart);
+  r.ncpy = ncpy;
+  r.grid = std::max(1, std::min(2 * cus, r.nitems));
+  r.status = b->status;
+  r.stream = hip_stream;
+  b->run_out = r;
+  b->run_step = r;
+  b->run_step.desc = reinterpret_cast<const BatchDesc*>(ws + L.desc_step);
+  *out = b;
+  return GCP_OK;
+}
+
+gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want) {
+  if (!b) return GCP_E_ARG;
+  want &= (GCP_WANT_LOSS | GCP_WANT_GRAD);
+  if (!want) return GCP_E_ARG;
+  return hip_status(batch_grad_run(b->run_out, (int)want));
+}
+
+gcp_status gcp_batch_update_factors(gcp_batch* b) {
+  if (!b) return GCP_E_ARG;
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < b->tau_f && e == hipSuccess; ++it) {
+    e = batch_grad_run(b->run_step, kWantGrad);
+    if (e == hipSuccess) e = batch_adam_run(b->run_step);
+  }
+  if (e == hipSuccess) e = batch_window_run(b->run_step);
+  return hip_status(e);
+}
+
+gcp_status gcp_batch_sync_streams(gcp_batch* b) {
+  if (!b) return GCP_E_ARG;
+  const int n = (int)b->streams.size();
+  std::vector<BatchState> state(n);
+  if (hipStreamSynchronize(b->st) != hipSuccess) return GCP_E_DEVICE;
+  if (hipMemcpy(state.data(), b->run_out.state, n * sizeof(BatchState), hipMemcpyDeviceToHost) != hipSuccess)
+    return GCP_E_DEVICE;
+  int word = 0;
+  if (hipMemcpy(&word, b->status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return GCP_E_DEVICE;
+  for (int i = 0; i < n; ++i) {
+    gcp_stream* s = b->streams[i];
+    s->t = state[i].t;
+    s->adam_i = state[i].adam_i;
+    s->nwin = state[i].nwin;
+    for (int h = 0; h < s->nwin; ++h) s->slot_t[h] = state[i].slot_t[h];
+  }
+  if (word != 0) {
+    if (hipMemset(b->status, 0, sizeof(int)) != hipSuccess) return GCP_E_DEVICE;
+    return GCP_E_NUMERIC;
+  }
+  return GCP_OK;
+}
+
+gcp_status gcp_batch_destroy(gcp_batch* b) {
+  if (!b) return GCP_E_ARG;
+  hipStreamSynchronize(b->st);
+  delete b;
+  return GCP_OK;
 }
 
 }  // extern "C"

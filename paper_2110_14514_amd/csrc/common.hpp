@@ -53,6 +53,36 @@ struct LossFn<T, kBernoulliLogit> {
   }
 };
 
+// FP32 loss evaluation on the hardware exp/log units (__expf, __logf: a few
+// ulp), for kernels where the loss is the dominant vector-ALU cost.  The
+// derivative is always formed; the loss value only when asked.
+template <int LOSS>
+struct LossFast;
+
+template <>
+struct LossFast<kGaussian> {
+  __device__ __forceinline__ static float y(float x, float m) { return 2.f * (m - x); }
+  __device__ __forceinline__ static float f(float x, float m) { return (x - m) * (x - m); }
+};
+
+template <>
+struct LossFast<kPoissonLog> {
+  __device__ __forceinline__ static float y(float x, float m) { return __expf(m) - x; }
+  __device__ __forceinline__ static float f(float x, float m) { return __expf(m) - x * m; }
+};
+
+template <>
+struct LossFast<kBernoulliLogit> {
+  __device__ __forceinline__ static float y(float x, float m) {
+    const float e = __expf(-fabsf(m));
+    const float inv = __frcp_rn(1.f + e);
+    return (m >= 0.f ? inv : e * inv) - x;
+  }
+  __device__ __forceinline__ static float f(float x, float m) {
+    return fmaxf(m, 0.f) + __logf(1.f + __expf(-fabsf(m))) - x * m;
+  }
+};
+
 // Kahan-compensated accumulation.
 template <typename T>
 struct Kahan {
@@ -74,6 +104,9 @@ struct DenseCall {
   int want;
   int dtype;                    // 0 = f32, 1 = f64
   const void* X[kMaxNs];        // slice h (0 = current)
+  const void* ring;             // window ring: slice h >= 1 is slot h-1 at ring + (h-1)*omega
+  const void* shist;            // window weights: s_h at shist + (h-1)*R
+  size_t omega;
   const void* S[kMaxNs];        // weight row of slice h (R values)
   double c[kMaxNs];             // c_0 = 1, c_h = w theta^(t-h)
   const void* A[3];
@@ -102,6 +135,61 @@ hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, 
 
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t dense_fused_run(const DenseCall& c);
+
+// Batched multi-stream path (dense FP32, matrix-core tiles).
+struct BatchDesc {                 // per stream, fixed at batch creation
+  const float* Xt;                 // registered input buffers
+  const float* st;
+  float* ring;                     // the stream's own workspace
+  float* shist;
+  float* A;
+  float* Aold;
+  float* u;
+  float* v;
+  float* Gs;
+  float* G1p;                      // partial slots (batch workspace)
+  float* G2p;
+  float* G3p;
+  float* gsp;
+  float* lossp;
+  float* outG[3];                  // where the reduce writes
+  float* outgs;
+  float* outloss;
+  int64_t omega, fac_elems, fac_off1, fac_off2;
+  int I1, I2, I3, R, H, loss, variant;
+  int tb1, tb2, nb1, nb2, nblocks, nwg;
+  float lam, mu, lower, beta1, beta2, eps;
+  double w, theta, alpha, beta1d, beta2d;   // history weights and ADAM rate in FP64
+  uint64_t seed;
+};
+struct BatchState {                // per stream, advanced on the device
+  int64_t t;
+  int64_t adam_i;
+  int nwin;
+  int pending_slot;
+  int64_t slot_t[kMaxNs];
+};
+struct BatchRun {
+  const BatchDesc* desc;
+  BatchState* state;
+  const int2* items;
+  int nitems;
+  int* counter;
+  int nstreams;
+  const int64_t* outstart;
+  int64_t nout;
+  const int64_t* facstart;
+  int64_t nfac;
+  const int64_t* cpystart;
+  int64_t ncpy;
+  int grid;
+  int* status;
+  hipStream_t stream;
+};
+int batch_variant(int loss, int R, int H);
+hipError_t batch_grad_run(const BatchRun& b, int want);
+hipError_t batch_adam_run(const BatchRun& b);
+hipError_t batch_window_run(const BatchRun& b);
 
 // Stratified sampled objective/gradient over COO slices (FP32).
 struct SampledCall {

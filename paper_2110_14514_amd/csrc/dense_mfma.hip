@@ -5,7 +5,7 @@
 // gradients of Section 4.2), organised around two small GEMMs per group of
 // 64 entries e of one (i1,i2) pair row:
 //   GEMM1  m[h][e]  = sum_j S[h][j] P[e][j],  P[e][j] = A1[i1,j] A2[i2,j] A3[i3,j]
-//   GEMM2  yhat[j][e] = sum_h S[h][j] c_h y(x_he, m[h][e])
+//   GEMM2  yhat[j][e] = sum_h (c_h S[h][j]) y(x_he, m[h][e])
 // (h runs over the current slice and the stored window, S[h] = s_h).  With
 // the 16x16x4 lane layout the accumulator of GEMM1 (rows h, columns e) is
 // directly the B operand of GEMM2 (K = h), so the loss derivative is applied
@@ -45,10 +45,15 @@ constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kTB = 32;
 
-struct MArgs {
-  const float* X[kMaxNs];
-  const float* S[kMaxNs];
-  float c[kMaxNs];
+// Everything one workgroup needs for its tile of pair blocks.  Slice h = 0 is
+// the current slice; slice h >= 1 is window slot h-1 of the ring (slot order),
+// with weight row s_{h} at shist + (h-1) R.
+struct TileArgs {
+  const float* Xt;
+  const float* ring;
+  size_t omega;
+  const float* st;
+  const float* shist;
   const float* A1;
   const float* A2;
   const float* A3;
@@ -59,6 +64,16 @@ struct MArgs {
   float* lossp;
   int I1, I2, I3, R, ns, want, tb1, tb2, nb2, nblocks;
 };
+
+struct MArgs {
+  TileArgs t;
+  float c[kMaxNs];
+};
+
+// LDS floats used by one workgroup at rank tile RT
+__host__ __device__ constexpr int lds_floats(int RT) {
+  return 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT + kWaves;
+}
 
 __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -84,25 +99,27 @@ __device__ __forceinline__ float row_reduce_scatter(float (&v)[NT], int n) {
   return r;
 }
 
+// One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
+// slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
 template <int LOSS, int RT, int NH>
-__global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
+__device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* sm, const float* cl) {
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
   constexpr int NU = RT == 32 ? 2 : 4;  // 16-entry tiles per group (register budget)
   constexpr int SW = 16 * NU;           // entries per full group
 
-  __shared__ float g1w[kWaves][kTB][RT];
-  __shared__ float g2w[kWaves][kTB][RT];
-  __shared__ float g3x[64][RT + 1];  // SW <= 64 rows used
-  __shared__ float gsx[kWaves][RT];
-  __shared__ float lsx[kWaves];
+  float(*g1w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(sm);
+  float(*g2w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(sm + kWaves * kTB * RT);
+  float(*g3x)[RT + 1] = reinterpret_cast<float(*)[RT + 1]>(sm + 2 * kWaves * kTB * RT);  // SW rows used
+  float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + 2 * kWaves * kTB * RT + 64 * (RT + 1));
+  float* lsx = sm + 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int n = lane & 15, g = lane >> 4;
   const int R = a.R, ns = a.ns, I1 = a.I1, I2 = a.I2, I3 = a.I3;
-  const int blk = blockIdx.x * kWaves + wave;
+  const int blk = wgi * kWaves + wave;
   const bool active = blk < a.nblocks;
   const int b1 = active ? blk / a.nb2 : 0, b2 = active ? blk % a.nb2 : 0;
   const int i10 = b1 * a.tb1, i20 = b2 * a.tb2;
@@ -115,21 +132,27 @@ __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
   for (int t = 0; t < NT; ++t) jt[t] = 16 * (t >> 2) + 4 * g + (t & 3);
 
   // weights as MFMA operands (zero outside h < ns, j < R)
-  auto sval = [&](int h, int j) -> float { return (h < ns && j < R) ? a.S[h][j] : 0.f; };
+  auto sval = [&](int h, int j) -> float {
+    return (h < ns && j < R) ? (h == 0 ? a.st[j] : a.shist[(size_t)(h - 1) * R + j]) : 0.f;
+  };
   float A1op[NH][NT], A2op[NM][NH][4], cv[NH][4];
 #pragma unroll
   for (int ht = 0; ht < NH; ++ht) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) A1op[ht][t] = sval(16 * ht + n, jt[t]);
 #pragma unroll
-    for (int mt = 0; mt < NM; ++mt)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) A2op[mt][ht][t] = sval(16 * ht + 4 * g + t, 16 * mt + n);
-#pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int h = 16 * ht + 4 * g + r;
-      cv[ht][r] = h < ns ? a.c[h] : 0.f;
+      cv[ht][r] = h < ns ? cl[h] : 0.f;
     }
+    // GEMM2's A operand carries the history weight: c_h S[h][j]
+#pragma unroll
+    for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int h = 16 * ht + 4 * g + t;
+        A2op[mt][ht][t] = (h < ns ? cl[h] : 0.f) * sval(h, 16 * mt + n);
+      }
   }
 
   for (int idx = lane; idx < kTB * RT; idx += 64) {
@@ -167,43 +190,66 @@ __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
         g3[u][t] = 0.f;
       }
 
-    for (int q = 0; q < npairs; ++q) {
-      const int i1l = q / n2, i2l = q - (q / n2) * n2;
-      const int i1 = i10 + i1l, i2 = i20 + i2l;
-      float W[NT];
+    // Software pipeline over the block's pairs: the loads of pair q+1 (slice
+    // values and factor rows) are issued before pair q is computed, and the
+    // compute part issues no global loads, so they stay in flight.
+    const int jslot = [&] {
+      const int tt = n >> (4 - LOGNT);
+      return 16 * (tt >> 2) + 4 * g + (tt & 3);
+    }();
+    float xb[NH][4][NU], Wb[NT], a1b = 0.f, a2b = 0.f;
+    auto load_pair = [&](int q) {
+      const int i1 = i10 + q / n2, i2 = i20 + (q - (q / n2) * n2);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        W[t] = jt[t] < R ? a.A1[(size_t)i1 * R + jt[t]] * a.A2[(size_t)i2 * R + jt[t]] : 0.f;
+        Wb[t] = jt[t] < R ? a.A1[(size_t)i1 * R + jt[t]] * a.A2[(size_t)i2 * R + jt[t]] : 0.f;
+      a1b = jslot < R ? a.A1[(size_t)i1 * R + jslot] : 0.f;
+      a2b = jslot < R ? a.A2[(size_t)i2 * R + jslot] : 0.f;
       const size_t base = ((size_t)i1 * I2 + i2) * I3;
-      float x[NH][4][NU];
 #pragma unroll
       for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int h = 16 * ht + 4 * g + r;
           if (h < ns) {
-            const float* Xh = a.X[h] + base;
+            const float* Xh = (h == 0 ? a.Xt : a.ring + (size_t)(h - 1) * a.omega) + base;
             if (wide && vec) {
               if constexpr (NU == 4) {
-                const f4 v = *reinterpret_cast<const f4*>(Xh + c0 + 4 * n);
-                x[ht][r][0] = v[0];
-                x[ht][r][1] = v[1];
-                x[ht][r][2] = v[2];
-                x[ht][r][3] = v[3];
+                const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(Xh + c0 + 4 * n));
+                xb[ht][r][0] = v[0];
+                xb[ht][r][1] = v[1];
+                xb[ht][r][2] = v[2];
+                xb[ht][r][3] = v[3];
               } else {
-                const f2 v = *reinterpret_cast<const f2*>(Xh + c0 + 2 * n);
-                x[ht][r][0] = v[0];
-                x[ht][r][1] = v[1];
+                const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(Xh + c0 + 2 * n));
+                xb[ht][r][0] = v[0];
+                xb[ht][r][1] = v[1];
               }
             } else {
 #pragma unroll
-              for (int u = 0; u < NU; ++u) x[ht][r][u] = vu[u] ? Xh[i3u[u]] : 0.f;
+              for (int u = 0; u < NU; ++u) xb[ht][r][u] = vu[u] ? Xh[i3u[u]] : 0.f;
             }
           } else {
 #pragma unroll
-            for (int u = 0; u < NU; ++u) x[ht][r][u] = 0.f;
+            for (int u = 0; u < NU; ++u) xb[ht][r][u] = 0.f;
           }
         }
+    };
+    if (npairs > 0) load_pair(0);
+
+    for (int q = 0; q < npairs; ++q) {
+      const int i1l = q / n2, i2l = q - (q / n2) * n2;
+      float W[NT], x[NH][4][NU];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) W[t] = Wb[t];
+#pragma unroll
+      for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int u = 0; u < NU; ++u) x[ht][r][u] = xb[ht][r][u];
+      const float a1s = a1b, a2s = a2b;
+      if (q + 1 < npairs) load_pair(q + 1);
 
       // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile)
       f4 D1[NH][NU];
@@ -219,19 +265,31 @@ __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
           D1[ht][u] = acc;
         }
 
-      // loss and weighted derivative in place
+      // loss and weighted derivative in place (cv = 0 marks padded slices;
+      // the objective terms of the group are summed plainly, then added to
+      // the lane's running sum with compensation)
+      if (want_loss) {
+        float part = 0.f;
+#pragma unroll
+        for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+          for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float fv = LossFast<LOSS>::f(x[ht][r][u], D1[ht][u][r]);
+              part += (vu[u] && cv[ht][r] != 0.f) ? cv[ht][r] * fv : 0.f;
+            }
+        lacc.add(part);
+      }
+      // y in place.  Entries past the end of a row (tail lanes) need no mask:
+      // their A3 values are zero, so every product that uses them vanishes
+      // and their mode-3 rows are never written.
 #pragma unroll
       for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
         for (int u = 0; u < NU; ++u)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float f, y;
-            LossFn<float, LOSS>::eval(x[ht][r][u], D1[ht][u][r], f, y);
-            const bool ok = vu[u] && cv[ht][r] != 0.f;
-            if (want_loss && ok) lacc.add(cv[ht][r] * f);
-            D1[ht][u][r] = ok ? cv[ht][r] * y : 0.f;
-          }
+          for (int r = 0; r < 4; ++r) D1[ht][u][r] = LossFast<LOSS>::y(x[ht][r][u], D1[ht][u][r]);
 
       // temporal-weight gradient: y_t sits in register 0 of lane group 0
       {
@@ -272,11 +330,9 @@ __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
       }
       const float v = row_reduce_scatter<NT>(Vp, n);
       if ((n & ((16 / NT) - 1)) == 0) {
-        const int tt = n >> (4 - LOGNT);
-        const int j = 16 * (tt >> 2) + 4 * g + (tt & 3);
-        if (j < R) {
-          g1w[wave][i1l][j] += v * a.A2[(size_t)i2 * R + j];
-          g2w[wave][i2l][j] += v * a.A1[(size_t)i1 * R + j];
+        if (jslot < R) {
+          g1w[wave][i1l][jslot] += v * a2s;
+          g2w[wave][i2l][jslot] += v * a1s;
         }
       }
     }
@@ -296,7 +352,7 @@ __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
     }
     for (int idx = tid; idx < SW * RT; idx += kThreads) {
       const int l = idx / RT, j = idx - (idx / RT) * RT;
-      if (c0 + l < I3 && j < R) a.G3p[((size_t)blockIdx.x * I3 + c0 + l) * R + j] = g3x[l][j];
+      if (c0 + l < I3 && j < R) a.G3p[((size_t)wgi * I3 + c0 + l) * R + j] = g3x[l][j];
     }
     __syncthreads();
   }
@@ -331,24 +387,35 @@ __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
   if (tid < R) {
     float s = 0.f;
     for (int w = 0; w < kWaves; ++w) s += gsx[w][tid];
-    a.gsp[(size_t)blockIdx.x * R + tid] = s;
+    a.gsp[(size_t)wgi * R + tid] = s;
   }
   if (tid == 0) {
     float s = 0.f;
     for (int w = 0; w < kWaves; ++w) s += lsx[w];
-    a.lossp[blockIdx.x] = s;
+    a.lossp[wgi] = s;
   }
+}
+
+template <int LOSS, int RT, int NH>
+__global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
+  __shared__ float sm[lds_floats(RT)];
+  __shared__ float cl[kMaxNs];
+  for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
+  __syncthreads();
+  mfma_tile<LOSS, RT, NH>(a.t, blockIdx.x, sm, cl);
 }
 
 template <int LOSS, int RT, int NH>
 hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p, float* gsp,
                   float* lossp) {
-  MArgs a;
-  for (int h = 0; h < c.ns; ++h) {
-    a.X[h] = static_cast<const float*>(c.X[h]);
-    a.S[h] = static_cast<const float*>(c.S[h]);
-    a.c[h] = (float)c.c[h];
-  }
+  MArgs m;
+  TileArgs& a = m.t;
+  for (int h = 0; h < kMaxNs; ++h) m.c[h] = h < c.ns ? (float)c.c[h] : 0.f;
+  a.Xt = static_cast<const float*>(c.X[0]);
+  a.ring = static_cast<const float*>(c.ring);
+  a.omega = c.omega;
+  a.st = static_cast<const float*>(c.S[0]);
+  a.shist = static_cast<const float*>(c.shist);
   a.A1 = static_cast<const float*>(c.A[0]);
   a.A2 = static_cast<const float*>(c.A[1]);
   a.A3 = static_cast<const float*>(c.A[2]);
@@ -359,7 +426,7 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.lossp = lossp;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
-  hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH>), dim3(p.nwg), dim3(kThreads), 0, c.stream, a);
+  hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
   return hipGetLastError();
 }
 
@@ -405,6 +472,274 @@ hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, 
     case kPoissonLog: return by_rank<kPoissonLog>(c, p, G1p, G2p, G3p, gsp, lossp);
     default: return by_rank<kBernoulliLogit>(c, p, G1p, G2p, G3p, gsp, lossp);
   }
+}
+
+}  // namespace gcp
+
+// ===========================================================================
+// Batched path: many independent streams in one persistent launch.
+//
+// Each stream's per-call state (time index, window fill, slot time stamps,
+// Adam iteration) lives in device memory, so a whole time step reads nothing
+// from the host and can be captured once as a HIP graph and replayed.  Work
+// items (stream, workgroup tile) are listed in decreasing cost; persistent
+// workgroups take the next item from a device counter.  Every item writes its
+// own partial slots, which the batched reduce sums in a fixed order, so the
+// results do not depend on which workgroup ran which item.
+// ===========================================================================
+namespace gcp {
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix64_dev(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int variant_of(int loss, int R, int H) {
+  return loss * 4 + (R > 16 ? 2 : 0) + (H + 1 > 16 ? 1 : 0);
+}
+
+template <int LOSS, int RT, int NH>
+__device__ __forceinline__ void run_variant(const TileArgs& ta, int wg, float* sm, const float* cl) {
+  mfma_tile<LOSS, RT, NH>(ta, wg, sm, cl);
+}
+
+__global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
+                                                              BatchState* __restrict__ state,
+                                                              const int2* __restrict__ items, int nitems,
+                                                              int* __restrict__ counter, int want) {
+  __shared__ float sm[lds_floats(32)];
+  __shared__ float cl[kMaxNs];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int si = items[it].x, wg = items[it].y;
+    const BatchDesc& d = desc[si];
+    const BatchState& s = state[si];
+    TileArgs ta;
+    ta.Xt = d.Xt;
+    ta.ring = d.ring;
+    ta.omega = (size_t)d.omega;
+    ta.st = d.st;
+    ta.shist = d.shist;
+    ta.A1 = d.A;
+    ta.A2 = d.A + d.fac_off1;
+    ta.A3 = d.A + d.fac_off2;
+    ta.G1p = d.G1p;
+    ta.G2p = d.G2p;
+    ta.G3p = d.G3p;
+    ta.gsp = d.gsp;
+    ta.lossp = d.lossp;
+    ta.I1 = d.I1; ta.I2 = d.I2; ta.I3 = d.I3; ta.R = d.R;
+    ta.ns = 1 + s.nwin;
+    ta.want = want;
+    ta.tb1 = d.tb1; ta.tb2 = d.tb2; ta.nb2 = d.nb2; ta.nblocks = d.nblocks;
+    for (int h = threadIdx.x; h < kMaxNs; h += kThreads) {
+      float v = 0.f;
+      if (h == 0) v = 1.f;
+      else if (h < ta.ns) v = (float)(d.w * pow(d.theta, (double)(s.t - s.slot_t[h - 1])));
+      cl[h] = v;
+    }
+    __syncthreads();
+    switch (d.variant) {
+      case 0: run_variant<kGaussian, 16, 1>(ta, wg, sm, cl); break;
+      case 1: run_variant<kGaussian, 16, 2>(ta, wg, sm, cl); break;
+      case 2: run_variant<kGaussian, 32, 1>(ta, wg, sm, cl); break;
+      case 3: run_variant<kGaussian, 32, 2>(ta, wg, sm, cl); break;
+      case 4: run_variant<kPoissonLog, 16, 1>(ta, wg, sm, cl); break;
+      case 5: run_variant<kPoissonLog, 16, 2>(ta, wg, sm, cl); break;
+      case 6: run_variant<kPoissonLog, 32, 1>(ta, wg, sm, cl); break;
+      case 7: run_variant<kPoissonLog, 32, 2>(ta, wg, sm, cl); break;
+      case 8: run_variant<kBernoulliLogit, 16, 1>(ta, wg, sm, cl); break;
+      case 9: run_variant<kBernoulliLogit, 16, 2>(ta, wg, sm, cl); break;
+      case 10: run_variant<kBernoulliLogit, 32, 1>(ta, wg, sm, cl); break;
+      default: run_variant<kBernoulliLogit, 32, 2>(ta, wg, sm, cl); break;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ float wave_sum_fixed_f(float v) {
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// Outputs of every stream: G1 | G2 | G3 | g_s | loss, one wave per element.
+// `outstart` is the prefix sum of per-stream output counts.  The last step
+// resets the work counter for the next launch.
+__global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchDesc* __restrict__ desc, int nstreams,
+                                                           const int64_t* __restrict__ outstart, int64_t nout,
+                                                           int* __restrict__ counter, int want, int* status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); o < nout; o += nwaves) {
+    int lo = 0, hi = nstreams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (outstart[mid] <= o) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc& d = desc[lo];
+    const int64_t e = o - outstart[lo];
+    const int R = d.R;
+    const int n1 = d.I1 * R, n2 = d.I2 * R, n3 = d.I3 * R;
+    const float* src;
+    int64_t stride;
+    int slots;
+    float reg;
+    float* dst;
+    bool is_loss = false;
+    if (e < n1) {
+      src = d.G1p + e; stride = n1; slots = d.nb2; reg = d.lam * d.A[e]; dst = d.outG[0] + e;
+    } else if (e < n1 + n2) {
+      const int64_t k = e - n1;
+      src = d.G2p + k; stride = n2; slots = d.nb1; reg = d.lam * d.A[d.fac_off1 + k]; dst = d.outG[1] + k;
+    } else if (e < n1 + n2 + n3) {
+      const int64_t k = e - n1 - n2;
+      src = d.G3p + k; stride = n3; slots = d.nwg; reg = d.lam * d.A[d.fac_off2 + k]; dst = d.outG[2] + k;
+    } else if (e < n1 + n2 + n3 + R) {
+      const int64_t k = e - n1 - n2 - n3;
+      src = d.gsp + k; stride = R; slots = d.nwg; reg = d.mu * d.st[k]; dst = d.outgs + k;
+    } else {
+      is_loss = true;
+      src = d.lossp; stride = 1; slots = d.nwg; dst = d.outloss;
+      // regularisation of the objective, summed by the same wave
+      Kahan<float> kr;
+      for (int64_t i = lane; i < d.fac_elems; i += 64) kr.add(d.A[i] * d.A[i]);
+      Kahan<float> ks;
+      for (int i = lane; i < R; i += 64) ks.add(d.st[i] * d.st[i]);
+      reg = 0.5f * d.lam * wave_sum_fixed_f(kr.s) + 0.5f * d.mu * wave_sum_fixed_f(ks.s);
+    }
+    if (is_loss ? !(want & kWantLoss) : !(want & kWantGrad)) continue;
+    Kahan<float> k;
+    for (int b = lane; b < slots; b += 64) k.add(src[(int64_t)b * stride]);
+    const float sum = wave_sum_fixed_f(k.s);
+    if (lane == 0) {
+      const float out = sum + reg;
+      *dst = out;
+      if (!isfinite(out)) atomicOr(status, (int)kStatusNonFinite);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+}
+
+// Adam Step (Algorithm 2) over the factor entries of every stream; the
+// bias-corrected rate comes from the stream's device-side iteration index.
+__global__ void __launch_bounds__(256) batch_adam_kernel(const BatchDesc* __restrict__ desc,
+                                                         const BatchState* __restrict__ state, int nstreams,
+                                                         const int64_t* __restrict__ facstart, int64_t nfac) {
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nfac; o += (int64_t)gridDim.x * 256) {
+    int lo = 0, hi = nstreams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (facstart[mid] <= o) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc& d = desc[lo];
+    const int64_t e = o - facstart[lo];
+    const double n = (double)(state[lo].adam_i + 1);
+    const float at = (float)(d.alpha * sqrt(1.0 - pow(d.beta2d, n)) / (1.0 - pow(d.beta1d, n)));
+    const float g = d.Gs[e];
+    const float u = d.beta1 * d.u[e] + (1.f - d.beta1) * g;
+    const float v = d.beta2 * d.v[e] + (1.f - d.beta2) * g * g;
+    d.u[e] = u;
+    d.v[e] = v;
+    const float a = d.A[e] - at * u / (sqrtf(v) + d.eps);
+    d.A[e] = a > d.lower ? a : d.lower;
+  }
+}
+
+__global__ void batch_adam_tick(BatchState* state, int nstreams) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nstreams) state[i].adam_i += 1;
+}
+
+// Reservoir decision of Algorithm 1 for every stream (one thread each):
+// append while the window is not full, else j = SplitMix64(seed ^ t) mod t + 1
+// replaces slot j-1 when j <= H.  Records the slot for the copy kernel, then
+// advances t.
+__global__ void batch_window_decide(const BatchDesc* __restrict__ desc, BatchState* __restrict__ state,
+                                    int nstreams) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nstreams) return;
+  BatchState& s = state[i];
+  const int H = desc[i].H;
+  int slot = -1;
+  if (H > 0) {
+    if (s.nwin < H) {
+      slot = s.nwin;
+      s.nwin += 1;
+    } else {
+      const uint64_t t = (uint64_t)s.t;
+      const uint64_t j = splitmix64_dev(desc[i].seed ^ t) % t + 1;
+      if (j <= (uint64_t)H) slot = (int)(j - 1);
+    }
+  }
+  s.pending_slot = slot;
+  if (slot >= 0) s.slot_t[slot] = s.t;
+  s.t += 1;
+}
+
+// Copies X_t and s_t into the chosen window slot and A into A_old.
+__global__ void __launch_bounds__(256) batch_window_copy(const BatchDesc* __restrict__ desc,
+                                                         const BatchState* __restrict__ state, int nstreams,
+                                                         const int64_t* __restrict__ cpystart, int64_t ncpy) {
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < ncpy; o += (int64_t)gridDim.x * 256) {
+    int lo = 0, hi = nstreams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cpystart[mid] <= o) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc& d = desc[lo];
+    const int slot = state[lo].pending_slot;
+    int64_t e = o - cpystart[lo];
+    if (e < d.fac_elems) {
+      d.Aold[e] = d.A[e];
+      continue;
+    }
+    e -= d.fac_elems;
+    if (slot < 0) continue;
+    if (e < d.omega)
+      d.ring[(int64_t)slot * d.omega + e] = d.Xt[e];
+    else if (e - d.omega < d.R)
+      d.shist[(int64_t)slot * d.R + (e - d.omega)] = d.st[e - d.omega];
+  }
+}
+
+}  // namespace
+
+int batch_variant(int loss, int R, int H) { return loss * 4 + (R > 16 ? 2 : 0) + (H + 1 > 16 ? 1 : 0); }
+
+hipError_t batch_grad_run(const BatchRun& b, int want) {
+  hipLaunchKernelGGL(batch_grad_kernel, dim3(b.grid), dim3(kThreads), 0, b.stream, b.desc, b.state, b.items,
+                     b.nitems, b.counter, want);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int rblocks = (int)std::min<int64_t>(4096, (b.nout + 3) / 4);
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(std::max(1, rblocks)), dim3(256), 0, b.stream, b.desc, b.nstreams,
+                     b.outstart, b.nout, b.counter, want, b.status);
+  return hipGetLastError();
+}
+
+hipError_t batch_adam_run(const BatchRun& b) {
+  const int blocks = (int)std::min<int64_t>(2048, (b.nfac + 255) / 256);
+  hipLaunchKernelGGL(batch_adam_kernel, dim3(std::max(1, blocks)), dim3(256), 0, b.stream, b.desc, b.state,
+                     b.nstreams, b.facstart, b.nfac);
+  hipLaunchKernelGGL(batch_adam_tick, dim3((b.nstreams + 63) / 64), dim3(64), 0, b.stream, b.state, b.nstreams);
+  return hipGetLastError();
+}
+
+hipError_t batch_window_run(const BatchRun& b) {
+  hipLaunchKernelGGL(batch_window_decide, dim3((b.nstreams + 63) / 64), dim3(64), 0, b.stream, b.desc, b.state,
+                     b.nstreams);
+  const int blocks = (int)std::min<int64_t>(8192, (b.ncpy + 255) / 256);
+  hipLaunchKernelGGL(batch_window_copy, dim3(std::max(1, blocks)), dim3(256), 0, b.stream, b.desc, b.state,
+                     b.nstreams, b.cpystart, b.ncpy);
+  return hipGetLastError();
 }
 
 }  // namespace gcp

@@ -208,3 +208,67 @@ def gcp_solve_st(stream: Stream, X_t, out=None):
 
 def gcp_update_factors(stream: Stream, X_t, s_t):
     return stream.update_factors(X_t, s_t)
+
+
+class Batch:
+    """Many dense streams advanced together (persistent multi-stream launch).
+
+    inputs: per stream a fixed X_t buffer and s_t buffer (refresh their
+    contents before each call); outputs: per stream (loss, [G1, G2, G3], g_s)
+    tensors written by loss_grad.  All calls run on the streams' HIP stream
+    and can be captured in a torch.cuda.CUDAGraph on that stream."""
+
+    def __init__(self, streams: Sequence[Stream], X_t: Sequence[torch.Tensor],
+                 s_t: Sequence[torch.Tensor], outputs=None):
+        self.lib = N.load()
+        self.streams = list(streams)
+        n = len(self.streams)
+        dev = self.streams[0].device
+        self.X_t = [x.contiguous() for x in X_t]
+        self.s_t = [s.contiguous() for s in s_t]
+        if outputs is None:
+            outputs = [(torch.empty(1, device=dev),
+                        [torch.empty(d, st.rank, device=dev) for d in st.dims],
+                        torch.empty(st.rank, device=dev)) for st in self.streams]
+        self.outputs = outputs
+        hs = (c_void_p * n)(*[st.handle.value for st in self.streams])
+        io = (N.GcpBatchIO * n)()
+        for i in range(n):
+            io[i].X_t = self.X_t[i].data_ptr()
+            io[i].s_t = self.s_t[i].data_ptr()
+            loss, G, g_s = outputs[i]
+            io[i].loss = loss.data_ptr()
+            for k in range(3):
+                io[i].G[k] = G[k].data_ptr()
+            io[i].g_s = g_s.data_ptr()
+        nbytes = c_size_t(0)
+        N.check(self.lib.gcp_batch_workspace_size(hs, n, byref(nbytes)), "gcp_batch_workspace_size")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        handle = c_void_p(0)
+        torch.cuda.synchronize(dev)
+        N.check(self.lib.gcp_batch_create(hs, io, n, _ptr(self.workspace), nbytes,
+                                          c_void_p(self.streams[0].hip_stream.cuda_stream),
+                                          byref(handle)), "gcp_batch_create")
+        self.handle = handle
+
+    def loss_grad(self, want_loss: bool = True, want_grad: bool = True):
+        want = (N.WANT_LOSS if want_loss else 0) | (N.WANT_GRAD if want_grad else 0)
+        N.check(self.lib.gcp_batch_loss_grad(self.handle, want), "gcp_batch_loss_grad")
+        return self.outputs
+
+    def update_factors(self):
+        N.check(self.lib.gcp_batch_update_factors(self.handle), "gcp_batch_update_factors")
+
+    def sync_streams(self) -> int:
+        return int(self.lib.gcp_batch_sync_streams(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.gcp_batch_destroy(self.handle)
+            self.handle = c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,7 +31,11 @@ def test_gradcheck_fp64_c3_subinstance(loss):
     st = make_stream(prob, dev)
     inputs = tuple(_leaf(a) for a in dev["A"]) + (_leaf(dev["s_t"]),)
     f = lambda A1, A2, A3, s: gcp_loss(st, dev["X_t"], [A1, A2, A3], s)
-    assert torch.autograd.gradcheck(f, inputs, eps=1e-6, atol=1e-6, rtol=1e-5)
+    # the Gaussian objective is exactly quadratic in any single factor entry
+    # and in s, so central differences are exact at any step: a larger step
+    # keeps FP64 rounding of F (~3e4) out of the comparison
+    eps = 1e-3 if loss == "gaussian" else 1e-6
+    assert torch.autograd.gradcheck(f, inputs, eps=eps, atol=1e-6, rtol=1e-5)
     assert st.sync() == 0
 
 
