@@ -120,6 +120,8 @@ def bench_c4(args):
     import gcp_inputs as gi
     from paper_2110_14514_amd import Batch, Stream
     specs = gi.c4_specs()
+    side = torch.cuda.Stream()       # graph capture needs a non-default stream
+    torch.cuda.set_stream(side)
     streams, Xb, Sb = [], [], []
     tot_bytes = 0
     tot_flops = 0
@@ -143,7 +145,7 @@ def bench_c4(args):
     torch.cuda.synchronize()
     with torch.cuda.graph(g, stream=cs):
         b.loss_grad()
-    gsec = _time(g.replay, args.steps, args.warmup, torch.cuda.synchronize)
+    gsec = _time(g.replay, args.steps, args.warmup, torch.cuda.synchronize)   # replays on `side`
     assert b.sync_streams() == 0
     _line("C4 64 independent streams, dims U{50..300}^3, rank {8,16,32}, window 4..16, "
           "Gaussian/Poisson-log; one batched gcp_batch_loss_grad (all 64 stream gradients)",

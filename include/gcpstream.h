@@ -215,6 +215,16 @@ gcp_status gcp_stream_sync(gcp_stream* s);
 
 gcp_status gcp_stream_destroy(gcp_stream* s);
 
+/* Autotuner for the matrix-core work plan (how the slice's (i1,i2) pairs are
+ * cut into wave blocks).  Times every candidate plan on the device with HIP
+ * events over X_t and the current window (synchronous; not for use inside a
+ * graph capture), keeps the fastest for this stream (and for batches created
+ * afterwards), and appends "<arch> <I1> <I2> <I3> R<r> H<h> ns<n> loss<l> =
+ * <plan>" to the text file cache_path (NULL: no cache).  A cache hit skips the
+ * timing.  Results are identical for every plan up to summation order.
+ * *chosen (may be NULL) receives the plan.  Dense FP32 streams only. */
+gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_path, int32_t* chosen);
+
 /* ------------------------------------------------------------------------
  * Batching: many independent dense FP32 streams (rank <= 32, window <= 31)
  * advanced together.  Each stream keeps its own workspace; the batch adds a

@@ -5,6 +5,7 @@
 #include "../../include/gcpstream.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -18,11 +19,11 @@
 using namespace gcp;
 
 struct WsLayout {
-  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, total;
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, rec, total;
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
   size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
-  size_t plain_bytes, part_bytes;
+  size_t plain_bytes, part_bytes, rec_bytes;
 };
 
 struct gcp_stream {
@@ -42,6 +43,7 @@ struct gcp_stream {
   int* status;
   std::vector<hipEvent_t> ev;   // begin/end pairs for gcp_kernel_timing
   int ev_used;
+  int plan_target;              // matrix-core work plan chosen by gcp_autotune
 };
 
 namespace {
@@ -108,6 +110,8 @@ WsLayout layout_for(const gcp_params* p) {
   L.ls = off; off = align_up(off + (coo ? 0 : ls_scratch_bytes(I1, I2, I3, R)), 256);
   L.plain_bytes = (p->flags & GCP_FLAG_PLAIN_SCRATCH) ? dense_plain_scratch_bytes(I1, I2, I3, R, p->dtype) : 0;
   L.plain = off; off = align_up(off + L.plain_bytes, 256);
+  L.rec_bytes = coo ? sampled_scratch_bytes(I1, I2, I3, R, p->window + 1, p->p, p->q) : 0;
+  L.rec = off; off = align_up(off + L.rec_bytes, 256);
   L.total = off;
   return L;
 }
@@ -174,6 +178,8 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.p = s->p.p; c.q = s->p.q; c.seed = s->p.seed;
   c.call = s->sample_call++;
   c.status = s->status; c.stream = s->st;
+  c.rec = s->L.rec_bytes ? s->ws + s->L.rec : nullptr;
+  c.rec_bytes = s->L.rec_bytes;
   return c;
 }
 
@@ -209,6 +215,7 @@ DenseCall base_call(gcp_stream* s) {
   c.stream = s->st;
   c.c[0] = 1.0;
   c.kernel = (s->p.flags & GCP_FLAG_KERNEL_VALU) ? 1 : ((s->p.flags & GCP_FLAG_KERNEL_MFMA) ? 2 : 0);
+  c.plan_target = s->plan_target;
   return c;
 }
 
@@ -283,6 +290,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   gcp_stream* s = new (std::nothrow) gcp_stream();
   if (!s) return GCP_E_ARG;
   s->p = *p;
+  s->plan_target = kDefaultPlanTarget;
   s->es = p->dtype == GCP_F64 ? 8 : 4;
   for (int k = 0; k < 3; ++k) s->dims[k] = (int)p->dims[k];
   s->omega = (size_t)s->dims[0] * s->dims[1] * s->dims[2];
@@ -549,6 +557,98 @@ const char* gcp_status_string(gcp_status st) {
 
 }  // extern "C"
 
+// ------------------------------------------------------------- autotuner
+namespace {
+
+bool cache_lookup(const char* path, const char* key, int* value) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[400];
+    int v = 0;
+    if (sscanf(line, "%399[^=]= %d", k, &v) == 2) {
+      size_t n = strlen(k);
+      while (n > 0 && k[n - 1] == ' ') k[--n] = 0;
+      if (strcmp(k, key) == 0) {
+        *value = v;
+        found = true;
+      }
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+}  // namespace
+
+extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_path, int32_t* chosen) {
+  if (!s) return GCP_E_ARG;
+  if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32) return GCP_E_UNSUPPORTED;
+  gcp_status st = check_dense_slice(s, X_t);
+  if (st != GCP_OK) return st;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return GCP_E_DEVICE;
+  char key[400];
+  snprintf(key, sizeof key, "%s %d %d %d R%d H%d ns%d loss%d", prop.gcnArchName, s->dims[0], s->dims[1],
+           s->dims[2], s->p.rank, s->p.window, 1 + s->nwin, s->p.loss);
+  int best = 0;
+  if (cache_lookup(cache_path, key, &best)) {
+    s->plan_target = best;
+    if (chosen) *chosen = best;
+    return GCP_OK;
+  }
+  DenseCall c = base_call(s);
+  c.want = kWantLoss | kWantGrad;
+  c.kernel = 2;
+  c.X[0] = X_t->vals;
+  c.S[0] = s->ws + s->L.shist;   // any R weights will do for timing
+  if (s->nwin == 0) c.S[0] = s->ws + s->L.A;
+  fill_window(s, c);
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = fac_ptr(s, s->L.A, k);
+    c.G[k] = fac_ptr(s, s->L.G, k);
+  }
+  c.gs = s->ws + s->L.gs;
+  c.loss_out = s->ws + s->L.loss;
+  if (!mfma_supported(c.R, c.ns, 0)) return GCP_E_UNSUPPORTED;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GCP_E_DEVICE;
+  float best_ms = 1e30f;
+  best = kDefaultPlanTarget;
+  for (int i = 0; i < kNumPlanTargets; ++i) {
+    c.plan_target = kPlanTargets[i];
+    hipError_t e = dense_fused_run(c);  // warm-up
+    if (e != hipSuccess) break;
+    hipEventRecord(e0, s->st);
+    const int reps = 5;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = dense_fused_run(c);
+    hipEventRecord(e1, s->st);
+    if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = kPlanTargets[i];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  s->plan_target = best;
+  if (chosen) *chosen = best;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s = %d\n", key, best);
+      fclose(f);
+    }
+  }
+  return GCP_OK;
+}
+
 // --------------------------------------------------------------- batching
 struct gcp_batch {
   std::vector<gcp_stream*> streams;
@@ -598,7 +698,7 @@ BatchLayout batch_layout(gcp_stream* const* streams, int32_t n) {
   L.nitems = 0;
   for (int i = 0; i < n; ++i) {
     const gcp_stream* s = streams[i];
-    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2]));
+    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2], s->plan_target));
     L.nitems += L.plans.back().nwg;
   }
   L.desc_out = off; off = align_up(off + n * sizeof(BatchDesc), 256);

@@ -63,12 +63,22 @@ template <>
 struct LossFast<kGaussian> {
   __device__ __forceinline__ static float y(float x, float m) { return 2.f * (m - x); }
   __device__ __forceinline__ static float f(float x, float m) { return (x - m) * (x - m); }
+  __device__ __forceinline__ static void fy(float x, float m, float& f, float& y) {
+    const float d = m - x;
+    f = d * d;
+    y = 2.f * d;
+  }
 };
 
 template <>
 struct LossFast<kPoissonLog> {
   __device__ __forceinline__ static float y(float x, float m) { return __expf(m) - x; }
   __device__ __forceinline__ static float f(float x, float m) { return __expf(m) - x * m; }
+  __device__ __forceinline__ static void fy(float x, float m, float& f, float& y) {
+    const float e = __expf(m);
+    f = e - x * m;
+    y = e - x;
+  }
 };
 
 template <>
@@ -80,6 +90,12 @@ struct LossFast<kBernoulliLogit> {
   }
   __device__ __forceinline__ static float f(float x, float m) {
     return fmaxf(m, 0.f) + __logf(1.f + __expf(-fabsf(m))) - x * m;
+  }
+  __device__ __forceinline__ static void fy(float x, float m, float& f, float& y) {
+    const float e = __expf(-fabsf(m));
+    const float inv = __frcp_rn(1.f + e);
+    f = fmaxf(m, 0.f) + __logf(1.f + e) - x * m;
+    y = (m >= 0.f ? inv : e * inv) - x;
   }
 };
 
@@ -121,6 +137,7 @@ struct DenseCall {
   hipEvent_t ev_begin;          // optional: recorded around the main kernel
   hipEvent_t ev_end;
   int kernel;                   // 0 automatic, 1 VALU kernel, 2 matrix-core kernel
+  int plan_target;              // matrix-core work plan (wanted wave blocks)
   const void* grad_scale;       // optional device scalar multiplying the gradients
 };
 
@@ -129,7 +146,12 @@ struct MfmaPlan {
   int tb1, tb2, nb1, nb2, nblocks, nwg;
 };
 bool mfma_supported(int R, int ns, int dtype);
-MfmaPlan mfma_plan(int I1, int I2, int I3);
+// target: wanted number of wave blocks (0 = default).  Candidates the
+// autotuner tries are kPlanTargets; workspaces are sized for all of them.
+constexpr int kPlanTargets[] = {1024, 2048, 4096, 8192, 16384};
+constexpr int kNumPlanTargets = 5;
+constexpr int kDefaultPlanTarget = 4096;
+MfmaPlan mfma_plan(int I1, int I2, int I3, int target = kDefaultPlanTarget);
 hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                              float* gsp, float* lossp);
 
@@ -209,9 +231,14 @@ struct SampledCall {
   uint64_t seed;
   int64_t call;                   // sampler call number
   int* status;
+  void* rec;                      // draw records of the two-phase variant (or null)
+  size_t rec_bytes;
   hipStream_t stream;
   hipEvent_t ev_begin, ev_end;
 };
+// Bytes of draw records for up to ns_max slices, 0 when the two-phase
+// variant does not apply to these sizes.
+size_t sampled_scratch_bytes(int I1, int I2, int I3, int R, int ns_max, int64_t p, int64_t q);
 hipError_t sampled_run(const SampledCall& c);
 
 // Unfused baseline: model, elementwise, per-mode MTTKRP kernels.

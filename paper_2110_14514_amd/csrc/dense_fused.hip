@@ -80,8 +80,8 @@ PartLayout part_layout(int I1, int I2, int I3, int R, size_t es) {
   return part_layout_slots(I1, I2, I3, R, es, t.nb2, t.nb1, t.ntiles);
 }
 
-PartLayout part_layout_mfma(int I1, int I2, int I3, int R) {
-  MfmaPlan m = mfma_plan(I1, I2, I3);
+PartLayout part_layout_mfma(int I1, int I2, int I3, int R, int target) {
+  MfmaPlan m = mfma_plan(I1, I2, I3, target);
   return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2, m.nb1, m.nwg);
 }
 
@@ -437,7 +437,8 @@ hipError_t dispatch_loss(const DenseCall& c, const Tiling& tl, const PartLayout&
 
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype) {
   size_t v = part_layout(I1, I2, I3, R, dtype ? sizeof(double) : sizeof(float)).total;
-  if (dtype == 0) v = std::max(v, part_layout_mfma(I1, I2, I3, R).total);
+  if (dtype == 0)
+    for (int i = 0; i < kNumPlanTargets; ++i) v = std::max(v, part_layout_mfma(I1, I2, I3, R, kPlanTargets[i]).total);
   return v;
 }
 
@@ -445,8 +446,8 @@ hipError_t dense_fused_run(const DenseCall& c) {
   const bool mfma_ok = mfma_supported(c.R, c.ns, c.dtype);
   bool use_mfma = c.kernel == 2 ? mfma_ok : (c.kernel == 1 ? false : (mfma_ok && c.R > 8));
   if (use_mfma) {
-    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3);
-    PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R);
+    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, c.plan_target);
+    PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R, c.plan_target);
     if (pl.total > c.part_bytes) return hipErrorInvalidValue;
     char* base = static_cast<char*>(c.part);
     if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);

@@ -23,16 +23,18 @@
 // step t held by lane group g is j(t,g) = 16 (t/4) + 4g + t%4, chosen so that
 // GEMM2's output row of register r in M-tile mt, j = 16 mt + 4g + r, is the
 // same j a lane already holds for step t = 4 mt + r.
-// Entries: a full group is NU 16-column tiles u (NU = 4 at rank 16, 2 at
-// rank 32, to fit the register file) with i3 = c0 + NU n + u, so each lane
-// loads NU contiguous values per slice; the ragged tail of a row uses
-// i3 = c0 + 16u + n with only the tiles that hold entries.
+// Entries: a full group is NU = 2 16-column tiles u (32 entries, sized to the
+// register file) with i3 = c0 + 2n + u, so each lane loads 2 contiguous
+// values per slice; the ragged tail of a row uses i3 = c0 + 16u + n with only
+// the tiles that hold entries.
 //
 // Work decomposition: each wave owns a TB1 x TB2 block of pairs over all of
 // I3; eight waves form a workgroup that combines its waves' mode-3 rows and
 // temporal-gradient partials in a fixed order.  All partials go to
 // block/workgroup-indexed slots and are summed in a fixed order by the
 // reduce kernel, so results are bitwise reproducible.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace gcp {
@@ -43,7 +45,7 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kTB = 32;
+constexpr int kTB = 16;
 
 // Everything one workgroup needs for its tile of pair blocks.  Slice h = 0 is
 // the current slice; slice h >= 1 is window slot h-1 of the ring (slot order),
@@ -70,13 +72,94 @@ struct MArgs {
   float c[kMaxNs];
 };
 
-// LDS floats used by one workgroup at rank tile RT
-__host__ __device__ constexpr int lds_floats(int RT) {
-  return 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT + kWaves;
+// Per-wave LDS ring of the staged pipeline: kStages stages, each holding
+// 16*NH slice rows of 32 values and the pair's two factor rows (64 values).
+constexpr int kStages = 3;
+__host__ __device__ constexpr int stage_floats(int NH) { return 16 * NH * 32 + 64; }
+__host__ __device__ constexpr int ring_floats(int NH) { return NH <= 2 ? kWaves * kStages * stage_floats(NH) : 0; }
+
+// LDS floats used by one workgroup at rank tile RT and NH h-tiles
+__host__ __device__ constexpr int lds_floats(int RT, int NH) {
+  return 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT + kWaves + ring_floats(NH);
 }
+
+// Wait until at most n vector-memory operations of this wave are in flight
+// (n is wave-uniform; the immediate must be a constant).  n >= 40 waits for
+// 40, which is always safe (it only waits longer).
+__device__ __forceinline__ void wait_vmcnt(int n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+    case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
+    case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
+    case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
+    case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
+    case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+    case 15: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
+    case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 17: asm volatile("s_waitcnt vmcnt(17)" ::: "memory"); break;
+    case 18: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
+    case 19: asm volatile("s_waitcnt vmcnt(19)" ::: "memory"); break;
+    case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 21: asm volatile("s_waitcnt vmcnt(21)" ::: "memory"); break;
+    case 22: asm volatile("s_waitcnt vmcnt(22)" ::: "memory"); break;
+    case 23: asm volatile("s_waitcnt vmcnt(23)" ::: "memory"); break;
+    case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    case 25: asm volatile("s_waitcnt vmcnt(25)" ::: "memory"); break;
+    case 26: asm volatile("s_waitcnt vmcnt(26)" ::: "memory"); break;
+    case 27: asm volatile("s_waitcnt vmcnt(27)" ::: "memory"); break;
+    case 28: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 29: asm volatile("s_waitcnt vmcnt(29)" ::: "memory"); break;
+    case 30: asm volatile("s_waitcnt vmcnt(30)" ::: "memory"); break;
+    case 31: asm volatile("s_waitcnt vmcnt(31)" ::: "memory"); break;
+    case 32: asm volatile("s_waitcnt vmcnt(32)" ::: "memory"); break;
+    case 33: asm volatile("s_waitcnt vmcnt(33)" ::: "memory"); break;
+    case 34: asm volatile("s_waitcnt vmcnt(34)" ::: "memory"); break;
+    case 35: asm volatile("s_waitcnt vmcnt(35)" ::: "memory"); break;
+    case 36: asm volatile("s_waitcnt vmcnt(36)" ::: "memory"); break;
+    case 37: asm volatile("s_waitcnt vmcnt(37)" ::: "memory"); break;
+    case 38: asm volatile("s_waitcnt vmcnt(38)" ::: "memory"); break;
+    case 39: asm volatile("s_waitcnt vmcnt(39)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(40)" ::: "memory"); break;
+  }
+#else
+  (void)n;
+#endif
+}
+
+// Direct global -> LDS copy of `bytes` (4 or 16) per lane: lane i writes at
+// lds + i * bytes (lds is wave-uniform); completion is counted by vmcnt.
+__device__ __forceinline__ void load_to_lds(const float* src, float* lds, int bytes) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (bytes == 16)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+#else
+  (void)src; (void)lds; (void)bytes;
+#endif
+}
+
+
 
 __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Bitwise select that cannot be turned into a select of addresses (which
+// would force the array it reads from into private memory).
+__device__ __forceinline__ float pick(bool c, float a, float b) {
+  const unsigned m = 0u - (unsigned)c;
+  return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
 }
 
 template <int NT>
@@ -88,8 +171,9 @@ __device__ __forceinline__ float row_reduce_scatter(float (&v)[NT], int n) {
     const bool hi = (n & mask) != 0;
 #pragma unroll
     for (int i = 0; i < half; ++i) {
-      float send = hi ? v[i] : v[i + half];
-      float keep = hi ? v[i + half] : v[i];
+      const float lo_v = v[i], hi_v = v[i + half];
+      const float send = pick(hi, lo_v, hi_v);
+      const float keep = pick(hi, hi_v, lo_v);
       v[i] = keep + __shfl_xor(send, mask);
     }
     mask >>= 1;
@@ -106,7 +190,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
-  constexpr int NU = RT == 32 ? 2 : 4;  // 16-entry tiles per group (register budget)
+  constexpr int NU = 2;                 // 16-entry tiles per group (register budget)
   constexpr int SW = 16 * NU;           // entries per full group
 
   float(*g1w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(sm);
@@ -116,8 +200,12 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   float* lsx = sm + 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform across the wave: keeping it scalar keeps all
+  // tile bookkeeping below in scalar registers and branches uniform
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = lane & 15, g = lane >> 4;
+  // this wave's staging ring (NH <= 2)
+  float* ring_w = lsx + kWaves + wave * kStages * stage_floats(NH);
   const int R = a.R, ns = a.ns, I1 = a.I1, I2 = a.I2, I3 = a.I3;
   const int blk = wgi * kWaves + wave;
   const bool active = blk < a.nblocks;
@@ -127,15 +215,31 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   const int n2 = active ? min(a.tb2, I2 - i20) : 0;
   const bool want_loss = a.want & kWantLoss;
 
-  int jt[NT];
+  // j held by this lane at GEMM1 step t; clamped index and 0/1 mask make the
+  // factor-row loads branch-free when R is not a multiple of the rank tile
+  int jt[NT], jc[NT];
+  float jm[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) jt[t] = 16 * (t >> 2) + 4 * g + (t & 3);
+  for (int t = 0; t < NT; ++t) {
+    jt[t] = 16 * (t >> 2) + 4 * g + (t & 3);
+    jc[t] = min(jt[t], R - 1);
+    jm[t] = jt[t] < R ? 1.f : 0.f;
+  }
+  const int jslot = [&] {
+    const int tt = n >> (4 - LOGNT);
+    return 16 * (tt >> 2) + 4 * g + (tt & 3);
+  }();
+  const int jsc = min(jslot, R - 1);
+  const float jsm = jslot < R ? 1.f : 0.f;
 
   // weights as MFMA operands (zero outside h < ns, j < R)
   auto sval = [&](int h, int j) -> float {
     return (h < ns && j < R) ? (h == 0 ? a.st[j] : a.shist[(size_t)(h - 1) * R + j]) : 0.f;
   };
   float A1op[NH][NT], A2op[NM][NH][4], cv[NH][4];
+  // base pointer of the slice each (h-tile, register) row of this lane reads
+  const float* sb[NH][4];
+  bool hv[NH][4];
 #pragma unroll
   for (int ht = 0; ht < NH; ++ht) {
 #pragma unroll
@@ -144,6 +248,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     for (int r = 0; r < 4; ++r) {
       const int h = 16 * ht + 4 * g + r;
       cv[ht][r] = h < ns ? cl[h] : 0.f;
+      hv[ht][r] = h < ns;
+      sb[ht][r] = (h == 0 || h >= ns) ? a.Xt : a.ring + (size_t)(h - 1) * a.omega;
     }
     // GEMM2's A operand carries the history weight: c_h S[h][j]
 #pragma unroll
@@ -159,6 +265,25 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     (&g1w[wave][0][0])[idx] = 0.f;
     (&g2w[wave][0][0])[idx] = 0.f;
   }
+  if constexpr (NH <= 2) {
+    // slice rows past the window are never loaded into the ring; they must
+    // hold finite values (their products are multiplied by zero weights)
+    for (int idx = lane; idx < kStages * stage_floats(NH); idx += 64) ring_w[idx] = 0.f;
+    // the zeros must land before any direct-to-LDS copy into the ring
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#endif
+  }
+  // Staged loads (NH <= 2).  With 16-byte copies (rows 16-byte aligned, I3 a
+  // multiple of 4) instruction k covers slice rows 8k .. 8k+7, lane l copying
+  // 4 values of row 8k + l/8; with 4-byte copies instruction k covers rows
+  // 2k, 2k+1, lane l copying value l%32 of row 2k + l/32.  Row h >= 1 lies
+  // at ring + (h-1) omega, row 0 is the current slice.
+  const bool dma16 = (I3 & 3) == 0;
+  const int hsub = dma16 ? (lane >> 3) : (lane >> 5);           // row within an instruction
+  const int esub = dma16 ? 4 * (lane & 7) : (lane & 31);         // entry within the 32-entry group
+  const int rows_per = dma16 ? 8 : 2;
+  const int kx = (ns + rows_per - 1) / rows_per;                 // row instructions per pair (uniform)
   float gsacc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) gsacc[t] = 0.f;
@@ -174,167 +299,263 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     const bool wide = sc < nfull;
     const int c0 = SW * sc;
     const int nu = wide ? NU : (tail + 15) >> 4;
+    // entries held by this lane: NU adjacent ones in a full group (and in
+    // every group of the staged path), else one per 16-entry tile
+    const bool adj = wide || NH <= 2;
     int i3u[NU];
     bool vu[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      i3u[u] = c0 + (wide ? NU * n + u : 16 * u + n);
-      vu[u] = u < nu && i3u[u] < I3;
+      i3u[u] = c0 + (adj ? NU * n + u : 16 * u + n);
+      vu[u] = (adj || u < nu) && i3u[u] < I3;
     }
     float a3r[NU][NT], g3[NU][NT];
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
+    for (int u = 0; u < NU; ++u) {
+      const size_t row = (size_t)(vu[u] ? i3u[u] : 0) * R;
+      const float um = vu[u] ? 1.f : 0.f;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        a3r[u][t] = (vu[u] && jt[t] < R) ? a.A3[(size_t)i3u[u] * R + jt[t]] : 0.f;
+        a3r[u][t] = a.A3[row + jc[t]] * (jm[t] * um);
         g3[u][t] = 0.f;
       }
+    }
 
     // Software pipeline over the block's pairs: the loads of pair q+1 (slice
-    // values and factor rows) are issued before pair q is computed, and the
-    // compute part issues no global loads, so they stay in flight.
-    const int jslot = [&] {
-      const int tt = n >> (4 - LOGNT);
-      return 16 * (tt >> 2) + 4 * g + (tt & 3);
-    }();
-    float xb[NH][4][NU], Wb[NT], a1b = 0.f, a2b = 0.f;
-    auto load_pair = [&](int q) {
-      const int i1 = i10 + q / n2, i2 = i20 + (q - (q / n2) * n2);
+    // values and factor rows) are issued before pair q is computed.  Loads
+    // are unconditional or masked-after-zeroing so that no control-flow join
+    // forces an early wait on them, and the compute part issues none.
+    // VEC: a full group of rows whose start is NU-aligned (one NU-wide load
+    // per lane and slice); otherwise per-entry loads.
+    auto run_pairs = [&](auto vec_tag) {
+      constexpr bool VEC = decltype(vec_tag)::value;
+      // Prefetch buffers hold raw loaded values only: any arithmetic on them
+      // at load time would force a wait for the loads.
+      struct Buf {
+        float x[NH][4][NU], a1[NT], a2[NT], a1s, a2s;
+      };
+      Buf bA, bB;
+      auto load_pair = [&](int q, Buf& b) {
+        const int i1 = i10 + q / n2, i2 = i20 + (q - (q / n2) * n2);
+        const float* r1 = a.A1 + (size_t)i1 * R;
+        const float* r2 = a.A2 + (size_t)i2 * R;
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        Wb[t] = jt[t] < R ? a.A1[(size_t)i1 * R + jt[t]] * a.A2[(size_t)i2 * R + jt[t]] : 0.f;
-      a1b = jslot < R ? a.A1[(size_t)i1 * R + jslot] : 0.f;
-      a2b = jslot < R ? a.A2[(size_t)i2 * R + jslot] : 0.f;
-      const size_t base = ((size_t)i1 * I2 + i2) * I3;
-#pragma unroll
-      for (int ht = 0; ht < NH; ++ht)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int h = 16 * ht + 4 * g + r;
-          if (h < ns) {
-            const float* Xh = (h == 0 ? a.Xt : a.ring + (size_t)(h - 1) * a.omega) + base;
-            if (wide && vec) {
-              if constexpr (NU == 4) {
-                const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(Xh + c0 + 4 * n));
-                xb[ht][r][0] = v[0];
-                xb[ht][r][1] = v[1];
-                xb[ht][r][2] = v[2];
-                xb[ht][r][3] = v[3];
-              } else {
-                const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(Xh + c0 + 2 * n));
-                xb[ht][r][0] = v[0];
-                xb[ht][r][1] = v[1];
-              }
-            } else {
-#pragma unroll
-              for (int u = 0; u < NU; ++u) xb[ht][r][u] = vu[u] ? Xh[i3u[u]] : 0.f;
-            }
-          } else {
-#pragma unroll
-            for (int u = 0; u < NU; ++u) xb[ht][r][u] = 0.f;
-          }
+        for (int t = 0; t < NT; ++t) {
+          b.a1[t] = r1[jc[t]];
+          b.a2[t] = r2[jc[t]];
         }
-    };
-    if (npairs > 0) load_pair(0);
-
-    for (int q = 0; q < npairs; ++q) {
-      const int i1l = q / n2, i2l = q - (q / n2) * n2;
-      float W[NT], x[NH][4][NU];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) W[t] = Wb[t];
-#pragma unroll
-      for (int ht = 0; ht < NH; ++ht)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int u = 0; u < NU; ++u) x[ht][r][u] = xb[ht][r][u];
-      const float a1s = a1b, a2s = a2b;
-      if (q + 1 < npairs) load_pair(q + 1);
-
-      // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile)
-      f4 D1[NH][NU];
-#pragma unroll
-      for (int ht = 0; ht < NH; ++ht)
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          f4 acc = {0.f, 0.f, 0.f, 0.f};
-          if (u < nu) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc = mfma(A1op[ht][t], W[t] * a3r[u][t], acc);
-          }
-          D1[ht][u] = acc;
-        }
-
-      // loss and weighted derivative in place (cv = 0 marks padded slices;
-      // the objective terms of the group are summed plainly, then added to
-      // the lane's running sum with compensation)
-      if (want_loss) {
-        float part = 0.f;
+        b.a1s = r1[jsc];
+        b.a2s = r2[jsc];
+        const size_t base = ((size_t)i1 * I2 + i2) * I3;
 #pragma unroll
         for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
-          for (int u = 0; u < NU; ++u)
+          for (int r = 0; r < 4; ++r) {
+            if constexpr (VEC) {
+              f2 v = {0.f, 0.f};
+              if (hv[ht][r])
+                v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(sb[ht][r] + base + c0 + 2 * n));
+              b.x[ht][r][0] = v[0];
+              b.x[ht][r][1] = v[1];
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const float fv = LossFast<LOSS>::f(x[ht][r][u], D1[ht][u][r]);
-              part += (vu[u] && cv[ht][r] != 0.f) ? cv[ht][r] * fv : 0.f;
+              for (int u = 0; u < NU; ++u) {
+                float v = 0.f;
+                if (hv[ht][r] && vu[u]) v = sb[ht][r][base + i3u[u]];
+                b.x[ht][r][u] = v;
+              }
             }
-        lacc.add(part);
-      }
-      // y in place.  Entries past the end of a row (tail lanes) need no mask:
-      // their A3 values are zero, so every product that uses them vanishes
-      // and their mode-3 rows are never written.
-#pragma unroll
-      for (int ht = 0; ht < NH; ++ht)
-#pragma unroll
-        for (int u = 0; u < NU; ++u)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) D1[ht][u][r] = LossFast<LOSS>::y(x[ht][r][u], D1[ht][u][r]);
+          }
+      };
 
-      // temporal-weight gradient: y_t sits in register 0 of lane group 0
-      {
-        float ps[NT];
+      auto compute = [&](int q, const Buf& b) {
+        const int i1l = q / n2, i2l = q - (q / n2) * n2;
+        float W[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) ps[t] = 0.f;
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const float yt = __shfl(D1[0][u][0], n);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) ps[t] += yt * a3r[u][t];
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) gsacc[t] += W[t] * ps[t];
-      }
+        for (int t = 0; t < NT; ++t) W[t] = b.a1[t] * b.a2[t] * jm[t];
+        const float a1s = b.a1s * jsm, a2s = b.a2s * jsm;
 
-      // GEMM2: yhat[j][e] = sum_h S[h][j] Yc[h][e]
-      float Vp[NT];
+        // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile)
+        f4 D1[NH][NU];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) Vp[t] = 0.f;
+        for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        if (u >= nu) continue;
+          for (int u = 0; u < NU; ++u) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            if (VEC || u < nu) {
 #pragma unroll
-        for (int mt = 0; mt < NM; ++mt) {
-          f4 acc = {0.f, 0.f, 0.f, 0.f};
+              for (int t = 0; t < NT; ++t) acc = mfma(A1op[ht][t], W[t] * a3r[u][t], acc);
+            }
+            D1[ht][u] = acc;
+          }
+
+        // loss derivative in place, and the objective terms of the group
+        // (cv = 0 marks padded slices) summed plainly and added to the lane's
+        // running sum with compensation.  Entries past the end of a row
+        // (tail lanes) need no mask in y: their A3 values are zero, so every
+        // product that uses them vanishes and their mode-3 rows are never
+        // written.
+        if (want_loss) {
+          float part = 0.f;
 #pragma unroll
           for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc = mfma(A2op[mt][ht][t], D1[ht][u][t], acc);
+            for (int u = 0; u < NU; ++u)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int tt = 4 * mt + r;
-            g3[u][tt] += acc[r] * W[tt];
-            Vp[tt] += acc[r] * a3r[u][tt];
+              for (int r = 0; r < 4; ++r) {
+                float fv, yv;
+                LossFast<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], fv, yv);
+                part += (vu[u] && cv[ht][r] != 0.f) ? cv[ht][r] * fv : 0.f;
+                D1[ht][u][r] = yv;
+              }
+          lacc.add(part);
+        } else {
+#pragma unroll
+          for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) D1[ht][u][r] = LossFast<LOSS>::y(b.x[ht][r][u], D1[ht][u][r]);
+        }
+
+        // temporal-weight gradient: y_t sits in register 0 of lane group 0
+        {
+          float ps[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) ps[t] = 0.f;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const float yt = __shfl(D1[0][u][0], n);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ps[t] += yt * a3r[u][t];
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) gsacc[t] += W[t] * ps[t];
+        }
+
+        // GEMM2: yhat[j][e] = sum_h (c_h S[h][j]) y[h][e]
+        float Vp[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Vp[t] = 0.f;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          if (!VEC && u >= nu) continue;
+#pragma unroll
+          for (int mt = 0; mt < NM; ++mt) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+              for (int t = 0; t < 4; ++t) acc = mfma(A2op[mt][ht][t], D1[ht][u][t], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int tt = 4 * mt + r;
+              g3[u][tt] += acc[r] * W[tt];
+              Vp[tt] += acc[r] * a3r[u][tt];
+            }
           }
         }
-      }
-      const float v = row_reduce_scatter<NT>(Vp, n);
-      if ((n & ((16 / NT) - 1)) == 0) {
-        if (jslot < R) {
+        const float v = row_reduce_scatter<NT>(Vp, n);
+        if ((n & ((16 / NT) - 1)) == 0 && jslot < R) {
           g1w[wave][i1l][jslot] += v * a2s;
           g2w[wave][i2l][jslot] += v * a1s;
         }
+      };
+
+      if constexpr (VEC && NH <= 2) {
+        // Staged pipeline: the slice rows and factor rows of pair q are
+        // copied global -> LDS by the direct-to-LDS loads two pairs ahead;
+        // these are the only vector-memory operations of the loop, so the
+        // wave waits for exactly the stage it is about to read.
+        const int K = kx + 1;   // load instructions per stage
+        // per-lane parts of the source addresses for this group; entries
+        // past the end of the row copy from the row start instead (finite
+        // values whose terms are masked)
+        const size_t eoff = (size_t)(c0 + esub < I3 ? c0 + esub : c0);
+        const float* src0 = hsub == 0 ? a.Xt + eoff : a.ring + (size_t)(hsub - 1) * a.omega + eoff;
+        const float* srck = a.ring + (size_t)hsub * a.omega + eoff;
+        auto issue = [&](int q, int st) {
+          const int i1 = i10 + q / n2, i2 = i20 + (q - (q / n2) * n2);
+          const size_t row = ((size_t)i1 * I2 + i2) * I3;
+          float* stg = ring_w + st * stage_floats(NH);
+          if (hsub < ns) load_to_lds(src0 + row, stg, dma16 ? 16 : 4);
+          if (dma16) {
+#pragma unroll
+            for (int k = 1; k < 2 * NH; ++k)
+              if (k < kx && rows_per * k + hsub < ns)
+                load_to_lds(srck + ((size_t)(rows_per * k - 1) * a.omega + row), stg + 256 * k, 16);
+          } else {
+#pragma unroll
+            for (int k = 1; k < 8 * NH; ++k)
+              if (k < kx && rows_per * k + hsub < ns)
+                load_to_lds(srck + ((size_t)(rows_per * k - 1) * a.omega + row), stg + 64 * k, 4);
+          }
+          // factor rows: lanes 0-31 copy row i1 of A1, lanes 32-63 row i2 of
+          // A2; columns j >= R are never written and keep their zeros
+          if ((lane & 31) < R) {
+            const float* fsrc = lane < 32 ? a.A1 + (size_t)i1 * R + lane : a.A2 + (size_t)i2 * R + (lane - 32);
+            load_to_lds(fsrc, stg + 512 * NH, 4);
+          }
+        };
+        if (npairs > 0) issue(0, 0);
+        if (npairs > 1) issue(1, 1);
+        for (int q = 0; q < npairs; ++q) {
+          const int st = q % kStages;
+          if (q + 2 < npairs) {
+            issue(q + 2, (q + 2) % kStages);
+            wait_vmcnt(2 * K);
+          } else if (q + 1 < npairs) {
+            wait_vmcnt(K);
+          } else {
+            wait_vmcnt(0);
+          }
+          const float* stg = ring_w + st * stage_floats(NH);
+          Buf b;
+#pragma unroll
+          for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const f2 v = *reinterpret_cast<const f2*>(stg + (16 * ht + 4 * g + r) * 32 + 2 * n);
+              b.x[ht][r][0] = v[0];
+              b.x[ht][r][1] = v[1];
+            }
+          // columns t of this lane are 16 (t / 4) + 4 g + t % 4: four
+          // contiguous values per 16-column tile (zero past R)
+          const float* fa = stg + 512 * NH;
+#pragma unroll
+          for (int t4 = 0; t4 < NT / 4; ++t4) {
+            const f4 v1 = *reinterpret_cast<const f4*>(fa + 16 * t4 + 4 * g);
+            const f4 v2 = *reinterpret_cast<const f4*>(fa + 32 + 16 * t4 + 4 * g);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              b.a1[4 * t4 + r] = v1[r];
+              b.a2[4 * t4 + r] = v2[r];
+            }
+          }
+          b.a1s = fa[jslot];
+          b.a2s = fa[32 + jslot];
+          compute(q, b);
+        }
+      } else {
+        // ping-pong: the buffer being computed was filled one step earlier
+        // while the other buffer's loads are in flight
+        if (npairs > 0) load_pair(0, bA);
+        for (int q = 0; q < npairs; q += 2) {
+          if (q + 1 < npairs) load_pair(q + 1, bB);
+          compute(q, bA);
+          if (q + 1 >= npairs) break;
+          if (q + 2 < npairs) load_pair(q + 2, bA);
+          compute(q + 1, bB);
+        }
       }
+    };
+    if constexpr (NH <= 2) {
+      run_pairs(std::integral_constant<bool, true>{});
+    } else {
+      if (wide && vec)
+        run_pairs(std::integral_constant<bool, true>{});
+      else
+        run_pairs(std::integral_constant<bool, false>{});
     }
 
     // combine the waves' mode-3 rows of this 64-wide group in wave order
@@ -398,7 +619,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 
 template <int LOSS, int RT, int NH>
 __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
-  __shared__ float sm[lds_floats(RT)];
+  __shared__ float sm[lds_floats(RT, NH)];
   __shared__ float cl[kMaxNs];
   for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
@@ -450,11 +671,11 @@ hipError_t by_rank(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p
 
 bool mfma_supported(int R, int ns, int dtype) { return dtype == 0 && R >= 1 && R <= 32 && ns <= 64; }
 
-MfmaPlan mfma_plan(int I1, int I2, int I3) {
+MfmaPlan mfma_plan(int I1, int I2, int I3, int target) {
   (void)I3;
   MfmaPlan p;
   const long pairs = (long)I1 * I2;
-  const long target_blocks = 4096;
+  const long target_blocks = target > 0 ? target : kDefaultPlanTarget;
   long per = std::max(1L, (pairs + target_blocks - 1) / target_blocks);
   p.tb2 = (int)std::min<long>(std::min<long>(I2, kTB), per);
   p.tb1 = (int)std::min<long>(std::min<long>(I1, kTB), std::max(1L, per / p.tb2));
@@ -510,7 +731,7 @@ __global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* _
                                                               BatchState* __restrict__ state,
                                                               const int2* __restrict__ items, int nitems,
                                                               int* __restrict__ counter, int want) {
-  __shared__ float sm[lds_floats(32)];
+  __shared__ float sm[lds_floats(32, 2)];
   __shared__ float cl[kMaxNs];
   __shared__ int cur;
   for (;;) {

@@ -100,8 +100,20 @@ __device__ bool is_stored(const int32_t* coords, int64_t nnz, int64_t key, int I
   return lo < nnz && lin_of(coords, lo, I2, I3) == key;
 }
 
-template <int LOSS, int SEG>
-__global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
+// Draw record of the two-phase variant: the three coordinates and the
+// weighted loss derivative c_h * w * y of one draw (zero for a draw that
+// contributes nothing).
+struct DrawRec {
+  int i1, i2, i3;
+  float y;
+};
+
+// REC = false: one pass; the SEG lanes of a draw add their rank columns of
+// the three MTTKRP rows with global atomics.
+// REC = true: first phase of the two-phase variant; the draw's record is
+// written to recs[h * (p + q) + id] instead, and sampled_scatter forms G.
+template <int LOSS, int SEG, bool REC>
+__global__ void __launch_bounds__(256) sampled_kernel(SArgs a, DrawRec* __restrict__ recs) {
   const int lane = threadIdx.x & 63;
   const int64_t gwave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int h = (int)(gwave / a.waves_per_slice);
@@ -152,6 +164,7 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   const float sj = j < R ? a.S[h][j] : 0.f;
   const bool cur = h == 0;
   float gsl = 0.f;
+  float yown = 0.f;
   Kahan<float> lacc;
   const int nd = (int)min<int64_t>(64, total - first);
   for (int base = 0; base < nd; base += PER) {
@@ -168,13 +181,26 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
     LossFn<float, LOSS>::eval(bx, m, f, y);
     const float yt = ch * bw * y;
     if (src < nd && j == 0 && (a.want & kWantLoss)) lacc.add(ch * bw * f);
-    if (live && bw != 0.f && (a.want & kWantGrad)) {
+    if (REC) {
+      // hand the draw's derivative back to the lane that owns the draw
+      const float yb = __shfl(bw != 0.f ? yt : 0.f, ((lane - base) & (PER - 1)) * SEG);
+      if (lane >= base && lane < base + PER) yown = yb;
+      if (live && bw != 0.f && cur && (a.want & kWantGrad)) gsl += yt * r1 * r2 * r3;
+    } else if (live && bw != 0.f && (a.want & kWantGrad)) {
       const float ys = yt * sj;
       unsafeAtomicAdd(&a.G1[(size_t)b1 * R + j], ys * r2 * r3);
       unsafeAtomicAdd(&a.G2[(size_t)b2 * R + j], ys * r1 * r3);
       unsafeAtomicAdd(&a.G3[(size_t)b3 * R + j], ys * r1 * r2);
       if (cur) gsl += yt * r1 * r2 * r3;
     }
+  }
+  if (REC && id < total) {
+    DrawRec rc;
+    rc.i1 = i1;
+    rc.i2 = i2;
+    rc.i3 = i3;
+    rc.y = yown;
+    recs[(size_t)h * total + id] = rc;
   }
   if (cur && (a.want & kWantGrad)) {
     for (int o = SEG; o < 64; o <<= 1) gsl += __shfl_xor(gsl, o);
@@ -238,19 +264,142 @@ __global__ void sampled_check(const float* G1, const float* G2, const float* G3,
   }
 }
 
-template <int LOSS>
-hipError_t launch_seg(const SampledCall& c, const SArgs& a, int64_t blocks) {
+// Second phase of the two-phase variant.  Workgroup (chunk, k) owns rank
+// columns [chunk*RC, chunk*RC + RC) and the k-th of wpc equal runs of the
+// draw records; it accumulates its columns of all three MTTKRPs for every
+// row in LDS, then adds them to G with one atomic per touched entry.
+// kScatterThreads / RC draws are taken per pass, U passes in flight.
+constexpr int kScatterThreads = 1024;
+
+template <int RC>
+__global__ void __launch_bounds__(kScatterThreads) sampled_scatter(SArgs a, const DrawRec* __restrict__ recs,
+                                                                   int64_t ndraws, int wpc) {
+  extern __shared__ float acc[];  // (I1 + I2 + I3) x RC
+  __shared__ float sS[kMaxNs * RC];
+  constexpr int DPI = kScatterThreads / RC;
+  constexpr int U = 4;
+  const int chunk = blockIdx.x / wpc, k = blockIdx.x - chunk * wpc;
+  const int I1 = a.I1, I2 = a.I2, I3 = a.I3, R = a.R;
+  const int nrow = I1 + I2 + I3;
+  const int c0 = chunk * RC;
+  for (int i = threadIdx.x; i < nrow * RC; i += kScatterThreads) acc[i] = 0.f;
+  for (int i = threadIdx.x; i < a.ns * RC; i += kScatterThreads) {
+    const int h = i / RC, jj = i - h * RC;
+    sS[i] = c0 + jj < R ? a.S[h][c0 + jj] : 0.f;
+  }
+  __syncthreads();
+  float* acc1 = acc;
+  float* acc2 = acc + I1 * RC;
+  float* acc3 = acc + (I1 + I2) * RC;
+  const int64_t per = (ndraws + wpc - 1) / wpc;
+  const int64_t lo = (int64_t)k * per, hi = min<int64_t>(ndraws, lo + per);
+  const int64_t total = a.p + a.q;
+  const int jj = threadIdx.x % RC, sub = threadIdx.x / RC;
+  const int col = min(c0 + jj, R - 1);
+  const bool colok = c0 + jj < R;
+  for (int64_t d0 = lo; d0 < hi; d0 += (int64_t)DPI * U) {
+    DrawRec rc[U];
+    int hh[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t d = d0 + u * DPI + sub;
+      if (d < hi) {
+        rc[u] = recs[d];
+        hh[u] = (int)(d / total);
+      } else {
+        rc[u].i1 = rc[u].i2 = rc[u].i3 = 0;
+        rc[u].y = 0.f;
+        hh[u] = 0;
+      }
+    }
+    float v1[U], v2[U], v3[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v1[u] = a.A1[(size_t)rc[u].i1 * R + col];
+      v2[u] = a.A2[(size_t)rc[u].i2 * R + col];
+      v3[u] = a.A3[(size_t)rc[u].i3 * R + col];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (rc[u].y != 0.f && colok) {
+        const float ys = rc[u].y * sS[hh[u] * RC + jj];
+        atomicAdd(&acc1[rc[u].i1 * RC + jj], ys * v2[u] * v3[u]);
+        atomicAdd(&acc2[rc[u].i2 * RC + jj], ys * v1[u] * v3[u]);
+        atomicAdd(&acc3[rc[u].i3 * RC + jj], ys * v1[u] * v2[u]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nrow * RC; i += kScatterThreads) {
+    const int row = i / RC, j = c0 + (i - row * RC);
+    const float v = acc[i];
+    if (j >= R || v == 0.f) continue;
+    if (row < I1)
+      unsafeAtomicAdd(&a.G1[(size_t)row * R + j], v);
+    else if (row < I1 + I2)
+      unsafeAtomicAdd(&a.G2[(size_t)(row - I1) * R + j], v);
+    else
+      unsafeAtomicAdd(&a.G3[(size_t)(row - I1 - I2) * R + j], v);
+  }
+}
+
+// LDS available to the accumulators of sampled_scatter (the column chunk of
+// S takes the rest).
+constexpr size_t kScatterLds = 155648;
+
+// Rank columns per workgroup for the two-phase variant, 0 when even one
+// column of the three factors does not fit in LDS.
+int scatter_rc(int I1, int I2, int I3, int R) {
+  const size_t nrow = (size_t)I1 + I2 + I3;
+  int rc = 8;
+  while (rc > 1 && (rc / 2 >= R || nrow * rc * 4 > kScatterLds)) rc /= 2;
+  return nrow * rc * 4 <= kScatterLds ? rc : 0;
+}
+
+template <int LOSS, bool REC>
+hipError_t launch_seg(const SampledCall& c, const SArgs& a, int64_t blocks, DrawRec* recs) {
   if (c.R <= 16) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 16>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 16, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a, recs);
   } else if (c.R <= 32) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 32>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 32, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a, recs);
   } else {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 64>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 64, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a, recs);
   }
   return hipGetLastError();
 }
 
+template <int LOSS>
+hipError_t launch_phase1(const SampledCall& c, const SArgs& a, int64_t blocks, DrawRec* recs) {
+  return recs ? launch_seg<LOSS, true>(c, a, blocks, recs) : launch_seg<LOSS, false>(c, a, blocks, nullptr);
+}
+
+template <int RC>
+hipError_t launch_scatter(const SampledCall& c, const SArgs& a, const DrawRec* recs, int64_t ndraws) {
+  const size_t lds = ((size_t)c.I1 + c.I2 + c.I3) * RC * 4;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sampled_scatter<RC>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kScatterLds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  const int nchunk = (c.R + RC - 1) / RC;
+  // about one workgroup per compute unit, but no fewer draws per
+  // workgroup than accumulator entries it has to clear and flush
+  const int64_t rows = (int64_t)c.I1 + c.I2 + c.I3;
+  int64_t wpc = std::max<int64_t>(1, (cus + nchunk - 1) / nchunk);
+  wpc = std::max<int64_t>(1, std::min<int64_t>(wpc, ndraws / std::max<int64_t>(1, rows)));
+  hipLaunchKernelGGL((sampled_scatter<RC>), dim3((unsigned)(nchunk * wpc)), dim3(kScatterThreads), lds, c.stream,
+                     a, recs, ndraws, (int)wpc);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+size_t sampled_scratch_bytes(int I1, int I2, int I3, int R, int ns_max, int64_t p, int64_t q) {
+  if (scatter_rc(I1, I2, I3, R) == 0) return 0;
+  return (size_t)ns_max * (size_t)(p + q) * sizeof(DrawRec);
+}
 
 hipError_t sampled_run(const SampledCall& c) {
   const int n1 = c.I1 * c.R, n2 = c.I2 * c.R, n3 = c.I3 * c.R;
@@ -290,14 +439,30 @@ hipError_t sampled_run(const SampledCall& c) {
   a.key1 = (uint32_t)(c.seed >> 32);
   a.call = (uint32_t)c.call;
   const int64_t blocks = (a.waves_per_slice * c.ns + 3) / 4;
+  // two-phase variant when the record buffer was provided and the gradient
+  // is wanted; the one-pass kernel otherwise
+  const int rc = scatter_rc(c.I1, c.I2, c.I3, c.R);
+  const int64_t ndraws = (int64_t)c.ns * (c.p + c.q);
+  DrawRec* recs = nullptr;
+  if (rc > 0 && (c.want & kWantGrad) && c.rec &&
+      c.rec_bytes >= (size_t)ndraws * sizeof(DrawRec))
+    recs = static_cast<DrawRec*>(c.rec);
   if (blocks > 0) {
-    if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);
+    if (c.ev_begin) (void)hipEventRecord(c.ev_begin, c.stream);
     switch (c.loss) {
-      case kGaussian: e = launch_seg<kGaussian>(c, a, blocks); break;
-      case kPoissonLog: e = launch_seg<kPoissonLog>(c, a, blocks); break;
-      default: e = launch_seg<kBernoulliLogit>(c, a, blocks);
+      case kGaussian: e = launch_phase1<kGaussian>(c, a, blocks, recs); break;
+      case kPoissonLog: e = launch_phase1<kPoissonLog>(c, a, blocks, recs); break;
+      default: e = launch_phase1<kBernoulliLogit>(c, a, blocks, recs);
     }
-    if (c.ev_end) hipEventRecord(c.ev_end, c.stream);
+    if (e == hipSuccess && recs) {
+      switch (rc) {
+        case 8: e = launch_scatter<8>(c, a, recs, ndraws); break;
+        case 4: e = launch_scatter<4>(c, a, recs, ndraws); break;
+        case 2: e = launch_scatter<2>(c, a, recs, ndraws); break;
+        default: e = launch_scatter<1>(c, a, recs, ndraws);
+      }
+    }
+    if (c.ev_end) (void)hipEventRecord(c.ev_end, c.stream);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(sampled_check, dim3(std::min(64, (n1 + n2 + n3 + c.R + 256) / 256)), dim3(256), 0, c.stream,

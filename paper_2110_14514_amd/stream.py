@@ -177,6 +177,15 @@ class Stream:
         N.check(self.lib.gcp_kernel_time(self.handle, byref(ms), byref(n)), "gcp_kernel_time")
         return ms.value, n.value
 
+    def autotune(self, X_t: torch.Tensor, cache_path: Optional[str] = None) -> int:
+        """Times the candidate work plans and keeps the fastest (synchronous)."""
+        sl = _slice(X_t)
+        chosen = c_int32(0)
+        N.check(self.lib.gcp_autotune(self.handle, byref(sl),
+                                      cache_path.encode() if cache_path else None, byref(chosen)),
+                "gcp_autotune")
+        return chosen.value
+
     def sync(self) -> int:
         return int(self.lib.gcp_stream_sync(self.handle))
 

@@ -61,7 +61,10 @@ def _run_steps(use_batch, graph, nsteps=4):
     import torch
     from paper_2110_14514_amd import Batch
     probs = _problems()
-    devs, streams = _make(probs, alpha_f=1e-2, tau_f=2, seed=7)
+    side = torch.cuda.Stream()       # graph capture needs a non-default stream
+    with torch.cuda.stream(side):
+        devs, streams = _make(probs, alpha_f=1e-2, tau_f=2, seed=7)
+    torch.cuda.synchronize()
     g = np.random.default_rng(3)
     data = [[(g.normal(size=p.dims).astype(np.float32) if p.loss == "gaussian" else
               g.poisson(1.0, size=p.dims).astype(np.float32) if p.loss == "poisson_log" else
@@ -85,18 +88,21 @@ def _run_steps(use_batch, graph, nsteps=4):
                     cg = torch.cuda.CUDAGraph()
                     with torch.cuda.graph(cg, stream=cs):
                         b.update_factors()
-                cg.replay()
+                with torch.cuda.stream(cs):
+                    cg.replay()
                 torch.cuda.synchronize()
             else:
-                b.update_factors()
+                with torch.cuda.stream(cs):
+                    b.update_factors()
         torch.cuda.synchronize()
         assert b.sync_streams() == 0
     else:
         for t in range(nsteps):
-            for i, st in enumerate(streams):
-                Xb[i].copy_(torch.from_numpy(data[t][i][0]))
-                Sb[i].copy_(torch.from_numpy(data[t][i][1]))
-                st.update_factors(Xb[i], Sb[i])
+            with torch.cuda.stream(cs):
+                for i, st in enumerate(streams):
+                    Xb[i].copy_(torch.from_numpy(data[t][i][0]))
+                    Sb[i].copy_(torch.from_numpy(data[t][i][1]))
+                    st.update_factors(Xb[i], Sb[i])
         torch.cuda.synchronize()
     return [[a.cpu().numpy() for a in st.factors()] for st in streams], [st.info() for st in streams]
 

@@ -204,3 +204,46 @@ def test_stream_steps_match_oracle():
     for k in range(3):
         assert rel_err(A_gpu[k], orc.A[k]) <= 1e-4
         assert rel_err(A_gpu[k] - A0f[k], orc.A[k] - A0f[k]) <= 1e-2
+
+
+def _tune_key(st, prob, ns):
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    loss_id = {"gaussian": 0, "poisson_log": 1, "bernoulli_logit": 2}[prob.loss]
+    d = prob.dims
+    return f"{arch} {d[0]} {d[1]} {d[2]} R{prob.rank} H{len(prob.X_hist)} ns{ns} loss{loss_id}"
+
+
+@pytest.mark.parametrize("target", [1024, 2048, 4096, 8192, 16384])
+def test_every_autotune_candidate_matches_oracle(target, tmp_path):
+    """Each candidate work plan (forced through the cache) gives the oracle's
+    result: the plan changes only the summation order."""
+    import torch
+    _print_case("plan", target)
+    prob = gi.random_dense((37, 45, 70), 16, 3, "poisson_log", seed=31, lam=0.1, mu=0.1)
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{_tune_key(st, prob, 4)} = {target}\n")
+    assert st.autotune(dev["X_t"], str(cache)) == target
+    loss, G, g_s = st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+    torch.cuda.synchronize()
+    got = (float(loss.item()), [g.double().cpu().numpy() for g in G], g_s.double().cpu().numpy())
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_autotune_writes_and_reuses_cache(tmp_path):
+    import torch
+    _print_case("autotune cache")
+    prob = gi.random_dense((64, 64, 64), 16, 5, "gaussian", seed=32)
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    cache = tmp_path / "tune.txt"
+    chosen = st.autotune(dev["X_t"], str(cache))
+    assert chosen in (1024, 2048, 4096, 8192, 16384)
+    text = cache.read_text()
+    assert _tune_key(st, prob, 6) in text and text.strip().endswith(str(chosen))
+    st2 = make_stream(prob, dev)
+    assert st2.autotune(dev["X_t"], str(cache)) == chosen
+    assert cache.read_text() == text      # a hit appends nothing
