@@ -111,7 +111,10 @@ typedef struct {
   double beta1, beta2, adam_eps;
   int32_t tau_f;          /* factor iterations per gcp_update_factors      */
   int32_t reserved0;
-  int64_t max_nnz;        /* COO: largest nnz of any slice                 */
+  int64_t max_nnz;        /* COO: largest nnz of any slice (X_t included);
+                           * sizes the window slots and the per-slice
+                           * membership tables (2 max_nnz keys of 8 B,
+                           * rounded up to a power of 2)                  */
   int64_t p, q;           /* COO: nonzero / zero samples per gradient      */
   uint64_t seed;          /* reservoir draws and the sampler               */
 } gcp_params;
@@ -266,6 +269,19 @@ gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want);
  * gradient, batched ADAM step], then A_old <- A and the reservoir window
  * update with the draw made on the device, then t <- t+1. */
 gcp_status gcp_batch_update_factors(gcp_batch* b);
+
+/* Least-squares temporal weights (as gcp_solve_st) for every Gaussian-loss
+ * stream of the batch, from its registered X_t and current factors, written
+ * into its registered s_t buffer (which is then an input/output buffer).
+ * Streams with other losses keep the s_t their caller wrote (the paper's
+ * gradient-based temporal solver is not part of this library).  One pair of
+ * launches per Gaussian stream on the batch's HIP stream; capturable.  A
+ * failed Cholesky pivot is reported by gcp_batch_sync_streams. */
+gcp_status gcp_batch_solve_st(gcp_batch* b);
+
+/* One time step of Alg. 1 for every stream: gcp_batch_solve_st, then
+ * gcp_batch_update_factors. */
+gcp_status gcp_batch_step(gcp_batch* b);
 
 /* Copies the device-side step state back into the stream handles (waits). */
 gcp_status gcp_batch_sync_streams(gcp_batch* b);

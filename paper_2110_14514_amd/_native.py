@@ -80,6 +80,8 @@ SIGNATURES = {
                                    c_size_t, c_void_p, POINTER(c_void_p)]),
     "gcp_batch_loss_grad": (c_int32, [c_void_p, c_uint32]),
     "gcp_batch_update_factors": (c_int32, [c_void_p]),
+    "gcp_batch_solve_st": (c_int32, [c_void_p]),
+    "gcp_batch_step": (c_int32, [c_void_p]),
     "gcp_batch_sync_streams": (c_int32, [c_void_p]),
     "gcp_batch_destroy": (c_int32, [c_void_p]),
     "gcp_kernel_timing": (c_int32, [c_void_p, c_int32, c_int32]),

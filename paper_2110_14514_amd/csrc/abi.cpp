@@ -19,11 +19,12 @@
 using namespace gcp;
 
 struct WsLayout {
-  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, rec, total;
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, total;
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
   size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
-  size_t plain_bytes, part_bytes, rec_bytes;
+  size_t plain_bytes, part_bytes;
+  uint64_t tab_cap;       // COO: capacity of each membership table (0: dense)
 };
 
 struct gcp_stream {
@@ -110,8 +111,9 @@ WsLayout layout_for(const gcp_params* p) {
   L.ls = off; off = align_up(off + (coo ? 0 : ls_scratch_bytes(I1, I2, I3, R)), 256);
   L.plain_bytes = (p->flags & GCP_FLAG_PLAIN_SCRATCH) ? dense_plain_scratch_bytes(I1, I2, I3, R, p->dtype) : 0;
   L.plain = off; off = align_up(off + L.plain_bytes, 256);
-  L.rec_bytes = coo ? sampled_scratch_bytes(I1, I2, I3, R, p->window + 1, p->p, p->q) : 0;
-  L.rec = off; off = align_up(off + L.rec_bytes, 256);
+  // COO: one membership table per window slot and one for the current slice
+  L.tab_cap = coo ? table_capacity(p->max_nnz) : 0;
+  L.tab = off; off = align_up(off + (size_t)(coo ? p->window + 1 : 0) * L.tab_cap * 8, 256);
   L.total = off;
   return L;
 }
@@ -127,7 +129,7 @@ gcp_status check_dense_slice(const gcp_stream* s, const gcp_slice* X) {
 
 gcp_status check_coo_slice(const gcp_stream* s, const gcp_slice* X) {
   if (!X || X->kind != GCP_SLICE_COO || s->p.slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
-  if (X->nnz < 0 || X->nnz >= ((int64_t)1 << 32)) return GCP_E_SHAPE;
+  if (X->nnz < 0 || X->nnz > s->p.max_nnz) return GCP_E_SHAPE;   // tables hold max_nnz entries
   if (X->nnz > 0 && (!X->vals || !X->coords)) return GCP_E_ARG;
   if (s->p.p > 0 && X->nnz == 0) return GCP_E_ARG;               // no nonzero to draw
   if (s->p.q > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;  // no zero to draw
@@ -140,6 +142,11 @@ char* coo_slot_vals(gcp_stream* s, int slot) {
   return coo_slot_coords(s, slot) + (size_t)s->p.max_nnz * 12;
 }
 
+// Membership table of window slot `slot`; slot == window: the current slice's.
+uint64_t* coo_table(gcp_stream* s, int slot) {
+  return reinterpret_cast<uint64_t*>(s->ws + s->L.tab + (size_t)slot * s->L.tab_cap * 8);
+}
+
 hipError_t store_coo_slot(gcp_stream* s, int slot, const gcp_slice* X) {
   hipError_t e = hipSuccess;
   if (X->nnz > 0) {
@@ -147,8 +154,16 @@ hipError_t store_coo_slot(gcp_stream* s, int slot, const gcp_slice* X) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(coo_slot_vals(s, slot), X->vals, (size_t)X->nnz * 4, hipMemcpyDeviceToDevice, s->st);
   }
+  if (e == hipSuccess)
+    e = table_build(reinterpret_cast<const int32_t*>(coo_slot_coords(s, slot)), X->nnz, s->dims[1], s->dims[2],
+                    coo_table(s, slot), s->L.tab_cap, s->st);
   s->slot_nnz[slot] = X->nnz;
   return e;
+}
+
+// Table of the current slice X_t, rebuilt for every call that samples it.
+hipError_t build_current_table(gcp_stream* s, const gcp_slice* X_t) {
+  return table_build(X_t->coords, X_t->nnz, s->dims[1], s->dims[2], coo_table(s, s->p.window), s->L.tab_cap, s->st);
 }
 
 SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, int want,
@@ -158,10 +173,13 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.I1 = s->dims[0]; c.I2 = s->dims[1]; c.I3 = s->dims[2]; c.R = s->p.rank;
   c.loss = s->p.loss; c.want = want;
   c.coords[0] = X_t->coords; c.vals[0] = X_t->vals; c.nnz[0] = X_t->nnz; c.stamp[0] = s->t;
+  c.tab[0] = coo_table(s, s->p.window);
+  c.tab_cap = s->L.tab_cap;
   c.S[0] = s_t; c.c[0] = 1.0;
   int n = 1;
   for (int slot = 0; slot < s->nwin; ++slot, ++n) {
     c.coords[n] = reinterpret_cast<const int32_t*>(coo_slot_coords(s, slot));
+    c.tab[n] = coo_table(s, slot);
     c.vals[n] = coo_slot_vals(s, slot);
     c.nnz[n] = s->slot_nnz[slot];
     c.stamp[n] = s->slot_t[slot];
@@ -178,8 +196,6 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.p = s->p.p; c.q = s->p.q; c.seed = s->p.seed;
   c.call = s->sample_call++;
   c.status = s->status; c.stream = s->st;
-  c.rec = s->L.rec_bytes ? s->ws + s->L.rec : nullptr;
-  c.rec_bytes = s->L.rec_bytes;
   return c;
 }
 
@@ -346,6 +362,8 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
     if ((want & GCP_IMPL_PLAIN) || grad_scale) return GCP_E_UNSUPPORTED;
     void* Gs[3];
     for (int k = 0; k < 3; ++k) Gs[k] = (want & GCP_WANT_GRAD) ? G[k] : fac_ptr(s, s->L.G, k);
+    hipError_t eb = build_current_table(s, X_t);
+    if (eb != hipSuccess) return hip_status(eb);
     SampledCall c = sampled_call(s, X_t, A, s_t, want & (GCP_WANT_LOSS | GCP_WANT_GRAD),
                                  (want & GCP_WANT_LOSS) ? loss : s->ws + s->L.loss, Gs,
                                  (want & GCP_WANT_GRAD) ? g_s : s->ws + s->L.gs);
@@ -403,9 +421,8 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
   const bool coo = s->p.slice_kind == GCP_SLICE_COO;
   gcp_status st = coo ? check_coo_slice(s, X_t) : check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
-  if (coo && X_t->nnz > s->p.max_nnz && s->p.window > 0) return GCP_E_SHAPE;
   const gcp_params& p = s->p;
-  hipError_t e = hipSuccess;
+  hipError_t e = coo ? build_current_table(s, X_t) : hipSuccess;
   for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
     if (coo) {
       const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
@@ -652,6 +669,7 @@ extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const ch
 // --------------------------------------------------------------- batching
 struct gcp_batch {
   std::vector<gcp_stream*> streams;
+  std::vector<gcp_batch_io> io;   // registered buffers, per stream
   hipStream_t st;
   char* ws;
   BatchRun run_out;     // reduce writes the registered outputs
@@ -812,13 +830,24 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
     const double cost = (double)s->omega * (s->p.window + 1) * (R > 16 ? 2.0 : 1.0) / m.nwg;
     order.push_back({cost, i});
   }
-  // work list: most expensive items first, so the tail is made of short items
-  std::sort(order.begin(), order.end(), [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+  // work list grouped by tile variant (one persistent launch each); inside a
+  // variant the most expensive streams come first, so each launch ends with
+  // short items
+  std::vector<int> var(n);
+  for (int i = 0; i < n; ++i) var[i] = batch_variant(streams[i]->p.loss, streams[i]->p.rank, streams[i]->p.window);
+  std::sort(order.begin(), order.end(), [&](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+    if (var[x.second] != var[y.second]) return var[x.second] < var[y.second];
     return x.first > y.first;
   });
   std::vector<int2> items;
-  for (auto& pr : order)
+  int vbegin[kBatchVariants], vend[kBatchVariants];
+  for (int v = 0; v < kBatchVariants; ++v) vbegin[v] = vend[v] = 0;
+  for (auto& pr : order) {
+    const int v = var[pr.second];
+    if (vend[v] == vbegin[v]) vbegin[v] = vend[v] = (int)items.size();
     for (int w = 0; w < L.plans[pr.second].nwg; ++w) items.push_back(make_int2(pr.second, w));
+    vend[v] = (int)items.size();
+  }
   hipError_t e = hipMemcpy(ws + L.desc_out, dout.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ws + L.desc_step, dstep.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ws + L.state, state.data(), n * sizeof(BatchState), hipMemcpyHostToDevice);
@@ -833,6 +862,7 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   gcp_batch* b = new (std::nothrow) gcp_batch();
   if (!b) return GCP_E_ARG;
   b->streams.assign(streams, streams + n);
+  b->io.assign(io, io + n);
   b->st = hip_stream;
   b->ws = ws;
   b->status = reinterpret_cast<int*>(ws + L.counter) + 16;
@@ -850,7 +880,13 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   r.nfac = nfac;
   r.cpystart = reinterpret_cast<const int64_t*>(ws + L.cpystart);
   r.ncpy = ncpy;
-  r.grid = std::max(1, std::min(2 * cus, r.nitems));
+  for (int v = 0; v < kBatchVariants; ++v) {
+    r.vbegin[v] = vbegin[v];
+    r.vend[v] = vend[v];
+    // the rank-16 single-tile variant fits two workgroups per compute unit
+    const int per_cu = batch_variant_r16(v) ? 2 : 1;
+    r.vgrid[v] = std::max(1, std::min(per_cu * cus, vend[v] - vbegin[v]));
+  }
   r.status = b->status;
   r.stream = hip_stream;
   b->run_out = r;
@@ -876,6 +912,25 @@ gcp_status gcp_batch_update_factors(gcp_batch* b) {
   }
   if (e == hipSuccess) e = batch_window_run(b->run_step);
   return hip_status(e);
+}
+
+gcp_status gcp_batch_solve_st(gcp_batch* b) {
+  if (!b) return GCP_E_ARG;
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < b->streams.size() && e == hipSuccess; ++i) {
+    gcp_stream* s = b->streams[i];
+    if (s->p.loss != GCP_LOSS_GAUSSIAN) continue;
+    const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+    e = ls_solve_run(s->dims[0], s->dims[1], s->dims[2], s->p.rank, s->p.dtype, b->io[i].X_t, A, s->p.mu,
+                     s->p.lower, const_cast<void*>(b->io[i].s_t), s->ws + s->L.ls, b->status, b->st);
+  }
+  return hip_status(e);
+}
+
+gcp_status gcp_batch_step(gcp_batch* b) {
+  gcp_status st = gcp_batch_solve_st(b);
+  if (st != GCP_OK) return st;
+  return gcp_batch_update_factors(b);
 }
 
 gcp_status gcp_batch_sync_streams(gcp_batch* b) {

@@ -191,12 +191,18 @@ struct BatchState {                // per stream, advanced on the device
   int pending_slot;
   int64_t slot_t[kMaxNs];
 };
+// Variants of the batched tile code: loss x (rank tile 16/32) x (one/two
+// h-tiles), index loss * 4 + (R > 16) * 2 + (window + 1 > 16).
+constexpr int kBatchVariants = 12;
+
 struct BatchRun {
   const BatchDesc* desc;
   BatchState* state;
-  const int2* items;
+  const int2* items;        // work list grouped by variant
   int nitems;
-  int* counter;
+  int vbegin[kBatchVariants], vend[kBatchVariants];  // each variant's items
+  int vgrid[kBatchVariants];                         // persistent workgroups per variant
+  int* counter;             // kBatchVariants work counters
   int nstreams;
   const int64_t* outstart;
   int64_t nout;
@@ -204,11 +210,12 @@ struct BatchRun {
   int64_t nfac;
   const int64_t* cpystart;
   int64_t ncpy;
-  int grid;
   int* status;
   hipStream_t stream;
 };
 int batch_variant(int loss, int R, int H);
+// Whether variant v runs two workgroups per compute unit.
+bool batch_variant_r16(int v);
 hipError_t batch_grad_run(const BatchRun& b, int want);
 hipError_t batch_adam_run(const BatchRun& b);
 hipError_t batch_window_run(const BatchRun& b);
@@ -218,6 +225,8 @@ struct SampledCall {
   int I1, I2, I3, R, ns, loss, want;
   const int32_t* coords[kMaxNs];  // nnz x 3, sorted by row-major linear index
   const void* vals[kMaxNs];
+  const uint64_t* tab[kMaxNs];    // membership table of slice h (table_build)
+  uint64_t tab_cap;               // capacity of every table
   int64_t nnz[kMaxNs];
   int64_t stamp[kMaxNs];          // time stamp of slice h (sampler counter word)
   const void* S[kMaxNs];
@@ -231,14 +240,14 @@ struct SampledCall {
   uint64_t seed;
   int64_t call;                   // sampler call number
   int* status;
-  void* rec;                      // draw records of the two-phase variant (or null)
-  size_t rec_bytes;
   hipStream_t stream;
   hipEvent_t ev_begin, ev_end;
 };
-// Bytes of draw records for up to ns_max slices, 0 when the two-phase
-// variant does not apply to these sizes.
-size_t sampled_scratch_bytes(int I1, int I2, int I3, int R, int ns_max, int64_t p, int64_t q);
+// Membership table of a COO slice: capacity for up to max_nnz entries, and
+// the build (fill + insert, two launches on `stream`).
+uint64_t table_capacity(int64_t max_nnz);
+hipError_t table_build(const int32_t* coords, int64_t nnz, int I2, int I3, uint64_t* tab, uint64_t cap,
+                       hipStream_t stream);
 hipError_t sampled_run(const SampledCall& c);
 
 // Unfused baseline: model, elementwise, per-mode MTTKRP kernels.

@@ -80,7 +80,7 @@ __host__ __device__ constexpr int ring_floats(int NH) { return NH <= 2 ? kWaves 
 
 // LDS floats used by one workgroup at rank tile RT and NH h-tiles
 __host__ __device__ constexpr int lds_floats(int RT, int NH) {
-  return 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT + kWaves + ring_floats(NH);
+  return 64 * (RT + 1) + kWaves * RT + kWaves;
 }
 
 // Wait until at most n vector-memory operations of this wave are in flight
@@ -183,21 +183,74 @@ __device__ __forceinline__ float row_reduce_scatter(float (&v)[NT], int n) {
   return r;
 }
 
+// Lane exchanges inside a 16-lane row on the VALU (DPP), no LDS round trip:
+// xor 8 is a rotation of the row by 8; xor 4 is the half-row mirror (lane
+// i <- 7 - i in each 8-lane half, i.e. xor 7) followed by the quad
+// permutation [3,2,1,0] (xor 3); xor 2 and xor 1 are quad permutations.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float row_xor8(float v) { return dpp<0x128>(v); }
+__device__ __forceinline__ float row_xor4(float v) { return dpp<0x1B>(dpp<0x141>(v)); }
+__device__ __forceinline__ float row_xor2(float v) { return dpp<0x4E>(v); }
+__device__ __forceinline__ float row_xor1(float v) { return dpp<0xB1>(v); }
+
+template <int M>
+__device__ __forceinline__ float row_xor(float v) {
+  if constexpr (M == 8) return row_xor8(v);
+  else if constexpr (M == 4) return row_xor4(v);
+  else if constexpr (M == 2) return row_xor2(v);
+  else return row_xor1(v);
+}
+
+// One reduce-scatter step over lane bit M: the lane keeps the upper half of
+// its H values when the bit is set, and adds the partner's copy of that half.
+template <int M, int H, int NT>
+__device__ __forceinline__ void rs_step(float (&v)[NT], int n) {
+  const bool hi = (n & M) != 0;
+#pragma unroll
+  for (int i = 0; i < H / 2; ++i) {
+    const float lo_v = v[i], hi_v = v[i + H / 2];
+    v[i] = pick(hi, hi_v, lo_v) + row_xor<M>(pick(hi, lo_v, hi_v));
+  }
+}
+
+// Same result and lane mapping as row_reduce_scatter, with DPP exchanges.
+template <int NT>
+__device__ __forceinline__ float row_reduce_scatter_dpp(float (&v)[NT], int n) {
+  static_assert(NT == 4 || NT == 8, "rank tile of 16 or 32");
+  rs_step<8, NT>(v, n);
+  rs_step<4, NT / 2>(v, n);
+  if constexpr (NT == 8) {
+    rs_step<2, 2>(v, n);
+    return v[0] + row_xor1(v[0]);
+  } else {
+    float r = v[0] + row_xor2(v[0]);
+    return r + row_xor1(r);
+  }
+}
+
 // One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
 // slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
 template <int LOSS, int RT, int NH>
-__device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* sm, const float* cl) {
+__device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
+                                          float* ring, const float* cl) {
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
   constexpr int NU = 2;                 // 16-entry tiles per group (register budget)
   constexpr int SW = 16 * NU;           // entries per full group
 
-  float(*g1w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(sm);
-  float(*g2w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(sm + kWaves * kTB * RT);
-  float(*g3x)[RT + 1] = reinterpret_cast<float(*)[RT + 1]>(sm + 2 * kWaves * kTB * RT);  // SW rows used
-  float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + 2 * kWaves * kTB * RT + 64 * (RT + 1));
-  float* lsx = sm + 2 * kWaves * kTB * RT + 64 * (RT + 1) + kWaves * RT;
+  // G1/G2 rows of each wave's block and the staging ring are LDS arrays of
+  // their own (declared by the kernel): reads of the row accumulators then
+  // cannot alias the in-flight direct-to-LDS copies, so the compiler adds no
+  // wait for those copies inside the pair loop
+  float(*g1w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g1s);
+  float(*g2w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g2s);
+  float(*g3x)[RT + 1] = reinterpret_cast<float(*)[RT + 1]>(sm);  // SW rows used
+  float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + 64 * (RT + 1));
+  float* lsx = sm + 64 * (RT + 1) + kWaves * RT;
 
   const int tid = threadIdx.x;
   // the wave index is uniform across the wave: keeping it scalar keeps all
@@ -205,7 +258,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = lane & 15, g = lane >> 4;
   // this wave's staging ring (NH <= 2)
-  float* ring_w = lsx + kWaves + wave * kStages * stage_floats(NH);
+  float* ring_w = ring + wave * kStages * stage_floats(NH);
   const int R = a.R, ns = a.ns, I1 = a.I1, I2 = a.I2, I3 = a.I3;
   const int blk = wgi * kWaves + wave;
   const bool active = blk < a.nblocks;
@@ -372,8 +425,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         const int i1l = q / n2, i2l = q - (q / n2) * n2;
         float W[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) W[t] = b.a1[t] * b.a2[t] * jm[t];
-        const float a1s = b.a1s * jsm, a2s = b.a2s * jsm;
+        // staged factor rows are zero past R; the register-prefetch path
+        // reads clamped columns and masks them here
+        for (int t = 0; t < NT; ++t) W[t] = NH <= 2 ? b.a1[t] * b.a2[t] : b.a1[t] * b.a2[t] * jm[t];
+        const float a1s = NH <= 2 ? b.a1s : b.a1s * jsm, a2s = NH <= 2 ? b.a2s : b.a2s * jsm;
 
         // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile)
         f4 D1[NH][NU];
@@ -455,10 +510,13 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             }
           }
         }
-        const float v = row_reduce_scatter<NT>(Vp, n);
+        const float v = row_reduce_scatter_dpp<NT>(Vp, n);
+        // the rows belong to this wave alone and its LDS adds complete in
+        // program order, so the sums are deterministic; the adds return
+        // nothing, so the wave does not wait for them
         if ((n & ((16 / NT) - 1)) == 0 && jslot < R) {
-          g1w[wave][i1l][jslot] += v * a2s;
-          g2w[wave][i2l][jslot] += v * a1s;
+          atomicAdd(&g1w[wave][i1l][jslot], v * a2s);
+          atomicAdd(&g2w[wave][i2l][jslot], v * a1s);
         }
       };
 
@@ -618,12 +676,31 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 }
 
 template <int LOSS, int RT, int NH>
-__global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
+__device__ __forceinline__ void fused_body(const MArgs& a) {
+  __shared__ float g1s[kWaves * kTB * RT];
+  __shared__ float g2s[kWaves * kTB * RT];
   __shared__ float sm[lds_floats(RT, NH)];
+  // the staging ring is an LDS object of its own: the direct-to-LDS copies
+  // write only this array
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
   __shared__ float cl[kMaxNs];
   for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH>(a.t, blockIdx.x, sm, cl);
+  mfma_tile<LOSS, RT, NH>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl);
+}
+
+template <int LOSS, int RT, int NH>
+__global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
+  fused_body<LOSS, RT, NH>(a);
+}
+
+// Rank tile 16 with one h-tile: the LDS of two workgroups fits a compute
+// unit, so the register budget is held to 128 (four waves per SIMD); the
+// few values that do not fit are spilled outside the pair loop.
+template <int LOSS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+fused_dense_mfma_r16(MArgs a) {
+  fused_body<LOSS, 16, 1>(a);
 }
 
 template <int LOSS, int RT, int NH>
@@ -647,7 +724,10 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.lossp = lossp;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
-  hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+  if constexpr (RT == 16 && NH == 1)
+    hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+  else
+    hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
   return hipGetLastError();
 }
 
@@ -718,28 +798,25 @@ __device__ __forceinline__ uint64_t splitmix64_dev(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ int variant_of(int loss, int R, int H) {
-  return loss * 4 + (R > 16 ? 2 : 0) + (H + 1 > 16 ? 1 : 0);
-}
-
+// One variant's share of the work list: items [begin, end), taken in order
+// from the variant's own counter.
 template <int LOSS, int RT, int NH>
-__device__ __forceinline__ void run_variant(const TileArgs& ta, int wg, float* sm, const float* cl) {
-  mfma_tile<LOSS, RT, NH>(ta, wg, sm, cl);
-}
-
-__global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
-                                                              BatchState* __restrict__ state,
-                                                              const int2* __restrict__ items, int nitems,
-                                                              int* __restrict__ counter, int want) {
-  __shared__ float sm[lds_floats(32, 2)];
+__device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ desc,
+                                                const BatchState* __restrict__ state,
+                                                const int2* __restrict__ items, int begin, int end,
+                                                int* __restrict__ counter, int want) {
+  __shared__ float g1s[kWaves * kTB * RT];
+  __shared__ float g2s[kWaves * kTB * RT];
+  __shared__ float sm[lds_floats(RT, NH)];
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
   __shared__ float cl[kMaxNs];
   __shared__ int cur;
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) cur = begin + atomicAdd(counter, 1);
     __syncthreads();
     const int it = cur;
     __syncthreads();
-    if (it >= nitems) break;
+    if (it >= end) break;
     const int si = items[it].x, wg = items[it].y;
     const BatchDesc& d = desc[si];
     const BatchState& s = state[si];
@@ -768,22 +845,25 @@ __global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* _
       cl[h] = v;
     }
     __syncthreads();
-    switch (d.variant) {
-      case 0: run_variant<kGaussian, 16, 1>(ta, wg, sm, cl); break;
-      case 1: run_variant<kGaussian, 16, 2>(ta, wg, sm, cl); break;
-      case 2: run_variant<kGaussian, 32, 1>(ta, wg, sm, cl); break;
-      case 3: run_variant<kGaussian, 32, 2>(ta, wg, sm, cl); break;
-      case 4: run_variant<kPoissonLog, 16, 1>(ta, wg, sm, cl); break;
-      case 5: run_variant<kPoissonLog, 16, 2>(ta, wg, sm, cl); break;
-      case 6: run_variant<kPoissonLog, 32, 1>(ta, wg, sm, cl); break;
-      case 7: run_variant<kPoissonLog, 32, 2>(ta, wg, sm, cl); break;
-      case 8: run_variant<kBernoulliLogit, 16, 1>(ta, wg, sm, cl); break;
-      case 9: run_variant<kBernoulliLogit, 16, 2>(ta, wg, sm, cl); break;
-      case 10: run_variant<kBernoulliLogit, 32, 1>(ta, wg, sm, cl); break;
-      default: run_variant<kBernoulliLogit, 32, 2>(ta, wg, sm, cl); break;
-    }
+    mfma_tile<LOSS, RT, NH>(ta, wg, g1s, g2s, sm, ring, cl);
     __syncthreads();
   }
+}
+
+template <int LOSS, int RT, int NH>
+__global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
+                                                              const BatchState* __restrict__ state,
+                                                              const int2* __restrict__ items, int begin, int end,
+                                                              int* __restrict__ counter, int want) {
+  batch_grad_body<LOSS, RT, NH>(desc, state, items, begin, end, counter, want);
+}
+
+// Rank tile 16, one h-tile: four waves per SIMD, as fused_dense_mfma_r16.
+template <int LOSS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+batch_grad_kernel_r16(const BatchDesc* __restrict__ desc, const BatchState* __restrict__ state,
+                      const int2* __restrict__ items, int begin, int end, int* __restrict__ counter, int want) {
+  batch_grad_body<LOSS, 16, 1>(desc, state, items, begin, end, counter, want);
 }
 
 __device__ __forceinline__ float wave_sum_fixed_f(float v) {
@@ -846,7 +926,7 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchDesc* __re
       if (!isfinite(out)) atomicOr(status, (int)kStatusNonFinite);
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kBatchVariants) counter[threadIdx.x] = 0;
 }
 
 // Adam Step (Algorithm 2) over the factor entries of every stream; the
@@ -935,11 +1015,46 @@ __global__ void __launch_bounds__(256) batch_window_copy(const BatchDesc* __rest
 
 int batch_variant(int loss, int R, int H) { return loss * 4 + (R > 16 ? 2 : 0) + (H + 1 > 16 ? 1 : 0); }
 
+namespace {
+
+template <int LOSS, int RT, int NH>
+void launch_batch_variant(const BatchRun& b, int v, int want) {
+  const dim3 grid((unsigned)b.vgrid[v]);
+  if constexpr (RT == 16 && NH == 1)
+    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state, b.items,
+                       b.vbegin[v], b.vend[v], b.counter + v, want);
+  else
+    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+                       b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
+}
+
+template <int LOSS>
+void launch_batch_loss(const BatchRun& b, int v, int want) {
+  switch (v & 3) {
+    case 0: launch_batch_variant<LOSS, 16, 1>(b, v, want); break;
+    case 1: launch_batch_variant<LOSS, 16, 2>(b, v, want); break;
+    case 2: launch_batch_variant<LOSS, 32, 1>(b, v, want); break;
+    default: launch_batch_variant<LOSS, 32, 2>(b, v, want); break;
+  }
+}
+
+}  // namespace
+
+bool batch_variant_r16(int v) { return (v & 3) == 0; }
+
 hipError_t batch_grad_run(const BatchRun& b, int want) {
-  hipLaunchKernelGGL(batch_grad_kernel, dim3(b.grid), dim3(kThreads), 0, b.stream, b.desc, b.state, b.items,
-                     b.nitems, b.counter, want);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  // one persistent launch per variant present, each over its own slice of
+  // the work list
+  for (int v = 0; v < kBatchVariants; ++v) {
+    if (b.vend[v] <= b.vbegin[v]) continue;
+    switch (v >> 2) {
+      case 0: launch_batch_loss<kGaussian>(b, v, want); break;
+      case 1: launch_batch_loss<kPoissonLog>(b, v, want); break;
+      default: launch_batch_loss<kBernoulliLogit>(b, v, want); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int rblocks = (int)std::min<int64_t>(4096, (b.nout + 3) / 4);
   hipLaunchKernelGGL(batch_reduce_kernel, dim3(std::max(1, rblocks)), dim3(256), 0, b.stream, b.desc, b.nstreams,
                      b.outstart, b.nout, b.counter, want, b.status);

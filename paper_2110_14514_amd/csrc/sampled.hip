@@ -13,21 +13,29 @@
 // counter = (draw number, slice time stamp, call number, stratum + 2*attempt);
 // word k of the output is scaled to [0, n) as floor(word * n / 2^32).
 //
+// Membership of a zero draw is tested in an open-addressing hash table of the
+// slice's stored linear indices (capacity a power of two >= 2 nnz, linear
+// probing), built when the slice is stored (window slots) or per call (the
+// current slice): about one cache line per test, where a binary search over
+// the sorted list would fetch a line for most of its log2(nnz) levels.
+//
 // Work decomposition: a wave takes 64 consecutive draws of one slice.
-// Phase 1, one lane per draw: generate the coordinates (zero draws test
-// membership by binary search over the slice's sorted COO list).  Phase 2,
-// lanes along the rank: SEG lanes per draw gather the three factor rows
-// (coalesced row reads), form m with a segmented reduction, and add the
-// per-row contributions with hardware float atomics; the weight gradient and
-// the objective are accumulated in registers and flushed once per wave.
+// Phase 1, one lane per draw: generate the coordinates.  Phase 2, lanes along
+// the rank: SEG lanes per draw gather the three factor rows (coalesced row
+// reads), form m with a segmented reduction, and add the per-row
+// contributions with hardware float atomics; the weight gradient and the
+// objective are accumulated in registers and flushed once per wave.
 #include "common.hpp"
 
 namespace gcp {
 namespace {
 
 constexpr int kMaxAttempts = 64;
+constexpr uint64_t kEmptyKey = ~0ull;   // never a linear index (those are < 2^63)
 
 struct SArgs {
+  const uint64_t* tab[kMaxNs];     // membership table of slice h
+  uint64_t tmask;                  // table capacity - 1
   const int32_t* coords[kMaxNs];
   const float* vals[kMaxNs];
   const float* S[kMaxNs];
@@ -82,38 +90,25 @@ __device__ __forceinline__ int64_t scale_to(uint32_t w, int64_t n) {
   return (int64_t)(((uint64_t)w * (uint64_t)n) >> 32);
 }
 
-__device__ __forceinline__ int64_t lin_of(const int32_t* c, int64_t i, int I2, int I3) {
-  return ((int64_t)c[3 * i] * I2 + c[3 * i + 1]) * I3 + c[3 * i + 2];
+// Hash of a linear index into a table of capacity mask + 1 (a power of 2).
+__device__ __forceinline__ uint64_t slot_of(uint64_t key, uint64_t mask) {
+  return ((key * 0x9E3779B97F4A7C15ull) >> 29) & mask;
 }
 
-// Is linear index `key` a stored entry of the sorted COO list?
-__device__ bool is_stored(const int32_t* coords, int64_t nnz, int64_t key, int I2, int I3) {
-  int64_t lo = 0, hi = nnz;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    const int64_t v = lin_of(coords, mid, I2, I3);
-    if (v < key)
-      lo = mid + 1;
-    else
-      hi = mid;
+// Is linear index `key` a stored entry of the slice whose table is `tab`?
+__device__ __forceinline__ bool is_stored(const uint64_t* __restrict__ tab, uint64_t mask, uint64_t key) {
+  for (uint64_t pos = slot_of(key, mask);; pos = (pos + 1) & mask) {
+    const uint64_t v = tab[pos];
+    if (v == key) return true;
+    if (v == kEmptyKey) return false;
   }
-  return lo < nnz && lin_of(coords, lo, I2, I3) == key;
 }
 
-// Draw record of the two-phase variant: the three coordinates and the
-// weighted loss derivative c_h * w * y of one draw (zero for a draw that
-// contributes nothing).
-struct DrawRec {
-  int i1, i2, i3;
-  float y;
-};
-
-// REC = false: one pass; the SEG lanes of a draw add their rank columns of
-// the three MTTKRP rows with global atomics.
-// REC = true: first phase of the two-phase variant; the draw's record is
-// written to recs[h * (p + q) + id] instead, and sampled_scatter forms G.
-template <int LOSS, int SEG, bool REC>
-__global__ void __launch_bounds__(256) sampled_kernel(SArgs a, DrawRec* __restrict__ recs) {
+// One-pass variant: phase 1 forms one draw per lane; phase 2 takes the
+// wave's draws SEG lanes (rank columns) at a time and adds their rows of the
+// three MTTKRPs with global atomics.
+template <int LOSS, int SEG>
+__global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t gwave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int h = (int)(gwave / a.waves_per_slice);
@@ -145,7 +140,7 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a, DrawRec* __restri
         i1 = (int)scale_to(r.v[0], I1);
         i2 = (int)scale_to(r.v[1], I2);
         i3 = (int)scale_to(r.v[2], I3);
-        ok = !is_stored(coords, nnz, ((int64_t)i1 * I2 + i2) * I3 + i3, I2, I3);
+        ok = !is_stored(a.tab[h], a.tmask, ((uint64_t)i1 * I2 + i2) * I3 + i3);
       }
       if (ok) {
         wgt = a.w_z[h];
@@ -164,43 +159,53 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a, DrawRec* __restri
   const float sj = j < R ? a.S[h][j] : 0.f;
   const bool cur = h == 0;
   float gsl = 0.f;
-  float yown = 0.f;
   Kahan<float> lacc;
   const int nd = (int)min<int64_t>(64, total - first);
-  for (int base = 0; base < nd; base += PER) {
-    const int src = base + sub;
-    const int b1 = __shfl(i1, src), b2 = __shfl(i2, src), b3 = __shfl(i3, src);
-    const float bx = __shfl(x, src), bw = __shfl(wgt, src);
-    const bool live = src < nd && j < R;
-    const float r1 = live ? a.A1[(size_t)b1 * R + j] : 0.f;
-    const float r2 = live ? a.A2[(size_t)b2 * R + j] : 0.f;
-    const float r3 = live ? a.A3[(size_t)b3 * R + j] : 0.f;
-    float m = sj * r1 * r2 * r3;
-    for (int o = SEG / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o);
-    float f, y;
-    LossFn<float, LOSS>::eval(bx, m, f, y);
-    const float yt = ch * bw * y;
-    if (src < nd && j == 0 && (a.want & kWantLoss)) lacc.add(ch * bw * f);
-    if (REC) {
-      // hand the draw's derivative back to the lane that owns the draw
-      const float yb = __shfl(bw != 0.f ? yt : 0.f, ((lane - base) & (PER - 1)) * SEG);
-      if (lane >= base && lane < base + PER) yown = yb;
-      if (live && bw != 0.f && cur && (a.want & kWantGrad)) gsl += yt * r1 * r2 * r3;
-    } else if (live && bw != 0.f && (a.want & kWantGrad)) {
-      const float ys = yt * sj;
-      unsafeAtomicAdd(&a.G1[(size_t)b1 * R + j], ys * r2 * r3);
-      unsafeAtomicAdd(&a.G2[(size_t)b2 * R + j], ys * r1 * r3);
-      unsafeAtomicAdd(&a.G3[(size_t)b3 * R + j], ys * r1 * r2);
-      if (cur) gsl += yt * r1 * r2 * r3;
+  const int jc = j < R ? j : 0;
+  // U draws per lane group at a time: their lane exchanges and their factor
+  // row gathers are all issued before any is used (loads of padded draws and
+  // columns read row 0 / column 0 and are masked afterwards, so the loads
+  // themselves are unconditional)
+  constexpr int U = 4;
+  for (int base = 0; base < nd; base += PER * U) {
+    int b1[U], b2[U], b3[U];
+    float bx[U], bw[U], r1[U], r2[U], r3[U];
+    bool live[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int src = base + PER * u + sub;
+      const int sl = src < 64 ? src : 0;
+      b1[u] = __shfl(i1, sl);
+      b2[u] = __shfl(i2, sl);
+      b3[u] = __shfl(i3, sl);
+      bx[u] = __shfl(x, sl);
+      bw[u] = __shfl(wgt, sl);
+      live[u] = src < nd && j < R;
     }
-  }
-  if (REC && id < total) {
-    DrawRec rc;
-    rc.i1 = i1;
-    rc.i2 = i2;
-    rc.i3 = i3;
-    rc.y = yown;
-    recs[(size_t)h * total + id] = rc;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      r1[u] = a.A1[(size_t)b1[u] * R + jc];
+      r2[u] = a.A2[(size_t)b2[u] * R + jc];
+      r3[u] = a.A3[(size_t)b3[u] * R + jc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float lm = live[u] ? 1.f : 0.f;
+      float m = sj * r1[u] * r2[u] * r3[u] * lm;
+      for (int o = SEG / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o);
+      float f, y;
+      LossFn<float, LOSS>::eval(bx[u], m, f, y);
+      const float w = base + PER * u + sub < nd ? bw[u] : 0.f;
+      const float yt = ch * w * y;
+      if (j == 0 && w != 0.f && (a.want & kWantLoss)) lacc.add(ch * w * f);
+      if (live[u] && w != 0.f && (a.want & kWantGrad)) {
+        const float ys = yt * sj;
+        unsafeAtomicAdd(&a.G1[(size_t)b1[u] * R + j], ys * r2[u] * r3[u]);
+        unsafeAtomicAdd(&a.G2[(size_t)b2[u] * R + j], ys * r1[u] * r3[u]);
+        unsafeAtomicAdd(&a.G3[(size_t)b3[u] * R + j], ys * r1[u] * r2[u]);
+        if (cur) gsl += yt * r1[u] * r2[u] * r3[u];
+      }
+    }
   }
   if (cur && (a.want & kWantGrad)) {
     for (int o = SEG; o < 64; o <<= 1) gsl += __shfl_xor(gsl, o);
@@ -264,141 +269,56 @@ __global__ void sampled_check(const float* G1, const float* G2, const float* G3,
   }
 }
 
-// Second phase of the two-phase variant.  Workgroup (chunk, k) owns rank
-// columns [chunk*RC, chunk*RC + RC) and the k-th of wpc equal runs of the
-// draw records; it accumulates its columns of all three MTTKRPs for every
-// row in LDS, then adds them to G with one atomic per touched entry.
-// kScatterThreads / RC draws are taken per pass, U passes in flight.
-constexpr int kScatterThreads = 1024;
-
-template <int RC>
-__global__ void __launch_bounds__(kScatterThreads) sampled_scatter(SArgs a, const DrawRec* __restrict__ recs,
-                                                                   int64_t ndraws, int wpc) {
-  extern __shared__ float acc[];  // (I1 + I2 + I3) x RC
-  __shared__ float sS[kMaxNs * RC];
-  constexpr int DPI = kScatterThreads / RC;
-  constexpr int U = 4;
-  const int chunk = blockIdx.x / wpc, k = blockIdx.x - chunk * wpc;
-  const int I1 = a.I1, I2 = a.I2, I3 = a.I3, R = a.R;
-  const int nrow = I1 + I2 + I3;
-  const int c0 = chunk * RC;
-  for (int i = threadIdx.x; i < nrow * RC; i += kScatterThreads) acc[i] = 0.f;
-  for (int i = threadIdx.x; i < a.ns * RC; i += kScatterThreads) {
-    const int h = i / RC, jj = i - h * RC;
-    sS[i] = c0 + jj < R ? a.S[h][c0 + jj] : 0.f;
-  }
-  __syncthreads();
-  float* acc1 = acc;
-  float* acc2 = acc + I1 * RC;
-  float* acc3 = acc + (I1 + I2) * RC;
-  const int64_t per = (ndraws + wpc - 1) / wpc;
-  const int64_t lo = (int64_t)k * per, hi = min<int64_t>(ndraws, lo + per);
-  const int64_t total = a.p + a.q;
-  const int jj = threadIdx.x % RC, sub = threadIdx.x / RC;
-  const int col = min(c0 + jj, R - 1);
-  const bool colok = c0 + jj < R;
-  for (int64_t d0 = lo; d0 < hi; d0 += (int64_t)DPI * U) {
-    DrawRec rc[U];
-    int hh[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t d = d0 + u * DPI + sub;
-      if (d < hi) {
-        rc[u] = recs[d];
-        hh[u] = (int)(d / total);
-      } else {
-        rc[u].i1 = rc[u].i2 = rc[u].i3 = 0;
-        rc[u].y = 0.f;
-        hh[u] = 0;
-      }
-    }
-    float v1[U], v2[U], v3[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      v1[u] = a.A1[(size_t)rc[u].i1 * R + col];
-      v2[u] = a.A2[(size_t)rc[u].i2 * R + col];
-      v3[u] = a.A3[(size_t)rc[u].i3 * R + col];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (rc[u].y != 0.f && colok) {
-        const float ys = rc[u].y * sS[hh[u] * RC + jj];
-        atomicAdd(&acc1[rc[u].i1 * RC + jj], ys * v2[u] * v3[u]);
-        atomicAdd(&acc2[rc[u].i2 * RC + jj], ys * v1[u] * v3[u]);
-        atomicAdd(&acc3[rc[u].i3 * RC + jj], ys * v1[u] * v2[u]);
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nrow * RC; i += kScatterThreads) {
-    const int row = i / RC, j = c0 + (i - row * RC);
-    const float v = acc[i];
-    if (j >= R || v == 0.f) continue;
-    if (row < I1)
-      unsafeAtomicAdd(&a.G1[(size_t)row * R + j], v);
-    else if (row < I1 + I2)
-      unsafeAtomicAdd(&a.G2[(size_t)(row - I1) * R + j], v);
-    else
-      unsafeAtomicAdd(&a.G3[(size_t)(row - I1 - I2) * R + j], v);
-  }
+// Membership tables: fill with the empty key, then insert every stored
+// entry's linear index (compare-and-swap, linear probing; the capacity is at
+// least twice the entry count, so a free slot is always found).
+__global__ void __launch_bounds__(256) table_fill(uint64_t* __restrict__ tab, uint64_t cap) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * 256)
+    tab[i] = kEmptyKey;
 }
 
-// LDS available to the accumulators of sampled_scatter (the column chunk of
-// S takes the rest).
-constexpr size_t kScatterLds = 155648;
-
-// Rank columns per workgroup for the two-phase variant, 0 when even one
-// column of the three factors does not fit in LDS.
-int scatter_rc(int I1, int I2, int I3, int R) {
-  const size_t nrow = (size_t)I1 + I2 + I3;
-  int rc = 8;
-  while (rc > 1 && (rc / 2 >= R || nrow * rc * 4 > kScatterLds)) rc /= 2;
-  return nrow * rc * 4 <= kScatterLds ? rc : 0;
-}
-
-template <int LOSS, bool REC>
-hipError_t launch_seg(const SampledCall& c, const SArgs& a, int64_t blocks, DrawRec* recs) {
-  if (c.R <= 16) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 16, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a, recs);
-  } else if (c.R <= 32) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 32, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a, recs);
-  } else {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 64, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a, recs);
+__global__ void __launch_bounds__(256) table_insert(const int32_t* __restrict__ coords, int64_t nnz, int I2, int I3,
+                                                    unsigned long long* __restrict__ tab, uint64_t mask) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * 256) {
+    const unsigned long long key =
+        ((unsigned long long)coords[3 * e] * I2 + (unsigned long long)coords[3 * e + 1]) * I3 + coords[3 * e + 2];
+    for (uint64_t pos = slot_of(key, mask);; pos = (pos + 1) & mask) {
+      const unsigned long long prev = atomicCAS(&tab[pos], (unsigned long long)kEmptyKey, key);
+      if (prev == (unsigned long long)kEmptyKey || prev == key) break;
+    }
   }
-  return hipGetLastError();
 }
 
 template <int LOSS>
-hipError_t launch_phase1(const SampledCall& c, const SArgs& a, int64_t blocks, DrawRec* recs) {
-  return recs ? launch_seg<LOSS, true>(c, a, blocks, recs) : launch_seg<LOSS, false>(c, a, blocks, nullptr);
-}
-
-template <int RC>
-hipError_t launch_scatter(const SampledCall& c, const SArgs& a, const DrawRec* recs, int64_t ndraws) {
-  const size_t lds = ((size_t)c.I1 + c.I2 + c.I3) * RC * 4;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sampled_scatter<RC>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kScatterLds);
-  if (e != hipSuccess) return e;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    cus = 256;
-  const int nchunk = (c.R + RC - 1) / RC;
-  // about one workgroup per compute unit, but no fewer draws per
-  // workgroup than accumulator entries it has to clear and flush
-  const int64_t rows = (int64_t)c.I1 + c.I2 + c.I3;
-  int64_t wpc = std::max<int64_t>(1, (cus + nchunk - 1) / nchunk);
-  wpc = std::max<int64_t>(1, std::min<int64_t>(wpc, ndraws / std::max<int64_t>(1, rows)));
-  hipLaunchKernelGGL((sampled_scatter<RC>), dim3((unsigned)(nchunk * wpc)), dim3(kScatterThreads), lds, c.stream,
-                     a, recs, ndraws, (int)wpc);
+hipError_t launch_seg(const SampledCall& c, const SArgs& a, int64_t blocks) {
+  if (c.R <= 16) {
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 16>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+  } else if (c.R <= 32) {
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 32>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+  } else {
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 64>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-size_t sampled_scratch_bytes(int I1, int I2, int I3, int R, int ns_max, int64_t p, int64_t q) {
-  if (scatter_rc(I1, I2, I3, R) == 0) return 0;
-  return (size_t)ns_max * (size_t)(p + q) * sizeof(DrawRec);
+uint64_t table_capacity(int64_t max_nnz) {
+  uint64_t cap = 64;
+  while (cap < 2 * (uint64_t)std::max<int64_t>(max_nnz, 1)) cap <<= 1;
+  return cap;
+}
+
+hipError_t table_build(const int32_t* coords, int64_t nnz, int I2, int I3, uint64_t* tab, uint64_t cap,
+                       hipStream_t stream) {
+  const unsigned fb = (unsigned)std::min<uint64_t>(4096, (cap + 255) / 256);
+  hipLaunchKernelGGL(table_fill, dim3(fb), dim3(256), 0, stream, tab, cap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nnz <= 0) return e;
+  const unsigned ib = (unsigned)std::min<int64_t>(8192, (nnz + 255) / 256);
+  hipLaunchKernelGGL(table_insert, dim3(ib), dim3(256), 0, stream, coords, nnz, I2, I3,
+                     reinterpret_cast<unsigned long long*>(tab), cap - 1);
+  return hipGetLastError();
 }
 
 hipError_t sampled_run(const SampledCall& c) {
@@ -420,6 +340,7 @@ hipError_t sampled_run(const SampledCall& c) {
   SArgs a;
   const double omega = (double)c.I1 * c.I2 * c.I3;
   for (int h = 0; h < c.ns; ++h) {
+    a.tab[h] = c.tab[h];
     a.coords[h] = c.coords[h];
     a.vals[h] = static_cast<const float*>(c.vals[h]);
     a.S[h] = static_cast<const float*>(c.S[h]);
@@ -429,6 +350,7 @@ hipError_t sampled_run(const SampledCall& c) {
     a.w_nz[h] = c.p > 0 ? (float)((double)c.nnz[h] / (double)c.p) : 0.f;
     a.w_z[h] = c.q > 0 ? (float)((omega - (double)c.nnz[h]) / (double)c.q) : 0.f;
   }
+  a.tmask = c.tab_cap - 1;
   a.A1 = A1; a.A2 = A2; a.A3 = A3;
   a.G1 = G1; a.G2 = G2; a.G3 = G3; a.gs = gs; a.loss = loss;
   a.status = c.status;
@@ -439,28 +361,12 @@ hipError_t sampled_run(const SampledCall& c) {
   a.key1 = (uint32_t)(c.seed >> 32);
   a.call = (uint32_t)c.call;
   const int64_t blocks = (a.waves_per_slice * c.ns + 3) / 4;
-  // two-phase variant when the record buffer was provided and the gradient
-  // is wanted; the one-pass kernel otherwise
-  const int rc = scatter_rc(c.I1, c.I2, c.I3, c.R);
-  const int64_t ndraws = (int64_t)c.ns * (c.p + c.q);
-  DrawRec* recs = nullptr;
-  if (rc > 0 && (c.want & kWantGrad) && c.rec &&
-      c.rec_bytes >= (size_t)ndraws * sizeof(DrawRec))
-    recs = static_cast<DrawRec*>(c.rec);
   if (blocks > 0) {
     if (c.ev_begin) (void)hipEventRecord(c.ev_begin, c.stream);
     switch (c.loss) {
-      case kGaussian: e = launch_phase1<kGaussian>(c, a, blocks, recs); break;
-      case kPoissonLog: e = launch_phase1<kPoissonLog>(c, a, blocks, recs); break;
-      default: e = launch_phase1<kBernoulliLogit>(c, a, blocks, recs);
-    }
-    if (e == hipSuccess && recs) {
-      switch (rc) {
-        case 8: e = launch_scatter<8>(c, a, recs, ndraws); break;
-        case 4: e = launch_scatter<4>(c, a, recs, ndraws); break;
-        case 2: e = launch_scatter<2>(c, a, recs, ndraws); break;
-        default: e = launch_scatter<1>(c, a, recs, ndraws);
-      }
+      case kGaussian: e = launch_seg<kGaussian>(c, a, blocks); break;
+      case kPoissonLog: e = launch_seg<kPoissonLog>(c, a, blocks); break;
+      default: e = launch_seg<kBernoulliLogit>(c, a, blocks);
     }
     if (c.ev_end) (void)hipEventRecord(c.ev_end, c.stream);
     if (e != hipSuccess) return e;

@@ -268,6 +268,14 @@ class Batch:
     def update_factors(self):
         N.check(self.lib.gcp_batch_update_factors(self.handle), "gcp_batch_update_factors")
 
+    def solve_st(self):
+        """LS temporal weights of every Gaussian stream into its registered s_t."""
+        N.check(self.lib.gcp_batch_solve_st(self.handle), "gcp_batch_solve_st")
+
+    def step(self):
+        """solve_st, then update_factors: one time step for every stream."""
+        N.check(self.lib.gcp_batch_step(self.handle), "gcp_batch_step")
+
     def sync_streams(self) -> int:
         return int(self.lib.gcp_batch_sync_streams(self.handle))
 

@@ -128,3 +128,34 @@ def test_batch_graph_replay_matches_eager():
         assert graph_i[i]["slot_times"] == eager_i[i]["slot_times"]
         for k in range(3):
             assert np.array_equal(graph_f[i][k], eager_f[i][k]), (i, k)
+
+
+def test_batch_solve_st_matches_streams_and_oracle():
+    """Batched LS temporal solve: Gaussian streams get the per-stream result
+    (same kernels, same inputs: bitwise) and the oracle's within tolerance;
+    other streams keep the s_t their caller wrote."""
+    import torch
+    from oracle.solve import ls_temporal
+    from paper_2110_14514_amd import Batch
+    print("case: batch solve_st", flush=True)
+    probs = _problems()
+    devs, streams = _make(probs)
+    Xb = [d["X_t"].clone() for d in devs]
+    Sb = [d["s_t"].clone() for d in devs]
+    before = [s.clone() for s in Sb]
+    b = Batch(streams, Xb, Sb)
+    b.solve_st()
+    torch.cuda.synchronize()
+    assert b.sync_streams() == 0
+    n_gauss = 0
+    for i, (p, d, st) in enumerate(zip(probs, devs, streams)):
+        if p.loss != "gaussian":
+            assert torch.equal(Sb[i], before[i]), i
+            continue
+        n_gauss += 1
+        ref = st.solve_st(d["X_t"])
+        torch.cuda.synchronize()
+        assert torch.equal(Sb[i], ref), i
+        pp = p.promoted()
+        assert rel_err(Sb[i].double().cpu().numpy(), ls_temporal(pp.X_t, pp.A, p.mu)) <= TOL, i
+    assert n_gauss >= 2
