@@ -723,6 +723,7 @@ BatchLayout batch_layout(gcp_stream* const* streams, int32_t n) {
   L.desc_step = off; off = align_up(off + n * sizeof(BatchDesc), 256);
   L.state = off; off = align_up(off + n * sizeof(BatchState), 256);
   L.items = off; off = align_up(off + (size_t)L.nitems * sizeof(int2), 256);
+  static_assert(kBatchVariants <= 32, "work counters precede the status word");
   L.counter = off; off += 256;
   L.outstart = off; off = align_up(off + n * sizeof(int64_t), 256);
   L.facstart = off; off = align_up(off + n * sizeof(int64_t), 256);
@@ -795,7 +796,7 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
     d.fac_off1 = (int64_t)s->L.fac_off[1];
     d.fac_off2 = (int64_t)s->L.fac_off[2];
     d.I1 = I1; d.I2 = I2; d.I3 = I3; d.R = R; d.H = s->p.window; d.loss = s->p.loss;
-    d.variant = batch_variant(s->p.loss, R, s->p.window);
+    d.variant = batch_variant(s->p.loss, R, s->p.window, I3);
     d.tb1 = m.tb1; d.tb2 = m.tb2; d.nb1 = m.nb1; d.nb2 = m.nb2; d.nblocks = m.nblocks; d.nwg = m.nwg;
     d.w = s->p.w; d.theta = s->p.theta; d.lam = (float)s->p.lambda; d.mu = (float)s->p.mu;
     d.lower = s->p.lower == -INFINITY ? -INFINITY : (float)s->p.lower;
@@ -834,7 +835,8 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   // variant the most expensive streams come first, so each launch ends with
   // short items
   std::vector<int> var(n);
-  for (int i = 0; i < n; ++i) var[i] = batch_variant(streams[i]->p.loss, streams[i]->p.rank, streams[i]->p.window);
+  for (int i = 0; i < n; ++i)
+    var[i] = batch_variant(streams[i]->p.loss, streams[i]->p.rank, streams[i]->p.window, streams[i]->dims[2]);
   std::sort(order.begin(), order.end(), [&](const std::pair<double, int>& x, const std::pair<double, int>& y) {
     if (var[x.second] != var[y.second]) return var[x.second] < var[y.second];
     return x.first > y.first;
@@ -865,7 +867,7 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   b->io.assign(io, io + n);
   b->st = hip_stream;
   b->ws = ws;
-  b->status = reinterpret_cast<int*>(ws + L.counter) + 16;
+  b->status = reinterpret_cast<int*>(ws + L.counter) + 32;   // after the kBatchVariants counters
   b->tau_f = streams[0]->p.tau_f;
   BatchRun r;
   r.desc = reinterpret_cast<const BatchDesc*>(ws + L.desc_out);

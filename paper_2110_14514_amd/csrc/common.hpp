@@ -192,8 +192,9 @@ struct BatchState {                // per stream, advanced on the device
   int64_t slot_t[kMaxNs];
 };
 // Variants of the batched tile code: loss x (rank tile 16/32) x (one/two
-// h-tiles), index loss * 4 + (R > 16) * 2 + (window + 1 > 16).
-constexpr int kBatchVariants = 12;
+// h-tiles) x (16- or 4-byte slice-row copies), index
+// loss * 8 + (R > 16) * 4 + (window + 1 > 16) * 2 + (I3 % 4 == 0).
+constexpr int kBatchVariants = 24;
 
 struct BatchRun {
   const BatchDesc* desc;
@@ -213,7 +214,7 @@ struct BatchRun {
   int* status;
   hipStream_t stream;
 };
-int batch_variant(int loss, int R, int H);
+int batch_variant(int loss, int R, int H, int I3);
 // Whether variant v runs two workgroups per compute unit.
 bool batch_variant_r16(int v);
 hipError_t batch_grad_run(const BatchRun& b, int want);

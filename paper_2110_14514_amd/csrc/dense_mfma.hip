@@ -183,6 +183,21 @@ __device__ __forceinline__ float row_reduce_scatter(float (&v)[NT], int n) {
   return r;
 }
 
+// Fire-and-forget LDS add.  Issued as an instruction the compiler does not
+// model: an LDS atomic it sees is treated as possibly aliasing the in-flight
+// direct-to-LDS copies and would be preceded by a wait for all of them.
+// Callers only target LDS arrays that no copy writes, and read them back
+// after a barrier; LDS operations complete in order, so the compiler's own
+// lgkmcnt waits stay conservative.
+__device__ __forceinline__ void lds_add(float* p, float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) float*)p;
+  asm volatile("ds_add_f32 %0, %1" ::"v"(off), "v"(v) : "memory");
+#else
+  (void)p; (void)v;
+#endif
+}
+
 // Lane exchanges inside a 16-lane row on the VALU (DPP), no LDS round trip:
 // xor 8 is a rotation of the row by 8; xor 4 is the half-row mirror (lane
 // i <- 7 - i in each 8-lane half, i.e. xor 7) followed by the quad
@@ -233,7 +248,7 @@ __device__ __forceinline__ float row_reduce_scatter_dpp(float (&v)[NT], int n) {
 
 // One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
 // slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
-template <int LOSS, int RT, int NH>
+template <int LOSS, int RT, int NH, bool DMA16>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
                                           float* ring, const float* cl) {
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
@@ -327,16 +342,13 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 #endif
   }
-  // Staged loads (NH <= 2).  With 16-byte copies (rows 16-byte aligned, I3 a
-  // multiple of 4) instruction k covers slice rows 8k .. 8k+7, lane l copying
-  // 4 values of row 8k + l/8; with 4-byte copies instruction k covers rows
-  // 2k, 2k+1, lane l copying value l%32 of row 2k + l/32.  Row h >= 1 lies
-  // at ring + (h-1) omega, row 0 is the current slice.
-  const bool dma16 = (I3 & 3) == 0;
-  const int hsub = dma16 ? (lane >> 3) : (lane >> 5);           // row within an instruction
-  const int esub = dma16 ? 4 * (lane & 7) : (lane & 31);         // entry within the 32-entry group
-  const int rows_per = dma16 ? 8 : 2;
-  const int kx = (ns + rows_per - 1) / rows_per;                 // row instructions per pair (uniform)
+  // Staged loads (NH <= 2).  With 16-byte copies (DMA16: rows 16-byte
+  // aligned, I3 a multiple of 4) instruction k covers slice rows 8k .. 8k+7,
+  // lane l copying 4 values of row 8k + l/8; with 4-byte copies instruction
+  // k covers rows 2k, 2k+1, lane l copying value l%32 of row 2k + l/32.  Row
+  // h >= 1 lies at ring + (h-1) omega, row 0 is the current slice.
+  const int hsub = DMA16 ? (lane >> 3) : (lane >> 5);   // row within an instruction
+  const int esub = DMA16 ? 4 * (lane & 7) : (lane & 31); // entry within the 32-entry group
   float gsacc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) gsacc[t] = 0.f;
@@ -421,8 +433,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           }
       };
 
-      auto compute = [&](int q, const Buf& b) {
-        const int i1l = q / n2, i2l = q - (q / n2) * n2;
+      auto compute = [&](int i1l, int i2l, const Buf& b) {
         float W[NT];
 #pragma unroll
         // staged factor rows are zero past R; the register-prefetch path
@@ -515,8 +526,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // program order, so the sums are deterministic; the adds return
         // nothing, so the wave does not wait for them
         if ((n & ((16 / NT) - 1)) == 0 && jslot < R) {
-          atomicAdd(&g1w[wave][i1l][jslot], v * a2s);
-          atomicAdd(&g2w[wave][i2l][jslot], v * a1s);
+          lds_add(&g1w[wave][i1l][jslot], v * a2s);
+          lds_add(&g2w[wave][i2l][jslot], v * a1s);
         }
       };
 
@@ -524,43 +535,63 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // Staged pipeline: the slice rows and factor rows of pair q are
         // copied global -> LDS by the direct-to-LDS loads two pairs ahead;
         // these are the only vector-memory operations of the loop, so the
-        // wave waits for exactly the stage it is about to read.
-        const int K = kx + 1;   // load instructions per stage
-        // per-lane parts of the source addresses for this group; entries
-        // past the end of the row copy from the row start instead (finite
-        // values whose terms are masked)
+        // wave waits for exactly the stage it is about to read.  Every stage
+        // takes the same KX + 1 copy instructions (rows past the window copy
+        // a valid row into padding that is never used), so the waits are
+        // compile-time constants.
+        constexpr int KX = DMA16 ? 2 * NH : 8 * NH;   // slice-row copies per stage
+        constexpr int K = KX + 1;                      // + the factor rows
+        // entries past the end of the row copy from the group start instead
+        // (finite values whose terms are masked)
         const size_t eoff = (size_t)(c0 + esub < I3 ? c0 + esub : c0);
-        const float* src0 = hsub == 0 ? a.Xt + eoff : a.ring + (size_t)(hsub - 1) * a.omega + eoff;
-        const float* srck = a.ring + (size_t)hsub * a.omega + eoff;
-        auto issue = [&](int q, int st) {
-          const int i1 = i10 + q / n2, i2 = i20 + (q - (q / n2) * n2);
-          const size_t row = ((size_t)i1 * I2 + i2) * I3;
-          float* stg = ring_w + st * stage_floats(NH);
-          if (hsub < ns) load_to_lds(src0 + row, stg, dma16 ? 16 : 4);
-          if (dma16) {
+        // per-lane source of row h = rows_per * k + hsub (rows >= ns: X_t)
+        auto row_src = [&](int h) -> const float* {
+          return (h == 0 || h >= ns) ? a.Xt + eoff : a.ring + (size_t)(h - 1) * a.omega + eoff;
+        };
+        const float* src16[DMA16 ? KX : 1];
+        if constexpr (DMA16) {
 #pragma unroll
-            for (int k = 1; k < 2 * NH; ++k)
-              if (k < kx && rows_per * k + hsub < ns)
-                load_to_lds(srck + ((size_t)(rows_per * k - 1) * a.omega + row), stg + 256 * k, 16);
+          for (int k = 0; k < KX; ++k) src16[k] = row_src(8 * k + hsub);
+        }
+        // 4-byte copies: rows 2k + hsub; base pointers for hsub = 0 / 1 of
+        // the ring part, the k-dependent offset is scalar
+        const float* ringl = a.ring + (size_t)hsub * a.omega + eoff;   // row 2k+hsub = ringl + (2k-1) omega
+        const float* xtl = a.Xt + eoff;
+        // pair of copy step p (row-major over the block), advanced incrementally
+        int pi1 = 0, pi2 = 0;
+        auto issue = [&](int st) {
+          const size_t row = ((size_t)(i10 + pi1) * I2 + (i20 + pi2)) * I3;
+          float* stg = ring_w + st * stage_floats(NH);
+          if constexpr (DMA16) {
+#pragma unroll
+            for (int k = 0; k < KX; ++k) load_to_lds(src16[k] + row, stg + 256 * k, 16);
           } else {
 #pragma unroll
-            for (int k = 1; k < 8 * NH; ++k)
-              if (k < kx && rows_per * k + hsub < ns)
-                load_to_lds(srck + ((size_t)(rows_per * k - 1) * a.omega + row), stg + 64 * k, 4);
+            for (int k = 0; k < KX; ++k) {
+              const int h = 2 * k + hsub;
+              const float* sp = (h == 0 || h >= ns) ? xtl : ringl + (size_t)(2 * k - 1) * a.omega;
+              load_to_lds(sp + row, stg + 64 * k, 4);
+            }
           }
           // factor rows: lanes 0-31 copy row i1 of A1, lanes 32-63 row i2 of
           // A2; columns j >= R are never written and keep their zeros
           if ((lane & 31) < R) {
-            const float* fsrc = lane < 32 ? a.A1 + (size_t)i1 * R + lane : a.A2 + (size_t)i2 * R + (lane - 32);
+            const float* fsrc = lane < 32 ? a.A1 + (size_t)(i10 + pi1) * R + lane
+                                          : a.A2 + (size_t)(i20 + pi2) * R + (lane - 32);
             load_to_lds(fsrc, stg + 512 * NH, 4);
           }
+          if (++pi2 == n2) {
+            pi2 = 0;
+            ++pi1;
+          }
         };
-        if (npairs > 0) issue(0, 0);
-        if (npairs > 1) issue(1, 1);
+        if (npairs > 0) issue(0);
+        if (npairs > 1) issue(1);
+        int ci1 = 0, ci2 = 0;
         for (int q = 0; q < npairs; ++q) {
           const int st = q % kStages;
           if (q + 2 < npairs) {
-            issue(q + 2, (q + 2) % kStages);
+            issue((q + 2) % kStages);
             wait_vmcnt(2 * K);
           } else if (q + 1 < npairs) {
             wait_vmcnt(K);
@@ -592,7 +623,11 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           }
           b.a1s = fa[jslot];
           b.a2s = fa[32 + jslot];
-          compute(q, b);
+          compute(ci1, ci2, b);
+          if (++ci2 == n2) {
+            ci2 = 0;
+            ++ci1;
+          }
         }
       } else {
         // ping-pong: the buffer being computed was filled one step earlier
@@ -600,10 +635,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         if (npairs > 0) load_pair(0, bA);
         for (int q = 0; q < npairs; q += 2) {
           if (q + 1 < npairs) load_pair(q + 1, bB);
-          compute(q, bA);
+          compute(q / n2, q % n2, bA);
           if (q + 1 >= npairs) break;
           if (q + 2 < npairs) load_pair(q + 2, bA);
-          compute(q + 1, bB);
+          compute((q + 1) / n2, (q + 1) % n2, bB);
         }
       }
     };
@@ -675,7 +710,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   }
 }
 
-template <int LOSS, int RT, int NH>
+template <int LOSS, int RT, int NH, bool DMA16>
 __device__ __forceinline__ void fused_body(const MArgs& a) {
   __shared__ float g1s[kWaves * kTB * RT];
   __shared__ float g2s[kWaves * kTB * RT];
@@ -686,21 +721,21 @@ __device__ __forceinline__ void fused_body(const MArgs& a) {
   __shared__ float cl[kMaxNs];
   for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl);
+  mfma_tile<LOSS, RT, NH, DMA16>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl);
 }
 
-template <int LOSS, int RT, int NH>
+template <int LOSS, int RT, int NH, bool DMA16>
 __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
-  fused_body<LOSS, RT, NH>(a);
+  fused_body<LOSS, RT, NH, DMA16>(a);
 }
 
 // Rank tile 16 with one h-tile: the LDS of two workgroups fits a compute
 // unit, so the register budget is held to 128 (four waves per SIMD); the
 // few values that do not fit are spilled outside the pair loop.
-template <int LOSS>
+template <int LOSS, bool DMA16>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 fused_dense_mfma_r16(MArgs a) {
-  fused_body<LOSS, 16, 1>(a);
+  fused_body<LOSS, 16, 1, DMA16>(a);
 }
 
 template <int LOSS, int RT, int NH>
@@ -724,10 +759,19 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.lossp = lossp;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
-  if constexpr (RT == 16 && NH == 1)
-    hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
-  else
-    hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+  // 16-byte slice-row copies need 16-byte aligned rows: I3 a multiple of 4
+  const bool dma16 = (c.I3 % 4) == 0;
+  if constexpr (RT == 16 && NH == 1) {
+    if (dma16)
+      hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+    else
+      hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+  } else {
+    if (dma16)
+      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+    else
+      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+  }
   return hipGetLastError();
 }
 
@@ -800,7 +844,7 @@ __device__ __forceinline__ uint64_t splitmix64_dev(uint64_t x) {
 
 // One variant's share of the work list: items [begin, end), taken in order
 // from the variant's own counter.
-template <int LOSS, int RT, int NH>
+template <int LOSS, int RT, int NH, bool DMA16>
 __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ desc,
                                                 const BatchState* __restrict__ state,
                                                 const int2* __restrict__ items, int begin, int end,
@@ -845,25 +889,25 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
       cl[h] = v;
     }
     __syncthreads();
-    mfma_tile<LOSS, RT, NH>(ta, wg, g1s, g2s, sm, ring, cl);
+    mfma_tile<LOSS, RT, NH, DMA16>(ta, wg, g1s, g2s, sm, ring, cl);
     __syncthreads();
   }
 }
 
-template <int LOSS, int RT, int NH>
+template <int LOSS, int RT, int NH, bool DMA16>
 __global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
                                                               const BatchState* __restrict__ state,
                                                               const int2* __restrict__ items, int begin, int end,
                                                               int* __restrict__ counter, int want) {
-  batch_grad_body<LOSS, RT, NH>(desc, state, items, begin, end, counter, want);
+  batch_grad_body<LOSS, RT, NH, DMA16>(desc, state, items, begin, end, counter, want);
 }
 
 // Rank tile 16, one h-tile: four waves per SIMD, as fused_dense_mfma_r16.
-template <int LOSS>
+template <int LOSS, bool DMA16>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 batch_grad_kernel_r16(const BatchDesc* __restrict__ desc, const BatchState* __restrict__ state,
                       const int2* __restrict__ items, int begin, int end, int* __restrict__ counter, int want) {
-  batch_grad_body<LOSS, 16, 1>(desc, state, items, begin, end, counter, want);
+  batch_grad_body<LOSS, 16, 1, DMA16>(desc, state, items, begin, end, counter, want);
 }
 
 __device__ __forceinline__ float wave_sum_fixed_f(float v) {
@@ -1013,41 +1057,48 @@ __global__ void __launch_bounds__(256) batch_window_copy(const BatchDesc* __rest
 
 }  // namespace
 
-int batch_variant(int loss, int R, int H) { return loss * 4 + (R > 16 ? 2 : 0) + (H + 1 > 16 ? 1 : 0); }
+int batch_variant(int loss, int R, int H, int I3) {
+  return loss * 8 + (R > 16 ? 4 : 0) + (H + 1 > 16 ? 2 : 0) + (I3 % 4 == 0 ? 1 : 0);
+}
 
 namespace {
 
-template <int LOSS, int RT, int NH>
+template <int LOSS, int RT, int NH, bool DMA16>
 void launch_batch_variant(const BatchRun& b, int v, int want) {
   const dim3 grid((unsigned)b.vgrid[v]);
   if constexpr (RT == 16 && NH == 1)
-    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state, b.items,
-                       b.vbegin[v], b.vend[v], b.counter + v, want);
+    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS, DMA16>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+                       b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
   else
-    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH, DMA16>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
 }
 
+// variant v = loss * 8 + (R > 16) * 4 + (two h-tiles) * 2 + (I3 % 4 == 0)
 template <int LOSS>
 void launch_batch_loss(const BatchRun& b, int v, int want) {
-  switch (v & 3) {
-    case 0: launch_batch_variant<LOSS, 16, 1>(b, v, want); break;
-    case 1: launch_batch_variant<LOSS, 16, 2>(b, v, want); break;
-    case 2: launch_batch_variant<LOSS, 32, 1>(b, v, want); break;
-    default: launch_batch_variant<LOSS, 32, 2>(b, v, want); break;
+  switch (v & 7) {
+    case 0: launch_batch_variant<LOSS, 16, 1, false>(b, v, want); break;
+    case 1: launch_batch_variant<LOSS, 16, 1, true>(b, v, want); break;
+    case 2: launch_batch_variant<LOSS, 16, 2, false>(b, v, want); break;
+    case 3: launch_batch_variant<LOSS, 16, 2, true>(b, v, want); break;
+    case 4: launch_batch_variant<LOSS, 32, 1, false>(b, v, want); break;
+    case 5: launch_batch_variant<LOSS, 32, 1, true>(b, v, want); break;
+    case 6: launch_batch_variant<LOSS, 32, 2, false>(b, v, want); break;
+    default: launch_batch_variant<LOSS, 32, 2, true>(b, v, want); break;
   }
 }
 
 }  // namespace
 
-bool batch_variant_r16(int v) { return (v & 3) == 0; }
+bool batch_variant_r16(int v) { return (v & 6) == 0; }
 
 hipError_t batch_grad_run(const BatchRun& b, int want) {
   // one persistent launch per variant present, each over its own slice of
   // the work list
   for (int v = 0; v < kBatchVariants; ++v) {
     if (b.vend[v] <= b.vbegin[v]) continue;
-    switch (v >> 2) {
+    switch (v >> 3) {
       case 0: launch_batch_loss<kGaussian>(b, v, want); break;
       case 1: launch_batch_loss<kPoissonLog>(b, v, want); break;
       default: launch_batch_loss<kBernoulliLogit>(b, v, want); break;
