@@ -65,6 +65,31 @@ def copy_probe(mib: int):
     return 0
 
 
+def _profiled_traffic(summary: str, sources):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated with a copy of known
+    size), or None when the kernel sources differ from the ones profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _time(fn, steps, warmup, sync):
     for _ in range(warmup):
         fn()
@@ -308,6 +333,9 @@ def main():
                "sample": "one full objective+gradient evaluation of the same 200^3 x 11-slice "
                          "workload (FP64 NumPy oracle, BLAS threads as listed)"}
 
+    traffic = _profiled_traffic("fused_dense_c2.txt",
+                                ["paper_2110_14514_amd/csrc/dense_mfma.hip",
+                                 "paper_2110_14514_amd/csrc/common.hpp"])
     res = {
         "metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
         "value": 1e3 / ms_per_step,
@@ -326,7 +354,7 @@ def main():
                    "dims": list(dims), "rank": R, "window": H, "loss": loss,
                    "input_sets": nsets, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fused dense objective+gradient kernel",
                      "kernel_ms": kavg_s * 1e3, "alg_bytes_per_launch": alg_bytes,
                      "alg_gflops_per_launch": alg_flops / 1e9,
