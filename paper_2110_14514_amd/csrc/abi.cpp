@@ -25,6 +25,8 @@ struct WsLayout {
   size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
   size_t plain_bytes, part_bytes;
   uint64_t tab_cap;       // COO: capacity of each membership table (0: dense)
+  size_t rp3;             // dense: row pitch of stored slices (I3 rounded up to 32 values)
+  size_t slot_elems;      // dense: elements of one stored slice (I1 I2 rp3)
 };
 
 struct gcp_stream {
@@ -104,8 +106,13 @@ WsLayout layout_for(const gcp_params* p) {
   L.shist = off; off = align_up(off + (size_t)p->window * R * es, 256);
   const bool coo = p->slice_kind == GCP_SLICE_COO;
   L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
+  // stored dense slices keep each (i1, i2) row on 128-byte lines: the row
+  // pitch is I3 rounded up to 32 values (the padding is never read)
+  L.rp3 = ((size_t)I3 + 31) / 32 * 32;
+  L.slot_elems = (size_t)I1 * I2 * L.rp3;
+  (void)omega;
   L.ring = off;
-  off = align_up(off + (coo ? (size_t)p->window * L.coo_slot : (size_t)p->window * omega * es), 256);
+  off = align_up(off + (coo ? (size_t)p->window * L.coo_slot : (size_t)p->window * L.slot_elems * es), 256);
   L.part_bytes = coo ? 0 : dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
   L.part = off; off = align_up(off + L.part_bytes, 256);
   L.ls = off; off = align_up(off + (coo ? 0 : ls_scratch_bytes(I1, I2, I3, R)), 256);
@@ -140,6 +147,13 @@ gcp_status check_coo_slice(const gcp_stream* s, const gcp_slice* X) {
 char* coo_slot_coords(gcp_stream* s, int slot) { return s->ws + s->L.ring + (size_t)slot * s->L.coo_slot; }
 char* coo_slot_vals(gcp_stream* s, int slot) {
   return coo_slot_coords(s, slot) + (size_t)s->p.max_nnz * 12;
+}
+
+// Copy a dense slice (row pitch I3) into window slot `slot` (row pitch rp3).
+hipError_t store_dense_slot(gcp_stream* s, int slot, const void* vals) {
+  const size_t w = (size_t)s->dims[2] * s->es;
+  return hipMemcpy2DAsync(s->ws + s->L.ring + (size_t)slot * s->L.slot_elems * s->es, s->L.rp3 * s->es, vals, w, w,
+                          (size_t)s->dims[0] * s->dims[1], hipMemcpyDeviceToDevice, s->st);
 }
 
 // Membership table of window slot `slot`; slot == window: the current slice's.
@@ -203,11 +217,13 @@ char* fac_ptr(gcp_stream* s, size_t block, int k) { return s->ws + block + s->L.
 
 void fill_window(gcp_stream* s, DenseCall& c) {
   c.ring = s->ws + s->L.ring;
+  c.ring_pitch = s->L.rp3;
+  c.ring_stride = s->L.slot_elems;
   c.shist = s->ws + s->L.shist;
   c.omega = s->omega;
   int n = 1;
   for (int slot = 0; slot < s->nwin; ++slot, ++n) {
-    c.X[n] = s->ws + s->L.ring + (size_t)slot * s->omega * s->es;
+    c.X[n] = s->ws + s->L.ring + (size_t)slot * s->L.slot_elems * s->es;
     c.S[n] = s->ws + s->L.shist + (size_t)slot * s->p.rank * s->es;
     c.c[n] = s->p.w * pow(s->p.theta, (double)(s->t - s->slot_t[slot]));
   }
@@ -329,8 +345,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
     if (p->slice_kind == GCP_SLICE_COO)
       e = store_coo_slot(s, h, &X_hist[h]);
     else
-      e = hipMemcpyAsync(s->ws + L.ring + (size_t)h * s->omega * s->es, X_hist[h].vals, s->omega * s->es,
-                         hipMemcpyDeviceToDevice, s->st);
+      e = store_dense_slot(s, h, X_hist[h].vals);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->ws + L.shist + (size_t)h * p->rank * s->es,
                          static_cast<const char*>(s_hist) + (size_t)h * p->rank * s->es, p->rank * s->es,
@@ -471,8 +486,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     if (coo)
       e = store_coo_slot(s, slot, X_t);
     else
-      e = hipMemcpyAsync(s->ws + s->L.ring + (size_t)slot * s->omega * s->es, X_t->vals, s->omega * s->es,
-                         hipMemcpyDeviceToDevice, s->st);
+      e = store_dense_slot(s, slot, X_t->vals);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->ws + s->L.shist + (size_t)slot * p.rank * s->es, s_t, p.rank * s->es,
                          hipMemcpyDeviceToDevice, s->st);
@@ -792,6 +806,8 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
     d.gsp = reinterpret_cast<float*>(pb + o); o = align_up(o + (size_t)m.nwg * R * 4, 256);
     d.lossp = reinterpret_cast<float*>(pb + o);
     d.omega = (int64_t)s->omega;
+    d.rp3 = (int64_t)s->L.rp3;
+    d.rstride = (int64_t)s->L.slot_elems;
     d.fac_elems = (int64_t)s->L.fac_elems;
     d.fac_off1 = (int64_t)s->L.fac_off[1];
     d.fac_off2 = (int64_t)s->L.fac_off[2];

@@ -120,9 +120,11 @@ struct DenseCall {
   int want;
   int dtype;                    // 0 = f32, 1 = f64
   const void* X[kMaxNs];        // slice h (0 = current)
-  const void* ring;             // window ring: slice h >= 1 is slot h-1 at ring + (h-1)*omega
+  const void* ring;             // window ring: slice h >= 1 is slot h-1 at ring + (h-1)*ring_stride
   const void* shist;            // window weights: s_h at shist + (h-1)*R
-  size_t omega;
+  size_t omega;                 // I1 I2 I3
+  size_t ring_pitch;            // row pitch of stored slices (>= I3; X[0] has pitch I3)
+  size_t ring_stride;           // elements per stored slice (I1 I2 ring_pitch)
   const void* S[kMaxNs];        // weight row of slice h (R values)
   double c[kMaxNs];             // c_0 = 1, c_h = w theta^(t-h)
   const void* A[3];
@@ -154,6 +156,18 @@ constexpr int kDefaultPlanTarget = 4096;
 MfmaPlan mfma_plan(int I1, int I2, int I3, int target = kDefaultPlanTarget);
 hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                              float* gsp, float* lossp);
+// Per-loss instantiations of the matrix-core tile code (one translation unit
+// each): the single-stream launch and one batched variant launch.
+hipError_t dense_mfma_launch_gaussian(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
+                                      float* gsp, float* lossp);
+hipError_t dense_mfma_launch_poisson(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
+                                     float* gsp, float* lossp);
+hipError_t dense_mfma_launch_bernoulli(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
+                                       float* gsp, float* lossp);
+struct BatchRun;
+void batch_launch_gaussian(const BatchRun& b, int v, int want);
+void batch_launch_poisson(const BatchRun& b, int v, int want);
+void batch_launch_bernoulli(const BatchRun& b, int v, int want);
 
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t dense_fused_run(const DenseCall& c);
@@ -178,6 +192,7 @@ struct BatchDesc {                 // per stream, fixed at batch creation
   float* outgs;
   float* outloss;
   int64_t omega, fac_elems, fac_off1, fac_off2;
+  int64_t rp3, rstride;          // row pitch / slot stride of the stored slices
   int I1, I2, I3, R, H, loss, variant;
   int tb1, tb2, nb1, nb2, nblocks, nwg;
   float lam, mu, lower, beta1, beta2, eps;

@@ -40,6 +40,7 @@ struct FusedArgs {
   T* gsp;
   T* lossp;
   int I1, I2, I3, R, ns, want, tb1, tb2, nb2;
+  size_t rp3;   // row pitch of slices h >= 1 (stored slices); slice 0 has pitch I3
 };
 
 struct Tiling {
@@ -179,10 +180,11 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
         P[j] = W[j] * a3r[j];
         yh[j] = T(0);
       }
-      const size_t off = ((size_t)(i10 + i1l) * I2 + (i20 + i2l)) * I3 + (valid ? i3 : 0);
+      const size_t pr = (size_t)(i10 + i1l) * I2 + (i20 + i2l);
+      const size_t off0 = pr * I3 + (valid ? i3 : 0), offr = pr * a.rp3 + (valid ? i3 : 0);
       for (int h = 0; h < a.ns; ++h) {
         const T* Sh = a.S[h];
-        T x = valid ? a.X[h][off] : T(0);
+        T x = valid ? a.X[h][h == 0 ? off0 : offr] : T(0);
         T m = T(0);
 #pragma unroll
         for (int j = 0; j < RT; ++j)
@@ -406,6 +408,7 @@ hipError_t launch_fused(const DenseCall& c, const Tiling& tl, const PartLayout& 
   a.lossp = reinterpret_cast<T*>(base + pl.loss);
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = tl.tb1; a.tb2 = tl.tb2; a.nb2 = tl.nb2;
+  a.rp3 = c.ring_pitch ? c.ring_pitch : (size_t)c.I3;
   if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);
   hipLaunchKernelGGL((fused_dense_v1<T, LOSS, RT>), dim3(tl.ntiles), dim3(kWG), 0, c.stream, a);
   hipError_t e = hipGetLastError();

@@ -1,0 +1,13 @@
+// Matrix-core tile kernels instantiated for the bernoulli loss.
+#include "mfma_tile.hpp"
+
+namespace gcp {
+
+hipError_t dense_mfma_launch_bernoulli(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
+                                    float* gsp, float* lossp) {
+  return by_rank<kBernoulliLogit>(c, p, G1p, G2p, G3p, gsp, lossp);
+}
+
+void batch_launch_bernoulli(const BatchRun& b, int v, int want) { launch_batch_loss<kBernoulliLogit>(b, v, want); }
+
+}  // namespace gcp

@@ -55,14 +55,20 @@ __global__ void __launch_bounds__(256) k_model(const float* __restrict__ A1, con
 
 template <int LOSS>
 __global__ void __launch_bounds__(256) k_elem(const float* __restrict__ X, const float* __restrict__ M,
-                                              float* __restrict__ Y, float ch, size_t omega,
-                                              float* __restrict__ lossp) {
+                                              float* __restrict__ Y, float ch, size_t omega, int I3,
+                                              size_t pitch, float* __restrict__ lossp) {
   __shared__ float red[256];
   Kahan<float> k;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < omega;
        e += (size_t)gridDim.x * blockDim.x) {
+    // X rows may be padded (stored slices): element e is row e / I3
+    size_t xe = e;
+    if (pitch != (size_t)I3) {
+      const size_t pr = e / (size_t)I3;
+      xe = pr * pitch + (e - pr * (size_t)I3);
+    }
     float f, y;
-    LossFn<float, LOSS>::eval(X[e], M[e], f, y);
+    LossFn<float, LOSS>::eval(X[xe], M[e], f, y);
     Y[e] = ch * y;
     k.add(ch * f);
   }
@@ -259,22 +265,23 @@ hipError_t run_rt(const DenseCall& c, char* base, const PlainLayout& L) {
   const int ygs = (c.I3 + 255) / 256;
   for (int h = 0; h < c.ns; ++h) {
     const float* X = static_cast<const float*>(c.X[h]);
+    const size_t pitch = (h == 0 || c.ring_pitch == 0) ? (size_t)c.I3 : c.ring_pitch;
     const float* s = static_cast<const float*>(c.S[h]);
     hipLaunchKernelGGL(k_model, dim3(2048), dim3(256), 0, c.stream, A1, A2, A3, s, M, c.I2, c.I3, c.R, omega);
     float ch = (float)c.c[h];
     hipError_t e;
     switch (c.loss) {
       case kGaussian:
-        hipLaunchKernelGGL(k_elem<kGaussian>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch, omega,
-                           lossp + (size_t)h * kEBlocks);
+        hipLaunchKernelGGL(k_elem<kGaussian>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch, omega, c.I3,
+                           pitch, lossp + (size_t)h * kEBlocks);
         break;
       case kPoissonLog:
-        hipLaunchKernelGGL(k_elem<kPoissonLog>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch, omega,
-                           lossp + (size_t)h * kEBlocks);
+        hipLaunchKernelGGL(k_elem<kPoissonLog>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch, omega, c.I3,
+                           pitch, lossp + (size_t)h * kEBlocks);
         break;
       default:
         hipLaunchKernelGGL(k_elem<kBernoulliLogit>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch,
-                           omega, lossp + (size_t)h * kEBlocks);
+                           omega, c.I3, pitch, lossp + (size_t)h * kEBlocks);
     }
     if (c.want & kWantGrad) {
       hipLaunchKernelGGL(k_mode1<RT>, dim3(c.I1), dim3(256), shm, c.stream, Y, A2, A3, s, G1, c.I2, c.I3, c.R,

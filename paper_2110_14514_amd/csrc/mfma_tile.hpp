@@ -1,0 +1,972 @@
+// Fused objective/gradient over a dense slice and its window, with the two
+// rank-R contractions on the FP32 matrix cores (v_mfma_f32_16x16x4_f32).
+//
+// Same quantities as the VALU kernel (eq. gcp_stream_problem_1 and the
+// gradients of Section 4.2), organised around two small GEMMs per group of
+// 64 entries e of one (i1,i2) pair row:
+//   GEMM1  m[h][e]  = sum_j S[h][j] P[e][j],  P[e][j] = A1[i1,j] A2[i2,j] A3[i3,j]
+//   GEMM2  yhat[j][e] = sum_h (c_h S[h][j]) y(x_he, m[h][e])
+// (h runs over the current slice and the stored window, S[h] = s_h).  With
+// the 16x16x4 lane layout the accumulator of GEMM1 (rows h, columns e) is
+// directly the B operand of GEMM2 (K = h), so the loss derivative is applied
+// in registers between the two and nothing is staged through memory.
+// The mode products that follow are elementwise in j and stay on the VALU:
+//   G3[i3,:]  += yhat[:,e] * A1[i1,:] * A2[i2,:]      (lane-local)
+//   V[i1,i2,:] = sum_i3 yhat[:,e] * A3[i3,:]          (16-lane reduce-scatter)
+//   G1[i1,:] += V * A2[i2,:],  G2[i2,:] += V * A1[i1,:]
+//   g_s      += y_t[e] * P[e,:]                       (current slice only)
+//
+// Lane layout of the 16x16x4 FP32 MFMA (lane l = 16 g + n):
+//   A operand: A[row n][k g];  B operand: B[k g][col n];
+//   accumulator register r: D[row 4g + r][col n].
+// GEMM1: rows = h (16 per h-tile), cols = 16 entries, K = j.  The K index of
+// step t held by lane group g is j(t,g) = 16 (t/4) + 4g + t%4, chosen so that
+// GEMM2's output row of register r in M-tile mt, j = 16 mt + 4g + r, is the
+// same j a lane already holds for step t = 4 mt + r.
+// Entries: a full group is NU = 2 16-column tiles u (32 entries, sized to the
+// register file) with i3 = c0 + 2n + u, so each lane loads 2 contiguous
+// values per slice; the ragged tail of a row uses i3 = c0 + 16u + n with only
+// the tiles that hold entries.
+//
+// Work decomposition: each wave owns a TB1 x TB2 block of pairs over all of
+// I3; eight waves form a workgroup that combines its waves' mode-3 rows and
+// temporal-gradient partials in a fixed order.  All partials go to
+// block/workgroup-indexed slots and are summed in a fixed order by the
+// reduce kernel, so results are bitwise reproducible.
+#pragma once
+
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace gcp {
+namespace {
+
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTB = 16;
+
+// Everything one workgroup needs for its tile of pair blocks.  Slice h = 0 is
+// the current slice; slice h >= 1 is window slot h-1 of the ring (slot order),
+// with weight row s_{h} at shist + (h-1) R.
+struct TileArgs {
+  const float* Xt;
+  const float* ring;
+  size_t rstride;   // elements per stored slice
+  size_t rp3;       // row pitch of stored slices (X_t rows have pitch I3)
+  const float* st;
+  const float* shist;
+  const float* A1;
+  const float* A2;
+  const float* A3;
+  float* G1p;
+  float* G2p;
+  float* G3p;
+  float* gsp;
+  float* lossp;
+  int I1, I2, I3, R, ns, want, tb1, tb2, nb2, nblocks;
+};
+
+struct MArgs {
+  TileArgs t;
+  float c[kMaxNs];
+};
+
+// Per-wave LDS ring of the staged pipeline: kStages stages, each holding
+// 16*NH slice rows of 32 values and the pair's two factor rows (64 values).
+constexpr int kStages = 3;
+__host__ __device__ constexpr int stage_floats(int NH) { return 16 * NH * 32 + 64; }
+__host__ __device__ constexpr int ring_floats(int NH) { return NH <= 2 ? kWaves * kStages * stage_floats(NH) : 0; }
+
+// LDS floats used by one workgroup at rank tile RT and NH h-tiles
+__host__ __device__ constexpr int lds_floats(int RT, int NH) {
+  return 64 * (RT + 1) + kWaves * RT + kWaves;
+}
+
+// Wait until at most n vector-memory operations of this wave are in flight
+// (n is wave-uniform; the immediate must be a constant).  n >= 40 waits for
+// 40, which is always safe (it only waits longer).
+__device__ __forceinline__ void wait_vmcnt(int n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  switch (n) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+    case 6: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+    case 7: asm volatile("s_waitcnt vmcnt(7)" ::: "memory"); break;
+    case 8: asm volatile("s_waitcnt vmcnt(8)" ::: "memory"); break;
+    case 9: asm volatile("s_waitcnt vmcnt(9)" ::: "memory"); break;
+    case 10: asm volatile("s_waitcnt vmcnt(10)" ::: "memory"); break;
+    case 11: asm volatile("s_waitcnt vmcnt(11)" ::: "memory"); break;
+    case 12: asm volatile("s_waitcnt vmcnt(12)" ::: "memory"); break;
+    case 13: asm volatile("s_waitcnt vmcnt(13)" ::: "memory"); break;
+    case 14: asm volatile("s_waitcnt vmcnt(14)" ::: "memory"); break;
+    case 15: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
+    case 16: asm volatile("s_waitcnt vmcnt(16)" ::: "memory"); break;
+    case 17: asm volatile("s_waitcnt vmcnt(17)" ::: "memory"); break;
+    case 18: asm volatile("s_waitcnt vmcnt(18)" ::: "memory"); break;
+    case 19: asm volatile("s_waitcnt vmcnt(19)" ::: "memory"); break;
+    case 20: asm volatile("s_waitcnt vmcnt(20)" ::: "memory"); break;
+    case 21: asm volatile("s_waitcnt vmcnt(21)" ::: "memory"); break;
+    case 22: asm volatile("s_waitcnt vmcnt(22)" ::: "memory"); break;
+    case 23: asm volatile("s_waitcnt vmcnt(23)" ::: "memory"); break;
+    case 24: asm volatile("s_waitcnt vmcnt(24)" ::: "memory"); break;
+    case 25: asm volatile("s_waitcnt vmcnt(25)" ::: "memory"); break;
+    case 26: asm volatile("s_waitcnt vmcnt(26)" ::: "memory"); break;
+    case 27: asm volatile("s_waitcnt vmcnt(27)" ::: "memory"); break;
+    case 28: asm volatile("s_waitcnt vmcnt(28)" ::: "memory"); break;
+    case 29: asm volatile("s_waitcnt vmcnt(29)" ::: "memory"); break;
+    case 30: asm volatile("s_waitcnt vmcnt(30)" ::: "memory"); break;
+    case 31: asm volatile("s_waitcnt vmcnt(31)" ::: "memory"); break;
+    case 32: asm volatile("s_waitcnt vmcnt(32)" ::: "memory"); break;
+    case 33: asm volatile("s_waitcnt vmcnt(33)" ::: "memory"); break;
+    case 34: asm volatile("s_waitcnt vmcnt(34)" ::: "memory"); break;
+    case 35: asm volatile("s_waitcnt vmcnt(35)" ::: "memory"); break;
+    case 36: asm volatile("s_waitcnt vmcnt(36)" ::: "memory"); break;
+    case 37: asm volatile("s_waitcnt vmcnt(37)" ::: "memory"); break;
+    case 38: asm volatile("s_waitcnt vmcnt(38)" ::: "memory"); break;
+    case 39: asm volatile("s_waitcnt vmcnt(39)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(40)" ::: "memory"); break;
+  }
+#else
+  (void)n;
+#endif
+}
+
+// Direct global -> LDS copy of `bytes` (4 or 16) per lane: lane i writes at
+// lds + i * bytes (lds is wave-uniform); completion is counted by vmcnt.
+__device__ __forceinline__ void load_to_lds(const float* src, float* lds, int bytes) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (bytes == 16)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+#else
+  (void)src; (void)lds; (void)bytes;
+#endif
+}
+
+
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Bitwise select that cannot be turned into a select of addresses (which
+// would force the array it reads from into private memory).
+__device__ __forceinline__ float pick(bool c, float a, float b) {
+  const unsigned m = 0u - (unsigned)c;
+  return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+
+template <int NT>
+__device__ __forceinline__ float row_reduce_scatter(float (&v)[NT], int n) {
+  // sum over the 16 lanes of a row; lane n ends with element n >> (4 - log2 NT)
+  int mask = 8;
+#pragma unroll
+  for (int half = NT / 2; half >= 1; half /= 2) {
+    const bool hi = (n & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float lo_v = v[i], hi_v = v[i + half];
+      const float send = pick(hi, lo_v, hi_v);
+      const float keep = pick(hi, hi_v, lo_v);
+      v[i] = keep + __shfl_xor(send, mask);
+    }
+    mask >>= 1;
+  }
+  float r = v[0];
+  for (; mask >= 1; mask >>= 1) r += __shfl_xor(r, mask);
+  return r;
+}
+
+// Fire-and-forget LDS add.  Issued as an instruction the compiler does not
+// model: an LDS atomic it sees is treated as possibly aliasing the in-flight
+// direct-to-LDS copies and would be preceded by a wait for all of them.
+// Callers only target LDS arrays that no copy writes, and read them back
+// after a barrier; LDS operations complete in order, so the compiler's own
+// lgkmcnt waits stay conservative.
+__device__ __forceinline__ void lds_add(float* p, float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned off = (unsigned)(size_t)(__attribute__((address_space(3))) float*)p;
+  asm volatile("ds_add_f32 %0, %1" ::"v"(off), "v"(v) : "memory");
+#else
+  (void)p; (void)v;
+#endif
+}
+
+// Lane exchanges inside a 16-lane row on the VALU (DPP), no LDS round trip:
+// xor 8 is a rotation of the row by 8; xor 4 is the half-row mirror (lane
+// i <- 7 - i in each 8-lane half, i.e. xor 7) followed by the quad
+// permutation [3,2,1,0] (xor 3); xor 2 and xor 1 are quad permutations.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float row_xor8(float v) { return dpp<0x128>(v); }
+__device__ __forceinline__ float row_xor4(float v) { return dpp<0x1B>(dpp<0x141>(v)); }
+__device__ __forceinline__ float row_xor2(float v) { return dpp<0x4E>(v); }
+__device__ __forceinline__ float row_xor1(float v) { return dpp<0xB1>(v); }
+
+template <int M>
+__device__ __forceinline__ float row_xor(float v) {
+  if constexpr (M == 8) return row_xor8(v);
+  else if constexpr (M == 4) return row_xor4(v);
+  else if constexpr (M == 2) return row_xor2(v);
+  else return row_xor1(v);
+}
+
+// One reduce-scatter step over lane bit M: the lane keeps the upper half of
+// its H values when the bit is set, and adds the partner's copy of that half.
+template <int M, int H, int NT>
+__device__ __forceinline__ void rs_step(float (&v)[NT], int n) {
+  const bool hi = (n & M) != 0;
+#pragma unroll
+  for (int i = 0; i < H / 2; ++i) {
+    const float lo_v = v[i], hi_v = v[i + H / 2];
+    v[i] = pick(hi, hi_v, lo_v) + row_xor<M>(pick(hi, lo_v, hi_v));
+  }
+}
+
+// Same result and lane mapping as row_reduce_scatter, with DPP exchanges.
+template <int NT>
+__device__ __forceinline__ float row_reduce_scatter_dpp(float (&v)[NT], int n) {
+  static_assert(NT == 4 || NT == 8, "rank tile of 16 or 32");
+  rs_step<8, NT>(v, n);
+  rs_step<4, NT / 2>(v, n);
+  if constexpr (NT == 8) {
+    rs_step<2, 2>(v, n);
+    return v[0] + row_xor1(v[0]);
+  } else {
+    float r = v[0] + row_xor2(v[0]);
+    return r + row_xor1(r);
+  }
+}
+
+// One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
+// slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
+// Registers / GEMM2 K-steps of the last h-tile that hold slices of the window
+// (NK = 0: decided at run time from ns; 1..4: fixed by the instantiation, so
+// the skipped work leaves no branches in the pair loop).
+template <int NK, int NH>
+__device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
+  if constexpr (NK == 0)
+    return 16 * ht + 4 * r < ns;
+  else
+    return ht < NH - 1 || r < NK;
+}
+
+template <int LOSS, int RT, int NH, bool DMA16, int NK = 0>
+__device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
+                                          float* ring, const float* cl) {
+  constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
+  constexpr int NM = RT / 16;  // M tiles of GEMM2
+  constexpr int LOGNT = NT == 4 ? 2 : 3;
+  constexpr int NU = 2;                 // 16-entry tiles per group (register budget)
+  constexpr int SW = 16 * NU;           // entries per full group
+
+  // G1/G2 rows of each wave's block and the staging ring are LDS arrays of
+  // their own (declared by the kernel): reads of the row accumulators then
+  // cannot alias the in-flight direct-to-LDS copies, so the compiler adds no
+  // wait for those copies inside the pair loop
+  float(*g1w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g1s);
+  float(*g2w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g2s);
+  float(*g3x)[RT + 1] = reinterpret_cast<float(*)[RT + 1]>(sm);  // SW rows used
+  float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + 64 * (RT + 1));
+  float* lsx = sm + 64 * (RT + 1) + kWaves * RT;
+
+  const int tid = threadIdx.x;
+  // the wave index is uniform across the wave: keeping it scalar keeps all
+  // tile bookkeeping below in scalar registers and branches uniform
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = lane & 15, g = lane >> 4;
+  // this wave's staging ring (NH <= 2)
+  float* ring_w = ring + wave * kStages * stage_floats(NH);
+  const int R = a.R, ns = a.ns, I1 = a.I1, I2 = a.I2, I3 = a.I3;
+  const int blk = wgi * kWaves + wave;
+  const bool active = blk < a.nblocks;
+  const int b1 = active ? blk / a.nb2 : 0, b2 = active ? blk % a.nb2 : 0;
+  const int i10 = b1 * a.tb1, i20 = b2 * a.tb2;
+  const int n1 = active ? min(a.tb1, I1 - i10) : 0;
+  const int n2 = active ? min(a.tb2, I2 - i20) : 0;
+  const bool want_loss = a.want & kWantLoss;
+
+  // j held by this lane at GEMM1 step t; clamped index and 0/1 mask make the
+  // factor-row loads branch-free when R is not a multiple of the rank tile
+  int jt[NT], jc[NT];
+  float jm[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    jt[t] = 16 * (t >> 2) + 4 * g + (t & 3);
+    jc[t] = min(jt[t], R - 1);
+    jm[t] = jt[t] < R ? 1.f : 0.f;
+  }
+  const int jslot = [&] {
+    const int tt = n >> (4 - LOGNT);
+    return 16 * (tt >> 2) + 4 * g + (tt & 3);
+  }();
+  const int jsc = min(jslot, R - 1);
+  const float jsm = jslot < R ? 1.f : 0.f;
+
+  // weights as MFMA operands (zero outside h < ns, j < R)
+  auto sval = [&](int h, int j) -> float {
+    return (h < ns && j < R) ? (h == 0 ? a.st[j] : a.shist[(size_t)(h - 1) * R + j]) : 0.f;
+  };
+  // Slice order inside an h-tile: row i of GEMM1's A operand holds slice
+  // 16 ht + 4 (i % 4) + i / 4, so accumulator register r of lane group g
+  // holds slice 16 ht + 4 r + g.  Each register (and each K-step of GEMM2)
+  // then covers four consecutive slices, and registers / K-steps lying
+  // wholly past the window are skipped with uniform branches.
+  float A1op[NH][NT], A2op[NM][NH][4], cv[NH][4];
+  // base pointer of the slice each (h-tile, register) row of this lane reads
+  const float* sb[NH][4];
+  bool hv[NH][4], sr[NH][4];   // row inside the window; row is a stored slice
+#pragma unroll
+  for (int ht = 0; ht < NH; ++ht) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) A1op[ht][t] = sval(16 * ht + 4 * (n & 3) + (n >> 2), jt[t]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int h = 16 * ht + 4 * r + g;
+      cv[ht][r] = h < ns ? cl[h] : 0.f;
+      hv[ht][r] = h < ns;
+      sb[ht][r] = (h == 0 || h >= ns) ? a.Xt : a.ring + (size_t)(h - 1) * a.rstride;
+      sr[ht][r] = h >= 1 && h < ns;
+    }
+    // GEMM2's A operand carries the history weight: c_h S[h][j]
+#pragma unroll
+    for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int h = 16 * ht + 4 * t + g;
+        A2op[mt][ht][t] = (h < ns ? cl[h] : 0.f) * sval(h, 16 * mt + n);
+      }
+  }
+
+  for (int idx = lane; idx < kTB * RT; idx += 64) {
+    (&g1w[wave][0][0])[idx] = 0.f;
+    (&g2w[wave][0][0])[idx] = 0.f;
+  }
+  if constexpr (NH <= 2) {
+    // slice rows past the window are never loaded into the ring; they must
+    // hold finite values (their products are multiplied by zero weights)
+    for (int idx = lane; idx < kStages * stage_floats(NH); idx += 64) ring_w[idx] = 0.f;
+    // the zeros must land before any direct-to-LDS copy into the ring
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#endif
+  }
+  // Staged loads (NH <= 2).  With 16-byte copies (DMA16: rows 16-byte
+  // aligned, I3 a multiple of 4) instruction k covers slice rows 8k .. 8k+7,
+  // lane l copying 4 values of row 8k + l/8; with 4-byte copies instruction
+  // k covers rows 2k, 2k+1, lane l copying value l%32 of row 2k + l/32.  Row
+  // h >= 1 lies at ring + (h-1) omega, row 0 is the current slice.
+  const int hsub = DMA16 ? (lane >> 3) : (lane >> 5);   // row within an instruction
+  const int esub = DMA16 ? 4 * (lane & 7) : (lane & 31); // entry within the 32-entry group
+  float gsacc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) gsacc[t] = 0.f;
+  Kahan<float> lacc;
+
+  const int nfull = I3 / SW;
+  const int tail = I3 - SW * nfull;
+  const int nsc = nfull + (tail > 0 ? 1 : 0);
+  const bool vec = (I3 % NU) == 0;
+  const int npairs = n1 * n2;
+
+  for (int sc = 0; sc < nsc; ++sc) {
+    const bool wide = sc < nfull;
+    const int c0 = SW * sc;
+    const int nu = wide ? NU : (tail + 15) >> 4;
+    // entries held by this lane: NU adjacent ones in a full group (and in
+    // every group of the staged path), else one per 16-entry tile
+    const bool adj = wide || NH <= 2;
+    int i3u[NU];
+    bool vu[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      i3u[u] = c0 + (adj ? NU * n + u : 16 * u + n);
+      vu[u] = (adj || u < nu) && i3u[u] < I3;
+    }
+    float a3r[NU][NT], g3[NU][NT];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const size_t row = (size_t)(vu[u] ? i3u[u] : 0) * R;
+      const float um = vu[u] ? 1.f : 0.f;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        a3r[u][t] = a.A3[row + jc[t]] * (jm[t] * um);
+        g3[u][t] = 0.f;
+      }
+    }
+
+    // Software pipeline over the block's pairs: the loads of pair q+1 (slice
+    // values and factor rows) are issued before pair q is computed.  Loads
+    // are unconditional or masked-after-zeroing so that no control-flow join
+    // forces an early wait on them, and the compute part issues none.
+    // VEC: a full group of rows whose start is NU-aligned (one NU-wide load
+    // per lane and slice); otherwise per-entry loads.
+    auto run_pairs = [&](auto vec_tag) {
+      constexpr bool VEC = decltype(vec_tag)::value;
+      // Prefetch buffers hold raw loaded values only: any arithmetic on them
+      // at load time would force a wait for the loads.
+      struct Buf {
+        float x[NH][4][NU], a1[NT], a2[NT], a1s, a2s;
+      };
+      Buf bA, bB;
+      auto load_pair = [&](int q, Buf& b) {
+        const int i1 = i10 + q / n2, i2 = i20 + (q - (q / n2) * n2);
+        const float* r1 = a.A1 + (size_t)i1 * R;
+        const float* r2 = a.A2 + (size_t)i2 * R;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          b.a1[t] = r1[jc[t]];
+          b.a2[t] = r2[jc[t]];
+        }
+        b.a1s = r1[jsc];
+        b.a2s = r2[jsc];
+        const size_t base_x = ((size_t)i1 * I2 + i2) * I3, base_r = ((size_t)i1 * I2 + i2) * a.rp3;
+#pragma unroll
+        for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const size_t base = sr[ht][r] ? base_r : base_x;
+            if constexpr (VEC) {
+              f2 v = {0.f, 0.f};
+              if (hv[ht][r])
+                v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(sb[ht][r] + base + c0 + 2 * n));
+              b.x[ht][r][0] = v[0];
+              b.x[ht][r][1] = v[1];
+            } else {
+#pragma unroll
+              for (int u = 0; u < NU; ++u) {
+                float v = 0.f;
+                if (hv[ht][r] && vu[u]) v = sb[ht][r][base + i3u[u]];
+                b.x[ht][r][u] = v;
+              }
+            }
+          }
+      };
+
+      auto compute = [&](int i1l, int i2l, const Buf& b) {
+        float W[NT];
+#pragma unroll
+        // staged factor rows are zero past R; the register-prefetch path
+        // reads clamped columns and masks them here
+        for (int t = 0; t < NT; ++t) W[t] = NH <= 2 ? b.a1[t] * b.a2[t] : b.a1[t] * b.a2[t] * jm[t];
+        const float a1s = NH <= 2 ? b.a1s : b.a1s * jsm, a2s = NH <= 2 ? b.a2s : b.a2s * jsm;
+
+        // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile)
+        f4 D1[NH][NU];
+#pragma unroll
+        for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            if (VEC || u < nu) {
+#pragma unroll
+              for (int t = 0; t < NT; ++t) acc = mfma(A1op[ht][t], W[t] * a3r[u][t], acc);
+            }
+            D1[ht][u] = acc;
+          }
+
+        // loss derivative in place, and the objective terms of the group
+        // (cv = 0 marks padded slices) summed plainly and added to the lane's
+        // running sum with compensation.  Entries past the end of a row
+        // (tail lanes) need no mask in y: their A3 values are zero, so every
+        // product that uses them vanishes and their mode-3 rows are never
+        // written.
+        // Registers holding only slices past the window are left as they
+        // are: GEMM2 skips their K-steps.
+        if (want_loss) {
+          float part = 0.f;
+#pragma unroll
+          for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (!reg_active<NK, NH>(ht, r, ns)) continue;
+#pragma unroll
+              for (int u = 0; u < NU; ++u) {
+                float fv, yv;
+                LossFast<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], fv, yv);
+                part += (vu[u] && cv[ht][r] != 0.f) ? cv[ht][r] * fv : 0.f;
+                D1[ht][u][r] = yv;
+              }
+            }
+          lacc.add(part);
+        } else {
+#pragma unroll
+          for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (!reg_active<NK, NH>(ht, r, ns)) continue;
+#pragma unroll
+              for (int u = 0; u < NU; ++u) D1[ht][u][r] = LossFast<LOSS>::y(b.x[ht][r][u], D1[ht][u][r]);
+            }
+        }
+
+        // temporal-weight gradient: y_t sits in register 0 of lane group 0
+        {
+          float ps[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) ps[t] = 0.f;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const float yt = __shfl(D1[0][u][0], n);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ps[t] += yt * a3r[u][t];
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) gsacc[t] += W[t] * ps[t];
+        }
+
+        // GEMM2: yhat[j][e] = sum_h (c_h S[h][j]) y[h][e]
+        float Vp[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Vp[t] = 0.f;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          if (!VEC && u >= nu) continue;
+#pragma unroll
+          for (int mt = 0; mt < NM; ++mt) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                if (reg_active<NK, NH>(ht, t, ns)) acc = mfma(A2op[mt][ht][t], D1[ht][u][t], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int tt = 4 * mt + r;
+              g3[u][tt] += acc[r] * W[tt];
+              Vp[tt] += acc[r] * a3r[u][tt];
+            }
+          }
+        }
+        const float v = row_reduce_scatter_dpp<NT>(Vp, n);
+        // the rows belong to this wave alone and its LDS adds complete in
+        // program order, so the sums are deterministic; the adds return
+        // nothing, so the wave does not wait for them
+        if ((n & ((16 / NT) - 1)) == 0 && jslot < R) {
+          lds_add(&g1w[wave][i1l][jslot], v * a2s);
+          lds_add(&g2w[wave][i2l][jslot], v * a1s);
+        }
+      };
+
+      if constexpr (VEC && NH <= 2) {
+        // Staged pipeline: the slice rows and factor rows of pair q are
+        // copied global -> LDS by the direct-to-LDS loads two pairs ahead;
+        // these are the only vector-memory operations of the loop, so the
+        // wave waits for exactly the stage it is about to read.  Every stage
+        // takes the same KX + 1 copy instructions (rows past the window copy
+        // a valid row into padding that is never used), so the waits are
+        // compile-time constants.
+        constexpr int KX = DMA16 ? 2 * NH : 8 * NH;   // slice-row copies per stage
+        constexpr int K = KX + 1;                      // + the factor rows
+        // entries past the end of the row copy from the group start instead
+        // (finite values whose terms are masked)
+        const size_t eoff = (size_t)(c0 + esub < I3 ? c0 + esub : c0);
+        // per-lane source of row h = rows_per * k + hsub (rows >= ns: X_t)
+        // and its row pitch: stored slices rp3, the current slice I3
+        auto row_src = [&](int h) -> const float* {
+          return (h == 0 || h >= ns) ? a.Xt + eoff : a.ring + (size_t)(h - 1) * a.rstride + eoff;
+        };
+        const float* src16[DMA16 ? KX : 1];
+        unsigned pit16[DMA16 ? KX : 1];
+        if constexpr (DMA16) {
+#pragma unroll
+          for (int k = 0; k < KX; ++k) {
+            const int h = 8 * k + hsub;
+            src16[k] = row_src(h);
+            pit16[k] = (h >= 1 && h < ns) ? (unsigned)a.rp3 : (unsigned)I3;
+          }
+        }
+        // 4-byte copies: rows 2k + hsub; base pointers for hsub = 0 / 1 of
+        // the ring part, the k-dependent offset is scalar
+        const float* ringl = a.ring + (size_t)hsub * a.rstride + eoff;   // row 2k+hsub = ringl + (2k-1) rstride
+        const float* xtl = a.Xt + eoff;
+        // pair of copy step p (row-major over the block), advanced incrementally
+        int pi1 = 0, pi2 = 0;
+        auto issue = [&](int st) {
+          const size_t pair = (size_t)(i10 + pi1) * I2 + (i20 + pi2);
+          float* stg = ring_w + st * stage_floats(NH);
+          if constexpr (DMA16) {
+#pragma unroll
+            for (int k = 0; k < KX; ++k) load_to_lds(src16[k] + pair * pit16[k], stg + 256 * k, 16);
+          } else {
+            const size_t rowx = pair * I3, rowr = pair * a.rp3;
+#pragma unroll
+            for (int k = 0; k < KX; ++k) {
+              const int h = 2 * k + hsub;
+              const bool stored = h >= 1 && h < ns;
+              const float* sp = stored ? ringl + ((size_t)(2 * k - 1) * a.rstride + rowr) : xtl + rowx;
+              load_to_lds(sp, stg + 64 * k, 4);
+            }
+          }
+          // factor rows: lanes 0-31 copy row i1 of A1, lanes 32-63 row i2 of
+          // A2; columns j >= R are never written and keep their zeros
+          if ((lane & 31) < R) {
+            const float* fsrc = lane < 32 ? a.A1 + (size_t)(i10 + pi1) * R + lane
+                                          : a.A2 + (size_t)(i20 + pi2) * R + (lane - 32);
+            load_to_lds(fsrc, stg + 512 * NH, 4);
+          }
+          if (++pi2 == n2) {
+            pi2 = 0;
+            ++pi1;
+          }
+        };
+        if (npairs > 0) issue(0);
+        if (npairs > 1) issue(1);
+        int ci1 = 0, ci2 = 0;
+        for (int q = 0; q < npairs; ++q) {
+          const int st = q % kStages;
+          if (q + 2 < npairs) {
+            issue((q + 2) % kStages);
+            wait_vmcnt(2 * K);
+          } else if (q + 1 < npairs) {
+            wait_vmcnt(K);
+          } else {
+            wait_vmcnt(0);
+          }
+          const float* stg = ring_w + st * stage_floats(NH);
+          Buf b;
+#pragma unroll
+          for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const f2 v = *reinterpret_cast<const f2*>(stg + (16 * ht + 4 * r + g) * 32 + 2 * n);
+              b.x[ht][r][0] = v[0];
+              b.x[ht][r][1] = v[1];
+            }
+          // columns t of this lane are 16 (t / 4) + 4 g + t % 4: four
+          // contiguous values per 16-column tile (zero past R)
+          const float* fa = stg + 512 * NH;
+#pragma unroll
+          for (int t4 = 0; t4 < NT / 4; ++t4) {
+            const f4 v1 = *reinterpret_cast<const f4*>(fa + 16 * t4 + 4 * g);
+            const f4 v2 = *reinterpret_cast<const f4*>(fa + 32 + 16 * t4 + 4 * g);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              b.a1[4 * t4 + r] = v1[r];
+              b.a2[4 * t4 + r] = v2[r];
+            }
+          }
+          b.a1s = fa[jslot];
+          b.a2s = fa[32 + jslot];
+          compute(ci1, ci2, b);
+          if (++ci2 == n2) {
+            ci2 = 0;
+            ++ci1;
+          }
+        }
+      } else {
+        // ping-pong: the buffer being computed was filled one step earlier
+        // while the other buffer's loads are in flight
+        if (npairs > 0) load_pair(0, bA);
+        for (int q = 0; q < npairs; q += 2) {
+          if (q + 1 < npairs) load_pair(q + 1, bB);
+          compute(q / n2, q % n2, bA);
+          if (q + 1 >= npairs) break;
+          if (q + 2 < npairs) load_pair(q + 2, bA);
+          compute((q + 1) / n2, (q + 1) % n2, bB);
+        }
+      }
+    };
+    if constexpr (NH <= 2) {
+      run_pairs(std::integral_constant<bool, true>{});
+    } else {
+      if (wide && vec)
+        run_pairs(std::integral_constant<bool, true>{});
+      else
+        run_pairs(std::integral_constant<bool, false>{});
+    }
+
+    if constexpr (NH <= 2) {
+      // Every stage of the staging rings is idle here: each wave stores its
+      // mode-3 rows of the group in its own ring, and the workgroup adds the
+      // waves in order (one barrier round instead of one per wave; the sums
+      // are the same, in the same order).
+      constexpr int SF = stage_floats(NH);
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ring_w[(NU * n + u) * RT + jt[t]] = g3[u][t];
+      __syncthreads();
+      for (int idx = tid; idx < SW * RT; idx += kThreads) {
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) sum += ring[w * kStages * SF + idx];
+        const int l = idx / RT, j = idx - (idx / RT) * RT;
+        if (c0 + l < I3 && j < R) a.G3p[((size_t)wgi * I3 + c0 + l) * R + j] = sum;
+      }
+      __syncthreads();
+      // the rows may have covered stage 0's factor columns, which must stay
+      // zero past R
+      if constexpr (SW * RT > 512 * NH) ring_w[512 * NH + lane] = 0.f;
+    } else {
+      // combine the waves' mode-3 rows of this group in wave order
+      for (int idx = tid; idx < SW * (RT + 1); idx += kThreads) (&g3x[0][0])[idx] = 0.f;
+      __syncthreads();
+      for (int w = 0; w < kWaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+          for (int u = 0; u < NU; ++u)
+            if (vu[u])
+#pragma unroll
+              for (int t = 0; t < NT; ++t) g3x[i3u[u] - c0][jt[t]] += g3[u][t];
+        }
+        __syncthreads();
+      }
+      for (int idx = tid; idx < SW * RT; idx += kThreads) {
+        const int l = idx / RT, j = idx - (idx / RT) * RT;
+        if (c0 + l < I3 && j < R) a.G3p[((size_t)wgi * I3 + c0 + l) * R + j] = g3x[l][j];
+      }
+      __syncthreads();
+    }
+  }
+
+  // mode-1/2 partial rows of this wave's block
+  if (active) {
+    for (int idx = lane; idx < kTB * RT; idx += 64) {
+      const int l = idx / RT, j = idx - (idx / RT) * RT;
+      if (j < R) {
+        if (l < n1) a.G1p[((size_t)b2 * I1 + i10 + l) * R + j] = g1w[wave][l][j];
+        if (l < n2) a.G2p[((size_t)b1 * I2 + i20 + l) * R + j] = g2w[wave][l][j];
+      }
+    }
+  }
+  // temporal-weight gradient and objective partials of the workgroup
+  {
+    float gv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) gv[t] = gsacc[t];
+    // sum over the 16 lanes of the row, then over the 4 rows
+    const float v = row_reduce_scatter<NT>(gv, n);
+    float vs = v;
+    if ((n & ((16 / NT) - 1)) == 0) {
+      const int tt = n >> (4 - LOGNT);
+      gsx[wave][16 * (tt >> 2) + 4 * g + (tt & 3)] = vs;
+    }
+    float ls = lacc.s;
+    for (int m = 32; m >= 1; m >>= 1) ls += __shfl_xor(ls, m);
+    if (lane == 0) lsx[wave] = ls;
+  }
+  __syncthreads();
+  if (tid < R) {
+    float s = 0.f;
+    for (int w = 0; w < kWaves; ++w) s += gsx[w][tid];
+    a.gsp[(size_t)wgi * R + tid] = s;
+  }
+  if (tid == 0) {
+    float s = 0.f;
+    for (int w = 0; w < kWaves; ++w) s += lsx[w];
+    a.lossp[wgi] = s;
+  }
+}
+
+template <int LOSS, int RT, int NH, bool DMA16, int NK>
+__device__ __forceinline__ void fused_body(const MArgs& a) {
+  __shared__ float g1s[kWaves * kTB * RT];
+  __shared__ float g2s[kWaves * kTB * RT];
+  __shared__ float sm[lds_floats(RT, NH)];
+  // the staging ring is an LDS object of its own: the direct-to-LDS copies
+  // write only this array
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
+  __shared__ float cl[kMaxNs];
+  for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
+  __syncthreads();
+  mfma_tile<LOSS, RT, NH, DMA16, NK>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl);
+}
+
+template <int LOSS, int RT, int NH, bool DMA16, int NK>
+__global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
+  fused_body<LOSS, RT, NH, DMA16, NK>(a);
+}
+
+// Rank tile 16 with one h-tile: the LDS of two workgroups fits a compute
+// unit, so the register budget is held to 128 (four waves per SIMD); the
+// few values that do not fit are spilled outside the pair loop.
+template <int LOSS, bool DMA16, int NK>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+fused_dense_mfma_r16(MArgs a) {
+  fused_body<LOSS, 16, 1, DMA16, NK>(a);
+}
+
+
+// One variant's share of the work list: items [begin, end), taken in order
+// from the variant's own counter.
+template <int LOSS, int RT, int NH, bool DMA16>
+__device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ desc,
+                                                const BatchState* __restrict__ state,
+                                                const int2* __restrict__ items, int begin, int end,
+                                                int* __restrict__ counter, int want) {
+  __shared__ float g1s[kWaves * kTB * RT];
+  __shared__ float g2s[kWaves * kTB * RT];
+  __shared__ float sm[lds_floats(RT, NH)];
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
+  __shared__ float cl[kMaxNs];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = begin + atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
+    if (it >= end) break;
+    const int si = items[it].x, wg = items[it].y;
+    const BatchDesc& d = desc[si];
+    const BatchState& s = state[si];
+    TileArgs ta;
+    ta.Xt = d.Xt;
+    ta.ring = d.ring;
+    ta.rstride = (size_t)d.rstride;
+    ta.rp3 = (size_t)d.rp3;
+    ta.st = d.st;
+    ta.shist = d.shist;
+    ta.A1 = d.A;
+    ta.A2 = d.A + d.fac_off1;
+    ta.A3 = d.A + d.fac_off2;
+    ta.G1p = d.G1p;
+    ta.G2p = d.G2p;
+    ta.G3p = d.G3p;
+    ta.gsp = d.gsp;
+    ta.lossp = d.lossp;
+    ta.I1 = d.I1; ta.I2 = d.I2; ta.I3 = d.I3; ta.R = d.R;
+    ta.ns = 1 + s.nwin;
+    ta.want = want;
+    ta.tb1 = d.tb1; ta.tb2 = d.tb2; ta.nb2 = d.nb2; ta.nblocks = d.nblocks;
+    for (int h = threadIdx.x; h < kMaxNs; h += kThreads) {
+      float v = 0.f;
+      if (h == 0) v = 1.f;
+      else if (h < ta.ns) v = (float)(d.w * pow(d.theta, (double)(s.t - s.slot_t[h - 1])));
+      cl[h] = v;
+    }
+    __syncthreads();
+    mfma_tile<LOSS, RT, NH, DMA16>(ta, wg, g1s, g2s, sm, ring, cl);
+    __syncthreads();
+  }
+}
+
+template <int LOSS, int RT, int NH, bool DMA16>
+__global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
+                                                              const BatchState* __restrict__ state,
+                                                              const int2* __restrict__ items, int begin, int end,
+                                                              int* __restrict__ counter, int want) {
+  batch_grad_body<LOSS, RT, NH, DMA16>(desc, state, items, begin, end, counter, want);
+}
+
+// Rank tile 16, one h-tile: four waves per SIMD, as fused_dense_mfma_r16.
+template <int LOSS, bool DMA16>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+batch_grad_kernel_r16(const BatchDesc* __restrict__ desc, const BatchState* __restrict__ state,
+                      const int2* __restrict__ items, int begin, int end, int* __restrict__ counter, int want) {
+  batch_grad_body<LOSS, 16, 1, DMA16>(desc, state, items, begin, end, counter, want);
+}
+
+template <int LOSS, int RT, int NH>
+hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p, float* gsp,
+                  float* lossp) {
+  MArgs m;
+  TileArgs& a = m.t;
+  for (int h = 0; h < kMaxNs; ++h) m.c[h] = h < c.ns ? (float)c.c[h] : 0.f;
+  a.Xt = static_cast<const float*>(c.X[0]);
+  a.ring = static_cast<const float*>(c.ring);
+  a.rstride = c.ring_stride;
+  a.rp3 = c.ring_pitch;
+  a.st = static_cast<const float*>(c.S[0]);
+  a.shist = static_cast<const float*>(c.shist);
+  a.A1 = static_cast<const float*>(c.A[0]);
+  a.A2 = static_cast<const float*>(c.A[1]);
+  a.A3 = static_cast<const float*>(c.A[2]);
+  a.G1p = G1p;
+  a.G2p = G2p;
+  a.G3p = G3p;
+  a.gsp = gsp;
+  a.lossp = lossp;
+  a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
+  a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
+  // 16-byte slice-row copies need 16-byte aligned rows: I3 a multiple of 4;
+  // nk: registers of the last h-tile that hold slices of the window
+  const bool dma16 = (c.I3 % 4) == 0;
+  const int nk = (c.ns - 16 * (NH - 1) + 3) / 4;
+  auto go = [&](auto nkc) {
+    constexpr int K = decltype(nkc)::value;
+    if constexpr (NH > 2) {
+      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, 0>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+    } else if constexpr (RT == 16 && NH == 1) {
+      if (dma16)
+        hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, true, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+      else
+        hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+    } else {
+      if (dma16)
+        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, true, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+      else
+        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+    }
+  };
+  if constexpr (NH > 2) {
+    go(std::integral_constant<int, 0>{});
+  } else {
+    switch (nk) {
+      case 1: go(std::integral_constant<int, 1>{}); break;
+      case 2: go(std::integral_constant<int, 2>{}); break;
+      case 3: go(std::integral_constant<int, 3>{}); break;
+      default: go(std::integral_constant<int, 4>{}); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int LOSS, int RT>
+hipError_t by_nh(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p, float* gsp,
+                 float* lossp) {
+  if (c.ns <= 16) return launch<LOSS, RT, 1>(c, p, G1p, G2p, G3p, gsp, lossp);
+  if (c.ns <= 32) return launch<LOSS, RT, 2>(c, p, G1p, G2p, G3p, gsp, lossp);
+  if (c.ns <= 48) return launch<LOSS, RT, 3>(c, p, G1p, G2p, G3p, gsp, lossp);
+  return launch<LOSS, RT, 4>(c, p, G1p, G2p, G3p, gsp, lossp);
+}
+
+template <int LOSS>
+hipError_t by_rank(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p, float* gsp,
+                   float* lossp) {
+  if (c.R <= 16) return by_nh<LOSS, 16>(c, p, G1p, G2p, G3p, gsp, lossp);
+  return by_nh<LOSS, 32>(c, p, G1p, G2p, G3p, gsp, lossp);
+}
+
+
+
+template <int LOSS, int RT, int NH, bool DMA16>
+void launch_batch_variant(const BatchRun& b, int v, int want) {
+  const dim3 grid((unsigned)b.vgrid[v]);
+  if constexpr (RT == 16 && NH == 1)
+    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS, DMA16>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+                       b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
+  else
+    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH, DMA16>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+                       b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
+}
+
+// variant v = loss * 8 + (R > 16) * 4 + (two h-tiles) * 2 + (I3 % 4 == 0)
+template <int LOSS>
+void launch_batch_loss(const BatchRun& b, int v, int want) {
+  switch (v & 7) {
+    case 0: launch_batch_variant<LOSS, 16, 1, false>(b, v, want); break;
+    case 1: launch_batch_variant<LOSS, 16, 1, true>(b, v, want); break;
+    case 2: launch_batch_variant<LOSS, 16, 2, false>(b, v, want); break;
+    case 3: launch_batch_variant<LOSS, 16, 2, true>(b, v, want); break;
+    case 4: launch_batch_variant<LOSS, 32, 1, false>(b, v, want); break;
+    case 5: launch_batch_variant<LOSS, 32, 1, true>(b, v, want); break;
+    case 6: launch_batch_variant<LOSS, 32, 2, false>(b, v, want); break;
+    default: launch_batch_variant<LOSS, 32, 2, true>(b, v, want); break;
+  }
+}
+
+}  // namespace
+}  // namespace gcp
