@@ -65,6 +65,13 @@ def copy_probe(mib: int):
     return 0
 
 
+# Sources of the C2 matrix-core kernel; the committed counter summary carries
+# their sha256 and its traffic figure is used only while they are unchanged.
+C2_KERNEL_SOURCES = ["paper_2110_14514_amd/csrc/mfma_tile.hpp",
+                     "paper_2110_14514_amd/csrc/dense_mfma_poisson.hip",
+                     "paper_2110_14514_amd/csrc/common.hpp"]
+
+
 def _profiled_traffic(summary: str, sources):
     """HBM bytes per launch of the dominant kernel from a committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated with a copy of known
@@ -333,9 +340,7 @@ def main():
                "sample": "one full objective+gradient evaluation of the same 200^3 x 11-slice "
                          "workload (FP64 NumPy oracle, BLAS threads as listed)"}
 
-    traffic = _profiled_traffic("fused_dense_c2.txt",
-                                ["paper_2110_14514_amd/csrc/dense_mfma.hip",
-                                 "paper_2110_14514_amd/csrc/common.hpp"])
+    traffic = _profiled_traffic("fused_dense_c2.txt", C2_KERNEL_SOURCES)
     res = {
         "metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
         "value": 1e3 / ms_per_step,

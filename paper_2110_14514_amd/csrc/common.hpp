@@ -206,9 +206,14 @@ struct BatchState {                // per stream, advanced on the device
   int pending_slot;
   int64_t slot_t[kMaxNs];
 };
+// Slice rows are copied to LDS 16 bytes at a time when they are 16-byte
+// aligned and their byte pitch fits 32 bits (the copy address is one
+// 32 x 32 -> 64-bit multiply-add), else 4 bytes at a time.
+inline bool dma16_ok(int I3) { return I3 % 4 == 0 && I3 < (1 << 29); }
+
 // Variants of the batched tile code: loss x (rank tile 16/32) x (one/two
 // h-tiles) x (16- or 4-byte slice-row copies), index
-// loss * 8 + (R > 16) * 4 + (window + 1 > 16) * 2 + (I3 % 4 == 0).
+// loss * 8 + (R > 16) * 4 + (window + 1 > 16) * 2 + dma16_ok(I3).
 constexpr int kBatchVariants = 24;
 
 struct BatchRun {

@@ -287,65 +287,90 @@ struct ReduceArgs {
 };
 
 // Sums the partial slots of every output in a fixed order and adds the
-// regularisation gradients; the last workgroup forms the objective.  One
-// wave per output element: lane l sums slots l, l+64, ... (Kahan), then the
-// 64 lane sums are combined by a fixed butterfly, so the result does not
-// depend on scheduling.
-template <typename T>
-__device__ __forceinline__ T wave_sum_fixed(T v) {
-  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-  return v;
+// regularisation gradients; the last workgroup forms the objective.  A
+// workgroup takes 16 consecutive outputs of one kind (G1, G2, G3 or g_s) and
+// splits their slots into 16 fixed chunks: thread (chunk c, output o) sums
+// chunk c of output o in slot order (Kahan), with consecutive threads on
+// consecutive outputs so that every load is a contiguous row segment; the 16
+// chunk sums of an output are then added in chunk order.  Nothing depends
+// on scheduling, so results are bitwise reproducible.
+constexpr int kRedOut = 16;     // outputs per workgroup
+constexpr int kRedChunks = 16;  // slot chunks per output
+constexpr int kRedUnroll = 8;   // loads in flight per thread
+
+// k += f(p[i]) for i = begin, begin + step, ... < end, in that order; the
+// loads of kRedUnroll consecutive terms are issued before their additions.
+template <typename T, typename F>
+__device__ __forceinline__ void kahan_strided(Kahan<T>& k, const T* p, size_t begin, size_t end, size_t step,
+                                              F f) {
+  for (size_t i = begin; i < end; i += kRedUnroll * step) {
+    T v[kRedUnroll];
+#pragma unroll
+    for (int u = 0; u < kRedUnroll; ++u) {
+      const size_t j = i + u * step;
+      v[u] = j < end ? p[j] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kRedUnroll; ++u)
+      if (i + u * step < end) k.add(f(v[u]));
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
   const int R = r.R;
-  const int lane = threadIdx.x & 63;
   if ((int)blockIdx.x < r.gblocks) {
+    __shared__ T part[kRedChunks][kRedOut];
     const int n1 = r.I1 * R, n2 = r.I2 * R, n3 = r.I3 * R;
-    const int total = n1 + n2 + n3 + R;
-    const T sc = r.gscale ? r.gscale[0] : T(1);
-    const int wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (int idx = wave0; idx < total; idx += r.gblocks * 4) {
-      const T* src;
-      size_t stride;
-      int slots;
-      T reg;
-      T* dst;
-      if (idx < n1) {
-        src = r.G1p + idx; stride = n1; slots = r.nb2; reg = r.lam * r.A1[idx]; dst = r.G1 + idx;
-      } else if (idx < n1 + n2) {
-        const int e = idx - n1;
-        src = r.G2p + e; stride = n2; slots = r.nb1; reg = r.lam * r.A2[e]; dst = r.G2 + e;
-      } else if (idx < n1 + n2 + n3) {
-        const int e = idx - n1 - n2;
-        src = r.G3p + e; stride = n3; slots = r.ntiles; reg = r.lam * r.A3[e]; dst = r.G3 + e;
-      } else {
-        const int j = idx - n1 - n2 - n3;
-        src = r.gsp + j; stride = R; slots = r.ntiles; reg = r.mu * r.st[j]; dst = r.gs + j;
-      }
-      Kahan<T> k;
-      for (int b = lane; b < slots; b += 64) k.add(src[(size_t)b * stride]);
-      const T sum = wave_sum_fixed(k.s);
-      if (lane == 0) {
-        const T out = sc * (sum + reg);
-        *dst = out;
-        if (!isfinite(out)) atomicOr(r.status, (int)kStatusNonFinite);
-      }
+    const int b1 = (n1 + kRedOut - 1) / kRedOut, b2 = (n2 + kRedOut - 1) / kRedOut;
+    const int b3 = (n3 + kRedOut - 1) / kRedOut;
+    int blk = blockIdx.x;
+    const T* src;
+    const T* A;
+    size_t stride;
+    int slots, nout;
+    T* dst;
+    T lam = r.lam;
+    if (blk < b1) {
+      src = r.G1p; stride = n1; slots = r.nb2; nout = n1; A = r.A1; dst = r.G1;
+    } else if ((blk -= b1) < b2) {
+      src = r.G2p; stride = n2; slots = r.nb1; nout = n2; A = r.A2; dst = r.G2;
+    } else if ((blk -= b2) < b3) {
+      src = r.G3p; stride = n3; slots = r.ntiles; nout = n3; A = r.A3; dst = r.G3;
+    } else {
+      blk -= b3;
+      src = r.gsp; stride = R; slots = r.ntiles; nout = R; A = r.st; dst = r.gs; lam = r.mu;
+    }
+    const int ol = threadIdx.x % kRedOut, c = threadIdx.x / kRedOut;
+    const int o = blk * kRedOut + ol;
+    const int s0 = (int)((long)slots * c / kRedChunks), s1 = (int)((long)slots * (c + 1) / kRedChunks);
+    Kahan<T> k;
+    if (o < nout) kahan_strided(k, src + o, (size_t)s0 * stride, (size_t)s1 * stride, stride, [](T v) { return v; });
+    part[c][ol] = k.s;
+    __syncthreads();
+    if (c == 0 && o < nout) {
+      Kahan<T> t;
+#pragma unroll
+      for (int cc = 0; cc < kRedChunks; ++cc) t.add(part[cc][ol]);
+      const T sc = r.gscale ? r.gscale[0] : T(1);
+      const T out = sc * (t.s + lam * A[o]);
+      dst[o] = out;
+      if (!isfinite(out)) atomicOr(r.status, (int)kStatusNonFinite);
     }
     return;
   }
   // objective: data partials + lambda/2 sum ||A||^2 + mu/2 ||s||^2
   __shared__ T red[256];
+  const auto id = [](T v) { return v; };
+  const auto sq = [](T v) { return v * v; };
   Kahan<T> k;
-  for (int b = threadIdx.x; b < r.ntiles; b += 256) k.add(r.lossp[b]);
+  kahan_strided(k, r.lossp, threadIdx.x, r.ntiles, 256, id);
   Kahan<T> kr;
-  const T* mats[3] = {r.A1, r.A2, r.A3};
-  const int rows[3] = {r.I1, r.I2, r.I3};
-  for (int m = 0; m < 3; ++m)
-    for (int e = threadIdx.x; e < rows[m] * R; e += 256) kr.add(mats[m][e] * mats[m][e]);
+  kahan_strided(kr, r.A1, threadIdx.x, (size_t)r.I1 * R, 256, sq);
+  kahan_strided(kr, r.A2, threadIdx.x, (size_t)r.I2 * R, 256, sq);
+  kahan_strided(kr, r.A3, threadIdx.x, (size_t)r.I3 * R, 256, sq);
   Kahan<T> ks;
-  for (int j = threadIdx.x; j < R; j += 256) ks.add(r.st[j] * r.st[j]);
+  kahan_strided(ks, r.st, threadIdx.x, R, 256, sq);
   red[threadIdx.x] = k.s + T(0.5) * r.lam * kr.s + T(0.5) * r.mu * ks.s;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
@@ -381,8 +406,8 @@ hipError_t launch_reduce(const DenseCall& c, const PartLayout& pl) {
   r.I1 = c.I1; r.I2 = c.I2; r.I3 = c.I3; r.R = c.R;
   r.nb1 = pl.s2; r.nb2 = pl.s1; r.ntiles = pl.s3; r.want = c.want;
   r.status = c.status;
-  const int total = (c.I1 + c.I2 + c.I3 + 1) * c.R;
-  r.gblocks = (c.want & kWantGrad) ? std::min(2048, (total + 3) / 4) : 0;
+  auto nblk = [](int n) { return (n + kRedOut - 1) / kRedOut; };
+  r.gblocks = (c.want & kWantGrad) ? nblk(c.I1 * c.R) + nblk(c.I2 * c.R) + nblk(c.I3 * c.R) + nblk(c.R) : 0;
   const int blocks = r.gblocks + ((c.want & kWantLoss) ? 1 : 0);
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL((fused_reduce<T>), dim3(blocks), dim3(256), 0, c.stream, r);

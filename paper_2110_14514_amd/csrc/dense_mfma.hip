@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) batch_window_copy(const BatchDesc* __rest
 }  // namespace
 
 int batch_variant(int loss, int R, int H, int I3) {
-  return loss * 8 + (R > 16 ? 4 : 0) + (H + 1 > 16 ? 2 : 0) + (I3 % 4 == 0 ? 1 : 0);
+  return loss * 8 + (R > 16 ? 4 : 0) + (H + 1 > 16 ? 2 : 0) + (dma16_ok(I3) ? 1 : 0);
 }
 
 bool batch_variant_r16(int v) { return (v & 6) == 0; }

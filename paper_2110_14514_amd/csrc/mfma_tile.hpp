@@ -250,6 +250,55 @@ __device__ __forceinline__ float row_reduce_scatter_dpp(float (&v)[NT], int n) {
   }
 }
 
+// Loss terms in the form the matrix-core kernel evaluates them.  GEMM1's
+// operand carries kM, so it returns d = kM m (kM = log2 e for the exponential
+// losses: exp(m) is then a single exp2); GEMM2's operand and the temporal
+// gradient carry kY (2 for the Gaussian loss, whose y = 2 (m - x)), so the
+// per-entry derivative formed here is y / kY; and the objective terms formed
+// here are f / kF, the lane sums being scaled by kF once at the end.  fy adds
+// cv f / kF to facc and returns y / kY.
+template <int LOSS>
+struct MLoss;
+
+template <>
+struct MLoss<kGaussian> {
+  static constexpr float kM = 1.f, kY = 2.f, kF = 1.f;
+  __device__ __forceinline__ static float y(float x, float d) { return d - x; }
+  __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
+    const float yv = d - x;
+    facc = fmaf(cv * yv, yv, facc);   // (m - x)^2
+    return yv;
+  }
+};
+
+template <>
+struct MLoss<kPoissonLog> {
+  static constexpr float kM = 1.44269504088896341f, kY = 1.f, kF = 0.693147180559945309f;
+  __device__ __forceinline__ static float y(float x, float d) { return __builtin_amdgcn_exp2f(d) - x; }
+  __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
+    const float e = __builtin_amdgcn_exp2f(d);
+    facc = fmaf(cv, fmaf(-x, d, e * kM), facc);   // (exp(m) - x m) / ln 2
+    return e - x;
+  }
+};
+
+template <>
+struct MLoss<kBernoulliLogit> {
+  static constexpr float kM = 1.44269504088896341f, kY = 1.f, kF = 0.693147180559945309f;
+  __device__ __forceinline__ static float y(float x, float d) {
+    const float e = __builtin_amdgcn_exp2f(-fabsf(d));
+    const float inv = __builtin_amdgcn_rcpf(1.f + e);
+    return (d >= 0.f ? inv : e * inv) - x;
+  }
+  __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
+    const float e = __builtin_amdgcn_exp2f(-fabsf(d));
+    const float inv = __builtin_amdgcn_rcpf(1.f + e);
+    // (max(m, 0) + log(1 + exp(-|m|)) - x m) / ln 2
+    facc = fmaf(cv, fmaf(-x, d, fmaxf(d, 0.f) + __builtin_amdgcn_logf(1.f + e)), facc);
+    return (d >= 0.f ? inv : e * inv) - x;
+  }
+};
+
 // One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
 // slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
 // Registers / GEMM2 K-steps of the last h-tile that hold slices of the window
@@ -331,7 +380,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
   for (int ht = 0; ht < NH; ++ht) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) A1op[ht][t] = sval(16 * ht + 4 * (n & 3) + (n >> 2), jt[t]);
+    for (int t = 0; t < NT; ++t) A1op[ht][t] = MLoss<LOSS>::kM * sval(16 * ht + 4 * (n & 3) + (n >> 2), jt[t]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int h = 16 * ht + 4 * r + g;
@@ -346,7 +395,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int h = 16 * ht + 4 * t + g;
-        A2op[mt][ht][t] = (h < ns ? cl[h] : 0.f) * sval(h, 16 * mt + n);
+        A2op[mt][ht][t] = MLoss<LOSS>::kY * (h < ns ? cl[h] : 0.f) * sval(h, 16 * mt + n);
       }
   }
 
@@ -463,7 +512,17 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         for (int t = 0; t < NT; ++t) W[t] = NH <= 2 ? b.a1[t] * b.a2[t] : b.a1[t] * b.a2[t] * jm[t];
         const float a1s = NH <= 2 ? b.a1s : b.a1s * jsm, a2s = NH <= 2 ? b.a2s : b.a2s * jsm;
 
-        // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile)
+        // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile).
+        // The pair's weights W multiply whichever operand has fewer values
+        // per lane (the weight rows with one h-tile, else the entries).
+        constexpr bool kWA = NH < NU;
+        float Aw[kWA ? NH : 1][NT];
+        if constexpr (kWA) {
+#pragma unroll
+          for (int ht = 0; ht < NH; ++ht)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) Aw[ht][t] = A1op[ht][t] * W[t];
+        }
         f4 D1[NH][NU];
 #pragma unroll
         for (int ht = 0; ht < NH; ++ht)
@@ -472,34 +531,42 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             f4 acc = {0.f, 0.f, 0.f, 0.f};
             if (VEC || u < nu) {
 #pragma unroll
-              for (int t = 0; t < NT; ++t) acc = mfma(A1op[ht][t], W[t] * a3r[u][t], acc);
+              for (int t = 0; t < NT; ++t) {
+                if constexpr (kWA)
+                  acc = mfma(Aw[ht][t], a3r[u][t], acc);
+                else
+                  acc = mfma(A1op[ht][t], W[t] * a3r[u][t], acc);
+              }
             }
             D1[ht][u] = acc;
           }
 
         // loss derivative in place, and the objective terms of the group
-        // (cv = 0 marks padded slices) summed plainly and added to the lane's
-        // running sum with compensation.  Entries past the end of a row
-        // (tail lanes) need no mask in y: their A3 values are zero, so every
-        // product that uses them vanishes and their mode-3 rows are never
-        // written.
+        // weighted by c_h, summed per entry tile and added to the lane's
+        // running sum with compensation.  Padded slices (c_h = 0) have zero
+        // weight rows, so d = 0 and a finite x give finite terms that the
+        // zero weight removes.  Entries past the end of a row (tail lanes)
+        // need no mask in y: their A3 values are zero, so every product that
+        // uses them vanishes and their mode-3 rows are never written; their
+        // objective terms are dropped per entry tile.
         // Registers holding only slices past the window are left as they
         // are: GEMM2 skips their K-steps.
         if (want_loss) {
-          float part = 0.f;
+          float fu[NU];
+#pragma unroll
+          for (int u = 0; u < NU; ++u) fu[u] = 0.f;
 #pragma unroll
           for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               if (!reg_active<NK, NH>(ht, r, ns)) continue;
 #pragma unroll
-              for (int u = 0; u < NU; ++u) {
-                float fv, yv;
-                LossFast<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], fv, yv);
-                part += (vu[u] && cv[ht][r] != 0.f) ? cv[ht][r] * fv : 0.f;
-                D1[ht][u][r] = yv;
-              }
+              for (int u = 0; u < NU; ++u)
+                D1[ht][u][r] = MLoss<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], cv[ht][r], fu[u]);
             }
+          float part = 0.f;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) part += vu[u] ? fu[u] : 0.f;
           lacc.add(part);
         } else {
 #pragma unroll
@@ -508,7 +575,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             for (int r = 0; r < 4; ++r) {
               if (!reg_active<NK, NH>(ht, r, ns)) continue;
 #pragma unroll
-              for (int u = 0; u < NU; ++u) D1[ht][u][r] = LossFast<LOSS>::y(b.x[ht][r][u], D1[ht][u][r]);
+              for (int u = 0; u < NU; ++u) D1[ht][u][r] = MLoss<LOSS>::y(b.x[ht][r][u], D1[ht][u][r]);
             }
         }
 
@@ -578,14 +645,16 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         auto row_src = [&](int h) -> const float* {
           return (h == 0 || h >= ns) ? a.Xt + eoff : a.ring + (size_t)(h - 1) * a.rstride + eoff;
         };
-        const float* src16[DMA16 ? KX : 1];
-        unsigned pit16[DMA16 ? KX : 1];
+        // 16-byte copies: the lane's address is base + pair x pitch (bytes),
+        // a single 32 x 32 -> 64-bit multiply-add per copy (pair < 2^32)
+        uint64_t src16[DMA16 ? KX : 1];
+        uint32_t pit16[DMA16 ? KX : 1];
         if constexpr (DMA16) {
 #pragma unroll
           for (int k = 0; k < KX; ++k) {
             const int h = 8 * k + hsub;
-            src16[k] = row_src(h);
-            pit16[k] = (h >= 1 && h < ns) ? (unsigned)a.rp3 : (unsigned)I3;
+            src16[k] = reinterpret_cast<uint64_t>(row_src(h));
+            pit16[k] = 4u * ((h >= 1 && h < ns) ? (uint32_t)a.rp3 : (uint32_t)I3);
           }
         }
         // 4-byte copies: rows 2k + hsub; base pointers for hsub = 0 / 1 of
@@ -598,8 +667,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           const size_t pair = (size_t)(i10 + pi1) * I2 + (i20 + pi2);
           float* stg = ring_w + st * stage_floats(NH);
           if constexpr (DMA16) {
+            const uint32_t p32 = (uint32_t)pair;
 #pragma unroll
-            for (int k = 0; k < KX; ++k) load_to_lds(src16[k] + pair * pit16[k], stg + 256 * k, 16);
+            for (int k = 0; k < KX; ++k)
+              load_to_lds(reinterpret_cast<const float*>((uint64_t)p32 * pit16[k] + src16[k]), stg + 256 * k, 16);
           } else {
             const size_t rowx = pair * I3, rowr = pair * a.rp3;
 #pragma unroll
@@ -625,10 +696,12 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         if (npairs > 0) issue(0);
         if (npairs > 1) issue(1);
         int ci1 = 0, ci2 = 0;
-        for (int q = 0; q < npairs; ++q) {
-          const int st = q % kStages;
+        // pair q uses stage q % kStages; the loop is unrolled by kStages so
+        // that every stage offset is a constant of the LDS instructions
+        auto step = [&](auto stage_tag, int q) {
+          constexpr int st = decltype(stage_tag)::value;
           if (q + 2 < npairs) {
-            issue((q + 2) % kStages);
+            issue((st + 2) % kStages);
             wait_vmcnt(2 * K);
           } else if (q + 1 < npairs) {
             wait_vmcnt(K);
@@ -665,6 +738,14 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             ci2 = 0;
             ++ci1;
           }
+        };
+        static_assert(kStages == 3, "the pair loop is unrolled by three");
+        for (int q = 0; q < npairs; q += kStages) {
+          step(std::integral_constant<int, 0>{}, q);
+          if (q + 1 >= npairs) break;
+          step(std::integral_constant<int, 1>{}, q + 1);
+          if (q + 2 >= npairs) break;
+          step(std::integral_constant<int, 2>{}, q + 2);
         }
       } else {
         // ping-pong: the buffer being computed was filled one step earlier
@@ -746,7 +827,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   {
     float gv[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) gv[t] = gsacc[t];
+    for (int t = 0; t < NT; ++t) gv[t] = MLoss<LOSS>::kY * gsacc[t];
     // sum over the 16 lanes of the row, then over the 4 rows
     const float v = row_reduce_scatter<NT>(gv, n);
     float vs = v;
@@ -754,7 +835,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       const int tt = n >> (4 - LOGNT);
       gsx[wave][16 * (tt >> 2) + 4 * g + (tt & 3)] = vs;
     }
-    float ls = lacc.s;
+    float ls = MLoss<LOSS>::kF * lacc.s;
     for (int m = 32; m >= 1; m >>= 1) ls += __shfl_xor(ls, m);
     if (lane == 0) lsx[wave] = ls;
   }
@@ -893,7 +974,7 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
   // 16-byte slice-row copies need 16-byte aligned rows: I3 a multiple of 4;
   // nk: registers of the last h-tile that hold slices of the window
-  const bool dma16 = (c.I3 % 4) == 0;
+  const bool dma16 = dma16_ok(c.I3);
   const int nk = (c.ns - 16 * (NH - 1) + 3) / 4;
   auto go = [&](auto nkc) {
     constexpr int K = decltype(nkc)::value;
@@ -953,7 +1034,7 @@ void launch_batch_variant(const BatchRun& b, int v, int want) {
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
 }
 
-// variant v = loss * 8 + (R > 16) * 4 + (two h-tiles) * 2 + (I3 % 4 == 0)
+// variant v = loss * 8 + (R > 16) * 4 + (two h-tiles) * 2 + dma16_ok(I3)
 template <int LOSS>
 void launch_batch_loss(const BatchRun& b, int v, int want) {
   switch (v & 7) {
