@@ -435,8 +435,11 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     const int c0 = SW * sc;
     const int nu = wide ? NU : (tail + 15) >> 4;
     // entries held by this lane: NU adjacent ones in a full group (and in
-    // every group of the staged path), else one per 16-entry tile
-    const bool adj = wide || NH <= 2;
+    // every group of the staged path but a tail of at most 16 entries), else
+    // one per 16-entry tile.  A staged tail of at most 16 entries is
+    // computed with one tile only (HALF below).
+    const bool half = NH <= 2 && !wide && tail <= 16;
+    const bool adj = (wide || NH <= 2) && !half;
     int i3u[NU];
     bool vu[NU];
 #pragma unroll
@@ -462,8 +465,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     // forces an early wait on them, and the compute part issues none.
     // VEC: a full group of rows whose start is NU-aligned (one NU-wide load
     // per lane and slice); otherwise per-entry loads.
-    auto run_pairs = [&](auto vec_tag) {
+    auto run_pairs = [&](auto vec_tag, auto half_tag) {
       constexpr bool VEC = decltype(vec_tag)::value;
+      constexpr bool HALF = decltype(half_tag)::value;   // one 16-entry tile (staged tail)
+      constexpr int NUA = HALF ? 1 : NU;                  // tiles computed
       // Prefetch buffers hold raw loaded values only: any arithmetic on them
       // at load time would force a wait for the loads.
       struct Buf {
@@ -527,7 +532,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
         for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
-          for (int u = 0; u < NU; ++u) {
+          for (int u = 0; u < NUA; ++u) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
             if (VEC || u < nu) {
 #pragma unroll
@@ -554,19 +559,19 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         if (want_loss) {
           float fu[NU];
 #pragma unroll
-          for (int u = 0; u < NU; ++u) fu[u] = 0.f;
+          for (int u = 0; u < NUA; ++u) fu[u] = 0.f;
 #pragma unroll
           for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               if (!reg_active<NK, NH>(ht, r, ns)) continue;
 #pragma unroll
-              for (int u = 0; u < NU; ++u)
+              for (int u = 0; u < NUA; ++u)
                 D1[ht][u][r] = MLoss<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], cv[ht][r], fu[u]);
             }
           float part = 0.f;
 #pragma unroll
-          for (int u = 0; u < NU; ++u) part += vu[u] ? fu[u] : 0.f;
+          for (int u = 0; u < NUA; ++u) part += vu[u] ? fu[u] : 0.f;
           lacc.add(part);
         } else {
 #pragma unroll
@@ -575,7 +580,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             for (int r = 0; r < 4; ++r) {
               if (!reg_active<NK, NH>(ht, r, ns)) continue;
 #pragma unroll
-              for (int u = 0; u < NU; ++u) D1[ht][u][r] = MLoss<LOSS>::y(b.x[ht][r][u], D1[ht][u][r]);
+              for (int u = 0; u < NUA; ++u) D1[ht][u][r] = MLoss<LOSS>::y(b.x[ht][r][u], D1[ht][u][r]);
             }
         }
 
@@ -585,7 +590,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
           for (int t = 0; t < NT; ++t) ps[t] = 0.f;
 #pragma unroll
-          for (int u = 0; u < NU; ++u) {
+          for (int u = 0; u < NUA; ++u) {
             const float yt = __shfl(D1[0][u][0], n);
 #pragma unroll
             for (int t = 0; t < NT; ++t) ps[t] += yt * a3r[u][t];
@@ -599,7 +604,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
         for (int t = 0; t < NT; ++t) Vp[t] = 0.f;
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
+        for (int u = 0; u < NUA; ++u) {
           if (!VEC && u >= nu) continue;
 #pragma unroll
           for (int mt = 0; mt < NM; ++mt) {
@@ -714,9 +719,14 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const f2 v = *reinterpret_cast<const f2*>(stg + (16 * ht + 4 * r + g) * 32 + 2 * n);
-              b.x[ht][r][0] = v[0];
-              b.x[ht][r][1] = v[1];
+              if constexpr (HALF) {
+                b.x[ht][r][0] = stg[(16 * ht + 4 * r + g) * 32 + n];
+                b.x[ht][r][1] = 0.f;
+              } else {
+                const f2 v = *reinterpret_cast<const f2*>(stg + (16 * ht + 4 * r + g) * 32 + 2 * n);
+                b.x[ht][r][0] = v[0];
+                b.x[ht][r][1] = v[1];
+              }
             }
           // columns t of this lane are 16 (t / 4) + 4 g + t % 4: four
           // contiguous values per 16-column tile (zero past R)
@@ -760,13 +770,18 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         }
       }
     };
+    using True = std::integral_constant<bool, true>;
+    using False = std::integral_constant<bool, false>;
     if constexpr (NH <= 2) {
-      run_pairs(std::integral_constant<bool, true>{});
+      if (half)
+        run_pairs(True{}, True{});
+      else
+        run_pairs(True{}, False{});
     } else {
       if (wide && vec)
-        run_pairs(std::integral_constant<bool, true>{});
+        run_pairs(True{}, False{});
       else
-        run_pairs(std::integral_constant<bool, false>{});
+        run_pairs(False{}, False{});
     }
 
     if constexpr (NH <= 2) {
@@ -778,7 +793,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) ring_w[(NU * n + u) * RT + jt[t]] = g3[u][t];
+        for (int t = 0; t < NT; ++t) ring_w[(i3u[u] - c0) * RT + jt[t]] = g3[u][t];
       __syncthreads();
       for (int idx = tid; idx < SW * RT; idx += kThreads) {
         float sum = 0.f;

@@ -28,6 +28,8 @@ SHAPES = [
     ((6, 5, 200), 16, 20),      # two h-tiles, 3 full 64-wide groups + 8-wide tail
     ((4, 7, 66), 32, 40),       # three h-tiles, I3 not a multiple of 4
     ((3, 4, 128), 20, 60),      # four h-tiles
+    ((9, 10, 48), 16, 4),       # 32-wide group + 16-wide tail (one-tile tail)
+    ((11, 13, 52), 16, 6),      # 32-wide group + 20-wide tail (two-tile tail)
 ]
 
 
