@@ -88,9 +88,14 @@ enum {
 enum {
   GCP_FLAG_PLAIN_SCRATCH = 1, /* reserve the unfused path's scratch (2 slices) */
   GCP_FLAG_KERNEL_VALU = 2,   /* fused path: always the vector-ALU kernel      */
-  GCP_FLAG_KERNEL_MFMA = 4    /* fused path: the matrix-core kernel wherever it
+  GCP_FLAG_KERNEL_MFMA = 4,   /* fused path: the matrix-core kernel wherever it
                                  applies (FP32, R <= 32, window <= 63);
                                  default: chosen by rank                     */
+  GCP_FLAG_SAMPLED_ATOMIC = 8 /* COO gradient: one float atomic per draw, row
+                                 and rank column instead of the row-sorted
+                                 reduction (less workspace, slower; the
+                                 sorted workspace is 64 (H+1)(p+q) bytes plus
+                                 12 (I_1+I_2+I_3) and is reserved by default) */
 };
 
 /* Table 1 (Section 4.2) of the paper, plus layout and sampling controls. */

@@ -30,6 +30,7 @@ WANT_LOSS, WANT_GRAD, IMPL_PLAIN = 1, 2, 256
 FLAG_PLAIN_SCRATCH = 1
 FLAG_KERNEL_VALU = 2
 FLAG_KERNEL_MFMA = 4
+FLAG_SAMPLED_ATOMIC = 8
 
 
 class GcpParams(Structure):

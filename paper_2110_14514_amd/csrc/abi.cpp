@@ -19,7 +19,8 @@
 using namespace gcp;
 
 struct WsLayout {
-  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, total;
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, total;
+  size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
   size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
@@ -80,7 +81,9 @@ gcp_status check_params(const gcp_params* p) {
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_PLAIN_SCRATCH) && p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
   if ((p->flags & GCP_FLAG_KERNEL_VALU) && (p->flags & GCP_FLAG_KERNEL_MFMA)) return GCP_E_ARG;
-  if (p->flags & ~(GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_KERNEL_VALU | GCP_FLAG_KERNEL_MFMA)) return GCP_E_ARG;
+  if (p->flags & ~(GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_KERNEL_VALU | GCP_FLAG_KERNEL_MFMA | GCP_FLAG_SAMPLED_ATOMIC))
+    return GCP_E_ARG;
+  if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
   return GCP_OK;
 }
 
@@ -121,6 +124,10 @@ WsLayout layout_for(const gcp_params* p) {
   // COO: one membership table per window slot and one for the current slice
   L.tab_cap = coo ? table_capacity(p->max_nnz) : 0;
   L.tab = off; off = align_up(off + (size_t)(coo ? p->window + 1 : 0) * L.tab_cap * 8, 256);
+  L.sorted_bytes = (coo && !(p->flags & GCP_FLAG_SAMPLED_ATOMIC))
+                       ? sampled_sorted_bytes(I1, I2, I3, R, p->window, p->p, p->q)
+                       : 0;
+  L.sorted = off; off = align_up(off + L.sorted_bytes, 256);
   L.total = off;
   return L;
 }
@@ -210,6 +217,7 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.p = s->p.p; c.q = s->p.q; c.seed = s->p.seed;
   c.call = s->sample_call++;
   c.status = s->status; c.stream = s->st;
+  if (s->L.sorted_bytes) sampled_sorted_bind(c, s->ws + s->L.sorted, s->p.window);
   return c;
 }
 

@@ -263,7 +263,21 @@ struct SampledCall {
   int* status;
   hipStream_t stream;
   hipEvent_t ev_begin, ev_end;
+  // Row-sorted reduction (null srec: one float atomic per draw, row and
+  // rank column instead).  srec: one 16-byte record per draw slot
+  // (ns x ceil((p+q)/64) x 64); ssrt: three lists of ns (p+q) 16-byte
+  // records; scnt: per mode I_k counts, I_k + 1 row starts and I_k cursors;
+  // sS: ns x R weight rows.
+  void* srec;
+  void* ssrt;
+  int* scnt;
+  float* sS;
 };
+// Workspace bytes of the row-sorted reduction for a stream (0: not used).
+size_t sampled_sorted_bytes(int I1, int I2, int I3, int R, int window, int64_t p, int64_t q);
+// Point c's row-sorted buffers into a workspace of sampled_sorted_bytes bytes
+// (c's sizes, p and q must be set).
+void sampled_sorted_bind(SampledCall& c, char* base, int window);
 // Membership table of a COO slice: capacity for up to max_nnz entries, and
 // the build (fill + insert, two launches on `stream`).
 uint64_t table_capacity(int64_t max_nnz);

@@ -19,12 +19,24 @@
 // current slice): about one cache line per test, where a binary search over
 // the sorted list would fetch a line for most of its log2(nnz) levels.
 //
-// Work decomposition: a wave takes 64 consecutive draws of one slice.
-// Phase 1, one lane per draw: generate the coordinates.  Phase 2, lanes along
+// Work decomposition: a wave takes 4 x 64 consecutive draws of one slice.
+// Phase 1, four draws per lane: generate the coordinates, with the random
+// reads of the four (COO entry, membership-table slot) issued together.
+// Phase 2, lanes along
 // the rank: SEG lanes per draw gather the three factor rows (coalesced row
-// reads), form m with a segmented reduction, and add the per-row
-// contributions with hardware float atomics; the weight gradient and the
+// reads) and form m with a segmented reduction; the weight gradient and the
 // objective are accumulated in registers and flushed once per wave.
+//
+// The MTTKRP rows are then summed in one of two ways.  Row-sorted (default):
+// each draw leaves a record (i1, i2, i3, ytilde) and adds one to the count of
+// its row in every mode; an exclusive scan of the counts gives each row's
+// start; a scatter writes, per mode, the draw's other two indices, its slice
+// and ytilde at the next free place of its row; and a segmented reduction
+// walks each mode's list in runs of consecutive records, SEG lanes per
+// record, keeping the row's sum in registers and adding it to G once per row
+// it meets (a handful of atomics per run instead of one per draw and rank
+// column).  Atomic: phase 2 adds every draw's three rows to G with hardware
+// float atomics (3 R per draw; the L2 atomic rate bounds it).
 #include "common.hpp"
 
 namespace gcp {
@@ -32,6 +44,18 @@ namespace {
 
 constexpr int kMaxAttempts = 64;
 constexpr uint64_t kEmptyKey = ~0ull;   // never a linear index (those are < 2^63)
+
+// Record of a draw (row-sorted reduction), at its draw slot gwave * 64 + lane.
+struct DrawRec {
+  int32_t i1, i2, i3;
+  float y;   // ytilde = c_h weight df/dm (0: the draw adds nothing)
+};
+// Entry of mode k's row-sorted list: the draw's other two indices, its slice
+// and ytilde (the row is implied by the position).
+struct RowRec {
+  int32_t a, b, h;
+  float y;
+};
 
 struct SArgs {
   const uint64_t* tab[kMaxNs];     // membership table of slice h
@@ -53,6 +77,7 @@ struct SArgs {
   float* gs;
   float* loss;
   int* status;
+  DrawRec* rec;                    // row-sorted reduction: draw records
   int I1, I2, I3, R, ns, want;
   int64_t p, q;
   int64_t waves_per_slice;
@@ -104,50 +129,103 @@ __device__ __forceinline__ bool is_stored(const uint64_t* __restrict__ tab, uint
   }
 }
 
-// One-pass variant: phase 1 forms one draw per lane; phase 2 takes the
-// wave's draws SEG lanes (rank columns) at a time and adds their rows of the
-// three MTTKRPs with global atomics.
-template <int LOSS, int SEG>
+// A wave takes kNB x 64 consecutive draws of one slice.  Phase 1 forms kNB
+// draws per lane, issuing the random reads of all of them (COO entry or the
+// first membership-table slot) before resolving any, so that each wave keeps
+// kNB times more of these HBM reads in flight.  Phase 2 takes the draws SEG
+// lanes (rank columns) at a time, forms m, f and ytilde, and either adds the
+// draw's rows of the three MTTKRPs with global atomics (REC = false) or
+// writes the draw's record (REC = true).
+constexpr int kNB = 4;
+
+template <int LOSS, int SEG, bool REC>
 __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t gwave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int h = (int)(gwave / a.waves_per_slice);
   if (h >= a.ns) return;
-  const int64_t first = (gwave - (int64_t)h * a.waves_per_slice) * 64;
+  const int64_t first = (gwave - (int64_t)h * a.waves_per_slice) * (64 * kNB);
   const int64_t total = a.p + a.q;
   const int I1 = a.I1, I2 = a.I2, I3 = a.I3, R = a.R;
   const int32_t* coords = a.coords[h];
   const int64_t nnz = a.nnz[h];
 
-  // phase 1: one draw per lane
-  const int64_t id = first + lane;
-  int i1 = 0, i2 = 0, i3 = 0;
-  float x = 0.f, wgt = 0.f;
-  if (id < total && (nnz > 0 || id >= a.p)) {
-    if (id < a.p) {
+  // phase 1: kNB draws per lane (draw first + 64 b + lane)
+  int i1[kNB], i2[kNB], i3[kNB];
+  float x[kNB], wgt[kNB];
+  int64_t e[kNB];
+  uint64_t key[kNB], pos[kNB], tv[kNB];
+  bool nz[kNB], zd[kNB];
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) {
+    const int64_t id = first + 64 * b + lane;
+    i1[b] = i2[b] = i3[b] = 0;
+    x[b] = 0.f;
+    wgt[b] = 0.f;
+    nz[b] = id < total && id < a.p && nnz > 0;
+    zd[b] = id < total && id >= a.p;
+    if (nz[b]) {
       const Philox r = philox4x32_10((uint32_t)id, a.stamp[h], a.call, 0u, a.key0, a.key1);
-      const int64_t e = scale_to(r.v[0], nnz);
-      i1 = coords[3 * e];
-      i2 = coords[3 * e + 1];
-      i3 = coords[3 * e + 2];
-      x = a.vals[h][e];
-      wgt = a.w_nz[h];
+      e[b] = scale_to(r.v[0], nnz);
     } else {
-      const uint32_t cz = (uint32_t)(id - a.p);  // zero draws may also run with nnz == 0 below
-      bool ok = false;
-      for (int att = 0; att < kMaxAttempts && !ok; ++att) {
-        const Philox r = philox4x32_10(cz, a.stamp[h], a.call, 1u + 2u * (uint32_t)att, a.key0, a.key1);
-        i1 = (int)scale_to(r.v[0], I1);
-        i2 = (int)scale_to(r.v[1], I2);
-        i3 = (int)scale_to(r.v[2], I3);
-        ok = !is_stored(a.tab[h], a.tmask, ((uint64_t)i1 * I2 + i2) * I3 + i3);
+      e[b] = 0;
+    }
+    if (zd[b]) {
+      const Philox r = philox4x32_10((uint32_t)(id - a.p), a.stamp[h], a.call, 1u, a.key0, a.key1);
+      i1[b] = (int)scale_to(r.v[0], I1);
+      i2[b] = (int)scale_to(r.v[1], I2);
+      i3[b] = (int)scale_to(r.v[2], I3);
+      key[b] = ((uint64_t)i1[b] * I2 + i2[b]) * I3 + i3[b];
+      pos[b] = slot_of(key[b], a.tmask);
+    } else {
+      key[b] = 0;
+      pos[b] = 0;
+    }
+  }
+  // the random reads of every draw, issued together
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) {
+    if (nz[b]) {
+      i1[b] = coords[3 * e[b]];
+      i2[b] = coords[3 * e[b] + 1];
+      i3[b] = coords[3 * e[b] + 2];
+      x[b] = a.vals[h][e[b]];
+      wgt[b] = a.w_nz[h];
+    }
+    tv[b] = zd[b] ? a.tab[h][pos[b]] : 0ull;
+  }
+  // zero draws: finish the membership test (linear probing), redrawing while
+  // the tuple is a stored entry
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) {
+    if (!zd[b]) continue;
+    const int64_t id = first + 64 * b + lane;
+    bool ok = false;
+    uint64_t v = tv[b], k = key[b], ps = pos[b];
+    for (int att = 0; att < kMaxAttempts;) {
+      if (v == kEmptyKey) {
+        ok = true;
+        break;
       }
-      if (ok) {
-        wgt = a.w_z[h];
+      if (v == k) {   // stored: draw again
+        if (++att >= kMaxAttempts) break;
+        const Philox r = philox4x32_10((uint32_t)(id - a.p), a.stamp[h], a.call, 1u + 2u * (uint32_t)att, a.key0,
+                                       a.key1);
+        i1[b] = (int)scale_to(r.v[0], I1);
+        i2[b] = (int)scale_to(r.v[1], I2);
+        i3[b] = (int)scale_to(r.v[2], I3);
+        k = ((uint64_t)i1[b] * I2 + i2[b]) * I3 + i3[b];
+        ps = slot_of(k, a.tmask);
       } else {
-        atomicOr(a.status, (int)kStatusSampler);
-        i1 = i2 = i3 = 0;
+        ps = (ps + 1) & a.tmask;
       }
+      v = a.tab[h][ps];
+    }
+    if (ok) {
+      wgt[b] = a.w_z[h];
+    } else {
+      atomicOr(a.status, (int)kStatusSampler);
+      i1[b] = i2[b] = i3[b] = 0;
     }
   }
 
@@ -160,50 +238,67 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   const bool cur = h == 0;
   float gsl = 0.f;
   Kahan<float> lacc;
-  const int nd = (int)min<int64_t>(64, total - first);
   const int jc = j < R ? j : 0;
-  // U draws per lane group at a time: their lane exchanges and their factor
-  // row gathers are all issued before any is used (loads of padded draws and
-  // columns read row 0 / column 0 and are masked afterwards, so the loads
-  // themselves are unconditional)
-  constexpr int U = 4;
-  for (int base = 0; base < nd; base += PER * U) {
-    int b1[U], b2[U], b3[U];
-    float bx[U], bw[U], r1[U], r2[U], r3[U];
-    bool live[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int src = base + PER * u + sub;
-      const int sl = src < 64 ? src : 0;
-      b1[u] = __shfl(i1, sl);
-      b2[u] = __shfl(i2, sl);
-      b3[u] = __shfl(i3, sl);
-      bx[u] = __shfl(x, sl);
-      bw[u] = __shfl(wgt, sl);
-      live[u] = src < nd && j < R;
-    }
+  for (int bb = 0; bb < kNB; ++bb) {
+    const int64_t fb = first + 64 * bb;
+    const int nd = (int)max<int64_t>(0, min<int64_t>(64, total - fb));
+    // U draws per lane group at a time: their lane exchanges and their
+    // factor row gathers are all issued before any is used (loads of padded
+    // draws and columns read row 0 / column 0 and are masked afterwards, so
+    // the loads themselves are unconditional)
+    constexpr int U = 4;
+    for (int base = 0; base < nd; base += PER * U) {
+      int b1[U], b2[U], b3[U];
+      float bx[U], bw[U], r1[U], r2[U], r3[U];
+      bool live[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      r1[u] = a.A1[(size_t)b1[u] * R + jc];
-      r2[u] = a.A2[(size_t)b2[u] * R + jc];
-      r3[u] = a.A3[(size_t)b3[u] * R + jc];
-    }
+      for (int u = 0; u < U; ++u) {
+        const int src = base + PER * u + sub;
+        const int sl = src < 64 ? src : 0;
+        b1[u] = __shfl(i1[bb], sl);
+        b2[u] = __shfl(i2[bb], sl);
+        b3[u] = __shfl(i3[bb], sl);
+        bx[u] = __shfl(x[bb], sl);
+        bw[u] = __shfl(wgt[bb], sl);
+        live[u] = src < nd && j < R;
+      }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float lm = live[u] ? 1.f : 0.f;
-      float m = sj * r1[u] * r2[u] * r3[u] * lm;
-      for (int o = SEG / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o);
-      float f, y;
-      LossFn<float, LOSS>::eval(bx[u], m, f, y);
-      const float w = base + PER * u + sub < nd ? bw[u] : 0.f;
-      const float yt = ch * w * y;
-      if (j == 0 && w != 0.f && (a.want & kWantLoss)) lacc.add(ch * w * f);
-      if (live[u] && w != 0.f && (a.want & kWantGrad)) {
-        const float ys = yt * sj;
-        unsafeAtomicAdd(&a.G1[(size_t)b1[u] * R + j], ys * r2[u] * r3[u]);
-        unsafeAtomicAdd(&a.G2[(size_t)b2[u] * R + j], ys * r1[u] * r3[u]);
-        unsafeAtomicAdd(&a.G3[(size_t)b3[u] * R + j], ys * r1[u] * r2[u]);
-        if (cur) gsl += yt * r1[u] * r2[u] * r3[u];
+      for (int u = 0; u < U; ++u) {
+        r1[u] = a.A1[(size_t)b1[u] * R + jc];
+        r2[u] = a.A2[(size_t)b2[u] * R + jc];
+        r3[u] = a.A3[(size_t)b3[u] * R + jc];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = base + PER * u + sub;
+        const float lm = live[u] ? 1.f : 0.f;
+        float m = sj * r1[u] * r2[u] * r3[u] * lm;
+        for (int o = SEG / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o);
+        float f, y;
+        LossFn<float, LOSS>::eval(bx[u], m, f, y);
+        const float w = src < nd ? bw[u] : 0.f;
+        const float yt = ch * w * y;
+        if (j == 0 && w != 0.f && (a.want & kWantLoss)) lacc.add(ch * w * f);
+        if constexpr (REC) {
+          if (j == 0 && src < nd && (a.want & kWantGrad)) {
+            DrawRec rr;
+            rr.i1 = b1[u];
+            rr.i2 = b2[u];
+            rr.i3 = b3[u];
+            rr.y = w != 0.f ? yt : 0.f;
+            a.rec[(gwave * kNB + bb) * 64 + src] = rr;
+          }
+          if (live[u] && w != 0.f && (a.want & kWantGrad) && cur) gsl += yt * r1[u] * r2[u] * r3[u];
+        } else {
+          if (live[u] && w != 0.f && (a.want & kWantGrad)) {
+            const float ys = yt * sj;
+            unsafeAtomicAdd(&a.G1[(size_t)b1[u] * R + j], ys * r2[u] * r3[u]);
+            unsafeAtomicAdd(&a.G2[(size_t)b2[u] * R + j], ys * r1[u] * r3[u]);
+            unsafeAtomicAdd(&a.G3[(size_t)b3[u] * R + j], ys * r1[u] * r2[u]);
+            if (cur) gsl += yt * r1[u] * r2[u] * r3[u];
+          }
+        }
       }
     }
   }
@@ -216,6 +311,191 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
     for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o);
     if (lane == 0) unsafeAtomicAdd(a.loss, l);
   }
+}
+
+// Row-sorted reduction.  The count and scatter steps take the draw slots in
+// chunks of kSortChunk per workgroup and keep a histogram of the chunk's rows
+// of all three modes in LDS (I1 + I2 + I3 <= kSortBins), so that the device
+// sees one atomic per (chunk, row) instead of one per draw.
+constexpr int kSortBins = 12288;
+constexpr int kSortChunk = 65536;
+
+__global__ void __launch_bounds__(256) sorted_zero(int* __restrict__ cnt, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) cnt[i] = 0;
+}
+
+struct CountArgs {
+  const DrawRec* rec;
+  int* cnt;             // I1 + I2 + I3 row counts, mode by mode
+  int* cur;             // scatter: I1 + I2 + I3 cursors (row starts on entry)
+  RowRec* srt[3];       // scatter: the three row-sorted lists
+  int64_t slots;        // draw slots per slice (a multiple of 64 kNB)
+  int64_t total;        // draws per slice
+  int64_t nslots;       // ns * slots
+  int I1, I2, I3;
+};
+
+// Adds this chunk's valid records (slot inside the slice's draws, nonzero
+// ytilde) to the LDS histogram.
+__device__ __forceinline__ void chunk_histogram(const CountArgs& a, int* hist, int64_t g0, int64_t g1) {
+  const int o2 = a.I1, o3 = a.I1 + a.I2;
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += 1024) {
+    const int64_t h = g / a.slots;
+    if (g - h * a.slots >= a.total) continue;
+    const DrawRec r = a.rec[g];
+    if (r.y == 0.f) continue;
+    atomicAdd(&hist[r.i1], 1);
+    atomicAdd(&hist[o2 + r.i2], 1);
+    atomicAdd(&hist[o3 + r.i3], 1);
+  }
+}
+
+// Step 2: row counts.
+__global__ void __launch_bounds__(1024) sorted_count(CountArgs a) {
+  __shared__ int hist[kSortBins];
+  const int nb = a.I1 + a.I2 + a.I3;
+  for (int i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
+  __syncthreads();
+  const int64_t g0 = (int64_t)blockIdx.x * kSortChunk;
+  chunk_histogram(a, hist, g0, min(g0 + (int64_t)kSortChunk, a.nslots));
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += 1024)
+    if (hist[i]) atomicAdd(&a.cnt[i], hist[i]);
+}
+
+// Step 4: the chunk's histogram again; one atomic per row reserves the
+// chunk's places in that row, and the records are written there (their order
+// inside a row is not fixed).
+__global__ void __launch_bounds__(1024) sorted_scatter(CountArgs a) {
+  __shared__ int hist[kSortBins];
+  const int nb = a.I1 + a.I2 + a.I3;
+  for (int i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
+  __syncthreads();
+  const int64_t g0 = (int64_t)blockIdx.x * kSortChunk;
+  const int64_t g1 = min(g0 + (int64_t)kSortChunk, a.nslots);
+  chunk_histogram(a, hist, g0, g1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += 1024) {
+    const int c = hist[i];
+    hist[i] = c ? atomicAdd(&a.cur[i], c) : 0;
+  }
+  __syncthreads();
+  const int o2 = a.I1, o3 = a.I1 + a.I2;
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += 1024) {
+    const int64_t h = g / a.slots;
+    if (g - h * a.slots >= a.total) continue;
+    const DrawRec r = a.rec[g];
+    if (r.y == 0.f) continue;
+    RowRec o;
+    o.h = (int)h;
+    o.y = r.y;
+    o.a = r.i2; o.b = r.i3;
+    a.srt[0][atomicAdd(&hist[r.i1], 1)] = o;
+    o.a = r.i1; o.b = r.i3;
+    a.srt[1][atomicAdd(&hist[o2 + r.i2], 1)] = o;
+    o.a = r.i1; o.b = r.i2;
+    a.srt[2][atomicAdd(&hist[o3 + r.i3], 1)] = o;
+  }
+}
+
+// Step 3 (after the draw kernel): exclusive scan of each mode's row counts
+// into row starts (I_k + 1 values, the last one the list length) and the
+// scatter cursors; copy the slices' weight rows into one ns x R table.
+struct ScanArgs {
+  const int* cnt[3];
+  int* start[3];
+  int* cur[3];
+  int n[3];
+  const float* S[kMaxNs];
+  float* Sall;
+  int ns, R;
+};
+
+__global__ void __launch_bounds__(1024) sorted_scan(ScanArgs a) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  for (int k = 0; k < 3; ++k) {
+    const int n = a.n[k];
+    const int chunk = (n + 1023) / 1024;
+    const int t0 = min(n, t * chunk), t1 = min(n, t0 + chunk);
+    int s = 0;
+    for (int i = t0; i < t1; ++i) s += a.cnt[k][i];
+    part[t] = s;
+    __syncthreads();
+    // inclusive scan of the 1024 chunk sums (Hillis-Steele)
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int v = t >= off ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int i = t0; i < t1; ++i) {
+      a.start[k][i] = run;
+      a.cur[k][i] = run;
+      run += a.cnt[k][i];
+    }
+    if (t == 1023) a.start[k][n] = part[1023];
+    __syncthreads();
+  }
+  for (int idx = t; idx < a.ns * a.R; idx += 1024) a.Sall[idx] = a.S[idx / a.R][idx % a.R];
+}
+
+// Step 5, one launch per mode: a group of SEG lanes (lane = rank column)
+// walks a run of kRun consecutive records of the mode's list, U records at a
+// time (their loads and factor-row gathers issued before any is used); the
+// row's sum stays in registers and is added to G when the run leaves the row
+// and at the end of the run.
+constexpr int kRun = 256;
+
+template <int SEG>
+__global__ void __launch_bounds__(256) sorted_reduce(const RowRec* __restrict__ srt, const int* __restrict__ start,
+                                                     int nrows, const float* __restrict__ Aa,
+                                                     const float* __restrict__ Ab, const float* __restrict__ Sall,
+                                                     float* __restrict__ G, int R) {
+  constexpr int PER = 64 / SEG;
+  constexpr int U = 8;
+  const int lane = threadIdx.x & 63;
+  const int j = lane % SEG, sub = lane / SEG;
+  const int jc = j < R ? j : 0;
+  const int64_t grp = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * PER + sub;
+  const int64_t nrec = start[nrows];
+  const int64_t p0 = grp * kRun;
+  if (p0 >= nrec) return;
+  const int64_t p1 = min(p0 + (int64_t)kRun, nrec);
+  // row of p0: the last row whose start is <= p0 (rows may be empty)
+  int lo = 0, hi = nrows;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= p0) lo = mid; else hi = mid;
+  }
+  int row = lo;
+  int64_t bound = start[row + 1];
+  float acc = 0.f;
+  for (int64_t pos = p0; pos < p1; pos += U) {
+    RowRec r[U];
+    float va[U], vb[U], vs[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = srt[pos + u < p1 ? pos + u : p0];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      va[u] = Aa[(size_t)r[u].a * R + jc];
+      vb[u] = Ab[(size_t)r[u].b * R + jc];
+      vs[u] = Sall[(size_t)r[u].h * R + jc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (pos + u >= p1) break;
+      while (pos + u >= bound) {
+        if (j < R && acc != 0.f) unsafeAtomicAdd(&G[(size_t)row * R + j], acc);
+        acc = 0.f;
+        ++row;
+        bound = start[row + 1];
+      }
+      acc += r[u].y * vs[u] * va[u] * vb[u];
+    }
+  }
+  if (j < R && acc != 0.f) unsafeAtomicAdd(&G[(size_t)row * R + j], acc);
 }
 
 // Outputs start from the exact regularisation terms: G = lambda A,
@@ -289,19 +569,83 @@ __global__ void __launch_bounds__(256) table_insert(const int32_t* __restrict__ 
   }
 }
 
-template <int LOSS>
+template <int LOSS, bool REC>
 hipError_t launch_seg(const SampledCall& c, const SArgs& a, int64_t blocks) {
   if (c.R <= 16) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 16>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 16, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
   } else if (c.R <= 32) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 32>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 32, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
   } else {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 64>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 64, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
   }
   return hipGetLastError();
 }
 
+template <bool REC>
+hipError_t launch_draws(const SampledCall& c, const SArgs& a, int64_t blocks) {
+  switch (c.loss) {
+    case kGaussian: return launch_seg<kGaussian, REC>(c, a, blocks);
+    case kPoissonLog: return launch_seg<kPoissonLog, REC>(c, a, blocks);
+    default: return launch_seg<kBernoulliLogit, REC>(c, a, blocks);
+  }
+}
+
+// Layout of the row-sorted workspace (byte offsets from its start).
+struct SortedLayout {
+  size_t rec, srt[3], cnt, S, total;
+  int64_t slots;   // draw slots per slice
+  size_t cnt_off[3], start_off[3], cur_off[3];   // int offsets inside cnt
+};
+
+SortedLayout sorted_layout(int I1, int I2, int I3, int R, int nsmax, int64_t p, int64_t q) {
+  SortedLayout L;
+  const int64_t total = p + q;
+  // a wave's kNB x 64 draw slots per slice, as the draw kernel numbers them
+  L.slots = (total + 64 * kNB - 1) / (64 * kNB) * (64 * kNB);
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  size_t off = 0;
+  L.rec = off; off = al(off + (size_t)nsmax * L.slots * sizeof(DrawRec));
+  for (int k = 0; k < 3; ++k) {
+    L.srt[k] = off;
+    off = al(off + (size_t)nsmax * total * sizeof(RowRec));
+  }
+  const int n[3] = {I1, I2, I3};
+  size_t io = 0;
+  for (int k = 0; k < 3; ++k) { L.cnt_off[k] = io; io += n[k]; }
+  for (int k = 0; k < 3; ++k) { L.start_off[k] = io; io += n[k] + 1; }
+  for (int k = 0; k < 3; ++k) { L.cur_off[k] = io; io += n[k]; }
+  L.cnt = off; off = al(off + io * sizeof(int));
+  L.S = off; off = al(off + (size_t)nsmax * R * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+template <int SEG>
+void launch_reduce_mode(const SampledCall& c, const RowRec* srt, const int* start, int nrows, const float* Aa,
+                        const float* Ab, const float* Sall, float* G, int64_t max_rec) {
+  const int64_t groups = (max_rec + kRun - 1) / kRun;
+  const int64_t blocks = (groups + 4 * (64 / SEG) - 1) / (4 * (64 / SEG));
+  if (blocks > 0)
+    hipLaunchKernelGGL((sorted_reduce<SEG>), dim3((unsigned)blocks), dim3(256), 0, c.stream, srt, start, nrows, Aa,
+                       Ab, Sall, G, c.R);
+}
+
 }  // namespace
+
+size_t sampled_sorted_bytes(int I1, int I2, int I3, int R, int window, int64_t p, int64_t q) {
+  // row counts and starts are 32-bit; the per-chunk row histograms live in LDS
+  if ((double)(window + 1) * (double)(p + q) >= 2147483647.0) return 0;
+  if ((int64_t)I1 + I2 + I3 > kSortBins) return 0;
+  return sorted_layout(I1, I2, I3, R, window + 1, p, q).total;
+}
+
+void sampled_sorted_bind(SampledCall& c, char* base, int window) {
+  const SortedLayout L = sorted_layout(c.I1, c.I2, c.I3, c.R, window + 1, c.p, c.q);
+  c.srec = base + L.rec;
+  c.ssrt = base + L.srt[0];
+  c.scnt = reinterpret_cast<int*>(base + L.cnt);
+  c.sS = reinterpret_cast<float*>(base + L.S);
+}
 
 uint64_t table_capacity(int64_t max_nnz) {
   uint64_t cap = 64;
@@ -356,20 +700,74 @@ hipError_t sampled_run(const SampledCall& c) {
   a.status = c.status;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.p = c.p; a.q = c.q;
-  a.waves_per_slice = (c.p + c.q + 63) / 64;
+  a.waves_per_slice = (c.p + c.q + 64 * kNB - 1) / (64 * kNB);
   a.key0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
   a.key1 = (uint32_t)(c.seed >> 32);
   a.call = (uint32_t)c.call;
   const int64_t blocks = (a.waves_per_slice * c.ns + 3) / 4;
+  const bool sorted = c.srec != nullptr && (c.want & kWantGrad);
   if (blocks > 0) {
     if (c.ev_begin) (void)hipEventRecord(c.ev_begin, c.stream);
-    switch (c.loss) {
-      case kGaussian: e = launch_seg<kGaussian>(c, a, blocks); break;
-      case kPoissonLog: e = launch_seg<kPoissonLog>(c, a, blocks); break;
-      default: e = launch_seg<kBernoulliLogit>(c, a, blocks);
+    if (!sorted) {
+      e = launch_draws<false>(c, a, blocks);
+      if (e != hipSuccess) return e;
+    } else {
+      // the workspace was sized for window + 1 slices; ns <= that
+      const SortedLayout L = sorted_layout(c.I1, c.I2, c.I3, c.R, c.ns, c.p, c.q);
+      char* base = static_cast<char*>(c.ssrt);
+      int* ib = c.scnt;
+      const int n[3] = {c.I1, c.I2, c.I3};
+      const int ncnt = c.I1 + c.I2 + c.I3;
+      hipLaunchKernelGGL(sorted_zero, dim3((unsigned)std::min(1024, (ncnt + 255) / 256)), dim3(256), 0, c.stream,
+                         ib, ncnt);
+      a.rec = static_cast<DrawRec*>(c.srec);
+      e = launch_draws<true>(c, a, blocks);
+      if (e != hipSuccess) return e;
+      CountArgs ca;
+      ca.rec = a.rec;
+      ca.cnt = ib + L.cnt_off[0];
+      ca.cur = ib + L.cur_off[0];
+      RowRec* srt[3];
+      for (int k = 0; k < 3; ++k) {
+        srt[k] = reinterpret_cast<RowRec*>(base + (L.srt[k] - L.srt[0]));
+        ca.srt[k] = srt[k];
+      }
+      ca.slots = L.slots;
+      ca.total = c.p + c.q;
+      ca.nslots = (int64_t)c.ns * L.slots;
+      ca.I1 = c.I1; ca.I2 = c.I2; ca.I3 = c.I3;
+      const unsigned nchunks = (unsigned)((ca.nslots + kSortChunk - 1) / kSortChunk);
+      hipLaunchKernelGGL(sorted_count, dim3(nchunks), dim3(1024), 0, c.stream, ca);
+      ScanArgs sa;
+      for (int k = 0; k < 3; ++k) {
+        sa.cnt[k] = ib + L.cnt_off[k];
+        sa.start[k] = ib + L.start_off[k];
+        sa.cur[k] = ib + L.cur_off[k];
+        sa.n[k] = n[k];
+      }
+      for (int h = 0; h < c.ns; ++h) sa.S[h] = static_cast<const float*>(c.S[h]);
+      sa.Sall = c.sS;
+      sa.ns = c.ns;
+      sa.R = c.R;
+      hipLaunchKernelGGL(sorted_scan, dim3(1), dim3(1024), 0, c.stream, sa);
+      hipLaunchKernelGGL(sorted_scatter, dim3(nchunks), dim3(1024), 0, c.stream, ca);
+      // one launch per mode; each list holds at most ns (p + q) records
+      const int64_t max_rec = (int64_t)c.ns * (c.p + c.q);
+      const float* fa[3][2] = {{A2, A3}, {A1, A3}, {A1, A2}};
+      float* Gk[3] = {G1, G2, G3};
+      for (int k = 0; k < 3; ++k) {
+        const int* st_k = ib + L.start_off[k];
+        if (c.R <= 16)
+          launch_reduce_mode<16>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+        else if (c.R <= 32)
+          launch_reduce_mode<32>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+        else
+          launch_reduce_mode<64>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+      }
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
     }
     if (c.ev_end) (void)hipEventRecord(c.ev_end, c.stream);
-    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(sampled_check, dim3(std::min(64, (n1 + n2 + n3 + c.R + 256) / 256)), dim3(256), 0, c.stream,
                      G1, G2, G3, gs, loss, n1, n2, n3, c.R, c.want, c.status);

@@ -45,7 +45,8 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 lam=0.0, mu=0.0, lower=-math.inf, alpha_f=1e-3, beta1=0.9,
                 beta2=0.999, adam_eps=1e-8, tau_f=1, seed=0,
                 dtype=torch.float32, plain=False, kernel: str = "auto",
-                slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0) -> N.GcpParams:
+                slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0,
+                sampled_atomic: bool = False) -> N.GcpParams:
     lib = N.load()
     n_p, n_q = p, q
     p = N.GcpParams()
@@ -60,7 +61,8 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.loss = N.LOSS_IDS[loss]
     p.dtype = N.F64 if dtype == torch.float64 else N.F32
     p.flags = (N.FLAG_PLAIN_SCRATCH if plain else 0) | {
-        "auto": 0, "valu": N.FLAG_KERNEL_VALU, "mfma": N.FLAG_KERNEL_MFMA}[kernel]
+        "auto": 0, "valu": N.FLAG_KERNEL_VALU, "mfma": N.FLAG_KERNEL_MFMA}[kernel] | (
+        N.FLAG_SAMPLED_ATOMIC if sampled_atomic else 0)
     p.w, p.theta, p.lam, p.mu, p.lower = float(w), float(theta), float(lam), float(mu), float(lower)
     p.alpha_f, p.beta1, p.beta2, p.adam_eps = float(alpha_f), float(beta1), float(beta2), float(adam_eps)
     p.tau_f = int(tau_f)

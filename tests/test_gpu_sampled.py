@@ -51,14 +51,16 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("reduction", ["sorted", "atomic"])
 @pytest.mark.parametrize("dims,R,H,nnz,p,q,loss", CASES)
-def test_sampled_matches_oracle(dims, R, H, nnz, p, q, loss):
+def test_sampled_matches_oracle(dims, R, H, nnz, p, q, loss, reduction):
+    """Both ways of summing the MTTKRP rows (row-sorted lists, float atomics)."""
     import torch
-    print("case: sampled", dims, R, H, nnz, p, q, loss, flush=True)
+    print("case: sampled", reduction, dims, R, H, nnz, p, q, loss, flush=True)
     prob = _f32(gi.sparse_problem(dims=dims, rank=R, window=H, nnz=nnz, p=p, q=q, seed=R + H,
                                   loss=loss))
     prob.lam, prob.mu, prob.theta, prob.w = 0.05, 0.1, 0.9, 1.3
-    st, T = _stream(prob)
+    st, T = _stream(prob, sampled_atomic=reduction == "atomic")
     Xt = _dev_coo(prob.X_t)
     A = [T(a) for a in prob.A]
     for call in range(2):
