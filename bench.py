@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
+    ap.add_argument("--sampled-atomic", action="store_true",
+                    help="c5: sum the MTTKRP rows with float atomics instead of the row-sorted lists")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the workload, run a plain device-to-device copy of this "
                          "many MiB a few times (calibrates the FETCH_SIZE/WRITE_SIZE counters)")
@@ -205,7 +207,8 @@ def bench_c5(args):
     R, H = prob.rank, len(prob.X_hist)
     st = Stream(prob.dims, R, H, prob.loss, [T(a) for a in prob.A], [coo(x) for x in prob.X_hist],
                 T(prob.s_hist), list(prob.t_hist), seed=prob.seed, slice_kind="coo",
-                max_nnz=prob.X_t.coords.shape[0], p=prob.p, q=prob.q)
+                max_nnz=prob.X_t.coords.shape[0], p=prob.p, q=prob.q,
+                sampled_atomic=args.sampled_atomic)
     Xt = coo(prob.X_t)
     A = [T(a) for a in prob.A]
     s_t = T(prob.s_t)
@@ -225,8 +228,9 @@ def bench_c5(args):
     alg = (H + 1) * (prob.p * 16 + prob.q * 8)
     _line("C5 sampled COO slices 2000x2000x500, 2M nonzeros, rank 32, window 8, p=q=2M, "
           "Poisson-log", "grad steps/s", sec * 1e3, args.steps, args.warmup, alg,
-          draws * 16 * R, ms / max(n, 1) / 1e3, {"draws_per_step": draws,
-                                                  "draws_per_s": draws / (ms / max(n, 1) / 1e3)})
+          draws * 16 * R, ms / max(n, 1) / 1e3,
+          {"draws_per_step": draws, "draws_per_s": draws / (ms / max(n, 1) / 1e3),
+           "reduction": "atomic" if args.sampled_atomic else "row-sorted"})
     return 0
 
 
