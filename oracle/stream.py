@@ -10,7 +10,9 @@ Follows the body of Algorithm 1 (Section 4.3) in the paper's order:
      full gradient of eq. gcp_stream_problem_1 (stored-slice history, see
      gcp.py) followed by the ADAM Step of Algorithm 2 with the global
      iteration index i carried across slices;
-  4. the reservoir window update (window.py), storing X_t and s_t;
+  4. the reservoir window update (window.py), storing X_t and s_t (with the
+     model-difference history of eq. gcp_stream_problem_2, hist="model",
+     only s_t is stored and the gradient is that of model_hist.py);
   5. A_old <- A.
 Algorithm 4's epoch loop with its sampled objective estimate and
 roll-back is not part of this step; every iteration is kept.
@@ -23,6 +25,7 @@ import numpy as np
 
 from .adam import adam_step
 from .gcp import gradient
+from .model_hist import gradient_model
 from .solve import ls_temporal
 from .window import window_update
 
@@ -31,14 +34,15 @@ class StreamOracle:
     def __init__(self, A0, X_hist, s_hist, t_hist, *, loss="gaussian",
                  window=0, w=1.0, theta=1.0, lam=0.0, mu=0.0,
                  lower=-np.inf, alpha_f=1e-3, beta1=0.9, beta2=0.999,
-                 adam_eps=1e-8, tau_f=1, seed=0):
+                 adam_eps=1e-8, tau_f=1, seed=0, hist="slices"):
         self.A = [np.array(a, np.float64) for a in A0]
         self.A_old = [a.copy() for a in self.A]
         self.u = [np.zeros_like(a) for a in self.A]
         self.v = [np.zeros_like(a) for a in self.A]
         self.i = 0
         self.slots = [int(t) for t in t_hist]
-        self.Xw = [np.array(x, np.float64) for x in X_hist]
+        self.hist = hist
+        self.Xw = [np.array(x, np.float64) for x in X_hist] if hist == "slices" else []
         self.Sw = [np.array(s, np.float64) for s in np.asarray(s_hist).reshape(len(self.slots), -1)]
         self.t = (max(self.slots) + 1) if self.slots else 1
         self.cfg = SimpleNamespace(loss=loss, H=window, w=w, theta=theta,
@@ -49,7 +53,7 @@ class StreamOracle:
     def problem(self, X_t, s_t, A=None):
         c = self.cfg
         return SimpleNamespace(X_t=X_t, A=self.A if A is None else A, s_t=s_t,
-                               X_hist=self.Xw,
+                               A_old=self.A_old, X_hist=self.Xw,
                                s_hist=np.array(self.Sw).reshape(len(self.Sw), -1),
                                t_hist=np.array(self.slots, np.int64), t=self.t,
                                w=c.w, theta=c.theta, lam=c.lam, mu=c.mu,
@@ -63,7 +67,8 @@ class StreamOracle:
     def update_factors(self, X_t, s_t):
         c = self.cfg
         for _ in range(c.tau_f):
-            G, _ = gradient(self.problem(X_t, s_t))
+            prob = self.problem(X_t, s_t)
+            G, _ = gradient(prob) if self.hist == "slices" else gradient_model(prob)
             for k in range(len(self.A)):
                 self.A[k], self.u[k], self.v[k] = adam_step(
                     self.A[k], G[k], self.u[k], self.v[k], self.i, c.alpha_f,
@@ -71,11 +76,14 @@ class StreamOracle:
             self.i += 1
         new_slots, slot = window_update(self.slots, c.H, self.t, c.seed)
         if slot >= 0:
-            if slot == len(self.Xw):
-                self.Xw.append(np.array(X_t, np.float64))
+            keep = self.hist == "slices"
+            if slot == len(self.Sw):
+                if keep:
+                    self.Xw.append(np.array(X_t, np.float64))
                 self.Sw.append(np.array(s_t, np.float64))
             else:
-                self.Xw[slot] = np.array(X_t, np.float64)
+                if keep:
+                    self.Xw[slot] = np.array(X_t, np.float64)
                 self.Sw[slot] = np.array(s_t, np.float64)
         self.slots = new_slots
         self.A_old = [a.copy() for a in self.A]
