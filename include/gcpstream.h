@@ -84,6 +84,18 @@ enum {
   GCP_IMPL_PLAIN = 256    /* run the unfused multi-kernel path instead    */
 };
 
+/* History term of the objective (gcp_params.hist), Section 4.1.
+ * SLICES: the window stores past slices X_h with their weights s_h and adds
+ *   sum_h w_h sum_i f(x_ih, m_i(s_h)) (eq. gcp_stream_problem_1).
+ * MODEL: the window stores only the weights s_h and adds
+ *   1/2 sum_h w_h ||[[Abar; s_h]] - [[A; s_h]]||_F^2 (eq. gcp_stream_problem_2),
+ *   Abar being the factors at the end of the previous time step (at stream
+ *   creation: A0); the data term is that of X_t alone, and the factor
+ *   gradient gains A_k B_k - Abar_k C_k (eq. spatial_gcp_grad), evaluated
+ *   through R x R Gram matrices in FP64.  No window slice is stored, so the
+ *   workspace holds no slice ring. */
+typedef enum { GCP_HIST_SLICES = 0, GCP_HIST_MODEL = 1 } gcp_hist;
+
 /* Flags of gcp_params.flags. */
 enum {
   GCP_FLAG_PLAIN_SCRATCH = 1, /* reserve the unfused path's scratch (2 slices) */
@@ -115,7 +127,7 @@ typedef struct {
   double alpha_f;         /* ADAM rate of the factor solver (Alg. 2)       */
   double beta1, beta2, adam_eps;
   int32_t tau_f;          /* factor iterations per gcp_update_factors      */
-  int32_t reserved0;
+  int32_t hist;           /* gcp_hist: the history term of the objective   */
   int64_t max_nnz;        /* COO: largest nnz of any slice (X_t included);
                            * sizes the window slots and the per-slice
                            * membership tables (2 max_nnz keys of 8 B,

@@ -31,6 +31,8 @@ FLAG_PLAIN_SCRATCH = 1
 FLAG_KERNEL_VALU = 2
 FLAG_KERNEL_MFMA = 4
 FLAG_SAMPLED_ATOMIC = 8
+HIST_SLICES = 0
+HIST_MODEL = 1
 
 
 class GcpParams(Structure):
@@ -41,7 +43,7 @@ class GcpParams(Structure):
         ("w", c_double), ("theta", c_double), ("lam", c_double), ("mu", c_double),
         ("lower", c_double), ("alpha_f", c_double), ("beta1", c_double),
         ("beta2", c_double), ("adam_eps", c_double), ("tau_f", c_int32),
-        ("reserved0", c_int32), ("max_nnz", c_int64), ("p", c_int64),
+        ("hist", c_int32), ("max_nnz", c_int64), ("p", c_int64),
         ("q", c_int64), ("seed", c_uint64),
     ]
 

@@ -19,7 +19,7 @@
 using namespace gcp;
 
 struct WsLayout {
-  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, total;
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -84,6 +84,7 @@ gcp_status check_params(const gcp_params* p) {
   if (p->flags & ~(GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_KERNEL_VALU | GCP_FLAG_KERNEL_MFMA | GCP_FLAG_SAMPLED_ATOMIC))
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
+  if (p->hist != GCP_HIST_SLICES && p->hist != GCP_HIST_MODEL) return GCP_E_ARG;
   return GCP_OK;
 }
 
@@ -108,6 +109,9 @@ WsLayout layout_for(const gcp_params* p) {
   L.loss = off; off += 256;
   L.shist = off; off = align_up(off + (size_t)p->window * R * es, 256);
   const bool coo = p->slice_kind == GCP_SLICE_COO;
+  const bool model = p->hist == GCP_HIST_MODEL;
+  // slices kept in the window (the model-difference history keeps none)
+  const int wslices = model ? 0 : p->window;
   L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
   // stored dense slices keep each (i1, i2) row on 128-byte lines: the row
   // pitch is I3 rounded up to 32 values (the padding is never read)
@@ -115,7 +119,7 @@ WsLayout layout_for(const gcp_params* p) {
   L.slot_elems = (size_t)I1 * I2 * L.rp3;
   (void)omega;
   L.ring = off;
-  off = align_up(off + (coo ? (size_t)p->window * L.coo_slot : (size_t)p->window * L.slot_elems * es), 256);
+  off = align_up(off + (coo ? (size_t)wslices * L.coo_slot : (size_t)wslices * L.slot_elems * es), 256);
   L.part_bytes = coo ? 0 : dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
   L.part = off; off = align_up(off + L.part_bytes, 256);
   L.ls = off; off = align_up(off + (coo ? 0 : ls_scratch_bytes(I1, I2, I3, R)), 256);
@@ -123,11 +127,12 @@ WsLayout layout_for(const gcp_params* p) {
   L.plain = off; off = align_up(off + L.plain_bytes, 256);
   // COO: one membership table per window slot and one for the current slice
   L.tab_cap = coo ? table_capacity(p->max_nnz) : 0;
-  L.tab = off; off = align_up(off + (size_t)(coo ? p->window + 1 : 0) * L.tab_cap * 8, 256);
+  L.tab = off; off = align_up(off + (size_t)(coo ? wslices + 1 : 0) * L.tab_cap * 8, 256);
   L.sorted_bytes = (coo && !(p->flags & GCP_FLAG_SAMPLED_ATOMIC))
-                       ? sampled_sorted_bytes(I1, I2, I3, R, p->window, p->p, p->q)
+                       ? sampled_sorted_bytes(I1, I2, I3, R, wslices, p->p, p->q)
                        : 0;
   L.sorted = off; off = align_up(off + L.sorted_bytes, 256);
+  L.hist = off; off = align_up(off + (model ? hist_ws_bytes(R) : 0), 256);
   L.total = off;
   return L;
 }
@@ -168,6 +173,14 @@ uint64_t* coo_table(gcp_stream* s, int slot) {
   return reinterpret_cast<uint64_t*>(s->ws + s->L.tab + (size_t)slot * s->L.tab_cap * 8);
 }
 
+bool model_hist(const gcp_stream* s) { return s->p.hist == GCP_HIST_MODEL; }
+
+// Window slices kept by the stream (the model-difference history keeps none).
+int window_slices(const gcp_stream* s) { return model_hist(s) ? 0 : s->p.window; }
+
+// Membership table of the current slice: after those of the window slots.
+uint64_t* current_table(gcp_stream* s) { return coo_table(s, window_slices(s)); }
+
 hipError_t store_coo_slot(gcp_stream* s, int slot, const gcp_slice* X) {
   hipError_t e = hipSuccess;
   if (X->nnz > 0) {
@@ -184,7 +197,7 @@ hipError_t store_coo_slot(gcp_stream* s, int slot, const gcp_slice* X) {
 
 // Table of the current slice X_t, rebuilt for every call that samples it.
 hipError_t build_current_table(gcp_stream* s, const gcp_slice* X_t) {
-  return table_build(X_t->coords, X_t->nnz, s->dims[1], s->dims[2], coo_table(s, s->p.window), s->L.tab_cap, s->st);
+  return table_build(X_t->coords, X_t->nnz, s->dims[1], s->dims[2], current_table(s), s->L.tab_cap, s->st);
 }
 
 SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, int want,
@@ -194,11 +207,11 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.I1 = s->dims[0]; c.I2 = s->dims[1]; c.I3 = s->dims[2]; c.R = s->p.rank;
   c.loss = s->p.loss; c.want = want;
   c.coords[0] = X_t->coords; c.vals[0] = X_t->vals; c.nnz[0] = X_t->nnz; c.stamp[0] = s->t;
-  c.tab[0] = coo_table(s, s->p.window);
+  c.tab[0] = current_table(s);
   c.tab_cap = s->L.tab_cap;
   c.S[0] = s_t; c.c[0] = 1.0;
   int n = 1;
-  for (int slot = 0; slot < s->nwin; ++slot, ++n) {
+  for (int slot = 0; slot < (model_hist(s) ? 0 : s->nwin); ++slot, ++n) {
     c.coords[n] = reinterpret_cast<const int32_t*>(coo_slot_coords(s, slot));
     c.tab[n] = coo_table(s, slot);
     c.vals[n] = coo_slot_vals(s, slot);
@@ -217,7 +230,7 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.p = s->p.p; c.q = s->p.q; c.seed = s->p.seed;
   c.call = s->sample_call++;
   c.status = s->status; c.stream = s->st;
-  if (s->L.sorted_bytes) sampled_sorted_bind(c, s->ws + s->L.sorted, s->p.window);
+  if (s->L.sorted_bytes) sampled_sorted_bind(c, s->ws + s->L.sorted, window_slices(s));
   return c;
 }
 
@@ -230,7 +243,7 @@ void fill_window(gcp_stream* s, DenseCall& c) {
   c.shist = s->ws + s->L.shist;
   c.omega = s->omega;
   int n = 1;
-  for (int slot = 0; slot < s->nwin; ++slot, ++n) {
+  for (int slot = 0; slot < (model_hist(s) ? 0 : s->nwin); ++slot, ++n) {
     c.X[n] = s->ws + s->L.ring + (size_t)slot * s->L.slot_elems * s->es;
     c.S[n] = s->ws + s->L.shist + (size_t)slot * s->p.rank * s->es;
     c.c[n] = s->p.w * pow(s->p.theta, (double)(s->t - s->slot_t[slot]));
@@ -310,12 +323,15 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   if (st != GCP_OK) return st;
   if (!A0 || !A0[0] || !A0[1] || !A0[2] || !workspace) return GCP_E_ARG;
   if (n_hist < 0 || n_hist > p->window) return GCP_E_ARG;
-  if (n_hist > 0 && (!X_hist || !s_hist || !t_hist)) return GCP_E_ARG;
+  const bool model = p->hist == GCP_HIST_MODEL;
+  if (n_hist > 0 && (!s_hist || !t_hist || (!model && !X_hist))) return GCP_E_ARG;
   if (((uintptr_t)workspace & 255u) != 0) return GCP_E_ALIGN;
   WsLayout L = layout_for(p);
   if (ws_bytes < L.total) return GCP_E_WORKSPACE;
   for (int h = 0; h < n_hist; ++h) {
-    if (p->slice_kind == GCP_SLICE_DENSE) {
+    if (model) {
+      // only the weights and time stamps of the window are kept
+    } else if (p->slice_kind == GCP_SLICE_DENSE) {
       if (X_hist[h].kind != GCP_SLICE_DENSE || !X_hist[h].vals) return GCP_E_ARG;
       if (!aligned16(X_hist[h].vals)) return GCP_E_ALIGN;
     } else {
@@ -350,7 +366,9 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
   for (int h = 0; h < n_hist && e == hipSuccess; ++h) {
-    if (p->slice_kind == GCP_SLICE_COO)
+    if (model)
+      ;
+    else if (p->slice_kind == GCP_SLICE_COO)
       e = store_coo_slot(s, h, &X_hist[h]);
     else
       e = store_dense_slot(s, h, X_hist[h].vals);
@@ -365,6 +383,33 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   }
   *out = s;
   return GCP_OK;
+}
+
+// The model-difference history term for factors A (previous step's factors:
+// the stream's A_old), added to *loss and G after the data term.
+hipError_t add_model_history(gcp_stream* s, const void* const* A, int want, void* loss, void* const* G,
+                             const void* grad_scale) {
+  if (!model_hist(s) || s->nwin == 0) return hipSuccess;
+  HistCall h;
+  for (int k = 0; k < 3; ++k) {
+    h.I[k] = s->dims[k];
+    h.A[k] = A[k];
+    h.Ab[k] = fac_ptr(s, s->L.Aold, k);
+    h.G[k] = G[k];
+  }
+  h.R = s->p.rank;
+  h.nwin = s->nwin;
+  h.dtype = s->p.dtype == GCP_F64 ? 1 : 0;
+  h.want = want;
+  h.shist = s->ws + s->L.shist;
+  for (int i = 0; i < kMaxNs; ++i)
+    h.c[i] = i < s->nwin ? s->p.w * pow(s->p.theta, (double)(s->t - s->slot_t[i])) : 0.0;
+  h.loss = loss;
+  h.grad_scale = grad_scale;
+  h.ws = reinterpret_cast<double*>(s->ws + s->L.hist);
+  h.status = s->status;
+  h.stream = s->st;
+  return hist_run(h);
 }
 
 gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, uint32_t want,
@@ -395,7 +440,9 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
       c.ev_end = s->ev[s->ev_used + 1];
       s->ev_used += 2;
     }
-    return hip_status(sampled_run(c));
+    hipError_t es = sampled_run(c);
+    if (es == hipSuccess) es = add_model_history(s, A, c.want, c.loss_out, c.G, nullptr);
+    return hip_status(es);
   }
   gcp_status st = check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
@@ -425,6 +472,7 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
     s->ev_used += 2;
   }
   hipError_t e = plain ? dense_plain_run(c, s->ws + s->L.plain, s->L.plain_bytes) : dense_fused_run(c);
+  if (e == hipSuccess) e = add_model_history(s, A, c.want, c.loss_out, c.G, grad_scale);
   return hip_status(e);
 }
 
@@ -452,6 +500,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
       void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
       SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs);
       e = sampled_run(c);
+      if (e == hipSuccess) e = add_model_history(s, A, kWantGrad, nullptr, G, nullptr);
       if (e != hipSuccess) break;
       const double n = (double)(s->adam_i + 1);
       const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
@@ -471,6 +520,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     }
     c.gs = s->ws + s->L.gs;
     e = dense_fused_run(c);
+    if (e == hipSuccess) e = add_model_history(s, c.A, kWantGrad, nullptr, c.G, nullptr);
     if (e != hipSuccess) break;
     const double n = (double)(s->adam_i + 1);
     const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
@@ -491,7 +541,9 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     }
   }
   if (slot >= 0 && e == hipSuccess) {
-    if (coo)
+    if (model_hist(s))
+      ;   // only s_t and t are kept
+    else if (coo)
       e = store_coo_slot(s, slot, X_t);
     else
       e = store_dense_slot(s, slot, X_t->vals);
@@ -726,6 +778,7 @@ gcp_status batch_check(gcp_stream* const* streams, int32_t n) {
     if (!s) return GCP_E_ARG;
     if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32) return GCP_E_UNSUPPORTED;
     if (s->p.rank > 32 || s->p.window > 31) return GCP_E_UNSUPPORTED;
+    if (model_hist(s)) return GCP_E_UNSUPPORTED;   // batches run the stored-slice history
     if (s->p.tau_f != streams[0]->p.tau_f) return GCP_E_ARG;
     if (s->st != streams[0]->st) return GCP_E_ARG;
   }

@@ -273,6 +273,25 @@ struct SampledCall {
   int* scnt;
   float* sS;
 };
+// Model-difference history term (eq. gcp_stream_problem_2): adds
+// 1/2 sum_h w_h ||[[Abar; s_h]] - [[A; s_h]]||^2 to *loss and its factor
+// gradient (times *grad_scale) to G, after the data term has written them.
+struct HistCall {
+  int I[3], R, nwin, dtype, want;
+  const void* A[3];
+  const void* Ab[3];        // previous step's factors
+  const void* shist;        // nwin x R stored weights
+  double c[kMaxNs];         // w_h of each window slot
+  void* G[3];
+  void* loss;
+  const void* grad_scale;
+  double* ws;               // hist_ws_bytes(R)
+  int* status;
+  hipStream_t stream;
+};
+size_t hist_ws_bytes(int R);
+hipError_t hist_run(const HistCall& c);
+
 // Workspace bytes of the row-sorted reduction for a stream (0: not used).
 size_t sampled_sorted_bytes(int I1, int I2, int I3, int R, int window, int64_t p, int64_t q);
 // Point c's row-sorted buffers into a workspace of sampled_sorted_bytes bytes

@@ -1,0 +1,165 @@
+// Model-difference history term of eq. gcp_stream_problem_2 (Section 4.1)
+// and its factor gradient, the history part of eq. spatial_gcp_grad
+// (Section 4.2).  The window keeps only the weights s_h; the term compares
+// the CP models of the previous step's factors Abar and of the current
+// factors A, both with weight s_h:
+//
+//   F_hist = 1/2 sum_h w_h ||[[Abar; s_h]] - [[A; s_h]]||_F^2
+//          = 1/2 <S_w, (*_k Abar_k' Abar_k) - 2 (*_k Abar_k' A_k) + (*_k A_k' A_k)>
+//   dF_hist/dA_k = A_k B_k - Abar_k C_k,
+//   B_k = (*_{l != k} A_l' A_l) o S_w,  C_k = (*_{l != k} Abar_l' A_l) o S_w,
+//   S_w = sum_h w_h s_h s_h'
+//
+// (* and o: Hadamard products of R x R matrices; the closed forms follow from
+// ||[[A; s]]||^2 = s' (*_k A_k' A_k) s and from diag(s) G diag(s) = G o s s').
+// Every sum is formed in FP64 in a fixed order: the terms nearly cancel when
+// the factors move little, and the results are bitwise repeatable.
+#include "common.hpp"
+
+namespace gcp {
+namespace {
+
+constexpr int kHistThreads = 256;
+
+// Offsets (in doubles) inside the history workspace.
+__host__ __device__ inline size_t gram_off(int kind, int k, int R) { return (size_t)(3 * kind + k) * R * R; }
+__host__ __device__ inline size_t b_off(int k, int R) { return (size_t)(9 + k) * R * R; }
+__host__ __device__ inline size_t c_off(int k, int R) { return (size_t)(12 + k) * R * R; }
+
+template <typename T>
+struct HistArgs {
+  const T* A[3];
+  const T* Ab[3];
+  const T* shist;
+  T* G[3];
+  T* loss;
+  const T* gscale;
+  double* ws;
+  int* status;
+  double c[kMaxNs];
+  int I[3];
+  int R, nwin, want;
+};
+
+// Row i of the Gram matrix X_k' Y_k (kind 0: A'A, 1: Abar'A, 2: Abar'Abar):
+// 64 columns per pass; four row chunks summed in order.
+template <typename T>
+__global__ void __launch_bounds__(kHistThreads) hist_gram(HistArgs<T> a) {
+  __shared__ double part[4][64];
+  const int i = blockIdx.x;
+  const int kind = blockIdx.y / 3, k = blockIdx.y % 3;
+  const T* X = kind == 0 ? a.A[k] : a.Ab[k];
+  const T* Y = kind == 2 ? a.Ab[k] : a.A[k];
+  const int R = a.R, n = a.I[k];
+  const int jl = threadIdx.x & 63, ch = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < R; j0 += 64) {
+    const int j = j0 + jl;
+    double s = 0.0;
+    if (j < R)
+      for (int r = ch; r < n; r += 4) s += (double)X[(size_t)r * R + i] * (double)Y[(size_t)r * R + j];
+    part[ch][jl] = s;
+    __syncthreads();
+    if (ch == 0 && j < R)
+      a.ws[gram_off(kind, k, R) + (size_t)i * R + j] = ((part[0][jl] + part[1][jl]) + part[2][jl]) + part[3][jl];
+    __syncthreads();
+  }
+}
+
+// S_w, the matrices B_k and C_k, and the objective term (added to the loss).
+template <typename T>
+__global__ void __launch_bounds__(kHistThreads) hist_combine(HistArgs<T> a) {
+  __shared__ double red[kHistThreads];
+  const int R = a.R;
+  const double* P = a.ws + gram_off(0, 0, R);
+  const double* Q = a.ws + gram_off(1, 0, R);
+  const double* O = a.ws + gram_off(2, 0, R);
+  const size_t RR = (size_t)R * R;
+  double f = 0.0;
+  for (int e = threadIdx.x; e < R * R; e += kHistThreads) {
+    const int i = e / R, j = e - (e / R) * R;
+    double sw = 0.0;
+    for (int h = 0; h < a.nwin; ++h) sw += a.c[h] * (double)a.shist[(size_t)h * R + i] * (double)a.shist[(size_t)h * R + j];
+    const double p0 = P[e], p1 = P[RR + e], p2 = P[2 * RR + e];
+    const double q0 = Q[e], q1 = Q[RR + e], q2 = Q[2 * RR + e];
+    const double o0 = O[e], o1 = O[RR + e], o2 = O[2 * RR + e];
+    a.ws[b_off(0, R) + e] = sw * (p1 * p2);
+    a.ws[b_off(1, R) + e] = sw * (p0 * p2);
+    a.ws[b_off(2, R) + e] = sw * (p0 * p1);
+    a.ws[c_off(0, R) + e] = sw * (q1 * q2);
+    a.ws[c_off(1, R) + e] = sw * (q0 * q2);
+    a.ws[c_off(2, R) + e] = sw * (q0 * q1);
+    f += sw * ((o0 * o1 * o2 - 2.0 * (q0 * q1 * q2)) + p0 * p1 * p2);
+  }
+  red[threadIdx.x] = f;
+  __syncthreads();
+  for (int w = kHistThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && (a.want & kWantLoss)) {
+    const T v = a.loss[0] + (T)(0.5 * red[0]);
+    a.loss[0] = v;
+    if (!isfinite(v)) atomicOr(a.status, (int)kStatusNonFinite);
+  }
+}
+
+// G_k += grad_scale * (A_k B_k - Abar_k C_k), one output per thread.
+template <typename T>
+__global__ void __launch_bounds__(kHistThreads) hist_grad(HistArgs<T> a) {
+  const int R = a.R;
+  const int n0 = a.I[0] * R, n1 = a.I[1] * R, n2 = a.I[2] * R;
+  const double sc = a.gscale ? (double)a.gscale[0] : 1.0;
+  for (int idx = blockIdx.x * kHistThreads + threadIdx.x; idx < n0 + n1 + n2; idx += gridDim.x * kHistThreads) {
+    int k = 0, e = idx;
+    if (e >= n0) { e -= n0; k = 1; if (e >= n1) { e -= n1; k = 2; } }
+    const int r = e / R, col = e - (e / R) * R;
+    const T* Ar = a.A[k] + (size_t)r * R;
+    const T* Br = a.Ab[k] + (size_t)r * R;
+    const double* B = a.ws + b_off(k, R);
+    const double* C = a.ws + c_off(k, R);
+    double s = 0.0;
+    for (int j = 0; j < R; ++j) s += (double)Ar[j] * B[(size_t)j * R + col] - (double)Br[j] * C[(size_t)j * R + col];
+    const T v = a.G[k][e] + (T)(sc * s);
+    a.G[k][e] = v;
+    if (!isfinite(v)) atomicOr(a.status, (int)kStatusNonFinite);
+  }
+}
+
+template <typename T>
+hipError_t hist_launch(const HistCall& c) {
+  HistArgs<T> a;
+  for (int k = 0; k < 3; ++k) {
+    a.A[k] = static_cast<const T*>(c.A[k]);
+    a.Ab[k] = static_cast<const T*>(c.Ab[k]);
+    a.G[k] = static_cast<T*>(c.G[k]);
+    a.I[k] = c.I[k];
+  }
+  a.shist = static_cast<const T*>(c.shist);
+  a.loss = static_cast<T*>(c.loss);
+  a.gscale = static_cast<const T*>(c.grad_scale);
+  a.ws = c.ws;
+  a.status = c.status;
+  for (int h = 0; h < kMaxNs; ++h) a.c[h] = h < c.nwin ? c.c[h] : 0.0;
+  a.R = c.R;
+  a.nwin = c.nwin;
+  a.want = c.want;
+  hipLaunchKernelGGL((hist_gram<T>), dim3(c.R, 9), dim3(kHistThreads), 0, c.stream, a);
+  hipLaunchKernelGGL((hist_combine<T>), dim3(1), dim3(kHistThreads), 0, c.stream, a);
+  if (c.want & kWantGrad) {
+    const int total = (c.I[0] + c.I[1] + c.I[2]) * c.R;
+    hipLaunchKernelGGL((hist_grad<T>), dim3((unsigned)std::min(2048, (total + kHistThreads - 1) / kHistThreads)),
+                       dim3(kHistThreads), 0, c.stream, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t hist_ws_bytes(int R) { return (size_t)15 * R * R * sizeof(double); }
+
+hipError_t hist_run(const HistCall& c) {
+  if (c.nwin <= 0 || !(c.want & (kWantLoss | kWantGrad))) return hipSuccess;
+  return c.dtype == 1 ? hist_launch<double>(c) : hist_launch<float>(c);
+}
+
+}  // namespace gcp

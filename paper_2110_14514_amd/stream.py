@@ -46,7 +46,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 beta2=0.999, adam_eps=1e-8, tau_f=1, seed=0,
                 dtype=torch.float32, plain=False, kernel: str = "auto",
                 slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0,
-                sampled_atomic: bool = False) -> N.GcpParams:
+                sampled_atomic: bool = False, hist: str = "slices") -> N.GcpParams:
     lib = N.load()
     n_p, n_q = p, q
     p = N.GcpParams()
@@ -63,6 +63,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.flags = (N.FLAG_PLAIN_SCRATCH if plain else 0) | {
         "auto": 0, "valu": N.FLAG_KERNEL_VALU, "mfma": N.FLAG_KERNEL_MFMA}[kernel] | (
         N.FLAG_SAMPLED_ATOMIC if sampled_atomic else 0)
+    p.hist = {"slices": N.HIST_SLICES, "model": N.HIST_MODEL}[hist]
     p.w, p.theta, p.lam, p.mu, p.lower = float(w), float(theta), float(lam), float(mu), float(lower)
     p.alpha_f, p.beta1, p.beta2, p.adam_eps = float(alpha_f), float(beta1), float(beta2), float(adam_eps)
     p.tau_f = int(tau_f)
@@ -97,7 +98,9 @@ class Stream:
         nbytes = gcp_workspace_size(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.hip_stream = torch.cuda.current_stream(self.device)
-        n_hist = len(X_hist)
+        # the model-difference history keeps no slices: its window is given
+        # by the weights and time stamps alone
+        n_hist = len(X_hist) if len(X_hist) else (len(t_hist) if t_hist is not None else 0)
         slices = (N.GcpSlice * max(1, n_hist))()
         for h, x in enumerate(X_hist):
             slices[h] = _slice(x)

@@ -1,0 +1,181 @@
+"""GPU parity of the model-difference history of eq. gcp_stream_problem_2:
+the window keeps only the weights s_h, and the objective and the factor
+gradient gain the term that compares the previous step's CP models with the
+current ones (formed on the device through R x R Gram matrices in FP64)."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import gcp_inputs as gi
+from oracle import gcp as og
+from oracle import model_hist as mh
+from oracle import sampled as osm
+from oracle.stream import StreamOracle
+
+from helpers import TOL, loss_err, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    ((5, 6, 7), 4, 2),
+    ((20, 30, 40), 16, 5),
+    ((17, 33, 129), 16, 3),
+    ((9, 4, 64), 32, 10),
+    ((12, 10, 70), 24, 30),
+    ((6, 5, 8), 64, 4),
+]
+
+
+def _case(dims, R, H, loss, seed, dtype=np.float32, drift=0.05):
+    """A window of weights, the previous step's factors A_old, and an
+    evaluation point A that has drifted from them."""
+    prob = gi.random_dense(dims, R, H, loss, seed=seed, w=1.1, theta=0.9, lam=0.05, mu=0.1,
+                           dtype=dtype)
+    g = np.random.default_rng(seed + 1000)
+    A_old = [(a + drift * g.uniform(-1, 1, size=a.shape)).astype(dtype) for a in prob.A]
+    return prob, A_old
+
+
+def _oracle(prob, A_old):
+    f64 = lambda a: np.asarray(a, np.float64)
+    p = SimpleNamespace(X_t=f64(prob.X_t), A=[f64(a) for a in prob.A], A_old=[f64(a) for a in A_old],
+                        s_t=f64(prob.s_t), s_hist=f64(prob.s_hist), t_hist=np.asarray(prob.t_hist),
+                        t=prob.t, w=prob.w, theta=prob.theta, lam=prob.lam, mu=prob.mu, loss=prob.loss)
+    F = mh.objective_model(p)
+    G, gs = mh.gradient_model(p)
+    c = og.history_weights(p.t, p.t_hist, p.w, p.theta)
+    cur = mh._current_only(p)
+    scale = og.loss_terms_abs(cur) + mh.history_objective(p.A, p.A_old, p.s_hist, c)
+    return F, G, gs, scale
+
+
+def _stream(prob, A_old, T, **kw):
+    from paper_2110_14514_amd import Stream
+    return Stream(prob.dims, prob.rank, len(prob.t_hist), prob.loss, [T(a) for a in A_old], [],
+                  T(np.asarray(prob.s_hist).reshape(len(prob.t_hist), prob.rank)), list(prob.t_hist),
+                  w=prob.w, theta=prob.theta, lam=prob.lam, mu=prob.mu, hist="model", **kw)
+
+
+@pytest.mark.parametrize("kernel", ["valu", "mfma"])
+@pytest.mark.parametrize("loss", og.LOSSES)
+@pytest.mark.parametrize("dims,R,H", SHAPES)
+def test_model_history_matches_oracle(dims, R, H, loss, kernel):
+    import torch
+    print("case: model history", dims, R, H, loss, kernel, flush=True)
+    prob, A_old = _case(dims, R, H, loss, seed=R + H)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    st = _stream(prob, A_old, T, kernel=kernel)
+    loss_v, G, g_s = st.loss_grad(T(prob.X_t), [T(a) for a in prob.A], T(prob.s_t))
+    torch.cuda.synchronize()
+    assert st.sync() == 0
+    F, Gr, gsr, scale = _oracle(prob, A_old)
+    assert loss_err(loss_v.item(), F, scale) <= TOL
+    for k in range(3):
+        assert rel_err(G[k].double().cpu().numpy(), Gr[k]) <= TOL, k
+    assert rel_err(g_s.double().cpu().numpy(), gsr) <= TOL
+
+
+def test_model_history_fp64_is_exact():
+    """The FP64 stream matches the FP64 oracle to rounding."""
+    import torch
+    print("case: model history fp64", flush=True)
+    prob, A_old = _case((7, 8, 9), 5, 4, "poisson_log", seed=3, dtype=np.float64)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    st = _stream(prob, A_old, T)
+    loss_v, G, g_s = st.loss_grad(T(prob.X_t), [T(a) for a in prob.A], T(prob.s_t))
+    torch.cuda.synchronize()
+    assert st.sync() == 0
+    F, Gr, gsr, scale = _oracle(prob, A_old)
+    assert loss_err(loss_v.item(), F, scale) <= 1e-12
+    for k in range(3):
+        assert rel_err(G[k].cpu().numpy(), Gr[k]) <= 1e-12
+    assert rel_err(g_s.cpu().numpy(), gsr) <= 1e-12
+
+
+def test_unchanged_factors_leave_the_single_slice_result():
+    """With A = A_old the history term vanishes: the result is that of a
+    stream with an empty window (the same fused data-term kernel)."""
+    import torch
+    from paper_2110_14514_amd import Stream
+    print("case: model history at A_old", flush=True)
+    prob, _ = _case((20, 30, 40), 16, 6, "gaussian", seed=5)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    st = _stream(prob, prob.A, T)
+    got = st.loss_grad(T(prob.X_t), [T(a) for a in prob.A], T(prob.s_t))
+    empty = Stream(prob.dims, prob.rank, 0, prob.loss, [T(a) for a in prob.A], lam=prob.lam, mu=prob.mu)
+    ref = empty.loss_grad(T(prob.X_t), [T(a) for a in prob.A], T(prob.s_t))
+    torch.cuda.synchronize()
+    assert abs(got[0].item() - ref[0].item()) <= 1e-6 * abs(ref[0].item())
+    for k in range(3):
+        assert torch.allclose(got[1][k], ref[1][k], rtol=1e-6, atol=1e-6 * float(ref[1][k].abs().max()))
+    assert torch.equal(got[2], ref[2])
+
+
+def test_sampled_model_history_matches_oracle():
+    """COO slices: the sampled data term of X_t alone plus the exact history."""
+    import torch
+    print("case: model history coo", flush=True)
+    prob = gi.sparse_problem(dims=(30, 40, 50), rank=8, window=3, nnz=2000, p=3000, q=3000, seed=7,
+                             loss="poisson_log")
+    prob.A = [a.astype(np.float32).astype(np.float64) for a in prob.A]
+    prob.s_t = prob.s_t.astype(np.float32).astype(np.float64)
+    prob.s_hist = prob.s_hist.astype(np.float32).astype(np.float64)
+    prob.X_t.vals = prob.X_t.vals.astype(np.float32).astype(np.float64)
+    prob.lam, prob.mu, prob.theta, prob.w = 0.05, 0.1, 0.9, 1.3
+    g = np.random.default_rng(8)
+    A_old = [(a + 0.05 * g.uniform(-1, 1, size=a.shape)).astype(np.float32).astype(np.float64) for a in prob.A]
+    from paper_2110_14514_amd import Stream
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    coo = lambda sl: (torch.from_numpy(np.ascontiguousarray(sl.coords, dtype=np.int32)).cuda(),
+                      T(sl.vals))
+    H = len(prob.t_hist)
+    st = Stream(prob.dims, prob.rank, H, prob.loss, [T(a) for a in A_old], [],
+                T(np.asarray(prob.s_hist).reshape(H, prob.rank)), list(prob.t_hist), w=prob.w,
+                theta=prob.theta, lam=prob.lam, mu=prob.mu, seed=prob.seed, slice_kind="coo",
+                max_nnz=prob.X_t.coords.shape[0], p=prob.p, q=prob.q, hist="model")
+    loss_v, G, g_s = st.loss_grad(coo(prob.X_t), [T(a) for a in prob.A], T(prob.s_t))
+    torch.cuda.synchronize()
+    assert st.sync() == 0
+    cur = SimpleNamespace(**vars(prob))
+    cur.X_hist = []
+    F, Gr, gsr = osm.sampled_loss_grad(cur, call=0)
+    c = og.history_weights(prob.t, prob.t_hist, prob.w, prob.theta)
+    F += mh.history_objective(prob.A, A_old, prob.s_hist, c)
+    Gh = mh.history_gradient(prob.A, A_old, prob.s_hist, c)
+    assert loss_err(loss_v.item(), F, max(abs(F), 1.0)) <= TOL
+    for k in range(3):
+        assert rel_err(G[k].double().cpu().numpy(), Gr[k] + Gh[k]) <= TOL, k
+    assert rel_err(g_s.double().cpu().numpy(), gsr) <= TOL
+
+
+def test_model_history_stream_steps_match_oracle():
+    """C1-shaped stream, model-difference history: LS weights, three Adam
+    iterations per step, reservoir push of s_t only, against the oracle."""
+    import torch
+    from paper_2110_14514_amd import Stream
+    print("case: model history stream", flush=True)
+    data = gi.c1_stream()
+    H = 3
+    g = gi.rng(98)
+    A0 = [(a + 0.1 * g.standard_normal(a.shape)).astype(np.float32) for a in data.A_true]
+    Xf = data.X.astype(np.float32)
+    S0 = data.S_true[:H].astype(np.float32)
+    kw = dict(w=1.0, theta=0.95, lam=0.01, mu=0.02, alpha_f=1e-2, tau_f=3, seed=11)
+    orc = StreamOracle([a.astype(np.float64) for a in A0], [], S0.astype(np.float64), np.arange(1, H + 1),
+                       loss="gaussian", window=H, hist="model", **kw)
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    st = Stream(Xf.shape[1:], 4, H, "gaussian", [tt(a) for a in A0], [], tt(S0), list(range(1, H + 1)),
+                hist="model", **kw)
+    for t in range(H, H + 8):
+        s_gpu = st.step(tt(Xf[t]))
+        s_or = orc.step(Xf[t].astype(np.float64))
+        torch.cuda.synchronize()
+        assert st.sync() == 0
+        assert rel_err(s_gpu.cpu().numpy(), s_or) <= 1e-4
+        info = st.info()
+        assert info["t"] == orc.t and info["slot_times"] == orc.slots
+    A_gpu = [a.cpu().numpy() for a in st.factors()]
+    for k in range(3):
+        assert rel_err(A_gpu[k], orc.A[k]) <= 1e-4
+        assert rel_err(A_gpu[k] - A0[k], orc.A[k] - A0[k]) <= 1e-2
