@@ -44,9 +44,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
+                    help="c2m: the dense data-term kernel (auto: chosen by the library)")
     ap.add_argument("--sampled-atomic", action="store_true",
                     help="c5: sum the MTTKRP rows with float atomics instead of the row-sorted lists")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -194,6 +196,38 @@ def bench_c4(args):
     return 0
 
 
+def bench_c2m(args):
+    """C2 shape with the model-difference history (eq. gcp_stream_problem_2):
+    the window keeps the 10 weights only; a step reads X_t once and adds the
+    history term through R x R Gram matrices."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream
+    dims, R, H, loss = (200, 200, 200), 16, 10, "poisson_log"
+    prob = gi.c2_problem(seed=1, dims=dims, rank=R, window=H)
+    g = np.random.default_rng(5)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    A_old = [a + 0.05 * g.uniform(-1, 1, size=a.shape) for a in prob.A]
+    st = Stream(dims, R, H, loss, [T(a) for a in A_old], [], T(prob.s_hist), list(prob.t_hist),
+                hist="model", kernel=args.kernel)
+    X_t, A, s_t = T(prob.X_t), [T(a) for a in prob.A], T(prob.s_t)
+    out = (torch.empty(1, device="cuda"), [torch.empty(n, R, device="cuda") for n in dims],
+           torch.empty(R, device="cuda"))
+    fn = lambda: st.loss_grad(X_t, A, s_t, out=out)
+    for _ in range(args.warmup):
+        fn()
+    st.kernel_timing(True, args.steps)
+    sec = _time(fn, args.steps, 0, torch.cuda.synchronize)
+    ms, n = st.kernel_time()
+    st.kernel_timing(False)
+    assert st.sync() == 0
+    omega = int(np.prod(dims))
+    _line("C2 shape with the model-difference history: 200x200x200 Poisson-count slice, rank 16, "
+          "window of 10 weights, Poisson-log", "grad steps/s", sec * 1e3, args.steps, args.warmup,
+          omega * 4, omega * (4 * R + 8 * R), ms / max(n, 1) / 1e3, {})
+    return 0
+
+
 def bench_c5(args):
     """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
     rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
@@ -243,7 +277,7 @@ def main():
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.workload != "c2":
-        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
+        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

@@ -41,27 +41,40 @@ struct HistArgs {
   int R, nwin, want;
 };
 
-// Row i of the Gram matrix X_k' Y_k (kind 0: A'A, 1: Abar'A, 2: Abar'Abar):
-// 64 columns per pass; four row chunks summed in order.
+// Row i of the Gram matrix X_k' Y_k (kind 0: A'A, 1: Abar'A, 2: Abar'Abar).
+// The workgroup's threads are (column j, row chunk c) with RP >= R columns
+// (a power of two) and 256 / RP chunks; chunk c takes rows c, c + nc, ...
+// with four independent partial sums (loads in flight), and the chunks are
+// added in order.
 template <typename T>
 __global__ void __launch_bounds__(kHistThreads) hist_gram(HistArgs<T> a) {
-  __shared__ double part[4][64];
+  __shared__ double part[kHistThreads];
   const int i = blockIdx.x;
   const int kind = blockIdx.y / 3, k = blockIdx.y % 3;
   const T* X = kind == 0 ? a.A[k] : a.Ab[k];
   const T* Y = kind == 2 ? a.Ab[k] : a.A[k];
   const int R = a.R, n = a.I[k];
-  const int jl = threadIdx.x & 63, ch = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < R; j0 += 64) {
-    const int j = j0 + jl;
-    double s = 0.0;
-    if (j < R)
-      for (int r = ch; r < n; r += 4) s += (double)X[(size_t)r * R + i] * (double)Y[(size_t)r * R + j];
-    part[ch][jl] = s;
-    __syncthreads();
-    if (ch == 0 && j < R)
-      a.ws[gram_off(kind, k, R) + (size_t)i * R + j] = ((part[0][jl] + part[1][jl]) + part[2][jl]) + part[3][jl];
-    __syncthreads();
+  int RP = 1;
+  while (RP < R) RP <<= 1;
+  const int nc = kHistThreads / RP;
+  const int j = threadIdx.x % RP, c = threadIdx.x / RP;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (j < R) {
+    int r = c;
+    for (; r + 3 * nc < n; r += 4 * nc) {
+      s0 += (double)X[(size_t)r * R + i] * (double)Y[(size_t)r * R + j];
+      s1 += (double)X[(size_t)(r + nc) * R + i] * (double)Y[(size_t)(r + nc) * R + j];
+      s2 += (double)X[(size_t)(r + 2 * nc) * R + i] * (double)Y[(size_t)(r + 2 * nc) * R + j];
+      s3 += (double)X[(size_t)(r + 3 * nc) * R + i] * (double)Y[(size_t)(r + 3 * nc) * R + j];
+    }
+    for (; r < n; r += nc) s0 += (double)X[(size_t)r * R + i] * (double)Y[(size_t)r * R + j];
+  }
+  part[threadIdx.x] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (c == 0 && j < R) {
+    double t = 0.0;
+    for (int cc = 0; cc < nc; ++cc) t += part[cc * RP + j];
+    a.ws[gram_off(kind, k, R) + (size_t)i * R + j] = t;
   }
 }
 
