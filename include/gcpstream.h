@@ -161,7 +161,9 @@ gcp_status gcp_workspace_size(const gcp_params* params, size_t* bytes);
  * (device, n_hist x R) and host time stamps t_hist are COPIED into the
  * workspace, so the caller may free them after the stream has executed the
  * copies.  The stream's time index starts at max(t_hist)+1 (1 if empty).
- * n_hist must not exceed params->window. */
+ * n_hist must not exceed params->window.  With GCP_HIST_MODEL no slice is
+ * kept: X_hist is ignored (it may be NULL) and the window is given by s_hist
+ * and t_hist alone; A0 is also the first "previous-step" factors. */
 gcp_status gcp_stream_init(const gcp_params* params, const void* const* A0,
                            int32_t n_hist, const gcp_slice* X_hist,
                            const void* s_hist, const int64_t* t_hist,
@@ -182,8 +184,13 @@ gcp_status gcp_stream_init(const gcp_params* params, const void* const* A0,
  * slice time stamp, call number, stratum + 2*attempt); the call number
  * starts at 0 and advances by one per sampled evaluation (including each
  * iteration of gcp_update_factors).  Zero draws are redrawn (at most 64
- * times, else GCP_E_NUMERIC) while they hit a stored entry.  Results are
- * accumulated with floating-point atomics (order-dependent rounding). */
+ * times, else GCP_E_NUMERIC) while they hit a stored entry.  The MTTKRP
+ * rows are summed through row-sorted lists (GCP_FLAG_SAMPLED_ATOMIC: one
+ * float atomic per draw and rank column); either way the order of the
+ * additions varies, so the rounding does.
+ * With GCP_HIST_MODEL the window term is the model difference of
+ * eq. gcp_stream_problem_2 (see gcp_hist), added after the data term of X_t;
+ * it uses the stream's previous-step factors and does not change g_s. */
 gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t,
                          const void* const* A, const void* s_t, uint32_t want,
                          void* loss, void* const* G, void* g_s);
