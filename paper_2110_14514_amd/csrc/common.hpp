@@ -111,6 +111,31 @@ struct Kahan {
   }
 };
 
+// Fixed-order reduction of partial slots (used by the single-stream and the
+// batched reduce kernels): a workgroup of 256 threads takes kRedOut outputs
+// and splits their slots into kRedChunks fixed chunks.
+constexpr int kRedOut = 16;     // outputs per workgroup
+constexpr int kRedChunks = 16;  // slot chunks per output
+constexpr int kRedUnroll = 8;   // loads in flight per thread
+
+// k += f(p[i]) for i = begin, begin + step, ... < end, in that order; the
+// loads of kRedUnroll consecutive terms are issued before their additions.
+template <typename T, typename F>
+__device__ __forceinline__ void kahan_strided(Kahan<T>& k, const T* p, size_t begin, size_t end, size_t step,
+                                              F f) {
+  for (size_t i = begin; i < end; i += kRedUnroll * step) {
+    T v[kRedUnroll];
+#pragma unroll
+    for (int u = 0; u < kRedUnroll; ++u) {
+      const size_t j = i + u * step;
+      v[u] = j < end ? p[j] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kRedUnroll; ++u)
+      if (i + u * step < end) k.add(f(v[u]));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dense fused objective / gradient over the current slice and the window.
 struct DenseCall {

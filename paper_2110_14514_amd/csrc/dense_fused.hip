@@ -294,28 +294,6 @@ struct ReduceArgs {
 // consecutive outputs so that every load is a contiguous row segment; the 16
 // chunk sums of an output are then added in chunk order.  Nothing depends
 // on scheduling, so results are bitwise reproducible.
-constexpr int kRedOut = 16;     // outputs per workgroup
-constexpr int kRedChunks = 16;  // slot chunks per output
-constexpr int kRedUnroll = 8;   // loads in flight per thread
-
-// k += f(p[i]) for i = begin, begin + step, ... < end, in that order; the
-// loads of kRedUnroll consecutive terms are issued before their additions.
-template <typename T, typename F>
-__device__ __forceinline__ void kahan_strided(Kahan<T>& k, const T* p, size_t begin, size_t end, size_t step,
-                                              F f) {
-  for (size_t i = begin; i < end; i += kRedUnroll * step) {
-    T v[kRedUnroll];
-#pragma unroll
-    for (int u = 0; u < kRedUnroll; ++u) {
-      const size_t j = i + u * step;
-      v[u] = j < end ? p[j] : T(0);
-    }
-#pragma unroll
-    for (int u = 0; u < kRedUnroll; ++u)
-      if (i + u * step < end) k.add(f(v[u]));
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
   const int R = r.R;

@@ -55,67 +55,96 @@ __device__ __forceinline__ uint64_t splitmix64_dev(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ float wave_sum_fixed_f(float v) {
-  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-  return v;
+
+// Outputs of every stream: G1 | G2 | G3 | g_s | loss; `outstart` is the
+// prefix sum of per-stream output counts.  The first nG workgroups take
+// kRedOut consecutive gradient outputs each (thread = output column x slot
+// chunk, consecutive threads reading consecutive outputs of a slot; the
+// chunk sums are added in order), the last nstreams workgroups form the
+// objectives.  Nothing depends on scheduling, so the results are bitwise
+// reproducible.  The objective workgroup of stream 0 resets the work
+// counters for the next launch.
+__device__ __forceinline__ int stream_of(const int64_t* __restrict__ outstart, int nstreams, int64_t o) {
+  int lo = 0, hi = nstreams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (outstart[mid] <= o) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
-// Outputs of every stream: G1 | G2 | G3 | g_s | loss, one wave per element.
-// `outstart` is the prefix sum of per-stream output counts.  The last step
-// resets the work counter for the next launch.
 __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchDesc* __restrict__ desc, int nstreams,
                                                            const int64_t* __restrict__ outstart, int64_t nout,
-                                                           int* __restrict__ counter, int want, int* status) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); o < nout; o += nwaves) {
-    int lo = 0, hi = nstreams - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (outstart[mid] <= o) lo = mid; else hi = mid - 1;
+                                                           int nG, int* __restrict__ counter, int want,
+                                                           int* status) {
+  const auto id = [](float v) { return v; };
+  if ((int)blockIdx.x < nG) {
+    __shared__ float part[kRedChunks][kRedOut];
+    const int ol = threadIdx.x % kRedOut, c = threadIdx.x / kRedOut;
+    const int64_t o = (int64_t)blockIdx.x * kRedOut + ol;
+    bool live = o < nout && (want & kWantGrad);
+    const float* src = nullptr;
+    const float* A = nullptr;
+    float* dst = nullptr;
+    int64_t stride = 1, e = 0;
+    int slots = 0;
+    float lam = 0.f;
+    if (live) {
+      const BatchDesc& d = desc[stream_of(outstart, nstreams, o)];
+      e = o - outstart[stream_of(outstart, nstreams, o)];
+      const int R = d.R;
+      const int64_t n1 = (int64_t)d.I1 * R, n2 = (int64_t)d.I2 * R, n3 = (int64_t)d.I3 * R;
+      lam = d.lam;
+      if (e < n1) {
+        src = d.G1p; stride = n1; slots = d.nb2; A = d.A; dst = d.outG[0];
+      } else if (e < n1 + n2) {
+        e -= n1; src = d.G2p; stride = n2; slots = d.nb1; A = d.A + d.fac_off1; dst = d.outG[1];
+      } else if (e < n1 + n2 + n3) {
+        e -= n1 + n2; src = d.G3p; stride = n3; slots = d.nwg; A = d.A + d.fac_off2; dst = d.outG[2];
+      } else if (e < n1 + n2 + n3 + R) {
+        e -= n1 + n2 + n3; src = d.gsp; stride = R; slots = d.nwg; A = d.st; dst = d.outgs; lam = d.mu;
+      } else {
+        live = false;   // the objective: formed by its own workgroup
+      }
     }
-    const BatchDesc& d = desc[lo];
-    const int64_t e = o - outstart[lo];
-    const int R = d.R;
-    const int n1 = d.I1 * R, n2 = d.I2 * R, n3 = d.I3 * R;
-    const float* src;
-    int64_t stride;
-    int slots;
-    float reg;
-    float* dst;
-    bool is_loss = false;
-    if (e < n1) {
-      src = d.G1p + e; stride = n1; slots = d.nb2; reg = d.lam * d.A[e]; dst = d.outG[0] + e;
-    } else if (e < n1 + n2) {
-      const int64_t k = e - n1;
-      src = d.G2p + k; stride = n2; slots = d.nb1; reg = d.lam * d.A[d.fac_off1 + k]; dst = d.outG[1] + k;
-    } else if (e < n1 + n2 + n3) {
-      const int64_t k = e - n1 - n2;
-      src = d.G3p + k; stride = n3; slots = d.nwg; reg = d.lam * d.A[d.fac_off2 + k]; dst = d.outG[2] + k;
-    } else if (e < n1 + n2 + n3 + R) {
-      const int64_t k = e - n1 - n2 - n3;
-      src = d.gsp + k; stride = R; slots = d.nwg; reg = d.mu * d.st[k]; dst = d.outgs + k;
-    } else {
-      is_loss = true;
-      src = d.lossp; stride = 1; slots = d.nwg; dst = d.outloss;
-      // regularisation of the objective, summed by the same wave
-      Kahan<float> kr;
-      for (int64_t i = lane; i < d.fac_elems; i += 64) kr.add(d.A[i] * d.A[i]);
-      Kahan<float> ks;
-      for (int i = lane; i < R; i += 64) ks.add(d.st[i] * d.st[i]);
-      reg = 0.5f * d.lam * wave_sum_fixed_f(kr.s) + 0.5f * d.mu * wave_sum_fixed_f(ks.s);
-    }
-    if (is_loss ? !(want & kWantLoss) : !(want & kWantGrad)) continue;
     Kahan<float> k;
-    for (int b = lane; b < slots; b += 64) k.add(src[(int64_t)b * stride]);
-    const float sum = wave_sum_fixed_f(k.s);
-    if (lane == 0) {
-      const float out = sum + reg;
-      *dst = out;
+    if (live) {
+      const int64_t s0 = (int64_t)slots * c / kRedChunks, s1 = (int64_t)slots * (c + 1) / kRedChunks;
+      kahan_strided(k, src + e, (size_t)(s0 * stride), (size_t)(s1 * stride), (size_t)stride, id);
+    }
+    part[c][ol] = k.s;
+    __syncthreads();
+    if (c == 0 && live) {
+      Kahan<float> t;
+#pragma unroll
+      for (int cc = 0; cc < kRedChunks; ++cc) t.add(part[cc][ol]);
+      const float out = t.s + lam * A[e];
+      dst[e] = out;
       if (!isfinite(out)) atomicOr(status, (int)kStatusNonFinite);
     }
+    return;
   }
-  if (blockIdx.x == 0 && threadIdx.x < kBatchVariants) counter[threadIdx.x] = 0;
+  // objective of stream si: data partials + lambda/2 sum ||A||^2 + mu/2 ||s||^2
+  const int si = (int)blockIdx.x - nG;
+  if (si == 0 && threadIdx.x < kBatchVariants) counter[threadIdx.x] = 0;
+  if (!(want & kWantLoss)) return;
+  const BatchDesc& d = desc[si];
+  const auto sq = [](float v) { return v * v; };
+  __shared__ float red[256];
+  Kahan<float> kl, kr, ks;
+  kahan_strided(kl, d.lossp, threadIdx.x, (size_t)d.nwg, 256, id);
+  kahan_strided(kr, d.A, threadIdx.x, (size_t)d.fac_elems, 256, sq);
+  kahan_strided(ks, d.st, threadIdx.x, (size_t)d.R, 256, sq);
+  red[threadIdx.x] = kl.s + 0.5f * d.lam * kr.s + 0.5f * d.mu * ks.s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.outloss[0] = red[0];
+    if (!isfinite(red[0])) atomicOr(status, (int)kStatusNonFinite);
+  }
 }
 
 // Adam Step (Algorithm 2) over the factor entries of every stream; the
@@ -223,9 +252,9 @@ hipError_t batch_grad_run(const BatchRun& b, int want) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int rblocks = (int)std::min<int64_t>(4096, (b.nout + 3) / 4);
-  hipLaunchKernelGGL(batch_reduce_kernel, dim3(std::max(1, rblocks)), dim3(256), 0, b.stream, b.desc, b.nstreams,
-                     b.outstart, b.nout, b.counter, want, b.status);
+  const int nG = (int)((b.nout + kRedOut - 1) / kRedOut);
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(nG + b.nstreams), dim3(256), 0, b.stream, b.desc, b.nstreams,
+                     b.outstart, b.nout, nG, b.counter, want, b.status);
   return hipGetLastError();
 }
 
