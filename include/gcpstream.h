@@ -312,6 +312,20 @@ gcp_status gcp_batch_sync_streams(gcp_batch* b);
 
 gcp_status gcp_batch_destroy(gcp_batch* b);
 
+/* The draws that the sampled gradient (Section 4.3, Algorithm 6) forms for
+ * one slice at sampler call number `call`: slice h_index (0: X_t, whose
+ * membership table is built here; h >= 1: window slot h-1 of a stored-slice
+ * stream).  Writes n = p + q draws in draw order (the p nonzero draws, then
+ * the q zero draws) into the device buffers coords (n x 3 int32, the
+ * multi-index) and weights (n floats: eta/p, zeta/q, or 0 for a zero draw
+ * that found no free cell in 64 attempts, which also sets the numeric
+ * status); *n (host) = p + q.  COO streams only; cap < p + q gives GCP_E_ARG.
+ * The stream's call counter does not advance.  For checking the sampler
+ * against its definition: the gradient kernels form their draws with the
+ * same device code. */
+gcp_status gcp_dump_samples(gcp_stream* s, const gcp_slice* X_t, int32_t h_index, int64_t call,
+                            int32_t* coords, float* weights, int64_t cap, int64_t* n);
+
 /* Measurement tooling.  With enable != 0, each following gcp_loss_grad
  * records a pair of HIP events on the stream's HIP stream immediately before
  * and after its main gradient kernel (up to `capacity` pairs; the events are

@@ -89,6 +89,8 @@ SIGNATURES = {
     "gcp_batch_destroy": (c_int32, [c_void_p]),
     "gcp_kernel_timing": (c_int32, [c_void_p, c_int32, c_int32]),
     "gcp_kernel_time": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
+    "gcp_dump_samples": (c_int32, [c_void_p, POINTER(GcpSlice), c_int32, c_int64, c_void_p, c_void_p,
+                                   c_int64, POINTER(c_int64)]),
     "gcp_status_string": (c_char_p, [c_int32]),
 }
 

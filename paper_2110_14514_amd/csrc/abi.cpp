@@ -201,7 +201,7 @@ hipError_t build_current_table(gcp_stream* s, const gcp_slice* X_t) {
 }
 
 SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t, int want,
-                         void* loss, void* const* G, void* g_s) {
+                         void* loss, void* const* G, void* g_s, int64_t call = -1) {
   SampledCall c;
   memset(&c, 0, sizeof(c));
   c.I1 = s->dims[0]; c.I2 = s->dims[1]; c.I3 = s->dims[2]; c.R = s->p.rank;
@@ -228,7 +228,8 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
   c.gs = g_s; c.loss_out = loss;
   c.lam = s->p.lambda; c.mu = s->p.mu;
   c.p = s->p.p; c.q = s->p.q; c.seed = s->p.seed;
-  c.call = s->sample_call++;
+  // a sampled evaluation takes the next call number; a sample dump names its own
+  c.call = call >= 0 ? call : s->sample_call++;
   c.status = s->status; c.stream = s->st;
   if (s->L.sorted_bytes) sampled_sorted_bind(c, s->ws + s->L.sorted, window_slices(s));
   return c;
@@ -593,6 +594,24 @@ gcp_status gcp_stream_sync(gcp_stream* s) {
     return GCP_E_NUMERIC;
   }
   return GCP_OK;
+}
+
+gcp_status gcp_dump_samples(gcp_stream* s, const gcp_slice* X_t, int32_t h_index, int64_t call, int32_t* coords,
+                            float* weights, int64_t cap, int64_t* n) {
+  if (!s || !coords || !weights || !n) return GCP_E_ARG;
+  if (s->p.slice_kind != GCP_SLICE_COO) return GCP_E_UNSUPPORTED;
+  if (call < 0 || h_index < 0 || h_index > (model_hist(s) ? 0 : s->nwin)) return GCP_E_ARG;
+  const int64_t total = s->p.p + s->p.q;
+  if (cap < total) return GCP_E_ARG;
+  gcp_status st = check_coo_slice(s, X_t);
+  if (st != GCP_OK) return st;
+  hipError_t e = h_index == 0 ? build_current_table(s, X_t) : hipSuccess;
+  if (e != hipSuccess) return hip_status(e);
+  const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
+  SampledCall c = sampled_call(s, X_t, A, s->ws + s->L.gs, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs, call);
+  *n = total;
+  return hip_status(sampled_dump_run(c, h_index, coords, weights));
 }
 
 gcp_status gcp_kernel_timing(gcp_stream* s, int32_t enable, int32_t capacity) {

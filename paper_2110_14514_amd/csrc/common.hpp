@@ -328,6 +328,8 @@ uint64_t table_capacity(int64_t max_nnz);
 hipError_t table_build(const int32_t* coords, int64_t nnz, int I2, int I3, uint64_t* tab, uint64_t cap,
                        hipStream_t stream);
 hipError_t sampled_run(const SampledCall& c);
+// Writes the draws of slice h of c (coordinates, weights) as sampled_run forms them.
+hipError_t sampled_dump_run(const SampledCall& c, int h, int32_t* coords, float* weights);
 
 // Unfused baseline: model, elementwise, per-mode MTTKRP kernels.
 size_t dense_plain_scratch_bytes(int I1, int I2, int I3, int R, int dtype);

@@ -37,6 +37,8 @@
 // it meets (a handful of atomics per run instead of one per draw and rank
 // column).  Atomic: phase 2 adds every draw's three rows to G with hardware
 // float atomics (3 R per draw; the L2 atomic rate bounds it).
+#include <cstring>
+
 #include "common.hpp"
 
 namespace gcp {
@@ -138,26 +140,24 @@ __device__ __forceinline__ bool is_stored(const uint64_t* __restrict__ tab, uint
 // writes the draw's record (REC = true).
 constexpr int kNB = 4;
 
-template <int LOSS, int SEG, bool REC>
-__global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t gwave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int h = (int)(gwave / a.waves_per_slice);
-  if (h >= a.ns) return;
-  const int64_t first = (gwave - (int64_t)h * a.waves_per_slice) * (64 * kNB);
+// Phase 1 of a wave's draws of slice h: NB draws per lane, draw number
+// first + 64 b + lane for b < NB.  The random reads of all of them (COO
+// entry, first membership-table slot) are issued before any is resolved.
+// Padded draws (number >= p + q) and nonzero draws of an empty slice get
+// weight 0 and index 0; a zero draw that still hits a stored entry after
+// kMaxAttempts redraws sets the sampler status and gets weight 0.
+template <int NB>
+__device__ __forceinline__ void form_draws(const SArgs& a, int h, int64_t first, int lane, int (&i1)[NB],
+                                           int (&i2)[NB], int (&i3)[NB], float (&x)[NB], float (&wgt)[NB]) {
   const int64_t total = a.p + a.q;
-  const int I1 = a.I1, I2 = a.I2, I3 = a.I3, R = a.R;
+  const int I1 = a.I1, I2 = a.I2, I3 = a.I3;
   const int32_t* coords = a.coords[h];
   const int64_t nnz = a.nnz[h];
-
-  // phase 1: kNB draws per lane (draw first + 64 b + lane)
-  int i1[kNB], i2[kNB], i3[kNB];
-  float x[kNB], wgt[kNB];
-  int64_t e[kNB];
-  uint64_t key[kNB], pos[kNB], tv[kNB];
-  bool nz[kNB], zd[kNB];
+  int64_t e[NB];
+  uint64_t key[NB], pos[NB], tv[NB];
+  bool nz[NB], zd[NB];
 #pragma unroll
-  for (int b = 0; b < kNB; ++b) {
+  for (int b = 0; b < NB; ++b) {
     const int64_t id = first + 64 * b + lane;
     i1[b] = i2[b] = i3[b] = 0;
     x[b] = 0.f;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   }
   // the random reads of every draw, issued together
 #pragma unroll
-  for (int b = 0; b < kNB; ++b) {
+  for (int b = 0; b < NB; ++b) {
     if (nz[b]) {
       i1[b] = coords[3 * e[b]];
       i2[b] = coords[3 * e[b] + 1];
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   // zero draws: finish the membership test (linear probing), redrawing while
   // the tuple is a stored entry
 #pragma unroll
-  for (int b = 0; b < kNB; ++b) {
+  for (int b = 0; b < NB; ++b) {
     if (!zd[b]) continue;
     const int64_t id = first + 64 * b + lane;
     bool ok = false;
@@ -228,6 +228,26 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
       i1[b] = i2[b] = i3[b] = 0;
     }
   }
+
+}
+
+
+template <int LOSS, int SEG, bool REC>
+__global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int h = (int)(gwave / a.waves_per_slice);
+  if (h >= a.ns) return;
+  const int64_t first = (gwave - (int64_t)h * a.waves_per_slice) * (64 * kNB);
+  const int64_t total = a.p + a.q;
+  const int I1 = a.I1, I2 = a.I2, I3 = a.I3, R = a.R;
+  const int32_t* coords = a.coords[h];
+  const int64_t nnz = a.nnz[h];
+
+  // phase 1: kNB draws per lane (draw first + 64 b + lane)
+  int i1[kNB], i2[kNB], i3[kNB];
+  float x[kNB], wgt[kNB];
+  form_draws<kNB>(a, h, first, lane, i1, i2, i3, x, wgt);
 
   // phase 2: SEG lanes per draw, lane = rank column
   constexpr int PER = 64 / SEG;
@@ -310,6 +330,30 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
     float l = lacc.s;
     for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o);
     if (lane == 0) unsafeAtomicAdd(a.loss, l);
+  }
+}
+
+// The draws of one slice (SArgs slice 0) as the gradient kernels form them:
+// draw number id -> coordinates (3 int32) and weight (eta/p or zeta/q, 0 for
+// a zero draw that found no free cell).
+__global__ void __launch_bounds__(256) sampled_dump(SArgs a, int32_t* __restrict__ coords_out,
+                                                    float* __restrict__ w_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 * kNB);
+  const int64_t total = a.p + a.q;
+  if (first >= total) return;
+  int i1[kNB], i2[kNB], i3[kNB];
+  float x[kNB], wgt[kNB];
+  form_draws<kNB>(a, 0, first, lane, i1, i2, i3, x, wgt);
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) {
+    const int64_t id = first + 64 * b + lane;
+    if (id < total) {
+      coords_out[3 * id] = i1[b];
+      coords_out[3 * id + 1] = i2[b];
+      coords_out[3 * id + 2] = i3[b];
+      w_out[id] = wgt[b];
+    }
   }
 }
 
@@ -662,6 +706,31 @@ hipError_t table_build(const int32_t* coords, int64_t nnz, int I2, int I3, uint6
   const unsigned ib = (unsigned)std::min<int64_t>(8192, (nnz + 255) / 256);
   hipLaunchKernelGGL(table_insert, dim3(ib), dim3(256), 0, stream, coords, nnz, I2, I3,
                      reinterpret_cast<unsigned long long*>(tab), cap - 1);
+  return hipGetLastError();
+}
+
+hipError_t sampled_dump_run(const SampledCall& c, int h, int32_t* coords, float* weights) {
+  if (h < 0 || h >= c.ns) return hipErrorInvalidValue;
+  SArgs a;
+  memset(&a, 0, sizeof(a));
+  const double omega = (double)c.I1 * c.I2 * c.I3;
+  a.tab[0] = c.tab[h];
+  a.coords[0] = c.coords[h];
+  a.vals[0] = static_cast<const float*>(c.vals[h]);
+  a.nnz[0] = c.nnz[h];
+  a.stamp[0] = (uint32_t)c.stamp[h];
+  a.w_nz[0] = c.p > 0 ? (float)((double)c.nnz[h] / (double)c.p) : 0.f;
+  a.w_z[0] = c.q > 0 ? (float)((omega - (double)c.nnz[h]) / (double)c.q) : 0.f;
+  a.tmask = c.tab_cap - 1;
+  a.status = c.status;
+  a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = 1;
+  a.p = c.p; a.q = c.q;
+  a.key0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
+  a.key1 = (uint32_t)(c.seed >> 32);
+  a.call = (uint32_t)c.call;
+  const int64_t waves = (c.p + c.q + 64 * kNB - 1) / (64 * kNB);
+  if (waves == 0) return hipSuccess;
+  hipLaunchKernelGGL(sampled_dump, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, c.stream, a, coords, weights);
   return hipGetLastError();
 }
 

@@ -138,6 +138,18 @@ class Stream:
                 "gcp_loss_grad")
         return loss, G, g_s
 
+    def dump_samples(self, X_t, h: int = 0, call: int = 0):
+        """The sampler's draws for slice h (0: X_t) at call number `call`:
+        (coords [n, 3] int32, weights [n]) on the device (COO streams)."""
+        n_all = int(self.params.p + self.params.q)
+        coords = torch.empty(n_all, 3, dtype=torch.int32, device=self.device)
+        weights = torch.empty(n_all, dtype=torch.float32, device=self.device)
+        n = c_int64(0)
+        sl = _slice(X_t)
+        N.check(self.lib.gcp_dump_samples(self.handle, byref(sl), int(h), int(call), _ptr(coords),
+                                          _ptr(weights), n_all, byref(n)), "gcp_dump_samples")
+        return coords[: n.value], weights[: n.value]
+
     def solve_st(self, X_t: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         s = out if out is not None else torch.empty(self.rank, dtype=self.dtype, device=self.device)
         sl = _dense_slice(X_t)

@@ -101,3 +101,57 @@ def test_sampled_update_factors_matches_oracle():
     info = st.info()
     assert info["t"] == prob.t + 1 and info["sample_call"] == 2
     assert info["n_window"] == 2          # window already full: reservoir kept or replaced
+
+
+def test_dump_samples_equal_the_oracle_draws():
+    """gcp_dump_samples returns the draws the gradient kernels form (the same
+    device code): they equal the oracle's draws from the published
+    generator, for the current slice and the window slots, at two call
+    numbers, and the stream's call counter does not move."""
+    print("case: sample dump", flush=True)
+    prob = _f32(gi.sparse_problem(dims=(30, 40, 50), rank=8, window=2, nnz=2000, p=3000, q=3000, seed=3,
+                                  loss="poisson_log"))
+    st, T = _stream(prob)
+    Xt = _dev_coo(prob.X_t)
+    for h in range(3):
+        sl = prob.X_t if h == 0 else prob.X_hist[h - 1]
+        stamp = prob.t if h == 0 else int(prob.t_hist[h - 1])
+        for call in (0, 5):
+            coords, w = st.dump_samples(Xt, h, call)
+            c_or, _, w_or = osm.sampled_terms(prob.loss, sl, None, None, prob.seed, stamp, call, prob.p, prob.q)
+            assert np.array_equal(coords.cpu().numpy(), c_or.astype(np.int32)), (h, call)
+            assert np.allclose(w.cpu().numpy(), w_or, rtol=1e-6), (h, call)
+            # zero draws avoid the stored entries; nonzero draws are stored entries
+            d = prob.dims
+            lin = lambda c: (c[:, 0].astype(np.int64) * d[1] + c[:, 1]) * d[2] + c[:, 2]
+            stored = set(lin(sl.coords).tolist())
+            got = lin(coords.cpu().numpy())
+            assert all(v in stored for v in got[:prob.p].tolist())
+            assert not any(v in stored for v in got[prob.p:].tolist())
+    assert st.sync() == 0
+    assert st.info()["sample_call"] == 0
+
+
+def test_dump_samples_are_uniform():
+    """Chi-square checks of the sampler on the device: nonzero draws uniform
+    over the stored entries, zero draws uniform over the other cells (fixed
+    seeds; thresholds at the 0.1% tail of the chi-square law)."""
+    from scipy.stats import chi2
+    print("case: sample uniformity", flush=True)
+    prob = _f32(gi.sparse_problem(dims=(4, 5, 6), rank=4, window=0, nnz=20, p=100_000, q=100_000, seed=9,
+                                  loss="poisson_log"))
+    st, T = _stream(prob)
+    coords, _ = st.dump_samples(_dev_coo(prob.X_t), 0, 0)
+    c = coords.cpu().numpy().astype(np.int64)
+    lin = (c[:, 0] * 5 + c[:, 1]) * 6 + c[:, 2]
+    stored = (prob.X_t.coords[:, 0].astype(np.int64) * 5 + prob.X_t.coords[:, 1]) * 6 + prob.X_t.coords[:, 2]
+    counts = np.bincount(lin, minlength=120)
+    nz = counts[stored]
+    zmask = np.ones(120, bool)
+    zmask[stored] = False
+    zc = counts[zmask]
+    assert nz.sum() >= prob.p and zc.sum() == prob.q
+    for obs in (np.bincount(np.searchsorted(np.sort(stored), lin[:prob.p]), minlength=len(stored)), zc):
+        exp = obs.sum() / len(obs)
+        stat = float(np.sum((obs - exp) ** 2 / exp))
+        assert stat < chi2.ppf(0.999, len(obs) - 1), stat
