@@ -118,6 +118,18 @@ def random_dense(dims, rank: int, window: int, loss: str, seed: int,
     return p.cast(dtype)
 
 
+def weight_problem(dims, rank: int, loss: str, seed: int, dtype=np.float32):
+    """Temporal-weight instance: planted factors A ~ U(-0.8, 0.8), weights
+    s* ~ U(1, 3), and X_t drawn around the model [[A; s*]].  Returns
+    (X_t, A, s*) with X_t and A in dtype."""
+    g = rng(seed)
+    dims = tuple(int(d) for d in dims)
+    A = [g.uniform(-0.8, 0.8, size=(n, rank)) for n in dims]
+    s_true = g.uniform(1.0, 3.0, size=rank)
+    X = _draw_data(g, loss, ktensor_full(A, s_true))
+    return X.astype(dtype), [a.astype(dtype) for a in A], s_true
+
+
 # ---------------------------------------------------------------- C1 ----
 @dataclass
 class GaussianStream:

@@ -96,6 +96,17 @@ enum {
  *   workspace holds no slice ring. */
 typedef enum { GCP_HIST_SLICES = 0, GCP_HIST_MODEL = 1 } gcp_hist;
 
+/* Temporal-weight solver of gcp_solve_st (gcp_params.tsolve).
+ * LS: the least-squares solve of Section 5 (Gaussian loss only).
+ * SGD: Algorithm 3 on dense slices, any loss: s <- 0 and fresh ADAM moments,
+ *   then at most kappa_w epochs while F > tol_w, each tau_w ADAM steps
+ *   (Algorithm 2, Step, rate alpha_w, iteration index i from 0) on the
+ *   gradient of F(s) = sum_i f(x_i, m_i(s)) + mu/2 ||s||^2 over X_t, then
+ *   F at the new s; an epoch that raised F is rolled back (s and the moments
+ *   return to the last accepted epoch, i goes back tau_w steps, the rate is
+ *   multiplied by 0.1).  Gradient and objective are exact over X_t. */
+typedef enum { GCP_TSOLVE_LS = 0, GCP_TSOLVE_SGD = 1 } gcp_tsolve;
+
 /* Flags of gcp_params.flags. */
 enum {
   GCP_FLAG_PLAIN_SCRATCH = 1, /* reserve the unfused path's scratch (2 slices) */
@@ -134,6 +145,12 @@ typedef struct {
                            * rounded up to a power of 2)                  */
   int64_t p, q;           /* COO: nonzero / zero samples per gradient      */
   uint64_t seed;          /* reservoir draws and the sampler               */
+  int32_t tsolve;         /* gcp_tsolve of gcp_solve_st                     */
+  int32_t tau_w;          /* SGD: ADAM steps per epoch, >= 1                */
+  int32_t kappa_w;        /* SGD: most epochs, 0..64                        */
+  int32_t reserved;       /* must be 0                                      */
+  double alpha_w;         /* SGD: initial ADAM rate, > 0                    */
+  double tol_w;           /* SGD: stop once F <= tol_w (-INFINITY: never)   */
 } gcp_params;
 
 /* One slice.  DENSE: vals holds prod(dims) values, coords is NULL.
@@ -206,11 +223,23 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t,
                                 void* loss, void* const* G, void* g_s);
 
 /* Temporal weights for X_t with the stream's factors held fixed (Alg. 1,
- * temporal step; eq. gcp_stream_temporal_problem).  Gaussian loss only: the
- * least-squares solve of Section 5, (Gamma + mu/2 I) s = Z^T vec(X_t) with
- * Gamma = hadamard_k A^(k)^T A^(k), formed and solved in FP64 on the device,
- * then s <- max(s, l).  Writes s_t (R values of the stream dtype). */
+ * temporal step; eq. gcp_stream_temporal_problem), by params->tsolve:
+ * GCP_TSOLVE_LS (Gaussian loss only): the least-squares solve of Section 5,
+ *   (Gamma + mu/2 I) s = Z^T vec(X_t) with Gamma = hadamard_k A^(k)^T A^(k),
+ *   formed and solved in FP64 on the device, then s <- max(s, l).
+ * GCP_TSOLVE_SGD (dense slices, any loss): Algorithm 3 as described at
+ *   gcp_tsolve, every decision taken on the device (kappa_w (tau_w + 1) + 2
+ *   kernel launches, no host synchronisation).  s_t is the solver's iterate
+ *   while it runs.
+ * Writes s_t (R values of the stream dtype). */
 gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t);
+
+/* State of the last GCP_TSOLVE_SGD solve (waits for the HIP stream): the
+ * objective at the returned weights, the final ADAM rate, the iteration
+ * index, the epochs run, and a mask whose bit e is set when epoch e was
+ * rolled back.  Any output may be NULL.  GCP_E_STATE for other solvers. */
+gcp_status gcp_solve_st_info(gcp_stream* s, double* F, double* alpha, int64_t* iters, int32_t* epochs,
+                             uint64_t* rolled);
 
 /* Factor update for X_t with weights s_t (Alg. 1 factor step; Alg. 4 inner
  * iterations): tau_f times [full gradient over X_t and the window, then the
@@ -294,13 +323,13 @@ gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want);
  * update with the draw made on the device, then t <- t+1. */
 gcp_status gcp_batch_update_factors(gcp_batch* b);
 
-/* Least-squares temporal weights (as gcp_solve_st) for every Gaussian-loss
- * stream of the batch, from its registered X_t and current factors, written
- * into its registered s_t buffer (which is then an input/output buffer).
- * Streams with other losses keep the s_t their caller wrote (the paper's
- * gradient-based temporal solver is not part of this library).  One pair of
- * launches per Gaussian stream on the batch's HIP stream; capturable.  A
- * failed Cholesky pivot is reported by gcp_batch_sync_streams. */
+/* Temporal weights (as gcp_solve_st) for every stream of the batch whose
+ * solver applies: GCP_TSOLVE_SGD streams and Gaussian-loss GCP_TSOLVE_LS
+ * streams, from the registered X_t and current factors, written into the
+ * registered s_t buffer (which is then an input/output buffer).  LS streams
+ * with other losses keep the s_t their caller wrote.  All launches go to the
+ * batch's HIP stream with no host synchronisation; capturable.  A failed
+ * Cholesky pivot or a non-finite value is reported by gcp_batch_sync_streams. */
 gcp_status gcp_batch_solve_st(gcp_batch* b);
 
 /* One time step of Alg. 1 for every stream: gcp_batch_solve_st, then

@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY (tests, smoke check and CPU baseline).
 Follows the body of Algorithm 1 (Section 4.3) in the paper's order:
   1. A <- A_old;
   2. the temporal weights s_t: the Gaussian least-squares solve that Section
-     5 allows in place of Algorithm 3 (see solve.py);
+     5 allows in place of Algorithm 3 (see solve.py), or with tsolve="sgd"
+     Algorithm 3 itself (see temporal_sgd.py);
   3. the factor update: tau_f iterations of Algorithm 4's inner loop, each a
      full gradient of eq. gcp_stream_problem_1 (stored-slice history, see
      gcp.py) followed by the ADAM Step of Algorithm 2 with the global
@@ -27,6 +28,7 @@ from .adam import adam_step
 from .gcp import gradient
 from .model_hist import gradient_model
 from .solve import ls_temporal
+from .temporal_sgd import temporal_sgd
 from .window import window_update
 
 
@@ -34,7 +36,8 @@ class StreamOracle:
     def __init__(self, A0, X_hist, s_hist, t_hist, *, loss="gaussian",
                  window=0, w=1.0, theta=1.0, lam=0.0, mu=0.0,
                  lower=-np.inf, alpha_f=1e-3, beta1=0.9, beta2=0.999,
-                 adam_eps=1e-8, tau_f=1, seed=0, hist="slices"):
+                 adam_eps=1e-8, tau_f=1, seed=0, hist="slices", tsolve="ls",
+                 tau_w=100, kappa_w=20, alpha_w=1.0, tol_w=-np.inf):
         self.A = [np.array(a, np.float64) for a in A0]
         self.A_old = [a.copy() for a in self.A]
         self.u = [np.zeros_like(a) for a in self.A]
@@ -48,7 +51,8 @@ class StreamOracle:
         self.cfg = SimpleNamespace(loss=loss, H=window, w=w, theta=theta,
                                    lam=lam, mu=mu, lower=lower,
                                    alpha_f=alpha_f, beta1=beta1, beta2=beta2,
-                                   eps=adam_eps, tau_f=tau_f, seed=seed)
+                                   eps=adam_eps, tau_f=tau_f, seed=seed, tsolve=tsolve,
+                                   tau_w=tau_w, kappa_w=kappa_w, alpha_w=alpha_w, tol_w=tol_w)
 
     def problem(self, X_t, s_t, A=None):
         c = self.cfg
@@ -60,6 +64,12 @@ class StreamOracle:
                                loss=c.loss)
 
     def solve_st(self, X_t):
+        c = self.cfg
+        if c.tsolve == "sgd":
+            s, self.solve_info = temporal_sgd(X_t, self.A, c.loss, mu=c.mu, lower=c.lower, alpha=c.alpha_w,
+                                              tau=c.tau_w, kappa=c.kappa_w, tol=c.tol_w, beta1=c.beta1,
+                                              beta2=c.beta2, eps=c.eps)
+            return s
         if self.cfg.loss != "gaussian":
             raise ValueError("least-squares temporal solve needs the Gaussian loss")
         return ls_temporal(X_t, self.A, self.cfg.mu, self.cfg.lower)

@@ -53,8 +53,10 @@ def weight_gradient(X_t, A, s, loss, mu) -> np.ndarray:
 
 def temporal_sgd(X_t, A, loss, *, mu=0.0, lower=-np.inf, alpha=1e-3, tau=10, kappa=5, tol=-np.inf,
                  beta1=0.9, beta2=0.999, eps=1e-8):
-    """Algorithm 3 with exact objective and gradient.  Returns (s, info)
-    where info records the objective after each epoch and the roll-backs."""
+    """Algorithm 3 with exact objective and gradient.  Returns (s, info):
+    info.F holds the accepted objective before the first epoch and after
+    each one, info.F_try the objective each epoch reached before its
+    decision, info.rolled the decisions."""
     R = np.asarray(A[0]).shape[1]
     s = np.zeros(R)
     u = np.zeros(R)
@@ -62,7 +64,7 @@ def temporal_sgd(X_t, A, loss, *, mu=0.0, lower=-np.inf, alpha=1e-3, tau=10, kap
     s_o, u_o, v_o = s.copy(), u.copy(), v.copy()
     F = weight_objective(X_t, A, s, loss, mu)
     i = 0
-    hist, rolled = [F], []
+    hist, tried, rolled = [F], [], []
     for _ in range(kappa):
         if not F > tol:
             break
@@ -72,6 +74,7 @@ def temporal_sgd(X_t, A, loss, *, mu=0.0, lower=-np.inf, alpha=1e-3, tau=10, kap
             s, u, v = adam_step(s, g, u, v, i, alpha, beta1, beta2, eps, lower)
             i += 1
         F = weight_objective(X_t, A, s, loss, mu)
+        tried.append(F)
         if F > F_old:
             s, u, v = s_o.copy(), u_o.copy(), v_o.copy()
             alpha *= DECAY
@@ -82,4 +85,4 @@ def temporal_sgd(X_t, A, loss, *, mu=0.0, lower=-np.inf, alpha=1e-3, tau=10, kap
             s_o, u_o, v_o = s.copy(), u.copy(), v.copy()
             rolled.append(False)
         hist.append(F)
-    return s, SimpleNamespace(F=hist, rolled=rolled, alpha=alpha, iters=i)
+    return s, SimpleNamespace(F=hist, F_try=tried, rolled=rolled, alpha=alpha, iters=i)

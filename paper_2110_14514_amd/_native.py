@@ -33,6 +33,8 @@ FLAG_KERNEL_MFMA = 4
 FLAG_SAMPLED_ATOMIC = 8
 HIST_SLICES = 0
 HIST_MODEL = 1
+TSOLVE_LS = 0
+TSOLVE_SGD = 1
 
 
 class GcpParams(Structure):
@@ -44,7 +46,9 @@ class GcpParams(Structure):
         ("lower", c_double), ("alpha_f", c_double), ("beta1", c_double),
         ("beta2", c_double), ("adam_eps", c_double), ("tau_f", c_int32),
         ("hist", c_int32), ("max_nnz", c_int64), ("p", c_int64),
-        ("q", c_int64), ("seed", c_uint64),
+        ("q", c_int64), ("seed", c_uint64), ("tsolve", c_int32),
+        ("tau_w", c_int32), ("kappa_w", c_int32), ("reserved", c_int32),
+        ("alpha_w", c_double), ("tol_w", c_double),
     ]
 
 
@@ -70,6 +74,8 @@ SIGNATURES = {
     "gcp_loss_grad_scaled": (c_int32, [c_void_p, POINTER(GcpSlice), POINTER(c_void_p), c_void_p,
                                        c_uint32, c_void_p, c_void_p, POINTER(c_void_p), c_void_p]),
     "gcp_solve_st": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p]),
+    "gcp_solve_st_info": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int64),
+                                    POINTER(c_int32), POINTER(c_uint64)]),
     "gcp_update_factors": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p]),
     "gcp_get_factors": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "gcp_factor_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),

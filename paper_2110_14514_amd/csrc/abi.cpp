@@ -19,7 +19,7 @@
 using namespace gcp;
 
 struct WsLayout {
-  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, total;
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -85,6 +85,13 @@ gcp_status check_params(const gcp_params* p) {
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
   if (p->hist != GCP_HIST_SLICES && p->hist != GCP_HIST_MODEL) return GCP_E_ARG;
+  if (p->reserved != 0) return GCP_E_ARG;
+  if (p->tsolve != GCP_TSOLVE_LS && p->tsolve != GCP_TSOLVE_SGD) return GCP_E_ARG;
+  if (p->tsolve == GCP_TSOLVE_SGD) {
+    if (p->tau_w < 1 || p->kappa_w < 0 || p->kappa_w > 64) return GCP_E_ARG;
+    if (!(p->alpha_w > 0.0) || !isfinite(p->alpha_w) || isnan(p->tol_w)) return GCP_E_ARG;
+    if (p->slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  }
   return GCP_OK;
 }
 
@@ -133,6 +140,8 @@ WsLayout layout_for(const gcp_params* p) {
                        : 0;
   L.sorted = off; off = align_up(off + L.sorted_bytes, 256);
   L.hist = off; off = align_up(off + (model ? hist_ws_bytes(R) : 0), 256);
+  L.tsgd = off;
+  off = align_up(off + (p->tsolve == GCP_TSOLVE_SGD ? tsgd_ws_bytes(I1, I2, I3, R, p->dtype == GCP_F64) : 0), 256);
   L.total = off;
   return L;
 }
@@ -275,6 +284,33 @@ DenseCall base_call(gcp_stream* s) {
 
 gcp_status hip_status(hipError_t e) { return e == hipSuccess ? GCP_OK : GCP_E_DEVICE; }
 
+// Algorithm 3 on X (dense, pitch I3) with the stream's factors A, iterating in s_t.
+TsgdCall tsgd_call(gcp_stream* s, const void* X, const void* const* A, void* s_t, int* status) {
+  TsgdCall c;
+  c.I1 = s->dims[0];
+  c.I2 = s->dims[1];
+  c.I3 = s->dims[2];
+  c.R = s->p.rank;
+  c.loss = s->p.loss;
+  c.dtype = s->p.dtype == GCP_F64;
+  c.X = X;
+  for (int k = 0; k < 3; ++k) c.A[k] = A[k];
+  c.s = s_t;
+  c.mu = s->p.mu;
+  c.lower = s->p.lower;
+  c.alpha = s->p.alpha_w;
+  c.beta1 = s->p.beta1;
+  c.beta2 = s->p.beta2;
+  c.eps = s->p.adam_eps;
+  c.tol = s->p.tol_w;
+  c.tau = s->p.tau_w;
+  c.kappa = s->p.kappa_w;
+  c.ws = s->ws + s->L.tsgd;
+  c.status = status;
+  c.stream = s->st;
+  return c;
+}
+
 uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -305,6 +341,11 @@ void gcp_params_default(gcp_params* p) {
   p->beta2 = 0.999;
   p->adam_eps = 1e-8;
   p->tau_f = 1;
+  p->tsolve = GCP_TSOLVE_LS;
+  p->tau_w = 100;
+  p->kappa_w = 20;
+  p->alpha_w = 1.0;
+  p->tol_w = -INFINITY;
 }
 
 gcp_status gcp_workspace_size(const gcp_params* p, size_t* bytes) {
@@ -479,13 +520,30 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
 
 gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
   if (!s || !s_t) return GCP_E_ARG;
-  if (s->p.loss != GCP_LOSS_GAUSSIAN) return GCP_E_UNSUPPORTED;
   if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  if (s->p.tsolve == GCP_TSOLVE_LS && s->p.loss != GCP_LOSS_GAUSSIAN) return GCP_E_UNSUPPORTED;
   gcp_status st = check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  if (s->p.tsolve == GCP_TSOLVE_SGD) return hip_status(tsgd_run(tsgd_call(s, X_t->vals, A, s_t, s->status)));
   return hip_status(ls_solve_run(s->dims[0], s->dims[1], s->dims[2], s->p.rank, s->p.dtype, X_t->vals, A, s->p.mu,
                                  s->p.lower, s_t, s->ws + s->L.ls, s->status, s->st));
+}
+
+gcp_status gcp_solve_st_info(gcp_stream* s, double* F, double* alpha, int64_t* iters, int32_t* epochs,
+                             uint64_t* rolled) {
+  if (!s) return GCP_E_ARG;
+  if (s->p.tsolve != GCP_TSOLVE_SGD) return GCP_E_STATE;
+  TsgdState h;
+  hipError_t e = hipMemcpyAsync(&h, s->ws + s->L.tsgd, sizeof(h), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return GCP_E_DEVICE;
+  if (F) *F = h.F;
+  if (alpha) *alpha = h.alpha;
+  if (iters) *iters = h.i;
+  if (epochs) *epochs = h.epoch;
+  if (rolled) *rolled = h.rolled;
+  return GCP_OK;
 }
 
 gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
@@ -1017,8 +1075,14 @@ gcp_status gcp_batch_solve_st(gcp_batch* b) {
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < b->streams.size() && e == hipSuccess; ++i) {
     gcp_stream* s = b->streams[i];
-    if (s->p.loss != GCP_LOSS_GAUSSIAN) continue;
     const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+    if (s->p.tsolve == GCP_TSOLVE_SGD) {
+      TsgdCall c = tsgd_call(s, b->io[i].X_t, A, const_cast<void*>(b->io[i].s_t), b->status);
+      c.stream = b->st;
+      e = tsgd_run(c);
+      continue;
+    }
+    if (s->p.loss != GCP_LOSS_GAUSSIAN) continue;
     e = ls_solve_run(s->dims[0], s->dims[1], s->dims[2], s->p.rank, s->p.dtype, b->io[i].X_t, A, s->p.mu,
                      s->p.lower, const_cast<void*>(b->io[i].s_t), s->ws + s->L.ls, b->status, b->st);
   }

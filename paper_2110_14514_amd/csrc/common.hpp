@@ -341,6 +341,33 @@ hipError_t ls_solve_run(int I1, int I2, int I3, int R, int dtype, const void* X,
                         const void* const* A, double mu, double lower, void* s_out,
                         void* scratch, int* status, hipStream_t st);
 
+// Temporal-weight solver of Algorithm 3 on a dense slice (ADAM epochs with
+// roll-back, decided on the device).  The workspace of tsgd_ws_bytes bytes
+// starts with the solver state.
+struct TsgdState {
+  double F;          // objective at the last accepted weights
+  double alpha;      // current ADAM rate
+  int64_t i;         // ADAM iteration index
+  uint64_t rolled;   // bit e set: epoch e was rolled back
+  int32_t done;      // stopping test met: later passes do nothing
+  int32_t epoch;     // epochs run
+  uint32_t ticket;   // last-workgroup counter of the running pass
+  int32_t pad;
+};
+struct TsgdCall {
+  int I1, I2, I3, R, loss, dtype;
+  const void* X;
+  const void* A[3];
+  void* s;           // weights: written from zero, the solver's iterate
+  double mu, lower, alpha, beta1, beta2, eps, tol;
+  int tau, kappa;
+  void* ws;
+  int* status;
+  hipStream_t stream;
+};
+size_t tsgd_ws_bytes(int I1, int I2, int I3, int R, int dtype);
+hipError_t tsgd_run(const TsgdCall& c);
+
 // ADAM step over a flat array (Algorithm 2, Step).
 hipError_t adam_run(int dtype, int64_t n, void* a, const void* g, void* u, void* v,
                     double alpha_t, double beta1, double beta2, double eps,

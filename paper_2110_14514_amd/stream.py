@@ -5,7 +5,7 @@ from __future__ import annotations
 
 import ctypes
 import math
-from ctypes import byref, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import byref, c_double, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 from typing import List, Optional, Sequence
 
 import torch
@@ -46,7 +46,9 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 beta2=0.999, adam_eps=1e-8, tau_f=1, seed=0,
                 dtype=torch.float32, plain=False, kernel: str = "auto",
                 slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0,
-                sampled_atomic: bool = False, hist: str = "slices") -> N.GcpParams:
+                sampled_atomic: bool = False, hist: str = "slices", tsolve: str = "ls",
+                tau_w: int = 100, kappa_w: int = 20, alpha_w: float = 1.0,
+                tol_w: float = -math.inf) -> N.GcpParams:
     lib = N.load()
     n_p, n_q = p, q
     p = N.GcpParams()
@@ -67,6 +69,8 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.w, p.theta, p.lam, p.mu, p.lower = float(w), float(theta), float(lam), float(mu), float(lower)
     p.alpha_f, p.beta1, p.beta2, p.adam_eps = float(alpha_f), float(beta1), float(beta2), float(adam_eps)
     p.tau_f = int(tau_f)
+    p.tsolve = {"ls": N.TSOLVE_LS, "sgd": N.TSOLVE_SGD}[tsolve]
+    p.tau_w, p.kappa_w, p.alpha_w, p.tol_w = int(tau_w), int(kappa_w), float(alpha_w), float(tol_w)
     p.seed = int(seed) & ((1 << 64) - 1)
     return p
 
@@ -155,6 +159,15 @@ class Stream:
         sl = _dense_slice(X_t)
         N.check(self.lib.gcp_solve_st(self.handle, byref(sl), _ptr(s)), "gcp_solve_st")
         return s
+
+    def solve_info(self) -> dict:
+        """State of the last SGD temporal solve (synchronises the stream)."""
+        F, alpha = c_double(0.0), c_double(0.0)
+        iters, epochs, rolled = c_int64(0), c_int32(0), c_uint64(0)
+        N.check(self.lib.gcp_solve_st_info(self.handle, byref(F), byref(alpha), byref(iters), byref(epochs),
+                                           byref(rolled)), "gcp_solve_st_info")
+        return {"F": F.value, "alpha": alpha.value, "iters": iters.value, "epochs": epochs.value,
+                "rolled": [bool(rolled.value >> e & 1) for e in range(epochs.value)]}
 
     def update_factors(self, X_t, s_t: torch.Tensor) -> None:
         sl = _slice(X_t)
@@ -286,7 +299,7 @@ class Batch:
         N.check(self.lib.gcp_batch_update_factors(self.handle), "gcp_batch_update_factors")
 
     def solve_st(self):
-        """LS temporal weights of every Gaussian stream into its registered s_t."""
+        """Temporal weights (SGD streams, and LS for Gaussian streams) into each registered s_t."""
         N.check(self.lib.gcp_batch_solve_st(self.handle), "gcp_batch_solve_st")
 
     def step(self):

@@ -40,7 +40,7 @@ def test_params_struct_layout_matches_header(lib):
     assert p.beta1 == 0.9 and p.beta2 == 0.999 and p.adam_eps == 1e-8
     assert p.w == 1.0 and p.theta == 1.0 and p.lam == 0.0 and p.mu == 0.0
     assert math.isinf(p.lower) and p.lower < 0 and p.tau_f == 1
-    assert ctypes.sizeof(N.GcpParams) == 168
+    assert ctypes.sizeof(N.GcpParams) == 200
     assert ctypes.sizeof(N.GcpSlice) == 32
 
 
@@ -71,6 +71,31 @@ def test_invalid_params_rejected(lib, field, value, code):
     from paper_2110_14514_amd import _native as N
     st, _ = _ws(lib, _params(lib, **{field: value}))
     assert st == getattr(N, code)
+
+
+@pytest.mark.parametrize("fields,code", [
+    ({"tsolve": 2}, "E_ARG"), ({"tsolve": -1}, "E_ARG"), ({"reserved": 1}, "E_ARG"),
+    ({"tsolve": 1, "tau_w": 0}, "E_ARG"), ({"tsolve": 1, "kappa_w": 65}, "E_ARG"),
+    ({"tsolve": 1, "kappa_w": -1}, "E_ARG"), ({"tsolve": 1, "alpha_w": 0.0}, "E_ARG"),
+    ({"tsolve": 1, "alpha_w": float("inf")}, "E_ARG"), ({"tsolve": 1, "tol_w": float("nan")}, "E_ARG"),
+    ({"tsolve": 1, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4}, "E_UNSUPPORTED"),
+])
+def test_invalid_temporal_solver_params_rejected(lib, fields, code):
+    from paper_2110_14514_amd import _native as N
+    st, _ = _ws(lib, _params(lib, **fields))
+    assert st == getattr(N, code)
+
+
+def test_temporal_sgd_defaults_and_workspace(lib):
+    """Table 1 parameters of Algorithm 3: the defaults are valid, only the SGD
+    solver reserves its (slice-independent, small) state."""
+    from paper_2110_14514_amd import _native as N
+    p = _params(lib)
+    assert p.tsolve == N.TSOLVE_LS and p.tau_w == 100 and p.kappa_w == 20
+    assert p.alpha_w == 1.0 and p.tol_w == float("-inf")
+    st, ls = _ws(lib, p)
+    st2, sgd = _ws(lib, _params(lib, tsolve=N.TSOLVE_SGD))
+    assert st == st2 == N.OK and ls < sgd < ls + (1 << 20)
 
 
 def test_workspace_monotone_in_window_and_dims(lib):
