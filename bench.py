@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
@@ -228,6 +228,45 @@ def bench_c2m(args):
     return 0
 
 
+def bench_c2w(args):
+    """C2 shape, temporal-weight solve of Algorithm 3 on the device (Poisson
+    counts around a planted rank-16 log-rate model, factors fixed): ADAM
+    epochs on s_t with the factors fixed, tau_w = 100 steps per epoch and
+    kappa_w = 20 epochs (the paper's experiment settings), so one solve is
+    20 x 101 + 1 passes over X_t.  Rate: solves per second; the roofline
+    entry is per pass (whole solve time over its passes, gaps included)."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream
+    dims, R, loss = (200, 200, 200), 16, "poisson_log"
+    tau, kappa = 100, 20
+    X, A, _ = gi.weight_problem(dims, R, loss, 1)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    st = Stream(dims, R, 0, loss, [T(a) for a in A], tsolve="sgd", tau_w=tau, kappa_w=kappa, alpha_w=0.05)
+    X_t = T(X)
+    s = torch.empty(R, device="cuda")
+    fn = lambda: st.solve_st(X_t, out=s)
+    cs = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0.record(cs)
+    sec = _time(fn, args.steps, 0, torch.cuda.synchronize)
+    ev1.record(cs)
+    torch.cuda.synchronize()
+    assert st.sync() == 0
+    info = st.solve_info()
+    passes = kappa * (tau + 1) + 1
+    per_pass = ev0.elapsed_time(ev1) / 1e3 / args.steps / passes
+    omega = int(np.prod(dims))
+    _line("C2 shape temporal-weight solve (Algorithm 3): 200x200x200 Poisson-count slice, rank 16, "
+          "100 ADAM steps x 20 epochs", "weight solves/s", sec * 1e3, args.steps, args.warmup,
+          omega * 4, omega * (4 * R + 8), per_pass,
+          {"passes_per_solve": passes, "solve_F": info["F"], "rolled_epochs": sum(info["rolled"])})
+    return 0
+
+
 def bench_c5(args):
     """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
     rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
@@ -277,7 +316,7 @@ def main():
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.workload != "c2":
-        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m}[args.workload](args)
+        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

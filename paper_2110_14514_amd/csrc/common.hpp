@@ -351,7 +351,6 @@ struct TsgdState {
   uint64_t rolled;   // bit e set: epoch e was rolled back
   int32_t done;      // stopping test met: later passes do nothing
   int32_t epoch;     // epochs run
-  uint32_t ticket;   // last-workgroup counter of the running pass
   int32_t pad;
 };
 struct TsgdCall {

@@ -12,9 +12,11 @@
 //
 // One pass over X_t forms either the gradient, followed by the ADAM Step of
 // Algorithm 2 on s, or the objective, followed by the epoch decision.  Every
-// workgroup writes a partial sum; the last workgroup to finish (a ticket
-// counter) adds the partials in a fixed order and applies the step or the
-// decision, so results are bitwise repeatable.
+// workgroup of the pass writes a partial sum; a one-workgroup kernel then adds
+// the partials in a fixed order and applies the step or the decision, so
+// results are bitwise repeatable.  (A last-workgroup ticket in the pass would
+// save that launch, but its device-scope fences write back and invalidate the
+// L2 of every XCD once per workgroup, which costs far more.)
 //
 // Work mapping: lane l of a wave owns the mode-3 index i3 = 64 c + l of its
 // workgroup's column chunk c and keeps row i3 of A^(3) in registers; a wave
@@ -28,7 +30,7 @@ namespace gcp {
 namespace {
 
 constexpr double kTsDecay = 0.1;   // rate factor of a rolled-back epoch
-constexpr int kTsRowUnroll = 4;    // slice rows whose loads are issued together
+constexpr int kTsRowUnroll = 8;    // slice rows whose loads are in flight together
 constexpr int kTsTargetBlocks = 512;        // workgroups per pass (two per compute unit)
 
 enum TsMode { kTsGrad = 0, kTsObjInit = 1, kTsObjEpoch = 2 };
@@ -36,7 +38,7 @@ enum TsMode { kTsGrad = 0, kTsObjInit = 1, kTsObjEpoch = 2 };
 template <typename T>
 struct TsArgs {
   const T* X;
-  const T* A1;
+  const T* A1;        // factors copied with rows padded to the rank tile (zeros past R)
   const T* A2;
   const T* A3;
   T* s;               // the weights (caller's output buffer)
@@ -100,9 +102,7 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
   constexpr int W = NT / 64;
   constexpr bool GRAD = MODE == kTsGrad;
   __shared__ T sh_s[RK];
-  __shared__ T sh_red[NT];
   __shared__ T sh_w[W][RK + 1];
-  __shared__ int sh_last;
   // written only by earlier launches, so every workgroup reads the same value
   if (a.st->done) return;
 
@@ -119,62 +119,89 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
   const bool valid = i3 < a.I3;
   T a3[RK];
 #pragma unroll
-  for (int j = 0; j < RK; ++j) a3[j] = (valid && j < R) ? a.A3[(size_t)i3 * R + j] : T(0);
+  for (int j = 0; j < RK; ++j) a3[j] = valid ? a.A3[(size_t)i3 * RK + j] : T(0);
 
-  const int64_t nrows = (int64_t)a.I1 * a.I2;
-  const int64_t g0 = (int64_t)grp * a.rows_per_grp;
-  const int64_t g1 = g0 + a.rows_per_grp < nrows ? g0 + a.rows_per_grp : nrows;
-  const int64_t per_wave = (g1 - g0 + W - 1) / W;
-  const int64_t r0 = g0 + wave * per_wave;
-  const int64_t r1 = r0 + per_wave < g1 ? r0 + per_wave : g1;
+  // rows of this wave: a contiguous run of (i1, i2); I1 I2 < 2^31
+  const int nrows = a.I1 * a.I2;
+  const int g0 = grp * a.rows_per_grp;
+  const int g1 = min(g0 + a.rows_per_grp, nrows);
+  const int per_wave = (g1 - g0 + W - 1) / W;
+  const int r0 = min(g0 + wave * per_wave, g1);
+  const int r1 = min(r0 + per_wave, g1);
 
-  T b[RK], acc[RK], acc2[RK], a1[RK];
+  T b[RK], acc[RK], acc2[RK];
 #pragma unroll
-  for (int j = 0; j < RK; ++j) acc[j] = acc2[j] = a1[j] = b[j] = T(0);
+  for (int j = 0; j < RK; ++j) acc[j] = acc2[j] = b[j] = T(0);
   T lacc = T(0);
-  int cur = -1;
+  // b_j = a1_j s_j a3_j for mode-1 index i1
+  auto load_b = [&](int i1) {
+#pragma unroll
+    for (int j = 0; j < RK; ++j) b[j] = a.A1[(size_t)i1 * RK + j] * sh_s[j] * a3[j];
+  };
+  // acc_j += a1_j acc2_j for the rows of mode-1 index i1 just finished
+  auto flush = [&](int i1) {
+#pragma unroll
+    for (int j = 0; j < RK; ++j) {
+      acc[j] += a.A1[(size_t)i1 * RK + j] * acc2[j];
+      acc2[j] = T(0);
+    }
+  };
 
-  for (int64_t r = r0; r < r1; r += kTsRowUnroll) {
-    T x[kTsRowUnroll];
+  if (r0 < r1) {
+    int i1 = r0 / a.I2;
+    int i2 = r0 - i1 * a.I2;
+    load_b(i1);
+    // lanes past I3 read a valid duplicate entry; their terms are masked
+    const int i3c = valid ? i3 : a.I3 - 1;
+    const int last = r1 - 1;
+    T xn[kTsRowUnroll];
 #pragma unroll
-    for (int u = 0; u < kTsRowUnroll; ++u)
-      x[u] = (valid && r + u < r1) ? a.X[(size_t)(r + u) * a.I3 + i3] : T(0);
+    for (int u = 0; u < kTsRowUnroll; ++u) xn[u] = a.X[(size_t)min(r0 + u, last) * a.I3 + i3c];
+    T a2n[RK];
 #pragma unroll
-    for (int u = 0; u < kTsRowUnroll; ++u) {
-      if (r + u >= r1) break;
-      const int i1 = (int)((r + u) / a.I2);
-      const int i2 = (int)((r + u) - (int64_t)i1 * a.I2);
-      if (i1 != cur) {
-        if (GRAD) {
+    for (int j = 0; j < RK; ++j) a2n[j] = a.A2[(size_t)i2 * RK + j];
+    for (int r = r0; r < r1; r += kTsRowUnroll) {
+      T x[kTsRowUnroll];
 #pragma unroll
-          for (int j = 0; j < RK; ++j) {
-            acc[j] += a1[j] * acc2[j];
-            acc2[j] = T(0);
-          }
-        }
+      for (int u = 0; u < kTsRowUnroll; ++u) {
+        x[u] = xn[u];
+        // next rows' loads are in flight while these rows are processed
+        xn[u] = a.X[(size_t)min(r + kTsRowUnroll + u, last) * a.I3 + i3c];
+      }
+#pragma unroll
+      for (int u = 0; u < kTsRowUnroll; ++u) {
+        if (r + u >= r1) break;
+        T a2[RK];
+        // the next row's a2 is requested before this row's arithmetic
+        const int i2n = i2 + 1 == a.I2 ? 0 : i2 + 1;
 #pragma unroll
         for (int j = 0; j < RK; ++j) {
-          a1[j] = j < R ? a.A1[(size_t)i1 * R + j] : T(0);
-          b[j] = a1[j] * sh_s[j] * a3[j];
+          a2[j] = a2n[j];
+          a2n[j] = a.A2[(size_t)i2n * RK + j];
         }
-        cur = i1;
-      }
-      const T* a2p = a.A2 + (size_t)i2 * R;
-      T a2[RK];
+        T m0 = T(0), m1 = T(0);
 #pragma unroll
-      for (int j = 0; j < RK; ++j) a2[j] = j < R ? a2p[j] : T(0);
-      T m = T(0);
+        for (int j = 0; j < RK; j += 2) {
+          m0 += a2[j] * b[j];
+          m1 += a2[j + 1] * b[j + 1];
+        }
+        T f, y;
+        TsLoss<T, LOSS>::fy(x[u], m0 + m1, f, y);
+        if (GRAD) {
 #pragma unroll
-      for (int j = 0; j < RK; ++j) m += a2[j] * b[j];
-      T f, y;
-      TsLoss<T, LOSS>::fy(x[u], m, f, y);
-      if (GRAD) {
-#pragma unroll
-        for (int j = 0; j < RK; ++j) acc2[j] += y * a2[j];
-      } else if (valid) {
-        lacc += f;
+          for (int j = 0; j < RK; ++j) acc2[j] += y * a2[j];
+        } else {
+          lacc += valid ? f : T(0);
+        }
+        if (++i2 == a.I2) {
+          if (GRAD) flush(i1);
+          i2 = 0;
+          ++i1;
+          if (r + u + 1 < r1) load_b(i1);
+        }
       }
     }
+    if (GRAD && i2 != 0) flush(i1);
   }
 
   T* prow = a.part + (size_t)blockIdx.x * (R + 1);
@@ -182,7 +209,7 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
     // lanes past I3 hold a3 = 0 and contribute nothing
 #pragma unroll
     for (int j = 0; j < RK; ++j) {
-      const T pj = wave_sum(a3[j] * (acc[j] + a1[j] * acc2[j]));
+      const T pj = wave_sum(a3[j] * acc[j]);
       if (lane == 0) sh_w[wave][j] = pj;
     }
     __syncthreads();
@@ -204,17 +231,21 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
     }
   }
 
-  // last workgroup: partials are published by a device-scope release before
-  // the ticket and read after a device-scope acquire
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) sh_last = atomicAdd(&a.st->ticket, 1u) == (unsigned)(a.nblk - 1);
-  __syncthreads();
-  if (!sh_last) return;
-  __threadfence();
+}
 
+// One workgroup: adds the pass's partial slots in a fixed order, then the
+// ADAM Step on s (gradient pass) or the epoch decision (objective pass).
+template <typename T, int RK, int MODE, int NT>
+__global__ void __launch_bounds__(NT) ts_final(TsArgs<T> a) {
+  __shared__ T sh_s[RK];
+  __shared__ T sh_red[NT];
+  __shared__ int sh_roll;
   TsgdState* st = a.st;
-  if (GRAD) {
+  if (st->done) return;
+  const int R = a.R;
+  if ((int)threadIdx.x < RK) sh_s[threadIdx.x] = (int)threadIdx.x < R ? a.s[threadIdx.x] : T(0);
+  __syncthreads();
+  if (MODE == kTsGrad) {
     T gj = sum_cols<T, NT, RK>(a.part, a.nblk, R + 1, 0, R, sh_red);
     if ((int)threadIdx.x < R) {
       const int j = threadIdx.x;
@@ -230,15 +261,11 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
       a.s[j] = sj > a.lower ? sj : a.lower;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      st->i += 1;
-      st->ticket = 0u;
-    }
+    if (threadIdx.x == 0) st->i += 1;
     return;
   }
 
   const T data = sum_cols<T, NT, 1>(a.part, a.nblk, R + 1, R, 1, sh_red);
-  __shared__ int sh_roll;
   if (threadIdx.x == 0) {
     T reg = T(0);
     for (int j = 0; j < R; ++j) reg += sh_s[j] * sh_s[j];
@@ -259,7 +286,6 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
       st->epoch += 1;
     }
     st->done = !(st->F > a.tol);
-    st->ticket = 0u;
     sh_roll = roll;
   }
   __syncthreads();
@@ -277,6 +303,20 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
   }
 }
 
+// Copies A^(1..3) (rows of R values) into rows of RK values, zeros past R.
+template <typename T>
+__global__ void ts_pad(const T* __restrict__ A1, const T* __restrict__ A2, const T* __restrict__ A3, T* __restrict__ P,
+                       int I1, int I2, int I3, int R, int RK) {
+  const int64_t n = ((int64_t)I1 + I2 + I3) * RK;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / RK;
+    const int j = (int)(e - row * RK);
+    const T* A = row < I1 ? A1 : (row < I1 + I2 ? A2 : A3);
+    const int64_t i = row < I1 ? row : (row < I1 + I2 ? row - I1 : row - I1 - I2);
+    P[e] = j < R ? A[i * R + j] : T(0);
+  }
+}
+
 template <typename T>
 __global__ void ts_init(T* s, T* u, T* v, T* so, T* uo, T* vo, int R, TsgdState* st, double alpha) {
   const int j = threadIdx.x;
@@ -288,7 +328,6 @@ __global__ void ts_init(T* s, T* u, T* v, T* so, T* uo, T* vo, int R, TsgdState*
     st->rolled = 0ull;
     st->done = 0;
     st->epoch = 0;
-    st->ticket = 0u;
   }
 }
 
@@ -314,17 +353,26 @@ constexpr int ts_threads() { return sizeof(T) * RK <= 128 ? 512 : 256; }
 template <typename T, int LOSS, int RK>
 void ts_launch_mode(int mode, const TsArgs<T>& a, hipStream_t st) {
   constexpr int NT = ts_threads<T, RK>();
-  if (mode == kTsGrad)
+  if (mode == kTsGrad) {
     hipLaunchKernelGGL((ts_pass<T, LOSS, RK, kTsGrad, NT>), dim3(a.nblk), dim3(NT), 0, st, a);
-  else if (mode == kTsObjInit)
+    hipLaunchKernelGGL((ts_final<T, RK, kTsGrad, 512>), dim3(1), dim3(512), 0, st, a);
+  } else if (mode == kTsObjInit) {
     hipLaunchKernelGGL((ts_pass<T, LOSS, RK, kTsObjInit, NT>), dim3(a.nblk), dim3(NT), 0, st, a);
-  else
+    hipLaunchKernelGGL((ts_final<T, RK, kTsObjInit, 512>), dim3(1), dim3(512), 0, st, a);
+  } else {
     hipLaunchKernelGGL((ts_pass<T, LOSS, RK, kTsObjEpoch, NT>), dim3(a.nblk), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((ts_final<T, RK, kTsObjEpoch, 512>), dim3(1), dim3(512), 0, st, a);
+  }
 }
+
+// Rank tile of the kernels for rank R.
+int ts_rank_tile(int R) { return R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64; }
 
 template <typename T, int LOSS>
 void ts_launch_loss(int mode, const TsArgs<T>& a, hipStream_t st) {
-  if (a.R <= 16)
+  if (a.R <= 8)
+    ts_launch_mode<T, LOSS, 8>(mode, a, st);
+  else if (a.R <= 16)
     ts_launch_mode<T, LOSS, 16>(mode, a, st);
   else if (a.R <= 32)
     ts_launch_mode<T, LOSS, 32>(mode, a, st);
@@ -344,6 +392,12 @@ void ts_launch(int loss, int mode, const TsArgs<T>& a, hipStream_t st) {
 
 size_t ts_vec_bytes(int R, size_t es) { return align_up((size_t)R * es, 64); }
 
+// Workspace: state (256 B), u, v, s_o, u_o, v_o, padded factors, partial slots.
+size_t ts_pad_off(int R, size_t es) { return align_up(256 + 5 * ts_vec_bytes(R, es), 256); }
+size_t ts_part_off(int I1, int I2, int I3, int R, size_t es) {
+  return ts_pad_off(R, es) + align_up(((size_t)I1 + I2 + I3) * ts_rank_tile(R) * es, 256);
+}
+
 template <typename T>
 hipError_t ts_run(const TsgdCall& c) {
   const TsGeom g = ts_geom(c.I1, c.I2, c.I3);
@@ -351,9 +405,11 @@ hipError_t ts_run(const TsgdCall& c) {
   const size_t vb = ts_vec_bytes(c.R, sizeof(T));
   TsArgs<T> a;
   a.X = static_cast<const T*>(c.X);
-  a.A1 = static_cast<const T*>(c.A[0]);
-  a.A2 = static_cast<const T*>(c.A[1]);
-  a.A3 = static_cast<const T*>(c.A[2]);
+  const int RK = ts_rank_tile(c.R);
+  T* pad = reinterpret_cast<T*>(base + ts_pad_off(c.R, sizeof(T)));
+  a.A1 = pad;
+  a.A2 = pad + (size_t)c.I1 * RK;
+  a.A3 = pad + ((size_t)c.I1 + c.I2) * RK;
   a.s = static_cast<T*>(c.s);
   a.st = reinterpret_cast<TsgdState*>(base);
   char* vec = base + 256;
@@ -362,7 +418,7 @@ hipError_t ts_run(const TsgdCall& c) {
   a.so = reinterpret_cast<T*>(vec + 2 * vb);
   a.uo = reinterpret_cast<T*>(vec + 3 * vb);
   a.vo = reinterpret_cast<T*>(vec + 4 * vb);
-  a.part = reinterpret_cast<T*>(base + align_up(256 + 5 * vb, 256));
+  a.part = reinterpret_cast<T*>(base + ts_part_off(c.I1, c.I2, c.I3, c.R, sizeof(T)));
   a.status = c.status;
   a.I1 = c.I1;
   a.I2 = c.I2;
@@ -380,6 +436,10 @@ hipError_t ts_run(const TsgdCall& c) {
   a.beta1 = c.beta1;
   a.beta2 = c.beta2;
   a.tol = c.tol;
+  const int64_t npad = ((int64_t)c.I1 + c.I2 + c.I3) * RK;
+  hipLaunchKernelGGL(ts_pad<T>, dim3((unsigned)std::min<int64_t>(1024, (npad + 255) / 256)), dim3(256), 0, c.stream,
+                     static_cast<const T*>(c.A[0]), static_cast<const T*>(c.A[1]), static_cast<const T*>(c.A[2]),
+                     pad, c.I1, c.I2, c.I3, c.R, RK);
   hipLaunchKernelGGL(ts_init<T>, dim3(1), dim3(64), 0, c.stream, a.s, a.u, a.v, a.so, a.uo, a.vo, c.R, a.st,
                      c.alpha);
   ts_launch<T>(c.loss, kTsObjInit, a, c.stream);
@@ -395,7 +455,7 @@ hipError_t ts_run(const TsgdCall& c) {
 size_t tsgd_ws_bytes(int I1, int I2, int I3, int R, int dtype) {
   const size_t es = dtype ? 8 : 4;
   const TsGeom g = ts_geom(I1, I2, I3);
-  return align_up(256 + 5 * ts_vec_bytes(R, es), 256) + align_up((size_t)g.nblk * (R + 1) * es, 256);
+  return ts_part_off(I1, I2, I3, R, es) + align_up((size_t)g.nblk * (R + 1) * es, 256);
 }
 
 hipError_t tsgd_run(const TsgdCall& c) { return c.dtype ? ts_run<double>(c) : ts_run<float>(c); }

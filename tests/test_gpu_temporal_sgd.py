@@ -222,3 +222,23 @@ def test_batch_solve_and_graph_replay():
             torch.cuda.synchronize()
             assert torch.equal(Sb[i], ref), (rep, i)
     assert b.sync_streams() == 0
+
+
+def test_c2_size_weight_solve():
+    """The C2 shape (200 x 200 x 200 Poisson-count slice, rank 16) in the
+    bench's launch configuration, with a short solve the FP64 oracle finishes
+    in seconds: decisions, objective and weights."""
+    import torch
+    print("case: c2 weight solve", flush=True)
+    dims, R = (200, 200, 200), 16
+    X, A, _ = gi.weight_problem(dims, R, "poisson_log", 1)
+    st = _stream(dims, R, "poisson_log", A, torch.float32, tau_w=3, kappa_w=2, alpha_w=0.05)
+    s = st.solve_st(torch.from_numpy(X).cuda()).double().cpu().numpy()
+    info = st.solve_info()
+    assert st.sync() == 0
+    ref, rinfo = ots.temporal_sgd(X.astype(np.float64), [a.astype(np.float64) for a in A], "poisson_log",
+                                  alpha=0.05, tau=3, kappa=2)
+    assert _clear_decisions(rinfo, 1e-4)
+    assert info["rolled"] == rinfo.rolled
+    assert abs(info["F"] - rinfo.F[-1]) <= 1e-5 * abs(rinfo.F[-1])
+    assert rel_err(s, ref) <= 1e-4
