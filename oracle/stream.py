@@ -10,13 +10,19 @@ Follows the body of Algorithm 1 (Section 4.3) in the paper's order:
   3. the factor update: tau_f iterations of Algorithm 4's inner loop, each a
      full gradient of eq. gcp_stream_problem_1 (stored-slice history, see
      gcp.py) followed by the ADAM Step of Algorithm 2 with the global
-     iteration index i carried across slices;
+     iteration index i carried across slices; with kappa_f > 0, Algorithm 4's
+     epochs: at most kappa_f epochs of tau_f iterations while F > tol_f, each
+     followed by the objective, and the ADAM Update of Algorithm 2 (keep the
+     epoch, or return A and the moments to the last accepted epoch, multiply
+     the rate by 0.1 and rewind i by tau_f).  The objective is exact (no
+     regulariser on s_t, as Algorithm 4 passes mu = 0), the rate and the saved
+     copies persist across time steps, and the saved solution starts as the
+     initial factors;
   4. the reservoir window update (window.py), storing X_t and s_t (with the
      model-difference history of eq. gcp_stream_problem_2, hist="model",
      only s_t is stored and the gradient is that of model_hist.py);
   5. A_old <- A.
-Algorithm 4's epoch loop with its sampled objective estimate and
-roll-back is not part of this step; every iteration is kept.
+Without epochs (kappa_f = 0) every iteration is kept.
 """
 from __future__ import annotations
 
@@ -28,7 +34,9 @@ from .adam import adam_step
 from .gcp import gradient
 from .model_hist import gradient_model
 from .solve import ls_temporal
-from .temporal_sgd import temporal_sgd
+from .gcp import objective
+from .model_hist import objective_model
+from .temporal_sgd import DECAY, temporal_sgd
 from .window import window_update
 
 
@@ -37,12 +45,16 @@ class StreamOracle:
                  window=0, w=1.0, theta=1.0, lam=0.0, mu=0.0,
                  lower=-np.inf, alpha_f=1e-3, beta1=0.9, beta2=0.999,
                  adam_eps=1e-8, tau_f=1, seed=0, hist="slices", tsolve="ls",
-                 tau_w=100, kappa_w=20, alpha_w=1.0, tol_w=-np.inf):
+                 tau_w=100, kappa_w=20, alpha_w=1.0, tol_w=-np.inf, kappa_f=0, tol_f=-np.inf):
         self.A = [np.array(a, np.float64) for a in A0]
         self.A_old = [a.copy() for a in self.A]
         self.u = [np.zeros_like(a) for a in self.A]
         self.v = [np.zeros_like(a) for a in self.A]
         self.i = 0
+        self.alpha_f = alpha_f
+        self.A_o = [a.copy() for a in self.A]
+        self.u_o = [np.zeros_like(a) for a in self.A]
+        self.v_o = [np.zeros_like(a) for a in self.A]
         self.slots = [int(t) for t in t_hist]
         self.hist = hist
         self.Xw = [np.array(x, np.float64) for x in X_hist] if hist == "slices" else []
@@ -52,7 +64,8 @@ class StreamOracle:
                                    lam=lam, mu=mu, lower=lower,
                                    alpha_f=alpha_f, beta1=beta1, beta2=beta2,
                                    eps=adam_eps, tau_f=tau_f, seed=seed, tsolve=tsolve,
-                                   tau_w=tau_w, kappa_w=kappa_w, alpha_w=alpha_w, tol_w=tol_w)
+                                   tau_w=tau_w, kappa_w=kappa_w, alpha_w=alpha_w, tol_w=tol_w,
+                                   kappa_f=kappa_f, tol_f=tol_f)
 
     def problem(self, X_t, s_t, A=None):
         c = self.cfg
@@ -74,16 +87,52 @@ class StreamOracle:
             raise ValueError("least-squares temporal solve needs the Gaussian loss")
         return ls_temporal(X_t, self.A, self.cfg.mu, self.cfg.lower)
 
-    def update_factors(self, X_t, s_t):
+    def factor_objective(self, X_t, s_t) -> float:
+        """The objective Algorithm 4 compares: every term but mu/2 ||s_t||^2."""
+        prob = self.problem(X_t, s_t)
+        prob.mu = 0.0
+        return objective(prob) if self.hist == "slices" else objective_model(prob)
+
+    def _iterations(self, X_t, s_t, n):
         c = self.cfg
-        for _ in range(c.tau_f):
+        for _ in range(n):
             prob = self.problem(X_t, s_t)
             G, _ = gradient(prob) if self.hist == "slices" else gradient_model(prob)
             for k in range(len(self.A)):
                 self.A[k], self.u[k], self.v[k] = adam_step(
-                    self.A[k], G[k], self.u[k], self.v[k], self.i, c.alpha_f,
+                    self.A[k], G[k], self.u[k], self.v[k], self.i, self.alpha_f,
                     c.beta1, c.beta2, c.eps, c.lower)
             self.i += 1
+
+    def update_factors(self, X_t, s_t):
+        c = self.cfg
+        if c.kappa_f == 0:
+            self._iterations(X_t, s_t, c.tau_f)
+        else:
+            F = self.factor_objective(X_t, s_t)
+            info = SimpleNamespace(F=[F], F_try=[], rolled=[])
+            for _ in range(c.kappa_f):
+                if not F > c.tol_f:
+                    break
+                F_old = F
+                self._iterations(X_t, s_t, c.tau_f)
+                F = self.factor_objective(X_t, s_t)
+                info.F_try.append(F)
+                if F > F_old:
+                    self.A = [a.copy() for a in self.A_o]
+                    self.u = [a.copy() for a in self.u_o]
+                    self.v = [a.copy() for a in self.v_o]
+                    self.alpha_f *= DECAY
+                    self.i -= c.tau_f
+                    F = F_old
+                    info.rolled.append(True)
+                else:
+                    self.A_o = [a.copy() for a in self.A]
+                    self.u_o = [a.copy() for a in self.u]
+                    self.v_o = [a.copy() for a in self.v]
+                    info.rolled.append(False)
+                info.F.append(F)
+            self.fac_info = info
         new_slots, slot = window_update(self.slots, c.H, self.t, c.seed)
         if slot >= 0:
             keep = self.hist == "slices"
