@@ -148,9 +148,11 @@ typedef struct {
   int32_t tsolve;         /* gcp_tsolve of gcp_solve_st                     */
   int32_t tau_w;          /* SGD: ADAM steps per epoch, >= 1                */
   int32_t kappa_w;        /* SGD: most epochs, 0..64                        */
-  int32_t reserved;       /* must be 0                                      */
+  int32_t kappa_f;        /* factor epochs per gcp_update_factors, 0..64;
+                           * 0: tau_f iterations, all kept (see there)     */
   double alpha_w;         /* SGD: initial ADAM rate, > 0                    */
   double tol_w;           /* SGD: stop once F <= tol_w (-INFINITY: never)   */
+  double tol_f;           /* factor epochs: stop once F <= tol_f            */
 } gcp_params;
 
 /* One slice.  DENSE: vals holds prod(dims) values, coords is NULL.
@@ -241,14 +243,31 @@ gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t);
 gcp_status gcp_solve_st_info(gcp_stream* s, double* F, double* alpha, int64_t* iters, int32_t* epochs,
                              uint64_t* rolled);
 
-/* Factor update for X_t with weights s_t (Alg. 1 factor step; Alg. 4 inner
- * iterations): tau_f times [full gradient over X_t and the window, then the
- * ADAM Step of Alg. 2 with the stream's global iteration index], then
- * A_old <- A, then the reservoir window update with X_t and s_t, then
+/* Factor update for X_t with weights s_t (Alg. 1 factor step; Alg. 4):
+ * kappa_f = 0: tau_f times [full gradient over X_t and the window, then the
+ *   ADAM Step of Alg. 2 with the stream's global iteration index], every
+ *   iteration kept.
+ * kappa_f > 0 (dense slices): Alg. 4's epochs.  F = the objective without
+ *   mu/2 ||s_t||^2 (exact over X_t and the window); at most kappa_f epochs
+ *   while F > tol_f, each tau_f [gradient, ADAM Step] iterations and then F
+ *   at the new factors; an epoch that raised F is undone (factors and
+ *   moments return to the last accepted epoch, the index goes back tau_f
+ *   steps, the rate is multiplied by 0.1).  The rate, index and saved copies
+ *   persist across calls (one ADAM object per stream, created with the
+ *   stream; the saved factors start as A0).  Every decision is taken on the
+ *   device: no host synchronisation.
+ * Then A_old <- A, the reservoir window update with X_t and s_t, and
  * t <- t+1.  X_t may be reused by the caller once the HIP stream has passed
  * this call. */
 gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t,
                               const void* s_t);
+
+/* State of the factor epochs of the last gcp_update_factors (waits for the
+ * HIP stream): the objective at the accepted factors, the current ADAM rate,
+ * the iteration index, the epochs run and the mask of rolled-back epochs.
+ * Any output may be NULL.  GCP_E_STATE when params->kappa_f is 0. */
+gcp_status gcp_factor_info(gcp_stream* s, double* F, double* alpha, int64_t* iters, int32_t* epochs,
+                           uint64_t* rolled);
 
 /* Copies the stream's current factors into A_out[k] (device). */
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out);
@@ -256,7 +275,8 @@ gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out);
 /* Device pointer to the stream's current factor k (valid until destroy). */
 gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr);
 
-/* Host-side stream state: current t, window size, Adam iteration index, the
+/* Host-side stream state: current t, window size, Adam iteration index (with
+ * kappa_f > 0 it is read from the device, which waits for the stream), the
  * time stamp held by each window slot (host array of params->window), and
  * the sampler's call number (COO streams: the number of sampled gradient
  * evaluations so far; the next one draws with this number).  Any output may

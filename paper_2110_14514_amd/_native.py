@@ -47,8 +47,8 @@ class GcpParams(Structure):
         ("beta2", c_double), ("adam_eps", c_double), ("tau_f", c_int32),
         ("hist", c_int32), ("max_nnz", c_int64), ("p", c_int64),
         ("q", c_int64), ("seed", c_uint64), ("tsolve", c_int32),
-        ("tau_w", c_int32), ("kappa_w", c_int32), ("reserved", c_int32),
-        ("alpha_w", c_double), ("tol_w", c_double),
+        ("tau_w", c_int32), ("kappa_w", c_int32), ("kappa_f", c_int32),
+        ("alpha_w", c_double), ("tol_w", c_double), ("tol_f", c_double),
     ]
 
 
@@ -77,6 +77,8 @@ SIGNATURES = {
     "gcp_solve_st_info": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int64),
                                     POINTER(c_int32), POINTER(c_uint64)]),
     "gcp_update_factors": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p]),
+    "gcp_factor_info": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int64),
+                                  POINTER(c_int32), POINTER(c_uint64)]),
     "gcp_get_factors": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "gcp_factor_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),
     "gcp_stream_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32),

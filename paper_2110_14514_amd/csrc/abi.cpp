@@ -19,7 +19,8 @@
 using namespace gcp;
 
 struct WsLayout {
-  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, total;
+  size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
+      total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -85,7 +86,8 @@ gcp_status check_params(const gcp_params* p) {
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
   if (p->hist != GCP_HIST_SLICES && p->hist != GCP_HIST_MODEL) return GCP_E_ARG;
-  if (p->reserved != 0) return GCP_E_ARG;
+  if (p->kappa_f < 0 || p->kappa_f > 64 || isnan(p->tol_f)) return GCP_E_ARG;
+  if (p->kappa_f > 0 && p->slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
   if (p->tsolve != GCP_TSOLVE_LS && p->tsolve != GCP_TSOLVE_SGD) return GCP_E_ARG;
   if (p->tsolve == GCP_TSOLVE_SGD) {
     if (p->tau_w < 1 || p->kappa_w < 0 || p->kappa_w > 64) return GCP_E_ARG;
@@ -142,6 +144,12 @@ WsLayout layout_for(const gcp_params* p) {
   L.hist = off; off = align_up(off + (model ? hist_ws_bytes(R) : 0), 256);
   L.tsgd = off;
   off = align_up(off + (p->tsolve == GCP_TSOLVE_SGD ? tsgd_ws_bytes(I1, I2, I3, R, p->dtype == GCP_F64) : 0), 256);
+  // factor epochs: state, objective scalar, saved factors and moments
+  const bool epochs = p->kappa_f > 0;
+  L.fac = off; off += epochs ? 512 : 0;
+  L.Ao = off; off += epochs ? fb : 0;
+  L.uo = off; off += epochs ? fb : 0;
+  L.vo = off; off += epochs ? fb : 0;
   L.total = off;
   return L;
 }
@@ -346,6 +354,8 @@ void gcp_params_default(gcp_params* p) {
   p->kappa_w = 20;
   p->alpha_w = 1.0;
   p->tol_w = -INFINITY;
+  p->kappa_f = 0;
+  p->tol_f = -INFINITY;
 }
 
 gcp_status gcp_workspace_size(const gcp_params* p, size_t* bytes) {
@@ -407,6 +417,13 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   }
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
+  if (e == hipSuccess && p->kappa_f > 0) {
+    e = fac_init_run(reinterpret_cast<FacState*>(s->ws + L.fac), p->alpha_f, s->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->ws + L.Ao, s->ws + L.A, L.fac_elems * s->es, hipMemcpyDeviceToDevice, s->st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.uo, 0, L.fac_elems * s->es, s->st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.vo, 0, L.fac_elems * s->es, s->st);
+  }
   for (int h = 0; h < n_hist && e == hipSuccess; ++h) {
     if (model)
       ;
@@ -546,6 +563,87 @@ gcp_status gcp_solve_st_info(gcp_stream* s, double* F, double* alpha, int64_t* i
   return GCP_OK;
 }
 
+namespace {
+
+// One full dense gradient of the stream's objective at its current factors
+// into the gradient scratch (data term, window, history, regularisation).
+hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+  DenseCall c = base_call(s);
+  c.want = kWantGrad;
+  c.X[0] = X_t->vals;
+  c.S[0] = s_t;
+  fill_window(s, c);
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = fac_ptr(s, s->L.A, k);
+    c.G[k] = fac_ptr(s, s->L.G, k);
+  }
+  c.gs = s->ws + s->L.gs;
+  hipError_t e = dense_fused_run(c);
+  if (e == hipSuccess) e = add_model_history(s, c.A, kWantGrad, nullptr, c.G, nullptr);
+  return e;
+}
+
+// The objective Algorithm 4 compares (no mu/2 ||s_t||^2 term) into `loss`.
+hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, void* loss) {
+  DenseCall c = base_call(s);
+  c.want = kWantLoss;
+  c.mu = 0.0;
+  c.X[0] = X_t->vals;
+  c.S[0] = s_t;
+  fill_window(s, c);
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = fac_ptr(s, s->L.A, k);
+    c.G[k] = fac_ptr(s, s->L.G, k);   // formed by the kernel, not used
+  }
+  c.gs = s->ws + s->L.gs;
+  c.loss_out = loss;
+  hipError_t e = dense_fused_run(c);
+  if (e == hipSuccess) e = add_model_history(s, c.A, kWantLoss, loss, c.G, nullptr);
+  return e;
+}
+
+// Algorithm 4's epochs with every decision on the device.
+hipError_t factor_epochs(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+  const gcp_params& p = s->p;
+  FacState* st = reinterpret_cast<FacState*>(s->ws + s->L.fac);
+  void* loss = s->ws + s->L.fac + 256;
+  const int64_t n = (int64_t)s->L.fac_elems;
+  const int dt = p.dtype == GCP_F64;
+  hipError_t e = dense_objective(s, X_t, s_t, loss);
+  if (e == hipSuccess) e = fac_begin_run(dt, st, loss, p.tol_f, s->st);
+  for (int ep = 0; ep < p.kappa_f && e == hipSuccess; ++ep) {
+    for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
+      e = dense_grad_step(s, X_t, s_t);
+      if (e == hipSuccess)
+        e = fac_step_run(dt, n, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u, s->ws + s->L.v, st, p.beta1,
+                         p.beta2, p.adam_eps, p.lower, s->st);
+    }
+    if (e == hipSuccess) e = dense_objective(s, X_t, s_t, loss);
+    if (e == hipSuccess)
+      e = fac_end_epoch_run(dt, n, s->ws + s->L.A, s->ws + s->L.u, s->ws + s->L.v, s->ws + s->L.Ao,
+                            s->ws + s->L.uo, s->ws + s->L.vo, st, loss, p.tau_f, p.tol_f, p.beta1, p.beta2, s->st);
+  }
+  return e;
+}
+
+}  // namespace
+
+gcp_status gcp_factor_info(gcp_stream* s, double* F, double* alpha, int64_t* iters, int32_t* epochs,
+                           uint64_t* rolled) {
+  if (!s) return GCP_E_ARG;
+  if (s->p.kappa_f == 0) return GCP_E_STATE;
+  FacState h;
+  hipError_t e = hipMemcpyAsync(&h, s->ws + s->L.fac, sizeof(h), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return GCP_E_DEVICE;
+  if (F) *F = h.F;
+  if (alpha) *alpha = h.alpha;
+  if (iters) *iters = h.i;
+  if (epochs) *epochs = h.epoch;
+  if (rolled) *rolled = h.rolled;
+  return GCP_OK;
+}
+
 gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   if (!s || !s_t) return GCP_E_ARG;
   const bool coo = s->p.slice_kind == GCP_SLICE_COO;
@@ -553,7 +651,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
   if (st != GCP_OK) return st;
   const gcp_params& p = s->p;
   hipError_t e = coo ? build_current_table(s, X_t) : hipSuccess;
-  for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
+  for (int it = 0; it < (p.kappa_f > 0 ? 0 : p.tau_f) && e == hipSuccess; ++it) {
     if (coo) {
       const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
       void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
@@ -568,18 +666,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
       s->adam_i += 1;
       continue;
     }
-    DenseCall c = base_call(s);
-    c.want = kWantGrad;
-    c.X[0] = X_t->vals;
-    c.S[0] = s_t;
-    fill_window(s, c);
-    for (int k = 0; k < 3; ++k) {
-      c.A[k] = fac_ptr(s, s->L.A, k);
-      c.G[k] = fac_ptr(s, s->L.G, k);
-    }
-    c.gs = s->ws + s->L.gs;
-    e = dense_fused_run(c);
-    if (e == hipSuccess) e = add_model_history(s, c.A, kWantGrad, nullptr, c.G, nullptr);
+    e = dense_grad_step(s, X_t, s_t);
     if (e != hipSuccess) break;
     const double n = (double)(s->adam_i + 1);
     const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
@@ -587,6 +674,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
                  s->ws + s->L.v, alpha_t, p.beta1, p.beta2, p.adam_eps, p.lower, s->st);
     s->adam_i += 1;
   }
+  if (p.kappa_f > 0 && e == hipSuccess) e = factor_epochs(s, X_t, s_t);
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->ws + s->L.Aold, s->ws + s->L.A, s->L.fac_elems * s->es, hipMemcpyDeviceToDevice, s->st);
   // reservoir window update (Algorithm 1), then t <- t+1
@@ -636,7 +724,18 @@ gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window, int64_t
   if (sample_call) *sample_call = s->sample_call;
   if (t) *t = s->t;
   if (n_window) *n_window = s->nwin;
-  if (adam_iter) *adam_iter = s->adam_i;
+  if (adam_iter) {
+    if (s->p.kappa_f > 0) {
+      // the factor epochs keep the index on the device
+      FacState h;
+      hipError_t e = hipMemcpyAsync(&h, s->ws + s->L.fac, sizeof(h), hipMemcpyDeviceToHost, s->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+      if (e != hipSuccess) return GCP_E_DEVICE;
+      *adam_iter = h.i;
+    } else {
+      *adam_iter = s->adam_i;
+    }
+  }
   if (slot_times)
     for (int h = 0; h < s->p.window; ++h) slot_times[h] = h < s->nwin ? s->slot_t[h] : 0;
   return GCP_OK;
@@ -856,6 +955,7 @@ gcp_status batch_check(gcp_stream* const* streams, int32_t n) {
     if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32) return GCP_E_UNSUPPORTED;
     if (s->p.rank > 32 || s->p.window > 31) return GCP_E_UNSUPPORTED;
     if (model_hist(s)) return GCP_E_UNSUPPORTED;   // batches run the stored-slice history
+    if (s->p.kappa_f > 0) return GCP_E_UNSUPPORTED;  // batches keep every factor iteration
     if (s->p.tau_f != streams[0]->p.tau_f) return GCP_E_ARG;
     if (s->st != streams[0]->st) return GCP_E_ARG;
   }

@@ -30,7 +30,7 @@ namespace gcp {
 namespace {
 
 constexpr double kTsDecay = 0.1;   // rate factor of a rolled-back epoch
-constexpr int kTsRowUnroll = 8;    // slice rows whose loads are in flight together
+constexpr int kTsRowUnroll = 4;    // slice rows whose loads are in flight together
 constexpr int kTsTargetBlocks = 512;        // workgroups per pass (two per compute unit)
 
 enum TsMode { kTsGrad = 0, kTsObjInit = 1, kTsObjEpoch = 2 };
@@ -117,9 +117,10 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
   const int grp = blockIdx.x / a.nchunk;
   const int i3 = chunk * 64 + lane;
   const bool valid = i3 < a.I3;
-  T a3[RK];
-#pragma unroll
-  for (int j = 0; j < RK; ++j) a3[j] = valid ? a.A3[(size_t)i3 * RK + j] : T(0);
+  // row i3 of A^(3) is read where it is used (at each change of i1 and at
+  // the end), which keeps it out of the registers of the row loop
+  const T* a3p = a.A3 + (size_t)(valid ? i3 : 0) * RK;
+  const T vmask = valid ? T(1) : T(0);
 
   // rows of this wave: a contiguous run of (i1, i2); I1 I2 < 2^31
   const int nrows = a.I1 * a.I2;
@@ -136,7 +137,7 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
   // b_j = a1_j s_j a3_j for mode-1 index i1
   auto load_b = [&](int i1) {
 #pragma unroll
-    for (int j = 0; j < RK; ++j) b[j] = a.A1[(size_t)i1 * RK + j] * sh_s[j] * a3[j];
+    for (int j = 0; j < RK; ++j) b[j] = a.A1[(size_t)i1 * RK + j] * sh_s[j] * (vmask * a3p[j]);
   };
   // acc_j += a1_j acc2_j for the rows of mode-1 index i1 just finished
   auto flush = [&](int i1) {
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
     // lanes past I3 hold a3 = 0 and contribute nothing
 #pragma unroll
     for (int j = 0; j < RK; ++j) {
-      const T pj = wave_sum(a3[j] * acc[j]);
+      const T pj = wave_sum(vmask * a3p[j] * acc[j]);
       if (lane == 0) sh_w[wave][j] = pj;
     }
     __syncthreads();
@@ -251,8 +252,9 @@ __global__ void __launch_bounds__(NT) ts_final(TsArgs<T> a) {
       const int j = threadIdx.x;
       gj += a.mu * sh_s[j];
       if (!isfinite(gj)) atomicOr(a.status, (int)kStatusNonFinite);
-      const double n = (double)(st->i + 1);
-      const T alpha_t = (T)(st->alpha * sqrt(1.0 - pow(a.beta2, n)) / (1.0 - pow(a.beta1, n)));
+      // bias correction with n = i + 1 from the carried powers beta^i
+      const double p1 = st->p1 * a.beta1, p2 = st->p2 * a.beta2;
+      const T alpha_t = (T)(st->alpha * sqrt(1.0 - p2) / (1.0 - p1));
       const T uj = a.b1 * a.u[j] + (T(1) - a.b1) * gj;
       const T vj = a.b2 * a.v[j] + (T(1) - a.b2) * gj * gj;
       a.u[j] = uj;
@@ -261,7 +263,11 @@ __global__ void __launch_bounds__(NT) ts_final(TsArgs<T> a) {
       a.s[j] = sj > a.lower ? sj : a.lower;
     }
     __syncthreads();
-    if (threadIdx.x == 0) st->i += 1;
+    if (threadIdx.x == 0) {
+      st->i += 1;
+      st->p1 *= a.beta1;
+      st->p2 *= a.beta2;
+    }
     return;
   }
 
@@ -279,6 +285,8 @@ __global__ void __launch_bounds__(NT) ts_final(TsArgs<T> a) {
       if (roll) {
         st->alpha *= kTsDecay;
         st->i -= a.tau;
+        st->p1 = pow(a.beta1, (double)st->i);
+        st->p2 = pow(a.beta2, (double)st->i);
         st->rolled |= 1ull << st->epoch;
       } else {
         st->F = (double)Fv;
@@ -325,6 +333,8 @@ __global__ void ts_init(T* s, T* u, T* v, T* so, T* uo, T* vo, int R, TsgdState*
     st->F = 0.0;
     st->alpha = alpha;
     st->i = 0;
+    st->p1 = 1.0;
+    st->p2 = 1.0;
     st->rolled = 0ull;
     st->done = 0;
     st->epoch = 0;

@@ -48,7 +48,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0,
                 sampled_atomic: bool = False, hist: str = "slices", tsolve: str = "ls",
                 tau_w: int = 100, kappa_w: int = 20, alpha_w: float = 1.0,
-                tol_w: float = -math.inf) -> N.GcpParams:
+                tol_w: float = -math.inf, kappa_f: int = 0, tol_f: float = -math.inf) -> N.GcpParams:
     lib = N.load()
     n_p, n_q = p, q
     p = N.GcpParams()
@@ -71,6 +71,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.tau_f = int(tau_f)
     p.tsolve = {"ls": N.TSOLVE_LS, "sgd": N.TSOLVE_SGD}[tsolve]
     p.tau_w, p.kappa_w, p.alpha_w, p.tol_w = int(tau_w), int(kappa_w), float(alpha_w), float(tol_w)
+    p.kappa_f, p.tol_f = int(kappa_f), float(tol_f)
     p.seed = int(seed) & ((1 << 64) - 1)
     return p
 
@@ -166,6 +167,15 @@ class Stream:
         iters, epochs, rolled = c_int64(0), c_int32(0), c_uint64(0)
         N.check(self.lib.gcp_solve_st_info(self.handle, byref(F), byref(alpha), byref(iters), byref(epochs),
                                            byref(rolled)), "gcp_solve_st_info")
+        return {"F": F.value, "alpha": alpha.value, "iters": iters.value, "epochs": epochs.value,
+                "rolled": [bool(rolled.value >> e & 1) for e in range(epochs.value)]}
+
+    def factor_info(self) -> dict:
+        """State of the factor epochs of the last update (synchronises the stream)."""
+        F, alpha = c_double(0.0), c_double(0.0)
+        iters, epochs, rolled = c_int64(0), c_int32(0), c_uint64(0)
+        N.check(self.lib.gcp_factor_info(self.handle, byref(F), byref(alpha), byref(iters), byref(epochs),
+                                         byref(rolled)), "gcp_factor_info")
         return {"F": F.value, "alpha": alpha.value, "iters": iters.value, "epochs": epochs.value,
                 "rolled": [bool(rolled.value >> e & 1) for e in range(epochs.value)]}
 

@@ -40,7 +40,7 @@ def test_params_struct_layout_matches_header(lib):
     assert p.beta1 == 0.9 and p.beta2 == 0.999 and p.adam_eps == 1e-8
     assert p.w == 1.0 and p.theta == 1.0 and p.lam == 0.0 and p.mu == 0.0
     assert math.isinf(p.lower) and p.lower < 0 and p.tau_f == 1
-    assert ctypes.sizeof(N.GcpParams) == 200
+    assert ctypes.sizeof(N.GcpParams) == 208
     assert ctypes.sizeof(N.GcpSlice) == 32
 
 
@@ -74,7 +74,9 @@ def test_invalid_params_rejected(lib, field, value, code):
 
 
 @pytest.mark.parametrize("fields,code", [
-    ({"tsolve": 2}, "E_ARG"), ({"tsolve": -1}, "E_ARG"), ({"reserved": 1}, "E_ARG"),
+    ({"tsolve": 2}, "E_ARG"), ({"tsolve": -1}, "E_ARG"), ({"kappa_f": -1}, "E_ARG"),
+    ({"kappa_f": 65}, "E_ARG"), ({"tol_f": float("nan")}, "E_ARG"),
+    ({"kappa_f": 2, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4}, "E_UNSUPPORTED"),
     ({"tsolve": 1, "tau_w": 0}, "E_ARG"), ({"tsolve": 1, "kappa_w": 65}, "E_ARG"),
     ({"tsolve": 1, "kappa_w": -1}, "E_ARG"), ({"tsolve": 1, "alpha_w": 0.0}, "E_ARG"),
     ({"tsolve": 1, "alpha_w": float("inf")}, "E_ARG"), ({"tsolve": 1, "tol_w": float("nan")}, "E_ARG"),
@@ -92,10 +94,13 @@ def test_temporal_sgd_defaults_and_workspace(lib):
     from paper_2110_14514_amd import _native as N
     p = _params(lib)
     assert p.tsolve == N.TSOLVE_LS and p.tau_w == 100 and p.kappa_w == 20
-    assert p.alpha_w == 1.0 and p.tol_w == float("-inf")
+    assert p.alpha_w == 1.0 and p.tol_w == float("-inf") and p.kappa_f == 0 and p.tol_f == float("-inf")
     st, ls = _ws(lib, p)
     st2, sgd = _ws(lib, _params(lib, tsolve=N.TSOLVE_SGD))
     assert st == st2 == N.OK and ls < sgd < ls + (1 << 20)
+    # factor epochs keep the saved factors and moments: three packed blocks
+    st3, ep = _ws(lib, _params(lib, kappa_f=3))
+    assert st3 == N.OK and ep - ls >= 3 * (20 + 30 + 40) * 4 * 4
 
 
 def test_workspace_monotone_in_window_and_dims(lib):
