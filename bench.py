@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
@@ -267,6 +267,49 @@ def bench_c2w(args):
     return 0
 
 
+def bench_c2step(args):
+    """Whole OnlineGCP time steps (Algorithm 1) at the C2 shape with both SGD
+    solvers on the device: Algorithm 3 for s_t (tau_w = 100, kappa_w = 20,
+    alpha_w = 1) and Algorithm 4's epochs for the factors (tau_f = 100,
+    kappa_f = 10, alpha_f = 1e-4), the iteration counts and rates of the
+    paper's synthetic Poisson experiment, over a window of 10 stored slices.
+    Each step takes a new slice; rate: time steps per second."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream
+    dims, R, H, loss = (200, 200, 200), 16, 10, "poisson_log"
+    X_t, A, s_t, Xh, Sh = gi.device_dense_window(dims, R, H, loss, seed=1)
+    st = Stream(dims, R, H, loss, A, Xh, Sh, list(range(1, H + 1)), tsolve="sgd", tau_w=100, kappa_w=20,
+                alpha_w=1.0, tau_f=100, kappa_f=10, alpha_f=1e-4, kernel=args.kernel)
+    del Xh
+    new = [gi.device_dense_window(dims, R, 0, loss, seed=100 + k)[0] for k in range(2)]
+    torch.cuda.synchronize()
+    k = [0]
+
+    def fn():
+        st.step(new[k[0] % 2])
+        k[0] += 1
+
+    steps = max(1, min(args.steps, 5))
+    warm = max(1, min(args.warmup, 1))
+    sec = _time(fn, steps, warm, torch.cuda.synchronize)
+    assert st.sync() == 0
+    fi, wi = st.factor_info(), st.solve_info()
+    omega = int(np.prod(dims))
+    passes = (100 + 1) * 10 + 1
+    out = {"metric": "OnlineGCP time steps/sec (both SGD solvers on the device)", "value": 1.0 / sec,
+           "unit": "time steps/s", "n_gpus": 1, "ms_per_step": sec * 1e3, "steps": steps, "warmup": warm,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "C2 shape OnlineGCP steps: 200x200x200 Poisson-count slices, rank 16, window "
+                                  "10, tau 100, kappa_w 20, kappa_f 10"},
+           "fused_passes_per_step": passes, "weight_passes_per_step": 20 * 101 + 1,
+           "alg_bytes_per_fused_pass": 4 * (H + 1) * omega,
+           "last_factor_epochs": fi["epochs"], "last_factor_rollbacks": sum(fi["rolled"]),
+           "last_weight_rollbacks": sum(wi["rolled"])}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_c5(args):
     """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
     rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
@@ -316,7 +359,8 @@ def main():
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.workload != "c2":
-        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w}[args.workload](args)
+        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
+                "c2step": bench_c2step}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

@@ -14,7 +14,7 @@
 #include <utility>
 #include <vector>
 
-#include "common.hpp"
+#include "solvers.hpp"
 
 using namespace gcp;
 

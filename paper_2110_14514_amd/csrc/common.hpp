@@ -341,56 +341,6 @@ hipError_t ls_solve_run(int I1, int I2, int I3, int R, int dtype, const void* X,
                         const void* const* A, double mu, double lower, void* s_out,
                         void* scratch, int* status, hipStream_t st);
 
-// Temporal-weight solver of Algorithm 3 on a dense slice (ADAM epochs with
-// roll-back, decided on the device).  The workspace of tsgd_ws_bytes bytes
-// starts with the solver state.
-struct TsgdState {
-  double F;          // objective at the last accepted weights
-  double alpha;      // current ADAM rate
-  int64_t i;         // ADAM iteration index
-  double p1, p2;     // beta1^i, beta2^i
-  uint64_t rolled;   // bit e set: epoch e was rolled back
-  int32_t done;      // stopping test met: later passes do nothing
-  int32_t epoch;     // epochs run
-  int32_t pad;
-};
-struct TsgdCall {
-  int I1, I2, I3, R, loss, dtype;
-  const void* X;
-  const void* A[3];
-  void* s;           // weights: written from zero, the solver's iterate
-  double mu, lower, alpha, beta1, beta2, eps, tol;
-  int tau, kappa;
-  void* ws;
-  int* status;
-  hipStream_t stream;
-};
-size_t tsgd_ws_bytes(int I1, int I2, int I3, int R, int dtype);
-hipError_t tsgd_run(const TsgdCall& c);
-
-// Epochs of the factor solver (Algorithm 4): state kept for the whole stream.
-struct FacState {
-  double F;          // objective at the last accepted factors
-  double alpha;      // current ADAM rate
-  double alpha_t;    // bias-corrected rate of the step being taken
-  int64_t i;         // ADAM iteration index
-  double p1, p2;     // beta1^i, beta2^i
-  uint64_t rolled;   // bit e set: epoch e of the last call was rolled back
-  int32_t done;      // stopping test met: later steps of the call do nothing
-  int32_t epoch;     // epochs run in the last call
-  int32_t roll;      // last decision: 1 undo, 0 keep, -1 none
-  int32_t pad;
-};
-hipError_t fac_init_run(FacState* st, double alpha, hipStream_t stream);
-// i <- i + 1 and the ADAM Step with the device-held rate (skipped once done).
-hipError_t fac_step_run(int dtype, int64_t n, void* a, const void* g, void* u, void* v, FacState* st, double beta1,
-                        double beta2, double eps, double lower, hipStream_t stream);
-hipError_t fac_begin_run(int dtype, FacState* st, const void* loss, double tol, hipStream_t stream);
-// Decision on *loss, then the copy it asks for (n factor entries).
-hipError_t fac_end_epoch_run(int dtype, int64_t n, void* a, void* u, void* v, void* ao, void* uo, void* vo,
-                             FacState* st, const void* loss, int tau, double tol, double beta1, double beta2,
-                             hipStream_t stream);
-
 // ADAM step over a flat array (Algorithm 2, Step).
 hipError_t adam_run(int dtype, int64_t n, void* a, const void* g, void* u, void* v,
                     double alpha_t, double beta1, double beta2, double eps,

@@ -5,7 +5,7 @@
 // epoch that raised the objective is undone, the rate is multiplied by 0.1 and
 // the index goes back tau_f steps.  Every kernel here is tiny or a plain
 // streaming copy; the gradients and objectives come from the fused kernels.
-#include "common.hpp"
+#include "solvers.hpp"
 
 namespace gcp {
 namespace {

@@ -24,7 +24,7 @@
 // when i1 changes, a row costs m = sum_j a2_j b_j and acc2_j += y a2_j
 // (2R multiply-adds per entry); acc_j += a1_j acc2_j when i1 changes, and the
 // lane's share of the gradient is a3_j acc_j.
-#include "common.hpp"
+#include "solvers.hpp"
 
 namespace gcp {
 namespace {
