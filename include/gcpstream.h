@@ -269,6 +269,27 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t,
 gcp_status gcp_factor_info(gcp_stream* s, double* F, double* alpha, int64_t* iters, int32_t* epochs,
                            uint64_t* rolled);
 
+/* Reconstruction loss of a dense slice X (Section 6, eq. local_loss) under
+ * the CP model of the stream's current factors with weights s_x (device, R
+ * values): *sum_f = sum_i f(x_i, m_i) (no history or regularisation terms),
+ * *sum_sq = ||X||_F^2, both host doubles (the call waits for the stream).
+ * The local loss is sum_f / sum_sq for the current slice; the global loss of
+ * Section 6 is the ratio of the sums over all past slices with the final
+ * factors.  Dense streams only (GCP_E_UNSUPPORTED for COO). */
+gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* sum_f, double* sum_sq);
+
+/* K-tensor score of Section 6.1 (congruence of the computed and a reference
+ * K-tensor, 1.0 for a perfect recovery): the stream's current factors with
+ * component weights w_a (device, R values) against B[k] (device, I_k x
+ * rank_b row-major) with weights w_b (device, rank_b values), all of the
+ * stream dtype.  Columns are normalised with their norms moved into the
+ * weights; a pair (r, q) scores (1 - |xi_r - eta_q| / max(xi_r, eta_q)) times
+ * the product over modes of |cos(a_r, b_q)|; pairs are matched greedily
+ * (highest first, each component once) and *score (host) is the sum of the
+ * matched pair scores over rank_b.  Waits for the stream. */
+gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* B, const void* w_b, int32_t rank_b,
+                             double* score);
+
 /* Copies the stream's current factors into A_out[k] (device). */
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out);
 

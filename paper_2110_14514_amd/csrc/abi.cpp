@@ -20,7 +20,7 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
-      total;
+      metric, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -150,6 +150,7 @@ WsLayout layout_for(const gcp_params* p) {
   L.Ao = off; off += epochs ? fb : 0;
   L.uo = off; off += epochs ? fb : 0;
   L.vo = off; off += epochs ? fb : 0;
+  L.metric = off; off += align_up(metrics_ws_bytes(), 256);
   L.total = off;
   return L;
 }
@@ -701,6 +702,116 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
   }
   s->t += 1;
   return hip_status(e);
+}
+
+gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* sum_f, double* sum_sq) {
+  if (!s || !s_x) return GCP_E_ARG;
+  if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  gcp_status st = check_dense_slice(s, X);
+  if (st != GCP_OK) return st;
+  DenseCall c = base_call(s);
+  c.want = kWantLoss;
+  c.lam = 0.0;
+  c.mu = 0.0;
+  c.X[0] = X->vals;
+  c.S[0] = s_x;
+  c.ns = 1;
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = fac_ptr(s, s->L.A, k);
+    c.G[k] = fac_ptr(s, s->L.G, k);   // formed by the kernel, not used
+  }
+  c.gs = s->ws + s->L.gs;
+  c.loss_out = s->ws + s->L.loss;
+  double* sq = reinterpret_cast<double*>(s->ws + s->L.loss + 64);
+  hipError_t e = dense_fused_run(c);
+  if (e == hipSuccess) e = sumsq_run(s->p.dtype == GCP_F64, X->vals, (int64_t)s->omega, s->ws + s->L.metric, sq, s->st);
+  double f = 0.0, q = 0.0;
+  if (e == hipSuccess) {
+    if (s->p.dtype == GCP_F64) {
+      e = hipMemcpyAsync(&f, s->ws + s->L.loss, 8, hipMemcpyDeviceToHost, s->st);
+    } else {
+      float f32 = 0.f;
+      e = hipMemcpyAsync(&f32, s->ws + s->L.loss, 4, hipMemcpyDeviceToHost, s->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+      f = f32;
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&q, sq, 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return GCP_E_DEVICE;
+  if (sum_f) *sum_f = f;
+  if (sum_sq) *sum_sq = q;
+  return GCP_OK;
+}
+
+gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* B, const void* w_b, int32_t rank_b,
+                             double* score) {
+  if (!s || !w_a || !B || !B[0] || !B[1] || !B[2] || !w_b || !score) return GCP_E_ARG;
+  if (rank_b < 1 || rank_b > GCP_MAX_RANK) return GCP_E_ARG;
+  const int Ra = s->p.rank, Rb = rank_b;
+  const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  const int dt = s->p.dtype == GCP_F64;
+  hipError_t e = cross_run(dt, A, B, s->dims, Ra, Rb, s->ws + s->L.metric, s->st);
+  std::vector<double> h((size_t)3 * Ra * Rb + 3 * Ra + 3 * Rb);
+  std::vector<double> wa(Ra), wb(Rb);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), cross_results(s->ws + s->L.metric), h.size() * 8, hipMemcpyDeviceToHost, s->st);
+  if (dt) {
+    if (e == hipSuccess) e = hipMemcpyAsync(wa.data(), w_a, Ra * 8, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(wb.data(), w_b, Rb * 8, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  } else {
+    std::vector<float> fa(Ra), fb(Rb);
+    if (e == hipSuccess) e = hipMemcpyAsync(fa.data(), w_a, Ra * 4, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(fb.data(), w_b, Rb * 4, hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    for (int r = 0; r < Ra; ++r) wa[r] = fa[r];
+    for (int q = 0; q < Rb; ++q) wb[q] = fb[q];
+  }
+  if (e != hipSuccess) return GCP_E_DEVICE;
+  const double* C = h.data();
+  const double* Na = C + (size_t)3 * Ra * Rb;
+  const double* Nb = Na + 3 * Ra;
+  // component weights with the column norms moved in, then pair scores
+  std::vector<double> xi(Ra), eta(Rb);
+  for (int r = 0; r < Ra; ++r) {
+    xi[r] = std::fabs(wa[r]);
+    for (int k = 0; k < 3; ++k) xi[r] *= std::sqrt(Na[k * Ra + r]);
+  }
+  for (int q = 0; q < Rb; ++q) {
+    eta[q] = std::fabs(wb[q]);
+    for (int k = 0; k < 3; ++k) eta[q] *= std::sqrt(Nb[k * Rb + q]);
+  }
+  struct Pair { double v; int r, q; };
+  std::vector<Pair> P;
+  P.reserve((size_t)Ra * Rb);
+  for (int r = 0; r < Ra; ++r)
+    for (int q = 0; q < Rb; ++q) {
+      double cg = 1.0;
+      for (int k = 0; k < 3; ++k) {
+        const double na = std::sqrt(Na[k * Ra + r]), nb = std::sqrt(Nb[k * Rb + q]);
+        cg *= (na > 0 && nb > 0) ? std::fabs(C[((size_t)k * Ra + r) * Rb + q]) / (na * nb) : 0.0;
+      }
+      const double big = std::max(xi[r], eta[q]);
+      const double pen = 1.0 - (big > 0 ? std::fabs(xi[r] - eta[q]) / big : 0.0);
+      P.push_back({cg * pen, r, q});
+    }
+  std::sort(P.begin(), P.end(), [](const Pair& a, const Pair& b) {
+    if (a.v != b.v) return a.v > b.v;
+    if (a.r != b.r) return a.r < b.r;
+    return a.q < b.q;
+  });
+  std::vector<char> ua(Ra, 0), ub(Rb, 0);
+  double total = 0.0;
+  int matched = 0;
+  for (const Pair& x : P) {
+    if (ua[x.r] || ub[x.q]) continue;
+    ua[x.r] = ub[x.q] = 1;
+    total += x.v;
+    if (++matched == std::min(Ra, Rb)) break;
+  }
+  *score = total / Rb;
+  return GCP_OK;
 }
 
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out) {

@@ -56,4 +56,14 @@ hipError_t fac_end_epoch_run(int dtype, int64_t n, void* a, void* u, void* v, vo
                              FacState* st, const void* loss, int tau, double tol, double beta1, double beta2,
                              hipStream_t stream);
 
+// Evaluation metrics (Section 6): workspace of metrics_ws_bytes bytes.
+size_t metrics_ws_bytes();
+// *out (device FP64) = sum of squares of n values of X.
+hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out, hipStream_t stream);
+// Column norms and cross products of two K-tensors' factors (Ra, Rb <= 64),
+// laid out at cross_results(ws) as C[3][Ra][Rb], Na[3][Ra], Nb[3][Rb].
+hipError_t cross_run(int dtype, const void* const* A, const void* const* B, const int* I, int Ra, int Rb, void* ws,
+                     hipStream_t stream);
+const double* cross_results(const void* ws);
+
 }  // namespace gcp

@@ -179,6 +179,29 @@ class Stream:
         return {"F": F.value, "alpha": alpha.value, "iters": iters.value, "epochs": epochs.value,
                 "rolled": [bool(rolled.value >> e & 1) for e in range(epochs.value)]}
 
+    def slice_loss(self, X: torch.Tensor, s_x: torch.Tensor):
+        """(sum_i f(x_i, m_i), ||X||_F^2) of a dense slice under the current
+        factors with weights s_x (synchronises the stream)."""
+        f, q = c_double(0.0), c_double(0.0)
+        sl = _dense_slice(X)
+        N.check(self.lib.gcp_slice_loss(self.handle, byref(sl), _ptr(s_x.contiguous()), byref(f), byref(q)),
+                "gcp_slice_loss")
+        return f.value, q.value
+
+    def local_loss(self, X: torch.Tensor, s_x: torch.Tensor) -> float:
+        f, q = self.slice_loss(X, s_x)
+        return f / q
+
+    def ktensor_score(self, w_a: torch.Tensor, B: Sequence[torch.Tensor], w_b: torch.Tensor) -> float:
+        """Congruence score of the current factors (weights w_a) against the
+        reference K-tensor (B, w_b)."""
+        B = [b.contiguous() for b in B]
+        out = c_double(0.0)
+        N.check(self.lib.gcp_ktensor_score(self.handle, _ptr(w_a.contiguous()), _ptr_array(B),
+                                           _ptr(w_b.contiguous()), int(B[0].shape[1]), byref(out)),
+                "gcp_ktensor_score")
+        return out.value
+
     def update_factors(self, X_t, s_t: torch.Tensor) -> None:
         sl = _slice(X_t)
         N.check(self.lib.gcp_update_factors(self.handle, byref(sl), _ptr(s_t.contiguous())),
