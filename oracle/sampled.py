@@ -129,3 +129,65 @@ def sampled_loss_grad(prob, call: int = 0):
         if n == 0:
             g_s += np.sum(yt[:, None] * rows[0] * rows[1] * rows[2], axis=0)
     return F, G, g_s
+
+
+# Call number of the objective estimates of Algorithm 5 within the factor
+# solve of time step t: fixed for the whole solve (every epoch compares
+# estimates over the same draws) and apart from the gradient calls, which
+# count up from 0.
+def estimate_call(t: int) -> int:
+    return 0x80000000 | (int(t) & 0x7FFFFFFF)
+
+
+def estimate_objective(prob, p_est: int, q_est: int, call: int) -> float:
+    """Algorithm 5 for the factor solver: the sampled objective with p_est
+    nonzero and q_est zero draws per slice, the exact regulariser of the
+    factors and no weight regulariser (Algorithm 4 passes mu = 0)."""
+    from types import SimpleNamespace
+    est = SimpleNamespace(**vars(prob))
+    est.p, est.q, est.mu = p_est, q_est, 0.0
+    return sampled_loss_grad(est, call=call)[0]
+
+
+def sampled_factor_epochs(prob, state, *, tau, kappa, tol=-np.inf, p_est, q_est, beta1=0.9, beta2=0.999, eps=1e-8,
+                          lower=-np.inf, decay=0.1):
+    """Algorithm 4 on a sparse problem: epochs of tau sampled-gradient ADAM
+    steps (a new call number for every gradient), each judged by Algorithm
+    5's estimate over draws fixed for the solve, with the ADAM Update of
+    Algorithm 2 (roll-back, rate times decay, index back tau).  `state`
+    holds A, u, v, the saved Ao, uo, vo, alpha, i and the next call number;
+    it is updated in place.  Returns the list of roll-back decisions."""
+    from .adam import adam_step
+    ecall = estimate_call(prob.t)
+    prob.A = [a.copy() for a in state.A]
+    F = estimate_objective(prob, p_est, q_est, ecall)
+    rolled = []
+    for _ in range(kappa):
+        if not F > tol:
+            break
+        F_old = F
+        for _ in range(tau):
+            prob.A = state.A
+            _, G, _ = sampled_loss_grad(prob, call=state.call)
+            state.call += 1
+            for k in range(3):
+                state.A[k], state.u[k], state.v[k] = adam_step(state.A[k], G[k], state.u[k], state.v[k], state.i,
+                                                               state.alpha, beta1, beta2, eps, lower)
+            state.i += 1
+        prob.A = state.A
+        F = estimate_objective(prob, p_est, q_est, ecall)
+        if F > F_old:
+            state.A = [a.copy() for a in state.Ao]
+            state.u = [a.copy() for a in state.uo]
+            state.v = [a.copy() for a in state.vo]
+            state.alpha *= decay
+            state.i -= tau
+            F = F_old
+            rolled.append(True)
+        else:
+            state.Ao = [a.copy() for a in state.A]
+            state.uo = [a.copy() for a in state.u]
+            state.vo = [a.copy() for a in state.v]
+            rolled.append(False)
+    state.F = F
+    return rolled
