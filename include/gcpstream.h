@@ -153,6 +153,8 @@ typedef struct {
   double alpha_w;         /* SGD: initial ADAM rate, > 0                    */
   double tol_w;           /* SGD: stop once F <= tol_w (-INFINITY: never)   */
   double tol_f;           /* factor epochs: stop once F <= tol_f            */
+  int64_t p_est, q_est;   /* COO factor epochs: nonzero / zero draws per
+                           * slice of Algorithm 5's objective estimate     */
 } gcp_params;
 
 /* One slice.  DENSE: vals holds prod(dims) values, coords is NULL.
@@ -247,8 +249,11 @@ gcp_status gcp_solve_st_info(gcp_stream* s, double* F, double* alpha, int64_t* i
  * kappa_f = 0: tau_f times [full gradient over X_t and the window, then the
  *   ADAM Step of Alg. 2 with the stream's global iteration index], every
  *   iteration kept.
- * kappa_f > 0 (dense slices): Alg. 4's epochs.  F = the objective without
- *   mu/2 ||s_t||^2 (exact over X_t and the window); at most kappa_f epochs
+ * kappa_f > 0: Alg. 4's epochs.  F = the objective without mu/2 ||s_t||^2:
+ *   exact over X_t and the window for dense slices; for COO slices Alg. 5's
+ *   estimate with p_est nonzero and q_est zero draws per slice, over draws
+ *   fixed for the call (call number 2^31 + t, apart from the gradients'
+ *   counter) with exact history and regulariser terms; at most kappa_f epochs
  *   while F > tol_f, each tau_f [gradient, ADAM Step] iterations and then F
  *   at the new factors; an epoch that raised F is undone (factors and
  *   moments return to the last accepted epoch, the index goes back tau_f

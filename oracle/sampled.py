@@ -161,7 +161,7 @@ def sampled_factor_epochs(prob, state, *, tau, kappa, tol=-np.inf, p_est, q_est,
     ecall = estimate_call(prob.t)
     prob.A = [a.copy() for a in state.A]
     F = estimate_objective(prob, p_est, q_est, ecall)
-    rolled = []
+    rolled, state.F_hist, state.F_try = [], [F], []
     for _ in range(kappa):
         if not F > tol:
             break
@@ -176,6 +176,7 @@ def sampled_factor_epochs(prob, state, *, tau, kappa, tol=-np.inf, p_est, q_est,
             state.i += 1
         prob.A = state.A
         F = estimate_objective(prob, p_est, q_est, ecall)
+        state.F_try.append(F)
         if F > F_old:
             state.A = [a.copy() for a in state.Ao]
             state.u = [a.copy() for a in state.uo]
@@ -189,5 +190,6 @@ def sampled_factor_epochs(prob, state, *, tau, kappa, tol=-np.inf, p_est, q_est,
             state.uo = [a.copy() for a in state.u]
             state.vo = [a.copy() for a in state.v]
             rolled.append(False)
+        state.F_hist.append(F)
     state.F = F
     return rolled

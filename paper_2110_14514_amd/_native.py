@@ -49,6 +49,7 @@ class GcpParams(Structure):
         ("q", c_int64), ("seed", c_uint64), ("tsolve", c_int32),
         ("tau_w", c_int32), ("kappa_w", c_int32), ("kappa_f", c_int32),
         ("alpha_w", c_double), ("tol_w", c_double), ("tol_f", c_double),
+        ("p_est", c_int64), ("q_est", c_int64),
     ]
 
 

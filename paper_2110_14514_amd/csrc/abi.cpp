@@ -87,7 +87,8 @@ gcp_status check_params(const gcp_params* p) {
   if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
   if (p->hist != GCP_HIST_SLICES && p->hist != GCP_HIST_MODEL) return GCP_E_ARG;
   if (p->kappa_f < 0 || p->kappa_f > 64 || isnan(p->tol_f)) return GCP_E_ARG;
-  if (p->kappa_f > 0 && p->slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  if (p->kappa_f > 0 && p->slice_kind == GCP_SLICE_COO && (p->p_est < 0 || p->q_est < 0 || p->p_est + p->q_est < 1))
+    return GCP_E_ARG;
   if (p->tsolve != GCP_TSOLVE_LS && p->tsolve != GCP_TSOLVE_SGD) return GCP_E_ARG;
   if (p->tsolve == GCP_TSOLVE_SGD) {
     if (p->tau_w < 1 || p->kappa_w < 0 || p->kappa_w > 64) return GCP_E_ARG;
@@ -170,6 +171,8 @@ gcp_status check_coo_slice(const gcp_stream* s, const gcp_slice* X) {
   if (X->nnz > 0 && (!X->vals || !X->coords)) return GCP_E_ARG;
   if (s->p.p > 0 && X->nnz == 0) return GCP_E_ARG;               // no nonzero to draw
   if (s->p.q > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;  // no zero to draw
+  if (s->p.kappa_f > 0 && s->p.p_est > 0 && X->nnz == 0) return GCP_E_ARG;
+  if (s->p.kappa_f > 0 && s->p.q_est > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;
   if (((uintptr_t)X->coords & 3u) || ((uintptr_t)X->vals & 3u)) return GCP_E_ALIGN;
   return GCP_OK;
 }
@@ -357,6 +360,8 @@ void gcp_params_default(gcp_params* p) {
   p->tol_w = -INFINITY;
   p->kappa_f = 0;
   p->tol_f = -INFINITY;
+  p->p_est = 0;
+  p->q_est = 0;
 }
 
 gcp_status gcp_workspace_size(const gcp_params* p, size_t* bytes) {
@@ -390,8 +395,9 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
     } else {
       if (X_hist[h].kind != GCP_SLICE_COO || X_hist[h].nnz < 0 || X_hist[h].nnz > p->max_nnz) return GCP_E_SHAPE;
       if (X_hist[h].nnz > 0 && (!X_hist[h].vals || !X_hist[h].coords)) return GCP_E_ARG;
-      if (p->p > 0 && X_hist[h].nnz == 0) return GCP_E_ARG;
-      if (p->q > 0 && X_hist[h].nnz >= p->dims[0] * p->dims[1] * p->dims[2]) return GCP_E_ARG;
+      if ((p->p > 0 || (p->kappa_f > 0 && p->p_est > 0)) && X_hist[h].nnz == 0) return GCP_E_ARG;
+      if ((p->q > 0 || (p->kappa_f > 0 && p->q_est > 0)) && X_hist[h].nnz >= p->dims[0] * p->dims[1] * p->dims[2])
+        return GCP_E_ARG;
     }
     if (h > 0 && t_hist[h] <= t_hist[h - 1]) return GCP_E_ARG;
     if (t_hist[h] < 1) return GCP_E_ARG;
@@ -603,23 +609,52 @@ hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t,
   return e;
 }
 
+// One sampled gradient of a COO stream's objective into the gradient scratch
+// (a new call number).
+hipError_t coo_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+  const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
+  SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs);
+  hipError_t e = sampled_run(c);
+  if (e == hipSuccess) e = add_model_history(s, A, kWantGrad, nullptr, G, nullptr);
+  return e;
+}
+
+// Algorithm 5's estimate for the factor solver of time step t: p_est and
+// q_est draws per slice under a call number fixed for the solve, exact
+// history and factor regulariser, no weight regulariser.
+hipError_t coo_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, void* loss) {
+  const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
+  SampledCall c = sampled_call(s, X_t, A, s_t, kWantLoss, loss, G, s->ws + s->L.gs,
+                               (int64_t)(0x80000000u | (uint32_t)(s->t & 0x7FFFFFFF)));
+  c.p = s->p.p_est;
+  c.q = s->p.q_est;
+  c.mu = 0.0;
+  hipError_t e = sampled_run(c);
+  if (e == hipSuccess) e = add_model_history(s, A, kWantLoss, loss, G, nullptr);
+  return e;
+}
+
 // Algorithm 4's epochs with every decision on the device.
 hipError_t factor_epochs(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   const gcp_params& p = s->p;
+  const bool coo = p.slice_kind == GCP_SLICE_COO;
   FacState* st = reinterpret_cast<FacState*>(s->ws + s->L.fac);
   void* loss = s->ws + s->L.fac + 256;
   const int64_t n = (int64_t)s->L.fac_elems;
   const int dt = p.dtype == GCP_F64;
-  hipError_t e = dense_objective(s, X_t, s_t, loss);
+  auto objective = [&]() { return coo ? coo_objective(s, X_t, s_t, loss) : dense_objective(s, X_t, s_t, loss); };
+  hipError_t e = objective();
   if (e == hipSuccess) e = fac_begin_run(dt, st, loss, p.tol_f, s->st);
   for (int ep = 0; ep < p.kappa_f && e == hipSuccess; ++ep) {
     for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
-      e = dense_grad_step(s, X_t, s_t);
+      e = coo ? coo_grad_step(s, X_t, s_t) : dense_grad_step(s, X_t, s_t);
       if (e == hipSuccess)
         e = fac_step_run(dt, n, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u, s->ws + s->L.v, st, p.beta1,
                          p.beta2, p.adam_eps, p.lower, s->st);
     }
-    if (e == hipSuccess) e = dense_objective(s, X_t, s_t, loss);
+    if (e == hipSuccess) e = objective();
     if (e == hipSuccess)
       e = fac_end_epoch_run(dt, n, s->ws + s->L.A, s->ws + s->L.u, s->ws + s->L.v, s->ws + s->L.Ao,
                             s->ws + s->L.uo, s->ws + s->L.vo, st, loss, p.tau_f, p.tol_f, p.beta1, p.beta2, s->st);

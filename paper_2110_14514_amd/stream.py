@@ -48,7 +48,8 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 slice_kind: str = "dense", max_nnz: int = 0, p: int = 0, q: int = 0,
                 sampled_atomic: bool = False, hist: str = "slices", tsolve: str = "ls",
                 tau_w: int = 100, kappa_w: int = 20, alpha_w: float = 1.0,
-                tol_w: float = -math.inf, kappa_f: int = 0, tol_f: float = -math.inf) -> N.GcpParams:
+                tol_w: float = -math.inf, kappa_f: int = 0, tol_f: float = -math.inf,
+                p_est: int = 0, q_est: int = 0) -> N.GcpParams:
     lib = N.load()
     n_p, n_q = p, q
     p = N.GcpParams()
@@ -72,6 +73,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.tsolve = {"ls": N.TSOLVE_LS, "sgd": N.TSOLVE_SGD}[tsolve]
     p.tau_w, p.kappa_w, p.alpha_w, p.tol_w = int(tau_w), int(kappa_w), float(alpha_w), float(tol_w)
     p.kappa_f, p.tol_f = int(kappa_f), float(tol_f)
+    p.p_est, p.q_est = int(p_est), int(q_est)
     p.seed = int(seed) & ((1 << 64) - 1)
     return p
 

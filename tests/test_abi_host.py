@@ -40,7 +40,7 @@ def test_params_struct_layout_matches_header(lib):
     assert p.beta1 == 0.9 and p.beta2 == 0.999 and p.adam_eps == 1e-8
     assert p.w == 1.0 and p.theta == 1.0 and p.lam == 0.0 and p.mu == 0.0
     assert math.isinf(p.lower) and p.lower < 0 and p.tau_f == 1
-    assert ctypes.sizeof(N.GcpParams) == 208
+    assert ctypes.sizeof(N.GcpParams) == 224
     assert ctypes.sizeof(N.GcpSlice) == 32
 
 
@@ -76,7 +76,8 @@ def test_invalid_params_rejected(lib, field, value, code):
 @pytest.mark.parametrize("fields,code", [
     ({"tsolve": 2}, "E_ARG"), ({"tsolve": -1}, "E_ARG"), ({"kappa_f": -1}, "E_ARG"),
     ({"kappa_f": 65}, "E_ARG"), ({"tol_f": float("nan")}, "E_ARG"),
-    ({"kappa_f": 2, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4}, "E_UNSUPPORTED"),
+    ({"kappa_f": 2, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4}, "E_ARG"),
+    ({"kappa_f": 2, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4, "p_est": -1, "q_est": 5}, "E_ARG"),
     ({"tsolve": 1, "tau_w": 0}, "E_ARG"), ({"tsolve": 1, "kappa_w": 65}, "E_ARG"),
     ({"tsolve": 1, "kappa_w": -1}, "E_ARG"), ({"tsolve": 1, "alpha_w": 0.0}, "E_ARG"),
     ({"tsolve": 1, "alpha_w": float("inf")}, "E_ARG"), ({"tsolve": 1, "tol_w": float("nan")}, "E_ARG"),

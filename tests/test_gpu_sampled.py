@@ -155,3 +155,34 @@ def test_dump_samples_are_uniform():
         exp = obs.sum() / len(obs)
         stat = float(np.sum((obs - exp) ** 2 / exp))
         assert stat < chi2.ppf(0.999, len(obs) - 1), stat
+
+
+@pytest.mark.parametrize("alpha,expect_roll", [(1e-2, False), (1.0, True), (0.3, False)])
+def test_sampled_factor_epochs_match_oracle(alpha, expect_roll):
+    """Algorithm 4 on COO slices: sampled gradients (new draws each step),
+    epochs judged by Algorithm 5's estimate over draws fixed for the solve,
+    decisions and factors equal to the oracle's."""
+    import torch
+    from types import SimpleNamespace
+    print("case: sampled epochs", alpha, flush=True)
+    prob = _f32(gi.sparse_problem(dims=(25, 30, 35), rank=8, window=2, nnz=1200, p=1500, q=1500,
+                                  seed=5, loss="poisson_log"))
+    st, T = _stream(prob, alpha_f=alpha, tau_f=2, kappa_f=3, p_est=2000, q_est=2000)
+    st.update_factors(_dev_coo(prob.X_t), T(prob.s_t))
+    info = st.factor_info()
+    assert st.sync() == 0
+    A = [np.asarray(a, np.float64).copy() for a in prob.A]
+    z = [np.zeros_like(a) for a in A]
+    state = SimpleNamespace(A=A, u=[a.copy() for a in z], v=[a.copy() for a in z], Ao=[a.copy() for a in A],
+                            uo=[a.copy() for a in z], vo=[a.copy() for a in z], alpha=alpha, i=0, call=0)
+    rolled = osm.sampled_factor_epochs(prob, state, tau=2, kappa=3, p_est=2000, q_est=2000)
+    assert rolled[0] == expect_roll
+    # decisions far from ties compared with FP32 rounding of the estimates
+    assert all(abs(t - f) > 1e-4 * abs(f) for t, f in zip(state.F_try, state.F_hist[:-1]))
+    assert info["rolled"] == rolled and info["iters"] == state.i
+    assert info["alpha"] == pytest.approx(state.alpha, rel=1e-15)
+    assert abs(info["F"] - state.F) <= 1e-5 * abs(state.F)
+    got = [a.double().cpu().numpy() for a in st.factors()]
+    for k in range(3):
+        assert rel_err(got[k], state.A[k]) <= 1e-5
+    assert st.info()["sample_call"] == 6
