@@ -98,13 +98,17 @@ typedef enum { GCP_HIST_SLICES = 0, GCP_HIST_MODEL = 1 } gcp_hist;
 
 /* Temporal-weight solver of gcp_solve_st (gcp_params.tsolve).
  * LS: the least-squares solve of Section 5 (Gaussian loss only).
- * SGD: Algorithm 3 on dense slices, any loss: s <- 0 and fresh ADAM moments,
+ * SGD: Algorithm 3, any loss: s <- 0 and fresh ADAM moments,
  *   then at most kappa_w epochs while F > tol_w, each tau_w ADAM steps
  *   (Algorithm 2, Step, rate alpha_w, iteration index i from 0) on the
  *   gradient of F(s) = sum_i f(x_i, m_i(s)) + mu/2 ||s||^2 over X_t, then
  *   F at the new s; an epoch that raised F is rolled back (s and the moments
  *   return to the last accepted epoch, i goes back tau_w steps, the rate is
- *   multiplied by 0.1).  Gradient and objective are exact over X_t. */
+ *   multiplied by 0.1).  Dense slices: gradient and objective exact over
+ *   X_t.  COO slices: each step's weight gradient is the sampled one of X_t
+ *   alone (p nonzero and q zero draws, a new call number each), and F is
+ *   Algorithm 5's estimate with p_est and q_est draws under the call number
+ *   2^31 + 2^30 + (t mod 2^30), fixed for the solve. */
 typedef enum { GCP_TSOLVE_LS = 0, GCP_TSOLVE_SGD = 1 } gcp_tsolve;
 
 /* Flags of gcp_params.flags. */
@@ -153,7 +157,8 @@ typedef struct {
   double alpha_w;         /* SGD: initial ADAM rate, > 0                    */
   double tol_w;           /* SGD: stop once F <= tol_w (-INFINITY: never)   */
   double tol_f;           /* factor epochs: stop once F <= tol_f            */
-  int64_t p_est, q_est;   /* COO factor epochs: nonzero / zero draws per
+  int64_t p_est, q_est;   /* COO streams with an SGD solver (kappa_f > 0 or
+                           * GCP_TSOLVE_SGD): nonzero / zero draws per
                            * slice of Algorithm 5's objective estimate     */
 } gcp_params;
 
@@ -231,10 +236,10 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t,
  * GCP_TSOLVE_LS (Gaussian loss only): the least-squares solve of Section 5,
  *   (Gamma + mu/2 I) s = Z^T vec(X_t) with Gamma = hadamard_k A^(k)^T A^(k),
  *   formed and solved in FP64 on the device, then s <- max(s, l).
- * GCP_TSOLVE_SGD (dense slices, any loss): Algorithm 3 as described at
- *   gcp_tsolve, every decision taken on the device (kappa_w (tau_w + 1) + 2
- *   kernel launches, no host synchronisation).  s_t is the solver's iterate
- *   while it runs.
+ * GCP_TSOLVE_SGD (any loss, dense or COO slices): Algorithm 3 as described
+ *   at gcp_tsolve, every decision taken on the device (a fixed sequence of
+ *   launches, no host synchronisation).  s_t is the solver's iterate while
+ *   it runs.
  * Writes s_t (R values of the stream dtype). */
 gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t);
 
@@ -252,8 +257,8 @@ gcp_status gcp_solve_st_info(gcp_stream* s, double* F, double* alpha, int64_t* i
  * kappa_f > 0: Alg. 4's epochs.  F = the objective without mu/2 ||s_t||^2:
  *   exact over X_t and the window for dense slices; for COO slices Alg. 5's
  *   estimate with p_est nonzero and q_est zero draws per slice, over draws
- *   fixed for the call (call number 2^31 + t, apart from the gradients'
- *   counter) with exact history and regulariser terms; at most kappa_f epochs
+ *   fixed for the call (call number 2^31 + (t mod 2^30), apart from the
+ *   gradients' counter) with exact history and regulariser terms; at most kappa_f epochs
  *   while F > tol_f, each tau_f [gradient, ADAM Step] iterations and then F
  *   at the new factors; an epoch that raised F is undone (factors and
  *   moments return to the last accepted epoch, the index goes back tau_f

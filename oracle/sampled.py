@@ -131,12 +131,16 @@ def sampled_loss_grad(prob, call: int = 0):
     return F, G, g_s
 
 
-# Call number of the objective estimates of Algorithm 5 within the factor
-# solve of time step t: fixed for the whole solve (every epoch compares
-# estimates over the same draws) and apart from the gradient calls, which
-# count up from 0.
+# Call numbers of the objective estimates of Algorithm 5 within the factor
+# and the weight solves of time step t: fixed for a whole solve (every epoch
+# compares estimates over the same draws), different for the two solvers and
+# for each slice, and apart from the gradient calls, which count up from 0.
 def estimate_call(t: int) -> int:
-    return 0x80000000 | (int(t) & 0x7FFFFFFF)
+    return 0x80000000 | (int(t) & 0x3FFFFFFF)
+
+
+def weight_estimate_call(t: int) -> int:
+    return 0xC0000000 | (int(t) & 0x3FFFFFFF)
 
 
 def estimate_objective(prob, p_est: int, q_est: int, call: int) -> float:
@@ -156,9 +160,11 @@ def sampled_factor_epochs(prob, state, *, tau, kappa, tol=-np.inf, p_est, q_est,
     5's estimate over draws fixed for the solve, with the ADAM Update of
     Algorithm 2 (roll-back, rate times decay, index back tau).  `state`
     holds A, u, v, the saved Ao, uo, vo, alpha, i and the next call number;
-    it is updated in place.  Returns the list of roll-back decisions."""
+    it is updated in place.  Every scheduled step consumes a call number,
+    also after the stopping test is met.  Returns the roll-back decisions."""
     from .adam import adam_step
     ecall = estimate_call(prob.t)
+    call_end = state.call + tau * kappa
     prob.A = [a.copy() for a in state.A]
     F = estimate_objective(prob, p_est, q_est, ecall)
     rolled, state.F_hist, state.F_try = [], [F], []
@@ -192,4 +198,58 @@ def sampled_factor_epochs(prob, state, *, tau, kappa, tol=-np.inf, p_est, q_est,
             rolled.append(False)
         state.F_hist.append(F)
     state.F = F
+    state.call = call_end
     return rolled
+
+
+def sampled_temporal_sgd(prob, call: int, *, alpha, tau, kappa, tol=-np.inf, p_est, q_est, beta1=0.9, beta2=0.999,
+                         eps=1e-8, lower=-np.inf, decay=0.1):
+    """Algorithm 3 on a sparse slice X_t (prob.X_t, factors prob.A fixed):
+    s <- 0, epochs of tau ADAM steps on sampled weight gradients of X_t
+    alone (no history, no factor regulariser; a new call number per step,
+    counting from `call`), each judged by Algorithm 5's estimate of
+    sum f + mu/2 ||s||^2 over draws fixed for the solve.  Returns
+    (s, info) with info.rolled, info.F (accepted estimates), info.F_try,
+    info.alpha, info.iters and info.call (the next call number)."""
+    from types import SimpleNamespace
+    from .adam import adam_step
+    R = np.asarray(prob.A[0]).shape[1]
+    base = SimpleNamespace(**vars(prob))
+    base.X_hist, base.s_hist, base.t_hist, base.lam = [], np.zeros((0, R)), np.zeros(0, np.int64), 0.0
+
+    def estimate(s):
+        e = SimpleNamespace(**vars(base))
+        e.s_t, e.p, e.q = s, p_est, q_est
+        return sampled_loss_grad(e, call=weight_estimate_call(prob.t))[0]
+
+    s = np.zeros(R)
+    u, v = np.zeros(R), np.zeros(R)
+    so, uo, vo = s.copy(), u.copy(), v.copy()
+    i, nxt, end = 0, call, call + tau * kappa
+    F = estimate(s)
+    info = SimpleNamespace(F=[F], F_try=[], rolled=[])
+    for _ in range(kappa):
+        if not F > tol:
+            break
+        F_old = F
+        for _ in range(tau):
+            g = SimpleNamespace(**vars(base))
+            g.s_t = s
+            gs = sampled_loss_grad(g, call=nxt)[2]
+            nxt += 1
+            s, u, v = adam_step(s, gs, u, v, i, alpha, beta1, beta2, eps, lower)
+            i += 1
+        F = estimate(s)
+        info.F_try.append(F)
+        if F > F_old:
+            s, u, v = so.copy(), uo.copy(), vo.copy()
+            alpha *= decay
+            i -= tau
+            F = F_old
+            info.rolled.append(True)
+        else:
+            so, uo, vo = s.copy(), u.copy(), v.copy()
+            info.rolled.append(False)
+        info.F.append(F)
+    info.alpha, info.iters, info.call = alpha, i, end
+    return s, info

@@ -53,6 +53,16 @@ struct gcp_stream {
 
 namespace {
 
+// COO streams whose SGD solvers judge epochs by Algorithm 5's estimates.
+bool needs_estimates(const gcp_params* p) {
+  return p->slice_kind == GCP_SLICE_COO && (p->kappa_f > 0 || p->tsolve == GCP_TSOLVE_SGD);
+}
+
+// Call numbers of the estimates of time step t: fixed for a solve, one per
+// solver, apart from the gradients' counter (which counts up from 0).
+uint32_t factor_estimate_call(int64_t t) { return 0x80000000u | (uint32_t)(t & 0x3FFFFFFF); }
+uint32_t weight_estimate_call(int64_t t) { return 0xC0000000u | (uint32_t)(t & 0x3FFFFFFF); }
+
 gcp_status check_params(const gcp_params* p) {
   if (!p) return GCP_E_ARG;
   if (p->abi_version != GCP_ABI_VERSION) return GCP_E_ARG;
@@ -87,13 +97,11 @@ gcp_status check_params(const gcp_params* p) {
   if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
   if (p->hist != GCP_HIST_SLICES && p->hist != GCP_HIST_MODEL) return GCP_E_ARG;
   if (p->kappa_f < 0 || p->kappa_f > 64 || isnan(p->tol_f)) return GCP_E_ARG;
-  if (p->kappa_f > 0 && p->slice_kind == GCP_SLICE_COO && (p->p_est < 0 || p->q_est < 0 || p->p_est + p->q_est < 1))
-    return GCP_E_ARG;
+  if (needs_estimates(p) && (p->p_est < 0 || p->q_est < 0 || p->p_est + p->q_est < 1)) return GCP_E_ARG;
   if (p->tsolve != GCP_TSOLVE_LS && p->tsolve != GCP_TSOLVE_SGD) return GCP_E_ARG;
   if (p->tsolve == GCP_TSOLVE_SGD) {
     if (p->tau_w < 1 || p->kappa_w < 0 || p->kappa_w > 64) return GCP_E_ARG;
     if (!(p->alpha_w > 0.0) || !isfinite(p->alpha_w) || isnan(p->tol_w)) return GCP_E_ARG;
-    if (p->slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
   }
   return GCP_OK;
 }
@@ -171,8 +179,8 @@ gcp_status check_coo_slice(const gcp_stream* s, const gcp_slice* X) {
   if (X->nnz > 0 && (!X->vals || !X->coords)) return GCP_E_ARG;
   if (s->p.p > 0 && X->nnz == 0) return GCP_E_ARG;               // no nonzero to draw
   if (s->p.q > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;  // no zero to draw
-  if (s->p.kappa_f > 0 && s->p.p_est > 0 && X->nnz == 0) return GCP_E_ARG;
-  if (s->p.kappa_f > 0 && s->p.q_est > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;
+  if (needs_estimates(&s->p) && s->p.p_est > 0 && X->nnz == 0) return GCP_E_ARG;
+  if (needs_estimates(&s->p) && s->p.q_est > 0 && (int64_t)s->omega - X->nnz <= 0) return GCP_E_ARG;
   if (((uintptr_t)X->coords & 3u) || ((uintptr_t)X->vals & 3u)) return GCP_E_ALIGN;
   return GCP_OK;
 }
@@ -395,8 +403,8 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
     } else {
       if (X_hist[h].kind != GCP_SLICE_COO || X_hist[h].nnz < 0 || X_hist[h].nnz > p->max_nnz) return GCP_E_SHAPE;
       if (X_hist[h].nnz > 0 && (!X_hist[h].vals || !X_hist[h].coords)) return GCP_E_ARG;
-      if ((p->p > 0 || (p->kappa_f > 0 && p->p_est > 0)) && X_hist[h].nnz == 0) return GCP_E_ARG;
-      if ((p->q > 0 || (p->kappa_f > 0 && p->q_est > 0)) && X_hist[h].nnz >= p->dims[0] * p->dims[1] * p->dims[2])
+      if ((p->p > 0 || (needs_estimates(p) && p->p_est > 0)) && X_hist[h].nnz == 0) return GCP_E_ARG;
+      if ((p->q > 0 || (needs_estimates(p) && p->q_est > 0)) && X_hist[h].nnz >= p->dims[0] * p->dims[1] * p->dims[2])
         return GCP_E_ARG;
     }
     if (h > 0 && t_hist[h] <= t_hist[h - 1]) return GCP_E_ARG;
@@ -542,12 +550,47 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
   return hip_status(e);
 }
 
+// Algorithm 3 on a COO slice: sampled weight gradients over X_t alone (a new
+// call number each), Algorithm 5's estimates over draws fixed for the solve.
+hipError_t coo_weight_sgd(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
+  const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
+  void* gs = s->ws + s->L.gs;
+  void* loss = s->ws + s->L.loss;
+  const TsgdCall tc = tsgd_call(s, nullptr, A, s_t, s->status);
+  auto estimate = [&]() {
+    SampledCall c = sampled_call(s, X_t, A, s_t, kWantLoss, loss, G, gs, (int64_t)weight_estimate_call(s->t));
+    c.ns = 1;             // the weight problem has no history term
+    c.lam = 0.0;
+    c.p = s->p.p_est;
+    c.q = s->p.q_est;
+    return sampled_run(c);
+  };
+  hipError_t e = build_current_table(s, X_t);
+  if (e == hipSuccess) e = tsgd_sampled_begin(tc);
+  if (e == hipSuccess) e = estimate();
+  if (e == hipSuccess) e = tsgd_sampled_decide(tc, loss, 1);
+  for (int ep = 0; ep < s->p.kappa_w && e == hipSuccess; ++ep) {
+    for (int it = 0; it < s->p.tau_w && e == hipSuccess; ++it) {
+      SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, loss, G, gs);
+      c.ns = 1;
+      c.lam = 0.0;
+      e = sampled_run(c);
+      if (e == hipSuccess) e = tsgd_sampled_step(tc, gs);
+    }
+    if (e == hipSuccess) e = estimate();
+    if (e == hipSuccess) e = tsgd_sampled_decide(tc, loss, 0);
+  }
+  return e;
+}
+
 gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
   if (!s || !s_t) return GCP_E_ARG;
-  if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
-  if (s->p.tsolve == GCP_TSOLVE_LS && s->p.loss != GCP_LOSS_GAUSSIAN) return GCP_E_UNSUPPORTED;
-  gcp_status st = check_dense_slice(s, X_t);
+  const bool coo = s->p.slice_kind == GCP_SLICE_COO;
+  if (s->p.tsolve == GCP_TSOLVE_LS && (coo || s->p.loss != GCP_LOSS_GAUSSIAN)) return GCP_E_UNSUPPORTED;
+  gcp_status st = coo ? check_coo_slice(s, X_t) : check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
+  if (coo) return hip_status(coo_weight_sgd(s, X_t, s_t));
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   if (s->p.tsolve == GCP_TSOLVE_SGD) return hip_status(tsgd_run(tsgd_call(s, X_t->vals, A, s_t, s->status)));
   return hip_status(ls_solve_run(s->dims[0], s->dims[1], s->dims[2], s->p.rank, s->p.dtype, X_t->vals, A, s->p.mu,
@@ -627,7 +670,7 @@ hipError_t coo_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, v
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
   SampledCall c = sampled_call(s, X_t, A, s_t, kWantLoss, loss, G, s->ws + s->L.gs,
-                               (int64_t)(0x80000000u | (uint32_t)(s->t & 0x7FFFFFFF)));
+                               (int64_t)factor_estimate_call(s->t));
   c.p = s->p.p_est;
   c.q = s->p.q_est;
   c.mu = 0.0;

@@ -32,6 +32,13 @@ struct TsgdCall {
 };
 size_t tsgd_ws_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t tsgd_run(const TsgdCall& c);
+// Pieces of Algorithm 3 for sampled (COO) slices, whose gradients and
+// objective estimates come from the sampled kernels: reset the solver, the
+// ADAM Step from a weight gradient g (mu s included), and the start (init)
+// or end-of-epoch decision on an estimate *F (mu/2 ||s||^2 included).
+hipError_t tsgd_sampled_begin(const TsgdCall& c);
+hipError_t tsgd_sampled_step(const TsgdCall& c, const void* g);
+hipError_t tsgd_sampled_decide(const TsgdCall& c, const void* F, int init);
 
 // Epochs of the factor solver (Algorithm 4): state kept for the whole stream.
 struct FacState {

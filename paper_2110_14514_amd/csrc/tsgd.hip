@@ -97,6 +97,50 @@ __device__ T sum_cols(const T* part, int nblk, int stride, int col0, int ncol, T
   return (int)threadIdx.x < C ? red[threadIdx.x] : T(0);
 }
 
+// Epoch bookkeeping on the objective Fv (thread 0): at the start F <- Fv;
+// after an epoch keep it (F <- Fv) or roll back (rate x decay, index back
+// tau, powers recomputed); then the stopping test.  Returns 1 for a roll-back.
+template <typename T>
+__device__ int ts_decide(const TsArgs<T>& a, T Fv, bool init) {
+  TsgdState* st = a.st;
+  if (!isfinite(Fv)) atomicOr(a.status, (int)kStatusNonFinite);
+  int roll = 0;
+  if (init) {
+    st->F = (double)Fv;
+  } else {
+    roll = (double)Fv > st->F;
+    if (roll) {
+      st->alpha *= kTsDecay;
+      st->i -= a.tau;
+      st->p1 = pow(a.beta1, (double)st->i);
+      st->p2 = pow(a.beta2, (double)st->i);
+      st->rolled |= 1ull << st->epoch;
+    } else {
+      st->F = (double)Fv;
+    }
+    st->epoch += 1;
+  }
+  st->done = !(st->F > a.tol);
+  return roll;
+}
+
+// ADAM Update: s, u, v back to the saved copies, or the copies refreshed
+// (threads j < R; s_now holds s as the epoch left it).
+template <typename T>
+__device__ void ts_keep_or_undo(const TsArgs<T>& a, int roll, const T* s_now) {
+  const int j = threadIdx.x;
+  if (j >= a.R) return;
+  if (roll) {
+    a.s[j] = a.so[j];
+    a.u[j] = a.uo[j];
+    a.v[j] = a.vo[j];
+  } else {
+    a.so[j] = s_now[j];
+    a.uo[j] = a.u[j];
+    a.vo[j] = a.v[j];
+  }
+}
+
 template <typename T, int LOSS, int RK, int MODE, int NT>
 __global__ void __launch_bounds__(NT) ts_pass(TsArgs<T> a) {
   constexpr int W = NT / 64;
@@ -275,40 +319,50 @@ __global__ void __launch_bounds__(NT) ts_final(TsArgs<T> a) {
   if (threadIdx.x == 0) {
     T reg = T(0);
     for (int j = 0; j < R; ++j) reg += sh_s[j] * sh_s[j];
-    const T Fv = data + T(0.5) * a.mu * reg;
-    if (!isfinite(Fv)) atomicOr(a.status, (int)kStatusNonFinite);
-    int roll = 0;
-    if (MODE == kTsObjInit) {
-      st->F = (double)Fv;
-    } else {
-      roll = (double)Fv > st->F;
-      if (roll) {
-        st->alpha *= kTsDecay;
-        st->i -= a.tau;
-        st->p1 = pow(a.beta1, (double)st->i);
-        st->p2 = pow(a.beta2, (double)st->i);
-        st->rolled |= 1ull << st->epoch;
-      } else {
-        st->F = (double)Fv;
-      }
-      st->epoch += 1;
-    }
-    st->done = !(st->F > a.tol);
-    sh_roll = roll;
+    sh_roll = ts_decide(a, data + T(0.5) * a.mu * reg, MODE == kTsObjInit);
   }
   __syncthreads();
-  if (MODE == kTsObjEpoch && (int)threadIdx.x < R) {
-    const int j = threadIdx.x;
-    if (sh_roll) {
-      a.s[j] = a.so[j];
-      a.u[j] = a.uo[j];
-      a.v[j] = a.vo[j];
-    } else {
-      a.so[j] = sh_s[j];
-      a.uo[j] = a.u[j];
-      a.vo[j] = a.v[j];
-    }
+  if (MODE == kTsObjEpoch) ts_keep_or_undo(a, sh_roll, sh_s);
+}
+
+// Sampled (COO) variant: the ADAM Step on s from a weight gradient g (which
+// holds mu s already), then i <- i + 1.  One workgroup of 64 threads.
+template <typename T>
+__global__ void ts_step_from(TsArgs<T> a, const T* g) {
+  TsgdState* st = a.st;
+  if (st->done) return;
+  const int j = threadIdx.x;
+  if (j < a.R) {
+    const double p1 = st->p1 * a.beta1, p2 = st->p2 * a.beta2;
+    const T alpha_t = (T)(st->alpha * sqrt(1.0 - p2) / (1.0 - p1));
+    const T gj = g[j];
+    if (!isfinite(gj)) atomicOr(a.status, (int)kStatusNonFinite);
+    const T uj = a.b1 * a.u[j] + (T(1) - a.b1) * gj;
+    const T vj = a.b2 * a.v[j] + (T(1) - a.b2) * gj * gj;
+    a.u[j] = uj;
+    a.v[j] = vj;
+    const T sj = a.s[j] - alpha_t * uj / (sqrt(vj) + a.eps);
+    a.s[j] = sj > a.lower ? sj : a.lower;
   }
+  __syncthreads();
+  if (j == 0) {
+    st->i += 1;
+    st->p1 *= a.beta1;
+    st->p2 *= a.beta2;
+  }
+}
+
+// Sampled (COO) variant of the objective decision, on an estimate *F that
+// holds mu/2 ||s||^2 already.  One workgroup of 64 threads.
+template <typename T>
+__global__ void ts_decide_from(TsArgs<T> a, const T* F, int init) {
+  __shared__ T sh_s[kMaxRank];
+  __shared__ int sh_roll;
+  if (a.st->done) return;
+  if ((int)threadIdx.x < a.R) sh_s[threadIdx.x] = a.s[threadIdx.x];
+  if (threadIdx.x == 0) sh_roll = ts_decide(a, *F, init != 0);
+  __syncthreads();
+  if (!init) ts_keep_or_undo(a, sh_roll, sh_s);
 }
 
 // Copies A^(1..3) (rows of R values) into rows of RK values, zeros past R.
@@ -409,7 +463,7 @@ size_t ts_part_off(int I1, int I2, int I3, int R, size_t es) {
 }
 
 template <typename T>
-hipError_t ts_run(const TsgdCall& c) {
+TsArgs<T> ts_args(const TsgdCall& c) {
   const TsGeom g = ts_geom(c.I1, c.I2, c.I3);
   char* base = static_cast<char*>(c.ws);
   const size_t vb = ts_vec_bytes(c.R, sizeof(T));
@@ -446,6 +500,15 @@ hipError_t ts_run(const TsgdCall& c) {
   a.beta1 = c.beta1;
   a.beta2 = c.beta2;
   a.tol = c.tol;
+  return a;
+}
+
+template <typename T>
+hipError_t ts_run(const TsgdCall& c) {
+  TsArgs<T> a = ts_args<T>(c);
+  char* base = static_cast<char*>(c.ws);
+  const int RK = ts_rank_tile(c.R);
+  T* pad = reinterpret_cast<T*>(base + ts_pad_off(c.R, sizeof(T)));
   const int64_t npad = ((int64_t)c.I1 + c.I2 + c.I3) * RK;
   hipLaunchKernelGGL(ts_pad<T>, dim3((unsigned)std::min<int64_t>(1024, (npad + 255) / 256)), dim3(256), 0, c.stream,
                      static_cast<const T*>(c.A[0]), static_cast<const T*>(c.A[1]), static_cast<const T*>(c.A[2]),
@@ -469,5 +532,38 @@ size_t tsgd_ws_bytes(int I1, int I2, int I3, int R, int dtype) {
 }
 
 hipError_t tsgd_run(const TsgdCall& c) { return c.dtype ? ts_run<double>(c) : ts_run<float>(c); }
+
+hipError_t tsgd_sampled_begin(const TsgdCall& c) {
+  if (c.dtype) {
+    TsArgs<double> a = ts_args<double>(c);
+    hipLaunchKernelGGL(ts_init<double>, dim3(1), dim3(64), 0, c.stream, a.s, a.u, a.v, a.so, a.uo, a.vo, c.R, a.st,
+                       c.alpha);
+  } else {
+    TsArgs<float> a = ts_args<float>(c);
+    hipLaunchKernelGGL(ts_init<float>, dim3(1), dim3(64), 0, c.stream, a.s, a.u, a.v, a.so, a.uo, a.vo, c.R, a.st,
+                       c.alpha);
+  }
+  return hipGetLastError();
+}
+
+hipError_t tsgd_sampled_step(const TsgdCall& c, const void* g) {
+  if (c.dtype)
+    hipLaunchKernelGGL(ts_step_from<double>, dim3(1), dim3(64), 0, c.stream, ts_args<double>(c),
+                       static_cast<const double*>(g));
+  else
+    hipLaunchKernelGGL(ts_step_from<float>, dim3(1), dim3(64), 0, c.stream, ts_args<float>(c),
+                       static_cast<const float*>(g));
+  return hipGetLastError();
+}
+
+hipError_t tsgd_sampled_decide(const TsgdCall& c, const void* F, int init) {
+  if (c.dtype)
+    hipLaunchKernelGGL(ts_decide_from<double>, dim3(1), dim3(64), 0, c.stream, ts_args<double>(c),
+                       static_cast<const double*>(F), init);
+  else
+    hipLaunchKernelGGL(ts_decide_from<float>, dim3(1), dim3(64), 0, c.stream, ts_args<float>(c),
+                       static_cast<const float*>(F), init);
+  return hipGetLastError();
+}
 
 }  // namespace gcp

@@ -159,7 +159,7 @@ class Stream:
 
     def solve_st(self, X_t: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         s = out if out is not None else torch.empty(self.rank, dtype=self.dtype, device=self.device)
-        sl = _dense_slice(X_t)
+        sl = _slice(X_t)
         N.check(self.lib.gcp_solve_st(self.handle, byref(sl), _ptr(s)), "gcp_solve_st")
         return s
 

@@ -81,7 +81,7 @@ def test_invalid_params_rejected(lib, field, value, code):
     ({"tsolve": 1, "tau_w": 0}, "E_ARG"), ({"tsolve": 1, "kappa_w": 65}, "E_ARG"),
     ({"tsolve": 1, "kappa_w": -1}, "E_ARG"), ({"tsolve": 1, "alpha_w": 0.0}, "E_ARG"),
     ({"tsolve": 1, "alpha_w": float("inf")}, "E_ARG"), ({"tsolve": 1, "tol_w": float("nan")}, "E_ARG"),
-    ({"tsolve": 1, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4}, "E_UNSUPPORTED"),
+    ({"tsolve": 1, "slice_kind": 1, "max_nnz": 10, "p": 4, "q": 4}, "E_ARG"),   # no estimate draws
 ])
 def test_invalid_temporal_solver_params_rejected(lib, fields, code):
     from paper_2110_14514_amd import _native as N

@@ -186,3 +186,25 @@ def test_sampled_factor_epochs_match_oracle(alpha, expect_roll):
     for k in range(3):
         assert rel_err(got[k], state.A[k]) <= 1e-5
     assert st.info()["sample_call"] == 6
+
+
+@pytest.mark.parametrize("alpha", [0.05, 1.0])
+def test_sampled_weight_solve_matches_oracle(alpha):
+    """Algorithm 3 on a COO slice: sampled weight gradients of X_t alone,
+    epochs judged by Algorithm 5's estimate; decisions, rate, index and
+    weights equal the oracle's, and the call counter moves by tau kappa."""
+    import torch
+    print("case: sampled weight solve", alpha, flush=True)
+    prob = _f32(gi.sparse_problem(dims=(25, 30, 35), rank=8, window=2, nnz=1200, p=1500, q=1500,
+                                  seed=5, loss="poisson_log"))
+    st, T = _stream(prob, tsolve="sgd", tau_w=3, kappa_w=3, alpha_w=alpha, p_est=2000, q_est=2000)
+    s = st.solve_st(_dev_coo(prob.X_t))
+    info = st.solve_info()
+    assert st.sync() == 0
+    ref, rinfo = osm.sampled_temporal_sgd(prob, 0, alpha=alpha, tau=3, kappa=3, p_est=2000, q_est=2000)
+    assert all(abs(t - f) > 1e-4 * abs(f) for t, f in zip(rinfo.F_try, rinfo.F[:-1]))
+    assert info["rolled"] == rinfo.rolled and info["iters"] == rinfo.iters
+    assert info["alpha"] == pytest.approx(rinfo.alpha, rel=1e-15)
+    assert abs(info["F"] - rinfo.F[-1]) <= 1e-5 * abs(rinfo.F[-1])
+    assert rel_err(s.double().cpu().numpy(), ref) <= 1e-4
+    assert st.info()["sample_call"] == 9

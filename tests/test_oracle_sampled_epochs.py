@@ -78,3 +78,32 @@ def test_rolled_back_epoch_restores_and_keeps_counting_draws():
     for x, y in zip(st.A, A0):
         assert np.array_equal(x, y)
     assert st.i == 0 and st.alpha == pytest.approx(0.3) and st.call == 2
+
+
+def test_sampled_weight_solve_is_adam_on_the_sampled_weight_gradient():
+    """Two accepted ADAM steps of Algorithm 3 on the sparse slice equal two
+    ADAM steps on the (separately pinned) sampled weight gradient of X_t
+    alone, calls 7 and 8, with the factor regulariser and history left out;
+    the epoch is judged on the estimate with the weight solver's draws."""
+    from types import SimpleNamespace
+    p = _prob(seed=8)
+    s, info = osm.sampled_temporal_sgd(p, 7, alpha=0.02, tau=2, kappa=1, p_est=300, q_est=300)
+    q = SimpleNamespace(**vars(p))
+    q.X_hist, q.s_hist, q.t_hist, q.lam = [], np.zeros((0, 3)), np.zeros(0, np.int64), 0.0
+    ref, u, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for it, call in enumerate((7, 8)):
+        q.s_t = ref
+        g = osm.sampled_loss_grad(q, call=call)[2]
+        ref, u, v = adam_step(ref, g, u, v, it, 0.02)
+    F1 = osm.estimate_objective(SimpleNamespace(**{**vars(q), "s_t": ref, "mu": p.mu}), 300, 300,
+                                osm.weight_estimate_call(p.t))
+    assert info.F_try[0] == pytest.approx(F1 + 0.5 * p.mu * float(ref @ ref), rel=1e-14)
+    if info.rolled == [False]:
+        assert np.array_equal(s, ref)
+    assert info.call == 9
+
+
+def test_sampled_weight_solve_draws_differ_from_the_factor_estimates():
+    p = _prob()
+    assert osm.weight_estimate_call(p.t) != osm.estimate_call(p.t)
+    assert osm.weight_estimate_call(p.t) != osm.weight_estimate_call(p.t + 1)
