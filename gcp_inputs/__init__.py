@@ -92,6 +92,11 @@ def _draw_data(g: np.random.Generator, loss: str, M: np.ndarray) -> np.ndarray:
     if loss == "bernoulli_logit":
         p = 1.0 / (1.0 + np.exp(-M))
         return (g.random(M.shape) < p).astype(np.float64)
+    if loss == "poisson_id":
+        return g.poisson(np.maximum(M, 0.0)).astype(np.float64)
+    if loss == "bernoulli_odds":
+        M = np.maximum(M, 0.0)
+        return (g.random(M.shape) < M / (1.0 + M)).astype(np.float64)
     raise ValueError(loss)
 
 
@@ -128,6 +133,26 @@ def weight_problem(dims, rank: int, loss: str, seed: int, dtype=np.float32):
     s_true = g.uniform(1.0, 3.0, size=rank)
     X = _draw_data(g, loss, ktensor_full(A, s_true))
     return X.astype(dtype), [a.astype(dtype) for a in A], s_true
+
+
+def nonneg_dense(dims, rank: int, window: int, loss: str, seed: int, w: float = 1.0, theta: float = 1.0,
+                 lam: float = 0.0, mu: float = 0.0, dtype=np.float32) -> DenseProblem:
+    """Instance for the identity- and odds-link losses (m >= 0): planted
+    factors U(0.1, 1), weights U(0.5, 1.5), data drawn around the planted
+    model; evaluation point factors U(0.1, 1) and weights U(0.5, 1.5)."""
+    g = rng(seed)
+    dims = tuple(int(d) for d in dims)
+    At = [g.uniform(0.1, 1.0, size=(n, rank)) for n in dims]
+    ns = window + 1
+    S_true = g.uniform(0.5, 1.5, size=(ns, rank))
+    Xs = [_draw_data(g, loss, ktensor_full(At, S_true[h])) for h in range(ns)]
+    A = [g.uniform(0.1, 1.0, size=(n, rank)) for n in dims]
+    S = g.uniform(0.5, 1.5, size=(ns, rank))
+    t = window + 1
+    t_hist = np.arange(1, t, dtype=np.int64)
+    p = DenseProblem(dims, rank, loss, Xs[-1], A, S[-1], Xs[:-1], S[:-1].reshape(window, rank), t_hist, t, w,
+                     theta, lam, mu, np.float64)
+    return p.cast(dtype)
 
 
 # ---------------------------------------------------------------- C1 ----

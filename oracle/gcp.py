@@ -40,6 +40,11 @@ from typing import List, Sequence
 import numpy as np
 
 LOSSES = ("gaussian", "poisson_log", "bernoulli_logit")
+# The two losses Section 2.2 writes out (identity and odds links), defined
+# for m >= 0, with log m replaced by log(m + eps) as its footnote says; the
+# paper leaves eps open ("a small constant"): 1e-10 here.
+PAPER_LOSSES = ("poisson_id", "bernoulli_odds")
+EPS = 1e-10
 
 
 # ------------------------------------------------------------- losses ----
@@ -54,6 +59,10 @@ def loss_f(loss: str, x, m):
     if loss == "bernoulli_logit":
         # log(1 + e^m) written so that it neither overflows nor cancels
         return np.maximum(m, 0.0) + np.log1p(np.exp(-np.abs(m))) - x * m
+    if loss == "poisson_id":
+        return m - x * np.log(m + EPS)
+    if loss == "bernoulli_odds":
+        return np.log1p(m) - x * np.log(m + EPS)
     raise ValueError(loss)
 
 
@@ -69,6 +78,10 @@ def loss_dfdm(loss: str, x, m):
         e = np.exp(-np.abs(m))
         sig = np.where(m >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
         return sig - x
+    if loss == "poisson_id":
+        return 1.0 - x / (m + EPS)
+    if loss == "bernoulli_odds":
+        return 1.0 / (m + 1.0) - x / (m + EPS)
     raise ValueError(loss)
 
 

@@ -355,3 +355,45 @@ def test_reservoir_inclusion_is_uniform():
     exp = trials * H / T
     chi2 = float(np.sum((obs - exp) ** 2 / exp))
     assert stats.chi2.sf(chi2, T - 1) > 1e-4, chi2
+
+
+# ------------------------------------------- identity / odds links ----
+@pytest.mark.parametrize("loss", og.PAPER_LOSSES)
+def test_paper_link_losses_are_negative_log_likelihoods(loss):
+    """Section 2.2's identity-link Poisson and odds-link Bernoulli losses:
+    f = -log p(x | l^-1(m)) up to terms free of m (eps = 1e-10 moves f by at
+    most x eps / m)."""
+    g = np.random.default_rng(11)
+    m = g.uniform(0.05, 4.0, size=60)
+    if loss == "poisson_id":
+        x = g.poisson(2.0, size=60).astype(float)
+        nll = -stats.poisson.logpmf(x, m)
+        const = gammaln(x + 1.0)
+    else:
+        x = (g.random(60) < 0.4).astype(float)
+        nll = -stats.bernoulli.logpmf(x, m / (1.0 + m))
+        const = 0.0
+    assert np.allclose(og.loss_f(loss, x, m) + const, nll, rtol=1e-9, atol=1e-8)
+
+
+@pytest.mark.parametrize("loss", og.PAPER_LOSSES)
+def test_paper_link_loss_derivatives_are_central_differences(loss):
+    g = np.random.default_rng(12)
+    m = g.uniform(0.1, 3.0, size=40)
+    x = g.poisson(1.5, size=40).astype(float) if loss == "poisson_id" else (g.random(40) < 0.5).astype(float)
+    h = 1e-6
+    fd = (og.loss_f(loss, x, m + h) - og.loss_f(loss, x, m - h)) / (2 * h)
+    assert np.allclose(og.loss_dfdm(loss, x, m), fd, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("loss", og.PAPER_LOSSES)
+def test_paper_link_gradient_matches_brute_force_loops(loss):
+    """The matrix formulas of the gradient with these losses agree with the
+    index-by-index loops on a tiny nonnegative instance."""
+    p = gi.nonneg_dense((3, 4, 5), 2, 2, loss, seed=13, lam=0.1, mu=0.2, dtype=np.float64)
+    assert og.objective(p) == pytest.approx(og.objective_loops(p), rel=1e-12)
+    G, gs = og.gradient(p)
+    Gl, gsl = og.gradient_loops(p)
+    for k in range(3):
+        assert rel(G[k], Gl[k]) <= 1e-12
+    assert rel(gs, gsl) <= 1e-12
