@@ -71,7 +71,13 @@ typedef enum {
 typedef enum {
   GCP_LOSS_GAUSSIAN = 0,
   GCP_LOSS_POISSON_LOG = 1,
-  GCP_LOSS_BERNOULLI_LOGIT = 2
+  GCP_LOSS_BERNOULLI_LOGIT = 2,
+  /* The two losses Section 2.2 writes out, for m >= 0 (take lower = 0):
+   * count data, identity link: f = m - x log(m + eps), eps = 1e-10;
+   * binary data, odds link:    f = log(m + 1) - x log(m + eps).
+   * Dense and COO single streams (not in batches); no LS solve. */
+  GCP_LOSS_POISSON_ID = 3,
+  GCP_LOSS_BERNOULLI_ODDS = 4
 } gcp_loss;
 
 typedef enum { GCP_F32 = 0, GCP_F64 = 1 } gcp_dtype;

@@ -23,7 +23,7 @@ OK, E_ARG, E_SHAPE, E_ALIGN, E_STATE, E_WORKSPACE, E_DEVICE, E_NUMERIC, E_UNSUPP
 STATUS_NAMES = ["GCP_OK", "GCP_E_ARG", "GCP_E_SHAPE", "GCP_E_ALIGN", "GCP_E_STATE",
                 "GCP_E_WORKSPACE", "GCP_E_DEVICE", "GCP_E_NUMERIC", "GCP_E_UNSUPPORTED"]
 
-LOSS_IDS = {"gaussian": 0, "poisson_log": 1, "bernoulli_logit": 2}
+LOSS_IDS = {"gaussian": 0, "poisson_log": 1, "bernoulli_logit": 2, "poisson_id": 3, "bernoulli_odds": 4}
 F32, F64 = 0, 1
 SLICE_DENSE, SLICE_COO = 0, 1
 WANT_LOSS, WANT_GRAD, IMPL_PLAIN = 1, 2, 256

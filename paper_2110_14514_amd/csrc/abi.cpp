@@ -73,7 +73,7 @@ gcp_status check_params(const gcp_params* p) {
   if ((double)p->dims[0] * p->dims[1] >= 2147483647.0) return GCP_E_SHAPE;
   if (p->rank < 1 || p->rank > GCP_MAX_RANK) return GCP_E_ARG;
   if (p->window < 0 || p->window > GCP_MAX_WINDOW) return GCP_E_ARG;
-  if (p->loss < 0 || p->loss > 2) return GCP_E_ARG;
+  if (p->loss < 0 || p->loss > 4) return GCP_E_ARG;
   if (p->dtype != GCP_F32 && p->dtype != GCP_F64) return GCP_E_ARG;
   if (p->slice_kind != GCP_SLICE_DENSE && p->slice_kind != GCP_SLICE_COO) return GCP_E_UNSUPPORTED;
   if (p->slice_kind == GCP_SLICE_COO) {
@@ -1144,6 +1144,7 @@ gcp_status batch_check(gcp_stream* const* streams, int32_t n) {
     if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32) return GCP_E_UNSUPPORTED;
     if (s->p.rank > 32 || s->p.window > 31) return GCP_E_UNSUPPORTED;
     if (model_hist(s)) return GCP_E_UNSUPPORTED;   // batches run the stored-slice history
+    if (s->p.loss > GCP_LOSS_BERNOULLI_LOGIT) return GCP_E_UNSUPPORTED;   // batch tiles: the first three losses
     if (s->p.kappa_f > 0) return GCP_E_UNSUPPORTED;  // batches keep every factor iteration
     if (s->p.tau_f != streams[0]->p.tau_f) return GCP_E_ARG;
     if (s->st != streams[0]->st) return GCP_E_ARG;

@@ -10,7 +10,9 @@ namespace gcp {
 constexpr int kMaxNs = 65;        // current slice + window of at most 64
 constexpr int kMaxRank = 64;
 
-enum Loss { kGaussian = 0, kPoissonLog = 1, kBernoulliLogit = 2 };
+enum Loss { kGaussian = 0, kPoissonLog = 1, kBernoulliLogit = 2, kPoissonId = 3, kBernoulliOdds = 4 };
+// epsilon of log(m + eps) in the identity- and odds-link losses (m >= 0)
+constexpr double kLossEps = 1e-10;
 enum Want { kWantLoss = 1, kWantGrad = 2 };
 
 // Deferred device status bits (workspace word).
@@ -50,6 +52,24 @@ struct LossFn<T, kBernoulliLogit> {
     T sig = m >= T(0) ? inv : e * inv;
     f = fmax(m, T(0)) + log1p(e) - x * m;
     y = sig - x;
+  }
+};
+
+template <typename T>
+struct LossFn<T, kPoissonId> {
+  __device__ __forceinline__ static void eval(T x, T m, T& f, T& y) {
+    const T me = m + T(kLossEps);
+    f = m - x * log(me);
+    y = T(1) - x / me;
+  }
+};
+
+template <typename T>
+struct LossFn<T, kBernoulliOdds> {
+  __device__ __forceinline__ static void eval(T x, T m, T& f, T& y) {
+    const T me = m + T(kLossEps);
+    f = log1p(m) - x * log(me);
+    y = T(1) / (m + T(1)) - x / me;
   }
 };
 
@@ -96,6 +116,32 @@ struct LossFast<kBernoulliLogit> {
     const float inv = __frcp_rn(1.f + e);
     f = fmaxf(m, 0.f) + __logf(1.f + e) - x * m;
     y = (m >= 0.f ? inv : e * inv) - x;
+  }
+};
+
+template <>
+struct LossFast<kPoissonId> {
+  __device__ __forceinline__ static float y(float x, float m) { return 1.f - x * __frcp_rn(m + (float)kLossEps); }
+  __device__ __forceinline__ static float f(float x, float m) { return m - x * __logf(m + (float)kLossEps); }
+  __device__ __forceinline__ static void fy(float x, float m, float& f, float& y) {
+    const float me = m + (float)kLossEps;
+    f = m - x * __logf(me);
+    y = 1.f - x * __frcp_rn(me);
+  }
+};
+
+template <>
+struct LossFast<kBernoulliOdds> {
+  __device__ __forceinline__ static float y(float x, float m) {
+    return __frcp_rn(m + 1.f) - x * __frcp_rn(m + (float)kLossEps);
+  }
+  __device__ __forceinline__ static float f(float x, float m) {
+    return __logf(m + 1.f) - x * __logf(m + (float)kLossEps);
+  }
+  __device__ __forceinline__ static void fy(float x, float m, float& f, float& y) {
+    const float me = m + (float)kLossEps;
+    f = __logf(m + 1.f) - x * __logf(me);
+    y = __frcp_rn(m + 1.f) - x * __frcp_rn(me);
   }
 };
 
@@ -187,6 +233,10 @@ hipError_t dense_mfma_launch_gaussian(const DenseCall& c, const MfmaPlan& p, flo
                                       float* gsp, float* lossp);
 hipError_t dense_mfma_launch_poisson(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                                      float* gsp, float* lossp);
+hipError_t dense_mfma_launch_poisson_id(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
+                                        float* gsp, float* lossp);
+hipError_t dense_mfma_launch_bernoulli_odds(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
+                                            float* G3p, float* gsp, float* lossp);
 hipError_t dense_mfma_launch_bernoulli(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                                        float* gsp, float* lossp);
 struct BatchRun;

@@ -435,7 +435,9 @@ hipError_t dispatch_loss(const DenseCall& c, const Tiling& tl, const PartLayout&
   switch (c.loss) {
     case kGaussian: return dispatch_rank<T, kGaussian>(c, tl, pl);
     case kPoissonLog: return dispatch_rank<T, kPoissonLog>(c, tl, pl);
-    default: return dispatch_rank<T, kBernoulliLogit>(c, tl, pl);
+    case kBernoulliLogit: return dispatch_rank<T, kBernoulliLogit>(c, tl, pl);
+    case kPoissonId: return dispatch_rank<T, kPoissonId>(c, tl, pl);
+    default: return dispatch_rank<T, kBernoulliOdds>(c, tl, pl);
   }
 }
 

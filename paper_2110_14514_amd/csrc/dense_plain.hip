@@ -279,8 +279,16 @@ hipError_t run_rt(const DenseCall& c, char* base, const PlainLayout& L) {
         hipLaunchKernelGGL(k_elem<kPoissonLog>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch, omega, c.I3,
                            pitch, lossp + (size_t)h * kEBlocks);
         break;
-      default:
+      case kBernoulliLogit:
         hipLaunchKernelGGL(k_elem<kBernoulliLogit>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch,
+                           omega, c.I3, pitch, lossp + (size_t)h * kEBlocks);
+        break;
+      case kPoissonId:
+        hipLaunchKernelGGL(k_elem<kPoissonId>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch, omega, c.I3,
+                           pitch, lossp + (size_t)h * kEBlocks);
+        break;
+      default:
+        hipLaunchKernelGGL(k_elem<kBernoulliOdds>, dim3(kEBlocks), dim3(256), 0, c.stream, X, M, Y, ch,
                            omega, c.I3, pitch, lossp + (size_t)h * kEBlocks);
     }
     if (c.want & kWantGrad) {

@@ -299,6 +299,33 @@ struct MLoss<kBernoulliLogit> {
   }
 };
 
+// Identity- and odds-link losses (m >= 0): the model is used as it is.
+template <>
+struct MLoss<kPoissonId> {
+  static constexpr float kM = 1.f, kY = 1.f, kF = 1.f;
+  __device__ __forceinline__ static float y(float x, float d) {
+    return 1.f - x * __builtin_amdgcn_rcpf(d + (float)kLossEps);
+  }
+  __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
+    const float me = d + (float)kLossEps;
+    facc = fmaf(cv, fmaf(-x, __logf(me), d), facc);   // m - x log(m + eps)
+    return 1.f - x * __builtin_amdgcn_rcpf(me);
+  }
+};
+
+template <>
+struct MLoss<kBernoulliOdds> {
+  static constexpr float kM = 1.f, kY = 1.f, kF = 1.f;
+  __device__ __forceinline__ static float y(float x, float d) {
+    return __builtin_amdgcn_rcpf(d + 1.f) - x * __builtin_amdgcn_rcpf(d + (float)kLossEps);
+  }
+  __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
+    const float me = d + (float)kLossEps;
+    facc = fmaf(cv, fmaf(-x, __logf(me), __logf(d + 1.f)), facc);   // log(m + 1) - x log(m + eps)
+    return __builtin_amdgcn_rcpf(d + 1.f) - x * __builtin_amdgcn_rcpf(me);
+  }
+};
+
 // One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
 // slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
 // Registers / GEMM2 K-steps of the last h-tile that hold slices of the window

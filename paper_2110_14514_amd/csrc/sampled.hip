@@ -630,7 +630,9 @@ hipError_t launch_draws(const SampledCall& c, const SArgs& a, int64_t blocks) {
   switch (c.loss) {
     case kGaussian: return launch_seg<kGaussian, REC>(c, a, blocks);
     case kPoissonLog: return launch_seg<kPoissonLog, REC>(c, a, blocks);
-    default: return launch_seg<kBernoulliLogit, REC>(c, a, blocks);
+    case kBernoulliLogit: return launch_seg<kBernoulliLogit, REC>(c, a, blocks);
+    case kPoissonId: return launch_seg<kPoissonId, REC>(c, a, blocks);
+    default: return launch_seg<kBernoulliOdds, REC>(c, a, blocks);
   }
 }
 

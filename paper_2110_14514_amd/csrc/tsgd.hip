@@ -450,8 +450,12 @@ void ts_launch(int loss, int mode, const TsArgs<T>& a, hipStream_t st) {
     ts_launch_loss<T, kGaussian>(mode, a, st);
   else if (loss == kPoissonLog)
     ts_launch_loss<T, kPoissonLog>(mode, a, st);
-  else
+  else if (loss == kBernoulliLogit)
     ts_launch_loss<T, kBernoulliLogit>(mode, a, st);
+  else if (loss == kPoissonId)
+    ts_launch_loss<T, kPoissonId>(mode, a, st);
+  else
+    ts_launch_loss<T, kBernoulliOdds>(mode, a, st);
 }
 
 size_t ts_vec_bytes(int R, size_t es) { return align_up((size_t)R * es, 64); }

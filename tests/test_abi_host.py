@@ -63,7 +63,7 @@ def _ws(lib, p):
 @pytest.mark.parametrize("field,value,code", [
     ("abi_version", 99, "E_ARG"), ("d", 4, "E_UNSUPPORTED"), ("rank", 0, "E_ARG"),
     ("rank", 65, "E_ARG"), ("window", 65, "E_ARG"), ("window", -1, "E_ARG"),
-    ("loss", 3, "E_ARG"), ("dtype", 5, "E_ARG"), ("theta", 0.0, "E_ARG"),
+    ("loss", 5, "E_ARG"), ("loss", -1, "E_ARG"), ("dtype", 5, "E_ARG"), ("theta", 0.0, "E_ARG"),
     ("theta", 1.5, "E_ARG"), ("mu", -1.0, "E_ARG"), ("slice_kind", 7, "E_UNSUPPORTED"),
     ("hist", 2, "E_ARG"), ("hist", -1, "E_ARG"), ("flags", 8, "E_ARG"),
 ])
