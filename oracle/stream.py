@@ -23,6 +23,12 @@ Follows the body of Algorithm 1 (Section 4.3) in the paper's order:
      only s_t is stored and the gradient is that of model_hist.py);
   5. A_old <- A.
 Without epochs (kappa_f = 0) every iteration is kept.
+
+Matrix slices (d = 2, the shape of the paper's first synthetic experiment):
+a slice X_t is I1 x I2, the model m_ij = sum_r s_r a_ir b_jr.  It is carried
+here as the d = 3 problem with I3 = 1 and a fixed third factor of ones, which
+has the same model; only A^(1), A^(2) take ADAM steps and the factor
+regulariser covers those two (the fixed row's lam/2 R is left out of F).
 """
 from __future__ import annotations
 
@@ -45,7 +51,12 @@ class StreamOracle:
                  window=0, w=1.0, theta=1.0, lam=0.0, mu=0.0,
                  lower=-np.inf, alpha_f=1e-3, beta1=0.9, beta2=0.999,
                  adam_eps=1e-8, tau_f=1, seed=0, hist="slices", tsolve="ls",
-                 tau_w=100, kappa_w=20, alpha_w=1.0, tol_w=-np.inf, kappa_f=0, tol_f=-np.inf):
+                 tau_w=100, kappa_w=20, alpha_w=1.0, tol_w=-np.inf, kappa_f=0, tol_f=-np.inf, d=3):
+        self.d = d
+        if d == 2:
+            R = np.asarray(A0[0]).shape[1]
+            A0 = [A0[0], A0[1], np.ones((1, R))]
+            X_hist = [np.asarray(x).reshape(np.asarray(x).shape[:2] + (1,)) for x in X_hist]
         self.A = [np.array(a, np.float64) for a in A0]
         self.A_old = [a.copy() for a in self.A]
         self.u = [np.zeros_like(a) for a in self.A]
@@ -58,7 +69,8 @@ class StreamOracle:
         self.slots = [int(t) for t in t_hist]
         self.hist = hist
         self.Xw = [np.array(x, np.float64) for x in X_hist] if hist == "slices" else []
-        self.Sw = [np.array(s, np.float64) for s in np.asarray(s_hist).reshape(len(self.slots), -1)]
+        self.Sw = ([np.array(s, np.float64) for s in np.asarray(s_hist).reshape(len(self.slots), -1)]
+                   if self.slots else [])
         self.t = (max(self.slots) + 1) if self.slots else 1
         self.cfg = SimpleNamespace(loss=loss, H=window, w=w, theta=theta,
                                    lam=lam, mu=mu, lower=lower,
@@ -71,13 +83,15 @@ class StreamOracle:
         c = self.cfg
         return SimpleNamespace(X_t=X_t, A=self.A if A is None else A, s_t=s_t,
                                A_old=self.A_old, X_hist=self.Xw,
-                               s_hist=np.array(self.Sw).reshape(len(self.Sw), -1),
+                               s_hist=(np.array(self.Sw).reshape(len(self.Sw), -1) if self.Sw
+                                       else np.zeros((0, self.A[0].shape[1]))),
                                t_hist=np.array(self.slots, np.int64), t=self.t,
                                w=c.w, theta=c.theta, lam=c.lam, mu=c.mu,
                                loss=c.loss)
 
     def solve_st(self, X_t):
         c = self.cfg
+        X_t = self._slice3(X_t)
         if c.tsolve == "sgd":
             s, self.solve_info = temporal_sgd(X_t, self.A, c.loss, mu=c.mu, lower=c.lower, alpha=c.alpha_w,
                                               tau=c.tau_w, kappa=c.kappa_w, tol=c.tol_w, beta1=c.beta1,
@@ -89,16 +103,21 @@ class StreamOracle:
 
     def factor_objective(self, X_t, s_t) -> float:
         """The objective Algorithm 4 compares: every term but mu/2 ||s_t||^2."""
-        prob = self.problem(X_t, s_t)
+        prob = self.problem(self._slice3(X_t), s_t)
         prob.mu = 0.0
-        return objective(prob) if self.hist == "slices" else objective_model(prob)
+        F = objective(prob) if self.hist == "slices" else objective_model(prob)
+        return F - (0.5 * self.cfg.lam * self.A[2].size if self.d == 2 else 0.0)
+
+    def _slice3(self, X_t):
+        X_t = np.asarray(X_t, np.float64)
+        return X_t.reshape(X_t.shape[:2] + (1,)) if self.d == 2 else X_t
 
     def _iterations(self, X_t, s_t, n):
         c = self.cfg
         for _ in range(n):
             prob = self.problem(X_t, s_t)
             G, _ = gradient(prob) if self.hist == "slices" else gradient_model(prob)
-            for k in range(len(self.A)):
+            for k in range(self.d):
                 self.A[k], self.u[k], self.v[k] = adam_step(
                     self.A[k], G[k], self.u[k], self.v[k], self.i, self.alpha_f,
                     c.beta1, c.beta2, c.eps, c.lower)
@@ -106,6 +125,7 @@ class StreamOracle:
 
     def update_factors(self, X_t, s_t):
         c = self.cfg
+        X_t = self._slice3(X_t)
         if c.kappa_f == 0:
             self._iterations(X_t, s_t, c.tau_f)
         else:
