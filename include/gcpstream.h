@@ -22,7 +22,7 @@
  * m-independent terms dropped).
  *
  * Conventions shared by every call
- *  - Only d = 3 slices are supported (GCP_E_UNSUPPORTED otherwise).
+ *  - Slices of order d = 3, or d = 2 (matrix slices; GCP_E_UNSUPPORTED otherwise).
  *  - A dense slice is I_1 x I_2 x I_3, row-major (last index contiguous),
  *    base aligned to 16 bytes.  A factor matrix A^(k) is I_k x R row-major.
  *  - Every array argument is a DEVICE pointer unless marked "host".
@@ -134,7 +134,13 @@ enum {
 /* Table 1 (Section 4.2) of the paper, plus layout and sampling controls. */
 typedef struct {
   uint32_t abi_version;   /* GCP_ABI_VERSION                               */
-  int32_t d;              /* slice order; must be 3                        */
+  int32_t d;              /* slice order: 3, or 2 for matrix slices (then
+                           * dims[2] = 1 and the third factor is a fixed
+                           * 1 x R row of ones: A0[2], A[2], G[2] and
+                           * A_out[2] may be NULL, only A^(1), A^(2) take
+                           * ADAM steps, and the objective's factor
+                           * regulariser covers those two; COO coords
+                           * keep three columns with i3 = 0; no batches)  */
   int64_t dims[GCP_MAX_D];/* I_1, I_2, I_3                                 */
   int32_t rank;           /* R, 1..GCP_MAX_RANK                            */
   int32_t window;         /* H, 0..GCP_MAX_WINDOW                          */

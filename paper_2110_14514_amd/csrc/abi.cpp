@@ -66,7 +66,8 @@ uint32_t weight_estimate_call(int64_t t) { return 0xC0000000u | (uint32_t)(t & 0
 gcp_status check_params(const gcp_params* p) {
   if (!p) return GCP_E_ARG;
   if (p->abi_version != GCP_ABI_VERSION) return GCP_E_ARG;
-  if (p->d != 3) return GCP_E_UNSUPPORTED;
+  if (p->d != 2 && p->d != 3) return GCP_E_UNSUPPORTED;
+  if (p->d == 2 && p->dims[2] != 1) return GCP_E_SHAPE;   // matrix slices: I3 = 1
   for (int k = 0; k < 3; ++k)
     if (p->dims[k] < 1 || p->dims[k] > (1 << 30)) return GCP_E_SHAPE;
   if ((double)p->dims[0] * p->dims[1] * p->dims[2] > 9.0e15) return GCP_E_SHAPE;
@@ -133,7 +134,7 @@ WsLayout layout_for(const gcp_params* p) {
   L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
   // stored dense slices keep each (i1, i2) row on 128-byte lines: the row
   // pitch is I3 rounded up to 32 values (the padding is never read)
-  L.rp3 = ((size_t)I3 + 31) / 32 * 32;
+  L.rp3 = p->d == 2 ? 1 : ((size_t)I3 + 31) / 32 * 32;   // matrix slices: rows of one value
   L.slot_elems = (size_t)I1 * I2 * L.rp3;
   (void)omega;
   L.ring = off;
@@ -304,6 +305,19 @@ DenseCall base_call(gcp_stream* s) {
 
 gcp_status hip_status(hipError_t e) { return e == hipSuccess ? GCP_OK : GCP_E_DEVICE; }
 
+// Factor entries that take ADAM steps: all three blocks, or the first two for
+// matrix slices (the fixed row is the last block of the packed layout).
+int64_t adam_elems(const gcp_stream* s) {
+  return (int64_t)(s->p.d == 2 ? s->L.fac_off[2] : s->L.fac_elems);
+}
+
+// Matrix slices: the kernels' factor regulariser also covers the fixed row
+// (lambda/2 R); take it out of an objective value on the device.
+hipError_t d2_fix_loss(gcp_stream* s, void* loss) {
+  if (s->p.d != 2 || s->p.lambda == 0.0 || !loss) return hipSuccess;
+  return scalar_add_run(s->p.dtype == GCP_F64, loss, -0.5 * s->p.lambda * s->p.rank, s->st);
+}
+
 // Algorithm 3 on X (dense, pitch I3) with the stream's factors A, iterating in s_t.
 TsgdCall tsgd_call(gcp_stream* s, const void* X, const void* const* A, void* s_t, int* status) {
   TsgdCall c;
@@ -387,7 +401,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   *out = nullptr;
   gcp_status st = check_params(p);
   if (st != GCP_OK) return st;
-  if (!A0 || !A0[0] || !A0[1] || !A0[2] || !workspace) return GCP_E_ARG;
+  if (!A0 || !A0[0] || !A0[1] || (!A0[2] && p->d == 3) || !workspace) return GCP_E_ARG;
   if (n_hist < 0 || n_hist > p->window) return GCP_E_ARG;
   const bool model = p->hist == GCP_HIST_MODEL;
   if (n_hist > 0 && (!s_hist || !t_hist || (!model && !X_hist))) return GCP_E_ARG;
@@ -425,11 +439,18 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   s->t = n_hist > 0 ? t_hist[n_hist - 1] + 1 : 1;
   for (int h = 0; h < n_hist; ++h) s->slot_t[h] = t_hist[h];
   hipError_t e = hipMemsetAsync(s->ws + L.status, 0, 256, s->st);
+  // matrix slices (d = 2): the third factor is a fixed 1 x R row of ones
+  std::vector<double> ones64(p->rank, 1.0);
+  std::vector<float> ones32(p->rank, 1.f);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     size_t nb = (size_t)s->dims[k] * p->rank * s->es;
-    e = hipMemcpyAsync(fac_ptr(s, L.A, k), A0[k], nb, hipMemcpyDeviceToDevice, s->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(fac_ptr(s, L.Aold, k), A0[k], nb, hipMemcpyDeviceToDevice, s->st);
+    const bool fixed = k == 2 && p->d == 2;
+    const void* src = fixed ? (s->es == 8 ? (const void*)ones64.data() : (const void*)ones32.data()) : A0[k];
+    const hipMemcpyKind kind = fixed ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    e = hipMemcpyAsync(fac_ptr(s, L.A, k), src, nb, kind, s->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(fac_ptr(s, L.Aold, k), src, nb, kind, s->st);
   }
+  if (e == hipSuccess && p->d == 2) e = hipStreamSynchronize(s->st);   // the host row must outlive its copies
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess && p->kappa_f > 0) {
@@ -491,9 +512,16 @@ gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const*
   return gcp_loss_grad_scaled(s, X_t, A, s_t, want, nullptr, loss, G, g_s);
 }
 
-gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void* const* A, const void* s_t,
-                                uint32_t want, const void* grad_scale, void* loss, void* const* G, void* g_s) {
-  if (!s || !A || !A[0] || !A[1] || !A[2] || !s_t) return GCP_E_ARG;
+gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void* const* A_in, const void* s_t,
+                                uint32_t want, const void* grad_scale, void* loss, void* const* G_in, void* g_s) {
+  if (!s || !A_in || !A_in[0] || !A_in[1] || !s_t) return GCP_E_ARG;
+  if (!A_in[2] && s->p.d == 3) return GCP_E_ARG;
+  // matrix slices: A[2] and G[2] may be NULL (the fixed row, its gradient to scratch)
+  const void* A[3] = {A_in[0], A_in[1], A_in[2] ? A_in[2] : fac_ptr(s, s->L.A, 2)};
+  void* Gv[3] = {nullptr, nullptr, nullptr};
+  if (G_in)
+    for (int k = 0; k < 3; ++k) Gv[k] = G_in[k] ? G_in[k] : (k == 2 && s->p.d == 2 ? fac_ptr(s, s->L.G, 2) : nullptr);
+  void* const* G = G_in ? Gv : nullptr;
   if (want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD | GCP_IMPL_PLAIN)) return GCP_E_ARG;
   if (!(want & (GCP_WANT_LOSS | GCP_WANT_GRAD))) return GCP_E_ARG;
   if ((want & GCP_WANT_LOSS) && !loss) return GCP_E_ARG;
@@ -516,6 +544,7 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
     }
     hipError_t es = sampled_run(c);
     if (es == hipSuccess) es = add_model_history(s, A, c.want, c.loss_out, c.G, nullptr);
+    if (es == hipSuccess && (want & GCP_WANT_LOSS)) es = d2_fix_loss(s, c.loss_out);
     return hip_status(es);
   }
   gcp_status st = check_dense_slice(s, X_t);
@@ -547,6 +576,7 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
   }
   hipError_t e = plain ? dense_plain_run(c, s->ws + s->L.plain, s->L.plain_bytes) : dense_fused_run(c);
   if (e == hipSuccess) e = add_model_history(s, A, c.want, c.loss_out, c.G, grad_scale);
+  if (e == hipSuccess && (want & GCP_WANT_LOSS)) e = d2_fix_loss(s, c.loss_out);
   return hip_status(e);
 }
 
@@ -649,6 +679,7 @@ hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t,
   c.loss_out = loss;
   hipError_t e = dense_fused_run(c);
   if (e == hipSuccess) e = add_model_history(s, c.A, kWantLoss, loss, c.G, nullptr);
+  if (e == hipSuccess) e = d2_fix_loss(s, loss);
   return e;
 }
 
@@ -676,6 +707,7 @@ hipError_t coo_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, v
   c.mu = 0.0;
   hipError_t e = sampled_run(c);
   if (e == hipSuccess) e = add_model_history(s, A, kWantLoss, loss, G, nullptr);
+  if (e == hipSuccess) e = d2_fix_loss(s, loss);
   return e;
 }
 
@@ -694,7 +726,7 @@ hipError_t factor_epochs(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
     for (int it = 0; it < p.tau_f && e == hipSuccess; ++it) {
       e = coo ? coo_grad_step(s, X_t, s_t) : dense_grad_step(s, X_t, s_t);
       if (e == hipSuccess)
-        e = fac_step_run(dt, n, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u, s->ws + s->L.v, st, p.beta1,
+        e = fac_step_run(dt, adam_elems(s), s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u, s->ws + s->L.v, st, p.beta1,
                          p.beta2, p.adam_eps, p.lower, s->st);
     }
     if (e == hipSuccess) e = objective();
@@ -740,7 +772,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
       if (e != hipSuccess) break;
       const double n = (double)(s->adam_i + 1);
       const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
-      e = adam_run(p.dtype, (int64_t)s->L.fac_elems, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u,
+      e = adam_run(p.dtype, adam_elems(s), s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u,
                    s->ws + s->L.v, alpha_t, p.beta1, p.beta2, p.adam_eps, p.lower, s->st);
       s->adam_i += 1;
       continue;
@@ -749,7 +781,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     if (e != hipSuccess) break;
     const double n = (double)(s->adam_i + 1);
     const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
-    e = adam_run(p.dtype, (int64_t)s->L.fac_elems, s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u,
+    e = adam_run(p.dtype, adam_elems(s), s->ws + s->L.A, s->ws + s->L.G, s->ws + s->L.u,
                  s->ws + s->L.v, alpha_t, p.beta1, p.beta2, p.adam_eps, p.lower, s->st);
     s->adam_i += 1;
   }
@@ -893,9 +925,10 @@ gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* 
 }
 
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out) {
-  if (!s || !A_out || !A_out[0] || !A_out[1] || !A_out[2]) return GCP_E_ARG;
+  if (!s || !A_out || !A_out[0] || !A_out[1] || (!A_out[2] && s->p.d == 3)) return GCP_E_ARG;
   hipError_t e = hipSuccess;
   for (int k = 0; k < 3 && e == hipSuccess; ++k)
+    if (A_out[k])
     e = hipMemcpyAsync(A_out[k], fac_ptr(s, s->L.A, k), (size_t)s->dims[k] * s->p.rank * s->es,
                        hipMemcpyDeviceToDevice, s->st);
   return hip_status(e);
@@ -1146,6 +1179,7 @@ gcp_status batch_check(gcp_stream* const* streams, int32_t n) {
     if (model_hist(s)) return GCP_E_UNSUPPORTED;   // batches run the stored-slice history
     if (s->p.loss > GCP_LOSS_BERNOULLI_LOGIT) return GCP_E_UNSUPPORTED;   // batch tiles: the first three losses
     if (s->p.kappa_f > 0) return GCP_E_UNSUPPORTED;  // batches keep every factor iteration
+    if (s->p.d != 3) return GCP_E_UNSUPPORTED;
     if (s->p.tau_f != streams[0]->p.tau_f) return GCP_E_ARG;
     if (s->st != streams[0]->st) return GCP_E_ARG;
   }

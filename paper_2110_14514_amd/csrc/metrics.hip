@@ -85,7 +85,20 @@ __global__ void __launch_bounds__(kMetThreads) k_cross(const T* A0, const T* A1,
   }
 }
 
+template <typename T>
+__global__ void k_add_scalar(T* p, double v) {
+  *p = (T)((double)*p + v);
+}
+
 }  // namespace
+
+hipError_t scalar_add_run(int dtype, void* p, double v, hipStream_t stream) {
+  if (dtype)
+    hipLaunchKernelGGL(k_add_scalar<double>, dim3(1), dim3(1), 0, stream, static_cast<double*>(p), v);
+  else
+    hipLaunchKernelGGL(k_add_scalar<float>, dim3(1), dim3(1), 0, stream, static_cast<float*>(p), v);
+  return hipGetLastError();
+}
 
 size_t metrics_ws_bytes() { return align_up((kMetBlocks + 1) * sizeof(double), 256) + align_up(
                                        (size_t)(3 * kMaxRank * kMaxRank + 6 * kMaxRank) * sizeof(double), 256); }

@@ -72,5 +72,7 @@ hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out,
 hipError_t cross_run(int dtype, const void* const* A, const void* const* B, const int* I, int Ra, int Rb, void* ws,
                      hipStream_t stream);
 const double* cross_results(const void* ws);
+// *p += v on the device (p: one value of the stream dtype).
+hipError_t scalar_add_run(int dtype, void* p, double v, hipStream_t stream);
 
 }  // namespace gcp

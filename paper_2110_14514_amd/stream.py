@@ -17,10 +17,12 @@ def _ptr(t: Optional[torch.Tensor]):
     return c_void_p(0 if t is None else t.data_ptr())
 
 
-def _ptr_array(ts: Sequence[torch.Tensor]):
-    arr = (c_void_p * len(ts))()
+def _ptr_array(ts: Sequence[torch.Tensor], n: int = 0):
+    """Device pointers of ts, padded with NULL to n entries (matrix slices
+    pass two factors where the C ABI takes three)."""
+    arr = (c_void_p * max(n, len(ts)))()
     for i, t in enumerate(ts):
-        arr[i] = t.data_ptr()
+        arr[i] = None if t is None else t.data_ptr()
     return arr
 
 
@@ -59,6 +61,8 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.d = len(dims)
     for k, n in enumerate(list(dims)[:3]):
         p.dims[k] = int(n)
+    if p.d == 2:
+        p.dims[2] = 1           # matrix slices: I3 = 1, fixed third factor
     p.rank = int(rank)
     p.window = int(window)
     p.loss = N.LOSS_IDS[loss]
@@ -115,7 +119,7 @@ class Stream:
         A0c = [a.contiguous() for a in A0]
         sh = s_hist.contiguous() if s_hist is not None and n_hist > 0 else None
         handle = c_void_p(0)
-        N.check(self.lib.gcp_stream_init(byref(self.params), _ptr_array(A0c), n_hist, slices,
+        N.check(self.lib.gcp_stream_init(byref(self.params), _ptr_array(A0c, 3), n_hist, slices,
                                          _ptr(sh), th, _ptr(self.workspace), nbytes,
                                          c_void_p(self.hip_stream.cuda_stream), byref(handle)),
                 "gcp_stream_init")
@@ -139,9 +143,9 @@ class Stream:
             loss, G, g_s = out
         sl = _slice(X_t)
         Ac = [a.contiguous() for a in A]
-        N.check(self.lib.gcp_loss_grad_scaled(self.handle, byref(sl), _ptr_array(Ac),
+        N.check(self.lib.gcp_loss_grad_scaled(self.handle, byref(sl), _ptr_array(Ac, 3),
                                               _ptr(s_t.contiguous()), want, _ptr(grad_scale),
-                                              _ptr(loss), _ptr_array(G), _ptr(g_s)),
+                                              _ptr(loss), _ptr_array(G, 3), _ptr(g_s)),
                 "gcp_loss_grad")
         return loss, G, g_s
 
@@ -217,7 +221,7 @@ class Stream:
 
     def factors(self) -> List[torch.Tensor]:
         out = [torch.empty(n, self.rank, dtype=self.dtype, device=self.device) for n in self.dims]
-        N.check(self.lib.gcp_get_factors(self.handle, _ptr_array(out)), "gcp_get_factors")
+        N.check(self.lib.gcp_get_factors(self.handle, _ptr_array(out, 3)), "gcp_get_factors")
         return out
 
     def info(self):

@@ -104,6 +104,15 @@ def test_temporal_sgd_defaults_and_workspace(lib):
     assert st3 == N.OK and ep - ls >= 3 * (20 + 30 + 40) * 4 * 4
 
 
+def test_matrix_slices_need_unit_third_dimension(lib):
+    from paper_2110_14514_amd import _native as N
+    p = _params(lib, d=2)
+    p.dims[2] = 40
+    assert _ws(lib, p)[0] == N.E_SHAPE
+    p.dims[2] = 1
+    assert _ws(lib, p)[0] == N.OK
+
+
 def test_workspace_monotone_in_window_and_dims(lib):
     sizes = [_ws(lib, _params(lib, window=h))[1] for h in (0, 1, 3, 10)]
     assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
