@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
@@ -310,6 +310,65 @@ def bench_c2step(args):
     return 0
 
 
+def bench_ops(args):
+    """The other calls of a time step at the C2 shape (200^3, rank 16,
+    window 10), each timed with HIP events on the stream the library uses:
+    the least-squares temporal solve (one pass over X_t plus an R x R FP64
+    solve), one factor update (gradient, ADAM step, A_old copy and the
+    window push of a 32 MB slice), and the differentiation wrapper's forward
+    + backward (two fused passes).  Algorithmic bytes: 4 B per entry of X_t
+    for the solve; the gradient's 352 MB plus the 32 MB slice push for the
+    update; twice the gradient's bytes for forward + backward."""
+    import torch
+    import gcp_inputs as gi
+    from paper_2110_14514_amd import Stream, gcp_loss
+    dims, R, H = (200, 200, 200), 16, 10
+    omega = int(np.prod(dims))
+    X_t, A, s_t, Xh, Sh = gi.device_dense_window(dims, R, H, "poisson_log", seed=1)
+    cs = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cs)
+        for _ in range(n):
+            fn()
+        e1.record(cs)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n * 1e-3
+
+    n = max(5, min(args.steps, 50))
+    g = Stream(dims, R, H, "gaussian", A, Xh, Sh, list(range(1, H + 1)))
+    t_ls = timed(lambda: g.solve_st(X_t), n)
+    del g
+    p = Stream(dims, R, H, "poisson_log", A, Xh, Sh, list(range(1, H + 1)), tau_f=1, alpha_f=1e-4)
+    t_grad = timed(lambda: p.loss_grad(X_t, A, s_t), n)
+    t_upd = timed(lambda: p.update_factors(X_t, s_t), n)
+    Al = [a.clone().requires_grad_(True) for a in A]
+    sl = s_t.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        F = gcp_loss(p, X_t, Al, sl)
+        F.backward()
+
+    t_ad = timed(fwd_bwd, n)
+    assert p.sync() == 0
+    grad_bytes = 4 * (H + 1) * omega
+    out = {"metric": "time-step calls at the C2 shape", "value": 1.0 / t_upd, "unit": "factor updates/s",
+           "n_gpus": 1, "steps": n, "warmup": 2, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "C2 shape 200x200x200, rank 16, window 10: LS solve (Gaussian), factor update "
+                                  "and autograd forward+backward (Poisson-log)"},
+           "ls_solve_ms": t_ls * 1e3, "ls_solve_GBps": 4 * omega / t_ls / 1e9,
+           "grad_ms": t_grad * 1e3,
+           "update_factors_ms": t_upd * 1e3, "update_GBps": (grad_bytes + 8 * omega) / t_upd / 1e9,
+           "update_minus_grad_ms": (t_upd - t_grad) * 1e3,
+           "autograd_fwd_bwd_ms": t_ad * 1e3, "autograd_GBps": 2 * grad_bytes / t_ad / 1e9}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_c5(args):
     """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
     rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
@@ -360,7 +419,7 @@ def main():
         return copy_probe(args.copy_probe)
     if args.workload != "c2":
         return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
-                "c2step": bench_c2step}[args.workload](args)
+                "c2step": bench_c2step, "ops": bench_ops}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

@@ -28,28 +28,48 @@ LsLayout ls_layout(int I1, int I2, int I3, int R) {
   return L;
 }
 
-// b partials: workgroup (chunk of pairs, block of 256 i3): thread i3 sums
-// x * A1[i1] * A2[i2] * A3[i3] over the chunk's pairs.
+// b partials: workgroup (chunk of 64 (i1, i2) pairs, block of 256 i3):
+// the chunk's products w = a1 * a2 are staged in LDS (zeros past R), thread
+// i3 sums x * w over the chunk and scales by a3[i3] at the end.
 template <typename T, int RT>
 __global__ void __launch_bounds__(256) k_ls_b(const T* __restrict__ X, const T* __restrict__ A1,
                                               const T* __restrict__ A2, const T* __restrict__ A3,
                                               double* __restrict__ bp, int I1, int I2, int I3, int R) {
+  __shared__ T w[kPairChunk][RT];
   __shared__ T sm[4][RT];
   const int chunk = blockIdx.x;
   const int i3 = blockIdx.y * 256 + threadIdx.x;
-  const size_t p0 = (size_t)chunk * kPairChunk;
-  const size_t npairs = (size_t)I1 * I2;
+  const int p0 = chunk * kPairChunk;
+  const int npairs = I1 * I2;                     // < 2^31 (checked at stream creation)
+  const int np = min(kPairChunk, npairs - p0);
+  for (int e = threadIdx.x; e < kPairChunk * RT; e += 256) {
+    const int q = e / RT, j = e - (e / RT) * RT;
+    T v = T(0);
+    if (q < np && j < R) {
+      const int p = p0 + q, i1 = p / I2, i2 = p - i1 * I2;
+      v = A1[(size_t)i1 * R + j] * A2[(size_t)i2 * R + j];
+    }
+    w[q][j] = v;
+  }
+  __syncthreads();
   T acc[RT];
+#pragma unroll
   for (int j = 0; j < RT; ++j) acc[j] = T(0);
   if (i3 < I3) {
-    T a3[RT];
-    for (int j = 0; j < RT; ++j) a3[j] = j < R ? A3[(size_t)i3 * R + j] : T(0);
-    for (size_t p = p0; p < p0 + kPairChunk && p < npairs; ++p) {
-      int i1 = (int)(p / I2), i2 = (int)(p - (size_t)i1 * I2);
-      T x = X[p * I3 + i3];
-      for (int j = 0; j < RT; ++j)
-        if (j < R) acc[j] += x * A1[(size_t)i1 * R + j] * A2[(size_t)i2 * R + j] * a3[j];
+    const T* xp = X + (size_t)p0 * I3 + i3;
+    for (int q0 = 0; q0 < np; q0 += 8) {
+      T x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = q0 + u < np ? xp[(size_t)(q0 + u) * I3] : T(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (q0 + u >= np) break;
+#pragma unroll
+        for (int j = 0; j < RT; ++j) acc[j] += x[u] * w[q0 + u][j];
+      }
     }
+#pragma unroll
+    for (int j = 0; j < RT; ++j) acc[j] *= j < R ? A3[(size_t)i3 * R + j] : T(0);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = 0; j < RT; ++j) {
@@ -65,6 +85,8 @@ __global__ void __launch_bounds__(256) k_ls_b(const T* __restrict__ X, const T* 
   }
 }
 
+constexpr int kGramRows = 32;   // factor rows staged in LDS per step of the Gram sums
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_ls_solve(const double* __restrict__ bp, int nparts,
                                                   const T* __restrict__ A1, const T* __restrict__ A2,
@@ -73,29 +95,60 @@ __global__ void __launch_bounds__(256) k_ls_solve(const double* __restrict__ bp,
                                                   int* status) {
   __shared__ double L[kMaxRank][kMaxRank + 1];
   __shared__ double b[kMaxRank];
+  __shared__ T st[kGramRows][kMaxRank + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
-  // b = sum of partials (fixed order)
-  for (int j = tid; j < R; j += 256) {
+  // b = sum of partials in a fixed order: thread tid = q RP + j sums parts
+  // q, q + 256/RP, ... of column j, then a fixed tree over q
+  {
+    __shared__ double red[256];
+    const int RP = R <= 8 ? 8 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+    const int groups = 256 / RP, j = tid % RP, q = tid / RP;
     double s = 0.0;
-    for (int c = 0; c < nparts; ++c) s += bp[(size_t)c * R + j];
-    b[j] = s;
-  }
-  // Gamma[r][c] = prod_k sum_i A_k[i][r] A_k[i][c]  (FP64)
-  for (int idx = tid; idx < R * R; idx += 256) {
-    int r = idx / R, c = idx % R;
-    if (c > r) continue;
-    const T* mats[3] = {A1, A2, A3};
-    const int rows[3] = {I1, I2, I3};
-    double g = 1.0;
-    for (int k = 0; k < 3; ++k) {
-      double d = 0.0;
-      for (int i = 0; i < rows[k]; ++i) d += (double)mats[k][(size_t)i * R + r] * (double)mats[k][(size_t)i * R + c];
-      g *= d;
+    if (j < R)
+      for (int c = q; c < nparts; c += groups) s += bp[(size_t)c * R + j];
+    red[tid] = s;
+    __syncthreads();
+    for (int w = groups / 2; w >= 1; w >>= 1) {
+      if (q < w) red[tid] += red[tid + w * RP];
+      __syncthreads();
     }
-    if (r == c) g += half_mu;
-    L[r][c] = g;
+    if (tid < R) b[tid] = red[tid];
+  }
+  // Gamma[r][c] = prod_k sum_i A_k[i][r] A_k[i][c] (FP64, lower triangle):
+  // thread tid owns entries tid, tid + 256, ... of the R x R square; rows of
+  // each factor pass through LDS kGramRows at a time.
+  constexpr int kMaxOwn = kMaxRank * kMaxRank / 256;
+  double g[kMaxOwn], d[kMaxOwn];
+  for (int o = 0; o < kMaxOwn; ++o) g[o] = 1.0;
+  const T* mats[3] = {A1, A2, A3};
+  const int rows[3] = {I1, I2, I3};
+  for (int k = 0; k < 3; ++k) {
+    for (int o = 0; o < kMaxOwn; ++o) d[o] = 0.0;
+    for (int i0 = 0; i0 < rows[k]; i0 += kGramRows) {
+      const int nr = min(kGramRows, rows[k] - i0);
+      __syncthreads();
+      for (int e = tid; e < nr * R; e += 256) st[e / R][e % R] = mats[k][(size_t)i0 * R + e];
+      __syncthreads();
+      for (int o = 0; o < kMaxOwn; ++o) {
+        const int idx = tid + 256 * o;
+        if (idx >= R * R) break;
+        const int r = idx / R, c = idx % R;
+        if (c > r) continue;
+        double acc = 0.0;
+        for (int i = 0; i < nr; ++i) acc += (double)st[i][r] * (double)st[i][c];
+        d[o] += acc;
+      }
+    }
+    for (int o = 0; o < kMaxOwn; ++o) g[o] *= d[o];
+  }
+  for (int o = 0; o < kMaxOwn; ++o) {
+    const int idx = tid + 256 * o;
+    if (idx >= R * R) break;
+    const int r = idx / R, c = idx % R;
+    if (c > r) continue;
+    L[r][c] = g[o] + (r == c ? half_mu : 0.0);
   }
   __syncthreads();
   // right-looking Cholesky, lower triangle in place
