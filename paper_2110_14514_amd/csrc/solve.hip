@@ -15,8 +15,12 @@ namespace {
 
 constexpr int kPairChunk = 64;
 
+constexpr int kGramRows = 64;   // factor rows per workgroup of the Gram partials
+
 struct LsLayout {
   int nchunks, ygs;
+  int gch[3];         // Gram row chunks per mode
+  size_t gram_off;    // byte offset of the Gram partials (R x R doubles per chunk)
   size_t bytes;
 };
 
@@ -24,7 +28,10 @@ LsLayout ls_layout(int I1, int I2, int I3, int R) {
   LsLayout L;
   L.nchunks = (int)(((size_t)I1 * I2 + kPairChunk - 1) / kPairChunk);
   L.ygs = (I3 + 255) / 256;
-  L.bytes = align_up((size_t)L.nchunks * L.ygs * R * sizeof(double), 256);
+  const int I[3] = {I1, I2, I3};
+  for (int k = 0; k < 3; ++k) L.gch[k] = (I[k] + kGramRows - 1) / kGramRows;
+  L.gram_off = align_up((size_t)L.nchunks * L.ygs * R * sizeof(double), 256);
+  L.bytes = L.gram_off + align_up((size_t)(L.gch[0] + L.gch[1] + L.gch[2]) * R * R * sizeof(double), 256);
   return L;
 }
 
@@ -85,18 +92,39 @@ __global__ void __launch_bounds__(256) k_ls_b(const T* __restrict__ X, const T* 
   }
 }
 
-constexpr int kGramRows = 32;   // factor rows staged in LDS per step of the Gram sums
+// Gram partials: workgroup b takes kGramRows rows of one factor (mode k,
+// row chunk c) through LDS and writes sum_i A_k[i][r] A_k[i][c] (FP64) for
+// the lower triangle; thread tid owns entries tid, tid + 256, ...
+template <typename T>
+__global__ void __launch_bounds__(256) k_ls_gram(const T* __restrict__ A1, const T* __restrict__ A2,
+                                                 const T* __restrict__ A3, int I1, int I2, int I3, int R, int c1,
+                                                 int c2, double* __restrict__ gp) {
+  __shared__ T st[kGramRows][kMaxRank + 1];
+  const int b = blockIdx.x;
+  const int k = b < c1 ? 0 : (b < c1 + c2 ? 1 : 2);
+  const int c = b - (k == 0 ? 0 : (k == 1 ? c1 : c1 + c2));
+  const T* A = k == 0 ? A1 : (k == 1 ? A2 : A3);
+  const int I = k == 0 ? I1 : (k == 1 ? I2 : I3);
+  const int i0 = c * kGramRows, nr = min(kGramRows, I - i0);
+  for (int e = threadIdx.x; e < nr * R; e += 256) st[e / R][e % R] = A[(size_t)i0 * R + e];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < R * R; idx += 256) {
+    const int r = idx / R, cc = idx % R;
+    if (cc > r) continue;
+    double acc = 0.0;
+    for (int i = 0; i < nr; ++i) acc += (double)st[i][r] * (double)st[i][cc];
+    gp[(size_t)b * R * R + idx] = acc;
+  }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_ls_solve(const double* __restrict__ bp, int nparts,
-                                                  const T* __restrict__ A1, const T* __restrict__ A2,
-                                                  const T* __restrict__ A3, int I1, int I2, int I3, int R,
-                                                  double half_mu, double lower, T* __restrict__ s_out,
-                                                  int* status) {
+                                                  const double* __restrict__ gp, int3 gch3, int R, double half_mu,
+                                                  double lower, T* __restrict__ s_out, int* status) {
   __shared__ double L[kMaxRank][kMaxRank + 1];
   __shared__ double b[kMaxRank];
-  __shared__ T st[kGramRows][kMaxRank + 1];
   __shared__ int bad;
+  const int gch[3] = {gch3.x, gch3.y, gch3.z};
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
   // b = sum of partials in a fixed order: thread tid = q RP + j sums parts
@@ -107,7 +135,16 @@ __global__ void __launch_bounds__(256) k_ls_solve(const double* __restrict__ bp,
     const int groups = 256 / RP, j = tid % RP, q = tid / RP;
     double s = 0.0;
     if (j < R)
-      for (int c = q; c < nparts; c += groups) s += bp[(size_t)c * R + j];
+      for (int c0 = q; c0 < nparts; c0 += 8 * groups) {
+        double v[8];   // eight loads in flight, added in part order
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + u * groups;
+          v[u] = c < nparts ? bp[(size_t)c * R + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
     red[tid] = s;
     __syncthreads();
     for (int w = groups / 2; w >= 1; w >>= 1) {
@@ -117,38 +154,19 @@ __global__ void __launch_bounds__(256) k_ls_solve(const double* __restrict__ bp,
     if (tid < R) b[tid] = red[tid];
   }
   // Gamma[r][c] = prod_k sum_i A_k[i][r] A_k[i][c] (FP64, lower triangle):
-  // thread tid owns entries tid, tid + 256, ... of the R x R square; rows of
-  // each factor pass through LDS kGramRows at a time.
-  constexpr int kMaxOwn = kMaxRank * kMaxRank / 256;
-  double g[kMaxOwn], d[kMaxOwn];
-  for (int o = 0; o < kMaxOwn; ++o) g[o] = 1.0;
-  const T* mats[3] = {A1, A2, A3};
-  const int rows[3] = {I1, I2, I3};
-  for (int k = 0; k < 3; ++k) {
-    for (int o = 0; o < kMaxOwn; ++o) d[o] = 0.0;
-    for (int i0 = 0; i0 < rows[k]; i0 += kGramRows) {
-      const int nr = min(kGramRows, rows[k] - i0);
-      __syncthreads();
-      for (int e = tid; e < nr * R; e += 256) st[e / R][e % R] = mats[k][(size_t)i0 * R + e];
-      __syncthreads();
-      for (int o = 0; o < kMaxOwn; ++o) {
-        const int idx = tid + 256 * o;
-        if (idx >= R * R) break;
-        const int r = idx / R, c = idx % R;
-        if (c > r) continue;
-        double acc = 0.0;
-        for (int i = 0; i < nr; ++i) acc += (double)st[i][r] * (double)st[i][c];
-        d[o] += acc;
-      }
-    }
-    for (int o = 0; o < kMaxOwn; ++o) g[o] *= d[o];
-  }
-  for (int o = 0; o < kMaxOwn; ++o) {
-    const int idx = tid + 256 * o;
-    if (idx >= R * R) break;
+  // each mode's chunk partials added in chunk order
+  for (int idx = tid; idx < R * R; idx += 256) {
     const int r = idx / R, c = idx % R;
     if (c > r) continue;
-    L[r][c] = g[o] + (r == c ? half_mu : 0.0);
+    double g = 1.0;
+    int b0 = 0;
+    for (int k = 0; k < 3; ++k) {
+      double d = 0.0;
+      for (int ch = 0; ch < gch[k]; ++ch) d += gp[(size_t)(b0 + ch) * R * R + idx];
+      b0 += gch[k];
+      g *= d;
+    }
+    L[r][c] = g + (r == c ? half_mu : 0.0);
   }
   __syncthreads();
   // right-looking Cholesky, lower triangle in place
@@ -199,11 +217,14 @@ hipError_t run_ls(int I1, int I2, int I3, int R, const void* X, const void* cons
   hipLaunchKernelGGL((k_ls_b<T, RT>), dim3(L.nchunks, L.ygs), dim3(256), 0, st, static_cast<const T*>(X),
                      static_cast<const T*>(A[0]), static_cast<const T*>(A[1]), static_cast<const T*>(A[2]), bp,
                      I1, I2, I3, R);
+  double* gp = reinterpret_cast<double*>(static_cast<char*>(scratch) + L.gram_off);
+  hipLaunchKernelGGL((k_ls_gram<T>), dim3(L.gch[0] + L.gch[1] + L.gch[2]), dim3(256), 0, st,
+                     static_cast<const T*>(A[0]), static_cast<const T*>(A[1]), static_cast<const T*>(A[2]), I1, I2,
+                     I3, R, L.gch[0], L.gch[1], gp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_ls_solve<T>), dim3(1), dim3(256), 0, st, bp, L.nchunks * L.ygs,
-                     static_cast<const T*>(A[0]), static_cast<const T*>(A[1]), static_cast<const T*>(A[2]), I1,
-                     I2, I3, R, 0.5 * mu, lower, static_cast<T*>(s_out), status);
+  hipLaunchKernelGGL((k_ls_solve<T>), dim3(1), dim3(256), 0, st, bp, L.nchunks * L.ygs, gp,
+                     make_int3(L.gch[0], L.gch[1], L.gch[2]), R, 0.5 * mu, lower, static_cast<T*>(s_out), status);
   return hipGetLastError();
 }
 
