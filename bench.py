@@ -314,7 +314,8 @@ def bench_ops(args):
     """The other calls of a time step at the C2 shape (200^3, rank 16,
     window 10), each timed with HIP events on the stream the library uses:
     the least-squares temporal solve (one pass over X_t plus an R x R FP64
-    solve), one factor update (gradient, ADAM step, A_old copy and the
+    solve), a gradient-only Gaussian call with and without the identity
+    path (Section 5: no model evaluation), one factor update (gradient, ADAM step, A_old copy and the
     window push of a 32 MB slice), and the differentiation wrapper's forward
     + backward (two fused passes).  Algorithmic bytes: 4 B per entry of X_t
     for the solve; the gradient's 352 MB plus the 32 MB slice push for the
@@ -342,7 +343,11 @@ def bench_ops(args):
     n = max(5, min(args.steps, 50))
     g = Stream(dims, R, H, "gaussian", A, Xh, Sh, list(range(1, H + 1)))
     t_ls = timed(lambda: g.solve_st(X_t), n)
+    t_gg = timed(lambda: g.loss_grad(X_t, A, s_t, want_loss=False), n)
     del g
+    gi_ = Stream(dims, R, H, "gaussian", A, Xh, Sh, list(range(1, H + 1)), gauss_identity=True)
+    t_gi = timed(lambda: gi_.loss_grad(X_t, A, s_t, want_loss=False), n)
+    del gi_
     p = Stream(dims, R, H, "poisson_log", A, Xh, Sh, list(range(1, H + 1)), tau_f=1, alpha_f=1e-4)
     t_grad = timed(lambda: p.loss_grad(X_t, A, s_t), n)
     t_upd = timed(lambda: p.update_factors(X_t, s_t), n)
@@ -361,6 +366,7 @@ def bench_ops(args):
            "config": {"workload": "C2 shape 200x200x200, rank 16, window 10: LS solve (Gaussian), factor update "
                                   "and autograd forward+backward (Poisson-log)"},
            "ls_solve_ms": t_ls * 1e3, "ls_solve_GBps": 4 * omega / t_ls / 1e9,
+           "gaussian_grad_only_ms": t_gg * 1e3, "gaussian_grad_identity_ms": t_gi * 1e3,
            "grad_ms": t_grad * 1e3,
            "update_factors_ms": t_upd * 1e3, "update_GBps": (grad_bytes + 8 * omega) / t_upd / 1e9,
            "update_minus_grad_ms": (t_upd - t_grad) * 1e3,

@@ -124,6 +124,17 @@ enum {
   GCP_FLAG_KERNEL_MFMA = 4,   /* fused path: the matrix-core kernel wherever it
                                  applies (FP32, R <= 32, window <= 63);
                                  default: chosen by rank                     */
+  GCP_FLAG_GAUSS_IDENTITY = 16, /* Gaussian dense streams: gradient-only calls
+                                 (want = GCP_WANT_GRAD, no grad_scale, the
+                                 fused path, every factor-update iteration)
+                                 skip the model: with Y = 2(M - X), Section 5
+                                 gives G_k = 2 A_k ((*_{l!=k} A_l'A_l) o S)
+                                 - 2 X_(k) Z_k diag(s) summed over the slices
+                                 (S = sum_h c_h s_h s_h'), so one pass forms
+                                 the X term and FP64 Gram matrices the rest.
+                                 The two terms cancel as the fit improves,
+                                 so the FP32 result loses relative accuracy
+                                 near a fit; objective calls are unchanged */
   GCP_FLAG_SAMPLED_ATOMIC = 8 /* COO gradient: one float atomic per draw, row
                                  and rank column instead of the row-sorted
                                  reduction (less workspace, slower; the

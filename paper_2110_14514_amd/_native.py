@@ -31,6 +31,7 @@ FLAG_PLAIN_SCRATCH = 1
 FLAG_KERNEL_VALU = 2
 FLAG_KERNEL_MFMA = 4
 FLAG_SAMPLED_ATOMIC = 8
+FLAG_GAUSS_IDENTITY = 16
 HIST_SLICES = 0
 HIST_MODEL = 1
 TSOLVE_LS = 0

@@ -20,7 +20,7 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
-      metric, total;
+      metric, ident, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -93,7 +93,10 @@ gcp_status check_params(const gcp_params* p) {
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_PLAIN_SCRATCH) && p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
   if ((p->flags & GCP_FLAG_KERNEL_VALU) && (p->flags & GCP_FLAG_KERNEL_MFMA)) return GCP_E_ARG;
-  if (p->flags & ~(GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_KERNEL_VALU | GCP_FLAG_KERNEL_MFMA | GCP_FLAG_SAMPLED_ATOMIC))
+  if (p->flags & ~(GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_KERNEL_VALU | GCP_FLAG_KERNEL_MFMA | GCP_FLAG_SAMPLED_ATOMIC |
+                   GCP_FLAG_GAUSS_IDENTITY))
+    return GCP_E_ARG;
+  if ((p->flags & GCP_FLAG_GAUSS_IDENTITY) && (p->loss != GCP_LOSS_GAUSSIAN || p->slice_kind != GCP_SLICE_DENSE))
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_SAMPLED_ATOMIC) && p->slice_kind != GCP_SLICE_COO) return GCP_E_ARG;
   if (p->hist != GCP_HIST_SLICES && p->hist != GCP_HIST_MODEL) return GCP_E_ARG;
@@ -161,6 +164,7 @@ WsLayout layout_for(const gcp_params* p) {
   L.uo = off; off += epochs ? fb : 0;
   L.vo = off; off += epochs ? fb : 0;
   L.metric = off; off += align_up(metrics_ws_bytes(), 256);
+  L.ident = off; off = align_up(off + ((p->flags & GCP_FLAG_GAUSS_IDENTITY) ? hist_ws_bytes(R) : 0), 256);
   L.total = off;
   return L;
 }
@@ -309,6 +313,32 @@ gcp_status hip_status(hipError_t e) { return e == hipSuccess ? GCP_OK : GCP_E_DE
 // matrix slices (the fixed row is the last block of the packed layout).
 int64_t adam_elems(const gcp_stream* s) {
   return (int64_t)(s->p.d == 2 ? s->L.fac_off[2] : s->L.fac_elems);
+}
+
+// Gradient-only Gaussian calls of a stream with GCP_FLAG_GAUSS_IDENTITY go
+// through the identity of Section 5: a data pass without the model, then the
+// model's part from Gram matrices.
+bool use_identity(const gcp_stream* s, int want, bool plain, const void* grad_scale) {
+  return (s->p.flags & GCP_FLAG_GAUSS_IDENTITY) && want == kWantGrad && !plain && !grad_scale;
+}
+
+hipError_t identity_terms(gcp_stream* s, const DenseCall& c) {
+  HistCall h;
+  memset(&h, 0, sizeof(h));
+  for (int k = 0; k < 3; ++k) {
+    h.I[k] = s->dims[k];
+    h.A[k] = c.A[k];
+    h.G[k] = c.G[k];
+  }
+  h.R = s->p.rank;
+  h.dtype = s->p.dtype == GCP_F64 ? 1 : 0;
+  h.nwin = c.ns - 1;
+  for (int i = 0; i + 1 < c.ns; ++i) h.c[i] = c.c[i + 1];
+  h.shist = s->ws + s->L.shist;
+  h.ws = reinterpret_cast<double*>(s->ws + s->L.ident);
+  h.status = s->status;
+  h.stream = s->st;
+  return ident_run(h, c.S[0], c.gs);
 }
 
 // Matrix slices: the kernels' factor regulariser also covers the fixed row
@@ -574,7 +604,10 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
     c.ev_end = s->ev[s->ev_used + 1];
     s->ev_used += 2;
   }
+  const bool ident = use_identity(s, c.want, plain, grad_scale);
+  if (ident) c.loss = kGaussianId;
   hipError_t e = plain ? dense_plain_run(c, s->ws + s->L.plain, s->L.plain_bytes) : dense_fused_run(c);
+  if (e == hipSuccess && ident) e = identity_terms(s, c);
   if (e == hipSuccess) e = add_model_history(s, A, c.want, c.loss_out, c.G, grad_scale);
   if (e == hipSuccess && (want & GCP_WANT_LOSS)) e = d2_fix_loss(s, c.loss_out);
   return hip_status(e);
@@ -658,7 +691,10 @@ hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t)
     c.G[k] = fac_ptr(s, s->L.G, k);
   }
   c.gs = s->ws + s->L.gs;
+  const bool ident = use_identity(s, kWantGrad, false, nullptr);
+  if (ident) c.loss = kGaussianId;
   hipError_t e = dense_fused_run(c);
+  if (e == hipSuccess && ident) e = identity_terms(s, c);
   if (e == hipSuccess) e = add_model_history(s, c.A, kWantGrad, nullptr, c.G, nullptr);
   return e;
 }

@@ -10,7 +10,10 @@ namespace gcp {
 constexpr int kMaxNs = 65;        // current slice + window of at most 64
 constexpr int kMaxRank = 64;
 
-enum Loss { kGaussian = 0, kPoissonLog = 1, kBernoulliLogit = 2, kPoissonId = 3, kBernoulliOdds = 4 };
+enum Loss { kGaussian = 0, kPoissonLog = 1, kBernoulliLogit = 2, kPoissonId = 3, kBernoulliOdds = 4,
+            // internal: the Gaussian gradient without the model (y = -2x); the
+            // model's part is added from Gram matrices
+            kGaussianId = 5 };
 // epsilon of log(m + eps) in the identity- and odds-link losses (m >= 0)
 constexpr double kLossEps = 1e-10;
 enum Want { kWantLoss = 1, kWantGrad = 2 };
@@ -54,6 +57,9 @@ struct LossFn<T, kBernoulliLogit> {
     y = sig - x;
   }
 };
+
+template <typename T>
+struct LossFn<T, kGaussianId> : LossFn<T, kGaussian> {};
 
 template <typename T>
 struct LossFn<T, kPoissonId> {
@@ -233,6 +239,8 @@ hipError_t dense_mfma_launch_gaussian(const DenseCall& c, const MfmaPlan& p, flo
                                       float* gsp, float* lossp);
 hipError_t dense_mfma_launch_poisson(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                                      float* gsp, float* lossp);
+hipError_t dense_mfma_launch_gaussian_id(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
+                                         float* G3p, float* gsp, float* lossp);
 hipError_t dense_mfma_launch_poisson_id(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                                         float* gsp, float* lossp);
 hipError_t dense_mfma_launch_bernoulli_odds(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
@@ -366,6 +374,11 @@ struct HistCall {
 };
 size_t hist_ws_bytes(int R);
 hipError_t hist_run(const HistCall& c);
+// Gaussian gradient through the identity of Section 5: after a data pass
+// with y = -2x, adds the model's part G_k += 2 A_k ((*_{l != k} A_l'A_l) o S),
+// S = s_t s_t' + sum_h c_h s_h s_h' (c.shist, c.c over c.nwin slots), and
+// g_s += 2 (*_l A_l'A_l) s_t.  Uses c.A, c.G, c.ws, c.R, c.I, c.dtype.
+hipError_t ident_run(const HistCall& c, const void* s_t, void* g_s);
 
 // Workspace bytes of the row-sorted reduction for a stream (0: not used).
 size_t sampled_sorted_bytes(int I1, int I2, int I3, int R, int window, int64_t p, int64_t q);

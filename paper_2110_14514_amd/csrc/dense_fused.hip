@@ -186,9 +186,11 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
         const T* Sh = a.S[h];
         T x = valid ? a.X[h][h == 0 ? off0 : offr] : T(0);
         T m = T(0);
+        if (LOSS != kGaussianId) {   // the identity path takes m = 0 (y = -2x)
 #pragma unroll
-        for (int j = 0; j < RT; ++j)
-          if (j < R) m += P[j] * Sh[j];
+          for (int j = 0; j < RT; ++j)
+            if (j < R) m += P[j] * Sh[j];
+        }
         T f, y;
         LossFn<T, LOSS>::eval(x, m, f, y);
         const T ch = a.c[h];
@@ -436,6 +438,7 @@ hipError_t dispatch_loss(const DenseCall& c, const Tiling& tl, const PartLayout&
     case kGaussian: return dispatch_rank<T, kGaussian>(c, tl, pl);
     case kPoissonLog: return dispatch_rank<T, kPoissonLog>(c, tl, pl);
     case kBernoulliLogit: return dispatch_rank<T, kBernoulliLogit>(c, tl, pl);
+    case kGaussianId: return dispatch_rank<T, kGaussianId>(c, tl, pl);
     case kPoissonId: return dispatch_rank<T, kPoissonId>(c, tl, pl);
     default: return dispatch_rank<T, kBernoulliOdds>(c, tl, pl);
   }

@@ -29,6 +29,7 @@ hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, 
     case kGaussian: return dense_mfma_launch_gaussian(c, p, G1p, G2p, G3p, gsp, lossp);
     case kPoissonLog: return dense_mfma_launch_poisson(c, p, G1p, G2p, G3p, gsp, lossp);
     case kBernoulliLogit: return dense_mfma_launch_bernoulli(c, p, G1p, G2p, G3p, gsp, lossp);
+    case kGaussianId: return dense_mfma_launch_gaussian_id(c, p, G1p, G2p, G3p, gsp, lossp);
     case kPoissonId: return dense_mfma_launch_poisson_id(c, p, G1p, G2p, G3p, gsp, lossp);
     default: return dense_mfma_launch_bernoulli_odds(c, p, G1p, G2p, G3p, gsp, lossp);
   }

@@ -166,7 +166,83 @@ hipError_t hist_launch(const HistCall& c) {
   return hipGetLastError();
 }
 
+// Gaussian identity: S from s_t and the window, B_k = (*_{l != k} P_l) o S,
+// and g_s += 2 (P_0 o P_1 o P_2) s_t (one workgroup).
+template <typename T>
+__global__ void __launch_bounds__(kHistThreads) id_combine(HistArgs<T> a, const T* st, T* gs) {
+  const int R = a.R;
+  const double* P = a.ws + gram_off(0, 0, R);
+  const size_t RR = (size_t)R * R;
+  for (int e = threadIdx.x; e < R * R; e += kHistThreads) {
+    const int i = e / R, j = e - (e / R) * R;
+    double sw = (double)st[i] * (double)st[j];
+    for (int h = 0; h < a.nwin; ++h) sw += a.c[h] * (double)a.shist[(size_t)h * R + i] * (double)a.shist[(size_t)h * R + j];
+    const double p0 = P[e], p1 = P[RR + e], p2 = P[2 * RR + e];
+    a.ws[b_off(0, R) + e] = sw * (p1 * p2);
+    a.ws[b_off(1, R) + e] = sw * (p0 * p2);
+    a.ws[b_off(2, R) + e] = sw * (p0 * p1);
+  }
+  for (int i = threadIdx.x; i < R; i += kHistThreads) {
+    double s = 0.0;
+    for (int j = 0; j < R; ++j) s += P[i * R + j] * P[RR + i * R + j] * P[2 * RR + i * R + j] * (double)st[j];
+    const T v = gs[i] + (T)(2.0 * s);
+    gs[i] = v;
+    if (!isfinite(v)) atomicOr(a.status, (int)kStatusNonFinite);
+  }
+}
+
+// G_k += 2 A_k B_k, one output per thread.
+template <typename T>
+__global__ void __launch_bounds__(kHistThreads) id_grad(HistArgs<T> a) {
+  const int R = a.R;
+  const int n0 = a.I[0] * R, n1 = a.I[1] * R, n2 = a.I[2] * R;
+  for (int idx = blockIdx.x * kHistThreads + threadIdx.x; idx < n0 + n1 + n2; idx += gridDim.x * kHistThreads) {
+    int k = 0, e = idx;
+    if (e >= n0) { e -= n0; k = 1; if (e >= n1) { e -= n1; k = 2; } }
+    const int r = e / R, col = e - (e / R) * R;
+    const T* Ar = a.A[k] + (size_t)r * R;
+    const double* B = a.ws + b_off(k, R);
+    double s = 0.0;
+    for (int j = 0; j < R; ++j) s += (double)Ar[j] * B[(size_t)j * R + col];
+    const T v = a.G[k][e] + (T)(2.0 * s);
+    a.G[k][e] = v;
+    if (!isfinite(v)) atomicOr(a.status, (int)kStatusNonFinite);
+  }
+}
+
+template <typename T>
+hipError_t ident_launch(const HistCall& c, const void* s_t, void* g_s) {
+  HistArgs<T> a;
+  for (int k = 0; k < 3; ++k) {
+    a.A[k] = static_cast<const T*>(c.A[k]);
+    a.Ab[k] = static_cast<const T*>(c.A[k]);
+    a.G[k] = static_cast<T*>(c.G[k]);
+    a.I[k] = c.I[k];
+  }
+  a.shist = static_cast<const T*>(c.shist);
+  a.loss = nullptr;
+  a.gscale = nullptr;
+  a.ws = c.ws;
+  a.status = c.status;
+  for (int h = 0; h < kMaxNs; ++h) a.c[h] = h < c.nwin ? c.c[h] : 0.0;
+  a.R = c.R;
+  a.nwin = c.nwin;
+  a.want = kWantGrad;
+  // Gram matrices A_k'A_k only (the first three of hist_gram's nine)
+  hipLaunchKernelGGL((hist_gram<T>), dim3(c.R, 3), dim3(kHistThreads), 0, c.stream, a);
+  hipLaunchKernelGGL((id_combine<T>), dim3(1), dim3(kHistThreads), 0, c.stream, a, static_cast<const T*>(s_t),
+                     static_cast<T*>(g_s));
+  const int total = (c.I[0] + c.I[1] + c.I[2]) * c.R;
+  hipLaunchKernelGGL((id_grad<T>), dim3((unsigned)std::min(2048, (total + kHistThreads - 1) / kHistThreads)),
+                     dim3(kHistThreads), 0, c.stream, a);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t ident_run(const HistCall& c, const void* s_t, void* g_s) {
+  return c.dtype == 1 ? ident_launch<double>(c, s_t, g_s) : ident_launch<float>(c, s_t, g_s);
+}
 
 size_t hist_ws_bytes(int R) { return (size_t)15 * R * R * sizeof(double); }
 

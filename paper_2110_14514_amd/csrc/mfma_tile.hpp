@@ -299,6 +299,9 @@ struct MLoss<kBernoulliLogit> {
   }
 };
 
+template <>
+struct MLoss<kGaussianId> : MLoss<kGaussian> {};
+
 // Identity- and odds-link losses (m >= 0): the model is used as it is.
 template <>
 struct MLoss<kPoissonId> {
@@ -561,7 +564,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
           for (int u = 0; u < NUA; ++u) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
-            if (VEC || u < nu) {
+            // the Gaussian identity path takes m = 0 here (y = -2x)
+            if (LOSS != kGaussianId && (VEC || u < nu)) {
 #pragma unroll
               for (int t = 0; t < NT; ++t) {
                 if constexpr (kWA)

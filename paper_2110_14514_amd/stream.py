@@ -51,7 +51,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
                 sampled_atomic: bool = False, hist: str = "slices", tsolve: str = "ls",
                 tau_w: int = 100, kappa_w: int = 20, alpha_w: float = 1.0,
                 tol_w: float = -math.inf, kappa_f: int = 0, tol_f: float = -math.inf,
-                p_est: int = 0, q_est: int = 0) -> N.GcpParams:
+                p_est: int = 0, q_est: int = 0, gauss_identity: bool = False) -> N.GcpParams:
     lib = N.load()
     n_p, n_q = p, q
     p = N.GcpParams()
@@ -69,7 +69,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.dtype = N.F64 if dtype == torch.float64 else N.F32
     p.flags = (N.FLAG_PLAIN_SCRATCH if plain else 0) | {
         "auto": 0, "valu": N.FLAG_KERNEL_VALU, "mfma": N.FLAG_KERNEL_MFMA}[kernel] | (
-        N.FLAG_SAMPLED_ATOMIC if sampled_atomic else 0)
+        N.FLAG_SAMPLED_ATOMIC if sampled_atomic else 0) | (N.FLAG_GAUSS_IDENTITY if gauss_identity else 0)
     p.hist = {"slices": N.HIST_SLICES, "model": N.HIST_MODEL}[hist]
     p.w, p.theta, p.lam, p.mu, p.lower = float(w), float(theta), float(lam), float(mu), float(lower)
     p.alpha_f, p.beta1, p.beta2, p.adam_eps = float(alpha_f), float(beta1), float(beta2), float(adam_eps)

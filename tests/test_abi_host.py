@@ -104,6 +104,13 @@ def test_temporal_sgd_defaults_and_workspace(lib):
     assert st3 == N.OK and ep - ls >= 3 * (20 + 30 + 40) * 4 * 4
 
 
+def test_gauss_identity_flag_only_for_dense_gaussian(lib):
+    from paper_2110_14514_amd import _native as N
+    assert _ws(lib, _params(lib, flags=N.FLAG_GAUSS_IDENTITY))[0] == N.OK
+    assert _ws(lib, _params(lib, flags=N.FLAG_GAUSS_IDENTITY, loss=1))[0] == N.E_ARG
+    assert _ws(lib, _params(lib, flags=N.FLAG_GAUSS_IDENTITY, slice_kind=1, max_nnz=10, p=4, q=4))[0] == N.E_ARG
+
+
 def test_matrix_slices_need_unit_third_dimension(lib):
     from paper_2110_14514_amd import _native as N
     p = _params(lib, d=2)
