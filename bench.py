@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
@@ -375,6 +375,41 @@ def bench_ops(args):
     return 0
 
 
+def bench_e5(args):
+    """Matrix slices at the shape of the paper's synthetic Gaussian experiment:
+    300 x 300 slices, rank 20, window 50 (Table of hyperparameters); one
+    gradient over X_t and the 50 stored slices, with each dense kernel."""
+    import torch
+    from paper_2110_14514_amd import Stream
+    dims, R, H = (300, 300), 20, 50
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    Xs = [torch.randn(dims, generator=g, device="cuda") for _ in range(H + 1)]
+    A = [(torch.rand(n, R, generator=g, device="cuda") - 0.5).contiguous() for n in dims]
+    S = torch.rand(H + 1, R, generator=g, device="cuda") + 0.5
+    res = {}
+    for kernel in ("valu", "mfma", "auto"):
+        st = Stream(dims, R, H, "gaussian", A, Xs[1:], S[1:].contiguous(), list(range(1, H + 1)), kernel=kernel)
+        out = (torch.empty(1, device="cuda"), [torch.empty(n, R, device="cuda") for n in dims],
+               torch.empty(R, device="cuda"))
+        fn = lambda: st.loss_grad(Xs[0], A, S[0], out=out)
+        for _ in range(args.warmup):
+            fn()
+        st.kernel_timing(True, args.steps)
+        sec = _time(fn, args.steps, 0, torch.cuda.synchronize)
+        ms, n = st.kernel_time()
+        st.kernel_timing(False)
+        assert st.sync() == 0
+        res[kernel] = (sec, ms / max(n, 1) / 1e3)
+        del st
+    sec, ks = res["auto"]
+    omega = 300 * 300
+    _line("E5 shape: 300x300 Gaussian matrix slices, rank 20, window 50", "grad steps/s", sec * 1e3, args.steps,
+          args.warmup, 4 * (H + 1) * omega, omega * (H + 1) * 4 * R, ks,
+          {"valu_kernel_ms": res["valu"][1] * 1e3, "mfma_kernel_ms": res["mfma"][1] * 1e3})
+    return 0
+
+
 def bench_c5(args):
     """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
     rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
@@ -425,7 +460,7 @@ def main():
         return copy_probe(args.copy_probe)
     if args.workload != "c2":
         return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
-                "c2step": bench_c2step, "ops": bench_ops}[args.workload](args)
+                "c2step": bench_c2step, "ops": bench_ops, "e5": bench_e5}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

@@ -145,13 +145,15 @@ enum {
 /* Table 1 (Section 4.2) of the paper, plus layout and sampling controls. */
 typedef struct {
   uint32_t abi_version;   /* GCP_ABI_VERSION                               */
-  int32_t d;              /* slice order: 3, or 2 for matrix slices (then
-                           * dims[2] = 1 and the third factor is a fixed
-                           * 1 x R row of ones: A0[2], A[2], G[2] and
-                           * A_out[2] may be NULL, only A^(1), A^(2) take
-                           * ADAM steps, and the objective's factor
-                           * regulariser covers those two; COO coords
-                           * keep three columns with i3 = 0; no batches)  */
+  int32_t d;              /* slice order: 3, or 2 for matrix slices: dims
+                           * (I1, I2, 1), slices I1 x I2 row-major, factors
+                           * A^(1) (I1 x R) and A^(2) (I2 x R) in entries 0
+                           * and 1 of every factor array (entry 2 unused,
+                           * may be NULL).  Internally an I1 x 1 x I2
+                           * tensor whose middle factor is a fixed row of
+                           * ones (no ADAM steps, no regulariser; requires
+                           * lower <= 1); COO coords are (i1, 0, i2).  No
+                           * batches.                                    */
   int64_t dims[GCP_MAX_D];/* I_1, I_2, I_3                                 */
   int32_t rank;           /* R, 1..GCP_MAX_RANK                            */
   int32_t window;         /* H, 0..GCP_MAX_WINDOW                          */

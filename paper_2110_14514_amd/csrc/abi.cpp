@@ -67,7 +67,8 @@ gcp_status check_params(const gcp_params* p) {
   if (!p) return GCP_E_ARG;
   if (p->abi_version != GCP_ABI_VERSION) return GCP_E_ARG;
   if (p->d != 2 && p->d != 3) return GCP_E_UNSUPPORTED;
-  if (p->d == 2 && p->dims[2] != 1) return GCP_E_SHAPE;   // matrix slices: I3 = 1
+  if (p->d == 2 && p->dims[2] != 1) return GCP_E_SHAPE;   // matrix slices: dims (I1, I2, 1)
+  if (p->d == 2 && p->lower > 1.0) return GCP_E_ARG;       // the fixed row of ones must satisfy the bound
   for (int k = 0; k < 3; ++k)
     if (p->dims[k] < 1 || p->dims[k] > (1 << 30)) return GCP_E_SHAPE;
   if ((double)p->dims[0] * p->dims[1] * p->dims[2] > 9.0e15) return GCP_E_SHAPE;
@@ -137,7 +138,7 @@ WsLayout layout_for(const gcp_params* p) {
   L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
   // stored dense slices keep each (i1, i2) row on 128-byte lines: the row
   // pitch is I3 rounded up to 32 values (the padding is never read)
-  L.rp3 = p->d == 2 ? 1 : ((size_t)I3 + 31) / 32 * 32;   // matrix slices: rows of one value
+  L.rp3 = ((size_t)I3 + 31) / 32 * 32;
   L.slot_elems = (size_t)I1 * I2 * L.rp3;
   (void)omega;
   L.ring = off;
@@ -311,8 +312,29 @@ gcp_status hip_status(hipError_t e) { return e == hipSuccess ? GCP_OK : GCP_E_DE
 
 // Factor entries that take ADAM steps: all three blocks, or the first two for
 // matrix slices (the fixed row is the last block of the packed layout).
-int64_t adam_elems(const gcp_stream* s) {
-  return (int64_t)(s->p.d == 2 ? s->L.fac_off[2] : s->L.fac_elems);
+int64_t adam_elems(const gcp_stream* s) { return (int64_t)s->L.fac_elems; }
+
+// Matrix slices are carried as I1 x 1 x I2 tensors (the same memory as the
+// I1 x I2 row-major slice, so that i2 runs along the lanes): the caller's
+// modes 0 and 1 are internal modes 0 and 2, and internal mode 1 is a fixed
+// 1 x R row of ones.  Internal mode of the caller's mode k:
+int int_mode(const gcp_stream* s, int k) { return s->p.d == 2 && k == 1 ? 2 : (s->p.d == 2 && k == 2 ? 1 : k); }
+
+// The parameters as the stream keeps them (matrix slices: dims (I1, 1, I2)).
+gcp_params internal_params(const gcp_params* p) {
+  gcp_params q = *p;
+  if (p->d == 2) {
+    q.dims[2] = p->dims[1];
+    q.dims[1] = 1;
+  }
+  return q;
+}
+
+// The fixed row takes no ADAM steps: its gradient is cleared after each
+// gradient (ADAM moves nothing with zero moments and a zero gradient).
+hipError_t d2_clear_fixed_grad(gcp_stream* s) {
+  if (s->p.d != 2) return hipSuccess;
+  return fill_run(s->p.dtype == GCP_F64, fac_ptr(s, s->L.G, 1), s->p.rank, 0.0, s->st);
 }
 
 // Gradient-only Gaussian calls of a stream with GCP_FLAG_GAUSS_IDENTITY go
@@ -420,7 +442,8 @@ gcp_status gcp_workspace_size(const gcp_params* p, size_t* bytes) {
   if (!bytes) return GCP_E_ARG;
   gcp_status st = check_params(p);
   if (st != GCP_OK) return st;
-  *bytes = layout_for(p).total;
+  const gcp_params q = internal_params(p);
+  *bytes = layout_for(&q).total;
   return GCP_OK;
 }
 
@@ -436,7 +459,8 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   const bool model = p->hist == GCP_HIST_MODEL;
   if (n_hist > 0 && (!s_hist || !t_hist || (!model && !X_hist))) return GCP_E_ARG;
   if (((uintptr_t)workspace & 255u) != 0) return GCP_E_ALIGN;
-  WsLayout L = layout_for(p);
+  const gcp_params q = internal_params(p);
+  WsLayout L = layout_for(&q);
   if (ws_bytes < L.total) return GCP_E_WORKSPACE;
   for (int h = 0; h < n_hist; ++h) {
     if (model) {
@@ -456,10 +480,10 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   }
   gcp_stream* s = new (std::nothrow) gcp_stream();
   if (!s) return GCP_E_ARG;
-  s->p = *p;
+  s->p = q;
   s->plan_target = kDefaultPlanTarget;
   s->es = p->dtype == GCP_F64 ? 8 : 4;
-  for (int k = 0; k < 3; ++k) s->dims[k] = (int)p->dims[k];
+  for (int k = 0; k < 3; ++k) s->dims[k] = (int)q.dims[k];
   s->omega = (size_t)s->dims[0] * s->dims[1] * s->dims[2];
   s->st = hip_stream;
   s->ws = static_cast<char*>(workspace);
@@ -474,12 +498,15 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   std::vector<float> ones32(p->rank, 1.f);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) {
     size_t nb = (size_t)s->dims[k] * p->rank * s->es;
-    const bool fixed = k == 2 && p->d == 2;
-    const void* src = fixed ? (s->es == 8 ? (const void*)ones64.data() : (const void*)ones32.data()) : A0[k];
+    const bool fixed = k == 1 && p->d == 2;
+    const void* src = fixed ? (s->es == 8 ? (const void*)ones64.data() : (const void*)ones32.data())
+                            : A0[p->d == 2 && k == 2 ? 1 : k];
     const hipMemcpyKind kind = fixed ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     e = hipMemcpyAsync(fac_ptr(s, L.A, k), src, nb, kind, s->st);
     if (e == hipSuccess) e = hipMemcpyAsync(fac_ptr(s, L.Aold, k), src, nb, kind, s->st);
   }
+  if (e == hipSuccess && p->d == 2)
+    e = fill_run(s->es == 8, metrics_ones(s->ws + L.metric), GCP_MAX_RANK, 1.0, s->st);
   if (e == hipSuccess && p->d == 2) e = hipStreamSynchronize(s->st);   // the host row must outlive its copies
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
@@ -545,12 +572,17 @@ gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const*
 gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void* const* A_in, const void* s_t,
                                 uint32_t want, const void* grad_scale, void* loss, void* const* G_in, void* g_s) {
   if (!s || !A_in || !A_in[0] || !A_in[1] || !s_t) return GCP_E_ARG;
-  if (!A_in[2] && s->p.d == 3) return GCP_E_ARG;
-  // matrix slices: A[2] and G[2] may be NULL (the fixed row, its gradient to scratch)
-  const void* A[3] = {A_in[0], A_in[1], A_in[2] ? A_in[2] : fac_ptr(s, s->L.A, 2)};
+  const bool d2 = s->p.d == 2;
+  if (!A_in[2] && !d2) return GCP_E_ARG;
+  // matrix slices: the caller's two factors are internal modes 0 and 2; the
+  // fixed row is the stream's own, its gradient goes to scratch
+  const void* A[3] = {A_in[0], d2 ? fac_ptr(s, s->L.A, 1) : A_in[1], d2 ? A_in[1] : A_in[2]};
   void* Gv[3] = {nullptr, nullptr, nullptr};
-  if (G_in)
-    for (int k = 0; k < 3; ++k) Gv[k] = G_in[k] ? G_in[k] : (k == 2 && s->p.d == 2 ? fac_ptr(s, s->L.G, 2) : nullptr);
+  if (G_in) {
+    Gv[0] = G_in[0];
+    Gv[1] = d2 ? fac_ptr(s, s->L.G, 1) : G_in[1];
+    Gv[2] = d2 ? G_in[1] : G_in[2];
+  }
   void* const* G = G_in ? Gv : nullptr;
   if (want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD | GCP_IMPL_PLAIN)) return GCP_E_ARG;
   if (!(want & (GCP_WANT_LOSS | GCP_WANT_GRAD))) return GCP_E_ARG;
@@ -696,6 +728,7 @@ hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t)
   hipError_t e = dense_fused_run(c);
   if (e == hipSuccess && ident) e = identity_terms(s, c);
   if (e == hipSuccess) e = add_model_history(s, c.A, kWantGrad, nullptr, c.G, nullptr);
+  if (e == hipSuccess) e = d2_clear_fixed_grad(s);
   return e;
 }
 
@@ -727,6 +760,7 @@ hipError_t coo_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs);
   hipError_t e = sampled_run(c);
   if (e == hipSuccess) e = add_model_history(s, A, kWantGrad, nullptr, G, nullptr);
+  if (e == hipSuccess) e = d2_clear_fixed_grad(s);
   return e;
 }
 
@@ -800,11 +834,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
   hipError_t e = coo ? build_current_table(s, X_t) : hipSuccess;
   for (int it = 0; it < (p.kappa_f > 0 ? 0 : p.tau_f) && e == hipSuccess; ++it) {
     if (coo) {
-      const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
-      void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
-      SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs);
-      e = sampled_run(c);
-      if (e == hipSuccess) e = add_model_history(s, A, kWantGrad, nullptr, G, nullptr);
+      e = coo_grad_step(s, X_t, s_t);
       if (e != hipSuccess) break;
       const double n = (double)(s->adam_i + 1);
       const double alpha_t = p.alpha_f * sqrt(1.0 - pow(p.beta2, n)) / (1.0 - pow(p.beta1, n));
@@ -892,12 +922,14 @@ gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, do
 
 gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* B, const void* w_b, int32_t rank_b,
                              double* score) {
-  if (!s || !w_a || !B || !B[0] || !B[1] || !B[2] || !w_b || !score) return GCP_E_ARG;
+  if (!s || !w_a || !B || !B[0] || !B[1] || (!B[2] && s->p.d == 3) || !w_b || !score) return GCP_E_ARG;
   if (rank_b < 1 || rank_b > GCP_MAX_RANK) return GCP_E_ARG;
   const int Ra = s->p.rank, Rb = rank_b;
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   const int dt = s->p.dtype == GCP_F64;
-  hipError_t e = cross_run(dt, A, B, s->dims, Ra, Rb, s->ws + s->L.metric, s->st);
+  // matrix slices: the reference's two factors go to internal modes 0 and 2
+  const void* Bi[3] = {B[0], s->p.d == 2 ? metrics_ones(s->ws + s->L.metric) : B[1], s->p.d == 2 ? B[1] : B[2]};
+  hipError_t e = cross_run(dt, A, Bi, s->dims, Ra, Rb, s->ws + s->L.metric, s->st);
   std::vector<double> h((size_t)3 * Ra * Rb + 3 * Ra + 3 * Rb);
   std::vector<double> wa(Ra), wb(Rb);
   if (e == hipSuccess)
@@ -963,16 +995,17 @@ gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* 
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out) {
   if (!s || !A_out || !A_out[0] || !A_out[1] || (!A_out[2] && s->p.d == 3)) return GCP_E_ARG;
   hipError_t e = hipSuccess;
-  for (int k = 0; k < 3 && e == hipSuccess; ++k)
-    if (A_out[k])
-    e = hipMemcpyAsync(A_out[k], fac_ptr(s, s->L.A, k), (size_t)s->dims[k] * s->p.rank * s->es,
+  for (int k = 0; k < (s->p.d == 2 ? 2 : 3) && e == hipSuccess; ++k) {
+    const int ki = int_mode(s, k);
+    e = hipMemcpyAsync(A_out[k], fac_ptr(s, s->L.A, ki), (size_t)s->dims[ki] * s->p.rank * s->es,
                        hipMemcpyDeviceToDevice, s->st);
+  }
   return hip_status(e);
 }
 
 gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr) {
   if (!s || !ptr || k < 0 || k > 2) return GCP_E_ARG;
-  *ptr = fac_ptr(s, s->L.A, k);
+  *ptr = fac_ptr(s, s->L.A, int_mode(s, k));
   return GCP_OK;
 }
 

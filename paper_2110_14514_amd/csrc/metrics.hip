@@ -90,7 +90,20 @@ __global__ void k_add_scalar(T* p, double v) {
   *p = (T)((double)*p + v);
 }
 
+template <typename T>
+__global__ void k_fill(T* p, int n, T v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t fill_run(int dtype, void* p, int n, double v, hipStream_t stream) {
+  if (dtype)
+    hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(256), 0, stream, static_cast<double*>(p), n, v);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(1), dim3(256), 0, stream, static_cast<float*>(p), n, (float)v);
+  return hipGetLastError();
+}
 
 hipError_t scalar_add_run(int dtype, void* p, double v, hipStream_t stream) {
   if (dtype)
@@ -100,8 +113,15 @@ hipError_t scalar_add_run(int dtype, void* p, double v, hipStream_t stream) {
   return hipGetLastError();
 }
 
-size_t metrics_ws_bytes() { return align_up((kMetBlocks + 1) * sizeof(double), 256) + align_up(
-                                       (size_t)(3 * kMaxRank * kMaxRank + 6 * kMaxRank) * sizeof(double), 256); }
+size_t metrics_ws_bytes() {
+  return align_up((kMetBlocks + 1) * sizeof(double), 256) +
+         align_up((size_t)(3 * kMaxRank * kMaxRank + 6 * kMaxRank) * sizeof(double), 256) +
+         kMaxRank * sizeof(double);   // a row of ones (matrix slices' fixed mode of a reference K-tensor)
+}
+
+void* metrics_ones(void* ws) {
+  return static_cast<char*>(ws) + metrics_ws_bytes() - kMaxRank * sizeof(double);
+}
 
 hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out, hipStream_t stream) {
   double* part = static_cast<double*>(ws);

@@ -72,6 +72,10 @@ hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out,
 hipError_t cross_run(int dtype, const void* const* A, const void* const* B, const int* I, int Ra, int Rb, void* ws,
                      hipStream_t stream);
 const double* cross_results(const void* ws);
+// p[0..n) = v (at most 256-thread single-workgroup fill; small n).
+hipError_t fill_run(int dtype, void* p, int n, double v, hipStream_t stream);
+// kMaxRank values inside the metrics workspace reserved for a row of ones.
+void* metrics_ones(void* ws);
 // *p += v on the device (p: one value of the stream dtype).
 hipError_t scalar_add_run(int dtype, void* p, double v, hipStream_t stream);
 

@@ -203,7 +203,7 @@ class Stream:
         reference K-tensor (B, w_b)."""
         B = [b.contiguous() for b in B]
         out = c_double(0.0)
-        N.check(self.lib.gcp_ktensor_score(self.handle, _ptr(w_a.contiguous()), _ptr_array(B),
+        N.check(self.lib.gcp_ktensor_score(self.handle, _ptr(w_a.contiguous()), _ptr_array(B, 3),
                                            _ptr(w_b.contiguous()), int(B[0].shape[1]), byref(out)),
                 "gcp_ktensor_score")
         return out.value

@@ -98,29 +98,49 @@ def test_stream_steps_with_both_sgd_solvers(loss):
 
 
 def test_sampled_matrix_slices_match_oracle():
-    """COO matrix slices (coords keep three columns, i3 = 0): the sampled
-    objective and gradients of the two free factors."""
+    """COO matrix slices (coords (i1, 0, i2): the stream's I1 x 1 x I2
+    layout): the sampled objective and gradients of the two free factors."""
     import torch
     from paper_2110_14514_amd import Stream
     print("case: d2 sampled", flush=True)
-    prob = gi.sparse_problem(dims=(60, 50, 1), rank=6, window=2, nnz=600, p=800, q=800, seed=3, loss="poisson_log")
+    prob = gi.sparse_problem(dims=(60, 1, 50), rank=6, window=2, nnz=600, p=800, q=800, seed=3, loss="poisson_log")
     R = 6
-    prob.A = [a.astype(np.float32).astype(np.float64) for a in prob.A[:2]] + [np.ones((1, R))]
+    prob.A = [prob.A[0].astype(np.float32).astype(np.float64), np.ones((1, R)),
+              prob.A[2].astype(np.float32).astype(np.float64)]
     prob.s_t = prob.s_t.astype(np.float32).astype(np.float64)
     prob.s_hist = prob.s_hist.astype(np.float32).astype(np.float64)
     for sl in [prob.X_t] + list(prob.X_hist):
         sl.vals = sl.vals.astype(np.float32).astype(np.float64)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     C = lambda sl: (torch.from_numpy(np.ascontiguousarray(sl.coords, dtype=np.int32)).cuda(), T(sl.vals))
-    st = Stream((60, 50), R, 2, "poisson_log", [T(a) for a in prob.A[:2]], [C(x) for x in prob.X_hist],
+    st = Stream((60, 50), R, 2, "poisson_log", [T(prob.A[0]), T(prob.A[2])], [C(x) for x in prob.X_hist],
                 T(prob.s_hist), list(prob.t_hist), w=prob.w, theta=prob.theta, lam=prob.lam, mu=prob.mu,
                 seed=prob.seed, slice_kind="coo", max_nnz=600, p=800, q=800)
-    loss_v, G, gs = st.loss_grad(C(prob.X_t), [T(a) for a in prob.A[:2]], T(prob.s_t))
+    loss_v, G, gs = st.loss_grad(C(prob.X_t), [T(prob.A[0]), T(prob.A[2])], T(prob.s_t))
     torch.cuda.synchronize()
     assert st.sync() == 0
     F, Gr, gsr = osm.sampled_loss_grad(prob, call=0)
     F -= 0.5 * prob.lam * R          # the fixed row is not regularised
     assert loss_err(loss_v.item(), F, abs(F)) <= TOL
-    for k in range(2):
-        assert rel_err(G[k].double().cpu().numpy(), Gr[k]) <= TOL
+    for k, ko in ((0, 0), (1, 2)):
+        assert rel_err(G[k].double().cpu().numpy(), Gr[ko]) <= TOL
     assert rel_err(gs.double().cpu().numpy(), gsr) <= TOL
+
+
+def test_matrix_slice_metrics_and_score():
+    """Slice loss and K-tensor score take the caller's two factors."""
+    import torch
+    from oracle import metrics as om
+    print("case: d2 metrics", flush=True)
+    g = np.random.default_rng(21)
+    dims, R = (40, 30), 5
+    A = [g.uniform(-0.6, 0.6, (n, R)) for n in dims]
+    X = g.normal(size=dims)
+    s = g.uniform(0.5, 1.5, R)
+    st, T = _stream("gaussian", dims, R, A, [], np.zeros((0, R)), torch.float64)
+    f, q = st.slice_loss(T(X), T(s))
+    M = A[0] @ np.diag(s) @ A[1].T
+    assert f == pytest.approx(float(np.sum((X - M) ** 2)), rel=1e-12) and q == pytest.approx(float(np.sum(X * X)))
+    B = [a[:, ::-1] * 2.0 for a in A]
+    score = st.ktensor_score(T(s), [T(b) for b in B], T(s[::-1] / 4.0))
+    assert score == pytest.approx(om.ktensor_score(A, s, B, s[::-1] / 4.0), rel=1e-12)
