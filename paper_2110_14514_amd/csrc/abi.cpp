@@ -539,7 +539,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
 
 // The model-difference history term for factors A (previous step's factors:
 // the stream's A_old), added to *loss and G after the data term.
-hipError_t add_model_history(gcp_stream* s, const void* const* A, int want, void* loss, void* const* G,
+static hipError_t add_model_history(gcp_stream* s, const void* const* A, int want, void* loss, void* const* G,
                              const void* grad_scale) {
   if (!model_hist(s) || s->nwin == 0) return hipSuccess;
   HistCall h;
@@ -647,7 +647,7 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
 
 // Algorithm 3 on a COO slice: sampled weight gradients over X_t alone (a new
 // call number each), Algorithm 5's estimates over draws fixed for the solve.
-hipError_t coo_weight_sgd(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
+static hipError_t coo_weight_sgd(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
   void* gs = s->ws + s->L.gs;
@@ -712,7 +712,7 @@ namespace {
 
 // One full dense gradient of the stream's objective at its current factors
 // into the gradient scratch (data term, window, history, regularisation).
-hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+static hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   DenseCall c = base_call(s);
   c.want = kWantGrad;
   c.X[0] = X_t->vals;
@@ -733,7 +733,7 @@ hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t)
 }
 
 // The objective Algorithm 4 compares (no mu/2 ||s_t||^2 term) into `loss`.
-hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, void* loss) {
+static hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, void* loss) {
   DenseCall c = base_call(s);
   c.want = kWantLoss;
   c.mu = 0.0;
@@ -754,7 +754,7 @@ hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t,
 
 // One sampled gradient of a COO stream's objective into the gradient scratch
 // (a new call number).
-hipError_t coo_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+static hipError_t coo_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
   SampledCall c = sampled_call(s, X_t, A, s_t, kWantGrad, s->ws + s->L.loss, G, s->ws + s->L.gs);
@@ -767,7 +767,7 @@ hipError_t coo_grad_step(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
 // Algorithm 5's estimate for the factor solver of time step t: p_est and
 // q_est draws per slice under a call number fixed for the solve, exact
 // history and factor regulariser, no weight regulariser.
-hipError_t coo_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, void* loss) {
+static hipError_t coo_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, void* loss) {
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   void* G[3] = {fac_ptr(s, s->L.G, 0), fac_ptr(s, s->L.G, 1), fac_ptr(s, s->L.G, 2)};
   SampledCall c = sampled_call(s, X_t, A, s_t, kWantLoss, loss, G, s->ws + s->L.gs,
@@ -782,7 +782,7 @@ hipError_t coo_objective(gcp_stream* s, const gcp_slice* X_t, const void* s_t, v
 }
 
 // Algorithm 4's epochs with every decision on the device.
-hipError_t factor_epochs(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
+static hipError_t factor_epochs(gcp_stream* s, const gcp_slice* X_t, const void* s_t) {
   const gcp_params& p = s->p;
   const bool coo = p.slice_kind == GCP_SLICE_COO;
   FacState* st = reinterpret_cast<FacState*>(s->ws + s->L.fac);

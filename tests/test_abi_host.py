@@ -32,6 +32,21 @@ def test_every_declared_symbol_is_exported(lib):
         assert n in N.SIGNATURES, f"binding lacks {n}"
 
 
+def test_only_declared_c_symbols_are_exported(lib):
+    """The library's unmangled exports are exactly the header's calls:
+    internal helpers stay internal."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    from paper_2110_14514_amd import _native as N
+    out = subprocess.run([nm, "-D", "--defined-only", N.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[2] for ln in out.splitlines()
+                if len(ln.split()) == 3 and ln.split()[1] == "T" and not ln.split()[2].startswith("_Z")}
+    assert exported == set(_declared_calls())
+
+
 def test_params_struct_layout_matches_header(lib):
     from paper_2110_14514_amd import _native as N
     p = N.GcpParams()
