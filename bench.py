@@ -112,7 +112,13 @@ def _time(fn, steps, warmup, sync):
     return (time.perf_counter() - t0) / steps
 
 
-def _line(workload, value_unit, ms, steps, warmup, alg_bytes, alg_flops, kern_s, extra):
+# FP32 vector-ALU peak without packed FP32 instructions (which this build
+# keeps out of every kernel): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz.
+VALU_FP32_PEAK_TFLOPS = 78.6
+
+
+def _line(workload, value_unit, ms, steps, warmup, alg_bytes, alg_flops, kern_s, extra, bound="hbm"):
     ach = alg_bytes / kern_s / 1e9
     out = {"metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
            "value": 1e3 / ms, "unit": value_unit, "n_gpus": 1, "ms_per_step": ms, "steps": steps,
@@ -123,6 +129,10 @@ def _line(workload, value_unit, ms, steps, warmup, alg_bytes, alg_flops, kern_s,
                         "alg_bytes_per_launch": alg_bytes,
                         "fp32_tflops": alg_flops / kern_s / 1e12,
                         "fp32_frac": alg_flops / kern_s / 1e12 / FP32_PEAK_TFLOPS}}
+    if bound == "alu":
+        tf = alg_flops / kern_s / 1e12
+        out["roofline"].update({"bound": "alu", "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": tf / VALU_FP32_PEAK_TFLOPS, "hbm_GBps": ach})
     out.update(extra)
     print(json.dumps(out), flush=True)
 
@@ -263,7 +273,7 @@ def bench_c2w(args):
     _line("C2 shape temporal-weight solve (Algorithm 3): 200x200x200 Poisson-count slice, rank 16, "
           "100 ADAM steps x 20 epochs", "weight solves/s", sec * 1e3, args.steps, args.warmup,
           omega * 4, omega * (4 * R + 8), per_pass,
-          {"passes_per_solve": passes, "solve_F": info["F"], "rolled_epochs": sum(info["rolled"])})
+          {"passes_per_solve": passes, "solve_F": info["F"], "rolled_epochs": sum(info["rolled"])}, bound="alu")
     return 0
 
 
