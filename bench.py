@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5", "e6",
+                                                      "e7"],
                     help="c2 (default) is the configuration the metric is quoted on; the others "
                          "print their own line")
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
@@ -325,7 +326,9 @@ def bench_ops(args):
     window 10), each timed with HIP events on the stream the library uses:
     the least-squares temporal solve (one pass over X_t plus an R x R FP64
     solve), a gradient-only Gaussian call with and without the identity
-    path (Section 5: no model evaluation), one factor update (gradient, ADAM step, A_old copy and the
+    path (Section 5: no model evaluation), the loss and gradient under the
+    paper's two identity-link losses (Poisson identity, Bernoulli odds), one
+    factor update (gradient, ADAM step, A_old copy and the
     window push of a 32 MB slice), and the differentiation wrapper's forward
     + backward (two fused passes).  Algorithmic bytes: 4 B per entry of X_t
     for the solve; the gradient's 352 MB plus the 32 MB slice push for the
@@ -358,6 +361,18 @@ def bench_ops(args):
     gi_ = Stream(dims, R, H, "gaussian", A, Xh, Sh, list(range(1, H + 1)), gauss_identity=True)
     t_gi = timed(lambda: gi_.loss_grad(X_t, A, s_t, want_loss=False), n)
     del gi_
+    # The paper's identity-link losses need a nonnegative model: the same
+    # factors in absolute value, the count data as is, its support as 0/1 data.
+    Ap = [a.abs().contiguous() for a in A]
+    q = Stream(dims, R, H, "poisson_id", Ap, Xh, Sh, list(range(1, H + 1)))
+    t_pid = timed(lambda: q.loss_grad(X_t, Ap, s_t), n)
+    assert q.sync() == 0
+    del q
+    Xb, Xhb = (X_t > 0).float(), [(x > 0).float() for x in Xh]
+    q = Stream(dims, R, H, "bernoulli_odds", Ap, Xhb, Sh, list(range(1, H + 1)))
+    t_bod = timed(lambda: q.loss_grad(Xb, Ap, s_t), n)
+    assert q.sync() == 0
+    del q, Xb, Xhb
     p = Stream(dims, R, H, "poisson_log", A, Xh, Sh, list(range(1, H + 1)), tau_f=1, alpha_f=1e-4)
     t_grad = timed(lambda: p.loss_grad(X_t, A, s_t), n)
     t_upd = timed(lambda: p.update_factors(X_t, s_t), n)
@@ -377,7 +392,8 @@ def bench_ops(args):
                                   "and autograd forward+backward (Poisson-log)"},
            "ls_solve_ms": t_ls * 1e3, "ls_solve_GBps": 4 * omega / t_ls / 1e9,
            "gaussian_grad_only_ms": t_gg * 1e3, "gaussian_grad_identity_ms": t_gi * 1e3,
-           "grad_ms": t_grad * 1e3,
+           "grad_ms": t_grad * 1e3, "grad_poisson_identity_ms": t_pid * 1e3,
+           "grad_bernoulli_odds_ms": t_bod * 1e3,
            "update_factors_ms": t_upd * 1e3, "update_GBps": (grad_bytes + 8 * omega) / t_upd / 1e9,
            "update_minus_grad_ms": (t_upd - t_grad) * 1e3,
            "autograd_fwd_bwd_ms": t_ad * 1e3, "autograd_GBps": 2 * grad_bytes / t_ad / 1e9}
@@ -422,12 +438,22 @@ def bench_e5(args):
 
 def bench_c5(args):
     """C5: sampled-sparse path, 2000x2000x500 COO slices (2M nonzeros),
-    rank 32, window 8, p = q = 2M draws per slice, Poisson-log."""
+    rank 32, window 8, p = q = 2M draws per slice, Poisson-log.  With
+    ``--workload e6`` / ``e7`` the same call at the paper's count-data shape:
+    263x263x24 slices at 3.8% density, rank 50, window 30, 10k + 10k (e6) or
+    50k + 50k (e7) draws per slice."""
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream
-    print("bench: generating C5", file=sys.stderr, flush=True)
-    prob = gi.sparse_problem()
+    print("bench: generating", args.workload, file=sys.stderr, flush=True)
+    if args.workload == "c5":
+        prob = gi.sparse_problem()
+        label = "C5 sampled COO slices 2000x2000x500, 2M nonzeros, rank 32, window 8, p=q=2M, Poisson-log"
+    else:
+        pq = 10000 if args.workload == "e6" else 50000
+        prob = gi.sparse_problem(dims=(263, 263, 24), rank=50, window=30, nnz=63000, p=pq, q=pq, seed=6,
+                                 loss="poisson_log")
+        label = f"sampled COO slices 263x263x24 at 3.8%, rank 50, window 30, p=q={pq}, Poisson-log"
     T = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
     coo = lambda sl: (T(sl.coords, torch.int32), T(sl.vals))
     R, H = prob.rank, len(prob.X_hist)
@@ -452,8 +478,7 @@ def bench_c5(args):
     # algorithmic bytes: a nonzero draw reads its coordinates and value (16 B);
     # a zero draw is a generated tuple plus one membership probe (8 B)
     alg = (H + 1) * (prob.p * 16 + prob.q * 8)
-    _line("C5 sampled COO slices 2000x2000x500, 2M nonzeros, rank 32, window 8, p=q=2M, "
-          "Poisson-log", "grad steps/s", sec * 1e3, args.steps, args.warmup, alg,
+    _line(label, "grad steps/s", sec * 1e3, args.steps, args.warmup, alg,
           draws * 16 * R, ms / max(n, 1) / 1e3,
           {"draws_per_step": draws, "draws_per_s": draws / (ms / max(n, 1) / 1e3),
            "reduction": "atomic" if args.sampled_atomic else "row-sorted"})
@@ -470,7 +495,8 @@ def main():
         return copy_probe(args.copy_probe)
     if args.workload != "c2":
         return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
-                "c2step": bench_c2step, "ops": bench_ops, "e5": bench_e5}[args.workload](args)
+                "c2step": bench_c2step, "ops": bench_ops, "e5": bench_e5, "e6": bench_c5,
+                "e7": bench_c5}[args.workload](args)
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream

@@ -232,7 +232,7 @@ __device__ __forceinline__ void form_draws(const SArgs& a, int h, int64_t first,
 }
 
 
-template <int LOSS, int SEG, bool REC>
+template <int LOSS, int SEG, int CPL, bool REC>
 __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t gwave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -249,16 +249,23 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
   float x[kNB], wgt[kNB];
   form_draws<kNB>(a, h, first, lane, i1, i2, i3, x, wgt);
 
-  // phase 2: SEG lanes per draw, lane = rank column
+  // phase 2: SEG lanes per draw; lane j holds rank columns j + SEG c, c < CPL
   constexpr int PER = 64 / SEG;
   const int j = lane % SEG;
   const int sub = lane / SEG;
   const float ch = a.c[h];
-  const float sj = j < R ? a.S[h][j] : 0.f;
+  float sj[CPL], gsl[CPL];
+  int jc[CPL];
+  bool jv[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    jv[cc] = j + SEG * cc < R;
+    jc[cc] = jv[cc] ? j + SEG * cc : 0;
+    sj[cc] = jv[cc] ? a.S[h][jc[cc]] : 0.f;
+    gsl[cc] = 0.f;
+  }
   const bool cur = h == 0;
-  float gsl = 0.f;
   Kahan<float> lacc;
-  const int jc = j < R ? j : 0;
 #pragma unroll
   for (int bb = 0; bb < kNB; ++bb) {
     const int64_t fb = first + 64 * bb;
@@ -270,7 +277,7 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
     constexpr int U = 4;
     for (int base = 0; base < nd; base += PER * U) {
       int b1[U], b2[U], b3[U];
-      float bx[U], bw[U], r1[U], r2[U], r3[U];
+      float bx[U], bw[U], r1[U][CPL], r2[U][CPL], r3[U][CPL];
       bool live[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -281,19 +288,24 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
         b3[u] = __shfl(i3[bb], sl);
         bx[u] = __shfl(x[bb], sl);
         bw[u] = __shfl(wgt[bb], sl);
-        live[u] = src < nd && j < R;
+        live[u] = src < nd;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        r1[u] = a.A1[(size_t)b1[u] * R + jc];
-        r2[u] = a.A2[(size_t)b2[u] * R + jc];
-        r3[u] = a.A3[(size_t)b3[u] * R + jc];
-      }
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          r1[u][cc] = a.A1[(size_t)b1[u] * R + jc[cc]];
+          r2[u][cc] = a.A2[(size_t)b2[u] * R + jc[cc]];
+          r3[u][cc] = a.A3[(size_t)b3[u] * R + jc[cc]];
+        }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int src = base + PER * u + sub;
         const float lm = live[u] ? 1.f : 0.f;
-        float m = sj * r1[u] * r2[u] * r3[u] * lm;
+        float m = 0.f;
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) m += sj[cc] * r1[u][cc] * r2[u][cc] * r3[u][cc];
+        m *= lm;
         for (int o = SEG / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o);
         float f, y;
         LossFn<float, LOSS>::eval(bx[u], m, f, y);
@@ -309,22 +321,33 @@ __global__ void __launch_bounds__(256) sampled_kernel(SArgs a) {
             rr.y = w != 0.f ? yt : 0.f;
             a.rec[(gwave * kNB + bb) * 64 + src] = rr;
           }
-          if (live[u] && w != 0.f && (a.want & kWantGrad) && cur) gsl += yt * r1[u] * r2[u] * r3[u];
+          if (live[u] && w != 0.f && (a.want & kWantGrad) && cur)
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) gsl[cc] += yt * r1[u][cc] * r2[u][cc] * r3[u][cc];
         } else {
           if (live[u] && w != 0.f && (a.want & kWantGrad)) {
-            const float ys = yt * sj;
-            unsafeAtomicAdd(&a.G1[(size_t)b1[u] * R + j], ys * r2[u] * r3[u]);
-            unsafeAtomicAdd(&a.G2[(size_t)b2[u] * R + j], ys * r1[u] * r3[u]);
-            unsafeAtomicAdd(&a.G3[(size_t)b3[u] * R + j], ys * r1[u] * r2[u]);
-            if (cur) gsl += yt * r1[u] * r2[u] * r3[u];
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) {
+              if (!jv[cc]) continue;
+              const int jj = jc[cc];
+              const float ys = yt * sj[cc];
+              unsafeAtomicAdd(&a.G1[(size_t)b1[u] * R + jj], ys * r2[u][cc] * r3[u][cc]);
+              unsafeAtomicAdd(&a.G2[(size_t)b2[u] * R + jj], ys * r1[u][cc] * r3[u][cc]);
+              unsafeAtomicAdd(&a.G3[(size_t)b3[u] * R + jj], ys * r1[u][cc] * r2[u][cc]);
+              if (cur) gsl[cc] += yt * r1[u][cc] * r2[u][cc] * r3[u][cc];
+            }
           }
         }
       }
     }
   }
   if (cur && (a.want & kWantGrad)) {
-    for (int o = SEG; o < 64; o <<= 1) gsl += __shfl_xor(gsl, o);
-    if (lane < SEG && j < R) unsafeAtomicAdd(&a.gs[j], gsl);
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      float g = gsl[cc];
+      for (int o = SEG; o < 64; o <<= 1) g += __shfl_xor(g, o);
+      if (lane < SEG && jv[cc]) unsafeAtomicAdd(&a.gs[jc[cc]], g);
+    }
   }
   if (a.want & kWantLoss) {
     float l = lacc.s;
@@ -358,11 +381,20 @@ __global__ void __launch_bounds__(256) sampled_dump(SArgs a, int32_t* __restrict
 }
 
 // Row-sorted reduction.  The count and scatter steps take the draw slots in
-// chunks of kSortChunk per workgroup and keep a histogram of the chunk's rows
-// of all three modes in LDS (I1 + I2 + I3 <= kSortBins), so that the device
-// sees one atomic per (chunk, row) instead of one per draw.
+// chunks of at most kSortChunk per workgroup and keep a histogram of the
+// chunk's rows of all three modes in LDS (I1 + I2 + I3 <= kSortBins), so that
+// the device sees one atomic per (chunk, row) instead of one per draw.  Small
+// draw counts take smaller chunks (down to 1024 slots) so that at least
+// kSortMinChunks workgroups run.
 constexpr int kSortBins = 12288;
 constexpr int kSortChunk = 65536;
+constexpr int kSortMinChunks = 512;
+
+int64_t sort_chunk(int64_t nslots) {
+  const int64_t want = (nslots + kSortMinChunks - 1) / kSortMinChunks;
+  const int64_t c = (want + 1023) / 1024 * 1024;
+  return std::min<int64_t>(kSortChunk, std::max<int64_t>(1024, c));
+}
 
 __global__ void __launch_bounds__(256) sorted_zero(int* __restrict__ cnt, int n) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) cnt[i] = 0;
@@ -376,6 +408,7 @@ struct CountArgs {
   int64_t slots;        // draw slots per slice (a multiple of 64 kNB)
   int64_t total;        // draws per slice
   int64_t nslots;       // ns * slots
+  int64_t chunk;        // slots per workgroup (sort_chunk)
   int I1, I2, I3;
 };
 
@@ -400,8 +433,8 @@ __global__ void __launch_bounds__(1024) sorted_count(CountArgs a) {
   const int nb = a.I1 + a.I2 + a.I3;
   for (int i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
   __syncthreads();
-  const int64_t g0 = (int64_t)blockIdx.x * kSortChunk;
-  chunk_histogram(a, hist, g0, min(g0 + (int64_t)kSortChunk, a.nslots));
+  const int64_t g0 = (int64_t)blockIdx.x * a.chunk;
+  chunk_histogram(a, hist, g0, min(g0 + a.chunk, a.nslots));
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += 1024)
     if (hist[i]) atomicAdd(&a.cnt[i], hist[i]);
@@ -415,8 +448,8 @@ __global__ void __launch_bounds__(1024) sorted_scatter(CountArgs a) {
   const int nb = a.I1 + a.I2 + a.I3;
   for (int i = threadIdx.x; i < nb; i += 1024) hist[i] = 0;
   __syncthreads();
-  const int64_t g0 = (int64_t)blockIdx.x * kSortChunk;
-  const int64_t g1 = min(g0 + (int64_t)kSortChunk, a.nslots);
+  const int64_t g0 = (int64_t)blockIdx.x * a.chunk;
+  const int64_t g1 = min(g0 + a.chunk, a.nslots);
   chunk_histogram(a, hist, g0, g1);
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += 1024) {
@@ -485,28 +518,45 @@ __global__ void __launch_bounds__(1024) sorted_scan(ScanArgs a) {
   for (int idx = t; idx < a.ns * a.R; idx += 1024) a.Sall[idx] = a.S[idx / a.R][idx % a.R];
 }
 
-// Step 5, one launch per mode: a group of SEG lanes (lane = rank column)
-// walks a run of kRun consecutive records of the mode's list, U records at a
+// Step 5, one launch per mode: a group of SEG lanes (lane j holds rank
+// columns j + SEG c, c < CPL) walks a run of consecutive records (reduce_run) of the mode's list, U records at a
 // time (their loads and factor-row gathers issued before any is used); the
 // row's sum stays in registers and is added to G when the run leaves the row
 // and at the end of the run.
 constexpr int kRun = 256;
 
-template <int SEG>
+// Run length: kRun, shortened (to no less than 64) when the list is too
+// short to give about 8192 runs, but long enough that a row meets about 128
+// runs at most: each run ends with R atomics on its last row, and on a mode
+// with few rows (24 at rank 50: 0.06 ms for 128 runs per row, 0.08 ms for 300)
+// those atomics collide.
+int reduce_run(int64_t max_rec, int nrows) {
+  auto r8 = [](int64_t v) { return (v + 7) / 8 * 8; };
+  const int64_t want = std::max(r8((max_rec + 8191) / 8192), r8(max_rec / (128 * (int64_t)std::max(nrows, 1))));
+  return (int)std::min<int64_t>(kRun, std::max<int64_t>(64, want));
+}
+
+template <int SEG, int CPL>
 __global__ void __launch_bounds__(256) sorted_reduce(const RowRec* __restrict__ srt, const int* __restrict__ start,
                                                      int nrows, const float* __restrict__ Aa,
                                                      const float* __restrict__ Ab, const float* __restrict__ Sall,
-                                                     float* __restrict__ G, int R) {
+                                                     float* __restrict__ G, int R, int run) {
   constexpr int PER = 64 / SEG;
   constexpr int U = 8;
   const int lane = threadIdx.x & 63;
   const int j = lane % SEG, sub = lane / SEG;
-  const int jc = j < R ? j : 0;
+  int jc[CPL];
+  bool jv[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    jv[cc] = j + SEG * cc < R;
+    jc[cc] = jv[cc] ? j + SEG * cc : 0;
+  }
   const int64_t grp = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * PER + sub;
   const int64_t nrec = start[nrows];
-  const int64_t p0 = grp * kRun;
+  const int64_t p0 = grp * run;
   if (p0 >= nrec) return;
-  const int64_t p1 = min(p0 + (int64_t)kRun, nrec);
+  const int64_t p1 = min(p0 + (int64_t)run, nrec);
   // row of p0: the last row whose start is <= p0 (rows may be empty)
   int lo = 0, hi = nrows;
   while (hi - lo > 1) {
@@ -515,31 +565,42 @@ __global__ void __launch_bounds__(256) sorted_reduce(const RowRec* __restrict__ 
   }
   int row = lo;
   int64_t bound = start[row + 1];
-  float acc = 0.f;
+  float acc[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) acc[cc] = 0.f;
+  auto flush = [&]() {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      if (jv[cc] && acc[cc] != 0.f) unsafeAtomicAdd(&G[(size_t)row * R + jc[cc]], acc[cc]);
+      acc[cc] = 0.f;
+    }
+  };
   for (int64_t pos = p0; pos < p1; pos += U) {
     RowRec r[U];
-    float va[U], vb[U], vs[U];
+    float va[U][CPL], vb[U][CPL], vs[U][CPL];
 #pragma unroll
     for (int u = 0; u < U; ++u) r[u] = srt[pos + u < p1 ? pos + u : p0];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      va[u] = Aa[(size_t)r[u].a * R + jc];
-      vb[u] = Ab[(size_t)r[u].b * R + jc];
-      vs[u] = Sall[(size_t)r[u].h * R + jc];
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        va[u][cc] = Aa[(size_t)r[u].a * R + jc[cc]];
+        vb[u][cc] = Ab[(size_t)r[u].b * R + jc[cc]];
+        vs[u][cc] = Sall[(size_t)r[u].h * R + jc[cc]];
+      }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (pos + u >= p1) break;
       while (pos + u >= bound) {
-        if (j < R && acc != 0.f) unsafeAtomicAdd(&G[(size_t)row * R + j], acc);
-        acc = 0.f;
+        flush();
         ++row;
         bound = start[row + 1];
       }
-      acc += r[u].y * vs[u] * va[u] * vb[u];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[cc] += r[u].y * vs[u][cc] * va[u][cc] * vb[u][cc];
     }
   }
-  if (j < R && acc != 0.f) unsafeAtomicAdd(&G[(size_t)row * R + j], acc);
+  flush();
 }
 
 // Outputs start from the exact regularisation terms: G = lambda A,
@@ -615,12 +676,13 @@ __global__ void __launch_bounds__(256) table_insert(const int32_t* __restrict__ 
 
 template <int LOSS, bool REC>
 hipError_t launch_seg(const SampledCall& c, const SArgs& a, int64_t blocks) {
+  // ranks above 32 take two columns per lane, so two draws share a wave
   if (c.R <= 16) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 16, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 16, 1, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
   } else if (c.R <= 32) {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 32, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 32, 1, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
   } else {
-    hipLaunchKernelGGL((sampled_kernel<LOSS, 64, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
+    hipLaunchKernelGGL((sampled_kernel<LOSS, 32, 2, REC>), dim3((unsigned)blocks), dim3(256), 0, c.stream, a);
   }
   return hipGetLastError();
 }
@@ -666,14 +728,15 @@ SortedLayout sorted_layout(int I1, int I2, int I3, int R, int nsmax, int64_t p, 
   return L;
 }
 
-template <int SEG>
+template <int SEG, int CPL>
 void launch_reduce_mode(const SampledCall& c, const RowRec* srt, const int* start, int nrows, const float* Aa,
                         const float* Ab, const float* Sall, float* G, int64_t max_rec) {
-  const int64_t groups = (max_rec + kRun - 1) / kRun;
+  const int run = reduce_run(max_rec, nrows);
+  const int64_t groups = (max_rec + run - 1) / run;
   const int64_t blocks = (groups + 4 * (64 / SEG) - 1) / (4 * (64 / SEG));
   if (blocks > 0)
-    hipLaunchKernelGGL((sorted_reduce<SEG>), dim3((unsigned)blocks), dim3(256), 0, c.stream, srt, start, nrows, Aa,
-                       Ab, Sall, G, c.R);
+    hipLaunchKernelGGL((sorted_reduce<SEG, CPL>), dim3((unsigned)blocks), dim3(256), 0, c.stream, srt, start, nrows, Aa,
+                       Ab, Sall, G, c.R, run);
 }
 
 }  // namespace
@@ -807,7 +870,8 @@ hipError_t sampled_run(const SampledCall& c) {
       ca.total = c.p + c.q;
       ca.nslots = (int64_t)c.ns * L.slots;
       ca.I1 = c.I1; ca.I2 = c.I2; ca.I3 = c.I3;
-      const unsigned nchunks = (unsigned)((ca.nslots + kSortChunk - 1) / kSortChunk);
+      ca.chunk = sort_chunk(ca.nslots);
+      const unsigned nchunks = (unsigned)((ca.nslots + ca.chunk - 1) / ca.chunk);
       hipLaunchKernelGGL(sorted_count, dim3(nchunks), dim3(1024), 0, c.stream, ca);
       ScanArgs sa;
       for (int k = 0; k < 3; ++k) {
@@ -829,11 +893,11 @@ hipError_t sampled_run(const SampledCall& c) {
       for (int k = 0; k < 3; ++k) {
         const int* st_k = ib + L.start_off[k];
         if (c.R <= 16)
-          launch_reduce_mode<16>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+          launch_reduce_mode<16, 1>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
         else if (c.R <= 32)
-          launch_reduce_mode<32>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+          launch_reduce_mode<32, 1>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
         else
-          launch_reduce_mode<64>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+          launch_reduce_mode<32, 2>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
       }
       e = hipGetLastError();
       if (e != hipSuccess) return e;

@@ -48,6 +48,11 @@ CASES = [
     ((13, 9, 70), 48, 1, 400, 777, 333, "poisson_log"),
     ((40, 40, 40), 12, 0, 5000, 0, 4096, "poisson_log"),   # zeros only
     ((40, 40, 40), 12, 2, 5000, 4096, 0, "poisson_log"),   # nonzeros only
+    # the paper's count-data shapes: 263 x 263 x 24 at 3.8% density, rank 50,
+    # window 30, 10k + 10k draws; 24 x 77 x 32 at 1.6%, rank 50, as many
+    # nonzero draws as nonzeros plus 1k zeros, window at the library's maximum
+    ((263, 263, 24), 50, 30, 63000, 10000, 10000, "poisson_log"),
+    ((24, 77, 32), 50, 64, 946, 946, 1000, "poisson_log"),
 ]
 
 
@@ -208,3 +213,23 @@ def test_sampled_weight_solve_matches_oracle(alpha):
     assert abs(info["F"] - rinfo.F[-1]) <= 1e-5 * abs(rinfo.F[-1])
     assert rel_err(s.double().cpu().numpy(), ref) <= 1e-4
     assert st.info()["sample_call"] == 9
+
+
+@pytest.mark.gpu
+def test_sampled_larger_draw_counts_match_oracle():
+    """263 x 263 x 24 at 3.8% density, rank 50, window 30 with 50k + 50k
+    draws per slice (one call: the oracle takes about ten seconds).  With
+    this many draws a wave of the draw kernel takes 4 x 64 of them and the
+    reduction walks runs of 256 records; the smaller cases above take the
+    short forms (64 draws per wave, shorter runs)."""
+    print("case: sampled 263x263x24 R50 H30 p=q=50000", flush=True)
+    prob = _f32(gi.sparse_problem(dims=(263, 263, 24), rank=50, window=30, nnz=63000, p=50000,
+                                  q=50000, seed=80, loss="poisson_log"))
+    st, T = _stream(prob)
+    loss_v, G, g_s = st.loss_grad(_dev_coo(prob.X_t), [T(a) for a in prob.A], T(prob.s_t))
+    assert st.sync() == 0
+    F, Gr, gsr = osm.sampled_loss_grad(prob, call=0)
+    assert loss_err(loss_v.item(), F, max(abs(F), 1.0)) <= TOL
+    for k in range(3):
+        assert rel_err(G[k].double().cpu().numpy(), Gr[k]) <= TOL, k
+    assert rel_err(g_s.double().cpu().numpy(), gsr) <= TOL
