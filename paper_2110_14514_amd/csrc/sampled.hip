@@ -629,8 +629,16 @@ __global__ void __launch_bounds__(256) sampled_init(const float* A1, const float
   Kahan<float> k;
   const float* mats[3] = {A1, A2, A3};
   const int cnt[3] = {n1, n2, n3};
+  // eight independent loads in flight per lane before their terms are added
+  constexpr int U = 8;
   for (int m = 0; m < 3; ++m)
-    for (int e = threadIdx.x; e < cnt[m]; e += 256) k.add(0.5f * lam * mats[m][e] * mats[m][e]);
+    for (int e0 = threadIdx.x; e0 < cnt[m]; e0 += 256 * U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = e0 + 256 * u < cnt[m] ? mats[m][e0 + 256 * u] : 0.f;
+#pragma unroll
+      for (int u = 0; u < U; ++u) k.add(0.5f * lam * v[u] * v[u]);
+    }
   for (int e = threadIdx.x; e < R; e += 256) k.add(0.5f * mu * st[e] * st[e]);
   red[threadIdx.x] = k.s;
   __syncthreads();
