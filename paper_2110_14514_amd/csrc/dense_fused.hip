@@ -11,7 +11,8 @@
 // Y, M and the Khatri-Rao matrices are never materialised.
 //
 // Work decomposition: a workgroup (4 waves) owns a tile of TB1 x TB2 index
-// pairs (i1,i2) and all of I3.  Lanes run along i3 (coalesced loads of each
+// pairs (i1,i2) and all of I3, or, when there are few tiles, one chunk of
+// I3 (a second grid dimension).  Lanes run along i3 (coalesced loads of each
 // slice row), waves split the tile's pairs.  Per pair, mode-3 contributions
 // stay lane-local; the mode-1/2 vector V = sum_i3 yhat * A3[i3] is reduced
 // across the wave with a reduce-scatter and added into per-wave LDS rows.
@@ -40,14 +41,20 @@ struct FusedArgs {
   T* gsp;
   T* lossp;
   int I1, I2, I3, R, ns, want, tb1, tb2, nb2;
+  int nch, cw;  // i3 chunks per tile (blockIdx.y) and their width, a multiple of 64
   size_t rp3;   // row pitch of slices h >= 1 (stored slices); slice 0 has pitch I3
 };
 
 struct Tiling {
-  int tb1, tb2, nb1, nb2, ntiles;
+  int tb1, tb2, nb1, nb2, ntiles, nch, cw;
 };
 
-Tiling tiling_for(int I1, int I2) {
+// Few pairs (fewer than 256 tiles of four waves) and long i3 rows: the i3
+// range of each tile is split into nch chunks of cw entries, one workgroup
+// each, so that about 512 workgroups run.  The chunks of a tile write their
+// mode-1 and mode-2 rows, g_s and loss into slots of their own; their G3 rows
+// are disjoint.
+Tiling tiling_for(int I1, int I2, int I3) {
   long pairs = (long)I1 * I2;
   int tb = pairs >= 200000 ? 16 : (pairs >= 4096 ? 8 : 4);
   Tiling t;
@@ -55,35 +62,40 @@ Tiling tiling_for(int I1, int I2) {
   t.nb1 = (I1 + tb - 1) / tb;
   t.nb2 = (I2 + tb - 1) / tb;
   t.ntiles = t.nb1 * t.nb2;
+  const int c64 = (I3 + 63) / 64;
+  int nch = 1;
+  if (t.ntiles < 256 && c64 > 1) nch = std::min(c64, (512 + t.ntiles - 1) / t.ntiles);
+  t.cw = (c64 + nch - 1) / nch * 64;
+  t.nch = I3 > 0 ? (I3 + t.cw - 1) / t.cw : 1;
   return t;
 }
 
 struct PartLayout {
   size_t g1, g2, g3, gs, loss, total;
-  int s1, s2, s3;               // slots of G1 rows, G2 rows, and G3/g_s/loss
+  int s1, s2, s3, s4;           // slots of G1 rows, G2 rows, G3 rows, g_s/loss
 };
 
-PartLayout part_layout_slots(int I1, int I2, int I3, int R, size_t es, int s1, int s2, int s3) {
+PartLayout part_layout_slots(int I1, int I2, int I3, int R, size_t es, int s1, int s2, int s3, int s4) {
   PartLayout p;
-  p.s1 = s1; p.s2 = s2; p.s3 = s3;
+  p.s1 = s1; p.s2 = s2; p.s3 = s3; p.s4 = s4;
   size_t off = 0;
   p.g1 = off; off = align_up(off + (size_t)s1 * I1 * R * es, 256);
   p.g2 = off; off = align_up(off + (size_t)s2 * I2 * R * es, 256);
   p.g3 = off; off = align_up(off + (size_t)s3 * I3 * R * es, 256);
-  p.gs = off; off = align_up(off + (size_t)s3 * R * es, 256);
-  p.loss = off; off = align_up(off + (size_t)s3 * es, 256);
+  p.gs = off; off = align_up(off + (size_t)s4 * R * es, 256);
+  p.loss = off; off = align_up(off + (size_t)s4 * es, 256);
   p.total = off;
   return p;
 }
 
 PartLayout part_layout(int I1, int I2, int I3, int R, size_t es) {
-  Tiling t = tiling_for(I1, I2);
-  return part_layout_slots(I1, I2, I3, R, es, t.nb2, t.nb1, t.ntiles);
+  Tiling t = tiling_for(I1, I2, I3);
+  return part_layout_slots(I1, I2, I3, R, es, t.nb2 * t.nch, t.nb1 * t.nch, t.ntiles, t.ntiles * t.nch);
 }
 
 PartLayout part_layout_mfma(int I1, int I2, int I3, int R, int target) {
   MfmaPlan m = mfma_plan(I1, I2, I3, target);
-  return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2, m.nb1, m.nwg);
+  return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2, m.nb1, m.nwg, m.nwg);
 }
 
 // Reduce-scatter of RT per-lane values over the 64 lanes of a wave.  On
@@ -133,6 +145,7 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int tile = blockIdx.x;
+  const int cy = blockIdx.y;
   const int b1 = tile / a.nb2;
   const int b2 = tile % a.nb2;
   const int i10 = b1 * a.tb1;
@@ -162,7 +175,8 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
   const int jl = lane >> (6 - log2c<RT>());
   const bool primary = (lane & ((64 / RT) - 1)) == 0;
 
-  for (int c0 = 0; c0 < I3; c0 += 64) {
+  const int cend = min(I3, (cy + 1) * a.cw);
+  for (int c0 = cy * a.cw; c0 < cend; c0 += 64) {
     const int i3 = c0 + lane;
     const bool valid = i3 < I3;
     T a3r[RT], g3[RT];
@@ -182,9 +196,20 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
       }
       const size_t pr = (size_t)(i10 + i1l) * I2 + (i20 + i2l);
       const size_t off0 = pr * I3 + (valid ? i3 : 0), offr = pr * a.rp3 + (valid ? i3 : 0);
-      for (int h = 0; h < a.ns; ++h) {
+      // the slice values of kPre slices are loaded before any is used, so a
+      // wave waits on one HBM round trip per kPre slices, not per slice
+      constexpr int kPre = 8;
+      for (int h0 = 0; h0 < a.ns; h0 += kPre) {
+      T xs[kPre];
+#pragma unroll
+      for (int u = 0; u < kPre; ++u)
+        xs[u] = (valid && h0 + u < a.ns) ? a.X[h0 + u][h0 + u == 0 ? off0 : offr] : T(0);
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int h = h0 + u;
+        if (h >= a.ns) break;
         const T* Sh = a.S[h];
-        T x = valid ? a.X[h][h == 0 ? off0 : offr] : T(0);
+        T x = xs[u];
         T m = T(0);
         if (LOSS != kGaussianId) {   // the identity path takes m = 0 (y = -2x)
 #pragma unroll
@@ -203,6 +228,7 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
 #pragma unroll
           for (int j = 0; j < RT; ++j) gs[j] += y * P[j];
         }
+      }
       }
       T V[RT];
 #pragma unroll
@@ -245,24 +271,24 @@ __global__ void __launch_bounds__(kWG) fused_dense_v1(FusedArgs<T> a) {
       if (l < n1) {
         T s = g1w[0][l][j];
         for (int w = 1; w < kNW; ++w) s += g1w[w][l][j];
-        a.G1p[((size_t)b2 * a.I1 + i10 + l) * R + j] = s;
+        a.G1p[((size_t)(b2 * a.nch + cy) * a.I1 + i10 + l) * R + j] = s;
       }
       if (l < n2) {
         T s = g2w[0][l][j];
         for (int w = 1; w < kNW; ++w) s += g2w[w][l][j];
-        a.G2p[((size_t)b1 * I2 + i20 + l) * R + j] = s;
+        a.G2p[((size_t)(b1 * a.nch + cy) * I2 + i20 + l) * R + j] = s;
       }
     }
   }
   if (tid < R) {
     T s = gsx[0][tid];
     for (int w = 1; w < kNW; ++w) s += gsx[w][tid];
-    a.gsp[(size_t)tile * R + tid] = s;
+    a.gsp[((size_t)tile * a.nch + cy) * R + tid] = s;
   }
   if (tid == 0) {
     T s = lsx[0];
     for (int w = 1; w < kNW; ++w) s += lsx[w];
-    a.lossp[tile] = s;
+    a.lossp[(size_t)tile * a.nch + cy] = s;
   }
 }
 
@@ -284,7 +310,7 @@ struct ReduceArgs {
   T* loss;
   T lam, mu;
   const T* gscale;
-  int I1, I2, I3, R, nb1, nb2, ntiles, want, gblocks;
+  int I1, I2, I3, R, nb1, nb2, ntiles, nsl, want, gblocks;   // nsl: g_s/loss slots
   int* status;
 };
 
@@ -319,7 +345,7 @@ __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
       src = r.G3p; stride = n3; slots = r.ntiles; nout = n3; A = r.A3; dst = r.G3;
     } else {
       blk -= b3;
-      src = r.gsp; stride = R; slots = r.ntiles; nout = R; A = r.st; dst = r.gs; lam = r.mu;
+      src = r.gsp; stride = R; slots = r.nsl; nout = R; A = r.st; dst = r.gs; lam = r.mu;
     }
     const int ol = threadIdx.x % kRedOut, c = threadIdx.x / kRedOut;
     const int o = blk * kRedOut + ol;
@@ -344,7 +370,7 @@ __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
   const auto id = [](T v) { return v; };
   const auto sq = [](T v) { return v * v; };
   Kahan<T> k;
-  kahan_strided(k, r.lossp, threadIdx.x, r.ntiles, 256, id);
+  kahan_strided(k, r.lossp, threadIdx.x, r.nsl, 256, id);
   Kahan<T> kr;
   kahan_strided(kr, r.A1, threadIdx.x, (size_t)r.I1 * R, 256, sq);
   kahan_strided(kr, r.A2, threadIdx.x, (size_t)r.I2 * R, 256, sq);
@@ -384,7 +410,7 @@ hipError_t launch_reduce(const DenseCall& c, const PartLayout& pl) {
   r.lam = (T)c.lam; r.mu = (T)c.mu;
   r.gscale = static_cast<const T*>(c.grad_scale);
   r.I1 = c.I1; r.I2 = c.I2; r.I3 = c.I3; r.R = c.R;
-  r.nb1 = pl.s2; r.nb2 = pl.s1; r.ntiles = pl.s3; r.want = c.want;
+  r.nb1 = pl.s2; r.nb2 = pl.s1; r.ntiles = pl.s3; r.nsl = pl.s4; r.want = c.want;
   r.status = c.status;
   auto nblk = [](int n) { return (n + kRedOut - 1) / kRedOut; };
   r.gblocks = (c.want & kWantGrad) ? nblk(c.I1 * c.R) + nblk(c.I2 * c.R) + nblk(c.I3 * c.R) + nblk(c.R) : 0;
@@ -413,9 +439,10 @@ hipError_t launch_fused(const DenseCall& c, const Tiling& tl, const PartLayout& 
   a.lossp = reinterpret_cast<T*>(base + pl.loss);
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = tl.tb1; a.tb2 = tl.tb2; a.nb2 = tl.nb2;
+  a.nch = tl.nch; a.cw = tl.cw;
   a.rp3 = c.ring_pitch ? c.ring_pitch : (size_t)c.I3;
   if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);
-  hipLaunchKernelGGL((fused_dense_v1<T, LOSS, RT>), dim3(tl.ntiles), dim3(kWG), 0, c.stream, a);
+  hipLaunchKernelGGL((fused_dense_v1<T, LOSS, RT>), dim3(tl.ntiles, tl.nch), dim3(kWG), 0, c.stream, a);
   hipError_t e = hipGetLastError();
   if (c.ev_end) hipEventRecord(c.ev_end, c.stream);
   if (e != hipSuccess) return e;
@@ -469,7 +496,7 @@ hipError_t dense_fused_run(const DenseCall& c) {
     if (e != hipSuccess) return e;
     return launch_reduce<float>(c, pl);
   }
-  Tiling tl = tiling_for(c.I1, c.I2);
+  Tiling tl = tiling_for(c.I1, c.I2, c.I3);
   PartLayout pl = part_layout(c.I1, c.I2, c.I3, c.R, c.dtype ? sizeof(double) : sizeof(float));
   if (pl.total > c.part_bytes) return hipErrorInvalidValue;
   return c.dtype ? dispatch_loss<double>(c, tl, pl) : dispatch_loss<float>(c, tl, pl);
