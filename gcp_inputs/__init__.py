@@ -157,14 +157,15 @@ def nonneg_dense(dims, rank: int, window: int, loss: str, seed: int, w: float = 
 
 # ---------------------------------------------------------------- C1 ----
 @dataclass
-class GaussianStream:
+class PlantedStream:
+    """A stream of slices drawn around a planted K-tensor (A_true, S_true[t])."""
     A_true: List[np.ndarray]
     S_true: np.ndarray   # T x R
     X: np.ndarray        # T x I1 x I2 x I3 (FP64)
 
 
 def c1_stream(seed: int = 0, dims=(20, 30, 40), rank: int = 4, steps: int = 20,
-              noise: float = 0.1) -> GaussianStream:
+              noise: float = 0.1) -> PlantedStream:
     """C1: factors N(0,1), temporal weights U(0.5,1.5), X_t = M_t plus noise
     scaled so that ||noise||_F = noise * ||M_t||_F (10% relative noise)."""
     g = rng(seed)
@@ -175,7 +176,19 @@ def c1_stream(seed: int = 0, dims=(20, 30, 40), rank: int = 4, steps: int = 20,
         M = ktensor_full(A, S[t])
         N = g.standard_normal(M.shape)
         X[t] = M + noise * (np.linalg.norm(M) / np.linalg.norm(N)) * N
-    return GaussianStream(A, S, X)
+    return PlantedStream(A, S, X)
+
+
+def poisson_log_stream(seed: int = 21, dims=(15, 18, 20), rank: int = 3, steps: int = 14,
+                       scale: float = 0.7) -> PlantedStream:
+    """Small planted count stream for the log link: factors N(0, scale^2),
+    weights U(0.5,1.5), X_t ~ Poisson(exp(M_t)) where M_t is the planted
+    K-tensor (the log-rate model the Poisson-log loss fits)."""
+    g = rng(seed)
+    A = [g.standard_normal((n, rank)) * scale for n in dims]
+    S = g.uniform(0.5, 1.5, size=(steps, rank))
+    X = np.stack([g.poisson(np.exp(ktensor_full(A, S[t]))).astype(np.float64) for t in range(steps)])
+    return PlantedStream(A, S, X)
 
 
 def c1_problem(seed: int = 0, window: int = 3, dtype=np.float32) -> DenseProblem:

@@ -206,7 +206,9 @@ void gcp_params_default(gcp_params* params);
 /* Bytes of device workspace a stream with these parameters needs. */
 gcp_status gcp_workspace_size(const gcp_params* params, size_t* bytes);
 
-/* Creates a stream.  A0[k] (k < d) are the initial factor matrices; they and
+/* Creates a stream: the inputs of Algorithm 1 (Section 4.3) with the
+ * arguments of Table 1 in params.  A0[k] (k < d) are the initial factor
+ * matrices (the warm start); they and
  * the n_hist initial window slices X_hist[h] (host array of slice structs
  * whose data pointers are device pointers) with their weights s_hist
  * (device, n_hist x R) and host time stamps t_hist are COPIED into the
@@ -312,6 +314,13 @@ gcp_status gcp_factor_info(gcp_stream* s, double* F, double* alpha, int64_t* ite
  * Section 6 is the ratio of the sums over all past slices with the final
  * factors.  Dense streams only (GCP_E_UNSUPPORTED for COO). */
 gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* sum_f, double* sum_sq);
+
+/* Local reconstruction loss of Section 6, eq. local_loss: sum_f / sum_sq of
+ * gcp_slice_loss for the dense slice X with weights s_x under the stream's
+ * current factors, written to *out (host double; the call waits for the
+ * stream).  *out is NaN when ||X||_F = 0 (the ratio is undefined).  Dense
+ * streams only (GCP_E_UNSUPPORTED for COO). */
+gcp_status gcp_local_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* out);
 
 /* K-tensor score of Section 6.1 (congruence of the computed and a reference
  * K-tensor, 1.0 for a perfect recovery): the stream's current factors with

@@ -82,6 +82,7 @@ SIGNATURES = {
     "gcp_factor_info": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_int64),
                                   POINTER(c_int32), POINTER(c_uint64)]),
     "gcp_slice_loss": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p, POINTER(c_double), POINTER(c_double)]),
+    "gcp_local_loss": (c_int32, [c_void_p, POINTER(GcpSlice), c_void_p, POINTER(c_double)]),
     "gcp_ktensor_score": (c_int32, [c_void_p, c_void_p, POINTER(c_void_p), c_void_p, c_int32, POINTER(c_double)]),
     "gcp_get_factors": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "gcp_factor_ptr": (c_int32, [c_void_p, c_int32, POINTER(c_void_p)]),

@@ -13,6 +13,7 @@
 #include <new>
 #include <utility>
 #include <vector>
+#include <limits>
 
 #include "solvers.hpp"
 
@@ -90,7 +91,7 @@ gcp_status check_params(const gcp_params* p) {
     return GCP_E_ARG;
   if (isnan(p->lower) || p->lower == INFINITY) return GCP_E_ARG;
   if (p->tau_f < 0) return GCP_E_ARG;
-  if (!(p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps >= 0))
+  if (!(p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1 && p->adam_eps > 0))
     return GCP_E_ARG;
   if ((p->flags & GCP_FLAG_PLAIN_SCRATCH) && p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
   if ((p->flags & GCP_FLAG_KERNEL_VALU) && (p->flags & GCP_FLAG_KERNEL_MFMA)) return GCP_E_ARG;
@@ -310,8 +311,10 @@ DenseCall base_call(gcp_stream* s) {
 
 gcp_status hip_status(hipError_t e) { return e == hipSuccess ? GCP_OK : GCP_E_DEVICE; }
 
-// Factor entries that take ADAM steps: all three blocks, or the first two for
-// matrix slices (the fixed row is the last block of the packed layout).
+// Factor entries that take ADAM steps: every block of the packed layout.  For
+// matrix slices the fixed row of ones (the middle block) is included; it
+// stays put because its gradient is cleared before every step and adam_eps
+// is required to be positive (a zero gradient then gives a zero step).
 int64_t adam_elems(const gcp_stream* s) { return (int64_t)s->L.fac_elems; }
 
 // Matrix slices are carried as I1 x 1 x I2 tensors (the same memory as the
@@ -854,17 +857,20 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
   if (p.kappa_f > 0 && e == hipSuccess) e = factor_epochs(s, X_t, s_t);
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->ws + s->L.Aold, s->ws + s->L.A, s->L.fac_elems * s->es, hipMemcpyDeviceToDevice, s->st);
+  // a failed launch leaves the window, the time index and the slot stamps
+  // as they were
+  if (e != hipSuccess) return hip_status(e);
   // reservoir window update (Algorithm 1), then t <- t+1
   int slot = -1;
   if (p.window > 0) {
     if (s->nwin < p.window) {
-      slot = s->nwin++;
+      slot = s->nwin;
     } else {
       uint64_t j = splitmix64(p.seed ^ (uint64_t)s->t) % (uint64_t)s->t + 1;
       if (j <= (uint64_t)p.window) slot = (int)(j - 1);
     }
   }
-  if (slot >= 0 && e == hipSuccess) {
+  if (slot >= 0) {
     if (model_hist(s))
       ;   // only s_t and t are kept
     else if (coo)
@@ -874,10 +880,12 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->ws + s->L.shist + (size_t)slot * p.rank * s->es, s_t, p.rank * s->es,
                          hipMemcpyDeviceToDevice, s->st);
+    if (e != hipSuccess) return hip_status(e);
+    if (s->nwin == slot) s->nwin += 1;
     s->slot_t[slot] = s->t;
   }
   s->t += 1;
-  return hip_status(e);
+  return GCP_OK;
 }
 
 gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* sum_f, double* sum_sq) {
@@ -917,6 +925,15 @@ gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, do
   if (e != hipSuccess) return GCP_E_DEVICE;
   if (sum_f) *sum_f = f;
   if (sum_sq) *sum_sq = q;
+  return GCP_OK;
+}
+
+gcp_status gcp_local_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* out) {
+  if (!out) return GCP_E_ARG;
+  double f = 0.0, q = 0.0;
+  gcp_status st = gcp_slice_loss(s, X, s_x, &f, &q);
+  if (st != GCP_OK) return st;
+  *out = q > 0.0 ? f / q : std::numeric_limits<double>::quiet_NaN();
   return GCP_OK;
 }
 

@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(256) k_adam(int64_t n, T* __restrict__ a, cons
     u[i] = ui;
     v[i] = vi;
     T ai = a[i] - alpha_t * ui / (sqrt(vi) + eps);
-    a[i] = ai > lower ? ai : lower;
+    a[i] = ai < lower ? lower : ai;   // keeps a NaN visible
   }
 }
 

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) batch_adam_kernel(const BatchDesc* __rest
     d.u[e] = u;
     d.v[e] = v;
     const float a = d.A[e] - at * u / (sqrtf(v) + d.eps);
-    d.A[e] = a > d.lower ? a : d.lower;
+    d.A[e] = a < d.lower ? d.lower : a;
   }
 }
 

@@ -4,8 +4,9 @@
 // for each slice h of {t} u H_t
 //   K_model  writes the full model tensor M_h  (eq. CP_model)
 //   K_elem   reads X_h and M_h, writes Y_h = c_h df/dm and loss partials
-//   K_mode1  G^(1) += Y_h(1) Z_1 diag(s_h)   (one workgroup per row i1)
-//   K_mode2  G^(2) += Y_h(2) Z_2 diag(s_h)   (one workgroup per row i2)
+//   K_mode1  G^(1) += Y_h(1) Z_1 diag(s_h)   (partial rows: a workgroup per
+//            row i1 and chunk of its (i2,i3) entries)
+//   K_mode2  G^(2) += Y_h(2) Z_2 diag(s_h)   (likewise per row i2)
 //   K_mode3  partial rows of Y_h(3) Z_3 diag(s_h) per chunk of (i1,i2) pairs
 //   K_gs     (current slice) partials of Z^T vec(Y_t)
 // then one kernel sums the partials and adds the regularisation terms.
@@ -18,20 +19,32 @@ namespace {
 constexpr int kPairChunk = 64;
 
 struct PlainLayout {
-  size_t M, Y, g3p, gsp, lossp, total;
-  int nchunks, eblocks;
+  size_t M, Y, g1p, g2p, g3p, gsp, lossp, total;
+  int nchunks, eblocks, split1, split2;
 };
 
 constexpr int kEBlocks = 1024;
+
+// Chunks per row of the mode-1 and mode-2 products: enough workgroups to
+// fill the device (about 2048), each chunk at least 1024 entries.
+int row_split(int rows, size_t per_row) {
+  const size_t want = (2048 + (size_t)rows - 1) / (size_t)rows;
+  const size_t cap = std::max<size_t>(1, per_row / 1024);
+  return (int)std::max<size_t>(1, std::min(want, cap));
+}
 
 PlainLayout plain_layout(int I1, int I2, int I3, int R) {
   PlainLayout p;
   size_t omega = (size_t)I1 * I2 * I3;
   p.nchunks = (int)(((size_t)I1 * I2 + kPairChunk - 1) / kPairChunk);
   p.eblocks = kEBlocks;
+  p.split1 = row_split(I1, (size_t)I2 * I3);
+  p.split2 = row_split(I2, (size_t)I1 * I3);
   size_t off = 0;
   p.M = off; off = align_up(off + omega * 4, 256);
   p.Y = off; off = align_up(off + omega * 4, 256);
+  p.g1p = off; off = align_up(off + (size_t)p.split1 * I1 * R * 4, 256);
+  p.g2p = off; off = align_up(off + (size_t)p.split2 * I2 * R * 4, 256);
   p.g3p = off; off = align_up(off + (size_t)p.nchunks * I3 * R * 4, 256);
   p.gsp = off; off = align_up(off + (size_t)p.nchunks * ((I3 + 255) / 256) * R * 4, 256);
   p.lossp = off; off = align_up(off + (size_t)kMaxNs * kEBlocks * 4, 256);
@@ -97,18 +110,21 @@ __device__ void block_reduce_rows(float (&acc)[RT], float* sm /* 4*RT */) {
   __syncthreads();
 }
 
-// G^(1) row i1 (+)= sum_{i2,i3} Y[i1,i2,i3] A2[i2,:] A3[i3,:] s_h
+// Partial row (i1, chunk blockIdx.y of its entries) of
+// G^(1) (+)= sum_{i2,i3} Y[i1,i2,i3] A2[i2,:] A3[i3,:] s_h
 template <int RT>
 __global__ void __launch_bounds__(256) k_mode1(const float* __restrict__ Y, const float* __restrict__ A2,
                                                const float* __restrict__ A3, const float* __restrict__ s,
-                                               float* __restrict__ G1, int I2, int I3, int R, int accumulate) {
+                                               float* __restrict__ G1p, int I1, int I2, int I3, int R,
+                                               int accumulate) {
   extern __shared__ float sm[];
   const int i1 = blockIdx.x;
   float acc[RT];
   for (int j = 0; j < RT; ++j) acc[j] = 0.f;
   const size_t n = (size_t)I2 * I3;
+  const size_t e0 = n * blockIdx.y / gridDim.y, e1 = n * (blockIdx.y + 1) / gridDim.y;
   const float* row = Y + (size_t)i1 * n;
-  for (size_t e = threadIdx.x; e < n; e += 256) {
+  for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
     int i2 = (int)(e / I3), i3 = (int)(e - (size_t)i2 * I3);
     float y = row[e];
     for (int j = 0; j < RT; ++j)
@@ -117,23 +133,25 @@ __global__ void __launch_bounds__(256) k_mode1(const float* __restrict__ Y, cons
   block_reduce_rows<RT>(acc, sm);
   if ((int)threadIdx.x < R) {
     float v = sm[threadIdx.x] * s[threadIdx.x];
-    float* g = G1 + (size_t)i1 * R + threadIdx.x;
+    float* g = G1p + ((size_t)blockIdx.y * I1 + i1) * R + threadIdx.x;
     *g = accumulate ? *g + v : v;
   }
 }
 
-// G^(2) row i2 (+)= sum_{i1,i3} Y[i1,i2,i3] A1[i1,:] A3[i3,:] s_h
+// Partial row (i2, chunk blockIdx.y) of
+// G^(2) (+)= sum_{i1,i3} Y[i1,i2,i3] A1[i1,:] A3[i3,:] s_h
 template <int RT>
 __global__ void __launch_bounds__(256) k_mode2(const float* __restrict__ Y, const float* __restrict__ A1,
                                                const float* __restrict__ A3, const float* __restrict__ s,
-                                               float* __restrict__ G2, int I1, int I2, int I3, int R,
+                                               float* __restrict__ G2p, int I1, int I2, int I3, int R,
                                                int accumulate) {
   extern __shared__ float sm[];
   const int i2 = blockIdx.x;
   float acc[RT];
   for (int j = 0; j < RT; ++j) acc[j] = 0.f;
   const size_t n = (size_t)I1 * I3;
-  for (size_t e = threadIdx.x; e < n; e += 256) {
+  const size_t e0 = n * blockIdx.y / gridDim.y, e1 = n * (blockIdx.y + 1) / gridDim.y;
+  for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
     int i1 = (int)(e / I3), i3 = (int)(e - (size_t)i1 * I3);
     float y = Y[((size_t)i1 * I2 + i2) * I3 + i3];
     for (int j = 0; j < RT; ++j)
@@ -142,7 +160,7 @@ __global__ void __launch_bounds__(256) k_mode2(const float* __restrict__ Y, cons
   block_reduce_rows<RT>(acc, sm);
   if ((int)threadIdx.x < R) {
     float v = sm[threadIdx.x] * s[threadIdx.x];
-    float* g = G2 + (size_t)i2 * R + threadIdx.x;
+    float* g = G2p + ((size_t)blockIdx.y * I2 + i2) * R + threadIdx.x;
     *g = accumulate ? *g + v : v;
   }
 }
@@ -191,9 +209,10 @@ __global__ void __launch_bounds__(256) k_mode3(const float* __restrict__ Y, cons
 
 __global__ void __launch_bounds__(256) k_final(float* G1, float* G2, float* G3, float* gs, float* loss,
                                                const float* A1, const float* A2, const float* A3,
-                                               const float* st, const float* g3p, const float* gsp,
-                                               const float* lossp, int nloss, int I1, int I2, int I3,
-                                               int R, int nchunks, int nygs, float lam, float mu,
+                                               const float* st, const float* g1p, const float* g2p,
+                                               const float* g3p, const float* gsp, const float* lossp,
+                                               int nloss, int I1, int I2, int I3, int R, int split1,
+                                               int split2, int nchunks, int nygs, float lam, float mu,
                                                int want, int* status) {
   if ((int)blockIdx.x < (int)gridDim.x - 1) {
     const int n1 = I1 * R, n2 = I2 * R, n3 = I3 * R;
@@ -201,11 +220,15 @@ __global__ void __launch_bounds__(256) k_final(float* G1, float* G2, float* G3, 
     for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += (gridDim.x - 1) * 256) {
       float out;
       if (idx < n1) {
-        out = G1[idx] + lam * A1[idx];
+        Kahan<float> k;
+        for (int c = 0; c < split1; ++c) k.add(g1p[(size_t)c * n1 + idx]);
+        out = k.s + lam * A1[idx];
         G1[idx] = out;
       } else if (idx < n1 + n2) {
         int e = idx - n1;
-        out = G2[e] + lam * A2[e];
+        Kahan<float> k;
+        for (int c = 0; c < split2; ++c) k.add(g2p[(size_t)c * n2 + e]);
+        out = k.s + lam * A2[e];
         G2[e] = out;
       } else if (idx < n1 + n2 + n3) {
         int e = idx - n1 - n2;
@@ -252,6 +275,8 @@ hipError_t run_rt(const DenseCall& c, char* base, const PlainLayout& L) {
   const size_t omega = (size_t)c.I1 * c.I2 * c.I3;
   float* M = reinterpret_cast<float*>(base + L.M);
   float* Y = reinterpret_cast<float*>(base + L.Y);
+  float* g1p = reinterpret_cast<float*>(base + L.g1p);
+  float* g2p = reinterpret_cast<float*>(base + L.g2p);
   float* g3p = reinterpret_cast<float*>(base + L.g3p);
   float* gsp = reinterpret_cast<float*>(base + L.gsp);
   float* lossp = reinterpret_cast<float*>(base + L.lossp);
@@ -292,10 +317,10 @@ hipError_t run_rt(const DenseCall& c, char* base, const PlainLayout& L) {
                            omega, c.I3, pitch, lossp + (size_t)h * kEBlocks);
     }
     if (c.want & kWantGrad) {
-      hipLaunchKernelGGL(k_mode1<RT>, dim3(c.I1), dim3(256), shm, c.stream, Y, A2, A3, s, G1, c.I2, c.I3, c.R,
-                         h > 0);
-      hipLaunchKernelGGL(k_mode2<RT>, dim3(c.I2), dim3(256), shm, c.stream, Y, A1, A3, s, G2, c.I1, c.I2,
-                         c.I3, c.R, h > 0);
+      hipLaunchKernelGGL(k_mode1<RT>, dim3(c.I1, L.split1), dim3(256), shm, c.stream, Y, A2, A3, s, g1p, c.I1,
+                         c.I2, c.I3, c.R, h > 0);
+      hipLaunchKernelGGL(k_mode2<RT>, dim3(c.I2, L.split2), dim3(256), shm, c.stream, Y, A1, A3, s, g2p, c.I1,
+                         c.I2, c.I3, c.R, h > 0);
       hipLaunchKernelGGL(k_mode3<RT>, dim3(L.nchunks, ygs), dim3(256), shm, c.stream, Y, A1, A2, A3, s, g3p,
                          h == 0 ? gsp : nullptr, c.I1, c.I2, c.I3, c.R, h > 0);
     }
@@ -304,9 +329,9 @@ hipError_t run_rt(const DenseCall& c, char* base, const PlainLayout& L) {
   const int total = (c.I1 + c.I2 + c.I3 + 1) * c.R;
   const int gblocks = (c.want & kWantGrad) ? std::min(1024, (total + 255) / 256) : 0;
   hipLaunchKernelGGL(k_final, dim3(gblocks + 1), dim3(256), 0, c.stream, G1, G2, G3, static_cast<float*>(c.gs),
-                     static_cast<float*>(c.loss_out), A1, A2, A3, static_cast<const float*>(c.S[0]), g3p, gsp,
-                     lossp, c.ns * kEBlocks, c.I1, c.I2, c.I3, c.R, L.nchunks, ygs, (float)c.lam, (float)c.mu,
-                     c.want, c.status);
+                     static_cast<float*>(c.loss_out), A1, A2, A3, static_cast<const float*>(c.S[0]), g1p, g2p,
+                     g3p, gsp, lossp, c.ns * kEBlocks, c.I1, c.I2, c.I3, c.R, L.split1, L.split2, L.nchunks,
+                     ygs, (float)c.lam, (float)c.mu, c.want, c.status);
   return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) fac_adam(int64_t n, T* __restrict__ a, co
     u[e] = ue;
     v[e] = ve;
     const T ae = a[e] - alpha_t * ue / (sqrt(ve) + eps);
-    a[e] = ae > lower ? ae : lower;
+    a[e] = ae < lower ? lower : ae;
   }
 }
 

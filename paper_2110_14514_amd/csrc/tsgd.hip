@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(NT) ts_final(TsArgs<T> a) {
       a.u[j] = uj;
       a.v[j] = vj;
       const T sj = sh_s[j] - alpha_t * uj / (sqrt(vj) + a.eps);
-      a.s[j] = sj > a.lower ? sj : a.lower;
+      a.s[j] = sj < a.lower ? a.lower : sj;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -342,7 +342,7 @@ __global__ void ts_step_from(TsArgs<T> a, const T* g) {
     a.u[j] = uj;
     a.v[j] = vj;
     const T sj = a.s[j] - alpha_t * uj / (sqrt(vj) + a.eps);
-    a.s[j] = sj > a.lower ? sj : a.lower;
+    a.s[j] = sj < a.lower ? a.lower : sj;
   }
   __syncthreads();
   if (j == 0) {

@@ -195,8 +195,12 @@ class Stream:
         return f.value, q.value
 
     def local_loss(self, X: torch.Tensor, s_x: torch.Tensor) -> float:
-        f, q = self.slice_loss(X, s_x)
-        return f / q
+        """Local reconstruction loss of a dense slice (NaN when ||X|| = 0)."""
+        out = c_double(0.0)
+        sl = _dense_slice(X)
+        N.check(self.lib.gcp_local_loss(self.handle, byref(sl), _ptr(s_x.contiguous()), byref(out)),
+                "gcp_local_loss")
+        return out.value
 
     def ktensor_score(self, w_a: torch.Tensor, B: Sequence[torch.Tensor], w_b: torch.Tensor) -> float:
         """Congruence score of the current factors (weights w_a) against the

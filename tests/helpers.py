@@ -1,5 +1,6 @@
 """Shared test helpers: move a synthetic problem to the device, run the HIP
-path through the C ABI, and compare with the oracle normwise."""
+path through the C ABI, and compare with the oracle normwise and per element
+(each element against its column's largest reference value)."""
 from __future__ import annotations
 
 import numpy as np
@@ -12,6 +13,24 @@ def rel_err(got, ref) -> float:
     ref = np.asarray(ref, np.float64)
     den = np.linalg.norm(ref)
     return float(np.linalg.norm(got - ref) / (den if den > 0 else 1.0))
+
+
+def elem_err(got, ref) -> float:
+    """Largest per-element error, each element against the largest |value| of
+    its column of the reference (a vector is one column): a wrong short row
+    or a wrong rank column shows here even when the matrix norm hides it."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if ref.ndim == 1:
+        got, ref = got[:, None], ref[:, None]
+    scale = np.max(np.abs(ref), axis=0)
+    scale = np.where(scale > 0, scale, 1.0)
+    return float(np.max(np.abs(got - ref) / scale[None, :])) if ref.size else 0.0
+
+
+def grad_err(got, ref) -> float:
+    """max(normwise, per-element) error of a gradient against the oracle's."""
+    return max(rel_err(got, ref), elem_err(got, ref))
 
 
 def loss_err(got: float, ref: float, scale: float) -> float:
@@ -60,5 +79,7 @@ def compare(prob, got, oracle_mod):
     errs = {"loss": loss_err(got[0], F, scale)}
     for k in range(3):
         errs[f"G{k + 1}"] = rel_err(got[1][k], G[k])
+        errs[f"G{k + 1}_elem"] = elem_err(got[1][k], G[k])
     errs["g_s"] = rel_err(got[2], gs)
+    errs["g_s_elem"] = elem_err(got[2], gs)
     return errs

@@ -81,6 +81,7 @@ def _ws(lib, p):
     ("loss", 5, "E_ARG"), ("loss", -1, "E_ARG"), ("dtype", 5, "E_ARG"), ("theta", 0.0, "E_ARG"),
     ("theta", 1.5, "E_ARG"), ("mu", -1.0, "E_ARG"), ("slice_kind", 7, "E_UNSUPPORTED"),
     ("hist", 2, "E_ARG"), ("hist", -1, "E_ARG"), ("flags", 8, "E_ARG"),
+    ("adam_eps", 0.0, "E_ARG"), ("adam_eps", -1e-8, "E_ARG"),
 ])
 def test_invalid_params_rejected(lib, field, value, code):
     from paper_2110_14514_amd import _native as N

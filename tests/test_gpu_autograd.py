@@ -6,7 +6,7 @@ import pytest
 import gcp_inputs as gi
 from oracle import gcp as og
 
-from helpers import TOL, make_stream, rel_err, to_device
+from helpers import TOL, make_stream, grad_err, rel_err, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -58,8 +58,8 @@ def test_backward_equals_direct_gradient_and_oracle():
     assert torch.allclose(s.grad, 3.0 * g_s, rtol=1e-6, atol=0)
     Gr, gsr = og.gradient(prob.promoted())
     for k in range(3):
-        assert rel_err(A[k].grad.double().cpu().numpy() / 3.0, Gr[k]) <= TOL
-    assert rel_err(s.grad.double().cpu().numpy() / 3.0, gsr) <= TOL
+        assert grad_err(A[k].grad.double().cpu().numpy() / 3.0, Gr[k]) <= TOL
+    assert grad_err(s.grad.double().cpu().numpy() / 3.0, gsr) <= TOL
 
 
 def test_no_model_tensor_is_materialised():

@@ -30,6 +30,8 @@ SHAPES = [
     ((3, 4, 128), 20, 60),      # four h-tiles
     ((9, 10, 48), 16, 4),       # 32-wide group + 16-wide tail (one-tile tail)
     ((11, 13, 52), 16, 6),      # 32-wide group + 20-wide tail (two-tile tail)
+    ((12, 10, 64), 32, 20),     # C3's build: rank tile 32, two h-tiles, 16-byte copies
+    ((8, 9, 68), 24, 24),       # the same build at rank 24, 25 slices, a 4-wide tail
 ]
 
 
