@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the streaming-GCP gradient step on one MI355X.
 
-Workload (the configuration the metric is quoted on): dense Poisson-count
-slices of 200x200x200 FP32, rank 16, window 10, Poisson loss with log link.
-One step = one gcp_loss_grad (objective and all gradients) over the current
-slice and its full window of 10 stored slices, inputs resident in HBM.
+Default workload (the batched configuration): 64 independent streams whose
+dense FP32 slices have dims drawn from U{50..300}^3, ranks from {8, 16, 32}
+and windows from 4..16, Gaussian and Poisson-log losses mixed.  One step =
+one gcp_batch_loss_grad: the objective and every gradient of all 64 streams
+over their current slices and full windows, replayed as a captured HIP graph
+with inputs resident in HBM.
 
-Prints ONE JSON line:  grad steps/s (fused), ms per step, the unfused
-("plain") path's rate on the same GPU, the roofline entry for the dominant
-kernel (algorithmic bytes / kernel time from HIP events on the library's
-stream), and the FP64 CPU oracle's rate on this host (with its error against
-the GPU result).
+Prints ONE JSON line: batched grad steps/s, ms per step (wall clock over K
+replays), the median / p10 / p90 of per-replay HIP-event times, the unfused
+("plain") path's time for the same 64 gradients on the same GPU, the
+roofline entry (algorithmic bytes / median replay time), the error of the
+GPU result against the FP64 oracle on a sample of streams, and the oracle's
+rate on this host.  --workload selects the other legs (C2, C3, C5, ...),
+each printing a line of its own.
 """
 from __future__ import annotations
 
@@ -44,9 +48,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5", "e6",
-                                                      "e7"],
-                    help="c2 (default) is the configuration the metric is quoted on; the others "
+    ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5",
+                                                      "e6", "e7"],
+                    help="c4 (default) is the batched configuration the metric is quoted on; the others "
                          "print their own line")
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"],
                     help="c2m: the dense data-term kernel (auto: chosen by the library)")
@@ -164,46 +168,186 @@ def bench_c3(args):
     return 0
 
 
+def _cpu_info():
+    """Host CPU model, NumPy's BLAS and the BLAS thread count (for the
+    oracle's baseline line)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        dep = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        blas = f"{dep.get('name', '')} {dep.get('version', '')}".strip()
+    except Exception:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    return model, blas, int(threads)
+
+
+C4_KERNEL_SOURCES = ["paper_2110_14514_amd/csrc/mfma_tile.hpp", "paper_2110_14514_amd/csrc/dense_mfma.hip",
+                     "paper_2110_14514_amd/csrc/dense_mfma_gaussian.hip",
+                     "paper_2110_14514_amd/csrc/dense_mfma_poisson.hip", "paper_2110_14514_amd/csrc/common.hpp"]
+
+
 def bench_c4(args):
     """C4: 64 streams, dims U{50..300}^3, rank {8,16,32}, window 4..16,
-    Gaussian/Poisson-log; one batched factor update (persistent launch)."""
+    Gaussian/Poisson-log; one step = one batched gcp_batch_loss_grad (all 64
+    stream gradients), captured once as a HIP graph and replayed."""
     import torch
     import gcp_inputs as gi
+    from oracle import gcp as og
     from paper_2110_14514_amd import Batch, Stream
     specs = gi.c4_specs()
     side = torch.cuda.Stream()       # graph capture needs a non-default stream
     torch.cuda.set_stream(side)
-    streams, Xb, Sb = [], [], []
-    tot_bytes = 0
-    tot_flops = 0
+    plain = not (args.no_plain or args.fused_only)
+    cpu_leg = not (args.no_cpu_baseline or args.fused_only)
+    # oracle sample: per tile class (loss, rank tile, h-tiles, copy width) the
+    # smallest stream, when its window holds at most 25M entries
+    classes = {}
+    for i, sp in enumerate(specs):
+        key = (sp.loss, sp.rank > 16, sp.window + 1 > 16, sp.dims[2] % 4 == 0)
+        es = int(np.prod(sp.dims)) * (sp.window + 1)
+        if key not in classes or es < classes[key][0]:
+            classes[key] = (es, i)
+    sample = sorted(i for es, i in classes.values() if es <= 25_000_000) if cpu_leg else []
+    streams, Xb, Sb, keep = [], [], [], {}
+    tot_bytes = tot_flops = tot_es = 0
     print("bench: generating C4 on the device", file=sys.stderr, flush=True)
-    for sp in specs:
+    for i, sp in enumerate(specs):
         X_t, A, s_t, Xh, Sh = gi.device_dense_window(sp.dims, sp.rank, sp.window, sp.loss, sp.seed)
         streams.append(Stream(sp.dims, sp.rank, sp.window, sp.loss, A, Xh, Sh,
-                              list(range(1, sp.window + 1)), alpha_f=1e-4, tau_f=1))
+                              list(range(1, sp.window + 1)), alpha_f=1e-4, tau_f=1, plain=plain))
         Xb.append(X_t)
         Sb.append(s_t)
-        om = int(np.prod(sp.dims))
-        tot_bytes += (sp.window + 1) * om * 4
-        tot_flops += om * (4 * sp.rank * (sp.window + 1) + 8 * sp.rank)
+        keep[i] = (A, Xh if i in sample else None, Sh)
+        om, ns, R = int(np.prod(sp.dims)), sp.window + 1, sp.rank
+        tot_es += om * ns
+        tot_bytes += ns * om * 4 + 4 * R * sum(sp.dims) * 2 + 4 * R * (ns + 1)
+        tot_flops += om * (4 * R * ns + 8 * R)
         del Xh
     torch.cuda.synchronize()
     b = Batch(streams, Xb, Sb)
-    fn = lambda: b.loss_grad()
-    sec = _time(fn, args.steps, args.warmup, torch.cuda.synchronize)
-    g = torch.cuda.CUDAGraph()
-    cs = streams[0].hip_stream
+    b.loss_grad()
     torch.cuda.synchronize()
-    with torch.cuda.graph(g, stream=cs):
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=streams[0].hip_stream):
         b.loss_grad()
-    gsec = _time(g.replay, args.steps, args.warmup, torch.cuda.synchronize)   # replays on `side`
-    assert b.sync_streams() == 0
-    _line("C4 64 independent streams, dims U{50..300}^3, rank {8,16,32}, window 4..16, "
-          "Gaussian/Poisson-log; one batched gcp_batch_loss_grad (all 64 stream gradients)",
-          "batched grad steps/s (64 streams each)", gsec * 1e3, args.steps, args.warmup,
-          tot_bytes, tot_flops, gsec,
-          {"eager_ms_per_step": sec * 1e3, "graph_ms_per_step": gsec * 1e3,
-           "stream_steps_per_s": 64 / gsec})
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    K = max(args.steps, 1)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(side)
+        g.replay()
+        e1.record(side)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert b.sync_streams() == 0, "device reported a numeric failure"
+    ms_per_step = (t1 - t0) * 1e3 / K
+    rep = np.array(sorted(e0.elapsed_time(e1) for e0, e1 in ev))
+    med, p10, p90 = (float(np.percentile(rep, q)) for q in (50, 10, 90))
+    print(f"bench: batched step {ms_per_step:.3f} ms (replay median {med:.3f} ms)", file=sys.stderr, flush=True)
+
+    # ---- unfused path: the same 64 gradients through the plain kernels ------
+    plain_ms = None
+    if plain:
+        outs = [(torch.empty(1, device="cuda"), [torch.empty(n, sp.rank, device="cuda") for n in sp.dims],
+                 torch.empty(sp.rank, device="cuda")) for sp in specs]
+
+        def plain_step():
+            for i, st in enumerate(streams):
+                st.loss_grad(Xb[i], keep[i][0], Sb[i], plain=True, out=outs[i])
+        plain_step()
+        torch.cuda.synchronize()
+        n_plain = 3
+        c0 = time.perf_counter()
+        for _ in range(n_plain):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - c0) * 1e3 / n_plain
+        for st in streams:
+            assert st.sync() == 0
+        print(f"bench: plain {plain_ms:.3f} ms per 64 gradients", file=sys.stderr, flush=True)
+
+    # ---- oracle: error of the GPU result and the CPU rate on the sample -----
+    err, cpu = None, None
+    if sample:
+        host = lambda x: x.double().cpu().numpy()
+        worst = {"loss": 0.0, "G_normwise": 0.0, "G_elementwise": 0.0, "g_s_normwise": 0.0,
+                 "g_s_elementwise": 0.0}
+        csec, ses = 0.0, 0
+        from types import SimpleNamespace
+        for i in sample:
+            sp = specs[i]
+            A, Xh, Sh = keep[i]
+            prob = SimpleNamespace(X_t=host(Xb[i]), A=[host(a) for a in A], s_t=host(Sb[i]),
+                                   X_hist=[host(x) for x in Xh], s_hist=host(Sh), t_hist=np.arange(1, sp.window + 1),
+                                   t=sp.window + 1, w=1.0, theta=1.0, lam=0.0, mu=0.0, loss=sp.loss)
+            c0 = time.perf_counter()
+            F = og.objective(prob)
+            Gr, gsr = og.gradient(prob)
+            csec += time.perf_counter() - c0
+            ses += int(np.prod(sp.dims)) * (sp.window + 1)
+            loss, G, g_s = b.outputs[i]
+            scale = og.loss_terms_abs(prob)
+            worst["loss"] = max(worst["loss"], abs(float(loss.item()) - F) / max(abs(F), scale))
+            for k in range(3):
+                gk = host(G[k])
+                worst["G_normwise"] = max(worst["G_normwise"], float(np.linalg.norm(gk - Gr[k]) / np.linalg.norm(Gr[k])))
+                colmax = np.max(np.abs(Gr[k]), axis=0)
+                worst["G_elementwise"] = max(worst["G_elementwise"],
+                                             float(np.max(np.abs(gk - Gr[k]) / np.where(colmax > 0, colmax, 1.0))))
+            gv = host(g_s)
+            worst["g_s_normwise"] = max(worst["g_s_normwise"], float(np.linalg.norm(gv - gsr) / np.linalg.norm(gsr)))
+            worst["g_s_elementwise"] = max(worst["g_s_elementwise"], float(np.max(np.abs(gv - gsr)) / np.max(np.abs(gsr))))
+        err = dict(worst, streams_checked=sample)
+        model, blas, threads = _cpu_info()
+        share = ses / tot_es
+        cpu = {"value": share / csec, "unit": "batched grad steps/s (64 streams each)", "cores": threads,
+               "kind": "oracle", "cpu_model": model, "blas": blas, "numpy": np.__version__,
+               "sample": f"FP64 NumPy oracle objective+gradient of {len(sample)} of the 64 streams (the smallest of "
+                         f"each tile class up to 25M window entries: streams {sample}), {csec:.1f} s for "
+                         f"{100 * share:.1f}% of the step's entry-slices, scaled to one batched step"}
+    traffic = _profiled_traffic("batch_c4.txt", C4_KERNEL_SOURCES)
+    ach = tot_bytes / (med / 1e3) / 1e9
+    res = {
+        "metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
+        "value": 1e3 / ms_per_step, "unit": "batched grad steps/s (64 streams each)", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C4: 64 independent streams, dense FP32 slices with dims U{50..300}^3, rank "
+                               "{8,16,32}, window 4..16, Gaussian/Poisson-log mixed; one gcp_batch_loss_grad "
+                               "(objective and all gradients of the 64 streams) replayed as a HIP graph",
+                   "streams": len(specs), "entry_slices_per_step": tot_es, "parallelism": "single GPU"},
+        "replay_ms": {"median": med, "p10": p10, "p90": p90, "replays": K},
+        "stream_steps_per_s": len(specs) * 1e3 / ms_per_step,
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "batched gradient step (tile kernels and their fixed-order reduce, one graph)",
+                     "kernel_ms": med, "alg_bytes_per_launch": tot_bytes,
+                     "alg_gflops_per_launch": tot_flops / 1e9,
+                     "fp32_tflops": tot_flops / (med / 1e3) / 1e12,
+                     "fp32_frac": tot_flops / (med / 1e3) / 1e12 / FP32_PEAK_TFLOPS},
+        "plain_ms_per_step": plain_ms,
+        "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
+        "err_vs_oracle": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
     return 0
 
 
@@ -485,18 +629,10 @@ def bench_c5(args):
     return 0
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported",
-              file=sys.stderr)
-        return 2
-    if args.copy_probe:
-        return copy_probe(args.copy_probe)
-    if args.workload != "c2":
-        return {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
-                "c2step": bench_c2step, "ops": bench_ops, "e5": bench_e5, "e6": bench_c5,
-                "e7": bench_c5}[args.workload](args)
+def bench_c2(args):
+    """C2: dense Poisson-count slices of 200x200x200 FP32, rank 16, window 10,
+    Poisson-log; one gcp_loss_grad over X_t and 10 stored slices, two input
+    sets in turn (704 MB, beyond the 256 MB last-level cache)."""
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream
@@ -630,6 +766,18 @@ def main():
     print(json.dumps(res), flush=True)
     return 0
 
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        return 2
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
+    return {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
+            "c2step": bench_c2step, "ops": bench_ops, "e5": bench_e5, "e6": bench_c5,
+            "e7": bench_c5}[args.workload](args)
 
 if __name__ == "__main__":
     sys.exit(main())

@@ -360,8 +360,10 @@ gcp_status gcp_stream_destroy(gcp_stream* s);
  * cut into wave blocks).  Times every candidate plan on the device with HIP
  * events over X_t and the current window (synchronous; not for use inside a
  * graph capture), keeps the fastest for this stream (and for batches created
- * afterwards), and appends "<arch> <I1> <I2> <I3> R<r> H<h> ns<n> loss<l> =
- * <plan>" to the text file cache_path (NULL: no cache).  A cache hit skips the
+ * afterwards), and appends "<key> = <plan>" to the text file cache_path
+ * (NULL: no cache), where the key is the shape bucket "<arch> loss<l>
+ * rt<16|32> nh<h-tiles> dma<0|1> pairs2^<floor(log2(I1 I2))>
+ * i3x64:<ceil(I3/64)>".  A cache hit (a valid plan for the bucket) skips the
  * timing.  Results are identical for every plan up to summation order.
  * *chosen (may be NULL) receives the plan.  Dense FP32 streams only. */
 gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_path, int32_t* chosen);
@@ -391,9 +393,23 @@ typedef struct {
   void* g_s;            /* device R, or NULL                          */
 } gcp_batch_io;
 
+/* Autotuning of a set of streams before they are batched (call it before
+ * gcp_batch_workspace_size): for each shape bucket present (see
+ * gcp_autotune), the stream with the most window entries is tuned over
+ * io[i].X_t, or the bucket's plan is read from cache_path, and every stream
+ * of the bucket takes that plan.  *buckets (may be NULL) receives the
+ * number of buckets.  Synchronous. */
+gcp_status gcp_batch_autotune(gcp_stream* const* streams, const gcp_batch_io* io, int32_t n,
+                              const char* cache_path, int32_t* buckets);
+
 gcp_status gcp_batch_workspace_size(gcp_stream* const* streams, int32_t n, size_t* bytes);
 
-/* Builds the batch (synchronous: uploads descriptors and state). */
+/* Builds the batch (synchronous: uploads descriptors and state).  Each
+ * gradient call runs one persistent launch per tile build present (loss,
+ * rank tile, h-tiles, copy width) over that build's work items; the launches
+ * go to up to four HIP streams (hip_stream and three the batch creates and
+ * destroys), forked from and joined back into hip_stream with events, so a
+ * graph captured on hip_stream holds them as parallel branches. */
 gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, int32_t n, void* workspace,
                             size_t ws_bytes, hipStream_t hip_stream, gcp_batch** out);
 

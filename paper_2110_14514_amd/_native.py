@@ -91,6 +91,8 @@ SIGNATURES = {
     "gcp_stream_sync": (c_int32, [c_void_p]),
     "gcp_stream_destroy": (c_int32, [c_void_p]),
     "gcp_autotune": (c_int32, [c_void_p, POINTER(GcpSlice), c_char_p, POINTER(c_int32)]),
+    "gcp_batch_autotune": (c_int32, [POINTER(c_void_p), POINTER(GcpBatchIO), c_int32, c_char_p,
+                                     POINTER(c_int32)]),
     "gcp_batch_workspace_size": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
     "gcp_batch_create": (c_int32, [POINTER(c_void_p), POINTER(GcpBatchIO), c_int32, c_void_p,
                                    c_size_t, c_void_p, POINTER(c_void_p)]),

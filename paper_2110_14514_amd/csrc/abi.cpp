@@ -13,6 +13,7 @@
 #include <new>
 #include <utility>
 #include <vector>
+#include <string>
 #include <limits>
 
 #include "solvers.hpp"
@@ -1157,6 +1158,24 @@ bool cache_lookup(const char* path, const char* key, int* value) {
   return found;
 }
 
+bool is_plan_target(int v) {
+  for (int i = 0; i < kNumPlanTargets; ++i)
+    if (kPlanTargets[i] == v) return true;
+  return false;
+}
+
+// Shape bucket of the tuned work plan: the tile build (loss, rank tile,
+// h-tiles, copy width), the (i1, i2) pair count by powers of two and I3 by
+// 64-entry groups.
+void tune_key(char* key, size_t n, const char* arch, const gcp_stream* s) {
+  const long pairs = (long)s->dims[0] * s->dims[1];
+  int lp = 0;
+  while ((1L << (lp + 1)) <= pairs) ++lp;
+  const int ns = 1 + s->nwin;
+  snprintf(key, n, "%s loss%d rt%d nh%d dma%d pairs2^%d i3x64:%d", arch, s->p.loss, s->p.rank > 16 ? 32 : 16,
+           (ns + 15) / 16, s->dims[2] % 4 == 0 ? 1 : 0, lp, (s->dims[2] + 63) / 64);
+}
+
 }  // namespace
 
 extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_path, int32_t* chosen) {
@@ -1168,10 +1187,9 @@ extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const ch
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return GCP_E_DEVICE;
   char key[400];
-  snprintf(key, sizeof key, "%s %d %d %d R%d H%d ns%d loss%d", prop.gcnArchName, s->dims[0], s->dims[1],
-           s->dims[2], s->p.rank, s->p.window, 1 + s->nwin, s->p.loss);
+  tune_key(key, sizeof key, prop.gcnArchName, s);
   int best = 0;
-  if (cache_lookup(cache_path, key, &best)) {
+  if (cache_lookup(cache_path, key, &best) && is_plan_target(best)) {
     s->plan_target = best;
     if (chosen) *chosen = best;
     return GCP_OK;
@@ -1224,6 +1242,48 @@ extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const ch
   return GCP_OK;
 }
 
+// Per-bucket autotuning for a set of streams about to be batched: the
+// largest stream (by window entries) of each shape bucket is tuned (or read
+// from the cache) and every stream of the bucket takes its plan.
+extern "C" gcp_status gcp_batch_autotune(gcp_stream* const* streams, const gcp_batch_io* io, int32_t n,
+                                         const char* cache_path, int32_t* buckets) {
+  if (!streams || !io || n < 1) return GCP_E_ARG;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return GCP_E_DEVICE;
+  std::vector<std::string> keys(n);
+  for (int i = 0; i < n; ++i) {
+    if (!streams[i] || !io[i].X_t) return GCP_E_ARG;
+    char key[400];
+    tune_key(key, sizeof key, prop.gcnArchName, streams[i]);
+    keys[i] = key;
+  }
+  int nb = 0;
+  std::vector<char> done(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    int rep = i;
+    auto size = [&](int k) { return (double)streams[k]->omega * (1 + streams[k]->nwin); };
+    for (int k = i; k < n; ++k)
+      if (keys[k] == keys[i] && size(k) > size(rep)) rep = k;
+    gcp_slice x;
+    memset(&x, 0, sizeof x);
+    x.kind = GCP_SLICE_DENSE;
+    x.vals = io[rep].X_t;
+    int32_t plan = 0;
+    gcp_status st = gcp_autotune(streams[rep], &x, cache_path, &plan);
+    if (st != GCP_OK) return st;
+    for (int k = i; k < n; ++k)
+      if (keys[k] == keys[i]) {
+        streams[k]->plan_target = plan;
+        done[k] = 1;
+      }
+    ++nb;
+  }
+  if (buckets) *buckets = nb;
+  return GCP_OK;
+}
+
 // --------------------------------------------------------------- batching
 struct gcp_batch {
   std::vector<gcp_stream*> streams;
@@ -1244,6 +1304,21 @@ struct BatchLayout {
   std::vector<size_t> part_off;
   std::vector<MfmaPlan> plans;
 };
+
+// The batch's own lane streams and fork/join events (lane 0 is the caller's).
+void batch_release_lanes(BatchRun& r) {
+  for (int l = 1; l < kBatchLanes; ++l) {
+    if (r.lane[l]) {
+      hipStreamSynchronize(r.lane[l]);
+      hipStreamDestroy(r.lane[l]);
+    }
+    if (r.join[l]) hipEventDestroy(r.join[l]);
+    r.lane[l] = nullptr;
+    r.join[l] = nullptr;
+  }
+  if (r.fork) hipEventDestroy(r.fork);
+  r.fork = nullptr;
+}
 
 size_t mfma_part_bytes(const MfmaPlan& m, int I1, int I2, int I3, int R) {
   size_t b = 0;
@@ -1446,15 +1521,51 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   r.nfac = nfac;
   r.cpystart = reinterpret_cast<const int64_t*>(ws + L.cpystart);
   r.ncpy = ncpy;
+  // variants present, most expensive first, each given to the lane (HIP
+  // stream) with the least work so far
+  std::vector<std::pair<double, int>> vcost;
   for (int v = 0; v < kBatchVariants; ++v) {
     r.vbegin[v] = vbegin[v];
     r.vend[v] = vend[v];
+    r.vlane[v] = 0;
     // the rank-16 single-tile variant fits two workgroups per compute unit
     const int per_cu = batch_variant_r16(v) ? 2 : 1;
     r.vgrid[v] = std::max(1, std::min(per_cu * cus, vend[v] - vbegin[v]));
+    if (vend[v] > vbegin[v]) vcost.push_back({0.0, v});
   }
+  for (auto& pr : order)
+    for (auto& vc : vcost)
+      if (vc.second == var[pr.second]) vc.first += pr.first * L.plans[pr.second].nwg;
+  std::sort(vcost.begin(), vcost.end(), [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+    return x.first != y.first ? x.first > y.first : x.second < y.second;
+  });
+  r.nvar = (int)vcost.size();
+  r.nlanes = std::max(1, std::min(r.nvar, kBatchLanes));
+  double lane_load[kBatchLanes] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < r.nvar; ++i) {
+    r.vorder[i] = vcost[i].second;
+    int best = 0;
+    for (int l = 1; l < r.nlanes; ++l)
+      if (lane_load[l] < lane_load[best]) best = l;
+    r.vlane[vcost[i].second] = best;
+    lane_load[best] += vcost[i].first;
+  }
+  r.lane[0] = hip_stream;
+  for (int l = 1; l < kBatchLanes; ++l) r.lane[l] = nullptr;
+  r.fork = nullptr;
+  for (int l = 0; l < kBatchLanes; ++l) r.join[l] = nullptr;
+  bool lanes_ok = hipEventCreateWithFlags(&r.fork, hipEventDisableTiming) == hipSuccess;
+  for (int l = 1; l < r.nlanes && lanes_ok; ++l)
+    lanes_ok = hipStreamCreateWithFlags(&r.lane[l], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&r.join[l], hipEventDisableTiming) == hipSuccess;
   r.status = b->status;
   r.stream = hip_stream;
+  if (!lanes_ok) {
+    b->run_out = r;
+    batch_release_lanes(b->run_out);
+    delete b;
+    return GCP_E_DEVICE;
+  }
   b->run_out = r;
   b->run_step = r;
   b->run_step.desc = reinterpret_cast<const BatchDesc*>(ws + L.desc_step);
@@ -1531,6 +1642,7 @@ gcp_status gcp_batch_sync_streams(gcp_batch* b) {
 gcp_status gcp_batch_destroy(gcp_batch* b) {
   if (!b) return GCP_E_ARG;
   hipStreamSynchronize(b->st);
+  batch_release_lanes(b->run_out);
   delete b;
   return GCP_OK;
 }

@@ -248,9 +248,9 @@ hipError_t dense_mfma_launch_bernoulli_odds(const DenseCall& c, const MfmaPlan& 
 hipError_t dense_mfma_launch_bernoulli(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                                        float* gsp, float* lossp);
 struct BatchRun;
-void batch_launch_gaussian(const BatchRun& b, int v, int want);
-void batch_launch_poisson(const BatchRun& b, int v, int want);
-void batch_launch_bernoulli(const BatchRun& b, int v, int want);
+void batch_launch_gaussian(const BatchRun& b, int v, int want, hipStream_t st);
+void batch_launch_poisson(const BatchRun& b, int v, int want, hipStream_t st);
+void batch_launch_bernoulli(const BatchRun& b, int v, int want, hipStream_t st);
 
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t dense_fused_run(const DenseCall& c);
@@ -299,6 +299,7 @@ inline bool dma16_ok(int I3) { return I3 % 4 == 0 && I3 < (1 << 29); }
 // loss * 8 + (R > 16) * 4 + (window + 1 > 16) * 2 + dma16_ok(I3).
 constexpr int kBatchVariants = 24;
 
+constexpr int kBatchLanes = 4;   // HIP streams the variant launches are spread over
 struct BatchRun {
   const BatchDesc* desc;
   BatchState* state;
@@ -306,6 +307,11 @@ struct BatchRun {
   int nitems;
   int vbegin[kBatchVariants], vend[kBatchVariants];  // each variant's items
   int vgrid[kBatchVariants];                         // persistent workgroups per variant
+  int vorder[kBatchVariants];  // the variants present, most expensive first
+  int vlane[kBatchVariants];   // lane (HIP stream) of each variant
+  int nvar, nlanes;
+  hipStream_t lane[kBatchLanes];   // lane 0 is `stream`; the others belong to the batch
+  hipEvent_t fork, join[kBatchLanes];
   int* counter;             // kBatchVariants work counters
   int nstreams;
   const int64_t* outstart;

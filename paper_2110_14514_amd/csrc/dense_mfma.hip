@@ -243,18 +243,35 @@ int batch_variant(int loss, int R, int H, int I3) {
 bool batch_variant_r16(int v) { return (v & 6) == 0; }
 
 hipError_t batch_grad_run(const BatchRun& b, int want) {
-  // one persistent launch per variant present, each over its own slice of
-  // the work list
-  for (int v = 0; v < kBatchVariants; ++v) {
-    if (b.vend[v] <= b.vbegin[v]) continue;
-    switch (v >> 3) {
-      case 0: batch_launch_gaussian(b, v, want); break;
-      case 1: batch_launch_poisson(b, v, want); break;
-      default: batch_launch_bernoulli(b, v, want); break;
-    }
-    hipError_t e = hipGetLastError();
+  // One persistent launch per variant present, each over its own slice of
+  // the work list.  The launches are spread over the batch's lanes (HIP
+  // streams forked from and joined back into `stream` through events, so a
+  // graph capture of `stream` records them as parallel branches): while one
+  // variant's workgroups drain at the end of its list, the compute units
+  // they free take the next variant's workgroups instead of idling.
+  hipError_t e = hipSuccess;
+  const int nl = b.nlanes;
+  if (nl > 1) {
+    e = hipEventRecord(b.fork, b.stream);
+    for (int l = 1; l < nl && e == hipSuccess; ++l) e = hipStreamWaitEvent(b.lane[l], b.fork, 0);
     if (e != hipSuccess) return e;
   }
+  for (int i = 0; i < b.nvar; ++i) {
+    const int v = b.vorder[i];
+    const hipStream_t st = b.vlane[v] == 0 ? b.stream : b.lane[b.vlane[v]];
+    switch (v >> 3) {
+      case 0: batch_launch_gaussian(b, v, want, st); break;
+      case 1: batch_launch_poisson(b, v, want, st); break;
+      default: batch_launch_bernoulli(b, v, want, st); break;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int l = 1; l < nl && e == hipSuccess; ++l) {
+    e = hipEventRecord(b.join[l], b.lane[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b.stream, b.join[l], 0);
+  }
+  if (e != hipSuccess) return e;
   const int nG = (int)((b.nout + kRedOut - 1) / kRedOut);
   hipLaunchKernelGGL(batch_reduce_kernel, dim3(nG + b.nstreams), dim3(256), 0, b.stream, b.desc, b.nstreams,
                      b.outstart, b.nout, nG, b.counter, want, b.status);

@@ -8,6 +8,6 @@ hipError_t dense_mfma_launch_bernoulli(const DenseCall& c, const MfmaPlan& p, fl
   return by_rank<kBernoulliLogit>(c, p, G1p, G2p, G3p, gsp, lossp);
 }
 
-void batch_launch_bernoulli(const BatchRun& b, int v, int want) { launch_batch_loss<kBernoulliLogit>(b, v, want); }
+void batch_launch_bernoulli(const BatchRun& b, int v, int want, hipStream_t st) { launch_batch_loss<kBernoulliLogit>(b, v, want, st); }
 
 }  // namespace gcp

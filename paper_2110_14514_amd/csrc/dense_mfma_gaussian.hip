@@ -13,6 +13,6 @@ hipError_t dense_mfma_launch_gaussian_id(const DenseCall& c, const MfmaPlan& p, 
   return by_rank<kGaussianId>(c, p, G1p, G2p, G3p, gsp, lossp);
 }
 
-void batch_launch_gaussian(const BatchRun& b, int v, int want) { launch_batch_loss<kGaussian>(b, v, want); }
+void batch_launch_gaussian(const BatchRun& b, int v, int want, hipStream_t st) { launch_batch_loss<kGaussian>(b, v, want, st); }
 
 }  // namespace gcp

@@ -8,6 +8,6 @@ hipError_t dense_mfma_launch_poisson(const DenseCall& c, const MfmaPlan& p, floa
   return by_rank<kPoissonLog>(c, p, G1p, G2p, G3p, gsp, lossp);
 }
 
-void batch_launch_poisson(const BatchRun& b, int v, int want) { launch_batch_loss<kPoissonLog>(b, v, want); }
+void batch_launch_poisson(const BatchRun& b, int v, int want, hipStream_t st) { launch_batch_loss<kPoissonLog>(b, v, want, st); }
 
 }  // namespace gcp

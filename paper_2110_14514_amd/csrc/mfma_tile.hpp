@@ -1070,28 +1070,28 @@ hipError_t by_rank(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p
 
 
 template <int LOSS, int RT, int NH, bool DMA16>
-void launch_batch_variant(const BatchRun& b, int v, int want) {
+void launch_batch_variant(const BatchRun& b, int v, int want, hipStream_t st) {
   const dim3 grid((unsigned)b.vgrid[v]);
   if constexpr (RT == 16 && NH == 1)
-    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS, DMA16>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS, DMA16>), grid, dim3(kThreads), 0, st, b.desc, b.state,
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
   else
-    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH, DMA16>), grid, dim3(kThreads), 0, b.stream, b.desc, b.state,
+    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH, DMA16>), grid, dim3(kThreads), 0, st, b.desc, b.state,
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
 }
 
 // variant v = loss * 8 + (R > 16) * 4 + (two h-tiles) * 2 + dma16_ok(I3)
 template <int LOSS>
-void launch_batch_loss(const BatchRun& b, int v, int want) {
+void launch_batch_loss(const BatchRun& b, int v, int want, hipStream_t st) {
   switch (v & 7) {
-    case 0: launch_batch_variant<LOSS, 16, 1, false>(b, v, want); break;
-    case 1: launch_batch_variant<LOSS, 16, 1, true>(b, v, want); break;
-    case 2: launch_batch_variant<LOSS, 16, 2, false>(b, v, want); break;
-    case 3: launch_batch_variant<LOSS, 16, 2, true>(b, v, want); break;
-    case 4: launch_batch_variant<LOSS, 32, 1, false>(b, v, want); break;
-    case 5: launch_batch_variant<LOSS, 32, 1, true>(b, v, want); break;
-    case 6: launch_batch_variant<LOSS, 32, 2, false>(b, v, want); break;
-    default: launch_batch_variant<LOSS, 32, 2, true>(b, v, want); break;
+    case 0: launch_batch_variant<LOSS, 16, 1, false>(b, v, want, st); break;
+    case 1: launch_batch_variant<LOSS, 16, 1, true>(b, v, want, st); break;
+    case 2: launch_batch_variant<LOSS, 16, 2, false>(b, v, want, st); break;
+    case 3: launch_batch_variant<LOSS, 16, 2, true>(b, v, want, st); break;
+    case 4: launch_batch_variant<LOSS, 32, 1, false>(b, v, want, st); break;
+    case 5: launch_batch_variant<LOSS, 32, 1, true>(b, v, want, st); break;
+    case 6: launch_batch_variant<LOSS, 32, 2, false>(b, v, want, st); break;
+    default: launch_batch_variant<LOSS, 32, 2, true>(b, v, want, st); break;
   }
 }
 

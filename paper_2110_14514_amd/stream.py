@@ -301,7 +301,8 @@ class Batch:
     and can be captured in a torch.cuda.CUDAGraph on that stream."""
 
     def __init__(self, streams: Sequence[Stream], X_t: Sequence[torch.Tensor],
-                 s_t: Sequence[torch.Tensor], outputs=None):
+                 s_t: Sequence[torch.Tensor], outputs=None, autotune: bool = False,
+                 tune_cache: Optional[str] = None):
         self.lib = N.load()
         self.streams = list(streams)
         n = len(self.streams)
@@ -323,6 +324,15 @@ class Batch:
             for k in range(3):
                 io[i].G[k] = G[k].data_ptr()
             io[i].g_s = g_s.data_ptr()
+        self.buckets = 0
+        if autotune:
+            # one tuning (or cache read) per shape bucket, before the partial
+            # buffers are sized for the chosen plans
+            nb = c_int32(0)
+            torch.cuda.synchronize(dev)
+            N.check(self.lib.gcp_batch_autotune(hs, io, n, tune_cache.encode() if tune_cache else None,
+                                                byref(nb)), "gcp_batch_autotune")
+            self.buckets = nb.value
         nbytes = c_size_t(0)
         N.check(self.lib.gcp_batch_workspace_size(hs, n, byref(nbytes)), "gcp_batch_workspace_size")
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)

@@ -159,3 +159,33 @@ def test_batch_solve_st_matches_streams_and_oracle():
         pp = p.promoted()
         assert rel_err(Sb[i].double().cpu().numpy(), ls_temporal(pp.X_t, pp.A, p.mu)) <= TOL, i
     assert n_gauss >= 2
+
+
+def test_batch_autotune_per_bucket_matches_oracle(tmp_path):
+    """gcp_batch_autotune tunes one stream per shape bucket and gives the
+    plan to the bucket's other streams; the batch built on the tuned plans
+    (launches spread over its lanes) still matches the oracle, and a second
+    tuning reads every bucket from the cache."""
+    import torch
+    from paper_2110_14514_amd import Batch
+    print("case: batch autotune", flush=True)
+    probs = _problems() + [gi.random_dense((22, 18, 70), 16, 4, "gaussian", seed=41, lam=0.05, mu=0.1)]
+    devs, streams = _make(probs)
+    cache = tmp_path / "tune.txt"
+    b = Batch(streams, [d["X_t"].clone() for d in devs], [d["s_t"].clone() for d in devs],
+              autotune=True, tune_cache=str(cache))
+    assert 1 <= b.buckets < len(probs)          # the two rank-16 Gaussian streams share a bucket
+    lines = cache.read_text().splitlines()
+    assert len(lines) == b.buckets
+    outs = b.loss_grad()
+    torch.cuda.synchronize()
+    assert b.sync_streams() == 0
+    for i, p in enumerate(probs):
+        bl, bG, bg = outs[i]
+        got = (float(bl.item()), [g.double().cpu().numpy() for g in bG], bg.double().cpu().numpy())
+        errs = compare(p, got, og)
+        assert max(errs.values()) <= TOL, (i, errs)
+    devs2, streams2 = _make(probs)
+    b2 = Batch(streams2, [d["X_t"].clone() for d in devs2], [d["s_t"].clone() for d in devs2],
+               autotune=True, tune_cache=str(cache))
+    assert b2.buckets == b.buckets and cache.read_text().splitlines() == lines

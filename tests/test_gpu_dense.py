@@ -211,11 +211,15 @@ def test_stream_steps_match_oracle():
 
 
 def _tune_key(st, prob, ns):
+    """The autotuner's shape bucket: tile build, pair count by powers of two,
+    I3 by 64-entry groups."""
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     loss_id = {"gaussian": 0, "poisson_log": 1, "bernoulli_logit": 2}[prob.loss]
     d = prob.dims
-    return f"{arch} {d[0]} {d[1]} {d[2]} R{prob.rank} H{len(prob.X_hist)} ns{ns} loss{loss_id}"
+    lp = (d[0] * d[1]).bit_length() - 1
+    return (f"{arch} loss{loss_id} rt{32 if prob.rank > 16 else 16} nh{(ns + 15) // 16} "
+            f"dma{1 if d[2] % 4 == 0 else 0} pairs2^{lp} i3x64:{(d[2] + 63) // 64}")
 
 
 @pytest.mark.parametrize("target", [1024, 2048, 4096, 8192, 16384])
@@ -251,3 +255,12 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
     st2 = make_stream(prob, dev)
     assert st2.autotune(dev["X_t"], str(cache)) == chosen
     assert cache.read_text() == text      # a hit appends nothing
+    # a stream of another shape in the same bucket takes the cached plan
+    prob3 = gi.random_dense((60, 70, 60), 16, 5, "gaussian", seed=33)
+    dev3 = to_device(prob3)
+    st3 = make_stream(prob3, dev3)
+    assert _tune_key(st3, prob3, 6) == _tune_key(st, prob, 6)
+    assert st3.autotune(dev3["X_t"], str(cache)) == chosen and cache.read_text() == text
+    # a value that is not a candidate plan is not taken from the cache
+    cache.write_text(f"{_tune_key(st, prob, 6)} = 777\n")
+    assert st2.autotune(dev["X_t"], str(cache)) in (1024, 2048, 4096, 8192, 16384)
