@@ -53,6 +53,9 @@ extern "C" {
 #define GCP_MAX_D 3
 #define GCP_MAX_RANK 64
 #define GCP_MAX_WINDOW 64
+/* Size of the library's fixed per-GPU device array used by
+ * gcp_loss_grad_static (64 MiB). */
+#define GCP_STATIC_SCRATCH_BYTES (64u << 20)
 
 typedef struct gcp_stream gcp_stream;
 
@@ -355,6 +358,36 @@ gcp_status gcp_stream_info(gcp_stream* s, int64_t* t, int32_t* n_window,
 gcp_status gcp_stream_sync(gcp_stream* s);
 
 gcp_status gcp_stream_destroy(gcp_stream* s);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the dense
+ * objective and gradients of gcp_loss_grad, with no stream handle and no
+ * workspace.  The partial sums live in a fixed device array of
+ * GCP_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; the call allocates nothing (no hipMalloc, no
+ * library allocation) and only launches kernels on hip_stream.
+ *   params: d = 3, dense, GCP_HIST_SLICES, FP32 or FP64 (dims, rank, loss,
+ *           w, theta, lambda, mu and the kernel flags are used; no plain
+ *           scratch or Gaussian-identity flag).
+ *   X_t: dense slice (device, I1*I2*I3 row-major, 16-byte aligned).
+ *   X_hist: device, n_hist slices of I1*I2*I3 values one after another
+ *           (16-byte aligned; may be NULL when n_hist = 0), 0 <= n_hist <=
+ *           params->window; s_hist: device n_hist x R weights; t_hist:
+ *           host time stamps, each below t; t: the current time index, so
+ *           slice h carries w theta^(t - t_hist[h]).
+ *   A, s_t, want, loss, G, g_s: as for gcp_loss_grad (device pointers;
+ *           outputs are overwritten).
+ * Returns GCP_E_WORKSPACE when the partial sums of this shape do not fit
+ * the array, the argument errors of gcp_loss_grad otherwise.  No
+ * status word is reported: a non-finite result shows in the outputs.  Every
+ * call on one GPU uses the same array, which keeps the last call's partial
+ * sums (each call overwrites every slot it reads), so calls that overlap on
+ * one GPU (on different HIP streams, or from different host threads) race
+ * and must be serialised by the caller. */
+gcp_status gcp_loss_grad_static(const gcp_params* params, const gcp_slice* X_t, int32_t n_hist,
+                                const void* X_hist, const void* s_hist, const int64_t* t_hist, int64_t t,
+                                const void* const* A, const void* s_t, uint32_t want, void* loss,
+                                void* const* G, void* g_s, hipStream_t hip_stream);
 
 /* Autotuner for the matrix-core work plan (how the slice's (i1,i2) pairs are
  * cut into wave blocks).  Times every candidate plan on the device with HIP

@@ -13,6 +13,7 @@
 #include <new>
 #include <utility>
 #include <vector>
+#include <mutex>
 #include <string>
 #include <limits>
 
@@ -1240,6 +1241,112 @@ extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const ch
     }
   }
   return GCP_OK;
+}
+
+// ------------------------------------------------- allocation-free entry
+namespace {
+
+// Partial sums of gcp_loss_grad_static: one array per GPU, held until the
+// process ends.  Host code never hands `scratch` itself to a kernel (its
+// host-side name is not a device address); each device's address is taken
+// once with hipGetSymbolAddress while that device is current.
+__device__ __align__(256) char scratch[GCP_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mutex;
+void* g_scratch_dev[256];
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" gcp_status gcp_loss_grad_static(const gcp_params* p, const gcp_slice* X_t, int32_t n_hist,
+                                           const void* X_hist, const void* s_hist, const int64_t* t_hist,
+                                           int64_t t, const void* const* A, const void* s_t, uint32_t want,
+                                           void* loss, void* const* G, void* g_s, hipStream_t stream) {
+  gcp_status st = check_params(p);
+  if (st != GCP_OK) return st;
+  if (p->d != 3 || p->slice_kind != GCP_SLICE_DENSE || p->hist != GCP_HIST_SLICES) return GCP_E_UNSUPPORTED;
+  if (p->flags & (GCP_FLAG_PLAIN_SCRATCH | GCP_FLAG_GAUSS_IDENTITY)) return GCP_E_UNSUPPORTED;
+  if (!X_t || X_t->kind != GCP_SLICE_DENSE || !X_t->vals || !A || !A[0] || !A[1] || !A[2] || !s_t)
+    return GCP_E_ARG;
+  if (n_hist < 0 || n_hist > p->window) return GCP_E_ARG;
+  if (n_hist > 0 && (!X_hist || !s_hist || !t_hist)) return GCP_E_ARG;
+  if ((want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD)) || !(want & (GCP_WANT_LOSS | GCP_WANT_GRAD)))
+    return GCP_E_ARG;
+  if ((want & GCP_WANT_LOSS) && !loss) return GCP_E_ARG;
+  if ((want & GCP_WANT_GRAD) && (!G || !G[0] || !G[1] || !G[2] || !g_s)) return GCP_E_ARG;
+  if (!aligned16(X_t->vals) || (n_hist > 0 && !aligned16(X_hist))) return GCP_E_ALIGN;
+  for (int h = 0; h < n_hist; ++h)
+    if (t_hist[h] >= t) return GCP_E_ARG;
+  const int I1 = (int)p->dims[0], I2 = (int)p->dims[1], I3 = (int)p->dims[2], R = p->rank;
+  const size_t es = p->dtype == GCP_F64 ? 8 : 4;
+  const size_t omega = (size_t)I1 * I2 * I3;
+  // scratch: status word | partial sums | (gradient-free calls) a sink for
+  // the gradients the fused kernel always forms
+  const size_t part = dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
+  const size_t sink = (want & GCP_WANT_GRAD) ? 0 : align_up((size_t)(I1 + I2 + I3 + 1) * R * es, 256);
+  if (256 + align_up(part, 256) + sink > (size_t)GCP_STATIC_SCRATCH_BYTES) return GCP_E_WORKSPACE;
+  void* vbase = nullptr;
+  if (scratch_address(&vbase) != hipSuccess) return GCP_E_DEVICE;
+  char* base = static_cast<char*>(vbase);
+  DenseCall c;
+  memset(&c, 0, sizeof(c));
+  c.I1 = I1;
+  c.I2 = I2;
+  c.I3 = I3;
+  c.R = R;
+  c.loss = p->loss;
+  c.dtype = p->dtype;
+  c.lam = p->lambda;
+  c.mu = p->mu;
+  c.status = reinterpret_cast<int*>(base);   // written by kernels, never read back
+  c.part = base + 256;
+  c.part_bytes = align_up(part, 256);
+  c.stream = stream;
+  c.kernel = (p->flags & GCP_FLAG_KERNEL_VALU) ? 1 : ((p->flags & GCP_FLAG_KERNEL_MFMA) ? 2 : 0);
+  c.want = want;
+  c.X[0] = X_t->vals;
+  c.S[0] = s_t;
+  c.c[0] = 1.0;
+  // window: n_hist slices one after another, rows of pitch I3
+  c.ring = X_hist;
+  c.ring_pitch = (size_t)I3;
+  c.ring_stride = omega;
+  c.shist = s_hist;
+  c.omega = omega;
+  for (int h = 0; h < n_hist; ++h) {
+    c.X[h + 1] = static_cast<const char*>(X_hist) + (size_t)h * omega * es;
+    c.S[h + 1] = static_cast<const char*>(s_hist) + (size_t)h * R * es;
+    c.c[h + 1] = p->w * pow(p->theta, (double)(t - t_hist[h]));
+  }
+  c.ns = n_hist + 1;
+  char* sk = base + 256 + align_up(part, 256);
+  size_t off = 0;
+  for (int k = 0; k < 3; ++k) {
+    c.A[k] = A[k];
+    if (want & GCP_WANT_GRAD) {
+      c.G[k] = G[k];
+    } else {
+      c.G[k] = sk + off;
+      off += (size_t)p->dims[k] * R * es;
+    }
+  }
+  c.gs = (want & GCP_WANT_GRAD) ? g_s : static_cast<void*>(sk + off);
+  c.loss_out = (want & GCP_WANT_LOSS) ? loss : nullptr;
+  return hip_status(dense_fused_run(c));
 }
 
 // Per-bucket autotuning for a set of streams about to be batched: the

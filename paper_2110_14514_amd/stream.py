@@ -275,6 +275,46 @@ class Stream:
             pass
 
 
+def loss_grad_static(dims, rank: int, loss: str, X_t: torch.Tensor, A: Sequence[torch.Tensor],
+                     s_t: torch.Tensor, X_hist: Optional[torch.Tensor] = None,
+                     s_hist: Optional[torch.Tensor] = None, t_hist: Sequence[int] = (),
+                     t: Optional[int] = None, *, w=1.0, theta=1.0, lam=0.0, mu=0.0,
+                     kernel: str = "auto", want_loss: bool = True, want_grad: bool = True, out=None):
+    """gcp_loss_grad_static: the dense objective and gradients with no stream
+    handle or workspace (the partial sums use the library's fixed per-GPU
+    array).  X_hist: contiguous [n_hist, I1, I2, I3] window slices (or None);
+    t defaults to max(t_hist) + 1.  Output tensors are created unless `out`
+    = (loss, [G1, G2, G3], g_s) is given, which allocates nothing."""
+    lib = N.load()
+    n_hist = 0 if X_hist is None else int(X_hist.shape[0])
+    th = list(t_hist)
+    if len(th) != n_hist:
+        raise ValueError("t_hist needs one time stamp per window slice")
+    if t is None:
+        t = (max(th) + 1) if th else 1
+    params = make_params(dims, rank, n_hist, loss, w=w, theta=theta, lam=lam, mu=mu, dtype=X_t.dtype,
+                         kernel=kernel)
+    dev = X_t.device
+    if out is None:
+        out = (torch.empty(1, dtype=X_t.dtype, device=dev),
+               [torch.empty(int(n), int(rank), dtype=X_t.dtype, device=dev) for n in dims],
+               torch.empty(int(rank), dtype=X_t.dtype, device=dev))
+    loss_t, G, g_s = out
+    sl = _dense_slice(X_t)
+    want = (N.WANT_LOSS if want_loss else 0) | (N.WANT_GRAD if want_grad else 0)
+    tarr = (c_int64 * max(1, n_hist))(*th)
+    xh = None if X_hist is None else X_hist
+    if xh is not None and not xh.is_contiguous():
+        raise ValueError("X_hist must be contiguous")
+    sh = None if s_hist is None else s_hist.contiguous()
+    N.check(lib.gcp_loss_grad_static(byref(params), byref(sl), n_hist, _ptr(xh), _ptr(sh), tarr, int(t),
+                                     _ptr_array([a.contiguous() for a in A], 3), _ptr(s_t.contiguous()), want,
+                                     _ptr(loss_t), _ptr_array(G, 3), _ptr(g_s),
+                                     c_void_p(torch.cuda.current_stream(dev).cuda_stream)),
+            "gcp_loss_grad_static")
+    return loss_t, G, g_s
+
+
 # names of the C calls, for callers that want them one-to-one
 def gcp_stream_init(*a, **kw) -> Stream:
     return Stream(*a, **kw)

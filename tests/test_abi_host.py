@@ -186,3 +186,27 @@ def test_null_handle_calls(lib):
     assert lib.gcp_stream_sync(None) == N.E_ARG
     assert lib.gcp_stream_destroy(None) == N.E_ARG
     assert lib.gcp_status_string(N.E_NUMERIC).startswith(b"non-finite")
+
+
+def test_static_entry_rejects_before_any_launch(lib):
+    """gcp_loss_grad_static validates on the host: arguments, the window,
+    alignment and the size of its fixed scratch array (no device access)."""
+    from paper_2110_14514_amd import _native as N
+    p = _params(lib)
+    fake = ctypes.c_void_p(1 << 20)                      # aligned, never dereferenced
+    sl = N.GcpSlice(N.SLICE_DENSE, 0, fake.value, None, 0)
+    A = (ctypes.c_void_p * 3)(fake.value, fake.value, fake.value)
+    G = (ctypes.c_void_p * 3)(fake.value, fake.value, fake.value)
+    th = (ctypes.c_int64 * 4)(1, 2, 3, 4)
+
+    def call(params, n_hist=0, t=1, want=3, x=sl, xh=None):
+        return lib.gcp_loss_grad_static(ctypes.byref(params), ctypes.byref(x), n_hist, xh, fake, th, t, A, fake,
+                                        want, fake, G, fake, None)
+    assert call(p, n_hist=4) == N.E_ARG                  # window larger than params->window (3)
+    assert call(p, n_hist=2, xh=fake, t=2) == N.E_ARG    # a time stamp not below t
+    assert call(p, want=0) == N.E_ARG
+    assert call(p, x=N.GcpSlice(N.SLICE_DENSE, 0, (1 << 20) + 4, None, 0)) == N.E_ALIGN
+    huge = _params(lib)
+    huge.dims[0], huge.dims[1], huge.dims[2], huge.rank = 30000, 30000, 4096, 64
+    assert call(huge) == N.E_WORKSPACE
+    assert call(_params(lib, hist=1)) == N.E_UNSUPPORTED
