@@ -27,9 +27,19 @@ FLAGS = [
 SOURCES = ["abi.cpp", "dense_fused.hip", "dense_plain.hip", "solve.hip", "adam.hip"]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hs.append(os.path.join(os.path.dirname(HERE), "include", "gcpstream.h"))
+    return max(os.path.getmtime(h) for h in hs if os.path.exists(h))
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJ, src + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(path) and t > _headers_mtime():
+            return obj
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
     cmd = [HIPCC, *FLAGS, *lang, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -38,14 +48,16 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compiles every source (incremental=True: only sources newer than their
+    object or than any header) and links the library."""
     os.makedirs(OBJ, exist_ok=True)
     extra = sorted(f for f in os.listdir(CSRC)
                    if f.endswith(".hip") and f not in SOURCES)
     srcs = SOURCES + extra
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,5 +70,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

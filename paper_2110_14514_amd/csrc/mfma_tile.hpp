@@ -82,10 +82,22 @@ constexpr int kStages = 3;
 __host__ __device__ constexpr int stage_floats(int NH) { return 16 * NH * 32 + 64; }
 __host__ __device__ constexpr int ring_floats(int NH) { return NH <= 2 ? kWaves * kStages * stage_floats(NH) : 0; }
 
-// LDS floats used by one workgroup at rank tile RT and NH h-tiles
+// LDS floats used by one workgroup at rank tile RT and NH h-tiles: the
+// mode-3 combine rows (NH > 2; with NH <= 2 the idle staging rings serve),
+// the temporal-gradient rows and the objective partials of the waves
 __host__ __device__ constexpr int lds_floats(int RT, int NH) {
-  return 64 * (RT + 1) + kWaves * RT + kWaves;
+  return (NH > 2 ? 64 * (RT + 1) : 0) + kWaves * RT + kWaves;
 }
+__host__ __device__ constexpr int lds_gs_offset(int RT, int NH) { return NH > 2 ? 64 * (RT + 1) : 0; }
+// The group's A3 values in GEMM2's transposed output layout, shared by the
+// workgroup's waves: [tile u][column j][row 4g + r], rows padded to 20
+// floats so that a 16-byte read by the 16 lanes of a row group touches
+// every bank once.
+constexpr int kA3TPitch = 20;
+// ... and in GEMM1's operand layout: [tile u][column n][j], rows padded to
+// RT + 4 floats for the same reason.
+__host__ __device__ constexpr int a3g_pitch(int RT) { return RT + 4; }
+__host__ __device__ constexpr int a3t_floats(int RT) { return 2 * RT * kA3TPitch + 2 * 16 * a3g_pitch(RT); }
 
 // Wait until at most n vector-memory operations of this wave are in flight
 // (n is wave-uniform; the immediate must be a constant).  n >= 40 waits for
@@ -235,6 +247,21 @@ __device__ __forceinline__ void rs_step(float (&v)[NT], int n) {
   }
 }
 
+// Sum of a value over the four 16-lane groups (lanes n, n+16, n+32, n+48),
+// left in every lane: a swap of the wave's halves, then of odd and even
+// lane groups (gfx950 lane-swap instructions), each followed by an add.
+// Every lane forms (v_n + v_n+32) + (v_n+16 + v_n+48).
+__device__ __forceinline__ float sum_lane_groups(float v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const float a = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(a), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+#else
+  return v;
+#endif
+}
+
 // Same result and lane mapping as row_reduce_scatter, with DPP exchanges.
 template <int NT>
 __device__ __forceinline__ float row_reduce_scatter_dpp(float (&v)[NT], int n) {
@@ -269,6 +296,11 @@ struct MLoss<kGaussian> {
     facc = fmaf(cv * yv, yv, facc);   // (m - x)^2
     return yv;
   }
+  __device__ __forceinline__ static float fr(float x, float d, float& facc) {
+    const float yv = d - x;
+    facc = fmaf(yv, yv, facc);
+    return yv;
+  }
 };
 
 template <>
@@ -278,6 +310,11 @@ struct MLoss<kPoissonLog> {
   __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
     const float e = __builtin_amdgcn_exp2f(d);
     facc = fmaf(cv, fmaf(-x, d, e * kM), facc);   // (exp(m) - x m) / ln 2
+    return e - x;
+  }
+  __device__ __forceinline__ static float fr(float x, float d, float& facc) {
+    const float e = __builtin_amdgcn_exp2f(d);
+    facc = fmaf(e, kM, fmaf(-x, d, facc));
     return e - x;
   }
 };
@@ -297,6 +334,12 @@ struct MLoss<kBernoulliLogit> {
     facc = fmaf(cv, fmaf(-x, d, fmaxf(d, 0.f) + __builtin_amdgcn_logf(1.f + e)), facc);
     return (d >= 0.f ? inv : e * inv) - x;
   }
+  __device__ __forceinline__ static float fr(float x, float d, float& facc) {
+    const float e = __builtin_amdgcn_exp2f(-fabsf(d));
+    const float inv = __builtin_amdgcn_rcpf(1.f + e);
+    facc = fmaf(-x, d, facc + (fmaxf(d, 0.f) + __builtin_amdgcn_logf(1.f + e)));
+    return (d >= 0.f ? inv : e * inv) - x;
+  }
 };
 
 template <>
@@ -314,6 +357,11 @@ struct MLoss<kPoissonId> {
     facc = fmaf(cv, fmaf(-x, __logf(me), d), facc);   // m - x log(m + eps)
     return 1.f - x * __builtin_amdgcn_rcpf(me);
   }
+  __device__ __forceinline__ static float fr(float x, float d, float& facc) {
+    const float me = d + (float)kLossEps;
+    facc = fmaf(-x, __logf(me), facc + d);
+    return 1.f - x * __builtin_amdgcn_rcpf(me);
+  }
 };
 
 template <>
@@ -325,6 +373,11 @@ struct MLoss<kBernoulliOdds> {
   __device__ __forceinline__ static float fy(float x, float d, float cv, float& facc) {
     const float me = d + (float)kLossEps;
     facc = fmaf(cv, fmaf(-x, __logf(me), __logf(d + 1.f)), facc);   // log(m + 1) - x log(m + eps)
+    return __builtin_amdgcn_rcpf(d + 1.f) - x * __builtin_amdgcn_rcpf(me);
+  }
+  __device__ __forceinline__ static float fr(float x, float d, float& facc) {
+    const float me = d + (float)kLossEps;
+    facc = fmaf(-x, __logf(me), facc + __logf(d + 1.f));
     return __builtin_amdgcn_rcpf(d + 1.f) - x * __builtin_amdgcn_rcpf(me);
   }
 };
@@ -344,7 +397,7 @@ __device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
 
 template <int LOSS, int RT, int NH, bool DMA16, int NK = 0>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
-                                          float* ring, const float* cl) {
+                                          float* ring, const float* cl, float* a3t) {
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
@@ -358,8 +411,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   float(*g1w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g1s);
   float(*g2w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g2s);
   float(*g3x)[RT + 1] = reinterpret_cast<float(*)[RT + 1]>(sm);  // SW rows used
-  float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + 64 * (RT + 1));
-  float* lsx = sm + 64 * (RT + 1) + kWaves * RT;
+  float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + lds_gs_offset(RT, NH));
+  float* lsx = sm + lds_gs_offset(RT, NH) + kWaves * RT;
 
   const int tid = threadIdx.x;
   // the wave index is uniform across the wave: keeping it scalar keeps all
@@ -387,12 +440,15 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     jc[t] = min(jt[t], R - 1);
     jm[t] = jt[t] < R ? 1.f : 0.f;
   }
-  const int jslot = [&] {
-    const int tt = n >> (4 - LOGNT);
-    return 16 * (tt >> 2) + 4 * g + (tt & 3);
-  }();
-  const int jsc = min(jslot, R - 1);
-  const float jsm = jslot < R ? 1.f : 0.f;
+  // column j = 16 mt + n of GEMM2's transposed output held by this lane
+  int jn[NM], jnc[NM];
+  float jnm[NM];
+#pragma unroll
+  for (int mt = 0; mt < NM; ++mt) {
+    jn[mt] = 16 * mt + n;
+    jnc[mt] = min(jn[mt], R - 1);
+    jnm[mt] = jn[mt] < R ? 1.f : 0.f;
+  }
 
   // weights as MFMA operands (zero outside h < ns, j < R)
   auto sval = [&](int h, int j) -> float {
@@ -477,17 +533,45 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       i3u[u] = c0 + (adj ? NU * n + u : 16 * u + n);
       vu[u] = (adj || u < nu) && i3u[u] < I3;
     }
-    float a3r[NU][NT], g3[NU][NT];
+    // A3 rows of the group in GEMM1's operand layout (entry of column n,
+    // j = jt[t]) and in GEMM2's transposed output layout (entry of column
+    // 4g + r, j = 16 mt + n); G3 accumulates in the second layout
+    float g3T[NU][NM][4];
+    // entry (offset from c0) of output row 4g + r of tile u
+    auto eT = [&](int u, int r) { return adj ? NU * (4 * g + r) + u : 16 * u + 4 * g + r; };
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const size_t row = (size_t)(vu[u] ? i3u[u] : 0) * R;
-      const float um = vu[u] ? 1.f : 0.f;
+    for (int u = 0; u < NU; ++u)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        a3r[u][t] = a.A3[row + jc[t]] * (jm[t] * um);
-        g3[u][t] = 0.f;
-      }
+      for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g3T[u][mt][r] = 0.f;
+    // The group's A3 values (zero outside the row and past R) in both
+    // layouts, written by the whole workgroup: every wave is at this group,
+    // and the previous group's last reads of the arrays came before the
+    // barrier that ended it.  Entry of column c of tile u: c0 + NU c + u
+    // (adjacent entries per lane) or c0 + 16 u + c.
+    float* a3g = a3t + 2 * RT * kA3TPitch;
+    for (int idx = tid; idx < NU * RT * 16; idx += kThreads) {
+      const int u = idx / (RT * 16), j = (idx / 16) % RT, col = idx % 16;
+      const int e = adj ? NU * col + u : 16 * u + col;
+      const bool ok = (adj || u < nu) && c0 + e < I3 && j < R;
+      const float v = ok ? a.A3[(size_t)(c0 + e) * R + j] : 0.f;
+      a3t[(u * RT + j) * kA3TPitch + col] = v;
+      a3g[(u * 16 + col) * a3g_pitch(RT) + j] = v;
     }
+    __syncthreads();
+    // GEMM1's operand values of this lane: column n of tile u, j = jt[t]
+    auto a3row = [&](int u, float (&out)[NT]) {
+#pragma unroll
+      for (int t4 = 0; t4 < NT / 4; ++t4) {
+        const f4 v = *reinterpret_cast<const f4*>(a3g + (u * 16 + n) * a3g_pitch(RT) + 16 * t4 + 4 * g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[4 * t4 + r] = v[r];
+      }
+    };
+    // every entry of the group is inside the row (no tail lanes to mask)
+    const bool allv = wide && adj;
+    float floss = 0.f;
 
     // Software pipeline over the block's pairs: the loads of pair q+1 (slice
     // values and factor rows) are issued before pair q is computed.  Loads
@@ -502,7 +586,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       // Prefetch buffers hold raw loaded values only: any arithmetic on them
       // at load time would force a wait for the loads.
       struct Buf {
-        float x[NH][4][NU], a1[NT], a2[NT], a1s, a2s;
+        float x[NH][4][NU], a1[NT], a2[NT], a1n[NM], a2n[NM];
       };
       Buf bA, bB;
       auto load_pair = [&](int q, Buf& b) {
@@ -514,8 +598,11 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           b.a1[t] = r1[jc[t]];
           b.a2[t] = r2[jc[t]];
         }
-        b.a1s = r1[jsc];
-        b.a2s = r2[jsc];
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          b.a1n[mt] = r1[jnc[mt]];
+          b.a2n[mt] = r2[jnc[mt]];
+        }
         const size_t base_x = ((size_t)i1 * I2 + i2) * I3, base_r = ((size_t)i1 * I2 + i2) * a.rp3;
 #pragma unroll
         for (int ht = 0; ht < NH; ++ht)
@@ -545,7 +632,13 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // staged factor rows are zero past R; the register-prefetch path
         // reads clamped columns and masks them here
         for (int t = 0; t < NT; ++t) W[t] = NH <= 2 ? b.a1[t] * b.a2[t] : b.a1[t] * b.a2[t] * jm[t];
-        const float a1s = NH <= 2 ? b.a1s : b.a1s * jsm, a2s = NH <= 2 ? b.a2s : b.a2s * jsm;
+        float a1n[NM], a2n[NM], Wn[NM];
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          a1n[mt] = NH <= 2 ? b.a1n[mt] : b.a1n[mt] * jnm[mt];
+          a2n[mt] = NH <= 2 ? b.a2n[mt] : b.a2n[mt] * jnm[mt];
+          Wn[mt] = a1n[mt] * a2n[mt];
+        }
 
         // GEMM1: model values for 16 h x 16 entries per (h-tile, entry tile).
         // The pair's weights W multiply whichever operand has fewer values
@@ -558,6 +651,9 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
             for (int t = 0; t < NT; ++t) Aw[ht][t] = A1op[ht][t] * W[t];
         }
+        float a3r[NU][NT];
+#pragma unroll
+        for (int u = 0; u < NUA; ++u) a3row(u, a3r[u]);
         f4 D1[NH][NU];
 #pragma unroll
         for (int ht = 0; ht < NH; ++ht)
@@ -588,22 +684,36 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // Registers holding only slices past the window are left as they
         // are: GEMM2 skips their K-steps.
         if (want_loss) {
-          float fu[NU];
+          // weighted terms summed in one register over the pairs of a row
+          // of the block; the row's sum joins the compensated lane total
+          if (allv) {
 #pragma unroll
-          for (int u = 0; u < NUA; ++u) fu[u] = 0.f;
+            for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
-          for (int ht = 0; ht < NH; ++ht)
+              for (int r = 0; r < 4; ++r) {
+                if (!reg_active<NK, NH>(ht, r, ns)) continue;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              if (!reg_active<NK, NH>(ht, r, ns)) continue;
+                for (int u = 0; u < NUA; ++u)
+                  D1[ht][u][r] = MLoss<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], cv[ht][r], floss);
+              }
+          } else {
 #pragma unroll
-              for (int u = 0; u < NUA; ++u)
-                D1[ht][u][r] = MLoss<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], cv[ht][r], fu[u]);
-            }
-          float part = 0.f;
+            for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
-          for (int u = 0; u < NUA; ++u) part += vu[u] ? fu[u] : 0.f;
-          lacc.add(part);
+              for (int r = 0; r < 4; ++r) {
+                if (!reg_active<NK, NH>(ht, r, ns)) continue;
+#pragma unroll
+                for (int u = 0; u < NUA; ++u) {
+                  float f = 0.f;
+                  D1[ht][u][r] = MLoss<LOSS>::fy(b.x[ht][r][u], D1[ht][u][r], cv[ht][r], f);
+                  floss += vu[u] ? f : 0.f;
+                }
+              }
+          }
+          if (i2l == n2 - 1) {
+            lacc.add(floss);
+            floss = 0.f;
+          }
         } else {
 #pragma unroll
           for (int ht = 0; ht < NH; ++ht)
@@ -630,10 +740,14 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           for (int t = 0; t < NT; ++t) gsacc[t] += W[t] * ps[t];
         }
 
-        // GEMM2: yhat[j][e] = sum_h (c_h S[h][j]) y[h][e]
-        float Vp[NT];
+        // GEMM2, transposed: yhat[e][j] = sum_h y[h][e] (c_h S[h][j]).  GEMM1's
+        // accumulator is the A operand (rows e, K = h) and the weights are
+        // the B operand, so register r of lane (g, n) holds entry row 4g + r
+        // and column j = 16 mt + n: the sum over the entries for V is four
+        // in-lane terms and two lane-swap steps.
+        float Vp[NM];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) Vp[t] = 0.f;
+        for (int mt = 0; mt < NM; ++mt) Vp[mt] = 0.f;
 #pragma unroll
         for (int u = 0; u < NUA; ++u) {
           if (!VEC && u >= nu) continue;
@@ -644,22 +758,25 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
               for (int t = 0; t < 4; ++t)
-                if (reg_active<NK, NH>(ht, t, ns)) acc = mfma(A2op[mt][ht][t], D1[ht][u][t], acc);
+                if (reg_active<NK, NH>(ht, t, ns)) acc = mfma(D1[ht][u][t], A2op[mt][ht][t], acc);
+            const f4 a3v = *reinterpret_cast<const f4*>(a3t + (u * RT + jn[mt]) * kA3TPitch + 4 * g);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int tt = 4 * mt + r;
-              g3[u][tt] += acc[r] * W[tt];
-              Vp[tt] += acc[r] * a3r[u][tt];
+              g3T[u][mt][r] += acc[r] * Wn[mt];
+              Vp[mt] += acc[r] * a3v[r];
             }
           }
         }
-        const float v = row_reduce_scatter_dpp<NT>(Vp, n);
         // the rows belong to this wave alone and its LDS adds complete in
         // program order, so the sums are deterministic; the adds return
         // nothing, so the wave does not wait for them
-        if ((n & ((16 / NT) - 1)) == 0 && jslot < R) {
-          lds_add(&g1w[wave][i1l][jslot], v * a2s);
-          lds_add(&g2w[wave][i2l][jslot], v * a1s);
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          const float v = sum_lane_groups(Vp[mt]);
+          if (g == 0 && jn[mt] < R) {
+            lds_add(&g1w[wave][i1l][jn[mt]], v * a2n[mt]);
+            lds_add(&g2w[wave][i2l][jn[mt]], v * a1n[mt]);
+          }
         }
       };
 
@@ -772,8 +889,11 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
               b.a2[4 * t4 + r] = v2[r];
             }
           }
-          b.a1s = fa[jslot];
-          b.a2s = fa[32 + jslot];
+#pragma unroll
+          for (int mt = 0; mt < NM; ++mt) {
+            b.a1n[mt] = fa[jn[mt]];
+            b.a2n[mt] = fa[32 + jn[mt]];
+          }
           compute(ci1, ci2, b);
           if (++ci2 == n2) {
             ci2 = 0;
@@ -824,7 +944,9 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) ring_w[(i3u[u] - c0) * RT + jt[t]] = g3[u][t];
+        for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ring_w[eT(u, r) * RT + jn[mt]] = g3T[u][mt][r];
       __syncthreads();
       for (int idx = tid; idx < SW * RT; idx += kThreads) {
         float sum = 0.f;
@@ -845,9 +967,11 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         if (wave == w) {
 #pragma unroll
           for (int u = 0; u < NU; ++u)
-            if (vu[u])
 #pragma unroll
-              for (int t = 0; t < NT; ++t) g3x[i3u[u] - c0][jt[t]] += g3[u][t];
+            for (int r = 0; r < 4; ++r)
+              if ((adj || u < nu) && c0 + eT(u, r) < I3)
+#pragma unroll
+                for (int mt = 0; mt < NM; ++mt) g3x[eT(u, r)][jn[mt]] += g3T[u][mt][r];
         }
         __syncthreads();
       }
@@ -907,9 +1031,10 @@ __device__ __forceinline__ void fused_body(const MArgs& a) {
   // write only this array
   __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
   __shared__ float cl[kMaxNs];
+  __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH, DMA16, NK>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl);
+  mfma_tile<LOSS, RT, NH, DMA16, NK>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
 }
 
 template <int LOSS, int RT, int NH, bool DMA16, int NK>
@@ -939,6 +1064,7 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
   __shared__ float sm[lds_floats(RT, NH)];
   __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
   __shared__ float cl[kMaxNs];
+  __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   __shared__ int cur;
   for (;;) {
     if (threadIdx.x == 0) cur = begin + atomicAdd(counter, 1);
@@ -975,7 +1101,7 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
       cl[h] = v;
     }
     __syncthreads();
-    mfma_tile<LOSS, RT, NH, DMA16>(ta, wg, g1s, g2s, sm, ring, cl);
+    mfma_tile<LOSS, RT, NH, DMA16>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
     __syncthreads();
   }
 }

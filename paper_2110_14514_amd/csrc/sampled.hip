@@ -518,7 +518,8 @@ __global__ void __launch_bounds__(1024) sorted_scan(ScanArgs a) {
   for (int idx = t; idx < a.ns * a.R; idx += 1024) a.Sall[idx] = a.S[idx / a.R][idx % a.R];
 }
 
-// Step 5, one launch per mode: a group of SEG lanes (lane j holds rank
+// Step 5, one launch for the three modes (each block serves one mode, its
+// blocks a contiguous range of the grid): a group of SEG lanes (lane j holds rank
 // columns j + SEG c, c < CPL) walks a run of consecutive records (reduce_run) of the mode's list, U records at a
 // time (their loads and factor-row gathers issued before any is used); the
 // row's sum stays in registers and is added to G when the run leaves the row
@@ -536,13 +537,29 @@ int reduce_run(int64_t max_rec, int nrows) {
   return (int)std::min<int64_t>(kRun, std::max<int64_t>(64, want));
 }
 
+// The three modes' lists: mode k's blocks are [first[k], first[k + 1]).
+struct ReduceModes {
+  const RowRec* srt[3];
+  const int* start[3];
+  const float* Aa[3];
+  const float* Ab[3];
+  float* G[3];
+  int nrows[3], run[3];
+  unsigned first[4];
+};
+
 template <int SEG, int CPL>
-__global__ void __launch_bounds__(256) sorted_reduce(const RowRec* __restrict__ srt, const int* __restrict__ start,
-                                                     int nrows, const float* __restrict__ Aa,
-                                                     const float* __restrict__ Ab, const float* __restrict__ Sall,
-                                                     float* __restrict__ G, int R, int run) {
+__global__ void __launch_bounds__(256) sorted_reduce(ReduceModes m, const float* __restrict__ Sall, int R) {
   constexpr int PER = 64 / SEG;
   constexpr int U = 8;
+  const int k = blockIdx.x < m.first[1] ? 0 : (blockIdx.x < m.first[2] ? 1 : 2);
+  const RowRec* __restrict__ srt = m.srt[k];
+  const int* __restrict__ start = m.start[k];
+  const float* __restrict__ Aa = m.Aa[k];
+  const float* __restrict__ Ab = m.Ab[k];
+  float* __restrict__ G = m.G[k];
+  const int nrows = m.nrows[k], run = m.run[k];
+  const unsigned blk = blockIdx.x - m.first[k];
   const int lane = threadIdx.x & 63;
   const int j = lane % SEG, sub = lane / SEG;
   int jc[CPL];
@@ -552,7 +569,7 @@ __global__ void __launch_bounds__(256) sorted_reduce(const RowRec* __restrict__ 
     jv[cc] = j + SEG * cc < R;
     jc[cc] = jv[cc] ? j + SEG * cc : 0;
   }
-  const int64_t grp = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * PER + sub;
+  const int64_t grp = ((int64_t)blk * 4 + (threadIdx.x >> 6)) * PER + sub;
   const int64_t nrec = start[nrows];
   const int64_t p0 = grp * run;
   if (p0 >= nrec) return;
@@ -736,15 +753,19 @@ SortedLayout sorted_layout(int I1, int I2, int I3, int R, int nsmax, int64_t p, 
   return L;
 }
 
+// One launch over the three modes' lists, each at most max_rec records.
 template <int SEG, int CPL>
-void launch_reduce_mode(const SampledCall& c, const RowRec* srt, const int* start, int nrows, const float* Aa,
-                        const float* Ab, const float* Sall, float* G, int64_t max_rec) {
-  const int run = reduce_run(max_rec, nrows);
-  const int64_t groups = (max_rec + run - 1) / run;
-  const int64_t blocks = (groups + 4 * (64 / SEG) - 1) / (4 * (64 / SEG));
-  if (blocks > 0)
-    hipLaunchKernelGGL((sorted_reduce<SEG, CPL>), dim3((unsigned)blocks), dim3(256), 0, c.stream, srt, start, nrows, Aa,
-                       Ab, Sall, G, c.R, run);
+void launch_reduce_modes(const SampledCall& c, ReduceModes m, const float* Sall, int64_t max_rec) {
+  unsigned b = 0;
+  for (int k = 0; k < 3; ++k) {
+    m.run[k] = reduce_run(max_rec, m.nrows[k]);
+    const int64_t groups = (max_rec + m.run[k] - 1) / m.run[k];
+    m.first[k] = b;
+    b += (unsigned)((groups + 4 * (64 / SEG) - 1) / (4 * (64 / SEG)));
+  }
+  m.first[3] = b;
+  if (b > 0)
+    hipLaunchKernelGGL((sorted_reduce<SEG, CPL>), dim3(b), dim3(256), 0, c.stream, m, Sall, c.R);
 }
 
 }  // namespace
@@ -894,19 +915,25 @@ hipError_t sampled_run(const SampledCall& c) {
       sa.R = c.R;
       hipLaunchKernelGGL(sorted_scan, dim3(1), dim3(1024), 0, c.stream, sa);
       hipLaunchKernelGGL(sorted_scatter, dim3(nchunks), dim3(1024), 0, c.stream, ca);
-      // one launch per mode; each list holds at most ns (p + q) records
+      // one launch for the three modes; each list holds at most ns (p + q) records
       const int64_t max_rec = (int64_t)c.ns * (c.p + c.q);
       const float* fa[3][2] = {{A2, A3}, {A1, A3}, {A1, A2}};
       float* Gk[3] = {G1, G2, G3};
+      ReduceModes m;
       for (int k = 0; k < 3; ++k) {
-        const int* st_k = ib + L.start_off[k];
-        if (c.R <= 16)
-          launch_reduce_mode<16, 1>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
-        else if (c.R <= 32)
-          launch_reduce_mode<32, 1>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
-        else
-          launch_reduce_mode<32, 2>(c, srt[k], st_k, n[k], fa[k][0], fa[k][1], c.sS, Gk[k], max_rec);
+        m.srt[k] = srt[k];
+        m.start[k] = ib + L.start_off[k];
+        m.Aa[k] = fa[k][0];
+        m.Ab[k] = fa[k][1];
+        m.G[k] = Gk[k];
+        m.nrows[k] = n[k];
       }
+      if (c.R <= 16)
+        launch_reduce_modes<16, 1>(c, m, c.sS, max_rec);
+      else if (c.R <= 32)
+        launch_reduce_modes<32, 1>(c, m, c.sS, max_rec);
+      else
+        launch_reduce_modes<32, 2>(c, m, c.sS, max_rec);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
