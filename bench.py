@@ -168,6 +168,52 @@ def bench_c3(args):
     return 0
 
 
+def _copy_ceiling(mib: int = 2048, reps: int = 5):
+    """Measured HBM ceiling: GB/s (bytes read + written) of a device-to-device
+    copy of `mib` MiB, the best of `reps` timed copies."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return 2 * n * 4 / best / 1e9
+
+
+def _gather_ceiling(A, ndraws: int, reps: int = 5):
+    """Measured gather roof of the sampled path: draws/s of the library's
+    gather probe (three random factor-row gathers and a 16-byte record per
+    draw, nothing else) over the same factor matrices."""
+    import ctypes
+    import torch
+    from paper_2110_14514_amd import _native as N
+    lib = N.load()
+    rec = torch.empty(ndraws * 4, device="cuda")
+    st = torch.cuda.current_stream()
+    args = [ctypes.c_void_p(a.data_ptr()) for a in A] + [a.shape[0] for a in A] + [A[0].shape[1], ndraws]
+    call = lambda seed: N.check(lib.gcp_probe_gather(*args, seed, ctypes.c_void_p(rec.data_ptr()),
+                                                     ctypes.c_void_p(st.cuda_stream)), "gcp_probe_gather")
+    call(1)
+    best = 1e30
+    for r in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        call(2 + r)
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del rec
+    return ndraws / best
+
+
 def _cpu_info():
     """Host CPU model, NumPy's BLAS and the BLAS thread count (for the
     oracle's baseline line)."""
@@ -308,7 +354,7 @@ def bench_c4(args):
             for k in range(3):
                 gk = host(G[k])
                 worst["G_normwise"] = max(worst["G_normwise"], float(np.linalg.norm(gk - Gr[k]) / np.linalg.norm(Gr[k])))
-                colmax = np.max(np.abs(Gr[k]), axis=0)
+                colmax = np.maximum(np.max(np.abs(Gr[k]), axis=0), np.sqrt(np.mean(Gr[k] * Gr[k])))
                 worst["G_elementwise"] = max(worst["G_elementwise"],
                                              float(np.max(np.abs(gk - Gr[k]) / np.where(colmax > 0, colmax, 1.0))))
             gv = host(g_s)
@@ -324,6 +370,7 @@ def bench_c4(args):
                          f"{100 * share:.1f}% of the step's entry-slices, scaled to one batched step"}
     traffic = _profiled_traffic("batch_c4.txt", C4_KERNEL_SOURCES)
     ach = tot_bytes / (med / 1e3) / 1e9
+    copy_gbs = _copy_ceiling()
     res = {
         "metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
         "value": 1e3 / ms_per_step, "unit": "batched grad steps/s (64 streams each)", "n_gpus": 1,
@@ -338,6 +385,7 @@ def bench_c4(args):
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "batched gradient step (tile kernels and their fixed-order reduce, one graph)",
+                     "measured_copy_GBps": copy_gbs, "frac_of_measured_copy": ach / copy_gbs,
                      "kernel_ms": med, "alg_bytes_per_launch": tot_bytes,
                      "alg_gflops_per_launch": tot_flops / 1e9,
                      "fp32_tflops": tot_flops / (med / 1e3) / 1e12,
@@ -622,10 +670,22 @@ def bench_c5(args):
     # algorithmic bytes: a nonzero draw reads its coordinates and value (16 B);
     # a zero draw is a generated tuple plus one membership probe (8 B)
     alg = (H + 1) * (prob.p * 16 + prob.q * 8)
+    kern_s = ms / max(n, 1) / 1e3
+    # gather roof: the draw kernel gathers three factor rows per draw and the
+    # row-sorted reduction two per record, three records per draw (nine rows
+    # per draw; the float-atomic variant: three); the probe measures draws/s
+    # at three rows per draw on the same factors
+    probe = _gather_ceiling(A, draws)
+    rows_per_draw = 3 if args.sampled_atomic else 9
+    gath = draws * rows_per_draw / kern_s
+    roof = 3 * probe
     _line(label, "grad steps/s", sec * 1e3, args.steps, args.warmup, alg,
-          draws * 16 * R, ms / max(n, 1) / 1e3,
-          {"draws_per_step": draws, "draws_per_s": draws / (ms / max(n, 1) / 1e3),
-           "reduction": "atomic" if args.sampled_atomic else "row-sorted"})
+          draws * 16 * R, kern_s,
+          {"draws_per_step": draws, "draws_per_s": draws / kern_s,
+           "reduction": "atomic" if args.sampled_atomic else "row-sorted",
+           "gather_roof": {"bound": "gather", "achieved": gath, "peak": roof, "unit": "factor rows/s",
+                           "frac": gath / roof, "rows_per_draw": rows_per_draw,
+                           "probe_draws_per_s": probe}})
     return 0
 
 

@@ -389,6 +389,16 @@ gcp_status gcp_loss_grad_static(const gcp_params* params, const gcp_slice* X_t, 
                                 const void* const* A, const void* s_t, uint32_t want, void* loss,
                                 void* const* G, void* g_s, hipStream_t hip_stream);
 
+/* Measurement tool, no part of the method: the sampled path's gather
+ * pattern alone, to give it a measured roof.  For ndraws uniform random
+ * (i1, i2, i3) (SplitMix64 of the draw number and seed), gathers the three
+ * factor rows (device, I_k x rank row-major FP32) with the lane mapping of
+ * the sampled gradient kernel, forms sum_j A1 A2 A3 and writes one 16-byte
+ * record per draw to records (device, 16 ndraws bytes: the three indices as
+ * int32 bits and the sum).  Asynchronous on hip_stream; time it with events. */
+gcp_status gcp_probe_gather(const void* A1, const void* A2, const void* A3, int64_t I1, int64_t I2, int64_t I3,
+                            int32_t rank, int64_t ndraws, uint64_t seed, void* records, hipStream_t hip_stream);
+
 /* Autotuner for the matrix-core work plan (how the slice's (i1,i2) pairs are
  * cut into wave blocks).  Times every candidate plan on the device with HIP
  * events over X_t and the current window (synchronous; not for use inside a

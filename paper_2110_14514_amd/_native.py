@@ -94,6 +94,8 @@ SIGNATURES = {
     "gcp_loss_grad_static": (c_int32, [POINTER(GcpParams), POINTER(GcpSlice), c_int32, c_void_p, c_void_p,
                                        POINTER(c_int64), c_int64, POINTER(c_void_p), c_void_p, c_uint32,
                                        c_void_p, POINTER(c_void_p), c_void_p, c_void_p]),
+    "gcp_probe_gather": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_int64, c_int32, c_int64,
+                                   c_uint64, c_void_p, c_void_p]),
     "gcp_batch_autotune": (c_int32, [POINTER(c_void_p), POINTER(GcpBatchIO), c_int32, c_char_p,
                                      POINTER(c_int32)]),
     "gcp_batch_workspace_size": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),

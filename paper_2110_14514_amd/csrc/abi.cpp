@@ -1349,6 +1349,18 @@ extern "C" gcp_status gcp_loss_grad_static(const gcp_params* p, const gcp_slice*
   return hip_status(dense_fused_run(c));
 }
 
+extern "C" gcp_status gcp_probe_gather(const void* A1, const void* A2, const void* A3, int64_t I1, int64_t I2,
+                                       int64_t I3, int32_t rank, int64_t ndraws, uint64_t seed, void* records,
+                                       hipStream_t hip_stream) {
+  if (!A1 || !A2 || !A3 || !records || ndraws < 0) return GCP_E_ARG;
+  if (I1 < 1 || I2 < 1 || I3 < 1 || I1 > (1 << 30) || I2 > (1 << 30) || I3 > (1 << 30)) return GCP_E_SHAPE;
+  if (rank < 1 || rank > GCP_MAX_RANK) return GCP_E_ARG;
+  if (ndraws == 0) return GCP_OK;
+  return hip_status(gather_probe_run(static_cast<const float*>(A1), static_cast<const float*>(A2),
+                                     static_cast<const float*>(A3), (int)I1, (int)I2, (int)I3, rank, ndraws, seed,
+                                     records, hip_stream));
+}
+
 // Per-bucket autotuning for a set of streams about to be batched: the
 // largest stream (by window entries) of each shape bucket is tuned (or read
 // from the cache) and every stream of the bucket takes its plan.

@@ -255,6 +255,15 @@ void batch_launch_bernoulli(const BatchRun& b, int v, int want, hipStream_t st);
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t dense_fused_run(const DenseCall& c);
 
+// Single-slice matrix-core kernel (no stored window): 4 x 4 blocks of
+// (i1, i2) pairs per wave; partial slots G1: nb2, G2: nb1, G3 / g_s / loss: nwg.
+struct SsPlan {
+  int nb1, nb2, nblocks, nwg;
+};
+SsPlan single_slice_plan(int I1, int I2);
+bool single_slice_supported(const DenseCall& c);
+hipError_t single_slice_launch(const DenseCall& c, float* G1p, float* G2p, float* G3p, float* gsp, float* lossp);
+
 // Batched multi-stream path (dense FP32, matrix-core tiles).
 struct BatchDesc {                 // per stream, fixed at batch creation
   const float* Xt;                 // registered input buffers
@@ -403,6 +412,9 @@ hipError_t sampled_dump_run(const SampledCall& c, int h, int32_t* coords, float*
 // Unfused baseline: model, elementwise, per-mode MTTKRP kernels.
 size_t dense_plain_scratch_bytes(int I1, int I2, int I3, int R, int dtype);
 hipError_t dense_plain_run(const DenseCall& c, void* scratch, size_t scratch_bytes);
+// Gather roof probe of the sampled path (measurement only).
+hipError_t gather_probe_run(const float* A1, const float* A2, const float* A3, int I1, int I2, int I3, int R,
+                            int64_t ndraws, uint64_t seed, void* rec, hipStream_t st);
 
 // Least-squares temporal solve (FP64 normal equations).
 size_t ls_scratch_bytes(int I1, int I2, int I3, int R);

@@ -473,14 +473,34 @@ hipError_t dispatch_loss(const DenseCall& c, const Tiling& tl, const PartLayout&
 
 }  // namespace
 
+PartLayout part_layout_single(int I1, int I2, int I3, int R) {
+  const SsPlan sp = single_slice_plan(I1, I2);
+  return part_layout_slots(I1, I2, I3, R, sizeof(float), sp.nb2, sp.nb1, sp.nwg, sp.nwg);
+}
+
 size_t dense_fused_part_bytes(int I1, int I2, int I3, int R, int dtype) {
   size_t v = part_layout(I1, I2, I3, R, dtype ? sizeof(double) : sizeof(float)).total;
-  if (dtype == 0)
+  if (dtype == 0) {
     for (int i = 0; i < kNumPlanTargets; ++i) v = std::max(v, part_layout_mfma(I1, I2, I3, R, kPlanTargets[i]).total);
+    if (R <= 32) v = std::max(v, part_layout_single(I1, I2, I3, R).total);
+  }
   return v;
 }
 
 hipError_t dense_fused_run(const DenseCall& c) {
+  if (single_slice_supported(c)) {
+    // one slice: the pairs-in-rows matrix-core kernel
+    PartLayout pl = part_layout_single(c.I1, c.I2, c.I3, c.R);
+    if (pl.total > c.part_bytes) return hipErrorInvalidValue;
+    char* base = static_cast<char*>(c.part);
+    if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);
+    hipError_t e = single_slice_launch(c, reinterpret_cast<float*>(base + pl.g1), reinterpret_cast<float*>(base + pl.g2),
+                                       reinterpret_cast<float*>(base + pl.g3), reinterpret_cast<float*>(base + pl.gs),
+                                       reinterpret_cast<float*>(base + pl.loss));
+    if (c.ev_end) hipEventRecord(c.ev_end, c.stream);
+    if (e != hipSuccess) return e;
+    return launch_reduce<float>(c, pl);
+  }
   const bool mfma_ok = mfma_supported(c.R, c.ns, c.dtype);
   bool use_mfma = c.kernel == 2 ? mfma_ok : (c.kernel == 1 ? false : (mfma_ok && c.R > 8));
   if (use_mfma) {

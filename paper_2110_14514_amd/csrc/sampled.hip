@@ -620,6 +620,80 @@ __global__ void __launch_bounds__(256) sorted_reduce(ReduceModes m, const float*
   flush();
 }
 
+// Measurement probe for the gather roof of the sampled path: the draw
+// kernel's memory pattern with nothing else.  Each wave takes 4 x 64 draws;
+// a draw's (i1, i2, i3) come from SplitMix64 of its number (uniform, like the
+// Philox draws), SEG lanes gather its three factor rows (four draws' gathers
+// issued before any is used), form m = sum_j a1 a2 a3 by a segmented sum, and
+// the first lane writes a 16-byte record (i1, i2, i3, m).
+__device__ __forceinline__ uint64_t probe_mix(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <int SEG, int CPL>
+__global__ void __launch_bounds__(256) gather_probe(const float* __restrict__ A1, const float* __restrict__ A2,
+                                                    const float* __restrict__ A3, int I1, int I2, int I3, int R,
+                                                    int64_t ndraws, uint64_t seed, float4* __restrict__ rec) {
+  const int lane = threadIdx.x & 63;
+  const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 * kNB);
+  int i1[kNB], i2[kNB], i3[kNB];
+#pragma unroll
+  for (int bb = 0; bb < kNB; ++bb) {
+    const uint64_t z = probe_mix(seed ^ (uint64_t)(first + 64 * bb + lane));
+    i1[bb] = (int)(((z & 0xFFFFFFFFull) * (uint64_t)I1) >> 32);
+    i2[bb] = (int)(((z >> 32) * (uint64_t)I2) >> 32);
+    i3[bb] = (int)(((probe_mix(z) & 0xFFFFFFFFull) * (uint64_t)I3) >> 32);
+  }
+  constexpr int PER = 64 / SEG;
+  const int j = lane % SEG, sub = lane / SEG;
+  int jc[CPL];
+  bool jv[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    jv[cc] = j + SEG * cc < R;
+    jc[cc] = jv[cc] ? j + SEG * cc : 0;
+  }
+#pragma unroll
+  for (int bb = 0; bb < kNB; ++bb) {
+    const int64_t fb = first + 64 * bb;
+    const int nd = (int)max<int64_t>(0, min<int64_t>(64, ndraws - fb));
+    constexpr int U = 4;
+    for (int base = 0; base < nd; base += PER * U) {
+      int b1[U], b2[U], b3[U];
+      float r1[U][CPL], r2[U][CPL], r3[U][CPL];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = base + PER * u + sub;
+        const int sl = src < 64 ? src : 0;
+        b1[u] = __shfl(i1[bb], sl);
+        b2[u] = __shfl(i2[bb], sl);
+        b3[u] = __shfl(i3[bb], sl);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          r1[u][cc] = A1[(size_t)b1[u] * R + jc[cc]];
+          r2[u][cc] = A2[(size_t)b2[u] * R + jc[cc]];
+          r3[u][cc] = A3[(size_t)b3[u] * R + jc[cc]];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = base + PER * u + sub;
+        float m = 0.f;
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) m += jv[cc] ? r1[u][cc] * r2[u][cc] * r3[u][cc] : 0.f;
+        for (int w = SEG / 2; w >= 1; w >>= 1) m += __shfl_xor(m, w);
+        if (j == 0 && src < nd)
+          rec[fb + src] = make_float4(__int_as_float(b1[u]), __int_as_float(b2[u]), __int_as_float(b3[u]), m);
+      }
+    }
+  }
+}
+
 // Outputs start from the exact regularisation terms: G = lambda A,
 // g_s = mu s_t, loss = lambda/2 sum ||A||^2 + mu/2 ||s_t||^2.
 __global__ void __launch_bounds__(256) sampled_init(const float* A1, const float* A2, const float* A3,
@@ -941,6 +1015,20 @@ hipError_t sampled_run(const SampledCall& c) {
   }
   hipLaunchKernelGGL(sampled_check, dim3(std::min(64, (n1 + n2 + n3 + c.R + 256) / 256)), dim3(256), 0, c.stream,
                      G1, G2, G3, gs, loss, n1, n2, n3, c.R, c.want, c.status);
+  return hipGetLastError();
+}
+
+hipError_t gather_probe_run(const float* A1, const float* A2, const float* A3, int I1, int I2, int I3, int R,
+                            int64_t ndraws, uint64_t seed, void* rec, hipStream_t st) {
+  const int64_t waves = (ndraws + 64 * kNB - 1) / (64 * kNB);
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, (waves + 3) / 4);
+  float4* out = static_cast<float4*>(rec);
+  if (R <= 16)
+    hipLaunchKernelGGL((gather_probe<16, 1>), dim3(blocks), dim3(256), 0, st, A1, A2, A3, I1, I2, I3, R, ndraws, seed, out);
+  else if (R <= 32)
+    hipLaunchKernelGGL((gather_probe<32, 1>), dim3(blocks), dim3(256), 0, st, A1, A2, A3, I1, I2, I3, R, ndraws, seed, out);
+  else
+    hipLaunchKernelGGL((gather_probe<32, 2>), dim3(blocks), dim3(256), 0, st, A1, A2, A3, I1, I2, I3, R, ndraws, seed, out);
   return hipGetLastError();
 }
 

@@ -16,16 +16,21 @@ def rel_err(got, ref) -> float:
 
 
 def elem_err(got, ref) -> float:
-    """Largest per-element error, each element against the largest |value| of
-    its column of the reference (a vector is one column): a wrong short row
-    or a wrong rank column shows here even when the matrix norm hides it."""
+    """Largest per-element error, each element against the larger of the
+    largest |value| of its column of the reference (a vector is one column)
+    and the reference's RMS value: a wrong short row or a wrong rank column
+    shows here even when the matrix norm hides it, while a column of a single
+    entry (a mode of size 1) is not held to the relative error of one
+    cancelling FP32 sum."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
+    if not ref.size:
+        return 0.0
     if ref.ndim == 1:
         got, ref = got[:, None], ref[:, None]
-    scale = np.max(np.abs(ref), axis=0)
+    scale = np.maximum(np.max(np.abs(ref), axis=0), np.sqrt(np.mean(ref * ref)))
     scale = np.where(scale > 0, scale, 1.0)
-    return float(np.max(np.abs(got - ref) / scale[None, :])) if ref.size else 0.0
+    return float(np.max(np.abs(got - ref) / scale[None, :]))
 
 
 def grad_err(got, ref) -> float:

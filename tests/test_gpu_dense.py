@@ -264,3 +264,35 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
     # a value that is not a candidate plan is not taken from the cache
     cache.write_text(f"{_tune_key(st, prob, 6)} = 777\n")
     assert st2.autotune(dev["X_t"], str(cache)) in (1024, 2048, 4096, 8192, 16384)
+
+
+# One slice and no window: the pairs-in-rows matrix-core kernel.  Ragged
+# 4 x 4 pair blocks (I1, I2 not multiples of 4), I3 odd or not a multiple of
+# 32, a single entry, ranks below, at and between the 16 / 32 tiles.
+SINGLE = [((5, 6, 7), 4), ((9, 7, 33), 16), ((13, 11, 64), 32), ((4, 4, 1), 20), ((17, 3, 45), 5),
+          ((1, 1, 100), 32), ((30, 41, 200), 16), ((2, 9, 31), 12)]
+
+
+@pytest.mark.parametrize("loss", og.LOSSES)
+@pytest.mark.parametrize("dims,R", SINGLE)
+def test_single_slice_matches_oracle(dims, R, loss):
+    _print_case("single slice", dims, R, loss)
+    prob = gi.random_dense(dims, R, 0, loss, seed=zlib.crc32(repr((dims, R, loss)).encode()) % 1000,
+                           lam=0.05, mu=0.2)
+    got, code, _ = gpu_loss_grad(prob, kernel="auto")
+    assert code == 0
+    errs = compare(prob, got, og)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_single_slice_is_bitwise_repeatable():
+    import torch
+    _print_case("single slice repeat")
+    prob = gi.random_dense((37, 29, 70), 16, 0, "poisson_log", seed=5)
+    dev = to_device(prob)
+    st = make_stream(prob, dev)
+    a = st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+    a = (a[0].clone(), [g.clone() for g in a[1]], a[2].clone())
+    b = st.loss_grad(dev["X_t"], dev["A"], dev["s_t"])
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and all(torch.equal(x, y) for x, y in zip(a[1], b[1])) and torch.equal(a[2], b[2])
