@@ -421,8 +421,11 @@ gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_p
  * gcp_batch_loss_grad (loss scalar, G[3], g_s; NULL: not written).  The
  * caller refreshes the input buffers' contents before each call.
  * All per-call state (time index, window fill and slot time stamps, ADAM
- * iteration) is kept on the device, so any sequence of batch calls issued on
- * the batch's HIP stream may be captured once as a HIP graph and replayed.
+ * iteration, and with kappa_f > 0 the factor solver's rate, objective and
+ * saved copies) is kept on the device, so any sequence of batch calls issued
+ * on the batch's HIP stream may be captured once as a HIP graph and
+ * replayed.  A single stream that fits these limits takes the same route as
+ * a batch of one: its whole time step (gcp_batch_step) is then one graph.
  * While a stream is in a batch its host-side state (gcp_stream_info) is stale
  * until gcp_batch_sync_streams.  Outputs match the per-stream calls.
  * ------------------------------------------------------------------------ */
@@ -462,9 +465,16 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
 gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want);
 
 /* gcp_update_factors for every stream with its registered X_t and s_t
- * (tau_f of the first stream; all streams must share it): tau_f x [batched
- * gradient, batched ADAM step], then A_old <- A and the reservoir window
- * update with the draw made on the device, then t <- t+1. */
+ * (tau_f and kappa_f of the first stream; all streams must share them):
+ * kappa_f = 0: tau_f x [batched gradient, batched ADAM step];
+ * kappa_f > 0: Alg. 4's epochs as in gcp_update_factors, per stream on the
+ * device (objective with s_t fixed, then per epoch tau_f x [gradient, ADAM
+ * step with the stream's device-held rate] and the keep-or-undo decision
+ * with Alg. 2's Update: rate x 0.1 and the iteration index back tau_f on an
+ * undo; a stream whose objective is at or below tol_f stops stepping);
+ * then A_old <- A and the reservoir window update with the draw made on the
+ * device, then t <- t+1.  gcp_factor_info reports each stream's solver
+ * state after gcp_batch_sync_streams. */
 gcp_status gcp_batch_update_factors(gcp_batch* b);
 
 /* Temporal weights (as gcp_solve_st) for every stream of the batch whose

@@ -1413,6 +1413,7 @@ struct gcp_batch {
   BatchRun run_step;    // reduce writes each stream's gradient scratch
   int* status;
   int tau_f;
+  int kappa_f;
 };
 
 namespace {
@@ -1458,7 +1459,7 @@ gcp_status batch_check(gcp_stream* const* streams, int32_t n) {
     if (s->p.rank > 32 || s->p.window > 31) return GCP_E_UNSUPPORTED;
     if (model_hist(s)) return GCP_E_UNSUPPORTED;   // batches run the stored-slice history
     if (s->p.loss > GCP_LOSS_BERNOULLI_LOGIT) return GCP_E_UNSUPPORTED;   // batch tiles: the first three losses
-    if (s->p.kappa_f > 0) return GCP_E_UNSUPPORTED;  // batches keep every factor iteration
+    if (s->p.kappa_f != streams[0]->p.kappa_f) return GCP_E_ARG;   // epochs run in lockstep
     if (s->p.d != 3) return GCP_E_UNSUPPORTED;
     if (s->p.tau_f != streams[0]->p.tau_f) return GCP_E_ARG;
     if (s->st != streams[0]->st) return GCP_E_ARG;
@@ -1562,6 +1563,13 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
     d.beta1d = s->p.beta1; d.beta2d = s->p.beta2;
     d.eps = (float)s->p.adam_eps;
     d.seed = s->p.seed;
+    if (s->p.kappa_f > 0) {
+      d.fac = reinterpret_cast<FacState*>(s->ws + s->L.fac);
+      d.Ao = reinterpret_cast<float*>(s->ws + s->L.Ao);
+      d.uo = reinterpret_cast<float*>(s->ws + s->L.uo);
+      d.vo = reinterpret_cast<float*>(s->ws + s->L.vo);
+      d.tol_f = s->p.tol_f;
+    }
     // step descriptor: gradients into the stream's scratch
     dstep[i] = d;
     for (int k = 0; k < 3; ++k) dstep[i].outG[k] = reinterpret_cast<float*>(fac_ptr(s, s->L.G, k));
@@ -1627,6 +1635,7 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   b->ws = ws;
   b->status = reinterpret_cast<int*>(ws + L.counter) + 32;   // after the kBatchVariants counters
   b->tau_f = streams[0]->p.tau_f;
+  b->kappa_f = streams[0]->p.kappa_f;
   BatchRun r;
   r.desc = reinterpret_cast<const BatchDesc*>(ws + L.desc_out);
   r.state = reinterpret_cast<BatchState*>(ws + L.state);
@@ -1702,9 +1711,26 @@ gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want) {
 gcp_status gcp_batch_update_factors(gcp_batch* b) {
   if (!b) return GCP_E_ARG;
   hipError_t e = hipSuccess;
-  for (int it = 0; it < b->tau_f && e == hipSuccess; ++it) {
-    e = batch_grad_run(b->run_step, kWantGrad);
-    if (e == hipSuccess) e = batch_adam_run(b->run_step);
+  if (b->kappa_f > 0) {
+    // Algorithm 4's epochs, every decision on the device (per stream):
+    // objective at the start, then per epoch tau_f gradient + ADAM steps and
+    // the keep-or-undo test on the objective
+    const int obj = kWantLoss | kWantObjective;
+    e = batch_grad_run(b->run_step, obj);
+    if (e == hipSuccess) e = batch_fac_begin_run(b->run_step);
+    for (int ep = 0; ep < b->kappa_f && e == hipSuccess; ++ep) {
+      for (int it = 0; it < b->tau_f && e == hipSuccess; ++it) {
+        e = batch_grad_run(b->run_step, kWantGrad);
+        if (e == hipSuccess) e = batch_fac_step_run(b->run_step);
+      }
+      if (e == hipSuccess) e = batch_grad_run(b->run_step, obj);
+      if (e == hipSuccess) e = batch_fac_end_run(b->run_step, b->tau_f);
+    }
+  } else {
+    for (int it = 0; it < b->tau_f && e == hipSuccess; ++it) {
+      e = batch_grad_run(b->run_step, kWantGrad);
+      if (e == hipSuccess) e = batch_adam_run(b->run_step);
+    }
   }
   if (e == hipSuccess) e = batch_window_run(b->run_step);
   return hip_status(e);

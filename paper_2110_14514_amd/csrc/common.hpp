@@ -16,7 +16,9 @@ enum Loss { kGaussian = 0, kPoissonLog = 1, kBernoulliLogit = 2, kPoissonId = 3,
             kGaussianId = 5 };
 // epsilon of log(m + eps) in the identity- and odds-link losses (m >= 0)
 constexpr double kLossEps = 1e-10;
-enum Want { kWantLoss = 1, kWantGrad = 2 };
+// kWantObjective (with kWantLoss): the objective of the factor solve, in
+// which s_t is fixed, so the mu/2 ||s_t||^2 term is left out
+enum Want { kWantLoss = 1, kWantGrad = 2, kWantObjective = 4 };
 
 // Deferred device status bits (workspace word).
 enum StatusBits { kStatusNonFinite = 1, kStatusPivot = 2, kStatusSampler = 4 };
@@ -265,6 +267,7 @@ bool single_slice_supported(const DenseCall& c);
 hipError_t single_slice_launch(const DenseCall& c, float* G1p, float* G2p, float* G3p, float* gsp, float* lossp);
 
 // Batched multi-stream path (dense FP32, matrix-core tiles).
+struct FacState;
 struct BatchDesc {                 // per stream, fixed at batch creation
   const float* Xt;                 // registered input buffers
   const float* st;
@@ -290,6 +293,13 @@ struct BatchDesc {                 // per stream, fixed at batch creation
   float lam, mu, lower, beta1, beta2, eps;
   double w, theta, alpha, beta1d, beta2d;   // history weights and ADAM rate in FP64
   uint64_t seed;
+  // epochs of the factor solve (kappa_f > 0): the stream's solver state and
+  // its saved copies of A, u, v (null without epochs)
+  FacState* fac;
+  float* Ao;
+  float* uo;
+  float* vo;
+  double tol_f;
 };
 struct BatchState {                // per stream, advanced on the device
   int64_t t;
@@ -338,6 +348,13 @@ bool batch_variant_r16(int v);
 hipError_t batch_grad_run(const BatchRun& b, int want);
 hipError_t batch_adam_run(const BatchRun& b);
 hipError_t batch_window_run(const BatchRun& b);
+// Algorithm 4's epochs for every stream of a batch, decided on the device:
+// begin (objective at the start), one ADAM step with the device-held rate,
+// end of epoch (keep or undo).  The objective is the one the last
+// batch_grad_run(kWantLoss | kWantObjective) wrote to the step descriptors.
+hipError_t batch_fac_begin_run(const BatchRun& b);
+hipError_t batch_fac_step_run(const BatchRun& b);
+hipError_t batch_fac_end_run(const BatchRun& b, int tau_f);
 
 // Stratified sampled objective/gradient over COO slices (FP32).
 struct SampledCall {

@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchDesc* __re
     return;
   }
   // objective of stream si: data partials + lambda/2 sum ||A||^2 + mu/2 ||s||^2
+  // (the last term left out for the factor solve's objective)
   const int si = (int)blockIdx.x - nG;
   if (si == 0 && threadIdx.x < kBatchVariants) counter[threadIdx.x] = 0;
   if (!(want & kWantLoss)) return;
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchDesc* __re
   kahan_strided(kl, d.lossp, threadIdx.x, (size_t)d.nwg, 256, id);
   kahan_strided(kr, d.A, threadIdx.x, (size_t)d.fac_elems, 256, sq);
   kahan_strided(ks, d.st, threadIdx.x, (size_t)d.R, 256, sq);
-  red[threadIdx.x] = kl.s + 0.5f * d.lam * kr.s + 0.5f * d.mu * ks.s;
+  red[threadIdx.x] = kl.s + 0.5f * d.lam * kr.s + ((want & kWantObjective) ? 0.f : 0.5f * d.mu * ks.s);
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];

@@ -104,6 +104,109 @@ __global__ void fac_init(FacState* st, double alpha) {
   st->roll = -1;
 }
 
+// ---- batched epochs (Algorithm 4 for every stream of a batch) ----
+// The same decisions as the single-stream kernels above, one thread (or one
+// flattened range of factor entries) per stream; every stream keeps its own
+// FacState in its own workspace, so a batch and the stream's own calls share
+// the solver state.
+
+__global__ void batch_fac_begin(const BatchDesc* __restrict__ desc, int nstreams) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nstreams) return;
+  const BatchDesc& d = desc[i];
+  FacState* st = d.fac;
+  st->F = (double)d.outloss[0];
+  st->epoch = 0;
+  st->rolled = 0ull;
+  st->done = !(st->F > d.tol_f);
+  st->roll = -1;
+}
+
+__global__ void batch_fac_prep(const BatchDesc* __restrict__ desc, int nstreams) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nstreams) return;
+  FacState* st = desc[i].fac;
+  if (st->done) return;
+  st->p1 *= desc[i].beta1d;
+  st->p2 *= desc[i].beta2d;
+  st->alpha_t = st->alpha * sqrt(1.0 - st->p2) / (1.0 - st->p1);
+  st->i += 1;
+}
+
+// stream of flattened entry o: the last start <= o
+__device__ __forceinline__ int stream_of(const int64_t* __restrict__ start, int nstreams, int64_t o) {
+  int lo = 0, hi = nstreams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= o) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) batch_fac_adam(const BatchDesc* __restrict__ desc, int nstreams,
+                                                      const int64_t* __restrict__ facstart, int64_t nfac) {
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nfac; o += (int64_t)gridDim.x * 256) {
+    const int si = stream_of(facstart, nstreams, o);
+    const BatchDesc& d = desc[si];
+    const FacState* st = d.fac;
+    if (st->done) continue;
+    const int64_t e = o - facstart[si];
+    const float at = (float)st->alpha_t;
+    const float g = d.Gs[e];
+    const float u = d.beta1 * d.u[e] + (1.f - d.beta1) * g;
+    const float v = d.beta2 * d.v[e] + (1.f - d.beta2) * g * g;
+    d.u[e] = u;
+    d.v[e] = v;
+    const float a = d.A[e] - at * u / (sqrtf(v) + d.eps);
+    d.A[e] = a < d.lower ? d.lower : a;
+  }
+}
+
+__global__ void batch_fac_decide(const BatchDesc* __restrict__ desc, int nstreams, int tau) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nstreams) return;
+  const BatchDesc& d = desc[i];
+  FacState* st = d.fac;
+  if (st->done) {
+    st->roll = -1;
+    return;
+  }
+  const double Fv = (double)d.outloss[0];
+  const int roll = Fv > st->F;
+  if (roll) {
+    st->alpha *= kFacDecay;
+    st->i -= tau;
+    st->p1 = pow(d.beta1d, (double)st->i);
+    st->p2 = pow(d.beta2d, (double)st->i);
+    st->rolled |= 1ull << st->epoch;
+  } else {
+    st->F = Fv;
+  }
+  st->epoch += 1;
+  st->done = !(st->F > d.tol_f);
+  st->roll = roll;
+}
+
+__global__ void __launch_bounds__(256) batch_fac_copy(const BatchDesc* __restrict__ desc, int nstreams,
+                                                      const int64_t* __restrict__ facstart, int64_t nfac) {
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nfac; o += (int64_t)gridDim.x * 256) {
+    const int si = stream_of(facstart, nstreams, o);
+    const BatchDesc& d = desc[si];
+    const int roll = d.fac->roll;
+    if (roll < 0) continue;
+    const int64_t e = o - facstart[si];
+    if (roll) {
+      d.A[e] = d.Ao[e];
+      d.u[e] = d.uo[e];
+      d.v[e] = d.vo[e];
+    } else {
+      d.Ao[e] = d.A[e];
+      d.uo[e] = d.u[e];
+      d.vo[e] = d.v[e];
+    }
+  }
+}
+
 int grid_for(int64_t n) { return (int)std::min<int64_t>(2048, (n + 255) / 256); }
 
 }  // namespace
@@ -151,6 +254,26 @@ hipError_t fac_end_epoch_run(int dtype, int64_t n, void* a, void* u, void* v, vo
                        static_cast<float*>(u), static_cast<float*>(v), static_cast<float*>(ao),
                        static_cast<float*>(uo), static_cast<float*>(vo), st);
   }
+  return hipGetLastError();
+}
+
+hipError_t batch_fac_begin_run(const BatchRun& b) {
+  hipLaunchKernelGGL(batch_fac_begin, dim3((b.nstreams + 63) / 64), dim3(64), 0, b.stream, b.desc, b.nstreams);
+  return hipGetLastError();
+}
+
+hipError_t batch_fac_step_run(const BatchRun& b) {
+  hipLaunchKernelGGL(batch_fac_prep, dim3((b.nstreams + 63) / 64), dim3(64), 0, b.stream, b.desc, b.nstreams);
+  hipLaunchKernelGGL(batch_fac_adam, dim3(std::max(1, grid_for(b.nfac))), dim3(256), 0, b.stream, b.desc,
+                     b.nstreams, b.facstart, b.nfac);
+  return hipGetLastError();
+}
+
+hipError_t batch_fac_end_run(const BatchRun& b, int tau_f) {
+  hipLaunchKernelGGL(batch_fac_decide, dim3((b.nstreams + 63) / 64), dim3(64), 0, b.stream, b.desc, b.nstreams,
+                     tau_f);
+  hipLaunchKernelGGL(batch_fac_copy, dim3(std::max(1, grid_for(b.nfac))), dim3(256), 0, b.stream, b.desc,
+                     b.nstreams, b.facstart, b.nfac);
   return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ namespace gcp {
 namespace {
 
 constexpr int kSsPitch = 20;   // padded LDS row (16-byte reads of 16 lanes hit every bank once)
+constexpr int kSsWaves = 4;    // pair blocks (waves) per workgroup
+constexpr int kSsThreads = 64 * kSsWaves;
 
 struct SsArgs {
   const float* X;
@@ -43,33 +45,36 @@ struct SsArgs {
   int I1, I2, I3, R, nb1, nb2, nblocks;
 };
 
+// A3 rows of one group of 32 entries in the two layouts the tile reads
+__host__ __device__ constexpr int ss_a3_floats(int RT) { return 2 * RT * kSsPitch + 2 * 16 * (RT + 4); }
+
 __host__ __device__ constexpr int ss_lds_floats(int RT) {
-  return 2 * RT * kSsPitch          // A3 of the group, GEMM3 layout [u][j][c]
-         + 2 * 16 * (RT + 4)        // A3 of the group, GEMM1 layout [u][c][j]
-         + kWaves * 2 * 16 * kSsPitch   // per-wave y transposes [u][p][c]
-         + kWaves * 32 * RT         // per-wave G3 rows of the group
-         + kWaves * RT + kWaves;    // per-wave g_s and objective
+  return 2 * ss_a3_floats(RT)               // A3 of a group, two buffers
+         + kSsWaves * 2 * 16 * kSsPitch     // per-wave y transposes [u][p][c]
+         + 2 * kSsWaves * 32 * RT           // per-wave G3 rows of a group, two buffers
+         + kSsWaves * RT + kSsWaves;        // per-wave g_s and objective
 }
 
 template <int LOSS, int RT>
-__global__ void __launch_bounds__(kThreads) single_slice_kernel(SsArgs a) {
+__global__ void __launch_bounds__(kSsThreads) __attribute__((amdgpu_waves_per_eu(RT == 16 ? 4 : 2, 4)))
+single_slice_kernel(SsArgs a) {
   constexpr int NT = RT / 4;    // GEMM1 K steps
   constexpr int NM = RT / 16;   // 16-column tiles of j
+  constexpr int NA = 32 * RT / kSsThreads;   // A3 values a thread stages per group
+  static_assert(NA * kSsThreads == 32 * RT, "a group's A3 values split evenly over the threads");
   __shared__ __attribute__((aligned(16))) float lds[ss_lds_floats(RT)];
-  float* a3t = lds;                                  // [u][j][c]
-  float* a3g = a3t + 2 * RT * kSsPitch;              // [u][c][j]
-  float* ytr_all = a3g + 2 * 16 * (RT + 4);          // [wave][u][p][c]
-  float* g3w_all = ytr_all + kWaves * 2 * 16 * kSsPitch;
-  float* gsw = g3w_all + kWaves * 32 * RT;
-  float* lsw = gsw + kWaves * RT;
+  float* a3buf = lds;                                      // [buf]{[u][j][c], [u][c][j]}
+  float* ytr_all = a3buf + 2 * ss_a3_floats(RT);           // [wave][u][p][c]
+  float* g3w_all = ytr_all + kSsWaves * 2 * 16 * kSsPitch; // [buf][wave][e][j]
+  float* gsw = g3w_all + 2 * kSsWaves * 32 * RT;
+  float* lsw = gsw + kSsWaves * RT;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = lane & 15, g = lane >> 4;
   float* ytr = ytr_all + wave * 2 * 16 * kSsPitch;
-  float* g3w = g3w_all + wave * 32 * RT;
   const int R = a.R, I1 = a.I1, I2 = a.I2, I3 = a.I3;
-  const int blk = blockIdx.x * kWaves + wave;
+  const int blk = blockIdx.x * kSsWaves + wave;
   const bool active = blk < a.nblocks;
   const int b1 = active ? blk / a.nb2 : 0, b2 = active ? blk % a.nb2 : 0;
   const int i10 = 4 * b1, i20 = 4 * b2;
@@ -111,33 +116,80 @@ __global__ void __launch_bounds__(kThreads) single_slice_kernel(SsArgs a) {
     rv[r] = pvalid(p);
     xrow[r] = ((size_t)pair_i1(p) * I2 + pair_i2(p)) * I3;
   }
-
-  f4 V[NM];
+  // this lane's slice values of group sc: pair 4g + r, entries 32 sc + 2n + u.
+  // Loads are unconditional: a pair past the slice reads row 0 and an entry
+  // past the row reads the row's last value.  Those terms never count: their
+  // GEMM1/GEMM2 operand rows (pairs) or A3 rows (entries) are zero and their
+  // objective terms are masked.
+  const float* xr[4];
 #pragma unroll
-  for (int mt = 0; mt < NM; ++mt) V[mt] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < 4; ++r) xr[r] = a.X + xrow[r];
+  auto load_x = [&](int sc, float (&xv)[4][2]) {
+    const int c0 = 32 * sc;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = min(c0 + 2 * n + u, I3 - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xv[r][u] = xr[r][e];
+    }
+  };
+  // the group's A3 values, thread value k <-> (u, c, j) with j fastest so
+  // that the lanes read whole A3 rows (zero past the row and past R)
+  auto load_a3 = [&](int sc, float (&av)[NA]) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const int idx = tid + k * kSsThreads;
+      const int j = idx % RT, c = (idx / RT) % 16, u = idx / (16 * RT);
+      const int e = 32 * sc + 2 * c + u;
+      av[k] = (e < I3 && j < R) ? a.A3[(size_t)e * R + j] : 0.f;
+    }
+  };
+  auto store_a3 = [&](int buf, const float (&av)[NA]) {
+    float* a3t = a3buf + buf * ss_a3_floats(RT);
+    float* a3g = a3t + 2 * RT * kSsPitch;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const int idx = tid + k * kSsThreads;
+      const int j = idx % RT, c = (idx / RT) % 16, u = idx / (16 * RT);
+      a3t[(u * RT + j) * kSsPitch + c] = av[k];
+      a3g[(u * 16 + c) * (RT + 4) + j] = av[k];
+    }
+  };
+
+  // V of the even and the odd 16-entry tiles kept apart, so that the two
+  // tiles' matrix-core chains of a group are independent and interleave
+  f4 V2[2][NM];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int mt = 0; mt < NM; ++mt) V2[u][mt] = f4{0.f, 0.f, 0.f, 0.f};
   Kahan<float> lacc;
   const int ngroups = (I3 + 31) / 32;
+  // software pipeline: the slice values and A3 rows of group sc + 1 are in
+  // flight while group sc computes; A3 and the per-wave G3 rows alternate
+  // between two LDS buffers, so one barrier per group separates
+  //   [compute sc, write G3 rows (buf sc), stage A3 of sc + 1 (buf sc + 1)]
+  // from [combine the G3 rows of sc, compute sc + 1].
+  float xc[4][2], xn[4][2];
+  float an[NA];
+  load_x(0, xc);
+  load_a3(0, an);
+  store_a3(0, an);
+  __syncthreads();
   for (int sc = 0; sc < ngroups; ++sc) {
-    const int c0 = 32 * sc;
-    // this lane's slice values: pair 4g + r, entries c0 + 2n + u
-    float x[4][2];
+    const int c0 = 32 * sc, buf = sc & 1;
+    const bool more = sc + 1 < ngroups;
+    if (more) {
+      load_x(sc + 1, xn);
+      load_a3(sc + 1, an);
+    }
+    const float* a3t = a3buf + buf * ss_a3_floats(RT);
+    const float* a3g = a3t + 2 * RT * kSsPitch;
     bool ev[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) ev[u] = c0 + 2 * n + u < I3;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) x[r][u] = (ev[u] && rv[r]) ? a.X[xrow[r] + c0 + 2 * n + u] : 0.f;
-    // the group's A3 values in both layouts (zero past the row and past R)
-    for (int idx = tid; idx < 2 * RT * 16; idx += kThreads) {
-      const int u = idx / (RT * 16), j = (idx / 16) % RT, c = idx % 16;
-      const int e = c0 + 2 * c + u;
-      const float v = (e < I3 && j < R) ? a.A3[(size_t)e * R + j] : 0.f;
-      a3t[(u * RT + j) * kSsPitch + c] = v;
-      a3g[(u * 16 + c) * (RT + 4) + j] = v;
-    }
-    __syncthreads();
     f4 G3acc[2][NM];
+    float fgroup = 0.f;   // the group's objective terms (compensated once per group)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       // GEMM1 B operand: column n of tile u, K step t <-> j = 16 (t/4) + 4g + t%4
@@ -158,10 +210,10 @@ __global__ void __launch_bounds__(kThreads) single_slice_kernel(SsArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         float f = 0.f;
-        D[r] = MLoss<LOSS>::fy(x[r][u], D[r], 1.f, f);
+        D[r] = MLoss<LOSS>::fy(xc[r][u], D[r], 1.f, f);
         fpart += (rv[r] && ev[u]) ? f : 0.f;
       }
-      lacc.add(fpart);
+      fgroup += fpart;
       // GEMM2: G3[j][c] over the block's pairs
 #pragma unroll
       for (int mt = 0; mt < NM; ++mt) {
@@ -184,31 +236,44 @@ __global__ void __launch_bounds__(kThreads) single_slice_kernel(SsArgs a) {
       for (int mt = 0; mt < NM; ++mt) {
         const f4 av = *reinterpret_cast<const f4*>(a3t + (u * RT + 16 * mt + n) * kSsPitch + 4 * g);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) V[mt] = mfma(av[t], yv[t], V[mt]);
+        for (int t = 0; t < 4; ++t) V2[u][mt] = mfma(av[t], yv[t], V2[u][mt]);
       }
     }
-    // G3 rows of the group: each wave's block, then the waves in order
+    lacc.add(fgroup);
+    // G3 rows of the group: each wave's block into buffer buf
+    float* g3w = g3w_all + (buf * kSsWaves + wave) * 32 * RT;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) g3w[(2 * n + u) * RT + 16 * mt + 4 * g + r] = G3acc[u][mt][r];
+    if (more) store_a3(buf ^ 1, an);
     __syncthreads();
-    for (int idx = tid; idx < 32 * RT; idx += kThreads) {
+    // the waves' G3 rows summed in a fixed order
+    const float* g3b = g3w_all + buf * kSsWaves * 32 * RT;
+    for (int idx = tid; idx < 32 * RT; idx += kSsThreads) {
       const int e = idx / RT, j = idx - (idx / RT) * RT;
       if (c0 + e < I3 && j < R) {
         float sum = 0.f;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) sum += g3w_all[w * 32 * RT + idx];
+        for (int w = 0; w < kSsWaves; ++w) sum += g3b[w * 32 * RT + idx];
         a.G3p[((size_t)blockIdx.x * I3 + c0 + e) * R + j] = sum;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) xc[r][u] = xn[r][u];
   }
 
   // V[j][p] of this lane: j = 16 mt + 4g + r, p = n.  Mode-1/2 rows and the
   // temporal gradient of the block.
+  f4 V[NM];
+#pragma unroll
+  for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) V[mt][r] = V2[0][mt][r] + V2[1][mt][r];
   {
     const int p = n;
     const bool v = pvalid(p);
@@ -258,12 +323,12 @@ __global__ void __launch_bounds__(kThreads) single_slice_kernel(SsArgs a) {
   __syncthreads();
   if (tid < R) {
     float sum = 0.f;
-    for (int w = 0; w < kWaves; ++w) sum += gsw[w * RT + tid];
+    for (int w = 0; w < kSsWaves; ++w) sum += gsw[w * RT + tid];
     a.gsp[(size_t)blockIdx.x * R + tid] = sum;
   }
   if (tid == 0) {
     float sum = 0.f;
-    for (int w = 0; w < kWaves; ++w) sum += lsw[w];
+    for (int w = 0; w < kSsWaves; ++w) sum += lsw[w];
     a.lossp[blockIdx.x] = sum;
   }
 }
@@ -271,9 +336,9 @@ __global__ void __launch_bounds__(kThreads) single_slice_kernel(SsArgs a) {
 template <int LOSS>
 hipError_t ss_launch_rt(const DenseCall& c, const SsArgs& a, int nwg) {
   if (c.R <= 16)
-    hipLaunchKernelGGL((single_slice_kernel<LOSS, 16>), dim3(nwg), dim3(kThreads), 0, c.stream, a);
+    hipLaunchKernelGGL((single_slice_kernel<LOSS, 16>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
   else
-    hipLaunchKernelGGL((single_slice_kernel<LOSS, 32>), dim3(nwg), dim3(kThreads), 0, c.stream, a);
+    hipLaunchKernelGGL((single_slice_kernel<LOSS, 32>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
   return hipGetLastError();
 }
 
@@ -284,7 +349,7 @@ SsPlan single_slice_plan(int I1, int I2) {
   p.nb1 = (I1 + 3) / 4;
   p.nb2 = (I2 + 3) / 4;
   p.nblocks = p.nb1 * p.nb2;
-  p.nwg = (p.nblocks + kWaves - 1) / kWaves;
+  p.nwg = (p.nblocks + kSsWaves - 1) / kSsWaves;
   return p;
 }
 

@@ -56,14 +56,15 @@ def test_batch_loss_grad_matches_streams_and_oracle():
         assert max(errs.values()) <= TOL, (i, errs)
 
 
-def _run_steps(use_batch, graph, nsteps=4):
-    """nsteps OnlineGCP factor updates with fresh X_t/s_t each step."""
+def _run_steps(use_batch, graph, nsteps=4, kappa_f=0):
+    """nsteps OnlineGCP factor updates with fresh X_t/s_t each step
+    (kappa_f > 0: Algorithm 4's epochs with the device-side decisions)."""
     import torch
     from paper_2110_14514_amd import Batch
     probs = _problems()
     side = torch.cuda.Stream()       # graph capture needs a non-default stream
     with torch.cuda.stream(side):
-        devs, streams = _make(probs, alpha_f=1e-2, tau_f=2, seed=7)
+        devs, streams = _make(probs, alpha_f=1e-2, tau_f=2, seed=7, kappa_f=kappa_f)
     torch.cuda.synchronize()
     g = np.random.default_rng(3)
     data = [[(g.normal(size=p.dims).astype(np.float32) if p.loss == "gaussian" else
@@ -104,7 +105,11 @@ def _run_steps(use_batch, graph, nsteps=4):
                     Sb[i].copy_(torch.from_numpy(data[t][i][1]))
                     st.update_factors(Xb[i], Sb[i])
         torch.cuda.synchronize()
-    return [[a.cpu().numpy() for a in st.factors()] for st in streams], [st.info() for st in streams]
+    infos = [st.info() for st in streams]
+    if kappa_f:
+        for st, inf in zip(streams, infos):
+            inf["fac"] = st.factor_info()
+    return [[a.cpu().numpy() for a in st.factors()] for st in streams], infos
 
 
 def test_batch_steps_match_per_stream_steps():
@@ -189,3 +194,34 @@ def test_batch_autotune_per_bucket_matches_oracle(tmp_path):
     b2 = Batch(streams2, [d["X_t"].clone() for d in devs2], [d["s_t"].clone() for d in devs2],
                autotune=True, tune_cache=str(cache))
     assert b2.buckets == b.buckets and cache.read_text().splitlines() == lines
+
+
+def test_batch_epochs_match_per_stream_epochs():
+    """kappa_f = 2 epochs of tau_f = 2 steps per time step in a batch: the
+    same keep/undo decisions, rates, objectives and factors as each stream's
+    own gcp_update_factors (which the oracle pins)."""
+    print("case: batch epochs", flush=True)
+    ref_f, ref_i = _run_steps(False, False, kappa_f=2)
+    got_f, got_i = _run_steps(True, False, kappa_f=2)
+    for i in range(len(SPECS)):
+        assert got_i[i]["t"] == ref_i[i]["t"] and got_i[i]["slot_times"] == ref_i[i]["slot_times"]
+        gf, rf = got_i[i]["fac"], ref_i[i]["fac"]
+        assert gf["rolled"] == rf["rolled"] and gf["epochs"] == rf["epochs"] and gf["iters"] == rf["iters"], (i, gf, rf)
+        assert gf["alpha"] == rf["alpha"], i
+        assert abs(gf["F"] - rf["F"]) <= 1e-6 * abs(rf["F"]), (i, gf["F"], rf["F"])
+        for k in range(3):
+            assert rel_err(got_f[i][k], ref_f[i][k]) <= 1e-5, (i, k)
+
+
+def test_batch_epochs_graph_replay_matches_eager():
+    """A time step with epochs captured once as a HIP graph and replayed
+    equals the eager batched steps bit for bit, decisions included."""
+    print("case: batch epochs graph", flush=True)
+    eager_f, eager_i = _run_steps(True, False, kappa_f=2)
+    graph_f, graph_i = _run_steps(True, True, kappa_f=2)
+    for i in range(len(SPECS)):
+        assert graph_i[i]["slot_times"] == eager_i[i]["slot_times"]
+        assert graph_i[i]["fac"] == eager_i[i]["fac"], i
+        for k in range(3):
+            assert np.array_equal(graph_f[i][k], eager_f[i][k]), (i, k)
+
