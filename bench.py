@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--fused-only", action="store_true",
                     help="time the fused step only (for profiler runs)")
-    ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5",
+    ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c3b", "c4", "c5", "c2m", "c2w", "c2step", "ops", "e5",
                                                       "e6", "e7"],
                     help="c4 (default) is the batched configuration the metric is quoted on; the others "
                          "print their own line")
@@ -142,15 +142,20 @@ def _line(workload, value_unit, ms, steps, warmup, alg_bytes, alg_flops, kern_s,
     print(json.dumps(out), flush=True)
 
 
-def bench_c3(args):
-    """C3: 1000x1000x64 binary slices, rank 32, window 20, Bernoulli-logit."""
+def bench_c3(args, bits=False):
+    """C3: 1000x1000x64 binary slices, rank 32, window 20, Bernoulli-logit
+    (bits: the same slices bit-packed, one bit per entry)."""
     import torch
     import gcp_inputs as gi
     from paper_2110_14514_amd import Stream
     dims, R, H = (1000, 1000, 64), 32, 20
     print("bench: generating C3 on the device", file=sys.stderr, flush=True)
     X_t, A, s_t, Xh, Sh = gi.device_dense_window(dims, R, H, "bernoulli_logit", seed=2)
-    st = Stream(dims, R, H, "bernoulli_logit", A, Xh, Sh, list(range(1, H + 1)))
+    if bits:
+        X_t = gi.device_pack_bits(X_t)
+        Xh = [gi.device_pack_bits(x) for x in Xh]
+    st = Stream(dims, R, H, "bernoulli_logit", A, Xh, Sh, list(range(1, H + 1)),
+                slice_kind="bits" if bits else "dense")
     del Xh
     torch.cuda.synchronize()
     out = (torch.empty(1, device="cuda"), [torch.empty(n, R, device="cuda") for n in dims],
@@ -162,8 +167,9 @@ def bench_c3(args):
     st.kernel_timing(False)
     assert st.sync() == 0
     omega = int(np.prod(dims))
-    _line("C3 dense binary slices 1000x1000x64, rank 32, window 20, Bernoulli-logit",
-          "grad steps/s", sec * 1e3, args.steps, 0, (H + 1) * omega * 4,
+    name = ("C3 bit-packed binary slices 1000x1000x64 (one bit per entry), rank 32, window 20, Bernoulli-logit"
+            if bits else "C3 dense binary slices 1000x1000x64, rank 32, window 20, Bernoulli-logit")
+    _line(name, "grad steps/s", sec * 1e3, args.steps, 0, (H + 1) * omega * (4 if not bits else 0.125),
           omega * (4 * R * (H + 1) + 8 * R), ms / max(n, 1) / 1e3, {})
     return 0
 
@@ -835,7 +841,7 @@ def main():
         return 2
     if args.copy_probe:
         return copy_probe(args.copy_probe)
-    return {"c2": bench_c2, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
+    return {"c2": bench_c2, "c3": bench_c3, "c3b": lambda a: bench_c3(a, bits=True), "c4": bench_c4, "c5": bench_c5, "c2m": bench_c2m, "c2w": bench_c2w,
             "c2step": bench_c2step, "ops": bench_ops, "e5": bench_e5, "e6": bench_c5,
             "e7": bench_c5}[args.workload](args)
 

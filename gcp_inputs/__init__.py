@@ -411,3 +411,29 @@ def device_dense_window(dims, rank: int, window: int, loss: str, seed: int, devi
     A = [(torch.rand(n, rank, generator=g, device=device) - 0.5).contiguous() for n in dims]
     S = torch.rand(ns, rank, generator=g, device=device) + 0.5
     return Xs[-1], A, S[-1].contiguous(), Xs[:-1], S[:-1].contiguous()
+
+
+def pack_bits(x: np.ndarray) -> np.ndarray:
+    """Bit-packed storage of a binary slice (any shape, last axis I3): every
+    row of I3 entries becomes ceil(I3/32) uint32 words, entry i3 in bit
+    i3 % 32 of word i3 // 32 (least significant bit first), padding bits 0.
+    Non-zero entries are ones."""
+    x = np.asarray(x)
+    I3 = x.shape[-1]
+    nw = (I3 + 31) // 32
+    padded = np.zeros(x.shape[:-1] + (nw * 32,), np.uint8)
+    padded[..., :I3] = x != 0
+    b = np.packbits(padded, axis=-1, bitorder="little")
+    return np.ascontiguousarray(b).view("<u4").reshape(x.shape[:-1] + (nw,))
+
+
+def device_pack_bits(x):
+    """pack_bits of a device tensor, as int32 words (the same bits)."""
+    import torch
+    I3 = x.shape[-1]
+    nw = (I3 + 31) // 32
+    xb = torch.zeros(x.shape[:-1] + (nw * 32,), dtype=torch.int64, device=x.device)
+    xb[..., :I3] = (x != 0).to(torch.int64)
+    w = (xb.view(*x.shape[:-1], nw, 32) << torch.arange(32, device=x.device)).sum(-1)
+    w = torch.where(w >= 2 ** 31, w - 2 ** 32, w)
+    return w.to(torch.int32).contiguous()

@@ -84,7 +84,14 @@ typedef enum {
 } gcp_loss;
 
 typedef enum { GCP_F32 = 0, GCP_F64 = 1 } gcp_dtype;
-typedef enum { GCP_SLICE_DENSE = 0, GCP_SLICE_COO = 1 } gcp_slice_kind;
+/* Slice storage.  BITS: a dense binary slice (the binary data of Section
+ * 2.2) packed one bit per entry: each (i1, i2) row of I3 entries takes
+ * ceil(I3 / 32) 32-bit words, entry i3 is bit i3 % 32 (least significant
+ * first) of word i3 / 32; bits past I3 are ignored.  Window slots keep the
+ * same layout, so a stored slice takes 1/32 of the FP32 bytes.  BITS streams:
+ * Bernoulli losses, GCP_F32, d = 3, window <= 31, rank <= 32, the
+ * stored-slice history, not GCP_FLAG_KERNEL_VALU, no batches. */
+typedef enum { GCP_SLICE_DENSE = 0, GCP_SLICE_COO = 1, GCP_SLICE_BITS = 2 } gcp_slice_kind;
 
 /* Bits of the `want` argument of gcp_loss_grad. */
 enum {
@@ -192,7 +199,9 @@ typedef struct {
 
 /* One slice.  DENSE: vals holds prod(dims) values, coords is NULL.
  * COO: nnz entries; coords is nnz x 3 int32 row-major, sorted by row-major
- * linear index with no duplicates; vals are the (non-zero) values. */
+ * linear index with no duplicates; vals are the (non-zero) values.
+ * BITS: vals holds I1 I2 ceil(I3/32) uint32 words (4-byte aligned), coords
+ * is NULL. */
 typedef struct {
   int32_t kind;           /* gcp_slice_kind */
   int32_t reserved;

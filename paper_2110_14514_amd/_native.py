@@ -25,7 +25,7 @@ STATUS_NAMES = ["GCP_OK", "GCP_E_ARG", "GCP_E_SHAPE", "GCP_E_ALIGN", "GCP_E_STAT
 
 LOSS_IDS = {"gaussian": 0, "poisson_log": 1, "bernoulli_logit": 2, "poisson_id": 3, "bernoulli_odds": 4}
 F32, F64 = 0, 1
-SLICE_DENSE, SLICE_COO = 0, 1
+SLICE_DENSE, SLICE_COO, SLICE_BITS = 0, 1, 2
 WANT_LOSS, WANT_GRAD, IMPL_PLAIN = 1, 2, 256
 FLAG_PLAIN_SCRATCH = 1
 FLAG_KERNEL_VALU = 2

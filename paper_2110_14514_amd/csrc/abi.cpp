@@ -23,15 +23,16 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
-      metric, ident, total;
+      metric, ident, xf, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
   size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
   size_t plain_bytes, part_bytes;
   uint64_t tab_cap;       // COO: capacity of each membership table (0: dense)
-  size_t rp3;             // dense: row pitch of stored slices (I3 rounded up to 32 values)
-  size_t slot_elems;      // dense: elements of one stored slice (I1 I2 rp3)
+  size_t rp3;             // dense: row pitch of stored slices (I3 rounded up to 32 values;
+                          // bit-packed: ceil(I3/32) words)
+  size_t slot_elems;      // dense: elements (bit-packed: words) of one stored slice (I1 I2 rp3)
 };
 
 struct gcp_stream {
@@ -80,7 +81,15 @@ gcp_status check_params(const gcp_params* p) {
   if (p->window < 0 || p->window > GCP_MAX_WINDOW) return GCP_E_ARG;
   if (p->loss < 0 || p->loss > 4) return GCP_E_ARG;
   if (p->dtype != GCP_F32 && p->dtype != GCP_F64) return GCP_E_ARG;
-  if (p->slice_kind != GCP_SLICE_DENSE && p->slice_kind != GCP_SLICE_COO) return GCP_E_UNSUPPORTED;
+  if (p->slice_kind != GCP_SLICE_DENSE && p->slice_kind != GCP_SLICE_COO && p->slice_kind != GCP_SLICE_BITS)
+    return GCP_E_UNSUPPORTED;
+  if (p->slice_kind == GCP_SLICE_BITS) {
+    // bit-packed binary slices: read by the matrix-core kernels only
+    if (p->loss != GCP_LOSS_BERNOULLI_LOGIT && p->loss != GCP_LOSS_BERNOULLI_ODDS) return GCP_E_UNSUPPORTED;
+    if (p->dtype != GCP_F32 || p->d != 3 || p->window > 31 || p->rank > 32) return GCP_E_UNSUPPORTED;
+    if (p->hist != GCP_HIST_SLICES) return GCP_E_UNSUPPORTED;
+    if (p->flags & (GCP_FLAG_KERNEL_VALU | GCP_FLAG_PLAIN_SCRATCH)) return GCP_E_UNSUPPORTED;
+  }
   if (p->slice_kind == GCP_SLICE_COO) {
     if (p->dtype != GCP_F32) return GCP_E_UNSUPPORTED;
     if (p->p < 0 || p->q < 0 || p->p + p->q < 1) return GCP_E_ARG;
@@ -140,10 +149,11 @@ WsLayout layout_for(const gcp_params* p) {
   const int wslices = model ? 0 : p->window;
   L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
   // stored dense slices keep each (i1, i2) row on 128-byte lines: the row
-  // pitch is I3 rounded up to 32 values (the padding is never read)
-  L.rp3 = ((size_t)I3 + 31) / 32 * 32;
+  // pitch is I3 rounded up to 32 values (the padding is never read);
+  // bit-packed slices keep their own layout, ceil(I3/32) words per row
+  const bool bits = p->slice_kind == GCP_SLICE_BITS;
+  L.rp3 = bits ? ((size_t)I3 + 31) / 32 : ((size_t)I3 + 31) / 32 * 32;
   L.slot_elems = (size_t)I1 * I2 * L.rp3;
-  (void)omega;
   L.ring = off;
   off = align_up(off + (coo ? (size_t)wslices * L.coo_slot : (size_t)wslices * L.slot_elems * es), 256);
   L.part_bytes = coo ? 0 : dense_fused_part_bytes(I1, I2, I3, R, p->dtype);
@@ -169,15 +179,27 @@ WsLayout layout_for(const gcp_params* p) {
   L.vo = off; off += epochs ? fb : 0;
   L.metric = off; off += align_up(metrics_ws_bytes(), 256);
   L.ident = off; off = align_up(off + ((p->flags & GCP_FLAG_GAUSS_IDENTITY) ? hist_ws_bytes(R) : 0), 256);
+  // bit-packed streams: one slice as FP32 values for the solvers and
+  // metrics that read floats (the weights' SGD solve, slice losses)
+  L.xf = off; off = align_up(off + (bits ? omega * 4 : 0), 256);
   L.total = off;
   return L;
 }
 
 bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
+bool bits_stream(const gcp_stream* s) { return s->p.slice_kind == GCP_SLICE_BITS; }
+
+// Dense slices (FP values, 16-byte aligned) or bit-packed ones (words,
+// 4-byte aligned), whichever the stream holds.
 gcp_status check_dense_slice(const gcp_stream* s, const gcp_slice* X) {
-  if (!X || X->kind != GCP_SLICE_DENSE || !X->vals) return GCP_E_ARG;
-  if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_ARG;
+  if (!X || !X->vals) return GCP_E_ARG;
+  if (s->p.slice_kind == GCP_SLICE_BITS) {
+    if (X->kind != GCP_SLICE_BITS) return GCP_E_ARG;
+    if ((uintptr_t)X->vals & 3u) return GCP_E_ALIGN;
+    return GCP_OK;
+  }
+  if (X->kind != GCP_SLICE_DENSE || s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_ARG;
   if (!aligned16(X->vals)) return GCP_E_ALIGN;
   return GCP_OK;
 }
@@ -199,8 +221,12 @@ char* coo_slot_vals(gcp_stream* s, int slot) {
   return coo_slot_coords(s, slot) + (size_t)s->p.max_nnz * 12;
 }
 
-// Copy a dense slice (row pitch I3) into window slot `slot` (row pitch rp3).
+// Copy a dense slice (row pitch I3) into window slot `slot` (row pitch rp3);
+// a bit-packed slice has the slot's layout already.
 hipError_t store_dense_slot(gcp_stream* s, int slot, const void* vals) {
+  if (s->p.slice_kind == GCP_SLICE_BITS)
+    return hipMemcpyAsync(s->ws + s->L.ring + (size_t)slot * s->L.slot_elems * 4, vals, s->L.slot_elems * 4,
+                          hipMemcpyDeviceToDevice, s->st);
   const size_t w = (size_t)s->dims[2] * s->es;
   return hipMemcpy2DAsync(s->ws + s->L.ring + (size_t)slot * s->L.slot_elems * s->es, s->L.rp3 * s->es, vals, w, w,
                           (size_t)s->dims[0] * s->dims[1], hipMemcpyDeviceToDevice, s->st);
@@ -308,6 +334,7 @@ DenseCall base_call(gcp_stream* s) {
   c.c[0] = 1.0;
   c.kernel = (s->p.flags & GCP_FLAG_KERNEL_VALU) ? 1 : ((s->p.flags & GCP_FLAG_KERNEL_MFMA) ? 2 : 0);
   c.plan_target = s->plan_target;
+  c.xbits = s->p.slice_kind == GCP_SLICE_BITS;
   return c;
 }
 
@@ -470,8 +497,8 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   for (int h = 0; h < n_hist; ++h) {
     if (model) {
       // only the weights and time stamps of the window are kept
-    } else if (p->slice_kind == GCP_SLICE_DENSE) {
-      if (X_hist[h].kind != GCP_SLICE_DENSE || !X_hist[h].vals) return GCP_E_ARG;
+    } else if (p->slice_kind == GCP_SLICE_DENSE || p->slice_kind == GCP_SLICE_BITS) {
+      if (X_hist[h].kind != p->slice_kind || !X_hist[h].vals) return GCP_E_ARG;
       if (!aligned16(X_hist[h].vals)) return GCP_E_ALIGN;
     } else {
       if (X_hist[h].kind != GCP_SLICE_COO || X_hist[h].nnz < 0 || X_hist[h].nnz > p->max_nnz) return GCP_E_SHAPE;
@@ -692,7 +719,17 @@ gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
   if (st != GCP_OK) return st;
   if (coo) return hip_status(coo_weight_sgd(s, X_t, s_t));
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
-  if (s->p.tsolve == GCP_TSOLVE_SGD) return hip_status(tsgd_run(tsgd_call(s, X_t->vals, A, s_t, s->status)));
+  if (s->p.tsolve == GCP_TSOLVE_SGD) {
+    const void* X = X_t->vals;
+    if (bits_stream(s)) {
+      // the weights' solve reads X_t as FP32 values
+      float* xf = reinterpret_cast<float*>(s->ws + s->L.xf);
+      hipError_t e = unpack_bits_run(X, xf, (int64_t)s->dims[0] * s->dims[1], s->dims[2], s->st);
+      if (e != hipSuccess) return hip_status(e);
+      X = xf;
+    }
+    return hip_status(tsgd_run(tsgd_call(s, X, A, s_t, s->status)));
+  }
   return hip_status(ls_solve_run(s->dims[0], s->dims[1], s->dims[2], s->p.rank, s->p.dtype, X_t->vals, A, s->p.mu,
                                  s->p.lower, s_t, s->ws + s->L.ls, s->status, s->st));
 }
@@ -892,14 +929,23 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
 
 gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, double* sum_f, double* sum_sq) {
   if (!s || !s_x) return GCP_E_ARG;
-  if (s->p.slice_kind != GCP_SLICE_DENSE) return GCP_E_UNSUPPORTED;
+  if (s->p.slice_kind == GCP_SLICE_COO) return GCP_E_UNSUPPORTED;
   gcp_status st = check_dense_slice(s, X);
   if (st != GCP_OK) return st;
+  const void* Xv = X->vals;
+  if (bits_stream(s)) {
+    // the loss and the norm over the slice as FP32 0/1 values
+    float* xf = reinterpret_cast<float*>(s->ws + s->L.xf);
+    hipError_t eu = unpack_bits_run(Xv, xf, (int64_t)s->dims[0] * s->dims[1], s->dims[2], s->st);
+    if (eu != hipSuccess) return hip_status(eu);
+    Xv = xf;
+  }
   DenseCall c = base_call(s);
+  c.xbits = 0;
   c.want = kWantLoss;
   c.lam = 0.0;
   c.mu = 0.0;
-  c.X[0] = X->vals;
+  c.X[0] = Xv;
   c.S[0] = s_x;
   c.ns = 1;
   for (int k = 0; k < 3; ++k) {
@@ -910,7 +956,7 @@ gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, do
   c.loss_out = s->ws + s->L.loss;
   double* sq = reinterpret_cast<double*>(s->ws + s->L.loss + 64);
   hipError_t e = dense_fused_run(c);
-  if (e == hipSuccess) e = sumsq_run(s->p.dtype == GCP_F64, X->vals, (int64_t)s->omega, s->ws + s->L.metric, sq, s->st);
+  if (e == hipSuccess) e = sumsq_run(s->p.dtype == GCP_F64, Xv, (int64_t)s->omega, s->ws + s->L.metric, sq, s->st);
   double f = 0.0, q = 0.0;
   if (e == hipSuccess) {
     if (s->p.dtype == GCP_F64) {

@@ -220,6 +220,7 @@ struct DenseCall {
   int kernel;                   // 0 automatic, 1 VALU kernel, 2 matrix-core kernel
   int plan_target;              // matrix-core work plan (wanted wave blocks)
   const void* grad_scale;       // optional device scalar multiplying the gradients
+  int xbits;                    // slices bit-packed (binary data; rows of ceil(I3/32) words)
 };
 
 // Matrix-core (MFMA) variant of the fused kernel: work plan and launcher.

@@ -503,6 +503,11 @@ hipError_t dense_fused_run(const DenseCall& c) {
   }
   const bool mfma_ok = mfma_supported(c.R, c.ns, c.dtype);
   bool use_mfma = c.kernel == 2 ? mfma_ok : (c.kernel == 1 ? false : (mfma_ok && c.R > 8));
+  // bit-packed slices are read by the matrix-core kernels only
+  if (c.xbits) {
+    if (!mfma_ok || c.ns > 32 || c.kernel == 1) return hipErrorInvalidValue;
+    use_mfma = true;
+  }
   if (use_mfma) {
     MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, c.plan_target);
     PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R, c.plan_target);

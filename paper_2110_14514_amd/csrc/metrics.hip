@@ -136,6 +136,27 @@ hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out,
   return hipGetLastError();
 }
 
+namespace {
+// out[row * I3 + i3] = bit i3 % 32 of word i3 / 32 of the row (rows of rpw words)
+__global__ void __launch_bounds__(256) k_unpack_bits(const uint32_t* __restrict__ words, float* __restrict__ out,
+                                                     int64_t rows, int I3, int rpw) {
+  const int64_t n = rows * I3;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256) {
+    const int64_t row = o / I3;
+    const int i3 = (int)(o - row * I3);
+    out[o] = (float)((words[row * rpw + (i3 >> 5)] >> (i3 & 31)) & 1u);
+  }
+}
+}  // namespace
+
+hipError_t unpack_bits_run(const void* words, float* out, int64_t rows, int I3, hipStream_t stream) {
+  const int64_t n = rows * I3;
+  const int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_unpack_bits, dim3(blocks), dim3(256), 0, stream, static_cast<const uint32_t*>(words), out,
+                     rows, I3, (I3 + 31) / 32);
+  return hipGetLastError();
+}
+
 hipError_t cross_run(int dtype, const void* const* A, const void* const* B, const int* I, int Ra, int Rb, void* ws,
                      hipStream_t stream) {
   double* out = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up((kMetBlocks + 1) * sizeof(double), 256));

@@ -69,6 +69,7 @@ struct TileArgs {
   float* gsp;
   float* lossp;
   int I1, I2, I3, R, ns, want, tb1, tb2, nb2, nblocks;
+  int rpw;          // bit-packed slices: 32-bit words per (i1, i2) row
 };
 
 struct MArgs {
@@ -395,9 +396,14 @@ __device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
     return ht < NH - 1 || r < NK;
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK = 0>
+// XB: the slices are bit-packed binary data (rows of rpw 32-bit words,
+// entry i3 is bit i3 % 32 of word i3 / 32, X_t and the window alike).  A
+// stage then holds one word per slice row (the row's 32-entry group) and
+// the values are unpacked when the stage is read.
+template <int LOSS, int RT, int NH, bool DMA16, int NK = 0, bool XB = false>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
                                           float* ring, const float* cl, float* a3t) {
+  static_assert(!XB || (NH <= 2 && !DMA16), "bit-packed slices take the staged 4-byte path");
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
@@ -788,7 +794,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // takes the same KX + 1 copy instructions (rows past the window copy
         // a valid row into padding that is never used), so the waits are
         // compile-time constants.
-        constexpr int KX = DMA16 ? 2 * NH : 8 * NH;   // slice-row copies per stage
+        constexpr int KX = XB ? 1 : (DMA16 ? 2 * NH : 8 * NH);   // slice-row copies per stage
         constexpr int K = KX + 1;                      // + the factor rows
         // entries past the end of the row copy from the group start instead
         // (finite values whose terms are masked)
@@ -816,10 +822,17 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         const float* xtl = a.Xt + eoff;
         // pair of copy step p (row-major over the block), advanced incrementally
         int pi1 = 0, pi2 = 0;
+        // bit-packed rows: lane l copies the group's word of slice row l
+        // (rows past the window copy the current slice's word)
+        const uint32_t* wrow = reinterpret_cast<const uint32_t*>(
+                                   (lane == 0 || lane >= ns) ? a.Xt : a.ring + (size_t)(lane - 1) * a.rstride) +
+                               c0 / 32;
         auto issue = [&](int st) {
           const size_t pair = (size_t)(i10 + pi1) * I2 + (i20 + pi2);
           float* stg = ring_w + st * stage_floats(NH);
-          if constexpr (DMA16) {
+          if constexpr (XB) {
+            load_to_lds(reinterpret_cast<const float*>(wrow + pair * (size_t)a.rpw), stg, 4);
+          } else if constexpr (DMA16) {
             const uint32_t p32 = (uint32_t)pair;
 #pragma unroll
             for (int k = 0; k < KX; ++k)
@@ -867,7 +880,17 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           for (int ht = 0; ht < NH; ++ht)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              if constexpr (HALF) {
+              if constexpr (XB) {
+                // entries c0 + n (one tile) or c0 + 2n + u of the row's word
+                const uint32_t w = reinterpret_cast<const uint32_t*>(stg)[16 * ht + 4 * r + g];
+                if constexpr (HALF) {
+                  b.x[ht][r][0] = (float)((w >> n) & 1u);
+                  b.x[ht][r][1] = 0.f;
+                } else {
+                  b.x[ht][r][0] = (float)((w >> (2 * n)) & 1u);
+                  b.x[ht][r][1] = (float)((w >> (2 * n + 1)) & 1u);
+                }
+              } else if constexpr (HALF) {
                 b.x[ht][r][0] = stg[(16 * ht + 4 * r + g) * 32 + n];
                 b.x[ht][r][1] = 0.f;
               } else {
@@ -1022,7 +1045,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   }
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK>
+template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false>
 __device__ __forceinline__ void fused_body(const MArgs& a) {
   __shared__ float g1s[kWaves * kTB * RT];
   __shared__ float g2s[kWaves * kTB * RT];
@@ -1034,21 +1057,21 @@ __device__ __forceinline__ void fused_body(const MArgs& a) {
   __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH, DMA16, NK>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
+  mfma_tile<LOSS, RT, NH, DMA16, NK, XB>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK>
+template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false>
 __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
-  fused_body<LOSS, RT, NH, DMA16, NK>(a);
+  fused_body<LOSS, RT, NH, DMA16, NK, XB>(a);
 }
 
 // Rank tile 16 with one h-tile: the LDS of two workgroups fits a compute
 // unit, so the register budget is held to 128 (four waves per SIMD); the
 // few values that do not fit are spilled outside the pair loop.
-template <int LOSS, bool DMA16, int NK>
+template <int LOSS, bool DMA16, int NK, bool XB = false>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 fused_dense_mfma_r16(MArgs a) {
-  fused_body<LOSS, 16, 1, DMA16, NK>(a);
+  fused_body<LOSS, 16, 1, DMA16, NK, XB>(a);
 }
 
 
@@ -1144,12 +1167,26 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.lossp = lossp;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
+  a.rpw = (c.I3 + 31) / 32;
   // 16-byte slice-row copies need 16-byte aligned rows: I3 a multiple of 4;
   // nk: registers of the last h-tile that hold slices of the window
   const bool dma16 = dma16_ok(c.I3);
   const int nk = (c.ns - 16 * (NH - 1) + 3) / 4;
+  constexpr bool kBinary = LOSS == kBernoulliLogit || LOSS == kBernoulliOdds;
+  if (c.xbits && (!kBinary || NH > 2)) return hipErrorInvalidValue;
   auto go = [&](auto nkc) {
     constexpr int K = decltype(nkc)::value;
+    if constexpr (kBinary && NH <= 2) {
+      if (c.xbits) {
+        if constexpr (RT == 16 && NH == 1)
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, K, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
+                             m);
+        else
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K, true>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+        return;
+      }
+    }
     if constexpr (NH > 2) {
       hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, 0>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
     } else if constexpr (RT == 16 && NH == 1) {

@@ -43,6 +43,8 @@ struct SsArgs {
   float* gsp;
   float* lossp;
   int I1, I2, I3, R, nb1, nb2, nblocks;
+  int xbits;        // X bit-packed: rows of rpw 32-bit words, entry i3 = bit i3 % 32 of word i3 / 32
+  int rpw;
 };
 
 // A3 rows of one group of 32 entries in the two layouts the tile reads
@@ -55,7 +57,7 @@ __host__ __device__ constexpr int ss_lds_floats(int RT) {
          + kSsWaves * RT + kSsWaves;        // per-wave g_s and objective
 }
 
-template <int LOSS, int RT>
+template <int LOSS, int RT, bool XB>
 __global__ void __launch_bounds__(kSsThreads) __attribute__((amdgpu_waves_per_eu(RT == 16 ? 4 : 2, 4)))
 single_slice_kernel(SsArgs a) {
   constexpr int NT = RT / 4;    // GEMM1 K steps
@@ -123,15 +125,27 @@ single_slice_kernel(SsArgs a) {
   // objective terms are masked.
   const float* xr[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) xr[r] = a.X + xrow[r];
+  for (int r = 0; r < 4; ++r)
+    xr[r] = XB ? a.X + ((size_t)pair_i1(4 * g + r) * I2 + pair_i2(4 * g + r)) * a.rpw : a.X + xrow[r];
+  // Bit-packed slices: the raw word of group sc is held (its bits 2n + u
+  // are the lane's entries) and unpacked where the values are used.
   auto load_x = [&](int sc, float (&xv)[4][2]) {
     const int c0 = 32 * sc;
+    if constexpr (XB) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int e = min(c0 + 2 * n + u, I3 - 1);
+      for (int r = 0; r < 4; ++r) xv[r][0] = xr[r][sc];
+    } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) xv[r][u] = xr[r][e];
+      for (int u = 0; u < 2; ++u) {
+        const int e = min(c0 + 2 * n + u, I3 - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xv[r][u] = xr[r][e];
+      }
     }
+  };
+  auto xval = [&](const float (&xv)[4][2], int r, int u) -> float {
+    if constexpr (XB) return (float)((__float_as_uint(xv[r][0]) >> (2 * n + u)) & 1u);
+    return xv[r][u];
   };
   // the group's A3 values, thread value k <-> (u, c, j) with j fastest so
   // that the lanes read whole A3 rows (zero past the row and past R)
@@ -210,7 +224,7 @@ single_slice_kernel(SsArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         float f = 0.f;
-        D[r] = MLoss<LOSS>::fy(xc[r][u], D[r], 1.f, f);
+        D[r] = MLoss<LOSS>::fy(xval(xc, r, u), D[r], 1.f, f);
         fpart += (rv[r] && ev[u]) ? f : 0.f;
       }
       fgroup += fpart;
@@ -335,10 +349,20 @@ single_slice_kernel(SsArgs a) {
 
 template <int LOSS>
 hipError_t ss_launch_rt(const DenseCall& c, const SsArgs& a, int nwg) {
+  if constexpr (LOSS == kBernoulliLogit || LOSS == kBernoulliOdds) {
+    if (c.xbits) {
+      if (c.R <= 16)
+        hipLaunchKernelGGL((single_slice_kernel<LOSS, 16, true>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
+      else
+        hipLaunchKernelGGL((single_slice_kernel<LOSS, 32, true>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
+      return hipGetLastError();
+    }
+  }
+  if (c.xbits) return hipErrorInvalidValue;   // bit-packed slices are binary data
   if (c.R <= 16)
-    hipLaunchKernelGGL((single_slice_kernel<LOSS, 16>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
+    hipLaunchKernelGGL((single_slice_kernel<LOSS, 16, false>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
   else
-    hipLaunchKernelGGL((single_slice_kernel<LOSS, 32>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
+    hipLaunchKernelGGL((single_slice_kernel<LOSS, 32, false>), dim3(nwg), dim3(kSsThreads), 0, c.stream, a);
   return hipGetLastError();
 }
 
@@ -372,6 +396,8 @@ hipError_t single_slice_launch(const DenseCall& c, float* G1p, float* G2p, float
   a.lossp = lossp;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R;
   a.nb1 = pl.nb1; a.nb2 = pl.nb2; a.nblocks = pl.nblocks;
+  a.xbits = c.xbits;
+  a.rpw = (c.I3 + 31) / 32;
   switch (c.loss) {
     case kGaussian: return ss_launch_rt<kGaussian>(c, a, pl.nwg);
     case kPoissonLog: return ss_launch_rt<kPoissonLog>(c, a, pl.nwg);

@@ -67,6 +67,9 @@ hipError_t fac_end_epoch_run(int dtype, int64_t n, void* a, void* u, void* v, vo
 size_t metrics_ws_bytes();
 // *out (device FP64) = sum of squares of n values of X.
 hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out, hipStream_t stream);
+// A bit-packed binary slice (rows of ceil(I3/32) words, entry i3 = bit i3 % 32
+// of word i3 / 32) written out as FP32 0/1 values, rows x I3.
+hipError_t unpack_bits_run(const void* words, float* out, int64_t rows, int I3, hipStream_t stream);
 // Column norms and cross products of two K-tensors' factors (Ra, Rb <= 64),
 // laid out at cross_results(ws) as C[3][Ra][Rb], Na[3][Ra], Nb[3][Rb].
 hipError_t cross_run(int dtype, const void* const* A, const void* const* B, const int* I, int Ra, int Rb, void* ws,

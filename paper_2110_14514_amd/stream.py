@@ -27,9 +27,12 @@ def _ptr_array(ts: Sequence[torch.Tensor], n: int = 0):
 
 
 def _dense_slice(x: torch.Tensor) -> N.GcpSlice:
+    """A dense slice of values, or (int32 words) a bit-packed binary slice:
+    rows of ceil(I3/32) words, entry i3 is bit i3 % 32 of word i3 // 32."""
     if not x.is_contiguous():
         raise ValueError("dense slices must be contiguous (row-major)")
-    return N.GcpSlice(N.SLICE_DENSE, 0, x.data_ptr(), None, 0)
+    kind = N.SLICE_BITS if x.dtype == torch.int32 else N.SLICE_DENSE
+    return N.GcpSlice(kind, 0, x.data_ptr(), None, 0)
 
 
 def _slice(x) -> N.GcpSlice:
@@ -56,7 +59,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     n_p, n_q = p, q
     p = N.GcpParams()
     lib.gcp_params_default(byref(p))
-    p.slice_kind = N.SLICE_COO if slice_kind == "coo" else N.SLICE_DENSE
+    p.slice_kind = {"coo": N.SLICE_COO, "bits": N.SLICE_BITS}.get(slice_kind, N.SLICE_DENSE)
     p.max_nnz, p.p, p.q = int(max_nnz), int(n_p), int(n_q)
     p.d = len(dims)
     for k, n in enumerate(list(dims)[:3]):
