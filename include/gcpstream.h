@@ -49,8 +49,8 @@
 extern "C" {
 #endif
 
-#define GCP_ABI_VERSION 1
-#define GCP_MAX_D 3
+#define GCP_ABI_VERSION 2
+#define GCP_MAX_D 4
 #define GCP_MAX_RANK 64
 #define GCP_MAX_WINDOW 64
 /* Size of the library's fixed per-GPU device array used by
@@ -163,8 +163,22 @@ typedef struct {
                            * tensor whose middle factor is a fixed row of
                            * ones (no ADAM steps, no regulariser; requires
                            * lower <= 1); COO coords are (i1, 0, i2).  No
-                           * batches.                                    */
-  int64_t dims[GCP_MAX_D];/* I_1, I_2, I_3                                 */
+                           * batches.
+                           * Or 4 (the higher-order slices of Section 3.2):
+                           * dims (I1, I2, I3, I4), dense slices
+                           * I1 x I2 x I3 x I4 row-major, four factors in
+                           * entries 0..3 of every factor and gradient
+                           * array.  Evaluated with modes 3 and 4 merged:
+                           * entry (i3, i4) is entry i3 I4 + i4 of an
+                           * I1 x I2 x (I3 I4) slice (the same memory) whose
+                           * third factor has the rows A3[i3] * A4[i4]
+                           * (formed on the device each call); the merged
+                           * mode's gradient projects onto A3 and A4 by the
+                           * chain rule.  Dense slices only (FP32 or FP64),
+                           * stored-slice history, I3 I4 <= 2^30; no COO,
+                           * bit-packed slices, batches, GCP_FLAG_GAUSS_IDENTITY,
+                           * GCP_FLAG_PLAIN_SCRATCH or autotuning.       */
+  int64_t dims[GCP_MAX_D];/* I_1, I_2, I_3 (and I_4 when d = 4)           */
   int32_t rank;           /* R, 1..GCP_MAX_RANK                            */
   int32_t window;         /* H, 0..GCP_MAX_WINDOW                          */
   int32_t loss;           /* gcp_loss                                      */
@@ -346,10 +360,10 @@ gcp_status gcp_local_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, do
 gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* B, const void* w_b, int32_t rank_b,
                              double* score);
 
-/* Copies the stream's current factors into A_out[k] (device). */
+/* Copies the stream's current factors into A_out[k] (device, k < d). */
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out);
 
-/* Device pointer to the stream's current factor k (valid until destroy). */
+/* Device pointer to the stream's current factor k < d (valid until destroy). */
 gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr);
 
 /* Host-side stream state: current t, window size, Adam iteration index (with

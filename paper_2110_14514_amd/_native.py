@@ -14,7 +14,7 @@ from ctypes import (POINTER, Structure, c_char_p, c_double, c_int32, c_int64,
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgcpstream.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_WINDOW = 64
 MAX_RANK = 64
 
@@ -40,7 +40,7 @@ TSOLVE_SGD = 1
 
 class GcpParams(Structure):
     _fields_ = [
-        ("abi_version", c_uint32), ("d", c_int32), ("dims", c_int64 * 3),
+        ("abi_version", c_uint32), ("d", c_int32), ("dims", c_int64 * 4),
         ("rank", c_int32), ("window", c_int32), ("loss", c_int32),
         ("dtype", c_int32), ("slice_kind", c_int32), ("flags", c_int32),
         ("w", c_double), ("theta", c_double), ("lam", c_double), ("mu", c_double),

@@ -23,11 +23,11 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
-      metric, ident, xf, total;
+      metric, ident, xf, A34, G34, B34, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
-  size_t fac_off[3];      // element offsets of A^(k) inside a packed factor block
+  size_t fac_off[4];      // element offsets of A^(k) inside a packed factor block
   size_t plain_bytes, part_bytes;
   uint64_t tab_cap;       // COO: capacity of each membership table (0: dense)
   size_t rp3;             // dense: row pitch of stored slices (I3 rounded up to 32 values;
@@ -39,7 +39,8 @@ struct gcp_stream {
   gcp_params p;
   size_t es;
   size_t omega;
-  int dims[3];
+  int dims[3];          // the kernels' slice shape (d = 4: I1, I2, I3 I4)
+  int d4[2];            // d = 4: I3 and I4 (modes 3 and 4 merged in the kernels)
   hipStream_t st;
   char* ws;
   WsLayout L;
@@ -70,12 +71,18 @@ uint32_t weight_estimate_call(int64_t t) { return 0xC0000000u | (uint32_t)(t & 0
 gcp_status check_params(const gcp_params* p) {
   if (!p) return GCP_E_ARG;
   if (p->abi_version != GCP_ABI_VERSION) return GCP_E_ARG;
-  if (p->d != 2 && p->d != 3) return GCP_E_UNSUPPORTED;
+  if (p->d != 2 && p->d != 3 && p->d != 4) return GCP_E_UNSUPPORTED;
   if (p->d == 2 && p->dims[2] != 1) return GCP_E_SHAPE;   // matrix slices: dims (I1, I2, 1)
   if (p->d == 2 && p->lower > 1.0) return GCP_E_ARG;       // the fixed row of ones must satisfy the bound
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < (p->d == 4 ? 4 : 3); ++k)
     if (p->dims[k] < 1 || p->dims[k] > (1 << 30)) return GCP_E_SHAPE;
-  if ((double)p->dims[0] * p->dims[1] * p->dims[2] > 9.0e15) return GCP_E_SHAPE;
+  if (p->d == 4) {
+    // four-way slices: modes 3 and 4 merged in the kernels
+    if ((double)p->dims[2] * p->dims[3] > (double)(1 << 30)) return GCP_E_SHAPE;
+    if (p->slice_kind != GCP_SLICE_DENSE || p->hist != GCP_HIST_SLICES) return GCP_E_UNSUPPORTED;
+    if (p->flags & (GCP_FLAG_GAUSS_IDENTITY | GCP_FLAG_PLAIN_SCRATCH)) return GCP_E_UNSUPPORTED;
+  }
+  if ((double)p->dims[0] * p->dims[1] * p->dims[2] * (p->d == 4 ? p->dims[3] : 1) > 9.0e15) return GCP_E_SHAPE;
   if ((double)p->dims[0] * p->dims[1] >= 2147483647.0) return GCP_E_SHAPE;
   if (p->rank < 1 || p->rank > GCP_MAX_RANK) return GCP_E_ARG;
   if (p->window < 0 || p->window > GCP_MAX_WINDOW) return GCP_E_ARG;
@@ -126,12 +133,17 @@ gcp_status check_params(const gcp_params* p) {
 WsLayout layout_for(const gcp_params* p) {
   WsLayout L;
   const size_t es = p->dtype == GCP_F64 ? 8 : 4;
-  const int I1 = (int)p->dims[0], I2 = (int)p->dims[1], I3 = (int)p->dims[2], R = p->rank;
+  // d = 4: the slice geometry is I1 x I2 x (I3 I4); the factor blocks keep
+  // the four modes
+  const bool four = p->d == 4;
+  const int I1 = (int)p->dims[0], I2 = (int)p->dims[1], R = p->rank;
+  const int I3 = four ? (int)(p->dims[2] * p->dims[3]) : (int)p->dims[2];
   const size_t omega = (size_t)I1 * I2 * I3;
   L.fac_off[0] = 0;
   L.fac_off[1] = (size_t)I1 * R;
   L.fac_off[2] = L.fac_off[1] + (size_t)I2 * R;
-  L.fac_elems = L.fac_off[2] + (size_t)I3 * R;
+  L.fac_off[3] = L.fac_off[2] + (size_t)p->dims[2] * R;
+  L.fac_elems = four ? L.fac_off[3] + (size_t)p->dims[3] * R : L.fac_off[2] + (size_t)I3 * R;
   const size_t fb = align_up(L.fac_elems * es, 256);
   size_t off = 0;
   L.status = off; off += 256;
@@ -182,6 +194,12 @@ WsLayout layout_for(const gcp_params* p) {
   // bit-packed streams: one slice as FP32 values for the solvers and
   // metrics that read floats (the weights' SGD solve, slice losses)
   L.xf = off; off = align_up(off + (bits ? omega * 4 : 0), 256);
+  // d = 4: the merged mode's factor rows (the stream's, and a reference
+  // K-tensor's for the score) and its gradient
+  const size_t m34 = four ? (size_t)I3 * R * es : 0;
+  L.A34 = off; off = align_up(off + m34, 256);
+  L.G34 = off; off = align_up(off + m34, 256);
+  L.B34 = off; off = align_up(off + m34, 256);
   L.total = off;
   return L;
 }
@@ -300,6 +318,39 @@ SampledCall sampled_call(gcp_stream* s, const gcp_slice* X_t, const void* const*
 }
 
 char* fac_ptr(gcp_stream* s, size_t block, int k) { return s->ws + block + s->L.fac_off[k] * s->es; }
+
+bool four_way(const gcp_stream* s) { return s->p.d == 4; }
+
+// The kernels' three factors for the caller's factors A (k < d): with d = 4
+// the third is the merged modes 3 and 4, formed into the workspace at
+// `scratch` (rows A3[i3] * A4[i4], rank R).
+hipError_t kernel_factors(gcp_stream* s, const void* const* A, const void* out[3], size_t scratch, int R) {
+  out[0] = A[0];
+  out[1] = A[1];
+  if (!four_way(s)) {
+    out[2] = A[2];
+    return hipSuccess;
+  }
+  void* dst = s->ws + scratch;
+  out[2] = dst;
+  return kr_merge_run(s->p.dtype == GCP_F64, A[2], A[3], s->d4[0], s->d4[1], R, dst, s->st);
+}
+
+// After a kernel call on merged modes: G3 and G4 from the merged gradient
+// (L.G34), and the objective's regulariser on A3 and A4 (the kernels put
+// none on the merged mode).  lam: the call's regulariser weight.
+hipError_t finish_four_way(gcp_stream* s, const void* const* A, int want, double lam, void* loss, void* G3, void* G4,
+                           const void* grad_scale) {
+  if (!four_way(s)) return hipSuccess;
+  const int dt = s->p.dtype == GCP_F64;
+  const int I3 = s->d4[0], I4 = s->d4[1], R = s->p.rank;
+  hipError_t e = hipSuccess;
+  if (want & kWantGrad)
+    e = merged_project_run(dt, s->ws + s->L.G34, A[2], A[3], I3, I4, R, lam, grad_scale, G3, G4, s->status, s->st);
+  if (e == hipSuccess && (want & kWantLoss) && loss && lam != 0.0)
+    e = merged_reg_run(dt, loss, A[2], (int64_t)I3 * R, A[3], (int64_t)I4 * R, lam, s->st);
+  return e;
+}
 
 void fill_window(gcp_stream* s, DenseCall& c) {
   c.ring = s->ws + s->L.ring;
@@ -486,7 +537,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   *out = nullptr;
   gcp_status st = check_params(p);
   if (st != GCP_OK) return st;
-  if (!A0 || !A0[0] || !A0[1] || (!A0[2] && p->d == 3) || !workspace) return GCP_E_ARG;
+  if (!A0 || !A0[0] || !A0[1] || (!A0[2] && p->d >= 3) || (p->d == 4 && !A0[3]) || !workspace) return GCP_E_ARG;
   if (n_hist < 0 || n_hist > p->window) return GCP_E_ARG;
   const bool model = p->hist == GCP_HIST_MODEL;
   if (n_hist > 0 && (!s_hist || !t_hist || (!model && !X_hist))) return GCP_E_ARG;
@@ -516,6 +567,12 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   s->plan_target = kDefaultPlanTarget;
   s->es = p->dtype == GCP_F64 ? 8 : 4;
   for (int k = 0; k < 3; ++k) s->dims[k] = (int)q.dims[k];
+  s->d4[0] = s->d4[1] = 0;
+  if (p->d == 4) {
+    s->d4[0] = (int)p->dims[2];
+    s->d4[1] = (int)p->dims[3];
+    s->dims[2] = (int)(p->dims[2] * p->dims[3]);
+  }
   s->omega = (size_t)s->dims[0] * s->dims[1] * s->dims[2];
   s->st = hip_stream;
   s->ws = static_cast<char*>(workspace);
@@ -528,8 +585,8 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   // matrix slices (d = 2): the third factor is a fixed 1 x R row of ones
   std::vector<double> ones64(p->rank, 1.0);
   std::vector<float> ones32(p->rank, 1.f);
-  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-    size_t nb = (size_t)s->dims[k] * p->rank * s->es;
+  for (int k = 0; k < (p->d == 4 ? 4 : 3) && e == hipSuccess; ++k) {
+    size_t nb = (size_t)q.dims[k] * p->rank * s->es;   // internal shape (d = 2: I1, 1, I2)
     const bool fixed = k == 1 && p->d == 2;
     const void* src = fixed ? (s->es == 8 ? (const void*)ones64.data() : (const void*)ones32.data())
                             : A0[p->d == 2 && k == 2 ? 1 : k];
@@ -604,22 +661,30 @@ gcp_status gcp_loss_grad(gcp_stream* s, const gcp_slice* X_t, const void* const*
 gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void* const* A_in, const void* s_t,
                                 uint32_t want, const void* grad_scale, void* loss, void* const* G_in, void* g_s) {
   if (!s || !A_in || !A_in[0] || !A_in[1] || !s_t) return GCP_E_ARG;
-  const bool d2 = s->p.d == 2;
+  const bool d2 = s->p.d == 2, d4 = four_way(s);
   if (!A_in[2] && !d2) return GCP_E_ARG;
+  if (d4 && !A_in[3]) return GCP_E_ARG;
+  if (want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD | GCP_IMPL_PLAIN)) return GCP_E_ARG;
+  if (!(want & (GCP_WANT_LOSS | GCP_WANT_GRAD))) return GCP_E_ARG;
+  if ((want & GCP_WANT_LOSS) && !loss) return GCP_E_ARG;
+  if ((want & GCP_WANT_GRAD) && d4 && (!G_in || !G_in[2] || !G_in[3])) return GCP_E_ARG;
   // matrix slices: the caller's two factors are internal modes 0 and 2; the
-  // fixed row is the stream's own, its gradient goes to scratch
+  // fixed row is the stream's own, its gradient goes to scratch.  Four-way
+  // slices: the kernels see modes 3 and 4 merged (gradient into scratch,
+  // projected afterwards).
   const void* A[3] = {A_in[0], d2 ? fac_ptr(s, s->L.A, 1) : A_in[1], d2 ? A_in[1] : A_in[2]};
   void* Gv[3] = {nullptr, nullptr, nullptr};
   if (G_in) {
     Gv[0] = G_in[0];
     Gv[1] = d2 ? fac_ptr(s, s->L.G, 1) : G_in[1];
-    Gv[2] = d2 ? G_in[1] : G_in[2];
+    Gv[2] = d2 ? G_in[1] : (d4 ? s->ws + s->L.G34 : G_in[2]);
   }
   void* const* G = G_in ? Gv : nullptr;
-  if (want & ~(uint32_t)(GCP_WANT_LOSS | GCP_WANT_GRAD | GCP_IMPL_PLAIN)) return GCP_E_ARG;
-  if (!(want & (GCP_WANT_LOSS | GCP_WANT_GRAD))) return GCP_E_ARG;
-  if ((want & GCP_WANT_LOSS) && !loss) return GCP_E_ARG;
   if ((want & GCP_WANT_GRAD) && (!G || !G[0] || !G[1] || !G[2] || !g_s)) return GCP_E_ARG;
+  if (d4) {
+    hipError_t em = kernel_factors(s, A_in, A, s->L.A34, s->p.rank);
+    if (em != hipSuccess) return hip_status(em);
+  }
   if (s->p.slice_kind == GCP_SLICE_COO) {
     gcp_status st = check_coo_slice(s, X_t);
     if (st != GCP_OK) return st;
@@ -661,8 +726,10 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
   if ((want & GCP_WANT_GRAD) == 0) {
     // the fused kernel always forms gradients; route them to scratch
     for (int k = 0; k < 3; ++k) c.G[k] = fac_ptr(s, s->L.G, k);
+    if (d4) c.G[2] = s->ws + s->L.G34;
     c.gs = s->ws + s->L.gs;
   }
+  c.merged34 = d4;
   if (!plain && s->ev_used + 2 <= (int)s->ev.size()) {
     c.ev_begin = s->ev[s->ev_used];
     c.ev_end = s->ev[s->ev_used + 1];
@@ -671,6 +738,9 @@ gcp_status gcp_loss_grad_scaled(gcp_stream* s, const gcp_slice* X_t, const void*
   const bool ident = use_identity(s, c.want, plain, grad_scale);
   if (ident) c.loss = kGaussianId;
   hipError_t e = plain ? dense_plain_run(c, s->ws + s->L.plain, s->L.plain_bytes) : dense_fused_run(c);
+  if (e == hipSuccess && d4)
+    e = finish_four_way(s, A_in, c.want, c.lam, c.loss_out, (want & GCP_WANT_GRAD) ? G_in[2] : nullptr,
+                        (want & GCP_WANT_GRAD) ? G_in[3] : nullptr, grad_scale);
   if (e == hipSuccess && ident) e = identity_terms(s, c);
   if (e == hipSuccess) e = add_model_history(s, A, c.want, c.loss_out, c.G, grad_scale);
   if (e == hipSuccess && (want & GCP_WANT_LOSS)) e = d2_fix_loss(s, c.loss_out);
@@ -719,6 +789,12 @@ gcp_status gcp_solve_st(gcp_stream* s, const gcp_slice* X_t, void* s_t) {
   if (st != GCP_OK) return st;
   if (coo) return hip_status(coo_weight_sgd(s, X_t, s_t));
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
+  if (four_way(s)) {
+    // the weights see the model through the merged modes 3 and 4
+    const void* A4[4] = {A[0], A[1], A[2], fac_ptr(s, s->L.A, 3)};
+    hipError_t em = kernel_factors(s, A4, A, s->L.A34, s->p.rank);
+    if (em != hipSuccess) return hip_status(em);
+  }
   if (s->p.tsolve == GCP_TSOLVE_SGD) {
     const void* X = X_t->vals;
     if (bits_stream(s)) {
@@ -765,9 +841,19 @@ static hipError_t dense_grad_step(gcp_stream* s, const gcp_slice* X_t, const voi
     c.G[k] = fac_ptr(s, s->L.G, k);
   }
   c.gs = s->ws + s->L.gs;
+  const void* A4[4] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2),
+                       four_way(s) ? fac_ptr(s, s->L.A, 3) : nullptr};
+  hipError_t e = hipSuccess;
+  if (four_way(s)) {
+    e = kernel_factors(s, A4, c.A, s->L.A34, s->p.rank);
+    c.G[2] = s->ws + s->L.G34;
+    c.merged34 = 1;
+  }
   const bool ident = use_identity(s, kWantGrad, false, nullptr);
   if (ident) c.loss = kGaussianId;
-  hipError_t e = dense_fused_run(c);
+  if (e == hipSuccess) e = dense_fused_run(c);
+  if (e == hipSuccess && four_way(s))
+    e = finish_four_way(s, A4, kWantGrad, c.lam, nullptr, fac_ptr(s, s->L.G, 2), fac_ptr(s, s->L.G, 3), nullptr);
   if (e == hipSuccess && ident) e = identity_terms(s, c);
   if (e == hipSuccess) e = add_model_history(s, c.A, kWantGrad, nullptr, c.G, nullptr);
   if (e == hipSuccess) e = d2_clear_fixed_grad(s);
@@ -788,7 +874,16 @@ static hipError_t dense_objective(gcp_stream* s, const gcp_slice* X_t, const voi
   }
   c.gs = s->ws + s->L.gs;
   c.loss_out = loss;
-  hipError_t e = dense_fused_run(c);
+  const void* A4[4] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2),
+                       four_way(s) ? fac_ptr(s, s->L.A, 3) : nullptr};
+  hipError_t e = hipSuccess;
+  if (four_way(s)) {
+    e = kernel_factors(s, A4, c.A, s->L.A34, s->p.rank);
+    c.G[2] = s->ws + s->L.G34;
+    c.merged34 = 1;
+  }
+  if (e == hipSuccess) e = dense_fused_run(c);
+  if (e == hipSuccess && four_way(s)) e = finish_four_way(s, A4, kWantLoss, c.lam, loss, nullptr, nullptr, nullptr);
   if (e == hipSuccess) e = add_model_history(s, c.A, kWantLoss, loss, c.G, nullptr);
   if (e == hipSuccess) e = d2_fix_loss(s, loss);
   return e;
@@ -955,7 +1050,14 @@ gcp_status gcp_slice_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, do
   c.gs = s->ws + s->L.gs;
   c.loss_out = s->ws + s->L.loss;
   double* sq = reinterpret_cast<double*>(s->ws + s->L.loss + 64);
-  hipError_t e = dense_fused_run(c);
+  hipError_t e = hipSuccess;
+  if (four_way(s)) {
+    const void* A4[4] = {c.A[0], c.A[1], c.A[2], fac_ptr(s, s->L.A, 3)};
+    e = kernel_factors(s, A4, c.A, s->L.A34, s->p.rank);
+    c.G[2] = s->ws + s->L.G34;
+    c.merged34 = 1;
+  }
+  if (e == hipSuccess) e = dense_fused_run(c);
   if (e == hipSuccess) e = sumsq_run(s->p.dtype == GCP_F64, Xv, (int64_t)s->omega, s->ws + s->L.metric, sq, s->st);
   double f = 0.0, q = 0.0;
   if (e == hipSuccess) {
@@ -987,14 +1089,25 @@ gcp_status gcp_local_loss(gcp_stream* s, const gcp_slice* X, const void* s_x, do
 
 gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* B, const void* w_b, int32_t rank_b,
                              double* score) {
-  if (!s || !w_a || !B || !B[0] || !B[1] || (!B[2] && s->p.d == 3) || !w_b || !score) return GCP_E_ARG;
+  if (!s || !w_a || !B || !B[0] || !B[1] || (!B[2] && s->p.d >= 3) || (!B[3] && s->p.d == 4) || !w_b || !score)
+    return GCP_E_ARG;
   if (rank_b < 1 || rank_b > GCP_MAX_RANK) return GCP_E_ARG;
+  if (four_way(s) && rank_b > s->p.rank) return GCP_E_ARG;   // the merged reference rows use the stream's scratch
   const int Ra = s->p.rank, Rb = rank_b;
   const void* A[3] = {fac_ptr(s, s->L.A, 0), fac_ptr(s, s->L.A, 1), fac_ptr(s, s->L.A, 2)};
   const int dt = s->p.dtype == GCP_F64;
   // matrix slices: the reference's two factors go to internal modes 0 and 2
   const void* Bi[3] = {B[0], s->p.d == 2 ? metrics_ones(s->ws + s->L.metric) : B[1], s->p.d == 2 ? B[1] : B[2]};
-  hipError_t e = cross_run(dt, A, Bi, s->dims, Ra, Rb, s->ws + s->L.metric, s->st);
+  hipError_t e = hipSuccess;
+  if (four_way(s)) {
+    // four-way: both K-tensors through merged modes 3 and 4.  A merged
+    // column is a3 (x) a4, whose norm and inner products are the products of
+    // the modes' ones, so the per-mode product of cosines is unchanged.
+    const void* A4[4] = {A[0], A[1], A[2], fac_ptr(s, s->L.A, 3)};
+    e = kernel_factors(s, A4, A, s->L.A34, Ra);
+    if (e == hipSuccess) e = kernel_factors(s, B, Bi, s->L.B34, Rb);
+  }
+  if (e == hipSuccess) e = cross_run(dt, A, Bi, s->dims, Ra, Rb, s->ws + s->L.metric, s->st);
   std::vector<double> h((size_t)3 * Ra * Rb + 3 * Ra + 3 * Rb);
   std::vector<double> wa(Ra), wb(Rb);
   if (e == hipSuccess)
@@ -1058,18 +1171,19 @@ gcp_status gcp_ktensor_score(gcp_stream* s, const void* w_a, const void* const* 
 }
 
 gcp_status gcp_get_factors(gcp_stream* s, void* const* A_out) {
-  if (!s || !A_out || !A_out[0] || !A_out[1] || (!A_out[2] && s->p.d == 3)) return GCP_E_ARG;
+  if (!s || !A_out || !A_out[0] || !A_out[1] || (!A_out[2] && s->p.d >= 3) || (s->p.d == 4 && !A_out[3]))
+    return GCP_E_ARG;
   hipError_t e = hipSuccess;
-  for (int k = 0; k < (s->p.d == 2 ? 2 : 3) && e == hipSuccess; ++k) {
+  for (int k = 0; k < (s->p.d == 2 ? 2 : s->p.d) && e == hipSuccess; ++k) {
     const int ki = int_mode(s, k);
-    e = hipMemcpyAsync(A_out[k], fac_ptr(s, s->L.A, ki), (size_t)s->dims[ki] * s->p.rank * s->es,
-                       hipMemcpyDeviceToDevice, s->st);
+    const size_t rows = four_way(s) && k >= 2 ? (size_t)s->d4[k - 2] : (size_t)s->dims[ki];
+    e = hipMemcpyAsync(A_out[k], fac_ptr(s, s->L.A, ki), rows * s->p.rank * s->es, hipMemcpyDeviceToDevice, s->st);
   }
   return hip_status(e);
 }
 
 gcp_status gcp_factor_ptr(gcp_stream* s, int32_t k, void** ptr) {
-  if (!s || !ptr || k < 0 || k > 2) return GCP_E_ARG;
+  if (!s || !ptr || k < 0 || k > (s->p.d == 4 ? 3 : 2)) return GCP_E_ARG;
   *ptr = fac_ptr(s, s->L.A, int_mode(s, k));
   return GCP_OK;
 }
@@ -1227,7 +1341,7 @@ void tune_key(char* key, size_t n, const char* arch, const gcp_stream* s) {
 
 extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_path, int32_t* chosen) {
   if (!s) return GCP_E_ARG;
-  if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32) return GCP_E_UNSUPPORTED;
+  if (s->p.slice_kind != GCP_SLICE_DENSE || s->p.dtype != GCP_F32 || four_way(s)) return GCP_E_UNSUPPORTED;
   gcp_status st = check_dense_slice(s, X_t);
   if (st != GCP_OK) return st;
   int dev = 0;

@@ -221,6 +221,7 @@ struct DenseCall {
   int plan_target;              // matrix-core work plan (wanted wave blocks)
   const void* grad_scale;       // optional device scalar multiplying the gradients
   int xbits;                    // slices bit-packed (binary data; rows of ceil(I3/32) words)
+  int merged34;                 // the third mode is modes 3 and 4 merged: no regulariser on it here
 };
 
 // Matrix-core (MFMA) variant of the fused kernel: work plan and launcher.

@@ -309,6 +309,7 @@ struct ReduceArgs {
   T* gs;
   T* loss;
   T lam, mu;
+  T lam3;           // regulariser of the third mode (0 when it is merged modes 3 and 4)
   const T* gscale;
   int I1, I2, I3, R, nb1, nb2, ntiles, nsl, want, gblocks;   // nsl: g_s/loss slots
   int* status;
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
     } else if ((blk -= b1) < b2) {
       src = r.G2p; stride = n2; slots = r.nb1; nout = n2; A = r.A2; dst = r.G2;
     } else if ((blk -= b2) < b3) {
-      src = r.G3p; stride = n3; slots = r.ntiles; nout = n3; A = r.A3; dst = r.G3;
+      src = r.G3p; stride = n3; slots = r.ntiles; nout = n3; A = r.A3; dst = r.G3; lam = r.lam3;
     } else {
       blk -= b3;
       src = r.gsp; stride = R; slots = r.nsl; nout = R; A = r.st; dst = r.gs; lam = r.mu;
@@ -374,10 +375,11 @@ __global__ void __launch_bounds__(256) fused_reduce(ReduceArgs<T> r) {
   Kahan<T> kr;
   kahan_strided(kr, r.A1, threadIdx.x, (size_t)r.I1 * R, 256, sq);
   kahan_strided(kr, r.A2, threadIdx.x, (size_t)r.I2 * R, 256, sq);
-  kahan_strided(kr, r.A3, threadIdx.x, (size_t)r.I3 * R, 256, sq);
+  Kahan<T> kr3;   // only used when the third mode has its own regulariser weight
+  kahan_strided(r.lam3 == r.lam ? kr : kr3, r.A3, threadIdx.x, (size_t)r.I3 * R, 256, sq);
   Kahan<T> ks;
   kahan_strided(ks, r.st, threadIdx.x, R, 256, sq);
-  red[threadIdx.x] = k.s + T(0.5) * r.lam * kr.s + T(0.5) * r.mu * ks.s;
+  red[threadIdx.x] = k.s + T(0.5) * r.lam * kr.s + T(0.5) * r.lam3 * kr3.s + T(0.5) * r.mu * ks.s;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -408,6 +410,7 @@ hipError_t launch_reduce(const DenseCall& c, const PartLayout& pl) {
   r.gs = static_cast<T*>(c.gs);
   r.loss = static_cast<T*>(c.loss_out);
   r.lam = (T)c.lam; r.mu = (T)c.mu;
+  r.lam3 = c.merged34 ? T(0) : (T)c.lam;
   r.gscale = static_cast<const T*>(c.grad_scale);
   r.I1 = c.I1; r.I2 = c.I2; r.I3 = c.I3; r.R = c.R;
   r.nb1 = pl.s2; r.nb2 = pl.s1; r.ntiles = pl.s3; r.nsl = pl.s4; r.want = c.want;

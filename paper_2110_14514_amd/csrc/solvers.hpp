@@ -67,6 +67,16 @@ hipError_t fac_end_epoch_run(int dtype, int64_t n, void* a, void* u, void* v, vo
 size_t metrics_ws_bytes();
 // *out (device FP64) = sum of squares of n values of X.
 hipError_t sumsq_run(int dtype, const void* X, int64_t n, void* ws, double* out, hipStream_t stream);
+// Four-way slices through merged modes 3 and 4 (row i3 I4 + i4):
+// out = the merged factor, rows A3[i3] * A4[i4];
+hipError_t kr_merge_run(int dtype, const void* A3, const void* A4, int I3, int I4, int R, void* out,
+                        hipStream_t stream);
+// G3, G4 from the merged mode's gradient G34, plus grad_scale x lam A3/A4;
+hipError_t merged_project_run(int dtype, const void* G34, const void* A3, const void* A4, int I3, int I4, int R,
+                              double lam, const void* gscale, void* G3, void* G4, int* status, hipStream_t stream);
+// *loss += lam/2 (||A3||^2 + ||A4||^2) (n3, n4: entries of A3, A4).
+hipError_t merged_reg_run(int dtype, void* loss, const void* A3, int64_t n3, const void* A4, int64_t n4, double lam,
+                          hipStream_t stream);
 // A bit-packed binary slice (rows of ceil(I3/32) words, entry i3 = bit i3 % 32
 // of word i3 / 32) written out as FP32 0/1 values, rows x I3.
 hipError_t unpack_bits_run(const void* words, float* out, int64_t rows, int I3, hipStream_t stream);

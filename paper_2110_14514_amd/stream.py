@@ -62,7 +62,7 @@ def make_params(dims, rank: int, window: int, loss: str, *, w=1.0, theta=1.0,
     p.slice_kind = {"coo": N.SLICE_COO, "bits": N.SLICE_BITS}.get(slice_kind, N.SLICE_DENSE)
     p.max_nnz, p.p, p.q = int(max_nnz), int(n_p), int(n_q)
     p.d = len(dims)
-    for k, n in enumerate(list(dims)[:3]):
+    for k, n in enumerate(list(dims)[:4]):
         p.dims[k] = int(n)
     if p.d == 2:
         p.dims[2] = 1           # matrix slices: I3 = 1, fixed third factor

@@ -55,7 +55,7 @@ def test_params_struct_layout_matches_header(lib):
     assert p.beta1 == 0.9 and p.beta2 == 0.999 and p.adam_eps == 1e-8
     assert p.w == 1.0 and p.theta == 1.0 and p.lam == 0.0 and p.mu == 0.0
     assert math.isinf(p.lower) and p.lower < 0 and p.tau_f == 1
-    assert ctypes.sizeof(N.GcpParams) == 224
+    assert ctypes.sizeof(N.GcpParams) == 232
     assert ctypes.sizeof(N.GcpSlice) == 32
 
 
@@ -76,7 +76,7 @@ def _ws(lib, p):
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("abi_version", 99, "E_ARG"), ("d", 4, "E_UNSUPPORTED"), ("rank", 0, "E_ARG"),
+    ("abi_version", 99, "E_ARG"), ("d", 5, "E_UNSUPPORTED"), ("d", 4, "E_SHAPE"), ("rank", 0, "E_ARG"),
     ("rank", 65, "E_ARG"), ("window", 65, "E_ARG"), ("window", -1, "E_ARG"),
     ("loss", 5, "E_ARG"), ("loss", -1, "E_ARG"), ("dtype", 5, "E_ARG"), ("theta", 0.0, "E_ARG"),
     ("theta", 1.5, "E_ARG"), ("mu", -1.0, "E_ARG"), ("slice_kind", 7, "E_UNSUPPORTED"),
