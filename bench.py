@@ -554,6 +554,17 @@ def bench_ops(args):
     n = max(5, min(args.steps, 50))
     g = Stream(dims, R, H, "gaussian", A, Xh, Sh, list(range(1, H + 1)))
     t_ls = timed(lambda: g.solve_st(X_t), n)
+    # the LS weights' error against the oracle's FP64 solve (explicit Z):
+    # the FP32 stream, and an FP64 stream over the same values
+    from oracle.solve import ls_temporal
+    s32 = g.solve_st(X_t).double().cpu().numpy()
+    A64 = [a.double() for a in A]
+    g64 = Stream(dims, R, 0, "gaussian", A64)
+    s64 = g64.solve_st(X_t.double()).cpu().numpy()
+    assert g64.sync() == 0
+    del g64
+    s_ref = ls_temporal(X_t.double().cpu().numpy(), [a.cpu().numpy() for a in A64])
+    ls_err = lambda v: float(np.linalg.norm(v - s_ref) / np.linalg.norm(s_ref))
     t_gg = timed(lambda: g.loss_grad(X_t, A, s_t, want_loss=False), n)
     del g
     gi_ = Stream(dims, R, H, "gaussian", A, Xh, Sh, list(range(1, H + 1)), gauss_identity=True)
@@ -589,6 +600,7 @@ def bench_ops(args):
            "config": {"workload": "C2 shape 200x200x200, rank 16, window 10: LS solve (Gaussian), factor update "
                                   "and autograd forward+backward (Poisson-log)"},
            "ls_solve_ms": t_ls * 1e3, "ls_solve_GBps": 4 * omega / t_ls / 1e9,
+           "ls_rel_err_vs_oracle": {"fp32_stream": ls_err(s32), "fp64_stream": ls_err(s64)},
            "gaussian_grad_only_ms": t_gg * 1e3, "gaussian_grad_identity_ms": t_gi * 1e3,
            "grad_ms": t_grad * 1e3, "grad_poisson_identity_ms": t_pid * 1e3,
            "grad_bernoulli_odds_ms": t_bod * 1e3,

@@ -52,7 +52,8 @@ extern "C" {
 #define GCP_ABI_VERSION 2
 #define GCP_MAX_D 4
 #define GCP_MAX_RANK 64
-#define GCP_MAX_WINDOW 64
+#define GCP_MAX_WINDOW 64          /* stored-slice history */
+#define GCP_MAX_WINDOW_MODEL 4096  /* model-difference history (weights only) */
 /* Size of the library's fixed per-GPU device array used by
  * gcp_loss_grad_static (64 MiB). */
 #define GCP_STATIC_SCRATCH_BYTES (64u << 20)
@@ -180,7 +181,9 @@ typedef struct {
                            * GCP_FLAG_PLAIN_SCRATCH or autotuning.       */
   int64_t dims[GCP_MAX_D];/* I_1, I_2, I_3 (and I_4 when d = 4)           */
   int32_t rank;           /* R, 1..GCP_MAX_RANK                            */
-  int32_t window;         /* H, 0..GCP_MAX_WINDOW                          */
+  int32_t window;         /* H, 0..GCP_MAX_WINDOW (stored slices), or
+                           * 0..GCP_MAX_WINDOW_MODEL with GCP_HIST_MODEL,
+                           * which keeps only R weights per slot          */
   int32_t loss;           /* gcp_loss                                      */
   int32_t dtype;          /* gcp_dtype: GCP_F64 is for verification only  */
   int32_t slice_kind;     /* gcp_slice_kind of every slice of the stream  */

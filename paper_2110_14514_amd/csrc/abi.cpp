@@ -23,7 +23,7 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
-      metric, ident, xf, A34, G34, B34, total;
+      metric, ident, xf, A34, G34, B34, stamps, cw, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -46,9 +46,9 @@ struct gcp_stream {
   WsLayout L;
   int64_t t;
   int nwin;
-  int64_t slot_t[GCP_MAX_WINDOW];
+  std::vector<int64_t> slot_t;     // time stamp of each window slot (host copy)
   int64_t adam_i;
-  int64_t slot_nnz[GCP_MAX_WINDOW];
+  std::vector<int64_t> slot_nnz;
   int64_t sample_call;
   int* status;
   std::vector<hipEvent_t> ev;   // begin/end pairs for gcp_kernel_timing
@@ -85,7 +85,8 @@ gcp_status check_params(const gcp_params* p) {
   if ((double)p->dims[0] * p->dims[1] * p->dims[2] * (p->d == 4 ? p->dims[3] : 1) > 9.0e15) return GCP_E_SHAPE;
   if ((double)p->dims[0] * p->dims[1] >= 2147483647.0) return GCP_E_SHAPE;
   if (p->rank < 1 || p->rank > GCP_MAX_RANK) return GCP_E_ARG;
-  if (p->window < 0 || p->window > GCP_MAX_WINDOW) return GCP_E_ARG;
+  if (p->window < 0 || p->window > (p->hist == GCP_HIST_MODEL ? GCP_MAX_WINDOW_MODEL : GCP_MAX_WINDOW))
+    return GCP_E_ARG;
   if (p->loss < 0 || p->loss > 4) return GCP_E_ARG;
   if (p->dtype != GCP_F32 && p->dtype != GCP_F64) return GCP_E_ARG;
   if (p->slice_kind != GCP_SLICE_DENSE && p->slice_kind != GCP_SLICE_COO && p->slice_kind != GCP_SLICE_BITS)
@@ -200,6 +201,10 @@ WsLayout layout_for(const gcp_params* p) {
   L.A34 = off; off = align_up(off + m34, 256);
   L.G34 = off; off = align_up(off + m34, 256);
   L.B34 = off; off = align_up(off + m34, 256);
+  // the window's slot time stamps and weights w_h on the device (the
+  // history kernels read them; up to GCP_MAX_WINDOW_MODEL slots)
+  L.stamps = off; off = align_up(off + (size_t)std::max(1, p->window) * 8, 256);
+  L.cw = off; off = align_up(off + (size_t)std::max(1, p->window) * 8, 256);
   L.total = off;
   return L;
 }
@@ -438,7 +443,11 @@ hipError_t identity_terms(gcp_stream* s, const DenseCall& c) {
   h.R = s->p.rank;
   h.dtype = s->p.dtype == GCP_F64 ? 1 : 0;
   h.nwin = c.ns - 1;
-  for (int i = 0; i + 1 < c.ns; ++i) h.c[i] = c.c[i + 1];
+  double* cw = reinterpret_cast<double*>(s->ws + s->L.cw);
+  hipError_t ew = hist_weights_run(reinterpret_cast<const int64_t*>(s->ws + s->L.stamps), h.nwin, s->t, s->p.w,
+                                   s->p.theta, cw, s->st);
+  if (ew != hipSuccess) return ew;
+  h.c = cw;
   h.shist = s->ws + s->L.shist;
   h.ws = reinterpret_cast<double*>(s->ws + s->L.ident);
   h.status = s->status;
@@ -580,6 +589,8 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   s->status = reinterpret_cast<int*>(s->ws + L.status);
   s->nwin = n_hist;
   s->t = n_hist > 0 ? t_hist[n_hist - 1] + 1 : 1;
+  s->slot_t.assign((size_t)std::max(1, p->window), 0);
+  s->slot_nnz.assign((size_t)std::max(1, p->window), 0);
   for (int h = 0; h < n_hist; ++h) s->slot_t[h] = t_hist[h];
   hipError_t e = hipMemsetAsync(s->ws + L.status, 0, 256, s->st);
   // matrix slices (d = 2): the third factor is a fixed 1 x R row of ones
@@ -618,6 +629,12 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
                          static_cast<const char*>(s_hist) + (size_t)h * p->rank * s->es, p->rank * s->es,
                          hipMemcpyDeviceToDevice, s->st);
   }
+  // the window's time stamps on the device (the host array is the caller's:
+  // wait for the copy)
+  if (e == hipSuccess && n_hist > 0) {
+    e = hipMemcpyAsync(s->ws + L.stamps, t_hist, (size_t)n_hist * 8, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  }
   if (e != hipSuccess) {
     delete s;
     return GCP_E_DEVICE;
@@ -631,6 +648,10 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
 static hipError_t add_model_history(gcp_stream* s, const void* const* A, int want, void* loss, void* const* G,
                              const void* grad_scale) {
   if (!model_hist(s) || s->nwin == 0) return hipSuccess;
+  double* cw = reinterpret_cast<double*>(s->ws + s->L.cw);
+  hipError_t ew = hist_weights_run(reinterpret_cast<const int64_t*>(s->ws + s->L.stamps), s->nwin, s->t, s->p.w,
+                                   s->p.theta, cw, s->st);
+  if (ew != hipSuccess) return ew;
   HistCall h;
   for (int k = 0; k < 3; ++k) {
     h.I[k] = s->dims[k];
@@ -643,8 +664,7 @@ static hipError_t add_model_history(gcp_stream* s, const void* const* A, int wan
   h.dtype = s->p.dtype == GCP_F64 ? 1 : 0;
   h.want = want;
   h.shist = s->ws + s->L.shist;
-  for (int i = 0; i < kMaxNs; ++i)
-    h.c[i] = i < s->nwin ? s->p.w * pow(s->p.theta, (double)(s->t - s->slot_t[i])) : 0.0;
+  h.c = cw;
   h.loss = loss;
   h.grad_scale = grad_scale;
   h.ws = reinterpret_cast<double*>(s->ws + s->L.hist);
@@ -1014,6 +1034,7 @@ gcp_status gcp_update_factors(gcp_stream* s, const gcp_slice* X_t, const void* s
     if (e == hipSuccess)
       e = hipMemcpyAsync(s->ws + s->L.shist + (size_t)slot * p.rank * s->es, s_t, p.rank * s->es,
                          hipMemcpyDeviceToDevice, s->st);
+    if (e == hipSuccess) e = hist_set_stamp_run(reinterpret_cast<int64_t*>(s->ws + s->L.stamps), slot, s->t, s->st);
     if (e != hipSuccess) return hip_status(e);
     if (s->nwin == slot) s->nwin += 1;
     s->slot_t[slot] = s->t;
@@ -1936,6 +1957,10 @@ gcp_status gcp_batch_sync_streams(gcp_batch* b) {
     s->adam_i = state[i].adam_i;
     s->nwin = state[i].nwin;
     for (int h = 0; h < s->nwin; ++h) s->slot_t[h] = state[i].slot_t[h];
+    // the device copy of the stamps follows (the host array lives on)
+    if (s->nwin > 0 && hipMemcpy(s->ws + s->L.stamps, s->slot_t.data(), (size_t)s->nwin * 8,
+                                 hipMemcpyHostToDevice) != hipSuccess)
+      return GCP_E_DEVICE;
   }
   if (word != 0) {
     if (hipMemset(b->status, 0, sizeof(int)) != hipSuccess) return GCP_E_DEVICE;

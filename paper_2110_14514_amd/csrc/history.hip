@@ -36,7 +36,7 @@ struct HistArgs {
   const T* gscale;
   double* ws;
   int* status;
-  double c[kMaxNs];
+  const double* c;   // device, w_h of each window slot
   int I[3];
   int R, nwin, want;
 };
@@ -152,7 +152,7 @@ hipError_t hist_launch(const HistCall& c) {
   a.gscale = static_cast<const T*>(c.grad_scale);
   a.ws = c.ws;
   a.status = c.status;
-  for (int h = 0; h < kMaxNs; ++h) a.c[h] = h < c.nwin ? c.c[h] : 0.0;
+  a.c = c.c;
   a.R = c.R;
   a.nwin = c.nwin;
   a.want = c.want;
@@ -224,7 +224,7 @@ hipError_t ident_launch(const HistCall& c, const void* s_t, void* g_s) {
   a.gscale = nullptr;
   a.ws = c.ws;
   a.status = c.status;
-  for (int h = 0; h < kMaxNs; ++h) a.c[h] = h < c.nwin ? c.c[h] : 0.0;
+  a.c = c.c;
   a.R = c.R;
   a.nwin = c.nwin;
   a.want = kWantGrad;
@@ -242,6 +242,28 @@ hipError_t ident_launch(const HistCall& c, const void* s_t, void* g_s) {
 
 hipError_t ident_run(const HistCall& c, const void* s_t, void* g_s) {
   return c.dtype == 1 ? ident_launch<double>(c, s_t, g_s) : ident_launch<float>(c, s_t, g_s);
+}
+
+namespace {
+// w_h = w theta^(t - t_h) of every window slot from the device-held stamps
+__global__ void k_hist_weights(const int64_t* __restrict__ stamps, int n, int64_t t, double w, double theta,
+                               double* __restrict__ out) {
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x)
+    out[h] = w * pow(theta, (double)(t - stamps[h]));
+}
+__global__ void k_set_stamp(int64_t* stamps, int slot, int64_t t) { stamps[slot] = t; }
+}  // namespace
+
+hipError_t hist_weights_run(const int64_t* stamps, int n, int64_t t, double w, double theta, double* out,
+                            hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hist_weights, dim3((n + 255) / 256), dim3(256), 0, stream, stamps, n, t, w, theta, out);
+  return hipGetLastError();
+}
+
+hipError_t hist_set_stamp_run(int64_t* stamps, int slot, int64_t t, hipStream_t stream) {
+  hipLaunchKernelGGL(k_set_stamp, dim3(1), dim3(1), 0, stream, stamps, slot, t);
+  return hipGetLastError();
 }
 
 size_t hist_ws_bytes(int R) { return (size_t)15 * R * R * sizeof(double); }

@@ -210,3 +210,15 @@ def test_static_entry_rejects_before_any_launch(lib):
     huge.dims[0], huge.dims[1], huge.dims[2], huge.rank = 30000, 30000, 4096, 64
     assert call(huge) == N.E_WORKSPACE
     assert call(_params(lib, hist=1)) == N.E_UNSUPPORTED
+
+
+def test_long_windows_only_with_model_history(lib):
+    """Stored-slice windows stop at 64 slots; the model-difference history
+    (weights only) takes up to 4096."""
+    from paper_2110_14514_amd import _native as N
+    assert _ws(lib, _params(lib, window=64))[0] == N.OK
+    assert _ws(lib, _params(lib, window=65))[0] == N.E_ARG
+    assert _ws(lib, _params(lib, window=500, hist=N.HIST_MODEL))[0] == N.OK
+    assert _ws(lib, _params(lib, window=4096, hist=N.HIST_MODEL))[0] == N.OK
+    assert _ws(lib, _params(lib, window=4097, hist=N.HIST_MODEL))[0] == N.E_ARG
+
