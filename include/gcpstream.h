@@ -486,7 +486,8 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
                             size_t ws_bytes, hipStream_t hip_stream, gcp_batch** out);
 
 /* Objective and gradients of every stream at its current factors over its
- * registered X_t and window: one persistent launch plus one reduce launch.
+ * registered X_t and window: one persistent launch per tile build present
+ * (spread over the batch's HIP streams) plus one reduce launch.
  * Writes the registered outputs (want: GCP_WANT_LOSS | GCP_WANT_GRAD). */
 gcp_status gcp_batch_loss_grad(gcp_batch* b, uint32_t want);
 

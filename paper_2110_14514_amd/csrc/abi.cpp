@@ -23,7 +23,7 @@ using namespace gcp;
 
 struct WsLayout {
   size_t status, A, Aold, u, v, G, gs, loss, shist, ring, part, ls, plain, tab, sorted, hist, tsgd, fac, Ao, uo, vo,
-      metric, ident, xf, A34, G34, B34, stamps, cw, total;
+      metric, ident, xf, A34, G34, B34, stamps, total;
   size_t sorted_bytes;    // COO: row-sorted reduction workspace (0: float atomics)
   size_t coo_slot;        // bytes of one COO window slot (coords then values)
   size_t fac_elems;       // sum_k I_k R
@@ -201,10 +201,9 @@ WsLayout layout_for(const gcp_params* p) {
   L.A34 = off; off = align_up(off + m34, 256);
   L.G34 = off; off = align_up(off + m34, 256);
   L.B34 = off; off = align_up(off + m34, 256);
-  // the window's slot time stamps and weights w_h on the device (the
-  // history kernels read them; up to GCP_MAX_WINDOW_MODEL slots)
+  // the window's slot time stamps on the device (the history kernels form
+  // w_h from them; up to GCP_MAX_WINDOW_MODEL slots)
   L.stamps = off; off = align_up(off + (size_t)std::max(1, p->window) * 8, 256);
-  L.cw = off; off = align_up(off + (size_t)std::max(1, p->window) * 8, 256);
   L.total = off;
   return L;
 }
@@ -443,11 +442,10 @@ hipError_t identity_terms(gcp_stream* s, const DenseCall& c) {
   h.R = s->p.rank;
   h.dtype = s->p.dtype == GCP_F64 ? 1 : 0;
   h.nwin = c.ns - 1;
-  double* cw = reinterpret_cast<double*>(s->ws + s->L.cw);
-  hipError_t ew = hist_weights_run(reinterpret_cast<const int64_t*>(s->ws + s->L.stamps), h.nwin, s->t, s->p.w,
-                                   s->p.theta, cw, s->st);
-  if (ew != hipSuccess) return ew;
-  h.c = cw;
+  h.stamps = reinterpret_cast<const int64_t*>(s->ws + s->L.stamps);
+  h.t = s->t;
+  h.w = s->p.w;
+  h.theta = s->p.theta;
   h.shist = s->ws + s->L.shist;
   h.ws = reinterpret_cast<double*>(s->ws + s->L.ident);
   h.status = s->status;
@@ -648,10 +646,6 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
 static hipError_t add_model_history(gcp_stream* s, const void* const* A, int want, void* loss, void* const* G,
                              const void* grad_scale) {
   if (!model_hist(s) || s->nwin == 0) return hipSuccess;
-  double* cw = reinterpret_cast<double*>(s->ws + s->L.cw);
-  hipError_t ew = hist_weights_run(reinterpret_cast<const int64_t*>(s->ws + s->L.stamps), s->nwin, s->t, s->p.w,
-                                   s->p.theta, cw, s->st);
-  if (ew != hipSuccess) return ew;
   HistCall h;
   for (int k = 0; k < 3; ++k) {
     h.I[k] = s->dims[k];
@@ -664,7 +658,10 @@ static hipError_t add_model_history(gcp_stream* s, const void* const* A, int wan
   h.dtype = s->p.dtype == GCP_F64 ? 1 : 0;
   h.want = want;
   h.shist = s->ws + s->L.shist;
-  h.c = cw;
+  h.stamps = reinterpret_cast<const int64_t*>(s->ws + s->L.stamps);
+  h.t = s->t;
+  h.w = s->p.w;
+  h.theta = s->p.theta;
   h.loss = loss;
   h.grad_scale = grad_scale;
   h.ws = reinterpret_cast<double*>(s->ws + s->L.hist);

@@ -398,7 +398,9 @@ struct HistCall {
   const void* A[3];
   const void* Ab[3];        // previous step's factors
   const void* shist;        // nwin x R stored weights
-  const double* c;          // device, w_h of each window slot (nwin values)
+  const int64_t* stamps;    // device, time stamp t_h of each window slot (nwin values)
+  int64_t t;                // current time: w_h = w theta^(t - t_h)
+  double w, theta;
   void* G[3];
   void* loss;
   const void* grad_scale;
@@ -408,11 +410,9 @@ struct HistCall {
 };
 size_t hist_ws_bytes(int R);
 hipError_t hist_run(const HistCall& c);
-// The window's weights w_h = w theta^(t - t_h) from device-held slot time
-// stamps (n slots) into out; and one stamp update (a slot push).
-hipError_t hist_weights_run(const int64_t* stamps, int n, int64_t t, double w, double theta, double* out,
-                            hipStream_t stream);
+// One device-held slot stamp update (a window push).
 hipError_t hist_set_stamp_run(int64_t* stamps, int slot, int64_t t, hipStream_t stream);
+constexpr int kMaxWindowModel = 4096;   // GCP_MAX_WINDOW_MODEL
 // Gaussian gradient through the identity of Section 5: after a data pass
 // with y = -2x, adds the model's part G_k += 2 A_k ((*_{l != k} A_l'A_l) o S),
 // S = s_t s_t' + sum_h c_h s_h s_h' (c.shist, c.c over c.nwin slots), and

@@ -36,10 +36,20 @@ struct HistArgs {
   const T* gscale;
   double* ws;
   int* status;
-  const double* c;   // device, w_h of each window slot
+  const int64_t* stamps;   // device, t_h of each window slot
+  int64_t t;
+  double w, theta;
   int I[3];
   int R, nwin, want;
 };
+
+// The window's weights w_h = w theta^(t - t_h) from the device-held slot
+// stamps, into the workgroup's LDS (every thread of the one workgroup).
+template <typename T>
+__device__ void window_weights(const HistArgs<T>& a, double* cw) {
+  for (int h = threadIdx.x; h < a.nwin; h += kHistThreads) cw[h] = a.w * pow(a.theta, (double)(a.t - a.stamps[h]));
+  __syncthreads();
+}
 
 // Row i of the Gram matrix X_k' Y_k (kind 0: A'A, 1: Abar'A, 2: Abar'Abar).
 // The workgroup's threads are (column j, row chunk c) with RP >= R columns
@@ -87,11 +97,13 @@ __global__ void __launch_bounds__(kHistThreads) hist_combine(HistArgs<T> a) {
   const double* Q = a.ws + gram_off(1, 0, R);
   const double* O = a.ws + gram_off(2, 0, R);
   const size_t RR = (size_t)R * R;
+  __shared__ double cw[kMaxWindowModel];
+  window_weights(a, cw);
   double f = 0.0;
   for (int e = threadIdx.x; e < R * R; e += kHistThreads) {
     const int i = e / R, j = e - (e / R) * R;
     double sw = 0.0;
-    for (int h = 0; h < a.nwin; ++h) sw += a.c[h] * (double)a.shist[(size_t)h * R + i] * (double)a.shist[(size_t)h * R + j];
+    for (int h = 0; h < a.nwin; ++h) sw += cw[h] * (double)a.shist[(size_t)h * R + i] * (double)a.shist[(size_t)h * R + j];
     const double p0 = P[e], p1 = P[RR + e], p2 = P[2 * RR + e];
     const double q0 = Q[e], q1 = Q[RR + e], q2 = Q[2 * RR + e];
     const double o0 = O[e], o1 = O[RR + e], o2 = O[2 * RR + e];
@@ -152,7 +164,10 @@ hipError_t hist_launch(const HistCall& c) {
   a.gscale = static_cast<const T*>(c.grad_scale);
   a.ws = c.ws;
   a.status = c.status;
-  a.c = c.c;
+  a.stamps = c.stamps;
+  a.t = c.t;
+  a.w = c.w;
+  a.theta = c.theta;
   a.R = c.R;
   a.nwin = c.nwin;
   a.want = c.want;
@@ -173,10 +188,12 @@ __global__ void __launch_bounds__(kHistThreads) id_combine(HistArgs<T> a, const 
   const int R = a.R;
   const double* P = a.ws + gram_off(0, 0, R);
   const size_t RR = (size_t)R * R;
+  __shared__ double cw[kMaxWindowModel];
+  window_weights(a, cw);
   for (int e = threadIdx.x; e < R * R; e += kHistThreads) {
     const int i = e / R, j = e - (e / R) * R;
     double sw = (double)st[i] * (double)st[j];
-    for (int h = 0; h < a.nwin; ++h) sw += a.c[h] * (double)a.shist[(size_t)h * R + i] * (double)a.shist[(size_t)h * R + j];
+    for (int h = 0; h < a.nwin; ++h) sw += cw[h] * (double)a.shist[(size_t)h * R + i] * (double)a.shist[(size_t)h * R + j];
     const double p0 = P[e], p1 = P[RR + e], p2 = P[2 * RR + e];
     a.ws[b_off(0, R) + e] = sw * (p1 * p2);
     a.ws[b_off(1, R) + e] = sw * (p0 * p2);
@@ -224,7 +241,10 @@ hipError_t ident_launch(const HistCall& c, const void* s_t, void* g_s) {
   a.gscale = nullptr;
   a.ws = c.ws;
   a.status = c.status;
-  a.c = c.c;
+  a.stamps = c.stamps;
+  a.t = c.t;
+  a.w = c.w;
+  a.theta = c.theta;
   a.R = c.R;
   a.nwin = c.nwin;
   a.want = kWantGrad;
@@ -245,21 +265,8 @@ hipError_t ident_run(const HistCall& c, const void* s_t, void* g_s) {
 }
 
 namespace {
-// w_h = w theta^(t - t_h) of every window slot from the device-held stamps
-__global__ void k_hist_weights(const int64_t* __restrict__ stamps, int n, int64_t t, double w, double theta,
-                               double* __restrict__ out) {
-  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x)
-    out[h] = w * pow(theta, (double)(t - stamps[h]));
-}
 __global__ void k_set_stamp(int64_t* stamps, int slot, int64_t t) { stamps[slot] = t; }
 }  // namespace
-
-hipError_t hist_weights_run(const int64_t* stamps, int n, int64_t t, double w, double theta, double* out,
-                            hipStream_t stream) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hist_weights, dim3((n + 255) / 256), dim3(256), 0, stream, stamps, n, t, w, theta, out);
-  return hipGetLastError();
-}
 
 hipError_t hist_set_stamp_run(int64_t* stamps, int slot, int64_t t, hipStream_t stream) {
   hipLaunchKernelGGL(k_set_stamp, dim3(1), dim3(1), 0, stream, stamps, slot, t);
