@@ -1658,7 +1658,7 @@ BatchLayout batch_layout(gcp_stream* const* streams, int32_t n) {
   L.desc_step = off; off = align_up(off + n * sizeof(BatchDesc), 256);
   L.state = off; off = align_up(off + n * sizeof(BatchState), 256);
   L.items = off; off = align_up(off + (size_t)L.nitems * sizeof(int2), 256);
-  static_assert(kBatchVariants <= 32, "work counters precede the status word");
+  static_assert(kBatchVariants <= 48, "work counters precede the status word");
   L.counter = off; off += 256;
   L.outstart = off; off = align_up(off + n * sizeof(int64_t), 256);
   L.facstart = off; off = align_up(off + n * sizeof(int64_t), 256);
@@ -1811,7 +1811,7 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   b->io.assign(io, io + n);
   b->st = hip_stream;
   b->ws = ws;
-  b->status = reinterpret_cast<int*>(ws + L.counter) + 32;   // after the kBatchVariants counters
+  b->status = reinterpret_cast<int*>(ws + L.counter) + 48;   // after the kBatchVariants counters
   b->tau_f = streams[0]->p.tau_f;
   b->kappa_f = streams[0]->p.kappa_f;
   BatchRun r;

@@ -315,10 +315,11 @@ struct BatchState {                // per stream, advanced on the device
 // 32 x 32 -> 64-bit multiply-add), else 4 bytes at a time.
 inline bool dma16_ok(int I3) { return I3 % 4 == 0 && I3 < (1 << 29); }
 
-// Variants of the batched tile code: loss x (rank tile 16/32) x (one/two
-// h-tiles) x (16- or 4-byte slice-row copies), index
-// loss * 8 + (R > 16) * 4 + (window + 1 > 16) * 2 + dma16_ok(I3).
-constexpr int kBatchVariants = 24;
+// Variants of the batched tile code: loss x (rank tile 16/32) x (one h-tile,
+// two h-tiles, or one h-tile with two pairs per step for windows of at
+// most 7 slots) x (16- or 4-byte slice-row copies), index
+// loss * 12 + (R > 16) * 6 + mode * 2 + dma16_ok(I3).
+constexpr int kBatchVariants = 36;
 
 constexpr int kBatchLanes = 4;   // HIP streams the variant launches are spread over
 struct BatchRun {

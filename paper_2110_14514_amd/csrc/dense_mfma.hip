@@ -238,10 +238,11 @@ __global__ void __launch_bounds__(256) batch_window_copy(const BatchDesc* __rest
 }  // namespace
 
 int batch_variant(int loss, int R, int H, int I3) {
-  return loss * 8 + (R > 16 ? 4 : 0) + (H + 1 > 16 ? 2 : 0) + (dma16_ok(I3) ? 1 : 0);
+  const int mode = H + 1 > 16 ? 1 : (H + 1 <= 8 ? 2 : 0);
+  return loss * 12 + (R > 16 ? 6 : 0) + mode * 2 + (dma16_ok(I3) ? 1 : 0);
 }
 
-bool batch_variant_r16(int v) { return (v & 6) == 0; }
+bool batch_variant_r16(int v) { return v % 12 < 6 && (v % 6) / 2 != 1; }
 
 hipError_t batch_grad_run(const BatchRun& b, int want) {
   // One persistent launch per variant present, each over its own slice of
@@ -260,7 +261,7 @@ hipError_t batch_grad_run(const BatchRun& b, int want) {
   for (int i = 0; i < b.nvar; ++i) {
     const int v = b.vorder[i];
     const hipStream_t st = b.vlane[v] == 0 ? b.stream : b.lane[b.vlane[v]];
-    switch (v >> 3) {
+    switch (v / 12) {
       case 0: batch_launch_gaussian(b, v, want, st); break;
       case 1: batch_launch_poisson(b, v, want, st); break;
       default: batch_launch_bernoulli(b, v, want, st); break;

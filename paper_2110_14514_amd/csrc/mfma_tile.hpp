@@ -78,10 +78,18 @@ struct MArgs {
 };
 
 // Per-wave LDS ring of the staged pipeline: kStages stages, each holding
-// 16*NH slice rows of 32 values and the pair's two factor rows (64 values).
+// 16*NH slice rows of 32 values and the pair's two factor rows (64 values:
+// A1 row at 0, A2 row at 32).  With two pairs per stage (PK = 2) pair B's
+// rows sit at pair_b_offset: in the unused upper halves (16, 48) at rank
+// tile 16, after pair A's (64, 96) at rank tile 32.
 constexpr int kStages = 3;
-__host__ __device__ constexpr int stage_floats(int NH) { return 16 * NH * 32 + 64; }
-__host__ __device__ constexpr int ring_floats(int NH) { return NH <= 2 ? kWaves * kStages * stage_floats(NH) : 0; }
+__host__ __device__ constexpr int pair_b_offset(int RT) { return RT > 16 ? 64 : 16; }
+__host__ __device__ constexpr int stage_floats(int NH, int PK = 1, int RT = 16) {
+  return 16 * NH * 32 + (PK == 2 && RT > 16 ? 128 : 64);
+}
+__host__ __device__ constexpr int ring_floats(int NH, int PK = 1, int RT = 16) {
+  return NH <= 2 ? kWaves * kStages * stage_floats(NH, PK, RT) : 0;
+}
 
 // LDS floats used by one workgroup at rank tile RT and NH h-tiles: the
 // mode-3 combine rows (NH > 2; with NH <= 2 the idle staging rings serve),
@@ -400,10 +408,16 @@ __device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
 // entry i3 is bit i3 % 32 of word i3 / 32, X_t and the window alike).  A
 // stage then holds one word per slice row (the row's 32-entry group) and
 // the values are unpacked when the stage is read.
-template <int LOSS, int RT, int NH, bool DMA16, int NK = 0, bool XB = false>
+// PK = 2: a window of at most 8 slices, two pairs per step.  GEMM1's 16
+// rows hold slot 8p + h for slice h of the step's pair p (accumulator
+// registers 0-1: pair A, 2-3: pair B), so the model, the loss terms and
+// GEMM2's K-steps carry no padding rows; GEMM2 splits its K-steps by pair
+// (0-1: A, 2-3: B), and the mode products follow per pair.
+template <int LOSS, int RT, int NH, bool DMA16, int NK = 0, bool XB = false, int PK = 1>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
                                           float* ring, const float* cl, float* a3t) {
   static_assert(!XB || (NH <= 2 && !DMA16), "bit-packed slices take the staged 4-byte path");
+  static_assert(PK == 1 || (PK == 2 && NH == 1), "two pairs per step: one h-tile");
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
@@ -426,7 +440,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = lane & 15, g = lane >> 4;
   // this wave's staging ring (NH <= 2)
-  float* ring_w = ring + wave * kStages * stage_floats(NH);
+  float* ring_w = ring + wave * kStages * stage_floats(NH, PK, RT);
   const int R = a.R, ns = a.ns, I1 = a.I1, I2 = a.I2, I3 = a.I3;
   const int blk = wgi * kWaves + wave;
   const bool active = blk < a.nblocks;
@@ -469,13 +483,16 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   // base pointer of the slice each (h-tile, register) row of this lane reads
   const float* sb[NH][4];
   bool hv[NH][4], sr[NH][4];   // row inside the window; row is a stored slice
+  // slice held by a row slot (PK = 2: slot 8p + h, slice h of pair p)
+  auto slot_slice = [](int slot) { return PK == 2 ? (slot & 7) : slot; };
 #pragma unroll
   for (int ht = 0; ht < NH; ++ht) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) A1op[ht][t] = MLoss<LOSS>::kM * sval(16 * ht + 4 * (n & 3) + (n >> 2), jt[t]);
+    for (int t = 0; t < NT; ++t)
+      A1op[ht][t] = MLoss<LOSS>::kM * sval(slot_slice(16 * ht + 4 * (n & 3) + (n >> 2)), jt[t]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int h = 16 * ht + 4 * r + g;
+      const int h = slot_slice(16 * ht + 4 * r + g);
       cv[ht][r] = h < ns ? cl[h] : 0.f;
       hv[ht][r] = h < ns;
       sb[ht][r] = (h == 0 || h >= ns) ? a.Xt : a.ring + (size_t)(h - 1) * a.rstride;
@@ -486,7 +503,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int h = 16 * ht + 4 * t + g;
+        const int h = slot_slice(16 * ht + 4 * t + g);
         A2op[mt][ht][t] = MLoss<LOSS>::kY * (h < ns ? cl[h] : 0.f) * sval(h, 16 * mt + n);
       }
   }
@@ -498,7 +515,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   if constexpr (NH <= 2) {
     // slice rows past the window are never loaded into the ring; they must
     // hold finite values (their products are multiplied by zero weights)
-    for (int idx = lane; idx < kStages * stage_floats(NH); idx += 64) ring_w[idx] = 0.f;
+    for (int idx = lane; idx < kStages * stage_floats(NH, PK, RT); idx += 64) ring_w[idx] = 0.f;
     // the zeros must land before any direct-to-LDS copy into the ring
 #if defined(__HIP_DEVICE_COMPILE__)
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -593,6 +610,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       // at load time would force a wait for the loads.
       struct Buf {
         float x[NH][4][NU], a1[NT], a2[NT], a1n[NM], a2n[NM];
+        float b1[PK == 2 ? NT : 1], b2[PK == 2 ? NT : 1], b1n[NM], b2n[NM];   // PK = 2: pair B's rows
       };
       Buf bA, bB;
       auto load_pair = [&](int q, Buf& b) {
@@ -786,6 +804,123 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         }
       };
 
+      // PK = 2: pairs A (local i1 ai1, i2 ai2) and B (bi1, bi2; bvalid false
+      // past the block's last pair, whose rows are then pair A's again) in
+      // one 16-row tile: slot 8p + h holds slice h of pair p.
+      auto compute2 = [&](int ai1, int ai2, int bi1, int bi2, bool bvalid, const Buf& b) {
+        float WA[NT], WB[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          WA[t] = b.a1[t] * b.a2[t];
+          WB[t] = bvalid ? b.b1[t] * b.b2[t] : 0.f;
+        }
+        float WnA[NM], WnB[NM];
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          WnA[mt] = b.a1n[mt] * b.a2n[mt];
+          WnB[mt] = b.b1n[mt] * b.b2n[mt];
+        }
+        // GEMM1's A operand: row n holds slot 4 (n % 4) + n / 4, pair B for
+        // n % 4 >= 2
+        const bool rowb = (n & 2) != 0;
+        float Aw[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Aw[t] = A1op[0][t] * (rowb ? WB[t] : WA[t]);
+        float a3r[NU][NT];
+#pragma unroll
+        for (int u = 0; u < NUA; ++u) a3row(u, a3r[u]);
+        f4 D1[NU];
+#pragma unroll
+        for (int u = 0; u < NUA; ++u) {
+          f4 acc = {0.f, 0.f, 0.f, 0.f};
+          if (LOSS != kGaussianId) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc = mfma(Aw[t], a3r[u][t], acc);
+          }
+          D1[u] = acc;
+        }
+        // register r holds slice 4 (r % 2) + g of pair r / 2; registers 1
+        // and 3 hold slices 4..7, used only when the window has more than 4
+        const bool hi = ns > 4;
+        if (want_loss) {
+          float fl = 0.f;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if ((r & 1) && !hi) continue;
+#pragma unroll
+            for (int u = 0; u < NUA; ++u) {
+              float f = 0.f;
+              D1[u][r] = MLoss<LOSS>::fy(b.x[0][r][u], D1[u][r], cv[0][r], f);
+              fl += (vu[u] && (r < 2 || bvalid)) ? f : 0.f;
+            }
+          }
+          lacc.add(fl);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if ((r & 1) && !hi) continue;
+#pragma unroll
+            for (int u = 0; u < NUA; ++u) D1[u][r] = MLoss<LOSS>::y(b.x[0][r][u], D1[u][r]);
+          }
+        }
+        // temporal-weight gradient: y_t of pair A in register 0, of pair B
+        // in register 2 (lane group 0)
+        {
+          float psA[NT], psB[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) psA[t] = psB[t] = 0.f;
+#pragma unroll
+          for (int u = 0; u < NUA; ++u) {
+            const float ya = __shfl(D1[u][0], n), yb = __shfl(D1[u][2], n);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              psA[t] += ya * a3r[u][t];
+              psB[t] += yb * a3r[u][t];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) gsacc[t] += WA[t] * psA[t] + WB[t] * psB[t];
+        }
+        // GEMM2, transposed, per pair: K-steps 0-1 are pair A's slices,
+        // 2-3 pair B's
+        float VpA[NM], VpB[NM];
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) VpA[mt] = VpB[mt] = 0.f;
+#pragma unroll
+        for (int u = 0; u < NUA; ++u) {
+#pragma unroll
+          for (int mt = 0; mt < NM; ++mt) {
+            f4 accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f};
+            accA = mfma(D1[u][0], A2op[mt][0][0], accA);
+            accB = mfma(D1[u][2], A2op[mt][0][2], accB);
+            if (hi) {
+              accA = mfma(D1[u][1], A2op[mt][0][1], accA);
+              accB = mfma(D1[u][3], A2op[mt][0][3], accB);
+            }
+            const f4 a3v = *reinterpret_cast<const f4*>(a3t + (u * RT + jn[mt]) * kA3TPitch + 4 * g);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              g3T[u][mt][r] += accA[r] * WnA[mt] + (bvalid ? accB[r] * WnB[mt] : 0.f);
+              VpA[mt] += accA[r] * a3v[r];
+              VpB[mt] += accB[r] * a3v[r];
+            }
+          }
+        }
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt) {
+          const float va = sum_lane_groups(VpA[mt]);
+          const float vb = sum_lane_groups(VpB[mt]);
+          if (g == 0 && jn[mt] < R) {
+            lds_add(&g1w[wave][ai1][jn[mt]], va * b.a2n[mt]);
+            lds_add(&g2w[wave][ai2][jn[mt]], va * b.a1n[mt]);
+            if (bvalid) {
+              lds_add(&g1w[wave][bi1][jn[mt]], vb * b.b2n[mt]);
+              lds_add(&g2w[wave][bi2][jn[mt]], vb * b.b1n[mt]);
+            }
+          }
+        }
+      };
+
       if constexpr (VEC && NH <= 2) {
         // Staged pipeline: the slice rows and factor rows of pair q are
         // copied global -> LDS by the direct-to-LDS loads two pairs ahead;
@@ -795,7 +930,9 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // a valid row into padding that is never used), so the waits are
         // compile-time constants.
         constexpr int KX = XB ? 1 : (DMA16 ? 2 * NH : 8 * NH);   // slice-row copies per stage
-        constexpr int K = KX + 1;                      // + the factor rows
+        // + the factor rows (one copy, or one per pair at rank tile 32)
+        constexpr int K = KX + (PK == 2 && RT > 16 ? 2 : 1);
+        constexpr int SFP = stage_floats(NH, PK, RT);
         // entries past the end of the row copy from the group start instead
         // (finite values whose terms are masked)
         const size_t eoff = (size_t)(c0 + esub < I3 ? c0 + esub : c0);
@@ -811,7 +948,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         if constexpr (DMA16) {
 #pragma unroll
           for (int k = 0; k < KX; ++k) {
-            const int h = 8 * k + hsub;
+            // PK = 2: copy k carries slice hsub of pair k
+            const int h = PK == 2 ? hsub : 8 * k + hsub;
             src16[k] = reinterpret_cast<uint64_t>(row_src(h));
             pit16[k] = 4u * ((h >= 1 && h < ns) ? (uint32_t)a.rp3 : (uint32_t)I3);
           }
@@ -822,59 +960,97 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         const float* xtl = a.Xt + eoff;
         // pair of copy step p (row-major over the block), advanced incrementally
         int pi1 = 0, pi2 = 0;
-        // bit-packed rows: lane l copies the group's word of slice row l
-        // (rows past the window copy the current slice's word)
+        // bit-packed rows: lane l copies the group's word of row slot l, slice
+        // l (PK = 2: slice l % 8 of pair l / 8); rows past the window copy
+        // the current slice's word
+        const int wsl = PK == 2 ? (lane & 7) : lane;
         const uint32_t* wrow = reinterpret_cast<const uint32_t*>(
-                                   (lane == 0 || lane >= ns) ? a.Xt : a.ring + (size_t)(lane - 1) * a.rstride) +
+                                   (wsl == 0 || wsl >= ns || (PK == 2 && lane >= 16))
+                                       ? a.Xt
+                                       : a.ring + (size_t)(wsl - 1) * a.rstride) +
                                c0 / 32;
+        // stage st's pairs: (pi1, pi2) and, with PK = 2, the next pair of the
+        // block (the same pair again past the block's last pair: its values
+        // are loaded but never used)
         auto issue = [&](int st) {
-          const size_t pair = (size_t)(i10 + pi1) * I2 + (i20 + pi2);
-          float* stg = ring_w + st * stage_floats(NH);
-          if constexpr (XB) {
-            load_to_lds(reinterpret_cast<const float*>(wrow + pair * (size_t)a.rpw), stg, 4);
-          } else if constexpr (DMA16) {
-            const uint32_t p32 = (uint32_t)pair;
-#pragma unroll
-            for (int k = 0; k < KX; ++k)
-              load_to_lds(reinterpret_cast<const float*>((uint64_t)p32 * pit16[k] + src16[k]), stg + 256 * k, 16);
-          } else {
-            const size_t rowx = pair * I3, rowr = pair * a.rp3;
-#pragma unroll
-            for (int k = 0; k < KX; ++k) {
-              const int h = 2 * k + hsub;
-              const bool stored = h >= 1 && h < ns;
-              const float* sp = stored ? ringl + ((size_t)(2 * k - 1) * a.rstride + rowr) : xtl + rowx;
-              load_to_lds(sp, stg + 64 * k, 4);
-            }
-          }
-          // factor rows: lanes 0-31 copy row i1 of A1, lanes 32-63 row i2 of
-          // A2; columns j >= R are never written and keep their zeros
-          if ((lane & 31) < R) {
-            const float* fsrc = lane < 32 ? a.A1 + (size_t)(i10 + pi1) * R + lane
-                                          : a.A2 + (size_t)(i20 + pi2) * R + (lane - 32);
-            load_to_lds(fsrc, stg + 512 * NH, 4);
-          }
+          const int a1i = i10 + pi1, a2i = i20 + pi2;
           if (++pi2 == n2) {
             pi2 = 0;
             ++pi1;
           }
+          int b1i = a1i, b2i = a2i;
+          if constexpr (PK == 2) {
+            if (pi1 < n1) {
+              b1i = i10 + pi1;
+              b2i = i20 + pi2;
+              if (++pi2 == n2) {
+                pi2 = 0;
+                ++pi1;
+              }
+            }
+          }
+          const size_t pair = (size_t)a1i * I2 + a2i, pairb = (size_t)b1i * I2 + b2i;
+          float* stg = ring_w + st * SFP;
+          if constexpr (XB) {
+            const size_t pw = PK == 2 && (lane & 8) ? pairb : pair;
+            load_to_lds(reinterpret_cast<const float*>(wrow + pw * (size_t)a.rpw), stg, 4);
+          } else if constexpr (DMA16) {
+#pragma unroll
+            for (int k = 0; k < KX; ++k) {
+              const uint32_t p32 = (uint32_t)(PK == 2 && k == 1 ? pairb : pair);
+              load_to_lds(reinterpret_cast<const float*>((uint64_t)p32 * pit16[k] + src16[k]), stg + 256 * k, 16);
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < KX; ++k) {
+              // PK = 2: copies 0-3 carry pair A's slices 2k + hsub, 4-7 pair B's
+              const int kk = PK == 2 ? (k & 3) : k;
+              const size_t pk = PK == 2 && k >= 4 ? pairb : pair;
+              const int h = 2 * kk + hsub;
+              const bool stored = h >= 1 && h < ns;
+              const float* sp = stored ? ringl + ((size_t)(2 * kk - 1) * a.rstride + pk * a.rp3) : xtl + pk * I3;
+              load_to_lds(sp, stg + 64 * k, 4);
+            }
+          }
+          // factor rows: lanes 0-31 copy row i1 of A1, lanes 32-63 row i2 of
+          // A2; columns j >= R are never written and keep their zeros.  Two
+          // pairs at rank tile 16: lanes 16-31 / 48-63 copy pair B's rows
+          // into the upper halves; at rank tile 32 a second copy follows.
+          if constexpr (PK == 2 && RT <= 16) {
+            const int col = lane & 15;
+            const bool pb = (lane & 16) != 0;
+            if (col < R) {
+              const float* fsrc = lane < 32 ? a.A1 + (size_t)(pb ? b1i : a1i) * R + col
+                                            : a.A2 + (size_t)(pb ? b2i : a2i) * R + col;
+              load_to_lds(fsrc, stg + 512 * NH, 4);
+            }
+          } else if ((lane & 31) < R) {
+            const float* fsrc = lane < 32 ? a.A1 + (size_t)a1i * R + lane : a.A2 + (size_t)a2i * R + (lane - 32);
+            load_to_lds(fsrc, stg + 512 * NH, 4);
+            if constexpr (PK == 2) {
+              const float* fsrcb = lane < 32 ? a.A1 + (size_t)b1i * R + lane : a.A2 + (size_t)b2i * R + (lane - 32);
+              load_to_lds(fsrcb, stg + 512 * NH + pair_b_offset(RT), 4);
+            }
+          }
         };
-        if (npairs > 0) issue(0);
-        if (npairs > 1) issue(1);
+        // steps of the loop: one pair each, or two with PK = 2
+        const int nsteps = PK == 2 ? (npairs + 1) / 2 : npairs;
+        if (nsteps > 0) issue(0);
+        if (nsteps > 1) issue(1);
         int ci1 = 0, ci2 = 0;
-        // pair q uses stage q % kStages; the loop is unrolled by kStages so
+        // step q uses stage q % kStages; the loop is unrolled by kStages so
         // that every stage offset is a constant of the LDS instructions
         auto step = [&](auto stage_tag, int q) {
           constexpr int st = decltype(stage_tag)::value;
-          if (q + 2 < npairs) {
+          if (q + 2 < nsteps) {
             issue((st + 2) % kStages);
             wait_vmcnt(2 * K);
-          } else if (q + 1 < npairs) {
+          } else if (q + 1 < nsteps) {
             wait_vmcnt(K);
           } else {
             wait_vmcnt(0);
           }
-          const float* stg = ring_w + st * stage_floats(NH);
+          const float* stg = ring_w + st * SFP;
           Buf b;
 #pragma unroll
           for (int ht = 0; ht < NH; ++ht)
@@ -917,18 +1093,49 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             b.a1n[mt] = fa[jn[mt]];
             b.a2n[mt] = fa[32 + jn[mt]];
           }
-          compute(ci1, ci2, b);
-          if (++ci2 == n2) {
-            ci2 = 0;
-            ++ci1;
+          if constexpr (PK == 2) {
+            const float* fb = fa + pair_b_offset(RT);
+#pragma unroll
+            for (int t4 = 0; t4 < NT / 4; ++t4) {
+              const f4 v1 = *reinterpret_cast<const f4*>(fb + 16 * t4 + 4 * g);
+              const f4 v2 = *reinterpret_cast<const f4*>(fb + 32 + 16 * t4 + 4 * g);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                b.b1[4 * t4 + r] = v1[r];
+                b.b2[4 * t4 + r] = v2[r];
+              }
+            }
+#pragma unroll
+            for (int mt = 0; mt < NM; ++mt) {
+              b.b1n[mt] = fb[jn[mt]];
+              b.b2n[mt] = fb[32 + jn[mt]];
+            }
+            // the step's two pairs in the block's row-major order
+            const int ai1 = ci1, ai2 = ci2;
+            if (++ci2 == n2) {
+              ci2 = 0;
+              ++ci1;
+            }
+            const bool bvalid = ci1 < n1;
+            compute2(ai1, ai2, ci1, ci2, bvalid, b);
+            if (bvalid && ++ci2 == n2) {
+              ci2 = 0;
+              ++ci1;
+            }
+          } else {
+            compute(ci1, ci2, b);
+            if (++ci2 == n2) {
+              ci2 = 0;
+              ++ci1;
+            }
           }
         };
         static_assert(kStages == 3, "the pair loop is unrolled by three");
-        for (int q = 0; q < npairs; q += kStages) {
+        for (int q = 0; q < nsteps; q += kStages) {
           step(std::integral_constant<int, 0>{}, q);
-          if (q + 1 >= npairs) break;
+          if (q + 1 >= nsteps) break;
           step(std::integral_constant<int, 1>{}, q + 1);
-          if (q + 2 >= npairs) break;
+          if (q + 2 >= nsteps) break;
           step(std::integral_constant<int, 2>{}, q + 2);
         }
       } else {
@@ -963,7 +1170,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       // mode-3 rows of the group in its own ring, and the workgroup adds the
       // waves in order (one barrier round instead of one per wave; the sums
       // are the same, in the same order).
-      constexpr int SF = stage_floats(NH);
+      constexpr int SF = stage_floats(NH, PK, RT);
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
@@ -981,7 +1188,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       __syncthreads();
       // the rows may have covered stage 0's factor columns, which must stay
       // zero past R
-      if constexpr (SW * RT > 512 * NH) ring_w[512 * NH + lane] = 0.f;
+      if constexpr (SW * RT > 512 * NH) {
+        ring_w[512 * NH + lane] = 0.f;
+        if constexpr (PK == 2 && RT > 16) ring_w[512 * NH + 64 + lane] = 0.f;
+      }
     } else {
       // combine the waves' mode-3 rows of this group in wave order
       for (int idx = tid; idx < SW * (RT + 1); idx += kThreads) (&g3x[0][0])[idx] = 0.f;
@@ -1045,39 +1255,39 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   }
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false>
+template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false, int PK = 1>
 __device__ __forceinline__ void fused_body(const MArgs& a) {
   __shared__ float g1s[kWaves * kTB * RT];
   __shared__ float g2s[kWaves * kTB * RT];
   __shared__ float sm[lds_floats(RT, NH)];
   // the staging ring is an LDS object of its own: the direct-to-LDS copies
   // write only this array
-  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH, PK, RT) > 0 ? ring_floats(NH, PK, RT) : 4];
   __shared__ float cl[kMaxNs];
   __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH, DMA16, NK, XB>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
+  mfma_tile<LOSS, RT, NH, DMA16, NK, XB, PK>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false>
+template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false, int PK = 1>
 __global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
-  fused_body<LOSS, RT, NH, DMA16, NK, XB>(a);
+  fused_body<LOSS, RT, NH, DMA16, NK, XB, PK>(a);
 }
 
 // Rank tile 16 with one h-tile: the LDS of two workgroups fits a compute
 // unit, so the register budget is held to 128 (four waves per SIMD); the
 // few values that do not fit are spilled outside the pair loop.
-template <int LOSS, bool DMA16, int NK, bool XB = false>
+template <int LOSS, bool DMA16, int NK, bool XB = false, int PK = 1>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 fused_dense_mfma_r16(MArgs a) {
-  fused_body<LOSS, 16, 1, DMA16, NK, XB>(a);
+  fused_body<LOSS, 16, 1, DMA16, NK, XB, PK>(a);
 }
 
 
 // One variant's share of the work list: items [begin, end), taken in order
 // from the variant's own counter.
-template <int LOSS, int RT, int NH, bool DMA16>
+template <int LOSS, int RT, int NH, bool DMA16, int PK = 1>
 __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ desc,
                                                 const BatchState* __restrict__ state,
                                                 const int2* __restrict__ items, int begin, int end,
@@ -1085,7 +1295,7 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
   __shared__ float g1s[kWaves * kTB * RT];
   __shared__ float g2s[kWaves * kTB * RT];
   __shared__ float sm[lds_floats(RT, NH)];
-  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH) > 0 ? ring_floats(NH) : 4];
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH, PK, RT) > 0 ? ring_floats(NH, PK, RT) : 4];
   __shared__ float cl[kMaxNs];
   __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   __shared__ int cur;
@@ -1124,25 +1334,25 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
       cl[h] = v;
     }
     __syncthreads();
-    mfma_tile<LOSS, RT, NH, DMA16>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
+    mfma_tile<LOSS, RT, NH, DMA16, 0, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
     __syncthreads();
   }
 }
 
-template <int LOSS, int RT, int NH, bool DMA16>
+template <int LOSS, int RT, int NH, bool DMA16, int PK = 1>
 __global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
                                                               const BatchState* __restrict__ state,
                                                               const int2* __restrict__ items, int begin, int end,
                                                               int* __restrict__ counter, int want) {
-  batch_grad_body<LOSS, RT, NH, DMA16>(desc, state, items, begin, end, counter, want);
+  batch_grad_body<LOSS, RT, NH, DMA16, PK>(desc, state, items, begin, end, counter, want);
 }
 
 // Rank tile 16, one h-tile: four waves per SIMD, as fused_dense_mfma_r16.
-template <int LOSS, bool DMA16>
+template <int LOSS, bool DMA16, int PK = 1>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 batch_grad_kernel_r16(const BatchDesc* __restrict__ desc, const BatchState* __restrict__ state,
                       const int2* __restrict__ items, int begin, int end, int* __restrict__ counter, int want) {
-  batch_grad_body<LOSS, 16, 1, DMA16>(desc, state, items, begin, end, counter, want);
+  batch_grad_body<LOSS, 16, 1, DMA16, PK>(desc, state, items, begin, end, counter, want);
 }
 
 template <int LOSS, int RT, int NH>
@@ -1174,6 +1384,38 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   const int nk = (c.ns - 16 * (NH - 1) + 3) / 4;
   constexpr bool kBinary = LOSS == kBernoulliLogit || LOSS == kBernoulliOdds;
   if (c.xbits && (!kBinary || NH > 2)) return hipErrorInvalidValue;
+  // a window of at most 8 slices: two pairs per step (PK = 2)
+  if constexpr (NH == 1) {
+    if (c.xbits && c.ns <= 8) {
+      if constexpr (kBinary) {
+        if constexpr (RT == 16)
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+        else
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+      }
+      return hipGetLastError();
+    }
+    if (c.ns <= 8) {
+      if constexpr (RT == 16) {
+        if (dma16)
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, true, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+        else
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+      } else {
+        if (dma16)
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, true, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+        else
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
+                             c.stream, m);
+      }
+      return hipGetLastError();
+    }
+  }
   auto go = [&](auto nkc) {
     constexpr int K = decltype(nkc)::value;
     if constexpr (kBinary && NH <= 2) {
@@ -1232,29 +1474,35 @@ hipError_t by_rank(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p
 
 
 
-template <int LOSS, int RT, int NH, bool DMA16>
+template <int LOSS, int RT, int NH, bool DMA16, int PK = 1>
 void launch_batch_variant(const BatchRun& b, int v, int want, hipStream_t st) {
   const dim3 grid((unsigned)b.vgrid[v]);
   if constexpr (RT == 16 && NH == 1)
-    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS, DMA16>), grid, dim3(kThreads), 0, st, b.desc, b.state,
+    hipLaunchKernelGGL((batch_grad_kernel_r16<LOSS, DMA16, PK>), grid, dim3(kThreads), 0, st, b.desc, b.state,
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
   else
-    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH, DMA16>), grid, dim3(kThreads), 0, st, b.desc, b.state,
+    hipLaunchKernelGGL((batch_grad_kernel<LOSS, RT, NH, DMA16, PK>), grid, dim3(kThreads), 0, st, b.desc, b.state,
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
 }
 
-// variant v = loss * 8 + (R > 16) * 4 + (two h-tiles) * 2 + dma16_ok(I3)
+// variant v = loss * 12 + (R > 16) * 6 + mode * 2 + dma16_ok(I3), mode 0:
+// one h-tile, 1: two h-tiles, 2: one h-tile with two pairs per step
+// (windows of at most 7 slots)
 template <int LOSS>
 void launch_batch_loss(const BatchRun& b, int v, int want, hipStream_t st) {
-  switch (v & 7) {
+  switch (v % 12) {
     case 0: launch_batch_variant<LOSS, 16, 1, false>(b, v, want, st); break;
     case 1: launch_batch_variant<LOSS, 16, 1, true>(b, v, want, st); break;
     case 2: launch_batch_variant<LOSS, 16, 2, false>(b, v, want, st); break;
     case 3: launch_batch_variant<LOSS, 16, 2, true>(b, v, want, st); break;
-    case 4: launch_batch_variant<LOSS, 32, 1, false>(b, v, want, st); break;
-    case 5: launch_batch_variant<LOSS, 32, 1, true>(b, v, want, st); break;
-    case 6: launch_batch_variant<LOSS, 32, 2, false>(b, v, want, st); break;
-    default: launch_batch_variant<LOSS, 32, 2, true>(b, v, want, st); break;
+    case 4: launch_batch_variant<LOSS, 16, 1, false, 2>(b, v, want, st); break;
+    case 5: launch_batch_variant<LOSS, 16, 1, true, 2>(b, v, want, st); break;
+    case 6: launch_batch_variant<LOSS, 32, 1, false>(b, v, want, st); break;
+    case 7: launch_batch_variant<LOSS, 32, 1, true>(b, v, want, st); break;
+    case 8: launch_batch_variant<LOSS, 32, 2, false>(b, v, want, st); break;
+    case 9: launch_batch_variant<LOSS, 32, 2, true>(b, v, want, st); break;
+    case 10: launch_batch_variant<LOSS, 32, 1, false, 2>(b, v, want, st); break;
+    default: launch_batch_variant<LOSS, 32, 1, true, 2>(b, v, want, st); break;
   }
 }
 

@@ -32,6 +32,8 @@ SHAPES = [
     ((11, 13, 52), 16, 6),      # 32-wide group + 20-wide tail (two-tile tail)
     ((12, 10, 64), 32, 20),     # C3's build: rank tile 32, two h-tiles, 16-byte copies
     ((8, 9, 68), 24, 24),       # the same build at rank 24, 25 slices, a 4-wide tail
+    ((7, 5, 33), 16, 7),        # two pairs per step, 8 slices, odd pair count, 4-byte copies
+    ((13, 11, 96), 32, 5),      # two pairs per step at rank tile 32, 16-byte copies
 ]
 
 
