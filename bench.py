@@ -123,17 +123,37 @@ def _time(fn, steps, warmup, sync):
 VALU_FP32_PEAK_TFLOPS = 78.6
 
 
+def _roof(alg_bytes, alg_flops, kern_s, traffic=None, **extra):
+    """Roofline entry of one kernel launch.  The binding roof is the one with
+    the longer minimum time: algorithmic bytes at the HBM peak, or
+    algorithmic FP32 flops at the FP32 matrix-core peak (the contraction's
+    own dtype).  Both fractions are kept beside it."""
+    gbs = alg_bytes / kern_s / 1e9
+    tf = alg_flops / kern_s / 1e12
+    t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = alg_flops / (FP32_PEAK_TFLOPS * 1e12)
+    r = {"traffic": traffic, "kernel_ms": kern_s * 1e3, "alg_bytes_per_launch": alg_bytes,
+         "alg_gflops_per_launch": alg_flops / 1e9,
+         "roof_ms": {"hbm": t_hbm * 1e3, "fp32_mfma": t_mfma * 1e3},
+         "hbm_GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+         "fp32_tflops": tf, "fp32_frac": tf / FP32_PEAK_TFLOPS}
+    if t_mfma > t_hbm:
+        r.update({"bound": "mfma", "achieved": tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": tf / FP32_PEAK_TFLOPS})
+    else:
+        r.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": gbs / HBM_PEAK_GBS})
+    r.update(extra)
+    return r
+
+
 def _line(workload, value_unit, ms, steps, warmup, alg_bytes, alg_flops, kern_s, extra, bound="hbm"):
     ach = alg_bytes / kern_s / 1e9
     out = {"metric": "GCP grad steps/sec + achieved HBM GB/s (% peak), fused vs plain, err<=1e-5",
            "value": 1e3 / ms, "unit": value_unit, "n_gpus": 1, "ms_per_step": ms, "steps": steps,
            "warmup": warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": workload},
-           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel_ms": kern_s * 1e3,
-                        "alg_bytes_per_launch": alg_bytes,
-                        "fp32_tflops": alg_flops / kern_s / 1e12,
-                        "fp32_frac": alg_flops / kern_s / 1e12 / FP32_PEAK_TFLOPS}}
+           "roofline": _roof(alg_bytes, alg_flops, kern_s)}
     if bound == "alu":
         tf = alg_flops / kern_s / 1e12
         out["roofline"].update({"bound": "alu", "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -388,14 +408,9 @@ def bench_c4(args):
                    "streams": len(specs), "entry_slices_per_step": tot_es, "parallelism": "single GPU"},
         "replay_ms": {"median": med, "p10": p10, "p90": p90, "replays": K},
         "stream_steps_per_s": len(specs) * 1e3 / ms_per_step,
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "batched gradient step (tile kernels and their fixed-order reduce, one graph)",
-                     "measured_copy_GBps": copy_gbs, "frac_of_measured_copy": ach / copy_gbs,
-                     "kernel_ms": med, "alg_bytes_per_launch": tot_bytes,
-                     "alg_gflops_per_launch": tot_flops / 1e9,
-                     "fp32_tflops": tot_flops / (med / 1e3) / 1e12,
-                     "fp32_frac": tot_flops / (med / 1e3) / 1e12 / FP32_PEAK_TFLOPS},
+        "roofline": _roof(tot_bytes, tot_flops, med / 1e3, traffic,
+                          kernel="batched gradient step (tile kernels and their fixed-order reduce, one graph)",
+                          measured_copy_GBps=copy_gbs, hbm_frac_of_measured_copy=ach / copy_gbs),
         "plain_ms_per_step": plain_ms,
         "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
         "err_vs_oracle": err,
@@ -829,13 +844,7 @@ def bench_c2(args):
                                "Poisson-log loss, one gcp_loss_grad over X_t and 10 stored slices",
                    "dims": list(dims), "rank": R, "window": H, "loss": loss,
                    "input_sets": nsets, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fused dense objective+gradient kernel",
-                     "kernel_ms": kavg_s * 1e3, "alg_bytes_per_launch": alg_bytes,
-                     "alg_gflops_per_launch": alg_flops / 1e9,
-                     "fp32_tflops": alg_flops / kavg_s / 1e12,
-                     "fp32_frac": alg_flops / kavg_s / 1e12 / FP32_PEAK_TFLOPS},
+        "roofline": _roof(alg_bytes, alg_flops, kavg_s, traffic, kernel="fused dense objective+gradient kernel"),
         "plain_ms_per_step": plain_ms,
         "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
         "err_vs_oracle": err,
