@@ -1651,7 +1651,7 @@ BatchLayout batch_layout(gcp_stream* const* streams, int32_t n) {
   L.nitems = 0;
   for (int i = 0; i < n; ++i) {
     const gcp_stream* s = streams[i];
-    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2], s->plan_target));
+    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2], kBatchTileWaves, s->plan_target));
     L.nitems += L.plans.back().nwg;
   }
   L.desc_out = off; off = align_up(off + n * sizeof(BatchDesc), 256);

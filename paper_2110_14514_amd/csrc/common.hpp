@@ -234,7 +234,15 @@ bool mfma_supported(int R, int ns, int dtype);
 constexpr int kPlanTargets[] = {1024, 2048, 4096, 8192, 16384};
 constexpr int kNumPlanTargets = 5;
 constexpr int kDefaultPlanTarget = 4096;
-MfmaPlan mfma_plan(int I1, int I2, int I3, int target = kDefaultPlanTarget);
+// Waves per workgroup of the matrix-core tile builds.  A single stream's
+// rank-32 builds take four: their LDS allows one eight-wave workgroup per
+// compute unit, but two or three four-wave ones, and one that finishes is
+// replaced while the others keep the unit busy.  Rank 16 and the batched
+// builds (whose work list already keeps every unit fed) take eight.
+constexpr int kBatchTileWaves = 8;
+constexpr int single_tile_waves(int R) { return R > 16 ? 4 : 8; }
+// waves: waves per workgroup of the launch the plan is for
+MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target = kDefaultPlanTarget);
 hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                              float* gsp, float* lossp);
 // Per-loss instantiations of the matrix-core tile code (one translation unit

@@ -94,7 +94,7 @@ PartLayout part_layout(int I1, int I2, int I3, int R, size_t es) {
 }
 
 PartLayout part_layout_mfma(int I1, int I2, int I3, int R, int target) {
-  MfmaPlan m = mfma_plan(I1, I2, I3, target);
+  MfmaPlan m = mfma_plan(I1, I2, I3, single_tile_waves(R), target);
   return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2, m.nb1, m.nwg, m.nwg);
 }
 
@@ -512,7 +512,7 @@ hipError_t dense_fused_run(const DenseCall& c) {
     use_mfma = true;
   }
   if (use_mfma) {
-    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, c.plan_target);
+    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, single_tile_waves(c.R), c.plan_target);
     PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R, c.plan_target);
     if (pl.total > c.part_bytes) return hipErrorInvalidValue;
     char* base = static_cast<char*>(c.part);

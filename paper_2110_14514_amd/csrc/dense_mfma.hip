@@ -8,7 +8,7 @@ namespace gcp {
 
 bool mfma_supported(int R, int ns, int dtype) { return dtype == 0 && R >= 1 && R <= 32 && ns <= 64; }
 
-MfmaPlan mfma_plan(int I1, int I2, int I3, int target) {
+MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target) {
   (void)I3;
   MfmaPlan p;
   const long pairs = (long)I1 * I2;
@@ -19,7 +19,7 @@ MfmaPlan mfma_plan(int I1, int I2, int I3, int target) {
   p.nb1 = (I1 + p.tb1 - 1) / p.tb1;
   p.nb2 = (I2 + p.tb2 - 1) / p.tb2;
   p.nblocks = p.nb1 * p.nb2;
-  p.nwg = (p.nblocks + kWaves - 1) / kWaves;
+  p.nwg = (p.nblocks + waves - 1) / waves;
   return p;
 }
 

@@ -46,9 +46,17 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 
-constexpr int kWaves = 8;
+constexpr int kWaves = kBatchTileWaves;   // rank tile 16 and the batched builds
 constexpr int kThreads = 64 * kWaves;
 constexpr int kTB = 16;
+// waves per workgroup of a single stream's build at rank tile RT
+__host__ __device__ constexpr int tile_waves(int RT) { return single_tile_waves(RT); }
+// Minimum waves per SIMD a single stream's build is compiled for (its
+// register budget): rank tile 32 with one h-tile, one pair per step and
+// 16-byte copies fits three four-wave workgroups per compute unit in 168
+// registers; the other builds two workgroups.
+template <int RT, int NH, int PK, bool DMA16>
+constexpr int tile_min_waves() { return RT == 32 && NH == 1 && PK == 1 && DMA16 ? 3 : 2; }
 
 // Everything one workgroup needs for its tile of pair blocks.  Slice h = 0 is
 // the current slice; slice h >= 1 is window slot h-1 of the ring (slot order),
@@ -87,15 +95,15 @@ __host__ __device__ constexpr int pair_b_offset(int RT) { return RT > 16 ? 64 : 
 __host__ __device__ constexpr int stage_floats(int NH, int PK = 1, int RT = 16) {
   return 16 * NH * 32 + (PK == 2 && RT > 16 ? 128 : 64);
 }
-__host__ __device__ constexpr int ring_floats(int NH, int PK = 1, int RT = 16) {
-  return NH <= 2 ? kWaves * kStages * stage_floats(NH, PK, RT) : 0;
+__host__ __device__ constexpr int ring_floats(int NH, int PK, int RT, int WV) {
+  return NH <= 2 ? WV * kStages * stage_floats(NH, PK, RT) : 0;
 }
 
 // LDS floats used by one workgroup at rank tile RT and NH h-tiles: the
 // mode-3 combine rows (NH > 2; with NH <= 2 the idle staging rings serve),
 // the temporal-gradient rows and the objective partials of the waves
-__host__ __device__ constexpr int lds_floats(int RT, int NH) {
-  return (NH > 2 ? 64 * (RT + 1) : 0) + kWaves * RT + kWaves;
+__host__ __device__ constexpr int lds_floats(int RT, int NH, int WV) {
+  return (NH > 2 ? 64 * (RT + 1) : 0) + WV * (RT + 1);
 }
 __host__ __device__ constexpr int lds_gs_offset(int RT, int NH) { return NH > 2 ? 64 * (RT + 1) : 0; }
 // The group's A3 values in GEMM2's transposed output layout, shared by the
@@ -392,7 +400,7 @@ struct MLoss<kBernoulliOdds> {
 };
 
 // One workgroup's tile: pair blocks wgi*8 .. wgi*8+7 of the stream, output
-// slot wgi.  sm: LDS scratch of lds_floats(RT) floats; cl: c_h table in LDS.
+// slot wgi.  sm: LDS scratch of lds_floats(RT, NH, WV) floats; cl: c_h table in LDS.
 // Registers / GEMM2 K-steps of the last h-tile that hold slices of the window
 // (NK = 0: decided at run time from ns; 1..4: fixed by the instantiation, so
 // the skipped work leaves no branches in the pair loop).
@@ -413,7 +421,7 @@ __device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
 // registers 0-1: pair A, 2-3: pair B), so the model, the loss terms and
 // GEMM2's K-steps carry no padding rows; GEMM2 splits its K-steps by pair
 // (0-1: A, 2-3: B), and the mode products follow per pair.
-template <int LOSS, int RT, int NH, bool DMA16, int NK = 0, bool XB = false, int PK = 1>
+template <int LOSS, int RT, int NH, bool DMA16, int NK = 0, bool XB = false, int PK = 1, int WV = kWaves>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
                                           float* ring, const float* cl, float* a3t) {
   static_assert(!XB || (NH <= 2 && !DMA16), "bit-packed slices take the staged 4-byte path");
@@ -432,7 +440,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   float(*g2w)[kTB][RT] = reinterpret_cast<float(*)[kTB][RT]>(g2s);
   float(*g3x)[RT + 1] = reinterpret_cast<float(*)[RT + 1]>(sm);  // SW rows used
   float(*gsx)[RT] = reinterpret_cast<float(*)[RT]>(sm + lds_gs_offset(RT, NH));
-  float* lsx = sm + lds_gs_offset(RT, NH) + kWaves * RT;
+  constexpr int NTH = 64 * WV;
+  float* lsx = sm + lds_gs_offset(RT, NH) + WV * RT;
 
   const int tid = threadIdx.x;
   // the wave index is uniform across the wave: keeping it scalar keeps all
@@ -442,7 +451,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   // this wave's staging ring (NH <= 2)
   float* ring_w = ring + wave * kStages * stage_floats(NH, PK, RT);
   const int R = a.R, ns = a.ns, I1 = a.I1, I2 = a.I2, I3 = a.I3;
-  const int blk = wgi * kWaves + wave;
+  const int blk = wgi * WV + wave;
   const bool active = blk < a.nblocks;
   const int b1 = active ? blk / a.nb2 : 0, b2 = active ? blk % a.nb2 : 0;
   const int i10 = b1 * a.tb1, i20 = b2 * a.tb2;
@@ -574,7 +583,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     // barrier that ended it.  Entry of column c of tile u: c0 + NU c + u
     // (adjacent entries per lane) or c0 + 16 u + c.
     float* a3g = a3t + 2 * RT * kA3TPitch;
-    for (int idx = tid; idx < NU * RT * 16; idx += kThreads) {
+    for (int idx = tid; idx < NU * RT * 16; idx += NTH) {
       const int u = idx / (RT * 16), j = (idx / 16) % RT, col = idx % 16;
       const int e = adj ? NU * col + u : 16 * u + col;
       const bool ok = (adj || u < nu) && c0 + e < I3 && j < R;
@@ -1178,10 +1187,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
 #pragma unroll
           for (int r = 0; r < 4; ++r) ring_w[eT(u, r) * RT + jn[mt]] = g3T[u][mt][r];
       __syncthreads();
-      for (int idx = tid; idx < SW * RT; idx += kThreads) {
+      for (int idx = tid; idx < SW * RT; idx += NTH) {
         float sum = 0.f;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) sum += ring[w * kStages * SF + idx];
+        for (int w = 0; w < WV; ++w) sum += ring[w * kStages * SF + idx];
         const int l = idx / RT, j = idx - (idx / RT) * RT;
         if (c0 + l < I3 && j < R) a.G3p[((size_t)wgi * I3 + c0 + l) * R + j] = sum;
       }
@@ -1194,9 +1203,9 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
       }
     } else {
       // combine the waves' mode-3 rows of this group in wave order
-      for (int idx = tid; idx < SW * (RT + 1); idx += kThreads) (&g3x[0][0])[idx] = 0.f;
+      for (int idx = tid; idx < SW * (RT + 1); idx += NTH) (&g3x[0][0])[idx] = 0.f;
       __syncthreads();
-      for (int w = 0; w < kWaves; ++w) {
+      for (int w = 0; w < WV; ++w) {
         if (wave == w) {
 #pragma unroll
           for (int u = 0; u < NU; ++u)
@@ -1208,7 +1217,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         }
         __syncthreads();
       }
-      for (int idx = tid; idx < SW * RT; idx += kThreads) {
+      for (int idx = tid; idx < SW * RT; idx += NTH) {
         const int l = idx / RT, j = idx - (idx / RT) * RT;
         if (c0 + l < I3 && j < R) a.G3p[((size_t)wgi * I3 + c0 + l) * R + j] = g3x[l][j];
       }
@@ -1245,33 +1254,35 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   __syncthreads();
   if (tid < R) {
     float s = 0.f;
-    for (int w = 0; w < kWaves; ++w) s += gsx[w][tid];
+    for (int w = 0; w < WV; ++w) s += gsx[w][tid];
     a.gsp[(size_t)wgi * R + tid] = s;
   }
   if (tid == 0) {
     float s = 0.f;
-    for (int w = 0; w < kWaves; ++w) s += lsx[w];
+    for (int w = 0; w < WV; ++w) s += lsx[w];
     a.lossp[wgi] = s;
   }
 }
 
 template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false, int PK = 1>
 __device__ __forceinline__ void fused_body(const MArgs& a) {
-  __shared__ float g1s[kWaves * kTB * RT];
-  __shared__ float g2s[kWaves * kTB * RT];
-  __shared__ float sm[lds_floats(RT, NH)];
+  constexpr int WV = tile_waves(RT);
+  __shared__ float g1s[WV * kTB * RT];
+  __shared__ float g2s[WV * kTB * RT];
+  __shared__ float sm[lds_floats(RT, NH, WV)];
   // the staging ring is an LDS object of its own: the direct-to-LDS copies
   // write only this array
-  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH, PK, RT) > 0 ? ring_floats(NH, PK, RT) : 4];
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH, PK, RT, WV) > 0 ? ring_floats(NH, PK, RT, WV) : 4];
   __shared__ float cl[kMaxNs];
   __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
-  for (int h = threadIdx.x; h < kMaxNs; h += kThreads) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
+  for (int h = threadIdx.x; h < kMaxNs; h += 64 * WV) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH, DMA16, NK, XB, PK>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
+  mfma_tile<LOSS, RT, NH, DMA16, NK, XB, PK, WV>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
 }
 
 template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false, int PK = 1>
-__global__ void __launch_bounds__(kThreads) fused_dense_mfma(MArgs a) {
+__global__ void __launch_bounds__(64 * tile_waves(RT))
+__attribute__((amdgpu_waves_per_eu(tile_min_waves<RT, NH, PK, DMA16>(), 8))) fused_dense_mfma(MArgs a) {
   fused_body<LOSS, RT, NH, DMA16, NK, XB, PK>(a);
 }
 
@@ -1294,8 +1305,8 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
                                                 int* __restrict__ counter, int want) {
   __shared__ float g1s[kWaves * kTB * RT];
   __shared__ float g2s[kWaves * kTB * RT];
-  __shared__ float sm[lds_floats(RT, NH)];
-  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH, PK, RT) > 0 ? ring_floats(NH, PK, RT) : 4];
+  __shared__ float sm[lds_floats(RT, NH, kWaves)];
+  __shared__ __attribute__((aligned(16))) float ring[ring_floats(NH, PK, RT, kWaves) > 0 ? ring_floats(NH, PK, RT, kWaves) : 4];
   __shared__ float cl[kMaxNs];
   __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   __shared__ int cur;
@@ -1392,7 +1403,7 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
           hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0,
                              c.stream, m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, true, 2>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
       }
       return hipGetLastError();
@@ -1407,10 +1418,10 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
                              c.stream, m);
       } else {
         if (dma16)
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, true, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, true, 0, false, 2>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, false, 2>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
       }
       return hipGetLastError();
@@ -1424,13 +1435,13 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
           hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, K, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
                              m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K, true>), dim3(p.nwg), dim3(kThreads), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K, true>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
         return;
       }
     }
     if constexpr (NH > 2) {
-      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, 0>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, 0>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream, m);
     } else if constexpr (RT == 16 && NH == 1) {
       if (dma16)
         hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, true, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
@@ -1438,9 +1449,9 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
         hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
     } else {
       if (dma16)
-        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, true, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, true, K>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream, m);
       else
-        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream, m);
     }
   };
   if constexpr (NH > 2) {

@@ -34,6 +34,9 @@ SHAPES = [
     ((8, 9, 68), 24, 24),       # the same build at rank 24, 25 slices, a 4-wide tail
     ((7, 5, 33), 16, 7),        # two pairs per step, 8 slices, odd pair count, 4-byte copies
     ((13, 11, 96), 32, 5),      # two pairs per step at rank tile 32, 16-byte copies
+    ((9, 7, 45), 32, 6),        # rank tile 32, two pairs per step, odd pair count, 4-byte copies, 13-wide tail
+    ((15, 11, 100), 24, 12),    # rank tile 32, one h-tile with four registers of slices, 16-byte copies
+    ((5, 3, 70), 32, 9),        # 15 pairs: most waves of the four-wave workgroups hold no block
 ]
 
 
