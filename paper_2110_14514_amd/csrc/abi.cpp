@@ -162,7 +162,8 @@ WsLayout layout_for(const gcp_params* p) {
   const int wslices = model ? 0 : p->window;
   L.coo_slot = coo ? align_up((size_t)p->max_nnz * 16, 256) : 0;
   // stored dense slices keep each (i1, i2) row on 128-byte lines: the row
-  // pitch is I3 rounded up to 32 values (the padding is never read);
+  // pitch is I3 rounded up to 32 values (the padding is zeroed at set-up
+  // and read only as the zero tail of a 16-byte copy);
   // bit-packed slices keep their own layout, ceil(I3/32) words per row
   const bool bits = p->slice_kind == GCP_SLICE_BITS;
   L.rp3 = bits ? ((size_t)I3 + 31) / 32 : ((size_t)I3 + 31) / 32 * 32;
@@ -608,6 +609,11 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   if (e == hipSuccess && p->d == 2) e = hipStreamSynchronize(s->st);   // the host row must outlive its copies
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.u, 0, L.fac_elems * s->es, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->ws + L.v, 0, L.fac_elems * s->es, s->st);
+  // the padding of stored rows past I3 must hold finite values: the
+  // matrix-core kernels copy rows 16 bytes at a time
+  if (e == hipSuccess && p->slice_kind == GCP_SLICE_DENSE && !model && p->window > 0 &&
+      s->L.rp3 != (size_t)s->dims[2])
+    e = hipMemsetAsync(s->ws + s->L.ring, 0, (size_t)p->window * s->L.slot_elems * s->es, s->st);
   if (e == hipSuccess && p->kappa_f > 0) {
     e = fac_init_run(reinterpret_cast<FacState*>(s->ws + L.fac), p->alpha_f, s->st);
     if (e == hipSuccess)
@@ -1352,7 +1358,7 @@ void tune_key(char* key, size_t n, const char* arch, const gcp_stream* s) {
   while ((1L << (lp + 1)) <= pairs) ++lp;
   const int ns = 1 + s->nwin;
   snprintf(key, n, "%s loss%d rt%d nh%d dma%d pairs2^%d i3x64:%d", arch, s->p.loss, s->p.rank > 16 ? 32 : 16,
-           (ns + 15) / 16, s->dims[2] % 4 == 0 ? 1 : 0, lp, (s->dims[2] + 63) / 64);
+           (ns + 15) / 16, copy_mode(s->L.rp3, s->dims[2]), lp, (s->dims[2] + 63) / 64);
 }
 
 }  // namespace
@@ -1733,7 +1739,7 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
     d.fac_off1 = (int64_t)s->L.fac_off[1];
     d.fac_off2 = (int64_t)s->L.fac_off[2];
     d.I1 = I1; d.I2 = I2; d.I3 = I3; d.R = R; d.H = s->p.window; d.loss = s->p.loss;
-    d.variant = batch_variant(s->p.loss, R, s->p.window, I3);
+    d.variant = batch_variant(s->p.loss, R, s->p.window, s->L.rp3, I3);
     d.tb1 = m.tb1; d.tb2 = m.tb2; d.nb1 = m.nb1; d.nb2 = m.nb2; d.nblocks = m.nblocks; d.nwg = m.nwg;
     d.w = s->p.w; d.theta = s->p.theta; d.lam = (float)s->p.lambda; d.mu = (float)s->p.mu;
     d.lower = s->p.lower == -INFINITY ? -INFINITY : (float)s->p.lower;
@@ -1780,7 +1786,8 @@ gcp_status gcp_batch_create(gcp_stream* const* streams, const gcp_batch_io* io, 
   // short items
   std::vector<int> var(n);
   for (int i = 0; i < n; ++i)
-    var[i] = batch_variant(streams[i]->p.loss, streams[i]->p.rank, streams[i]->p.window, streams[i]->dims[2]);
+    var[i] = batch_variant(streams[i]->p.loss, streams[i]->p.rank, streams[i]->p.window, streams[i]->L.rp3,
+                           streams[i]->dims[2]);
   std::sort(order.begin(), order.end(), [&](const std::pair<double, int>& x, const std::pair<double, int>& y) {
     if (var[x.second] != var[y.second]) return var[x.second] < var[y.second];
     return x.first > y.first;

@@ -318,15 +318,24 @@ struct BatchState {                // per stream, advanced on the device
   int pending_slot;
   int64_t slot_t[kMaxNs];
 };
-// Slice rows are copied to LDS 16 bytes at a time when they are 16-byte
-// aligned and their byte pitch fits 32 bits (the copy address is one
-// 32 x 32 -> 64-bit multiply-add), else 4 bytes at a time.
-inline bool dma16_ok(int I3) { return I3 % 4 == 0 && I3 < (1 << 29); }
+// Copy mode of the matrix-core kernels' staged slice rows, for stored rows
+// of pitch `pitch` values and a current slice of row length I3: rows are
+// copied to LDS 16 bytes at a time when they are 16-byte aligned and their
+// byte pitch fits 32 bits (the copy address is one 32 x 32 -> 64-bit
+// multiply-add).  2: every row so (I3 a multiple of 4); 1: the stored rows
+// so and the current slice's rows by 4-byte copies of their own; 0: 4-byte
+// copies only.  A stream's window rows are padded to 32 values, so its
+// stored rows always qualify.
+inline int copy_mode(size_t pitch, int I3) {
+  if (pitch % 4 != 0 || pitch >= ((size_t)1 << 29)) return 0;
+  return I3 % 4 == 0 ? 2 : 1;
+}
 
 // Variants of the batched tile code: loss x (rank tile 16/32) x (one h-tile,
 // two h-tiles, or one h-tile with two pairs per step for windows of at
 // most 7 slots) x (16- or 4-byte slice-row copies), index
-// loss * 12 + (R > 16) * 6 + mode * 2 + dma16_ok(I3).
+// loss * 12 + (R > 16) * 6 + mode * 2 + (copy mode 2 ? 1 : 0); batched
+// streams take copy mode 1 or 2.
 constexpr int kBatchVariants = 36;
 
 constexpr int kBatchLanes = 4;   // HIP streams the variant launches are spread over
@@ -353,7 +362,7 @@ struct BatchRun {
   int* status;
   hipStream_t stream;
 };
-int batch_variant(int loss, int R, int H, int I3);
+int batch_variant(int loss, int R, int H, size_t pitch, int I3);
 // Whether variant v runs two workgroups per compute unit.
 bool batch_variant_r16(int v);
 hipError_t batch_grad_run(const BatchRun& b, int want);

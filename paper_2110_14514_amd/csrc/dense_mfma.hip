@@ -237,9 +237,9 @@ __global__ void __launch_bounds__(256) batch_window_copy(const BatchDesc* __rest
 
 }  // namespace
 
-int batch_variant(int loss, int R, int H, int I3) {
+int batch_variant(int loss, int R, int H, size_t pitch, int I3) {
   const int mode = H + 1 > 16 ? 1 : (H + 1 <= 8 ? 2 : 0);
-  return loss * 12 + (R > 16 ? 6 : 0) + mode * 2 + (dma16_ok(I3) ? 1 : 0);
+  return loss * 12 + (R > 16 ? 6 : 0) + mode * 2 + (copy_mode(pitch, I3) == 2 ? 1 : 0);
 }
 
 bool batch_variant_r16(int v) { return v % 12 < 6 && (v % 6) / 2 != 1; }

@@ -55,8 +55,8 @@ __host__ __device__ constexpr int tile_waves(int RT) { return single_tile_waves(
 // register budget): rank tile 32 with one h-tile, one pair per step and
 // 16-byte copies fits three four-wave workgroups per compute unit in 168
 // registers; the other builds two workgroups.
-template <int RT, int NH, int PK, bool DMA16>
-constexpr int tile_min_waves() { return RT == 32 && NH == 1 && PK == 1 && DMA16 ? 3 : 2; }
+template <int RT, int NH, int PK, int DMA16>
+constexpr int tile_min_waves() { return RT == 32 && NH == 1 && PK == 1 && DMA16 != 0 ? 3 : 2; }
 
 // Everything one workgroup needs for its tile of pair blocks.  Slice h = 0 is
 // the current slice; slice h >= 1 is window slot h-1 of the ring (slot order),
@@ -89,7 +89,11 @@ struct MArgs {
 // 16*NH slice rows of 32 values and the pair's two factor rows (64 values:
 // A1 row at 0, A2 row at 32).  With two pairs per stage (PK = 2) pair B's
 // rows sit at pair_b_offset: in the unused upper halves (16, 48) at rank
-// tile 16, after pair A's (64, 96) at rank tile 32.
+// tile 16, after pair A's (64, 96) at rank tile 32.  XS (16-byte copies of
+// the stored rows): row i holds stored slice i + 1, and the last row of the
+// pair's rows (16 NH - 1, or 8p + 7 with PK = 2), whose slice is always past
+// the window, holds the current slice, copied 4 bytes at a time because its
+// start need not be 16-byte aligned.
 constexpr int kStages = 3;
 __host__ __device__ constexpr int pair_b_offset(int RT) { return RT > 16 ? 64 : 16; }
 __host__ __device__ constexpr int stage_floats(int NH, int PK = 1, int RT = 16) {
@@ -168,6 +172,9 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
   (void)n;
 #endif
 }
+
+// A row of zeros: the source of staged rows past the window.
+__device__ __attribute__((aligned(16))) float g_zero_row[32];
 
 // Direct global -> LDS copy of `bytes` (4 or 16) per lane: lane i writes at
 // lds + i * bytes (lds is wave-uniform); completion is counted by vmcnt.
@@ -421,11 +428,15 @@ __device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
 // registers 0-1: pair A, 2-3: pair B), so the model, the loss terms and
 // GEMM2's K-steps carry no padding rows; GEMM2 splits its K-steps by pair
 // (0-1: A, 2-3: B), and the mode products follow per pair.
-template <int LOSS, int RT, int NH, bool DMA16, int NK = 0, bool XB = false, int PK = 1, int WV = kWaves>
+template <int LOSS, int RT, int NH, int DMA16, int NK = 0, bool XB = false, int PK = 1, int WV = kWaves>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
                                           float* ring, const float* cl, float* a3t) {
-  static_assert(!XB || (NH <= 2 && !DMA16), "bit-packed slices take the staged 4-byte path");
+  static_assert(!XB || (NH <= 2 && DMA16 == 0), "bit-packed slices take the staged 4-byte path");
   static_assert(PK == 1 || (PK == 2 && NH == 1), "two pairs per step: one h-tile");
+  // DMA16: copy mode of the staged slice rows (0: 4-byte copies; 1: 16-byte
+  // copies of the stored rows, the current slice's rows by 4-byte copies of
+  // their own (XS); 2: 16-byte copies of every row)
+  constexpr bool XS = DMA16 == 1 && !XB;
   constexpr int NT = RT / 4;   // K steps of GEMM1 = j slots per lane
   constexpr int NM = RT / 16;  // M tiles of GEMM2
   constexpr int LOGNT = NT == 4 ? 2 : 3;
@@ -535,8 +546,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   // lane l copying 4 values of row 8k + l/8; with 4-byte copies instruction
   // k covers rows 2k, 2k+1, lane l copying value l%32 of row 2k + l/32.  Row
   // h >= 1 lies at ring + (h-1) omega, row 0 is the current slice.
-  const int hsub = DMA16 ? (lane >> 3) : (lane >> 5);   // row within an instruction
-  const int esub = DMA16 ? 4 * (lane & 7) : (lane & 31); // entry within the 32-entry group
+  const int hsub = DMA16 != 0 ? (lane >> 3) : (lane >> 5);   // row within an instruction
+  const int esub = DMA16 != 0 ? 4 * (lane & 7) : (lane & 31); // entry within the 32-entry group
   float gsacc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) gsacc[t] = 0.f;
@@ -938,29 +949,45 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
         // takes the same KX + 1 copy instructions (rows past the window copy
         // a valid row into padding that is never used), so the waits are
         // compile-time constants.
-        constexpr int KX = XB ? 1 : (DMA16 ? 2 * NH : 8 * NH);   // slice-row copies per stage
-        // + the factor rows (one copy, or one per pair at rank tile 32)
-        constexpr int K = KX + (PK == 2 && RT > 16 ? 2 : 1);
+        constexpr int KX = XB ? 1 : (DMA16 != 0 ? 2 * NH : 8 * NH);   // slice-row copies per stage
+        // + the factor rows (one copy, or one per pair at rank tile 32),
+        // + the current slice's rows (XS: one copy per pair)
+        constexpr int K = KX + (PK == 2 && RT > 16 ? 2 : 1) + (XS ? PK : 0);
         constexpr int SFP = stage_floats(NH, PK, RT);
         // entries past the end of the row copy from the group start instead
         // (finite values whose terms are masked)
         const size_t eoff = (size_t)(c0 + esub < I3 ? c0 + esub : c0);
-        // per-lane source of row h = rows_per * k + hsub (rows >= ns: X_t)
-        // and its row pitch: stored slices rp3, the current slice I3
-        auto row_src = [&](int h) -> const float* {
-          return (h == 0 || h >= ns) ? a.Xt + eoff : a.ring + (size_t)(h - 1) * a.rstride + eoff;
-        };
-        // 16-byte copies: the lane's address is base + pair x pitch (bytes),
-        // a single 32 x 32 -> 64-bit multiply-add per copy (pair < 2^32)
-        uint64_t src16[DMA16 ? KX : 1];
-        uint32_t pit16[DMA16 ? KX : 1];
-        if constexpr (DMA16) {
+        // XS: entry of the current slice's row copied by this lane
+        const size_t xoff = (size_t)(c0 + (lane & 31) < I3 ? c0 + (lane & 31) : c0);
+        // 16-byte copies of stored slice s (window slot s - 1) at LDS row
+        // s - 1: the lane's address is base + pair x pitch (bytes), a single
+        // 32 x 32 -> 64-bit multiply-add per copy (pair < 2^32).  Rows past
+        // the window copy a row of zeros (pitch 0) that no term uses; the
+        // lanes of a pair's last row copy nothing (the current slice's row
+        // goes there).  Stored rows keep I3 rounded up to 32 values, so a
+        // 16-byte piece never leaves its row; the values past I3 are zero.
+        uint64_t src16[DMA16 != 0 ? KX : 1];
+        uint32_t pit16[DMA16 != 0 ? KX : 1];
+        if constexpr (XS) {
+#pragma unroll
+          for (int k = 0; k < KX; ++k) {
+            // PK = 2: copy k carries stored slice hsub + 1 of pair k
+            const int h = (PK == 2 ? hsub : 8 * k + hsub) + 1;
+            const bool stored = h < ns;
+            src16[k] = stored ? reinterpret_cast<uint64_t>(a.ring + (size_t)(h - 1) * a.rstride + eoff)
+                              : reinterpret_cast<uint64_t>(g_zero_row + esub);
+            pit16[k] = stored ? 4u * (uint32_t)a.rp3 : 0u;
+          }
+        } else if constexpr (DMA16 == 2) {
+          // every row 16-byte aligned (I3 a multiple of 4): slice h at row h,
+          // rows past the window copy the current slice's row again
 #pragma unroll
           for (int k = 0; k < KX; ++k) {
             // PK = 2: copy k carries slice hsub of pair k
             const int h = PK == 2 ? hsub : 8 * k + hsub;
-            src16[k] = reinterpret_cast<uint64_t>(row_src(h));
-            pit16[k] = 4u * ((h >= 1 && h < ns) ? (uint32_t)a.rp3 : (uint32_t)I3);
+            const bool stored = h >= 1 && h < ns;
+            src16[k] = reinterpret_cast<uint64_t>(stored ? a.ring + (size_t)(h - 1) * a.rstride + eoff : a.Xt + eoff);
+            pit16[k] = 4u * (stored ? (uint32_t)a.rp3 : (uint32_t)I3);
           }
         }
         // 4-byte copies: rows 2k + hsub; base pointers for hsub = 0 / 1 of
@@ -1003,11 +1030,23 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
           if constexpr (XB) {
             const size_t pw = PK == 2 && (lane & 8) ? pairb : pair;
             load_to_lds(reinterpret_cast<const float*>(wrow + pw * (size_t)a.rpw), stg, 4);
-          } else if constexpr (DMA16) {
+          } else if constexpr (DMA16 != 0) {
 #pragma unroll
             for (int k = 0; k < KX; ++k) {
               const uint32_t p32 = (uint32_t)(PK == 2 && k == 1 ? pairb : pair);
-              load_to_lds(reinterpret_cast<const float*>((uint64_t)p32 * pit16[k] + src16[k]), stg + 256 * k, 16);
+              const float* src = reinterpret_cast<const float*>((uint64_t)p32 * pit16[k] + src16[k]);
+              if constexpr (XS) {
+                // lanes 56-63 of the copy holding a pair's last row
+                if ((PK == 2 || k == KX - 1) && lane >= 56) continue;
+              }
+              load_to_lds(src, stg + 256 * k, 16);
+            }
+            if constexpr (XS) {
+              // the current slice's rows, 32 lanes per pair
+              if (lane < 32) {
+                load_to_lds(a.Xt + pair * (size_t)I3 + xoff, stg + (PK == 2 ? 7 : 16 * NH - 1) * 32, 4);
+                if constexpr (PK == 2) load_to_lds(a.Xt + pairb * (size_t)I3 + xoff, stg + 15 * 32, 4);
+              }
             }
           } else {
 #pragma unroll
@@ -1060,6 +1099,20 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
             wait_vmcnt(0);
           }
           const float* stg = ring_w + st * SFP;
+          // LDS offset of the row read by register r of h-tile ht: slice
+          // row 16 ht + 4 r + g, or with XS stored slice s at row s - 1 and
+          // the current slice in the pair's last row
+          auto xrow = [&](int ht, int r) -> int {
+            if constexpr (!XS) {
+              return (16 * ht + 4 * r + g) * 32;
+            } else if constexpr (PK == 2) {
+              const int p = r >> 1, h = 4 * (r & 1) + g;
+              return (h == 0 ? 8 * p + 7 : 8 * p + h - 1) * 32;
+            } else {
+              const int slot = 16 * ht + 4 * r + g;
+              return (slot == 0 ? 16 * NH - 1 : slot - 1) * 32;
+            }
+          };
           Buf b;
 #pragma unroll
           for (int ht = 0; ht < NH; ++ht)
@@ -1076,10 +1129,10 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
                   b.x[ht][r][1] = (float)((w >> (2 * n + 1)) & 1u);
                 }
               } else if constexpr (HALF) {
-                b.x[ht][r][0] = stg[(16 * ht + 4 * r + g) * 32 + n];
+                b.x[ht][r][0] = stg[xrow(ht, r) + n];
                 b.x[ht][r][1] = 0.f;
               } else {
-                const f2 v = *reinterpret_cast<const f2*>(stg + (16 * ht + 4 * r + g) * 32 + 2 * n);
+                const f2 v = *reinterpret_cast<const f2*>(stg + xrow(ht, r) + 2 * n);
                 b.x[ht][r][0] = v[0];
                 b.x[ht][r][1] = v[1];
               }
@@ -1264,7 +1317,7 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   }
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false, int PK = 1>
+template <int LOSS, int RT, int NH, int DMA16, int NK, bool XB = false, int PK = 1>
 __device__ __forceinline__ void fused_body(const MArgs& a) {
   constexpr int WV = tile_waves(RT);
   __shared__ float g1s[WV * kTB * RT];
@@ -1280,7 +1333,7 @@ __device__ __forceinline__ void fused_body(const MArgs& a) {
   mfma_tile<LOSS, RT, NH, DMA16, NK, XB, PK, WV>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int NK, bool XB = false, int PK = 1>
+template <int LOSS, int RT, int NH, int DMA16, int NK, bool XB = false, int PK = 1>
 __global__ void __launch_bounds__(64 * tile_waves(RT))
 __attribute__((amdgpu_waves_per_eu(tile_min_waves<RT, NH, PK, DMA16>(), 8))) fused_dense_mfma(MArgs a) {
   fused_body<LOSS, RT, NH, DMA16, NK, XB, PK>(a);
@@ -1289,7 +1342,7 @@ __attribute__((amdgpu_waves_per_eu(tile_min_waves<RT, NH, PK, DMA16>(), 8))) fus
 // Rank tile 16 with one h-tile: the LDS of two workgroups fits a compute
 // unit, so the register budget is held to 128 (four waves per SIMD); the
 // few values that do not fit are spilled outside the pair loop.
-template <int LOSS, bool DMA16, int NK, bool XB = false, int PK = 1>
+template <int LOSS, int DMA16, int NK, bool XB = false, int PK = 1>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 fused_dense_mfma_r16(MArgs a) {
   fused_body<LOSS, 16, 1, DMA16, NK, XB, PK>(a);
@@ -1298,7 +1351,7 @@ fused_dense_mfma_r16(MArgs a) {
 
 // One variant's share of the work list: items [begin, end), taken in order
 // from the variant's own counter.
-template <int LOSS, int RT, int NH, bool DMA16, int PK = 1>
+template <int LOSS, int RT, int NH, int DMA16, int PK = 1>
 __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ desc,
                                                 const BatchState* __restrict__ state,
                                                 const int2* __restrict__ items, int begin, int end,
@@ -1350,7 +1403,7 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
   }
 }
 
-template <int LOSS, int RT, int NH, bool DMA16, int PK = 1>
+template <int LOSS, int RT, int NH, int DMA16, int PK = 1>
 __global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* __restrict__ desc,
                                                               const BatchState* __restrict__ state,
                                                               const int2* __restrict__ items, int begin, int end,
@@ -1359,7 +1412,7 @@ __global__ void __launch_bounds__(kThreads) batch_grad_kernel(const BatchDesc* _
 }
 
 // Rank tile 16, one h-tile: four waves per SIMD, as fused_dense_mfma_r16.
-template <int LOSS, bool DMA16, int PK = 1>
+template <int LOSS, int DMA16, int PK = 1>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 batch_grad_kernel_r16(const BatchDesc* __restrict__ desc, const BatchState* __restrict__ state,
                       const int2* __restrict__ items, int begin, int end, int* __restrict__ counter, int want) {
@@ -1389,9 +1442,16 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
   a.rpw = (c.I3 + 31) / 32;
-  // 16-byte slice-row copies need 16-byte aligned rows: I3 a multiple of 4;
+  // copy mode of the slice rows (16-byte copies need 16-byte aligned rows);
   // nk: registers of the last h-tile that hold slices of the window
-  const bool dma16 = dma16_ok(c.I3);
+  const int cp = copy_mode(c.ring_pitch, c.I3);
+  auto by_cp = [&](auto f) {
+    switch (cp) {
+      case 2: f(std::integral_constant<int, 2>{}); break;
+      case 1: f(std::integral_constant<int, 1>{}); break;
+      default: f(std::integral_constant<int, 0>{}); break;
+    }
+  };
   const int nk = (c.ns - 16 * (NH - 1) + 3) / 4;
   constexpr bool kBinary = LOSS == kBernoulliLogit || LOSS == kBernoulliOdds;
   if (c.xbits && (!kBinary || NH > 2)) return hipErrorInvalidValue;
@@ -1400,30 +1460,24 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
     if (c.xbits && c.ns <= 8) {
       if constexpr (kBinary) {
         if constexpr (RT == 16)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0,
-                             c.stream, m);
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, 0, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
+                             m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, true, 2>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
-                             c.stream, m);
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, 0, 0, true, 2>), dim3(p.nwg),
+                             dim3(64 * tile_waves(RT)), 0, c.stream, m);
       }
       return hipGetLastError();
     }
     if (c.ns <= 8) {
-      if constexpr (RT == 16) {
-        if (dma16)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, true, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
-                             c.stream, m);
+      by_cp([&](auto cpc) {
+        constexpr int CP = decltype(cpc)::value;
+        if constexpr (RT == 16)
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, CP, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
+                             m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0,
-                             c.stream, m);
-      } else {
-        if (dma16)
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, true, 0, false, 2>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
-                             c.stream, m);
-        else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, false, 0, false, 2>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
-                             c.stream, m);
-      }
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, CP, 0, false, 2>), dim3(p.nwg),
+                             dim3(64 * tile_waves(RT)), 0, c.stream, m);
+      });
       return hipGetLastError();
     }
   }
@@ -1432,26 +1486,25 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
     if constexpr (kBinary && NH <= 2) {
       if (c.xbits) {
         if constexpr (RT == 16 && NH == 1)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, K, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
-                             m);
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, 0, K, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K, true>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, 0, K, true>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
         return;
       }
     }
     if constexpr (NH > 2) {
-      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, 0>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream, m);
-    } else if constexpr (RT == 16 && NH == 1) {
-      if (dma16)
-        hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, true, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
-      else
-        hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, false, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, 0, 0>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream,
+                         m);
     } else {
-      if (dma16)
-        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, true, K>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream, m);
-      else
-        hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, false, K>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream, m);
+      by_cp([&](auto cpc) {
+        constexpr int CP = decltype(cpc)::value;
+        if constexpr (RT == 16 && NH == 1)
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, CP, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+        else
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, CP, K>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
+                             c.stream, m);
+      });
     }
   };
   if constexpr (NH > 2) {
@@ -1485,7 +1538,7 @@ hipError_t by_rank(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p
 
 
 
-template <int LOSS, int RT, int NH, bool DMA16, int PK = 1>
+template <int LOSS, int RT, int NH, int DMA16, int PK = 1>
 void launch_batch_variant(const BatchRun& b, int v, int want, hipStream_t st) {
   const dim3 grid((unsigned)b.vgrid[v]);
   if constexpr (RT == 16 && NH == 1)
@@ -1496,24 +1549,24 @@ void launch_batch_variant(const BatchRun& b, int v, int want, hipStream_t st) {
                        b.items, b.vbegin[v], b.vend[v], b.counter + v, want);
 }
 
-// variant v = loss * 12 + (R > 16) * 6 + mode * 2 + dma16_ok(I3), mode 0:
+// variant v = loss * 12 + (R > 16) * 6 + mode * 2 + (copy mode 2), mode 0:
 // one h-tile, 1: two h-tiles, 2: one h-tile with two pairs per step
 // (windows of at most 7 slots)
 template <int LOSS>
 void launch_batch_loss(const BatchRun& b, int v, int want, hipStream_t st) {
   switch (v % 12) {
-    case 0: launch_batch_variant<LOSS, 16, 1, false>(b, v, want, st); break;
-    case 1: launch_batch_variant<LOSS, 16, 1, true>(b, v, want, st); break;
-    case 2: launch_batch_variant<LOSS, 16, 2, false>(b, v, want, st); break;
-    case 3: launch_batch_variant<LOSS, 16, 2, true>(b, v, want, st); break;
-    case 4: launch_batch_variant<LOSS, 16, 1, false, 2>(b, v, want, st); break;
-    case 5: launch_batch_variant<LOSS, 16, 1, true, 2>(b, v, want, st); break;
-    case 6: launch_batch_variant<LOSS, 32, 1, false>(b, v, want, st); break;
-    case 7: launch_batch_variant<LOSS, 32, 1, true>(b, v, want, st); break;
-    case 8: launch_batch_variant<LOSS, 32, 2, false>(b, v, want, st); break;
-    case 9: launch_batch_variant<LOSS, 32, 2, true>(b, v, want, st); break;
-    case 10: launch_batch_variant<LOSS, 32, 1, false, 2>(b, v, want, st); break;
-    default: launch_batch_variant<LOSS, 32, 1, true, 2>(b, v, want, st); break;
+    case 0: launch_batch_variant<LOSS, 16, 1, 1>(b, v, want, st); break;
+    case 1: launch_batch_variant<LOSS, 16, 1, 2>(b, v, want, st); break;
+    case 2: launch_batch_variant<LOSS, 16, 2, 1>(b, v, want, st); break;
+    case 3: launch_batch_variant<LOSS, 16, 2, 2>(b, v, want, st); break;
+    case 4: launch_batch_variant<LOSS, 16, 1, 1, 2>(b, v, want, st); break;
+    case 5: launch_batch_variant<LOSS, 16, 1, 2, 2>(b, v, want, st); break;
+    case 6: launch_batch_variant<LOSS, 32, 1, 1>(b, v, want, st); break;
+    case 7: launch_batch_variant<LOSS, 32, 1, 2>(b, v, want, st); break;
+    case 8: launch_batch_variant<LOSS, 32, 2, 1>(b, v, want, st); break;
+    case 9: launch_batch_variant<LOSS, 32, 2, 2>(b, v, want, st); break;
+    case 10: launch_batch_variant<LOSS, 32, 1, 1, 2>(b, v, want, st); break;
+    default: launch_batch_variant<LOSS, 32, 1, 2, 2>(b, v, want, st); break;
   }
 }
 

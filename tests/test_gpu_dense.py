@@ -217,14 +217,15 @@ def test_stream_steps_match_oracle():
 
 def _tune_key(st, prob, ns):
     """The autotuner's shape bucket: tile build, pair count by powers of two,
-    I3 by 64-entry groups."""
+    I3 by 64-entry groups.  A stream's stored rows are padded to 32 values,
+    so its copy mode is 2 when I3 is a multiple of 4, else 1."""
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName
     loss_id = {"gaussian": 0, "poisson_log": 1, "bernoulli_logit": 2}[prob.loss]
     d = prob.dims
     lp = (d[0] * d[1]).bit_length() - 1
     return (f"{arch} loss{loss_id} rt{32 if prob.rank > 16 else 16} nh{(ns + 15) // 16} "
-            f"dma{1 if d[2] % 4 == 0 else 0} pairs2^{lp} i3x64:{(d[2] + 63) // 64}")
+            f"dma{2 if d[2] % 4 == 0 else 1} pairs2^{lp} i3x64:{(d[2] + 63) // 64}")
 
 
 @pytest.mark.parametrize("target", [1024, 2048, 4096, 8192, 16384])
