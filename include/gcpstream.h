@@ -466,11 +466,18 @@ typedef struct {
 } gcp_batch_io;
 
 /* Autotuning of a set of streams before they are batched (call it before
- * gcp_batch_workspace_size): for each shape bucket present (see
- * gcp_autotune), the stream with the most window entries is tuned over
- * io[i].X_t, or the bucket's plan is read from cache_path, and every stream
- * of the bucket takes that plan.  *buckets (may be NULL) receives the
- * number of buckets.  Synchronous. */
+ * gcp_batch_workspace_size).  A stream's share of a batched call has a work
+ * plan of its own (pair blocks per stream; default 1024, fewer and larger
+ * blocks than a single stream's since the other streams supply the
+ * parallelism).  This call times one batched objective+gradient call over
+ * the registered io for each candidate plan (512, 1024, 2048, 4096 blocks
+ * per stream), on a scratch workspace it allocates and frees, and gives
+ * every stream the fastest; or it reads the plan from cache_path, keyed on
+ * the device and the batch's shape buckets (see gcp_autotune), and appends
+ * a tuned plan there.  The registered outputs are written.  *buckets (may
+ * be NULL) receives the number of distinct shape buckets.  Synchronous.
+ * Errors: GCP_E_ARG (NULL arguments, n < 1), GCP_E_DEVICE (device calls,
+ * including the scratch allocation), or those of gcp_batch_create. */
 gcp_status gcp_batch_autotune(gcp_stream* const* streams, const gcp_batch_io* io, int32_t n,
                               const char* cache_path, int32_t* buckets);
 

@@ -54,6 +54,7 @@ struct gcp_stream {
   std::vector<hipEvent_t> ev;   // begin/end pairs for gcp_kernel_timing
   int ev_used;
   int plan_target;              // matrix-core work plan chosen by gcp_autotune
+  int batch_plan_target;        // the plan of the stream's share of a batched call
 };
 
 namespace {
@@ -573,6 +574,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   if (!s) return GCP_E_ARG;
   s->p = q;
   s->plan_target = kDefaultPlanTarget;
+  s->batch_plan_target = kBatchPlanTarget;
   s->es = p->dtype == GCP_F64 ? 8 : 4;
   for (int k = 0; k < 3; ++k) s->dims[k] = (int)q.dims[k];
   s->d4[0] = s->d4[1] = 0;
@@ -1561,29 +1563,67 @@ extern "C" gcp_status gcp_batch_autotune(gcp_stream* const* streams, const gcp_b
     tune_key(key, sizeof key, prop.gcnArchName, streams[i]);
     keys[i] = key;
   }
-  int nb = 0;
-  std::vector<char> done(n, 0);
-  for (int i = 0; i < n; ++i) {
-    if (done[i]) continue;
-    int rep = i;
-    auto size = [&](int k) { return (double)streams[k]->omega * (1 + streams[k]->nwin); };
-    for (int k = i; k < n; ++k)
-      if (keys[k] == keys[i] && size(k) > size(rep)) rep = k;
-    gcp_slice x;
-    memset(&x, 0, sizeof x);
-    x.kind = GCP_SLICE_DENSE;
-    x.vals = io[rep].X_t;
-    int32_t plan = 0;
-    gcp_status st = gcp_autotune(streams[rep], &x, cache_path, &plan);
-    if (st != GCP_OK) return st;
-    for (int k = i; k < n; ++k)
-      if (keys[k] == keys[i]) {
-        streams[k]->plan_target = plan;
-        done[k] = 1;
-      }
-    ++nb;
-  }
+  // the batch's key: its shape buckets, sorted, with their counts (FNV-1a)
+  std::vector<std::string> sorted = keys;
+  std::sort(sorted.begin(), sorted.end());
+  uint64_t h = 1469598103934665603ull;
+  for (const std::string& k : sorted)
+    for (unsigned char ch : k + "\n") h = (h ^ ch) * 1099511628211ull;
+  const int nb = (int)(std::unique(sorted.begin(), sorted.end()) - sorted.begin());
   if (buckets) *buckets = nb;
+  char bkey[160];
+  snprintf(bkey, sizeof bkey, "%s batch n%d buckets%d %016llx", prop.gcnArchName, n, nb, (unsigned long long)h);
+  int best = 0;
+  if (cache_lookup(cache_path, bkey, &best) && is_plan_target(best)) {
+    for (int i = 0; i < n; ++i) streams[i]->batch_plan_target = best;
+    return GCP_OK;
+  }
+  // time one batched objective+gradient call per candidate plan, on a
+  // scratch workspace of the candidate's size (the registered outputs are
+  // written and later overwritten)
+  const int cands[] = {512, 1024, 2048, 4096};
+  float best_ms = 1e30f;
+  best = kBatchPlanTarget;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GCP_E_DEVICE;
+  gcp_status st = GCP_OK;
+  for (int c = 0; c < 4 && st == GCP_OK; ++c) {
+    for (int i = 0; i < n; ++i) streams[i]->batch_plan_target = cands[c];
+    size_t bytes = 0;
+    st = gcp_batch_workspace_size(streams, n, &bytes);
+    if (st != GCP_OK) break;
+    void* ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) {
+      st = GCP_E_DEVICE;
+      break;
+    }
+    gcp_batch* b = nullptr;
+    st = gcp_batch_create(streams, io, n, ws, bytes, streams[0]->st, &b);
+    if (st == GCP_OK) st = gcp_batch_loss_grad(b, GCP_WANT_LOSS | GCP_WANT_GRAD);   // warm-up
+    if (st == GCP_OK && hipEventRecord(e0, streams[0]->st) != hipSuccess) st = GCP_E_DEVICE;
+    for (int r = 0; r < 3 && st == GCP_OK; ++r) st = gcp_batch_loss_grad(b, GCP_WANT_LOSS | GCP_WANT_GRAD);
+    if (st == GCP_OK && (hipEventRecord(e1, streams[0]->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      st = GCP_E_DEVICE;
+    float ms = 0.f;
+    if (st == GCP_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = cands[c];
+    }
+    if (b) gcp_batch_destroy(b);
+    if (hipStreamSynchronize(streams[0]->st) != hipSuccess && st == GCP_OK) st = GCP_E_DEVICE;
+    hipFree(ws);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  for (int i = 0; i < n; ++i) streams[i]->batch_plan_target = best;
+  if (st != GCP_OK) return st;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s = %d\n", bkey, best);
+      fclose(f);
+    }
+  }
   return GCP_OK;
 }
 
@@ -1657,7 +1697,7 @@ BatchLayout batch_layout(gcp_stream* const* streams, int32_t n) {
   L.nitems = 0;
   for (int i = 0; i < n; ++i) {
     const gcp_stream* s = streams[i];
-    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2], kBatchTileWaves, s->plan_target));
+    L.plans.push_back(mfma_plan(s->dims[0], s->dims[1], s->dims[2], kBatchTileWaves, s->batch_plan_target));
     L.nitems += L.plans.back().nwg;
   }
   L.desc_out = off; off = align_up(off + n * sizeof(BatchDesc), 256);
