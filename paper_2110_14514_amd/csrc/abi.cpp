@@ -53,7 +53,7 @@ struct gcp_stream {
   int* status;
   std::vector<hipEvent_t> ev;   // begin/end pairs for gcp_kernel_timing
   int ev_used;
-  int plan_target;              // matrix-core work plan chosen by gcp_autotune
+  int plan_target;              // matrix-core work plan chosen by gcp_autotune (0: automatic)
   int batch_plan_target;        // the plan of the stream's share of a batched call
 };
 
@@ -573,7 +573,7 @@ gcp_status gcp_stream_init(const gcp_params* p, const void* const* A0, int32_t n
   gcp_stream* s = new (std::nothrow) gcp_stream();
   if (!s) return GCP_E_ARG;
   s->p = q;
-  s->plan_target = kDefaultPlanTarget;
+  s->plan_target = 0;
   s->batch_plan_target = kBatchPlanTarget;
   s->es = p->dtype == GCP_F64 ? 8 : 4;
   for (int k = 0; k < 3; ++k) s->dims[k] = (int)q.dims[k];

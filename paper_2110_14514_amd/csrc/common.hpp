@@ -248,6 +248,10 @@ constexpr int kBatchTileWaves = 8;
 constexpr int single_tile_waves(int R) { return R > 16 ? 4 : 8; }
 // waves: waves per workgroup of the launch the plan is for
 MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target = kDefaultPlanTarget);
+// Plan target of a single stream's call when none was tuned (a stream's
+// plan_target of 0): the candidate whose workgroups fill their last round
+// of resident workgroups best.
+int auto_plan_target(int I1, int I2, int I3, int R, int ns);
 hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                              float* gsp, float* lossp);
 // Per-loss instantiations of the matrix-core tile code (one translation unit

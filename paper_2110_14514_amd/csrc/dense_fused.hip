@@ -512,8 +512,9 @@ hipError_t dense_fused_run(const DenseCall& c) {
     use_mfma = true;
   }
   if (use_mfma) {
-    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, single_tile_waves(c.R), c.plan_target);
-    PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R, c.plan_target);
+    const int target = c.plan_target > 0 ? c.plan_target : auto_plan_target(c.I1, c.I2, c.I3, c.R, c.ns);
+    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, single_tile_waves(c.R), target);
+    PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R, target);
     if (pl.total > c.part_bytes) return hipErrorInvalidValue;
     char* base = static_cast<char*>(c.part);
     if (c.ev_begin) hipEventRecord(c.ev_begin, c.stream);

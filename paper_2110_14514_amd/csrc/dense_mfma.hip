@@ -23,6 +23,37 @@ MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target) {
   return p;
 }
 
+// A launch runs in rounds of resident workgroups (two per compute unit for
+// every single-stream build but the rank-16 two-h-tile one, which holds a
+// unit alone); a last round of a few workgroups leaves most units idle while
+// it runs.  C3 (1000 x 1000 x 64, rank 32): 4096 blocks make 1056 four-wave
+// workgroups, 2.06 rounds of 512, and took 3.90 ms; 2048 blocks make 993,
+// 1.94 rounds, and took 3.24 ms.  Among 4096, 2048 and 8192 blocks the plan
+// with the fullest last round is taken, 4096 unless another fills it
+// clearly better.
+int auto_plan_target(int I1, int I2, int I3, int R, int ns) {
+  static const int cus = [] {
+    int d = 0, n = 256;
+    if (hipGetDevice(&d) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess)
+      n = 256;
+    return n;
+  }();
+  const int per_cu = (R <= 16 && ns > 16) ? 1 : 2;
+  const double slots = (double)per_cu * cus;
+  int best = kDefaultPlanTarget;
+  double best_fill = -1.0;
+  for (int t : {kDefaultPlanTarget, 2048, 8192}) {
+    const MfmaPlan p = mfma_plan(I1, I2, I3, single_tile_waves(R), t);
+    const double rounds = p.nwg / slots;
+    const double fill = rounds / std::ceil(rounds);
+    if (fill > best_fill + 0.02) {
+      best_fill = fill;
+      best = t;
+    }
+  }
+  return best;
+}
+
 hipError_t dense_mfma_launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p, float* G3p,
                              float* gsp, float* lossp) {
   switch (c.loss) {
