@@ -52,9 +52,10 @@ constexpr int kTB = 16;
 // waves per workgroup of a single stream's build at rank tile RT
 __host__ __device__ constexpr int tile_waves(int RT) { return single_tile_waves(RT); }
 // Minimum waves per SIMD a single stream's build is compiled for (its
-// register budget): rank tile 32 with one h-tile, one pair per step and
-// 16-byte copies fits three four-wave workgroups per compute unit in 168
-// registers; the other builds two workgroups.
+// register budget): 3 (168 registers) for rank tile 32 with one h-tile, one
+// pair per step and 16-byte copies, which fit so without spills in the pair
+// loop (its 54.5 KB of LDS, rounded up to the allocation granule, still
+// admits two workgroups per compute unit); 2 (256 registers) otherwise.
 template <int RT, int NH, int PK, int DMA16>
 constexpr int tile_min_waves() { return RT == 32 && NH == 1 && PK == 1 && DMA16 != 0 ? 3 : 2; }
 
@@ -541,11 +542,12 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 #endif
   }
-  // Staged loads (NH <= 2).  With 16-byte copies (DMA16: rows 16-byte
-  // aligned, I3 a multiple of 4) instruction k covers slice rows 8k .. 8k+7,
-  // lane l copying 4 values of row 8k + l/8; with 4-byte copies instruction
-  // k covers rows 2k, 2k+1, lane l copying value l%32 of row 2k + l/32.  Row
-  // h >= 1 lies at ring + (h-1) omega, row 0 is the current slice.
+  // Staged loads (NH <= 2).  With 16-byte copies (copy mode 1 or 2)
+  // instruction k covers LDS rows 8k .. 8k+7, lane l copying 4 values of row
+  // 8k + l/8; with 4-byte copies instruction k covers rows 2k, 2k+1, lane l
+  // copying value l%32 of row 2k + l/32.  Slice h >= 1 lies at ring + (h-1)
+  // omega, slice 0 is the current slice (its LDS row in copy mode 1: see the
+  // stage layout above).
   const int hsub = DMA16 != 0 ? (lane >> 3) : (lane >> 5);   // row within an instruction
   const int esub = DMA16 != 0 ? 4 * (lane & 7) : (lane & 31); // entry within the 32-entry group
   float gsacc[NT];
