@@ -425,16 +425,20 @@ gcp_status gcp_loss_grad_static(const gcp_params* params, const gcp_slice* X_t, 
 gcp_status gcp_probe_gather(const void* A1, const void* A2, const void* A3, int64_t I1, int64_t I2, int64_t I3,
                             int32_t rank, int64_t ndraws, uint64_t seed, void* records, hipStream_t hip_stream);
 
-/* Autotuner for the matrix-core work plan (how the slice's (i1,i2) pairs are
- * cut into wave blocks).  Times every candidate plan on the device with HIP
- * events over X_t and the current window (synchronous; not for use inside a
- * graph capture), keeps the fastest for this stream (and for batches created
- * afterwards), and appends "<key> = <plan>" to the text file cache_path
- * (NULL: no cache), where the key is the shape bucket "<arch> loss<l>
- * rt<16|32> nh<h-tiles> dma<0|1> pairs2^<floor(log2(I1 I2))>
- * i3x64:<ceil(I3/64)>".  A cache hit (a valid plan for the bucket) skips the
- * timing.  Results are identical for every plan up to summation order.
- * *chosen (may be NULL) receives the plan.  Dense FP32 streams only. */
+/* Autotuner for the matrix-core work plan of a stream's own calls (how the
+ * slice's (i1,i2) pairs are cut into wave blocks: 256, 512, ..., 16384
+ * blocks).  Untuned, a stream takes among 2048, 4096 and 8192 blocks the
+ * plan whose workgroups fill their last round of resident workgroups best.
+ * This call times every candidate plan on the device with HIP events over
+ * X_t and the current window (synchronous; not for use inside a graph
+ * capture), keeps the fastest for this stream, and appends "<key> = <plan>"
+ * to the text file cache_path (NULL: no cache), where the key is the shape
+ * bucket "<arch> loss<l> rt<16|32> nh<h-tiles> dma<copy mode 0|1|2>
+ * pairs2^<floor(log2(I1 I2))> i3x64:<ceil(I3/64)>".  A cache hit (a valid
+ * plan for the bucket) skips the timing.  Batched calls use the plan set by
+ * gcp_batch_autotune instead.  Results are identical for every plan up to
+ * summation order.  *chosen (may be NULL) receives the plan.  Dense FP32
+ * streams only. */
 gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const char* cache_path, int32_t* chosen);
 
 /* ------------------------------------------------------------------------
