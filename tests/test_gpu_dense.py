@@ -37,6 +37,8 @@ SHAPES = [
     ((9, 7, 45), 32, 6),        # rank tile 32, two pairs per step, odd pair count, 4-byte copies, 13-wide tail
     ((15, 11, 100), 24, 12),    # rank tile 32, one h-tile with four registers of slices, 16-byte copies
     ((5, 3, 70), 32, 9),        # 15 pairs: most waves of the four-wave workgroups hold no block
+    ((6, 7, 99), 32, 20),       # two h-tiles at rank tile 32, stored rows by 16-byte copies, I3 not a multiple of 4
+    ((5, 9, 101), 16, 18),      # two h-tiles at rank tile 16, the same copy mode
 ]
 
 
