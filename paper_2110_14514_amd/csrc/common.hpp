@@ -227,6 +227,10 @@ struct DenseCall {
 // Matrix-core (MFMA) variant of the fused kernel: work plan and launcher.
 struct MfmaPlan {
   int tb1, tb2, nb1, nb2, nblocks, nwg;
+  // I3 chunks (whole 32-entry groups, gpc per chunk): a single stream whose
+  // pair tiles fill few compute units gives each (tile, chunk) a workgroup
+  // of its own; the launch has nwg * nch workgroups
+  int nch = 1, gpc = 1 << 30;
 };
 bool mfma_supported(int R, int ns, int dtype);
 // target: wanted number of wave blocks (0 = default).  Candidates the
@@ -247,7 +251,7 @@ constexpr int kBatchPlanTarget = 1024;
 constexpr int kBatchTileWaves = 8;
 constexpr int single_tile_waves(int R) { return R > 16 ? 4 : 8; }
 // waves: waves per workgroup of the launch the plan is for
-MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target = kDefaultPlanTarget);
+MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target = kDefaultPlanTarget, bool chunk_i3 = false);
 // Plan target of a single stream's call when none was tuned (a stream's
 // plan_target of 0): the candidate whose workgroups fill their last round
 // of resident workgroups best.

@@ -94,8 +94,10 @@ PartLayout part_layout(int I1, int I2, int I3, int R, size_t es) {
 }
 
 PartLayout part_layout_mfma(int I1, int I2, int I3, int R, int target) {
-  MfmaPlan m = mfma_plan(I1, I2, I3, single_tile_waves(R), target);
-  return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2, m.nb1, m.nwg, m.nwg);
+  MfmaPlan m = mfma_plan(I1, I2, I3, single_tile_waves(R), target, true);
+  // mode-1/2 rows per (pair block, I3 chunk), mode-3 rows per tile (the
+  // chunks of a tile write disjoint rows), g_s and objective per workgroup
+  return part_layout_slots(I1, I2, I3, R, sizeof(float), m.nb2 * m.nch, m.nb1 * m.nch, m.nwg, m.nwg * m.nch);
 }
 
 // Reduce-scatter of RT per-lane values over the 64 lanes of a wave.  On
@@ -513,7 +515,7 @@ hipError_t dense_fused_run(const DenseCall& c) {
   }
   if (use_mfma) {
     const int target = c.plan_target > 0 ? c.plan_target : auto_plan_target(c.I1, c.I2, c.I3, c.R, c.ns);
-    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, single_tile_waves(c.R), target);
+    MfmaPlan mp = mfma_plan(c.I1, c.I2, c.I3, single_tile_waves(c.R), target, true);
     PartLayout pl = part_layout_mfma(c.I1, c.I2, c.I3, c.R, target);
     if (pl.total > c.part_bytes) return hipErrorInvalidValue;
     char* base = static_cast<char*>(c.part);

@@ -8,7 +8,7 @@ namespace gcp {
 
 bool mfma_supported(int R, int ns, int dtype) { return dtype == 0 && R >= 1 && R <= 32 && ns <= 64; }
 
-MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target) {
+MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target, bool chunk_i3) {
   (void)I3;
   MfmaPlan p;
   const long pairs = (long)I1 * I2;
@@ -20,6 +20,17 @@ MfmaPlan mfma_plan(int I1, int I2, int I3, int waves, int target) {
   p.nb2 = (I2 + p.tb2 - 1) / p.tb2;
   p.nblocks = p.nb1 * p.nb2;
   p.nwg = (p.nblocks + waves - 1) / waves;
+  // Few pair tiles (a matrix slice of 300 x 300 has 300 pairs): split I3 so
+  // that the (tile, chunk) workgroups fill about two per compute unit.
+  if (chunk_i3) {
+    const int nsc = (I3 + 31) / 32;
+    const int slots = 2 * 256;
+    if (2 * p.nwg <= slots && nsc > 1) {
+      const int want = std::min(nsc, slots / p.nwg);
+      p.gpc = (nsc + want - 1) / want;
+      p.nch = (nsc + p.gpc - 1) / p.gpc;
+    }
+  }
   return p;
 }
 

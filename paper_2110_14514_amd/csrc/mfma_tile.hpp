@@ -78,6 +78,7 @@ struct TileArgs {
   float* gsp;
   float* lossp;
   int I1, I2, I3, R, ns, want, tb1, tb2, nb2, nblocks;
+  int nch, gpc;     // I3 chunks of the launch, 32-entry groups per chunk
   int rpw;          // bit-packed slices: 32-bit words per (i1, i2) row
 };
 
@@ -431,7 +432,7 @@ __device__ __forceinline__ bool reg_active(int ht, int r, int ns) {
 // (0-1: A, 2-3: B), and the mode products follow per pair.
 template <int LOSS, int RT, int NH, int DMA16, int NK = 0, bool XB = false, int PK = 1, int WV = kWaves>
 __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, float* g1s, float* g2s, float* sm,
-                                          float* ring, const float* cl, float* a3t) {
+                                          float* ring, const float* cl, float* a3t, const int chunk = 0) {
   static_assert(!XB || (NH <= 2 && DMA16 == 0), "bit-packed slices take the staged 4-byte path");
   static_assert(PK == 1 || (PK == 2 && NH == 1), "two pairs per step: one h-tile");
   // DMA16: copy mode of the staged slice rows (0: 4-byte copies; 1: 16-byte
@@ -561,7 +562,9 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   const bool vec = (I3 % NU) == 0;
   const int npairs = n1 * n2;
 
-  for (int sc = 0; sc < nsc; ++sc) {
+  // groups of this workgroup's I3 chunk
+  const int sc_end = min(nsc, (chunk + 1) * a.gpc);
+  for (int sc = chunk * a.gpc; sc < sc_end; ++sc) {
     const bool wide = sc < nfull;
     const int c0 = SW * sc;
     const int nu = wide ? NU : (tail + 15) >> 4;
@@ -1285,8 +1288,8 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
     for (int idx = lane; idx < kTB * RT; idx += 64) {
       const int l = idx / RT, j = idx - (idx / RT) * RT;
       if (j < R) {
-        if (l < n1) a.G1p[((size_t)b2 * I1 + i10 + l) * R + j] = g1w[wave][l][j];
-        if (l < n2) a.G2p[((size_t)b1 * I2 + i20 + l) * R + j] = g2w[wave][l][j];
+        if (l < n1) a.G1p[(((size_t)chunk * a.nb2 + b2) * I1 + i10 + l) * R + j] = g1w[wave][l][j];
+        if (l < n2) a.G2p[(((size_t)chunk * (a.nblocks / a.nb2) + b1) * I2 + i20 + l) * R + j] = g2w[wave][l][j];
       }
     }
   }
@@ -1310,12 +1313,12 @@ __device__ __forceinline__ void mfma_tile(const TileArgs& a, const int wgi, floa
   if (tid < R) {
     float s = 0.f;
     for (int w = 0; w < WV; ++w) s += gsx[w][tid];
-    a.gsp[(size_t)wgi * R + tid] = s;
+    a.gsp[((size_t)wgi * a.nch + chunk) * R + tid] = s;
   }
   if (tid == 0) {
     float s = 0.f;
     for (int w = 0; w < WV; ++w) s += lsx[w];
-    a.lossp[wgi] = s;
+    a.lossp[(size_t)wgi * a.nch + chunk] = s;
   }
 }
 
@@ -1332,7 +1335,8 @@ __device__ __forceinline__ void fused_body(const MArgs& a) {
   __shared__ __attribute__((aligned(16))) float a3t[a3t_floats(RT)];
   for (int h = threadIdx.x; h < kMaxNs; h += 64 * WV) cl[h] = h < a.t.ns ? a.c[h] : 0.f;
   __syncthreads();
-  mfma_tile<LOSS, RT, NH, DMA16, NK, XB, PK, WV>(a.t, blockIdx.x, g1s, g2s, sm, ring, cl, a3t);
+  mfma_tile<LOSS, RT, NH, DMA16, NK, XB, PK, WV>(a.t, blockIdx.x / a.t.nch, g1s, g2s, sm, ring, cl, a3t,
+                                                 blockIdx.x % a.t.nch);
 }
 
 template <int LOSS, int RT, int NH, int DMA16, int NK, bool XB = false, int PK = 1>
@@ -1393,6 +1397,8 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
     ta.ns = 1 + s.nwin;
     ta.want = want;
     ta.tb1 = d.tb1; ta.tb2 = d.tb2; ta.nb2 = d.nb2; ta.nblocks = d.nblocks;
+    ta.nch = 1;
+    ta.gpc = 1 << 30;
     for (int h = threadIdx.x; h < kMaxNs; h += kThreads) {
       float v = 0.f;
       if (h == 0) v = 1.f;
@@ -1443,6 +1449,8 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
   a.lossp = lossp;
   a.I1 = c.I1; a.I2 = c.I2; a.I3 = c.I3; a.R = c.R; a.ns = c.ns; a.want = c.want;
   a.tb1 = p.tb1; a.tb2 = p.tb2; a.nb2 = p.nb2; a.nblocks = p.nblocks;
+  a.nch = p.nch;
+  a.gpc = p.gpc;
   a.rpw = (c.I3 + 31) / 32;
   // copy mode of the slice rows (16-byte copies need 16-byte aligned rows);
   // nk: registers of the last h-tile that hold slices of the window
@@ -1462,10 +1470,10 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
     if (c.xbits && c.ns <= 8) {
       if constexpr (kBinary) {
         if constexpr (RT == 16)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, 0, 0, true, 2>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, 0, 0, true, 2>), dim3(p.nwg * p.nch), dim3(kThreads), 0, c.stream,
                              m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, 0, 0, true, 2>), dim3(p.nwg),
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, 0, 0, true, 2>), dim3(p.nwg * p.nch),
                              dim3(64 * tile_waves(RT)), 0, c.stream, m);
       }
       return hipGetLastError();
@@ -1474,10 +1482,10 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
       by_cp([&](auto cpc) {
         constexpr int CP = decltype(cpc)::value;
         if constexpr (RT == 16)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, CP, 0, false, 2>), dim3(p.nwg), dim3(kThreads), 0, c.stream,
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, CP, 0, false, 2>), dim3(p.nwg * p.nch), dim3(kThreads), 0, c.stream,
                              m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, CP, 0, false, 2>), dim3(p.nwg),
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, 1, CP, 0, false, 2>), dim3(p.nwg * p.nch),
                              dim3(64 * tile_waves(RT)), 0, c.stream, m);
       });
       return hipGetLastError();
@@ -1488,23 +1496,23 @@ hipError_t launch(const DenseCall& c, const MfmaPlan& p, float* G1p, float* G2p,
     if constexpr (kBinary && NH <= 2) {
       if (c.xbits) {
         if constexpr (RT == 16 && NH == 1)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, 0, K, true>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, 0, K, true>), dim3(p.nwg * p.nch), dim3(kThreads), 0, c.stream, m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, 0, K, true>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, 0, K, true>), dim3(p.nwg * p.nch), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
         return;
       }
     }
     if constexpr (NH > 2) {
-      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, 0, 0>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0, c.stream,
+      hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, 0, 0>), dim3(p.nwg * p.nch), dim3(64 * tile_waves(RT)), 0, c.stream,
                          m);
     } else {
       by_cp([&](auto cpc) {
         constexpr int CP = decltype(cpc)::value;
         if constexpr (RT == 16 && NH == 1)
-          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, CP, K>), dim3(p.nwg), dim3(kThreads), 0, c.stream, m);
+          hipLaunchKernelGGL((fused_dense_mfma_r16<LOSS, CP, K>), dim3(p.nwg * p.nch), dim3(kThreads), 0, c.stream, m);
         else
-          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, CP, K>), dim3(p.nwg), dim3(64 * tile_waves(RT)), 0,
+          hipLaunchKernelGGL((fused_dense_mfma<LOSS, RT, NH, CP, K>), dim3(p.nwg * p.nch), dim3(64 * tile_waves(RT)), 0,
                              c.stream, m);
       });
     }
