@@ -1406,7 +1406,20 @@ __device__ __forceinline__ void batch_grad_body(const BatchDesc* __restrict__ de
       cl[h] = v;
     }
     __syncthreads();
-    mfma_tile<LOSS, RT, NH, DMA16, 0, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
+    // GEMM2 K-steps of the last h-tile fixed per item, as in a single
+    // stream's build; a window that has not yet reached the variant's
+    // h-tiles keeps the run-time masks
+    const int nl = ta.ns - 16 * (NH - 1);
+    if (PK != 1 || nl <= 0)
+      mfma_tile<LOSS, RT, NH, DMA16, 0, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
+    else if (nl <= 4)
+      mfma_tile<LOSS, RT, NH, DMA16, 1, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
+    else if (nl <= 8)
+      mfma_tile<LOSS, RT, NH, DMA16, 2, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
+    else if (nl <= 12)
+      mfma_tile<LOSS, RT, NH, DMA16, 3, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
+    else
+      mfma_tile<LOSS, RT, NH, DMA16, 4, false, PK>(ta, wg, g1s, g2s, sm, ring, cl, a3t);
     __syncthreads();
   }
 }
