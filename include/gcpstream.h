@@ -473,10 +473,12 @@ typedef struct {
  * gcp_batch_workspace_size).  A stream's share of a batched call has a work
  * plan of its own (pair blocks per stream; default 1024, fewer and larger
  * blocks than a single stream's since the other streams supply the
- * parallelism).  This call times one batched objective+gradient call over
- * the registered io for each candidate plan (512, 1024, 2048, 4096 blocks
- * per stream), on a scratch workspace it allocates and frees, and gives
- * every stream the fastest; or it reads the plan from cache_path, keyed on
+ * parallelism).  This call builds one batch over the registered io for
+ * each candidate plan (512, 1024, 2048, 4096 blocks per stream), each on a
+ * scratch workspace it allocates and frees, times nine single
+ * objective+gradient calls per candidate taken round-robin over the
+ * candidates, and gives every stream the plan with the lowest median call;
+ * or it reads the plan from cache_path, keyed on
  * the device and the batch's shape buckets (see gcp_autotune), and appends
  * a tuned plan there.  The registered outputs are written.  *buckets (may
  * be NULL) receives the number of distinct shape buckets.  Synchronous.

@@ -1578,43 +1578,64 @@ extern "C" gcp_status gcp_batch_autotune(gcp_stream* const* streams, const gcp_b
     for (int i = 0; i < n; ++i) streams[i]->batch_plan_target = best;
     return GCP_OK;
   }
-  // time one batched objective+gradient call per candidate plan, on a
-  // scratch workspace of the candidate's size (the registered outputs are
-  // written and later overwritten)
-  const int cands[] = {512, 1024, 2048, 4096};
-  float best_ms = 1e30f;
+  // one batch per candidate plan, each on a scratch workspace of its own size
+  // (the registered outputs are written and later overwritten); then single
+  // objective+gradient calls timed round-robin over the candidates, so that
+  // clock and thermal drift falls on all of them alike, and the median call
+  // of each candidate decides
+  constexpr int kCands = 4, kReps = 9;
+  const int cands[kCands] = {512, 1024, 2048, 4096};
+  gcp_batch* bs[kCands] = {};
+  void* wss[kCands] = {};
   best = kBatchPlanTarget;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GCP_E_DEVICE;
   gcp_status st = GCP_OK;
-  for (int c = 0; c < 4 && st == GCP_OK; ++c) {
+  for (int c = 0; c < kCands && st == GCP_OK; ++c) {
     for (int i = 0; i < n; ++i) streams[i]->batch_plan_target = cands[c];
     size_t bytes = 0;
     st = gcp_batch_workspace_size(streams, n, &bytes);
-    if (st != GCP_OK) break;
-    void* ws = nullptr;
-    if (hipMalloc(&ws, bytes) != hipSuccess) {
+    if (st == GCP_OK && hipMalloc(&wss[c], bytes) != hipSuccess) {
+      wss[c] = nullptr;
       st = GCP_E_DEVICE;
-      break;
     }
-    gcp_batch* b = nullptr;
-    st = gcp_batch_create(streams, io, n, ws, bytes, streams[0]->st, &b);
-    if (st == GCP_OK) st = gcp_batch_loss_grad(b, GCP_WANT_LOSS | GCP_WANT_GRAD);   // warm-up
-    if (st == GCP_OK && hipEventRecord(e0, streams[0]->st) != hipSuccess) st = GCP_E_DEVICE;
-    for (int r = 0; r < 3 && st == GCP_OK; ++r) st = gcp_batch_loss_grad(b, GCP_WANT_LOSS | GCP_WANT_GRAD);
-    if (st == GCP_OK && (hipEventRecord(e1, streams[0]->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-      st = GCP_E_DEVICE;
-    float ms = 0.f;
-    if (st == GCP_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-      best_ms = ms;
+    if (st == GCP_OK) st = gcp_batch_create(streams, io, n, wss[c], bytes, streams[0]->st, &bs[c]);
+    if (st == GCP_OK) st = gcp_batch_loss_grad(bs[c], GCP_WANT_LOSS | GCP_WANT_GRAD);   // warm-up
+  }
+  hipEvent_t ev[kCands][kReps][2] = {};
+  for (int c = 0; c < kCands && st == GCP_OK; ++c)
+    for (int r = 0; r < kReps && st == GCP_OK; ++r)
+      for (int k = 0; k < 2 && st == GCP_OK; ++k)
+        if (hipEventCreate(&ev[c][r][k]) != hipSuccess) {
+          ev[c][r][k] = nullptr;
+          st = GCP_E_DEVICE;
+        }
+  for (int r = 0; r < kReps && st == GCP_OK; ++r)
+    for (int c = 0; c < kCands && st == GCP_OK; ++c) {
+      if (hipEventRecord(ev[c][r][0], streams[0]->st) != hipSuccess) st = GCP_E_DEVICE;
+      if (st == GCP_OK) st = gcp_batch_loss_grad(bs[c], GCP_WANT_LOSS | GCP_WANT_GRAD);
+      if (st == GCP_OK && hipEventRecord(ev[c][r][1], streams[0]->st) != hipSuccess) st = GCP_E_DEVICE;
+    }
+  if (st == GCP_OK && hipStreamSynchronize(streams[0]->st) != hipSuccess) st = GCP_E_DEVICE;
+  float best_ms = 1e30f;
+  for (int c = 0; c < kCands && st == GCP_OK; ++c) {
+    float t[kReps];
+    for (int r = 0; r < kReps && st == GCP_OK; ++r)
+      if (hipEventElapsedTime(&t[r], ev[c][r][0], ev[c][r][1]) != hipSuccess) st = GCP_E_DEVICE;
+    if (st != GCP_OK) break;
+    std::sort(t, t + kReps);
+    if (t[kReps / 2] < best_ms) {
+      best_ms = t[kReps / 2];
       best = cands[c];
     }
-    if (b) gcp_batch_destroy(b);
-    if (hipStreamSynchronize(streams[0]->st) != hipSuccess && st == GCP_OK) st = GCP_E_DEVICE;
-    hipFree(ws);
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  for (int c = 0; c < kCands; ++c)
+    for (int r = 0; r < kReps; ++r)
+      for (int k = 0; k < 2; ++k)
+        if (ev[c][r][k]) hipEventDestroy(ev[c][r][k]);
+  if (hipStreamSynchronize(streams[0]->st) != hipSuccess && st == GCP_OK) st = GCP_E_DEVICE;
+  for (int c = 0; c < kCands; ++c) {
+    if (bs[c]) gcp_batch_destroy(bs[c]);
+    if (wss[c]) hipFree(wss[c]);
+  }
   for (int i = 0; i < n; ++i) streams[i]->batch_plan_target = best;
   if (st != GCP_OK) return st;
   if (cache_path) {
