@@ -431,7 +431,9 @@ gcp_status gcp_probe_gather(const void* A1, const void* A2, const void* A3, int6
  * plan whose workgroups fill their last round of resident workgroups best.
  * This call times every candidate plan on the device with HIP events over
  * X_t and the current window (synchronous; not for use inside a graph
- * capture), keeps the fastest for this stream, and appends "<key> = <plan>"
+ * capture): seven single calls per plan, taken round-robin over the plans;
+ * it keeps the plan with the lowest median call for this stream (errors:
+ * GCP_E_DEVICE when a device call fails), and appends "<key> = <plan>"
  * to the text file cache_path (NULL: no cache), where the key is the shape
  * bucket "<arch> loss<l> rt<16|32> nh<h-tiles> dma<copy mode 0|1|2>
  * pairs2^<floor(log2(I1 I2))> i3x64:<ceil(I3/64)>".  A cache hit (a valid

@@ -1395,28 +1395,45 @@ extern "C" gcp_status gcp_autotune(gcp_stream* s, const gcp_slice* X_t, const ch
   c.gs = s->ws + s->L.gs;
   c.loss_out = s->ws + s->L.loss;
   if (!mfma_supported(c.R, c.ns, 0)) return GCP_E_UNSUPPORTED;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GCP_E_DEVICE;
+  // one warm-up call per candidate plan, then single calls timed
+  // round-robin over the candidates (clock drift falls on all alike); the
+  // lowest median call decides
+  constexpr int kReps = 7;
+  hipEvent_t ev[kNumPlanTargets][kReps][2] = {};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kNumPlanTargets && e == hipSuccess; ++i)
+    for (int r = 0; r < kReps && e == hipSuccess; ++r)
+      for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        if ((e = hipEventCreate(&ev[i][r][k])) != hipSuccess) ev[i][r][k] = nullptr;
+  for (int i = 0; i < kNumPlanTargets && e == hipSuccess; ++i) {
+    c.plan_target = kPlanTargets[i];
+    e = dense_fused_run(c);
+  }
+  for (int r = 0; r < kReps && e == hipSuccess; ++r)
+    for (int i = 0; i < kNumPlanTargets && e == hipSuccess; ++i) {
+      c.plan_target = kPlanTargets[i];
+      e = hipEventRecord(ev[i][r][0], s->st);
+      if (e == hipSuccess) e = dense_fused_run(c);
+      if (e == hipSuccess) e = hipEventRecord(ev[i][r][1], s->st);
+    }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   float best_ms = 1e30f;
   best = kDefaultPlanTarget;
-  for (int i = 0; i < kNumPlanTargets; ++i) {
-    c.plan_target = kPlanTargets[i];
-    hipError_t e = dense_fused_run(c);  // warm-up
+  for (int i = 0; i < kNumPlanTargets && e == hipSuccess; ++i) {
+    float t[kReps];
+    for (int r = 0; r < kReps && e == hipSuccess; ++r) e = hipEventElapsedTime(&t[r], ev[i][r][0], ev[i][r][1]);
     if (e != hipSuccess) break;
-    hipEventRecord(e0, s->st);
-    const int reps = 5;
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = dense_fused_run(c);
-    hipEventRecord(e1, s->st);
-    if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) break;
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) {
-      best_ms = ms;
+    std::sort(t, t + kReps);
+    if (t[kReps / 2] < best_ms) {
+      best_ms = t[kReps / 2];
       best = kPlanTargets[i];
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  for (int i = 0; i < kNumPlanTargets; ++i)
+    for (int r = 0; r < kReps; ++r)
+      for (int k = 0; k < 2; ++k)
+        if (ev[i][r][k]) hipEventDestroy(ev[i][r][k]);
+  if (e != hipSuccess) return GCP_E_DEVICE;
   s->plan_target = best;
   if (chosen) *chosen = best;
   if (cache_path) {
