@@ -226,3 +226,40 @@ def test_batch_epochs_graph_replay_matches_eager():
         for k in range(3):
             assert np.array_equal(graph_f[i][k], eager_f[i][k]), (i, k)
 
+
+
+# window capacity H against slices held: two-h-tile builds (H >= 16) whose
+# windows still hold at most 16 slices, and one-h-tile windows of 9..15
+# slices (the last h-tile's GEMM2 K-steps fixed per work item at 3 and 4)
+FILL_SPECS = [((21, 13, 37), 16, 20, 9, "gaussian"), ((17, 11, 44), 32, 24, 14, "poisson_log"),
+              ((19, 15, 52), 16, 10, 10, "poisson_log"), ((13, 22, 48), 32, 14, 14, "gaussian"),
+              ((25, 9, 61), 8, 12, 12, "gaussian"), ((11, 14, 36), 32, 9, 9, "poisson_log")]
+
+
+def test_batch_partial_and_mid_windows_match_streams_and_oracle():
+    import torch
+    from paper_2110_14514_amd import Batch, Stream
+    print("case: batch partial / mid windows", flush=True)
+    probs = [gi.random_dense(d, R, n, loss, seed=40 + i, w=1.1, theta=0.9, lam=0.05, mu=0.1)
+             for i, (d, R, H, n, loss) in enumerate(FILL_SPECS)]
+    devs = [to_device(p) for p in probs]
+    streams = [Stream(p.dims, p.rank, H, p.loss, d["A"], d["X_hist"], d["s_hist"], d["t_hist"], w=p.w,
+                      theta=p.theta, lam=p.lam, mu=p.mu, kernel="mfma")
+               for p, d, (_, _, H, _, _) in zip(probs, devs, FILL_SPECS)]
+    b = Batch(streams, [d["X_t"].clone() for d in devs], [d["s_t"].clone() for d in devs])
+    outs = b.loss_grad()
+    torch.cuda.synchronize()
+    assert b.sync_streams() == 0
+    for i, (p, d, st) in enumerate(zip(probs, devs, streams)):
+        loss, G, g_s = st.loss_grad(d["X_t"], d["A"], d["s_t"])
+        torch.cuda.synchronize()
+        bl, bG, bg = outs[i]
+        # the batch's build has the window's capacity in h-tiles, the
+        # stream's own call the slices it holds: same sums up to their order
+        assert rel_err(bl.cpu().numpy(), loss.cpu().numpy()) <= 1e-5, i
+        for k in range(3):
+            assert rel_err(bG[k].cpu().numpy(), G[k].cpu().numpy()) <= 1e-5, (i, k)
+        assert rel_err(bg.cpu().numpy(), g_s.cpu().numpy()) <= 1e-5, i
+        got = (float(bl.item()), [g.double().cpu().numpy() for g in bG], bg.double().cpu().numpy())
+        errs = compare(p, got, og)
+        assert max(errs.values()) <= TOL, (i, errs)
